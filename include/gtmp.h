@@ -1,0 +1,211 @@
+/*
+ * gtmp.h -- C ABI of the MI355X (gfx950) implementation of the data-parallel
+ * hot path of Global Tensor Motion Planning with a straight-line local
+ * planner ("Anytime Global Tensor Motion Planning", Coumar, Le, Kingston).
+ *
+ * The planner:  sample a layered multipartite graph of waypoints (Sec. III-A),
+ * realise every adjacent-layer edge with the straight-line local planner and
+ * collision-check its interpolated states (Sec. III-B), run the min-plus
+ * Bellman recursion backwards over the layers (Sec. IV-B) and follow the
+ * minimisers from the start (Alg. 1, extraction).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Layers are numbered as in Alg. 1: intermediate layers m = 0..M-1, the
+ *   start q0 precedes layer 0 and the goals follow layer M-1.
+ * - Pointers named in the comments as "device" must point to device memory of
+ *   the current HIP device; "host" pointers are read before the call returns.
+ *   The caller owns every buffer; the library never allocates, frees or
+ *   keeps a pointer after the call returns.
+ * - Each call validates its arguments on the host first.  On an invalid
+ *   argument it returns GTMP_EINVAL, enqueues nothing and writes nothing.
+ *   GTMP_EHIP means a HIP launch or API call failed.  gtmp_last_error()
+ *   returns a thread-local message describing the last failure.
+ * - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *   the call returns without waiting for it.  Results are valid once the
+ *   stream has reached the call.
+ * - All floating-point work is FP32.  Samples, costs and values are float32.
+ */
+#ifndef GTMP_H
+#define GTMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int gtmp_status;
+#define GTMP_OK 0
+#define GTMP_ENOPATH 1      /* informational: the graph holds no feasible chain */
+#define GTMP_EINVAL (-1)    /* invalid argument; nothing was enqueued */
+#define GTMP_EHIP (-2)      /* a HIP call failed */
+#define GTMP_EWORKSPACE (-3) /* workspace too small */
+
+/* Human-readable name of a status code (static storage). */
+const char *gtmp_status_string(gtmp_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char *gtmp_last_error(void);
+/* Library version string. */
+const char *gtmp_version(void);
+
+/* ---------------------------------------------------------------- limits */
+#define GTMP_MAX_DOF 8             /* configuration dimension d */
+#define GTMP_MAX_JOINTS 8          /* revolute joints of a serial arm */
+#define GTMP_MAX_ROBOT_SPHERES 64  /* collision spheres of a serial arm */
+#define GTMP_MAX_H 256             /* interpolated states per edge */
+
+/* --------------------------------------------------------------- problem */
+/* Sizes and constants of one layered graph (Sec. III-A; Alg. 1 data).
+ *   d        configuration dimension, 1..GTMP_MAX_DOF
+ *   M        intermediate layers (>= 1)
+ *   N        samples per layer (>= 1)
+ *   G        goals (>= 1)
+ *   H        interpolated states per edge, endpoints included (2..GTMP_MAX_H)
+ *   lo, hi   sampling box, lo[j] < hi[j] for j < d
+ *   penalty  cost added to an edge whose local planner fails; +INF gives the
+ *            paper's absent edge (Sec. IV-B: an absent edge costs +inf)
+ *   max_edge_len  length limit ell of the local planner query (Sec. III-B):
+ *            an edge longer than this fails; +INF disables the limit.     */
+typedef struct gtmp_problem {
+    int32_t d, M, N, G, H;
+    float lo[GTMP_MAX_DOF];
+    float hi[GTMP_MAX_DOF];
+    float penalty;
+    float max_edge_len;
+} gtmp_problem;
+
+/* ----------------------------------------------------------------- robot */
+#define GTMP_ROBOT_POINT 0   /* configuration = point in workspace (d == wdim) */
+#define GTMP_ROBOT_DH_ARM 1  /* revolute serial arm, standard DH, sphere model  */
+
+/* Host memory, read during the call.  For a DH arm, joint i (0-based) has the
+ * link transform Rz(q_i + dh[i][3]) Tz(dh[i][2]) Tx(dh[i][0]) Rx(dh[i][1]),
+ * chained from a base frame at the origin; sphere k sits on link
+ * sph_link[k] (1..n_joints) at fraction sph_t[k] from frame origin
+ * o_{L-1} to o_L, with radius sph_r[k].  Spheres must be listed in
+ * non-decreasing link order.  A point robot ignores every field but kind. */
+typedef struct gtmp_robot {
+    int32_t kind;
+    int32_t n_joints;   /* == d for an arm */
+    int32_t n_spheres;  /* 1..GTMP_MAX_ROBOT_SPHERES for an arm */
+    int32_t reserved;
+    float dh[GTMP_MAX_JOINTS][4]; /* (a, alpha, d, theta_offset) */
+    int32_t sph_link[GTMP_MAX_ROBOT_SPHERES];
+    float sph_t[GTMP_MAX_ROBOT_SPHERES];
+    float sph_r[GTMP_MAX_ROBOT_SPHERES];
+} gtmp_robot;
+
+/* ----------------------------------------------------------------- scene */
+/* Obstacles in a workspace of dimension wdim (2 or 3; a point robot needs
+ * wdim == d, an arm needs wdim == 3).  Device memory:
+ *   spheres [n_spheres][wdim + 1]  (centre, radius)      -- circles in 2D
+ *   boxes   [n_boxes][2 * wdim]    (centre, half extents), axis-aligned
+ * A configuration is in collision iff its signed distance to the union of
+ * obstacles is <= 0 (Sec. III: the free space is open).                  */
+typedef struct gtmp_scene {
+    int32_t wdim;
+    int32_t n_spheres;
+    const float *spheres;
+    int32_t n_boxes;
+    const float *boxes;
+} gtmp_scene;
+
+/* ------------------------------------------------------------ a1 sampler */
+/* Uniform layer samples (Alg. 1: "uniformly sample Q"; Sec. III-A: N
+ * independent samples in each of the M layers).
+ * Q: device float32 [M][N][d], written.
+ * Coordinate j of sample n in layer m is lo[j] + u * (hi[j] - lo[j]) rounded
+ * once to float32, u = (w >> 8) * 2^-24 with w word (j mod 4) of
+ * Philox4x32-10 (Salmon et al., SC'11) at key (seed mod 2^32, seed div 2^32)
+ * and counter (n, m, stage mod 2^32, j div 4).  Deterministic in
+ * (seed, stage); `stage` separates the stages of the anytime loops. */
+gtmp_status gtmp_sample_layers(const gtmp_problem *prob, uint64_t seed, uint64_t stage, float *Q,
+                               void *stream);
+
+/* -------------------------------------------------- a2-a4 edge checking */
+#define GTMP_CHECK_FAST 0  /* endpoint pre-pass + early-exit interior checks */
+#define GTMP_CHECK_FULL 1  /* every state of every edge, exact signed distance */
+
+/* Tuning knobs; zero-initialise for the defaults. */
+typedef struct gtmp_edge_opts {
+    int32_t mode;             /* GTMP_CHECK_FAST (default) or GTMP_CHECK_FULL */
+    int32_t states_per_iter;  /* point robots: interior states per lane and iteration (1,2,4,8; 0 = auto) */
+    int32_t block;            /* threads per block for the interior kernel (64..1024, multiple of 64; 0 = auto) */
+    int32_t blocks_per_cu;    /* resident blocks per CU for the persistent interior kernel (0 = auto) */
+    int32_t chunk;            /* work-list items a wave takes per refill (0 = auto) */
+    int32_t reserved[3];
+    unsigned long long *stats; /* optional device [4]: states evaluated, edges checked in the
+                                  interior pass, reserved, reserved.  Added to. */
+    void *ev_begin;            /* optional hipEvent_t recorded on `stream` just before the
+                                  interior (fast mode) or every-state (full mode) kernel */
+    void *ev_end;              /* optional hipEvent_t recorded just after it */
+} gtmp_edge_opts;
+
+/* Bytes of device workspace gtmp_edge_check_cost needs for this problem. */
+gtmp_status gtmp_edge_check_workspace_size(const gtmp_problem *prob, size_t *bytes);
+
+/* Realise and cost every candidate edge (Sec. III-B; Alg. 1 "compute cost
+ * matrices C_s, C_h, C_l"; SEV local planner of Sec. V).
+ * Edge (x, y) is checked at the H states x + (h/(H-1)) (y - x), h = 0..H-1;
+ * it fails if a state is in collision or |y - x| > max_edge_len.  Its cost
+ * is |y - x| (Euclidean, configuration space) plus `penalty` if it failed.
+ *   q0      device float32 [d]
+ *   goals   device float32 [G][d]
+ *   Q       device float32 [M][N][d]
+ *   C_s     device float32 [N]           q0 -> layer 0 vertex v
+ *   C_h     device float32 [M-1][N][N]   layer m vertex u (row) -> layer m+1 vertex v (column)
+ *   C_l     device float32 [N][G]        layer M-1 vertex u -> goal g
+ *   minsd   device float32 [E] or NULL   minimum signed distance over the edge's states
+ *           (E = N + (M-1) N^2 + N G, ordered as C_s, C_h, C_l); forces GTMP_CHECK_FULL
+ *   flags   device uint8 [E] or NULL     1 = local planner failed, same order as minsd
+ *   prune   device uint8 [E] or NULL     nonzero = edge pruned by a surrogate: not checked,
+ *           cost |y - x| + penalty, flag 1
+ *   workspace, ws_bytes   device scratch of at least gtmp_edge_check_workspace_size bytes
+ *   opts    host, may be NULL
+ * C_h may be NULL when M == 1. */
+gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                                 const float *q0, const float *goals, const float *Q, float *C_s, float *C_h,
+                                 float *C_l, float *minsd, uint8_t *flags, const uint8_t *prune,
+                                 void *workspace, size_t ws_bytes, const gtmp_edge_opts *opts,
+                                 void *stream);
+
+/* Signed distance / collision flag of a batch of configurations (the state
+ * test of Sec. III used by the edge check).  X device float32 [n][d];
+ * sd device float32 [n] or NULL (exact signed distance); coll device
+ * uint8 [n] or NULL (1 iff sd <= 0). */
+gtmp_status gtmp_state_check(const gtmp_robot *robot, const gtmp_scene *scene, int32_t d, int64_t n,
+                             const float *X, float *sd, uint8_t *coll, void *stream);
+
+/* --------------------------------------------------- a5 min-plus sweep */
+/* Backward value iteration on the layered DAG (Sec. IV-B; Alg. 1):
+ *   V[M-1][u] = min_g C_l[u][g] + V_g[g]
+ *   V[m][u]   = min_v C_h[m][u][v] + V[m+1][v],   m = M-2 .. 0
+ *   V_s       = min_u C_s[u] + V[0][u]
+ * A[m][u] / a_s receive the minimiser (lowest index among equal values; -1
+ * when the minimum is +inf).  One backward pass reaches the fixed point of
+ * Alg. 1's repeated sweeps on this depth-(M+1) DAG.
+ *   Vg      device float32 [G] or NULL (zeros: terminal cost-to-go 0)
+ *   V       device float32 [M][N];  A device int32 [M][N]
+ *   V_s     device float32 [1];     a_s device int32 [1]            */
+gtmp_status gtmp_minplus_sweep(int32_t M, int32_t N, int32_t G, const float *C_s, const float *C_h,
+                               const float *C_l, const float *Vg, float *V, int32_t *A, float *V_s,
+                               int32_t *a_s, void *stream);
+
+/* ------------------------------------------------------ a6 extraction */
+/* Follow the minimisers from the start (Alg. 1 extraction; Sec. IV-B).
+ *   idx   device int32 [M+1]: idx[m] = chosen vertex of layer m, idx[M] = goal
+ *   wp    device float32 [M+2][d]: q0, Q[0][idx0], ..., Q[M-1][idx_{M-1}], goals[idx_M]
+ *   cost  device float32 [1] = V_s
+ * With no path (a_s < 0 or V_s = +inf) idx is filled with -1, wp with
+ * NaN and cost with +inf. */
+gtmp_status gtmp_extract_path(int32_t M, int32_t N, int32_t G, int32_t d, const int32_t *a_s,
+                              const int32_t *A, const float *V_s, const float *Q, const float *q0,
+                              const float *goals, int32_t *idx, float *wp, float *cost, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GTMP_H */

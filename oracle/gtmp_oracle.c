@@ -1,0 +1,376 @@
+/*
+ * gtmp_oracle.c -- plain, slow FP64 reference of the layered-graph planner
+ * (Global Tensor Motion Planning with a straight-line local planner).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The HIP product path
+ * never links, calls or includes anything from here, and this file includes
+ * nothing from the product path: the two implementations share no code.
+ *
+ * Every routine follows the definition it cites, written out with plain loops
+ * in double precision.  Inputs (scenes, robot models, samples) are float32
+ * arrays, the precision the planner stores; they are promoted exactly to
+ * double on entry.
+ *
+ * Paper: "Anytime Global Tensor Motion Planning" (Coumar, Le, Kingston).
+ *   Sec. III        configuration space, open free space (boundary = collision)
+ *   Sec. III-A      layered sampling model, vertex sets V_0 = {q0}, V_m, goals
+ *   Sec. III-B      local planner LP, edge present iff LP succeeds
+ *   Alg. 1 (gtmp)   cost matrices C_s, C_h, C_l; value tensor; argmin
+ *                   extraction
+ *   Sec. IV-B       Bellman recursion on the layered DAG, absent edge = +inf
+ */
+#include <math.h>
+#include <omp.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Threads the OpenMP loops of this file use. */
+int or_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw,        */
+/* "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11).  Ten rounds of the */
+/* 4x32 S-box: two 32x32->64 multiplications, xor with the other two counter */
+/* words and the key, followed by a Weyl increment of the key.               */
+/* ------------------------------------------------------------------------ */
+#define OR_PHILOX_MULT_A 0xD2511F53u
+#define OR_PHILOX_MULT_B 0xCD9E8D57u
+#define OR_PHILOX_WEYL_A 0x9E3779B9u
+#define OR_PHILOX_WEYL_B 0xBB67AE85u
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += OR_PHILOX_WEYL_A;
+            k1 += OR_PHILOX_WEYL_B;
+        }
+        uint64_t pa = (uint64_t)OR_PHILOX_MULT_A * (uint64_t)x0;
+        uint64_t pb = (uint64_t)OR_PHILOX_MULT_B * (uint64_t)x2;
+        uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
+        uint32_t y0 = hi_b ^ x1 ^ k0;
+        uint32_t y1 = lo_b;
+        uint32_t y2 = hi_a ^ x3 ^ k1;
+        uint32_t y3 = lo_a;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* a1: uniform layer samples (Alg. 1: "uniformly sample Q in R^{MxNxd}";     */
+/* Sec. III-A: N independent samples per intermediate layer).               */
+/*                                                                          */
+/* Random word for (layer m, sample n, coordinate j) at stage `stage`:      */
+/*   key     = (seed mod 2^32, seed div 2^32)                               */
+/*   counter = (n, m, stage mod 2^32, stream * 2^16 + j div 4)              */
+/*   word    = Philox4x32-10(counter, key)[j mod 4]                         */
+/* u = (word >> 8) * 2^-24 in [0,1); the stored sample is the float32       */
+/* rounding of lo_j + u * w_j with w_j the float32 difference hi_j - lo_j.  */
+/* ------------------------------------------------------------------------ */
+double or_unit_from_word(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+
+void or_words(uint64_t seed, uint64_t stage, uint32_t stream, uint32_t n, uint32_t m, uint32_t blk,
+              uint32_t out[4])
+{
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {n, m, (uint32_t)(stage & 0xffffffffu), (stream << 16) | blk};
+    or_philox4x32_10(ctr, key, out);
+}
+
+void or_sample_layers(int M, int N, int d, const float *lo, const float *hi, uint64_t seed,
+                      uint64_t stage, float *Q /* [M][N][d] */)
+{
+    for (int m = 0; m < M; ++m)
+        for (int n = 0; n < N; ++n)
+            for (int j = 0; j < d; ++j) {
+                uint32_t w[4];
+                or_words(seed, stage, 0u, (uint32_t)n, (uint32_t)m, (uint32_t)(j / 4), w);
+                double u = or_unit_from_word(w[j % 4]);
+                double width = (double)(float)((double)hi[j] - (double)lo[j]);
+                Q[((size_t)m * N + n) * d + j] = (float)((double)lo[j] + u * width);
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collision model (Sec. III: C_free is open, so a configuration whose       */
+/* signed distance to the obstacles is <= 0 is in collision).                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int kind;            /* 0: point robot, configuration = workspace point; 1: serial arm */
+    int d;               /* configuration dimension */
+    int wdim;            /* workspace dimension of the obstacles (2 or 3) */
+    int n_joints;        /* arm: number of revolute joints (== d) */
+    const float *dh;     /* arm: [n_joints][4] = (a, alpha, d, theta_offset), standard DH */
+    int n_rsph;          /* arm: collision spheres */
+    const int *rsph_link;  /* [n_rsph] link index 1..n_joints */
+    const float *rsph_t;   /* [n_rsph] fraction along the link o_{i-1} -> o_i */
+    const float *rsph_r;   /* [n_rsph] radius */
+    int n_osph;          /* sphere / circle obstacles */
+    const float *osph;   /* [n_osph][wdim + 1] = (centre, radius) */
+    int n_obox;          /* axis-aligned box obstacles */
+    const float *obox;   /* [n_obox][2 * wdim] = (centre, half extents) */
+} or_model;
+
+/* Euclidean distance from p to the sphere surface: |p - c| - r. */
+static double or_sd_sphere(int wdim, const double *p, const float *s)
+{
+    double acc = 0.0;
+    for (int i = 0; i < wdim; ++i) {
+        double t = p[i] - (double)s[i];
+        acc += t * t;
+    }
+    return sqrt(acc) - (double)s[wdim];
+}
+
+/* Exact signed distance to an axis-aligned box with centre c, half extents h:
+ * q = |p - c| - h;  sd = |max(q, 0)| + min(max_i q_i, 0). */
+static double or_sd_box(int wdim, const double *p, const float *b)
+{
+    double outside = 0.0, inside = -INFINITY;
+    for (int i = 0; i < wdim; ++i) {
+        double q = fabs(p[i] - (double)b[i]) - (double)b[wdim + i];
+        double qp = q > 0.0 ? q : 0.0;
+        outside += qp * qp;
+        if (q > inside) inside = q;
+    }
+    return sqrt(outside) + (inside < 0.0 ? inside : 0.0);
+}
+
+double or_sd_point(const or_model *mdl, const double *p)
+{
+    double best = INFINITY;
+    for (int o = 0; o < mdl->n_osph; ++o) {
+        double v = or_sd_sphere(mdl->wdim, p, mdl->osph + (size_t)o * (mdl->wdim + 1));
+        if (v < best) best = v;
+    }
+    for (int o = 0; o < mdl->n_obox; ++o) {
+        double v = or_sd_box(mdl->wdim, p, mdl->obox + (size_t)o * 2 * mdl->wdim);
+        if (v < best) best = v;
+    }
+    return best;
+}
+
+/* Standard Denavit-Hartenberg forward kinematics.  Link transform
+ *   A_i = Rz(theta_i) Tz(d_i) Tx(a_i) Rx(alpha_i),  theta_i = q_i + offset_i,
+ * chained from the base frame (identity at the origin): T_i = T_{i-1} A_i.
+ * Writes the frame origins o_0 (= base origin) .. o_J, [J + 1][3]. */
+void or_fk_origins(int J, const float *dh, const double *q, double *o)
+{
+    double T[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    o[0] = o[1] = o[2] = 0.0;
+    for (int i = 0; i < J; ++i) {
+        double a = dh[4 * i + 0], alpha = dh[4 * i + 1], dz = dh[4 * i + 2], off = dh[4 * i + 3];
+        double th = q[i] + off;
+        double ct = cos(th), st = sin(th), ca = cos(alpha), sa = sin(alpha);
+        double A[4][4] = {{ct, -st * ca, st * sa, a * ct},
+                          {st, ct * ca, -ct * sa, a * st},
+                          {0.0, sa, ca, dz},
+                          {0.0, 0.0, 0.0, 1.0}};
+        double R[4][4];
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 4; ++k) acc += T[r][k] * A[k][c];
+                R[r][c] = acc;
+            }
+        memcpy(T, R, sizeof(T));
+        o[3 * (i + 1) + 0] = T[0][3];
+        o[3 * (i + 1) + 1] = T[1][3];
+        o[3 * (i + 1) + 2] = T[2][3];
+    }
+}
+
+/* Centres of the arm's collision spheres: c_k = o_{L-1} + t_k (o_L - o_{L-1}). */
+void or_arm_spheres(const or_model *mdl, const double *q, double *centres /* [n_rsph][3] */)
+{
+    double o[3 * 33];
+    or_fk_origins(mdl->n_joints, mdl->dh, q, o);
+    for (int k = 0; k < mdl->n_rsph; ++k) {
+        int L = mdl->rsph_link[k];
+        double t = mdl->rsph_t[k];
+        for (int i = 0; i < 3; ++i)
+            centres[3 * k + i] = o[3 * (L - 1) + i] + t * (o[3 * L + i] - o[3 * (L - 1) + i]);
+    }
+}
+
+/* Signed distance of a configuration to the obstacle set. */
+double or_state_sd(const or_model *mdl, const double *q)
+{
+    if (mdl->kind == 0) return or_sd_point(mdl, q);
+    double c[3 * 256];
+    or_arm_spheres(mdl, q, c);
+    double best = INFINITY;
+    for (int k = 0; k < mdl->n_rsph; ++k) {
+        double v = or_sd_point(mdl, c + 3 * k) - (double)mdl->rsph_r[k];
+        if (v < best) best = v;
+    }
+    return best;
+}
+
+void or_state_sd_batch(const or_model *mdl, long n, const float *X /* [n][d] */, double *sd)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long i = 0; i < n; ++i) {
+        double q[64];
+        for (int j = 0; j < mdl->d; ++j) q[j] = X[(size_t)i * mdl->d + j];
+        sd[i] = or_state_sd(mdl, q);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* a2-a4: straight-line local planner on one edge (Sec. III-B; SEV in       */
+/* Sec. V).  The edge is realised by the H states x_h = u + (h/(H-1))(v-u), */
+/* h = 0..H-1 (both endpoints included).  The LP fails (edge absent) iff a  */
+/* state is in collision or |v - u| exceeds the length limit.  An edge that */
+/* succeeds costs its length; a failed edge costs length + penalty, and     */
+/* +inf when the penalty is +inf (absent edge, Sec. IV-B).                  */
+/* ------------------------------------------------------------------------ */
+void or_edge(const or_model *mdl, int H, double penalty, double max_len, const float *u,
+             const float *v, double *cost, double *minsd, int *flag)
+{
+    int d = mdl->d;
+    double du[64], dv[64], x[64];
+    double len2 = 0.0;
+    for (int j = 0; j < d; ++j) {
+        du[j] = u[j];
+        dv[j] = v[j];
+        len2 += (dv[j] - du[j]) * (dv[j] - du[j]);
+    }
+    double len = sqrt(len2);
+    double best = INFINITY;
+    for (int h = 0; h < H; ++h) {
+        double t = (double)h / (double)(H - 1);
+        for (int j = 0; j < d; ++j) x[j] = du[j] + t * (dv[j] - du[j]);
+        double sd = or_state_sd(mdl, x);
+        if (sd < best) best = sd;
+    }
+    int f = (best <= 0.0) || (len > max_len);
+    *flag = f;
+    *minsd = best;
+    *cost = f ? len + penalty : len;
+}
+
+/* Flattened edge numbering used by the subset routine:
+ *   [0, N)                         start -> layer 0 vertex u
+ *   [N, N + (M-1) N^2)             layer m vertex u -> layer m+1 vertex v, (m, u, v) row-major
+ *   [N + (M-1) N^2, ... + N G)     layer M-1 vertex u -> goal g, (u, g) row-major       */
+static void or_edge_endpoints(int M, int N, int G, int d, const float *q0, const float *goals,
+                              const float *Q, long e, const float **pu, const float **pv)
+{
+    long nin = (long)(M - 1) * N * N;
+    if (e < N) {
+        *pu = q0;
+        *pv = Q + (size_t)e * d; /* layer 0 */
+    } else if (e < N + nin) {
+        long r = e - N;
+        long m = r / ((long)N * N), uv = r % ((long)N * N);
+        *pu = Q + ((size_t)m * N + uv / N) * d;
+        *pv = Q + ((size_t)(m + 1) * N + uv % N) * d;
+    } else {
+        long r = e - N - nin;
+        *pu = Q + ((size_t)(M - 1) * N + r / G) * d;
+        *pv = goals + (size_t)(r % G) * d;
+    }
+}
+
+void or_edge_subset(const or_model *mdl, int M, int N, int G, int H, double penalty, double max_len,
+                    const float *q0, const float *goals, const float *Q, long n_sel,
+                    const long *edge_ids, double *cost, double *minsd, int *flag)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < n_sel; ++i) {
+        const float *pu, *pv;
+        or_edge_endpoints(M, N, G, mdl->d, q0, goals, Q, edge_ids[i], &pu, &pv);
+        or_edge(mdl, H, penalty, max_len, pu, pv, &cost[i], &minsd[i], &flag[i]);
+    }
+}
+
+/* All edges: C_s[N], C_h[M-1][N][N] (row = source in layer m, column =
+ * destination in layer m+1), C_l[N][G]; the same shape for minsd and flags. */
+void or_edge_costs(const or_model *mdl, int M, int N, int G, int H, double penalty, double max_len,
+                   const float *q0, const float *goals, const float *Q, double *cost /* [E] */,
+                   double *minsd /* [E] */, int *flag /* [E] */)
+{
+    long E = (long)N + (long)(M - 1) * N * N + (long)N * G;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long e = 0; e < E; ++e) {
+        const float *pu, *pv;
+        or_edge_endpoints(M, N, G, mdl->d, q0, goals, Q, e, &pu, &pv);
+        or_edge(mdl, H, penalty, max_len, pu, pv, &cost[e], &minsd[e], &flag[e]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* a5: backward value iteration on the layered DAG (Sec. IV-B):             */
+/*   J at the goals = V_g (0 unless given);                                  */
+/*   V[M-1][u] = min_g C_l[u][g] + V_g[g];                                   */
+/*   V[m][u]   = min_v C_h[m][u][v] + V[m+1][v],   m = M-2 .. 0;             */
+/*   V_s       = min_u C_s[u] + V[0][u].                                     */
+/* A holds a minimiser (the lowest index among equal values); a row whose    */
+/* minimum is +inf has no minimiser and stores -1.                           */
+/* ------------------------------------------------------------------------ */
+static void or_row_min(int n, const double *c, const double *next, double *val, int *arg)
+{
+    double best = INFINITY;
+    int who = -1;
+    for (int v = 0; v < n; ++v) {
+        double s = c[v] + next[v];
+        if (s < best) {
+            best = s;
+            who = v;
+        }
+    }
+    *val = best;
+    *arg = who;
+}
+
+void or_minplus(int M, int N, int G, const double *Cs, const double *Ch, const double *Cl,
+                const double *Vg, double *V /* [M][N] */, int *A /* [M][N] */, double *Vs, int *as)
+{
+    double *vg = (double *)malloc(sizeof(double) * (size_t)G);
+    for (int g = 0; g < G; ++g) vg[g] = Vg ? Vg[g] : 0.0;
+    for (int u = 0; u < N; ++u)
+        or_row_min(G, Cl + (size_t)u * G, vg, &V[(size_t)(M - 1) * N + u], &A[(size_t)(M - 1) * N + u]);
+    for (int m = M - 2; m >= 0; --m)
+        for (int u = 0; u < N; ++u)
+            or_row_min(N, Ch + ((size_t)m * N + u) * N, V + (size_t)(m + 1) * N, &V[(size_t)m * N + u],
+                       &A[(size_t)m * N + u]);
+    or_row_min(N, Cs, V, Vs, as);
+    free(vg);
+}
+
+/* ------------------------------------------------------------------------ */
+/* a6: follow the minimisers from the start (Alg. 1 extraction; Sec. IV-B   */
+/* "applying it repeatedly from q0").  idx[m] = vertex of layer m           */
+/* (m = 0..M-1), idx[M] = goal index; waypoints [q0, Q[0][idx0], ...,       */
+/* Q[M-1][idx_{M-1}], goals[idx_M]].  Returns 0, or 1 when there is no path */
+/* (V_s = +inf), in which case idx is filled with -1.                       */
+/* ------------------------------------------------------------------------ */
+int or_extract(int M, int N, int G, int d, int as, const int *A, double Vs, const float *Q,
+               const float *q0, const float *goals, int *idx /* [M+1] */, double *wp /* [M+2][d] */,
+               double *cost)
+{
+    (void)G;
+    *cost = Vs;
+    if (as < 0 || isinf(Vs)) {
+        for (int m = 0; m <= M; ++m) idx[m] = -1;
+        return 1;
+    }
+    int i = as;
+    for (int j = 0; j < d; ++j) wp[j] = q0[j];
+    for (int m = 0; m < M; ++m) {
+        idx[m] = i;
+        for (int j = 0; j < d; ++j) wp[(size_t)(m + 1) * d + j] = Q[((size_t)m * N + i) * d + j];
+        i = A[(size_t)m * N + i];
+    }
+    idx[M] = i;
+    for (int j = 0; j < d; ++j) wp[(size_t)(M + 1) * d + j] = goals[(size_t)i * d + j];
+    return 0;
+}

@@ -1,0 +1,213 @@
+// api.hip -- the C ABI of include/gtmp.h: host-side validation, translation of
+// the public structs into kernel arguments, and dispatch to the launchers.
+// No C++ exception crosses the boundary; every failure returns a status and
+// records a thread-local message.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "gtmp_launch.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+gtmp_status fail(gtmp_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+gtmp_status hip_status(hipError_t e, const char *where) {
+    if (e == hipSuccess) return GTMP_OK;
+    return fail(GTMP_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+gtmp_status check_problem(const gtmp_problem *p) {
+    if (!p) return fail(GTMP_EINVAL, "problem is NULL");
+    if (p->d < 1 || p->d > GTMP_MAX_DOF) return fail(GTMP_EINVAL, "d=%d outside 1..%d", p->d, GTMP_MAX_DOF);
+    if (p->M < 1) return fail(GTMP_EINVAL, "M=%d < 1", p->M);
+    if (p->N < 1) return fail(GTMP_EINVAL, "N=%d < 1", p->N);
+    if (p->G < 1) return fail(GTMP_EINVAL, "G=%d < 1", p->G);
+    if (p->H < 2 || p->H > GTMP_MAX_H) return fail(GTMP_EINVAL, "H=%d outside 2..%d", p->H, GTMP_MAX_H);
+    for (int j = 0; j < p->d; ++j)
+        if (!(isfinite(p->lo[j]) && isfinite(p->hi[j]) && p->lo[j] < p->hi[j]))
+            return fail(GTMP_EINVAL, "sampling box coordinate %d: lo=%g hi=%g", j, (double)p->lo[j], (double)p->hi[j]);
+    if (isnan(p->penalty) || p->penalty < 0.f) return fail(GTMP_EINVAL, "penalty must be >= 0 or +inf");
+    if (isnan(p->max_edge_len) || p->max_edge_len <= 0.f) return fail(GTMP_EINVAL, "max_edge_len must be > 0 or +inf");
+    const unsigned long long N = (unsigned long long)p->N;
+    const unsigned long long E = N + (unsigned long long)(p->M - 1) * N * N + N * (unsigned long long)p->G;
+    if (E >= (1ull << 32)) return fail(GTMP_EINVAL, "edge count %llu exceeds 2^32 - 1", E);
+    const unsigned long long V = 1ull + (unsigned long long)p->M * N + (unsigned long long)p->G;
+    if (V >= (1ull << 31)) return fail(GTMP_EINVAL, "vertex count too large");
+    return GTMP_OK;
+}
+
+gtmp_status to_arm(const gtmp_robot *r, int d, gtmp::ArmParams *out) {
+    if (r->n_joints != d) return fail(GTMP_EINVAL, "arm n_joints=%d must equal d=%d", r->n_joints, d);
+    if (r->n_joints < 1 || r->n_joints > GTMP_MAX_JOINTS) return fail(GTMP_EINVAL, "n_joints=%d", r->n_joints);
+    if (r->n_spheres < 1 || r->n_spheres > GTMP_MAX_ROBOT_SPHERES)
+        return fail(GTMP_EINVAL, "n_spheres=%d outside 1..%d", r->n_spheres, GTMP_MAX_ROBOT_SPHERES);
+    gtmp::ArmParams a{};
+    a.n_joints = r->n_joints;
+    a.n_spheres = r->n_spheres;
+    for (int j = 0; j < r->n_joints; ++j) {
+        for (int c = 0; c < 4; ++c)
+            if (!isfinite(r->dh[j][c])) return fail(GTMP_EINVAL, "dh[%d][%d] not finite", j, c);
+        a.a[j] = r->dh[j][0];
+        a.dz[j] = r->dh[j][2];
+        a.off[j] = r->dh[j][3];
+        a.ca[j] = (float)cos((double)r->dh[j][1]);
+        a.sa[j] = (float)sin((double)r->dh[j][1]);
+    }
+    int prev = 1;
+    a.uniform_r = 1;
+    a.r0 = r->sph_r[0];
+    for (int k = 0; k < r->n_spheres; ++k) {
+        const int L = r->sph_link[k];
+        if (L < 1 || L > r->n_joints) return fail(GTMP_EINVAL, "sph_link[%d]=%d outside 1..%d", k, L, r->n_joints);
+        if (L < prev) return fail(GTMP_EINVAL, "spheres must be listed in non-decreasing link order");
+        prev = L;
+        if (!isfinite(r->sph_t[k]) || !isfinite(r->sph_r[k]) || r->sph_r[k] < 0.f)
+            return fail(GTMP_EINVAL, "sphere %d: bad t or radius", k);
+        a.link[k] = L;
+        a.t[k] = r->sph_t[k];
+        a.r[k] = r->sph_r[k];
+        if (r->sph_r[k] != a.r0) a.uniform_r = 0;
+    }
+    *out = a;
+    return GTMP_OK;
+}
+
+gtmp_status check_model(const gtmp_robot *robot, const gtmp_scene *scene, int d, gtmp::ArmParams *arm,
+                        bool *is_arm, gtmp::SceneParams *sp) {
+    if (!robot || !scene) return fail(GTMP_EINVAL, "robot or scene is NULL");
+    if (scene->wdim != 2 && scene->wdim != 3) return fail(GTMP_EINVAL, "scene wdim=%d must be 2 or 3", scene->wdim);
+    if (scene->n_spheres < 0 || scene->n_boxes < 0) return fail(GTMP_EINVAL, "negative obstacle count");
+    if (scene->n_spheres > 0 && !scene->spheres) return fail(GTMP_EINVAL, "scene spheres is NULL");
+    if (scene->n_boxes > 0 && !scene->boxes) return fail(GTMP_EINVAL, "scene boxes is NULL");
+    if (robot->kind == GTMP_ROBOT_POINT) {
+        if (scene->wdim != d) return fail(GTMP_EINVAL, "point robot needs wdim == d (%d vs %d)", scene->wdim, d);
+        *is_arm = false;
+    } else if (robot->kind == GTMP_ROBOT_DH_ARM) {
+        if (scene->wdim != 3) return fail(GTMP_EINVAL, "arm needs a 3D scene");
+        const gtmp_status st = to_arm(robot, d, arm);
+        if (st != GTMP_OK) return st;
+        *is_arm = true;
+    } else {
+        return fail(GTMP_EINVAL, "unknown robot kind %d", robot->kind);
+    }
+    sp->sph = scene->spheres;
+    sp->box = scene->boxes;
+    sp->n_sph = scene->n_spheres;
+    sp->n_box = scene->n_boxes;
+    return GTMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gtmp_status_string(gtmp_status s) {
+    switch (s) {
+        case GTMP_OK: return "GTMP_OK";
+        case GTMP_ENOPATH: return "GTMP_ENOPATH";
+        case GTMP_EINVAL: return "GTMP_EINVAL";
+        case GTMP_EHIP: return "GTMP_EHIP";
+        case GTMP_EWORKSPACE: return "GTMP_EWORKSPACE";
+        default: return "GTMP_UNKNOWN";
+    }
+}
+
+const char *gtmp_last_error(void) { return g_err; }
+
+const char *gtmp_version(void) { return "gtmp-gfx950 0.1"; }
+
+gtmp_status gtmp_sample_layers(const gtmp_problem *prob, uint64_t seed, uint64_t stage, float *Q, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (!Q) return fail(GTMP_EINVAL, "Q is NULL");
+    return hip_status(gtmp::launch_sample_layers(*prob, seed, stage, Q, (hipStream_t)stream), "gtmp_sample_layers");
+}
+
+gtmp_status gtmp_edge_check_workspace_size(const gtmp_problem *prob, size_t *bytes) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::make_edge_plan(*prob).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                                 const float *q0, const float *goals, const float *Q, float *C_s, float *C_h,
+                                 float *C_l, float *minsd, uint8_t *flags, const uint8_t *prune, void *workspace,
+                                 size_t ws_bytes, const gtmp_edge_opts *opts, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    gtmp::ArmParams arm{};
+    gtmp::SceneParams sp{};
+    bool is_arm = false;
+    st = check_model(robot, scene, prob->d, &arm, &is_arm, &sp);
+    if (st != GTMP_OK) return st;
+    if (!q0 || !goals || !Q || !C_s || !C_l) return fail(GTMP_EINVAL, "q0, goals, Q, C_s and C_l must be non-NULL");
+    if (prob->M > 1 && !C_h) return fail(GTMP_EINVAL, "C_h is NULL with M > 1");
+    const gtmp::EdgePlan plan = gtmp::make_edge_plan(*prob);
+    if (!workspace) return fail(GTMP_EINVAL, "workspace is NULL");
+    if (ws_bytes < plan.total)
+        return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, plan.total);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    gtmp_edge_opts o{};
+    if (opts) o = *opts;
+    if (o.mode != GTMP_CHECK_FAST && o.mode != GTMP_CHECK_FULL) return fail(GTMP_EINVAL, "unknown mode %d", o.mode);
+    if (o.states_per_iter < 0 || o.states_per_iter > 8) return fail(GTMP_EINVAL, "states_per_iter=%d", o.states_per_iter);
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 32) return fail(GTMP_EINVAL, "blocks_per_cu=%d", o.blocks_per_cu);
+    gtmp::EdgeBuffers b{q0, goals, Q, C_s, C_h, C_l, minsd, flags, prune, workspace};
+    return hip_status(gtmp::launch_edge_check(plan, is_arm ? &arm : nullptr, sp, scene->wdim, b, o, (hipStream_t)stream),
+                      "gtmp_edge_check_cost");
+}
+
+gtmp_status gtmp_state_check(const gtmp_robot *robot, const gtmp_scene *scene, int32_t d, int64_t n, const float *X,
+                             float *sd, uint8_t *coll, void *stream) {
+    g_err[0] = 0;
+    if (d < 1 || d > GTMP_MAX_DOF) return fail(GTMP_EINVAL, "d=%d", d);
+    if (n < 0) return fail(GTMP_EINVAL, "n=%lld < 0", (long long)n);
+    gtmp::ArmParams arm{};
+    gtmp::SceneParams sp{};
+    bool is_arm = false;
+    gtmp_status st = check_model(robot, scene, d, &arm, &is_arm, &sp);
+    if (st != GTMP_OK) return st;
+    if (n > 0 && !X) return fail(GTMP_EINVAL, "X is NULL");
+    if (!sd && !coll) return fail(GTMP_EINVAL, "sd and coll are both NULL");
+    return hip_status(gtmp::launch_state_check(is_arm ? &arm : nullptr, sp, scene->wdim, d, n, X, sd, coll,
+                                               (hipStream_t)stream),
+                      "gtmp_state_check");
+}
+
+gtmp_status gtmp_minplus_sweep(int32_t M, int32_t N, int32_t G, const float *C_s, const float *C_h, const float *C_l,
+                               const float *Vg, float *V, int32_t *A, float *V_s, int32_t *a_s, void *stream) {
+    g_err[0] = 0;
+    if (M < 1 || N < 1 || G < 1) return fail(GTMP_EINVAL, "M=%d N=%d G=%d must be >= 1", M, N, G);
+    if ((long long)(M - 1) * N * (long long)N >= (1ll << 40)) return fail(GTMP_EINVAL, "C_h too large");
+    if (!C_s || !C_l || !V || !A || !V_s || !a_s) return fail(GTMP_EINVAL, "NULL buffer");
+    if (M > 1 && !C_h) return fail(GTMP_EINVAL, "C_h is NULL with M > 1");
+    return hip_status(gtmp::launch_minplus(M, N, G, C_s, C_h, C_l, Vg, V, A, V_s, a_s, (hipStream_t)stream),
+                      "gtmp_minplus_sweep");
+}
+
+gtmp_status gtmp_extract_path(int32_t M, int32_t N, int32_t G, int32_t d, const int32_t *a_s, const int32_t *A,
+                              const float *V_s, const float *Q, const float *q0, const float *goals, int32_t *idx,
+                              float *wp, float *cost, void *stream) {
+    g_err[0] = 0;
+    if (M < 1 || N < 1 || G < 1 || d < 1 || d > GTMP_MAX_DOF) return fail(GTMP_EINVAL, "bad sizes");
+    if (!a_s || !A || !V_s || !Q || !q0 || !goals || !idx || !wp || !cost) return fail(GTMP_EINVAL, "NULL buffer");
+    return hip_status(gtmp::launch_extract(M, N, G, d, a_s, A, V_s, Q, q0, goals, idx, wp, cost, (hipStream_t)stream),
+                      "gtmp_extract_path");
+}
+
+}  // extern "C"

@@ -1,0 +1,718 @@
+// edge.hip -- realisation and costing of every candidate edge of the layered
+// graph with the straight-line local planner (Sec. III-B; Alg. 1 "compute
+// cost matrices C_s, C_h, C_l"; the SEV planner of Sec. V).
+//
+// Fast mode (default) runs three kernels:
+//   1. k_vertices   : packs q0 | Q | goals into one vertex array and tests every
+//                     vertex once.  The endpoints are states h = 0 and h = H-1
+//                     of every edge that touches them, so an edge with a
+//                     colliding endpoint fails without further work.
+//   2. k_prepass    : one thread per edge, memory bound.  Writes the
+//                     provisional cost |v-u| + penalty (and flag 1) for every
+//                     edge and compacts the edges that still need their
+//                     interior states checked into per-tile candidate lists.
+//   3. k_interior   : persistent waves.  Each lane owns one candidate edge and
+//                     evaluates its interior states in bisection order,
+//                     stopping at the first collision; a lane whose edge is
+//                     done takes the next candidate of the wave's current tile
+//                     (ballot + mbcnt), so the wave stays full however the
+//                     early exits fall.  Only edges found free are written
+//                     again (cost |v-u|, flag 0).
+// Full mode evaluates the exact signed distance of every state of every edge
+// (lanes = states, wave-level segmented min per edge) and writes minsd.
+#include "gtmp_launch.hpp"
+
+namespace gtmp {
+
+// ------------------------------------------------------------------ plan
+EdgePlan make_edge_plan(const gtmp_problem &p) {
+    EdgePlan e{};
+    e.d = p.d; e.M = p.M; e.N = p.N; e.G = p.G; e.H = p.H;
+    e.penalty = p.penalty; e.max_len = p.max_edge_len;
+    e.n_vertices = 1u + (uint32_t)p.M * (uint32_t)p.N + (uint32_t)p.G;
+    e.rows = 1u + (uint32_t)(p.M - 1) * (uint32_t)p.N + (uint32_t)p.G;
+    e.tiles_per_row = (uint32_t)((p.N + kTile - 1) / kTile);
+    e.n_tiles = e.rows * e.tiles_per_row;
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t o = 0;
+    e.off_verts = o; o = up(o + sizeof(float) * (size_t)vertex_stride(p.d) * e.n_vertices);
+    e.off_vflag = o; o = up(o + e.n_vertices);
+    e.off_tile_off = o; o = up(o + (size_t)e.n_tiles * kTile);
+    e.off_tile_cnt = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
+    e.off_counter = o; o = up(o + 256);
+    e.total = o;
+    return e;
+}
+
+int interior_order(int H, uint8_t *order) {
+    // breadth-first bisection of [0, H-1]
+    int n = 0;
+    int qa[GTMP_MAX_H], qb[GTMP_MAX_H];
+    int head = 0, tail = 0;
+    qa[tail] = 0; qb[tail] = H - 1; ++tail;
+    while (head < tail) {
+        const int a = qa[head], b = qb[head];
+        ++head;
+        if (b - a < 2) continue;
+        const int mid = (a + b) / 2;
+        order[n++] = (uint8_t)mid;
+        qa[tail] = a; qb[tail] = mid; ++tail;
+        qa[tail] = mid; qb[tail] = b; ++tail;
+    }
+    return n;
+}
+
+// ------------------------------------------------------------------ kernel args
+struct EdgeArgs {
+    int d, M, N, G, H, dp;
+    float penalty, max_len;
+    uint32_t tiles_per_row, n_tiles, n_vertices;
+    const float *__restrict__ verts;
+    const uint8_t *__restrict__ vflag;
+    float *C_s, *C_h, *C_l;
+    uint8_t *flags;
+    const uint8_t *__restrict__ prune;
+    uint8_t *tile_off;
+    uint32_t *tile_cnt;
+    uint32_t *counter;  // [0] tile cursor of the interior kernel
+    unsigned long long *stats;
+    int n_int;
+    float tord[GTMP_MAX_H];  // t = h / (H-1) of the interior states, in check order
+};
+
+// Row / tile decoding.  Rows enumerate the edges by their shared endpoint:
+//   row 0                 : q0 -> layer 0 vertex n            (C_s[n])
+//   row 1 + m N + u       : layer m vertex u -> layer m+1 vertex n  (C_h[m][u][n])
+//   row 1 + (M-1) N + g   : layer M-1 vertex n -> goal g       (C_l[n][g])
+// n is the varying index of the row (0..N-1).  Vertex ids index the packed
+// array [q0 | Q[0][0..N) | ... | Q[M-1][0..N) | goals].
+struct RowInfo {
+    uint32_t u_base, u_step, v_base, v_step;  // vertex ids of (u, v) = base + n * step
+    uint64_t e_base, e_step;                  // flat edge id (C_s | C_h | C_l order)
+    float *c_base;                            // cost element of n = c_base + n * c_step
+    uint32_t c_step;
+};
+
+__device__ __forceinline__ RowInfo decode_row(const EdgeArgs &A, uint32_t row) {
+    RowInfo r;
+    const uint32_t N = (uint32_t)A.N;
+    const uint32_t inner_rows = (uint32_t)(A.M - 1) * N;
+    if (row == 0) {
+        r.u_base = 0; r.u_step = 0; r.v_base = 1; r.v_step = 1;
+        r.e_base = 0; r.e_step = 1; r.c_base = A.C_s; r.c_step = 1;
+    } else if (row <= inner_rows) {
+        const uint32_t ri = row - 1;       // = m N + u
+        const uint32_t m = ri / N;
+        r.u_base = 1 + ri; r.u_step = 0;
+        r.v_base = 1 + (m + 1) * N; r.v_step = 1;
+        r.e_base = (uint64_t)N + (uint64_t)ri * N; r.e_step = 1;
+        r.c_base = A.C_h + (size_t)ri * N; r.c_step = 1;
+    } else {
+        const uint32_t g = row - 1 - inner_rows;
+        r.u_base = 1 + (uint32_t)(A.M - 1) * N; r.u_step = 1;
+        r.v_base = 1 + (uint32_t)A.M * N + g; r.v_step = 0;
+        r.e_base = (uint64_t)N + (uint64_t)inner_rows * N + g; r.e_step = (uint32_t)A.G;
+        r.c_base = A.C_l + g; r.c_step = (uint32_t)A.G;
+    }
+    return r;
+}
+
+template <int D>
+__device__ __forceinline__ void load_vertex(const EdgeArgs &A, uint32_t vid, float (&x)[D]) {
+    const float *p = A.verts + (size_t)vid * A.dp;
+    if constexpr (D <= 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(p);
+        const float t[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int i = 0; i < D; ++i) x[i] = t[i];
+    } else {
+        const float4 a = *reinterpret_cast<const float4 *>(p);
+        const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+        const float t[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int i = 0; i < D; ++i) x[i] = t[i];
+    }
+}
+
+// Euclidean length in configuration space (FP32, fixed summation order so
+// that the pre-pass and the interior kernel produce the same value).
+template <int D>
+__device__ __forceinline__ float edge_len(const float (&u)[D], const float (&v)[D], int d) {
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+        if (i < d) {
+            const float t = v[i] - u[i];
+            acc = __builtin_fmaf(t, t, acc);
+        }
+    return __builtin_sqrtf(acc);
+}
+
+__device__ __forceinline__ float failed_cost(float len, float penalty) { return len + penalty; }
+
+// ------------------------------------------------------------------ robot adapters
+// Point robot in R^W: a state is one probe of radius 0.  Arm: a state is KP
+// probes (the collision spheres) obtained by forward kinematics.
+template <int W, int S>
+struct PointModel {
+    static constexpr bool kArm = false;
+    static constexpr int D = W;
+    static constexpr int KP = S;  // probes per evaluation = S states
+};
+
+template <int KPm>
+struct ArmModel {
+    static constexpr bool kArm = true;
+    static constexpr int D = GTMP_MAX_JOINTS;
+    static constexpr int KP = KPm;
+};
+
+__global__ void k_zero_u32(uint32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ------------------------------------------------------------------ 1. vertices
+template <int KP>
+__global__ void __launch_bounds__(256) k_vertices_arm(EdgeArgs A, ArmParams R, SceneParams S, const float *q0,
+                                                      const float *goals, const float *Q, float *verts,
+                                                      uint8_t *vflag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < A.n_vertices;
+    const uint32_t MN = (uint32_t)A.M * (uint32_t)A.N;
+    float q[GTMP_MAX_JOINTS];
+#pragma unroll
+    for (int j = 0; j < GTMP_MAX_JOINTS; ++j) q[j] = 0.f;
+    if (valid) {
+        const float *src = i == 0 ? q0 : (i <= MN ? Q + (size_t)(i - 1) * A.d : goals + (size_t)(i - 1 - MN) * A.d);
+#pragma unroll
+        for (int j = 0; j < GTMP_MAX_JOINTS; ++j)
+            if (j < A.d) q[j] = src[j];
+#pragma unroll
+        for (int j = 0; j < GTMP_MAX_JOINTS; ++j) verts[(size_t)i * A.dp + j] = q[j];
+    }
+    const v32f o = arm_fk<GTMP_MAX_JOINTS>(R, q);
+    Probes<3, KP> P;
+    arm_spheres<KP>(R, o, P);
+    float pr[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) pr[k] = k < R.n_spheres ? R.r[k] : 0.f;
+    const float gap = R.uniform_r ? probes_min_gap<3, KP, true>(P, pr, R.r0, S)
+                                  : probes_min_gap<3, KP, false>(P, pr, R.r0, S);
+    if (valid) vflag[i] = gap <= 0.f ? 1 : 0;
+}
+
+template <int W>
+__global__ void __launch_bounds__(256) k_vertices_point(EdgeArgs A, SceneParams S, const float *q0,
+                                                        const float *goals, const float *Q, float *verts,
+                                                        uint8_t *vflag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n_vertices) return;
+    const uint32_t MN = (uint32_t)A.M * (uint32_t)A.N;
+    const float *src = i == 0 ? q0 : (i <= MN ? Q + (size_t)(i - 1) * W : goals + (size_t)(i - 1 - MN) * W);
+    Probes<W, 1> P;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) verts[(size_t)i * A.dp + j] = j < W ? src[j] : 0.f;
+#pragma unroll
+    for (int j = 0; j < W; ++j) P.p[j][0] = src[j];
+    const float pr[1] = {0.f};
+    const float gap = probes_min_gap<W, 1, true>(P, pr, 0.f, S);
+    vflag[i] = gap <= 0.f ? 1 : 0;
+}
+
+// ------------------------------------------------------------------ 2. pre-pass
+template <int D>
+__global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
+    __shared__ uint32_t wave_cnt[kTile / kWave];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t row = tile / A.tiles_per_row;
+    const uint32_t seg = tile - row * A.tiles_per_row;
+    const RowInfo ri = decode_row(A, row);
+    const uint32_t n = seg * kTile + threadIdx.x;
+    const bool valid = n < (uint32_t)A.N;
+    bool cand = false;
+    if (valid) {
+        const uint32_t uid = ri.u_base + n * ri.u_step, vid = ri.v_base + n * ri.v_step;
+        float u[D], v[D];
+        load_vertex<D>(A, uid, u);
+        load_vertex<D>(A, vid, v);
+        const float len = edge_len<D>(u, v, A.d);
+        const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
+        bool failed = (A.vflag[uid] | A.vflag[vid]) != 0 || len > A.max_len;
+        if (A.prune) failed = failed || A.prune[e] != 0;
+        ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
+        if (A.flags) A.flags[e] = 1;
+        cand = !failed;
+    }
+    const uint64_t mask = ballot(cand);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) wave_cnt[w] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kTile / kWave; ++k) {
+        if (k < w) base += wave_cnt[k];
+        total += wave_cnt[k];
+    }
+    if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
+    if (threadIdx.x == 0) A.tile_cnt[tile] = total;
+}
+
+// ------------------------------------------------------------------ 3. interior
+// Persistent: blocks loop until the tile cursor runs past n_tiles.  Every
+// wave owns its tile cursor state; lanes own edges.
+template <class Model, bool UNIFORM_R>
+__global__ void __launch_bounds__(256, 3) k_interior(EdgeArgs A, ArmParams R, SceneParams S) {
+    constexpr int D = Model::D;
+    constexpr int KP = Model::KP;
+    constexpr bool ARM = Model::kArm;
+    constexpr int W = ARM ? 3 : D;
+    constexpr int SP = ARM ? 1 : KP;  // interior states per evaluation
+    __shared__ float tord[GTMP_MAX_H];
+    for (int i = threadIdx.x; i < A.n_int; i += blockDim.x) tord[i] = A.tord[i];
+    __syncthreads();
+
+    const int lane = lane_id();
+
+    // wave-uniform tile state
+    uint32_t tile = 0, cnt = 0, pos = 0;
+    RowInfo ri{};
+    bool exhausted = false;
+    unsigned long long n_states = 0, n_edges = 0;
+
+    // lane state
+    bool has = false;
+    float u[D], dv[D], len = 0.f;
+    float *cptr = nullptr;
+    uint64_t e = 0;
+    int j = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) { u[i] = 0.f; dv[i] = 0.f; }
+
+    float pr[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) pr[k] = ARM ? (k < R.n_spheres ? R.r[k] : 0.f) : 0.f;
+    const float r0 = ARM ? R.r0 : 0.f;
+
+    while (true) {
+        // ---- refill idle lanes from the current tile, taking new tiles as needed
+        uint64_t need = ballot(!has);
+        int n_need = __popcll(need);
+        while (n_need > 0 && !exhausted) {
+            const uint32_t avail = cnt - pos;
+            if (avail == 0) {
+                uint32_t t = 0;
+                if (lane == 0) t = atomicAdd(A.counter, 1u);
+                t = uniform(t);
+                if (t >= A.n_tiles) {
+                    exhausted = true;
+                    break;
+                }
+                tile = t;
+                const uint32_t row = t / A.tiles_per_row;
+                ri = decode_row(A, row);
+                cnt = uniform(A.tile_cnt[t]);
+                pos = 0;
+                continue;
+            }
+            const uint32_t take = avail < (uint32_t)n_need ? avail : (uint32_t)n_need;
+            const int r = rank_in(need);
+            if (!has && (uint32_t)r < take) {
+                const uint32_t seg = tile - (tile / A.tiles_per_row) * A.tiles_per_row;
+                const uint32_t n = seg * kTile + A.tile_off[(size_t)tile * kTile + pos + r];
+                const uint32_t uid = ri.u_base + n * ri.u_step, vid = ri.v_base + n * ri.v_step;
+                float v[D];
+                load_vertex<D>(A, uid, u);
+                load_vertex<D>(A, vid, v);
+                len = edge_len<D>(u, v, A.d);
+#pragma unroll
+                for (int i = 0; i < D; ++i) dv[i] = v[i] - u[i];
+                cptr = ri.c_base + (size_t)n * ri.c_step;
+                e = ri.e_base + (uint64_t)n * ri.e_step;
+                j = 0;
+                has = true;
+            }
+            pos += take;
+            n_edges += take;
+            need = ballot(!has);
+            n_need = __popcll(need);
+        }
+        const uint64_t busy = ballot(has);
+        if (busy == 0) break;  // exhausted and every lane idle
+        n_states += (unsigned long long)__popcll(busy) * SP;
+
+        // ---- evaluate the next interior state(s) of every busy lane
+        Probes<W, KP> P;
+        if constexpr (ARM) {
+            float q[D];
+            const float t = tord[has ? j : 0];
+#pragma unroll
+            for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, dv[i], u[i]);
+            const v32f o = arm_fk<D>(R, q);
+            arm_spheres<KP>(R, o, P);
+        } else {
+#pragma unroll
+            for (int s = 0; s < SP; ++s) {
+                int jj = j + s;
+                jj = jj < A.n_int ? jj : A.n_int - 1;
+                const float t = tord[has ? jj : 0];
+#pragma unroll
+                for (int i = 0; i < W; ++i) P.p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
+            }
+        }
+        const float gap = probes_min_gap<W, KP, UNIFORM_R>(P, pr, r0, S);
+        if (has) {
+            if (gap <= 0.f) {
+                has = false;  // failed: provisional cost and flag stand
+            } else {
+                j += SP;
+                if (j >= A.n_int) {
+                    *cptr = len;
+                    if (A.flags) A.flags[e] = 0;
+                    has = false;
+                }
+            }
+        }
+    }
+    if (A.stats && lane == 0) {
+        atomicAdd(&A.stats[0], n_states);
+        atomicAdd(&A.stats[1], n_edges);
+    }
+}
+
+// Edges with H == 2 have no interior state: the pre-pass result is final
+// except that every candidate edge is free.
+template <int D>
+__global__ void __launch_bounds__(kTile) k_finalize_no_interior(EdgeArgs A) {
+    const uint32_t tile = blockIdx.x;
+    const uint32_t cnt = A.tile_cnt[tile];
+    if (threadIdx.x >= cnt) return;
+    const uint32_t row = tile / A.tiles_per_row;
+    const uint32_t seg = tile - row * A.tiles_per_row;
+    const RowInfo ri = decode_row(A, row);
+    const uint32_t n = seg * kTile + A.tile_off[(size_t)tile * kTile + threadIdx.x];
+    float u[D], v[D];
+    load_vertex<D>(A, ri.u_base + n * ri.u_step, u);
+    load_vertex<D>(A, ri.v_base + n * ri.v_step, v);
+    ri.c_base[(size_t)n * ri.c_step] = edge_len<D>(u, v, A.d);
+    if (A.flags) A.flags[ri.e_base + (uint64_t)n * ri.e_step] = 0;
+}
+
+// ------------------------------------------------------------------ full mode
+// Exact signed distance of every state.  Lanes are (edge, state) pairs: HP
+// lanes (a power of two >= min(H, 64)) per edge, 64 / HP edges per wave; for
+// H > 64 each lane strides over the states.  The per-edge minimum is a
+// butterfly over the HP-lane segment.
+template <int W>
+__device__ __forceinline__ float state_sd_point(const float (&x)[W], const SceneParams &S) {
+    return point_sd<W>(x, S);
+}
+
+__device__ __forceinline__ float state_sd_arm(const ArmParams &R, const float (&q)[GTMP_MAX_JOINTS],
+                                              const SceneParams &S) {
+    const v32f o = arm_fk<GTMP_MAX_JOINTS>(R, q);
+    float best = __builtin_inff();
+    for (int k = 0; k < R.n_spheres; ++k) {
+        const int b = 3 * R.link[k];
+        const float t = R.t[k];
+        float c[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float lo = o[b - 3 + i];
+            const float hi = o[b + i];
+            c[i] = __builtin_fmaf(t, hi - lo, lo);
+        }
+        best = __builtin_fminf(best, point_sd<3>(c, S) - R.r[k]);
+    }
+    return best;
+}
+
+template <bool ARMK, int D>
+__global__ void __launch_bounds__(256) k_full(EdgeArgs A, ArmParams R, SceneParams S, float *minsd, int hp_log2) {
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+    const int HP = 1 << hp_log2;
+    const int epw = kWave / HP;
+    const int seg = lane >> hp_log2;
+    const int hl = lane & (HP - 1);
+    const uint64_t E = (uint64_t)A.N + (uint64_t)(A.M - 1) * A.N * A.N + (uint64_t)A.N * A.G;
+    const uint64_t inner_end = (uint64_t)A.N + (uint64_t)(A.M - 1) * A.N * A.N;
+    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t base = gw * epw; base < E; base += nw * epw) {
+        const uint64_t e = base + seg;
+        const bool valid = e < E;
+        uint32_t uid = 0, vid = 0;
+        float *cp = A.C_s;
+        if (valid) {
+            if (e < (uint64_t)A.N) {
+                uid = 0; vid = 1 + (uint32_t)e; cp = A.C_s + e;
+            } else if (e < inner_end) {
+                const uint64_t r = e - A.N;
+                const uint64_t ri = r / A.N, n = r - ri * A.N;  // ri = m N + u
+                const uint64_t m = ri / A.N;
+                uid = 1 + (uint32_t)ri; vid = 1 + (uint32_t)((m + 1) * A.N + n); cp = A.C_h + r;
+            } else {
+                const uint64_t r = e - inner_end;
+                const uint64_t n = r / A.G, g = r - n * A.G;
+                uid = 1 + (uint32_t)((A.M - 1) * A.N + n); vid = 1 + (uint32_t)A.M * A.N + (uint32_t)g;
+                cp = A.C_l + r;
+            }
+        }
+        float u[D], v[D];
+        load_vertex<D>(A, uid, u);
+        load_vertex<D>(A, vid, v);
+        float best = __builtin_inff();
+        for (int h0 = 0; h0 < A.H; h0 += HP) {
+            const int h = h0 + hl;
+            const bool act = h < A.H;
+            const float t = (float)(act ? h : A.H - 1) / (float)(A.H - 1);
+            float sd;
+            if constexpr (ARMK) {
+                float q[GTMP_MAX_JOINTS];
+#pragma unroll
+                for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, v[i] - u[i], u[i]);
+                sd = state_sd_arm(R, q, S);
+            } else {
+                float x[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) x[i] = __builtin_fmaf(t, v[i] - u[i], u[i]);
+                sd = state_sd_point<D>(x, S);
+            }
+            if (act) best = __builtin_fminf(best, sd);
+        }
+        for (int off = HP >> 1; off > 0; off >>= 1) best = __builtin_fminf(best, __shfl_xor(best, off));
+        if (valid && hl == 0) {
+            const float len = edge_len<D>(u, v, A.d);
+            bool failed = best <= 0.f || len > A.max_len;
+            if (A.prune) failed = failed || A.prune[e] != 0;
+            *cp = failed ? failed_cost(len, A.penalty) : len;
+            if (A.flags) A.flags[e] = failed ? 1 : 0;
+            if (minsd) minsd[e] = best;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ state check
+template <bool ARMK, int D, int KP>
+__global__ void __launch_bounds__(256) k_state_check(ArmParams R, SceneParams S, int d, int64_t n, const float *X,
+                                                     float *sd, uint8_t *coll) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    float x[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) x[j] = (valid && j < d) ? X[i * d + j] : 0.f;
+    if constexpr (ARMK) {
+        if (coll) {
+            const v32f o = arm_fk<D>(R, x);
+            Probes<3, KP> P;
+            arm_spheres<KP>(R, o, P);
+            float pr[KP];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) pr[k] = k < R.n_spheres ? R.r[k] : 0.f;
+            const float gap = R.uniform_r ? probes_min_gap<3, KP, true>(P, pr, R.r0, S)
+                                          : probes_min_gap<3, KP, false>(P, pr, R.r0, S);
+            if (valid) coll[i] = gap <= 0.f ? 1 : 0;
+        }
+        if (sd) {
+            const float s = state_sd_arm(R, x, S);
+            if (valid) sd[i] = s;
+        }
+    } else {
+        if (coll) {
+            Probes<D, 1> P;
+#pragma unroll
+            for (int j = 0; j < D; ++j) P.p[j][0] = x[j];
+            const float pr[1] = {0.f};
+            const float gap = probes_min_gap<D, 1, true>(P, pr, 0.f, S);
+            if (valid) coll[i] = gap <= 0.f ? 1 : 0;
+        }
+        if (sd && valid) sd[i] = point_sd<D>(x, S);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static int round_kp(int k) { return ((k + 7) / 8) * 8; }
+
+template <int KP>
+static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, const EdgeBuffers &b,
+                                const gtmp_edge_opts &o, int grid_persist, hipStream_t s, const float *q0,
+                                const float *goals, const float *Q, float *verts, uint8_t *vflag) {
+    const unsigned vb = (A.n_vertices + 255) / 256;
+    hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
+    hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
+    if (A.n_int == 0) {
+        hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    } else if (R.uniform_r) {
+        hipLaunchKernelGGL((k_interior<ArmModel<KP>, true>), dim3(grid_persist), dim3(256), 0, s, A, R, S);
+    } else {
+        hipLaunchKernelGGL((k_interior<ArmModel<KP>, false>), dim3(grid_persist), dim3(256), 0, s, A, R, S);
+    }
+    if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
+    (void)b;
+    return hipGetLastError();
+}
+
+template <int W, int SPI>
+static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, int grid_persist,
+                                 const gtmp_edge_opts &o, hipStream_t s) {
+    if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
+    if (A.n_int == 0)
+        hipLaunchKernelGGL(k_finalize_no_interior<W>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_interior<PointModel<W, SPI>, true>), dim3(grid_persist), dim3(256), 0, s, A, R, S);
+    if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t launch_point(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, int spi,
+                               int grid_persist, const gtmp_edge_opts &o, hipStream_t s, const float *q0,
+                               const float *goals, const float *Q, float *verts, uint8_t *vflag) {
+    const unsigned vb = (A.n_vertices + 255) / 256;
+    hipLaunchKernelGGL(k_vertices_point<W>, dim3(vb), dim3(256), 0, s, A, S, q0, goals, Q, verts, vflag);
+    hipLaunchKernelGGL(k_prepass<W>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    switch (spi) {
+        case 1: return launch_point_s<W, 1>(A, R, S, grid_persist, o, s);
+        case 2: return launch_point_s<W, 2>(A, R, S, grid_persist, o, s);
+        case 4: return launch_point_s<W, 4>(A, R, S, grid_persist, o, s);
+        default: return launch_point_s<W, 8>(A, R, S, grid_persist, o, s);
+    }
+}
+
+static int persistent_grid(const void *kernel, int block, int blocks_per_cu_req) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    int per_cu = blocks_per_cu_req;
+    if (per_cu <= 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0) != hipSuccess || occ <= 0) occ = 2;
+        per_cu = occ;
+    }
+    return cus * per_cu;
+}
+
+hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
+                             const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s) {
+    EdgeArgs A{};
+    A.d = plan.d; A.M = plan.M; A.N = plan.N; A.G = plan.G; A.H = plan.H; A.dp = vertex_stride(plan.d);
+    A.penalty = plan.penalty; A.max_len = plan.max_len;
+    A.tiles_per_row = plan.tiles_per_row; A.n_tiles = plan.n_tiles; A.n_vertices = plan.n_vertices;
+    char *ws = static_cast<char *>(b.workspace);
+    float *verts = reinterpret_cast<float *>(ws + plan.off_verts);
+    uint8_t *vflag = reinterpret_cast<uint8_t *>(ws + plan.off_vflag);
+    A.verts = verts; A.vflag = vflag;
+    A.C_s = b.C_s; A.C_h = b.C_h; A.C_l = b.C_l; A.flags = b.flags; A.prune = b.prune;
+    A.tile_off = reinterpret_cast<uint8_t *>(ws + plan.off_tile_off);
+    A.tile_cnt = reinterpret_cast<uint32_t *>(ws + plan.off_tile_cnt);
+    A.counter = reinterpret_cast<uint32_t *>(ws + plan.off_counter);
+    A.stats = o.stats;
+    uint8_t order[GTMP_MAX_H];
+    A.n_int = interior_order(plan.H, order);
+    for (int i = 0; i < A.n_int; ++i) A.tord[i] = (float)order[i] / (float)(plan.H - 1);
+
+    ArmParams R{};
+    if (arm) R = *arm;
+
+    const bool full = o.mode == GTMP_CHECK_FULL || b.minsd != nullptr;
+    if (full) {
+        // pack vertices (flags are not needed but the kernel is cheap)
+        const unsigned vb = (A.n_vertices + 255) / 256;
+        int hp = 1, hpl = 0;
+        const int hcap = plan.H < kWave ? plan.H : kWave;
+        while (hp < hcap) { hp <<= 1; ++hpl; }
+        const uint64_t E = (uint64_t)plan.N + (uint64_t)(plan.M - 1) * plan.N * plan.N + (uint64_t)plan.N * plan.G;
+        const uint64_t waves = (E + (kWave / hp) - 1) / (kWave / hp);
+        uint64_t blocks = (waves + 3) / 4;
+        if (blocks > 65536) blocks = 65536;
+        if (arm) {
+            const int kp = round_kp(R.n_spheres);
+            switch (kp) {
+#define GTMP_VA(K) case K: hipLaunchKernelGGL(k_vertices_arm<K>, dim3(vb), dim3(256), 0, s, A, R, scene, b.q0, b.goals, b.Q, verts, vflag); break;
+                GTMP_VA(8) GTMP_VA(16) GTMP_VA(24) GTMP_VA(32) GTMP_VA(40) GTMP_VA(48) GTMP_VA(56) GTMP_VA(64)
+#undef GTMP_VA
+                default: return hipErrorInvalidValue;
+            }
+            if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
+            hipLaunchKernelGGL((k_full<true, GTMP_MAX_JOINTS>), dim3((unsigned)blocks), dim3(256), 0, s, A, R, scene,
+                               b.minsd, hpl);
+            if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
+        } else if (wdim == 2) {
+            hipLaunchKernelGGL(k_vertices_point<2>, dim3(vb), dim3(256), 0, s, A, scene, b.q0, b.goals, b.Q, verts, vflag);
+            if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
+            hipLaunchKernelGGL((k_full<false, 2>), dim3((unsigned)blocks), dim3(256), 0, s, A, R, scene, b.minsd, hpl);
+            if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
+        } else {
+            hipLaunchKernelGGL(k_vertices_point<3>, dim3(vb), dim3(256), 0, s, A, scene, b.q0, b.goals, b.Q, verts, vflag);
+            if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
+            hipLaunchKernelGGL((k_full<false, 3>), dim3((unsigned)blocks), dim3(256), 0, s, A, R, scene, b.minsd, hpl);
+            if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
+        }
+        return hipGetLastError();
+    }
+
+    // fast mode: reset the tile cursor with a fill kernel (no memset node, so
+    // the sequence can be captured into a graph and replayed)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, A.counter, 1);
+    if (arm) {
+        const int kp = round_kp(R.n_spheres);
+        const void *kern = nullptr;
+        switch (kp) {
+#define GTMP_KK(K) case K: kern = R.uniform_r ? (const void *)k_interior<ArmModel<K>, true> : (const void *)k_interior<ArmModel<K>, false>; break;
+            GTMP_KK(8) GTMP_KK(16) GTMP_KK(24) GTMP_KK(32) GTMP_KK(40) GTMP_KK(48) GTMP_KK(56) GTMP_KK(64)
+#undef GTMP_KK
+            default: return hipErrorInvalidValue;
+        }
+        const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
+        switch (kp) {
+#define GTMP_LA(K) case K: return launch_arm_kp<K>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag);
+            GTMP_LA(8) GTMP_LA(16) GTMP_LA(24) GTMP_LA(32) GTMP_LA(40) GTMP_LA(48) GTMP_LA(56) GTMP_LA(64)
+#undef GTMP_LA
+            default: return hipErrorInvalidValue;
+        }
+    }
+    int spi = o.states_per_iter;
+    if (spi <= 0) spi = 4;
+    if (spi != 1 && spi != 2 && spi != 4) spi = 8;
+    if (wdim == 2) {
+        const void *kern = spi == 1 ? (const void *)k_interior<PointModel<2, 1>, true>
+                         : spi == 2 ? (const void *)k_interior<PointModel<2, 2>, true>
+                         : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true>
+                                    : (const void *)k_interior<PointModel<2, 8>, true>;
+        const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
+        return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag);
+    }
+    const void *kern = spi == 1 ? (const void *)k_interior<PointModel<3, 1>, true>
+                     : spi == 2 ? (const void *)k_interior<PointModel<3, 2>, true>
+                     : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true>
+                                : (const void *)k_interior<PointModel<3, 8>, true>;
+    const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
+    return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag);
+}
+
+hipError_t launch_state_check(const ArmParams *arm, const SceneParams &scene, int wdim, int d, int64_t n,
+                              const float *X, float *sd, uint8_t *coll, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    ArmParams R{};
+    if (arm) {
+        R = *arm;
+        switch (round_kp(R.n_spheres)) {
+#define GTMP_SC(K) case K: hipLaunchKernelGGL((k_state_check<true, GTMP_MAX_JOINTS, K>), dim3(blocks), dim3(256), 0, s, R, scene, d, n, X, sd, coll); break;
+            GTMP_SC(8) GTMP_SC(16) GTMP_SC(24) GTMP_SC(32) GTMP_SC(40) GTMP_SC(48) GTMP_SC(56) GTMP_SC(64)
+#undef GTMP_SC
+            default: return hipErrorInvalidValue;
+        }
+    } else if (wdim == 2) {
+        hipLaunchKernelGGL((k_state_check<false, 2, 1>), dim3(blocks), dim3(256), 0, s, R, scene, d, n, X, sd, coll);
+    } else {
+        hipLaunchKernelGGL((k_state_check<false, 3, 1>), dim3(blocks), dim3(256), 0, s, R, scene, d, n, X, sd, coll);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gtmp

@@ -1,0 +1,242 @@
+// gtmp_device.hpp -- device-side building blocks of the gfx950 planner:
+// counter-based RNG, the robot/obstacle collision model in the form the
+// kernels evaluate it, and wave64 helpers.  Included by the kernel sources
+// only; the public boundary is include/gtmp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gtmp.h"
+
+namespace gtmp {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit products whose halves are mixed with the other counter words
+// and the round key; the key advances by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo_a = 0xD2511F53u * c.x, hi_a = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo_b = 0xCD9E8D57u * c.z, hi_b = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// 24 high bits of a word as a float in [0, 1); exact in FP32.
+__device__ __forceinline__ float unit_from_word(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+// ---------------------------------------------------------------------------
+// Robot model as passed by value in kernel arguments (uniform for the whole
+// grid, so every field is read through the scalar unit).
+// ---------------------------------------------------------------------------
+struct ArmParams {
+    int n_joints;
+    int n_spheres;
+    int uniform_r;  // 1 if every collision sphere has radius r0
+    float r0;
+    float a[GTMP_MAX_JOINTS], dz[GTMP_MAX_JOINTS], off[GTMP_MAX_JOINTS];
+    float ca[GTMP_MAX_JOINTS], sa[GTMP_MAX_JOINTS];  // cos / sin of the twist
+    int link[GTMP_MAX_ROBOT_SPHERES];
+    float t[GTMP_MAX_ROBOT_SPHERES];
+    float r[GTMP_MAX_ROBOT_SPHERES];
+};
+
+// Obstacles: raw device arrays of the scene, spheres [n][wdim+1], boxes
+// [n][2*wdim].  They are read with wave-uniform indices through the constant
+// address space, which lets the compiler fetch them with scalar loads into
+// SGPRs (read-only for the lifetime of a launch).
+typedef const __attribute__((address_space(4))) float *cfp;
+
+struct SceneParams {
+    const float *sph;
+    const float *box;
+    int n_sph;
+    int n_box;
+};
+
+__device__ __forceinline__ cfp as_const(const float *p) { return (cfp)(p); }
+
+// ---------------------------------------------------------------------------
+// Collision test of a set of KP probe spheres against every obstacle.
+// Returns min over (probe, obstacle) of |p - closest point|^2 - R^2, so the
+// probe set is in collision iff the result is <= 0.  R = obstacle radius +
+// probe radius for sphere obstacles, probe radius for boxes.  Obstacles are
+// the outer loop: each obstacle is loaded once (scalar registers) and tested
+// against all probes held in vector registers.
+// ---------------------------------------------------------------------------
+template <int W, int KP>
+struct Probes {
+    float p[W][KP];
+};
+
+template <int W, int KP, bool UNIFORM_R>
+__device__ __forceinline__ float probes_min_gap(const Probes<W, KP> &P, const float (&pr)[KP], float r0,
+                                                const SceneParams &S) {
+    float m0 = __builtin_inff(), m1 = __builtin_inff();
+    const int ssph = W + 1;
+    const cfp sph = as_const(S.sph);
+    const cfp box = as_const(S.box);
+    for (int o = 0; o < S.n_sph; ++o) {
+        float c[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) c[i] = sph[o * ssph + i];
+        const float ro = sph[o * ssph + W];
+        const float R = ro + r0;
+        const float nR2 = -R * R;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            float g;
+            if (UNIFORM_R) {
+                g = nR2;
+            } else {
+                const float Rk = ro + pr[k];
+                g = -Rk * Rk;
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const float dlt = P.p[i][k] - c[i];
+                g = __builtin_fmaf(dlt, dlt, g);
+            }
+            if (k & 1) m1 = __builtin_fminf(m1, g);
+            else m0 = __builtin_fminf(m0, g);
+        }
+    }
+    const int sbox = 2 * W;
+    for (int o = 0; o < S.n_box; ++o) {
+        float lo[W], hi[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const float c = box[o * sbox + i];
+            const float h = box[o * sbox + W + i];
+            lo[i] = c - h;
+            hi[i] = c + h;
+        }
+        const float nr2 = -r0 * r0;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            float g = UNIFORM_R ? nr2 : -pr[k] * pr[k];
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const float x = P.p[i][k];
+                const float dlt = x - __builtin_amdgcn_fmed3f(x, lo[i], hi[i]);
+                g = __builtin_fmaf(dlt, dlt, g);
+            }
+            if (k & 1) m1 = __builtin_fminf(m1, g);
+            else m0 = __builtin_fminf(m0, g);
+        }
+    }
+    return __builtin_fminf(m0, m1);
+}
+
+// Exact signed distance of one workspace point to the obstacle set:
+// spheres |p - c| - r, boxes |max(q,0)| + min(max_i q_i, 0), q = |p - c| - h.
+template <int W>
+__device__ __forceinline__ float point_sd(const float (&p)[W], const SceneParams &S) {
+    float best = __builtin_inff();
+    for (int o = 0; o < S.n_sph; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const float dlt = p[i] - S.sph[o * (W + 1) + i];
+            acc = __builtin_fmaf(dlt, dlt, acc);
+        }
+        best = __builtin_fminf(best, __builtin_sqrtf(acc) - S.sph[o * (W + 1) + W]);
+    }
+    for (int o = 0; o < S.n_box; ++o) {
+        float out = 0.f, in = -__builtin_inff();
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const float q = __builtin_fabsf(p[i] - S.box[o * 2 * W + i]) - S.box[o * 2 * W + W + i];
+            const float qp = __builtin_fmaxf(q, 0.f);
+            out = __builtin_fmaf(qp, qp, out);
+            in = __builtin_fmaxf(in, q);
+        }
+        best = __builtin_fminf(best, __builtin_sqrtf(out) + __builtin_fminf(in, 0.f));
+    }
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// Serial-arm forward kinematics, standard DH: frame i+1 = frame i *
+// Rz(q_i + off_i) Tz(dz_i) Tx(a_i) Rx(alpha_i).  The frame is updated in place
+// (columns x, y, z and origin p).  The origins o_0..o_J are returned packed in
+// one 32-wide register vector [o_0.xyz, o_1.xyz, ...]; the sphere loop reads
+// it with wave-uniform indices (the link id of a sphere is the same for every
+// lane), which gfx9 serves with relative VGPR addressing.
+// ---------------------------------------------------------------------------
+typedef float v32f __attribute__((ext_vector_type(32)));
+
+template <int D>
+__device__ __forceinline__ v32f arm_fk(const ArmParams &A, const float (&q)[D]) {
+    v32f o = (v32f)(0.f);
+    float x0 = 1.f, x1 = 0.f, x2 = 0.f;
+    float y0 = 0.f, y1 = 1.f, y2 = 0.f;
+    float z0 = 0.f, z1 = 0.f, z2 = 1.f;
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if (j >= A.n_joints) break;
+        float st, ct;
+        sincosf(q[j] + A.off[j], &st, &ct);
+        const float xn0 = ct * x0 + st * y0, xn1 = ct * x1 + st * y1, xn2 = ct * x2 + st * y2;
+        const float yp0 = ct * y0 - st * x0, yp1 = ct * y1 - st * x1, yp2 = ct * y2 - st * x2;
+        p0 += A.a[j] * xn0 + A.dz[j] * z0;
+        p1 += A.a[j] * xn1 + A.dz[j] * z1;
+        p2 += A.a[j] * xn2 + A.dz[j] * z2;
+        const float ca = A.ca[j], sa = A.sa[j];
+        const float yn0 = ca * yp0 + sa * z0, yn1 = ca * yp1 + sa * z1, yn2 = ca * yp2 + sa * z2;
+        const float zn0 = ca * z0 - sa * yp0, zn1 = ca * z1 - sa * yp1, zn2 = ca * z2 - sa * yp2;
+        x0 = xn0; x1 = xn1; x2 = xn2;
+        y0 = yn0; y1 = yn1; y2 = yn2;
+        z0 = zn0; z1 = zn1; z2 = zn2;
+        o[3 * (j + 1) + 0] = p0;
+        o[3 * (j + 1) + 1] = p1;
+        o[3 * (j + 1) + 2] = p2;
+    }
+    return o;
+}
+
+// Collision sphere centres c_k = o_{L-1} + t_k (o_L - o_{L-1}); slots beyond
+// n_spheres are parked far away so that they can never collide.
+template <int KP>
+__device__ __forceinline__ void arm_spheres(const ArmParams &A, const v32f &o, Probes<3, KP> &P) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        if (k < A.n_spheres) {
+            const int b = 3 * A.link[k];
+            const float t = A.t[k];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float lo = o[b - 3 + i];
+                const float hi = o[b + i];
+                P.p[i][k] = __builtin_fmaf(t, hi - lo, lo);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) P.p[i][k] = 1.0e18f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int rank_in(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+}  // namespace gtmp

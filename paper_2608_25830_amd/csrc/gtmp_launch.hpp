@@ -1,0 +1,65 @@
+// gtmp_launch.hpp -- host-side launchers shared between the kernel sources
+// and the C-ABI layer (api.hip).  Arguments have been validated by the
+// caller; launchers only enqueue.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gtmp.h"
+#include "gtmp_device.hpp"
+
+namespace gtmp {
+
+// Vertex stride (floats) of the packed vertex array used by the edge kernels:
+// every vertex takes GTMP_MAX_DOF floats (zero padded), 32-byte aligned.
+inline int vertex_stride(int) { return GTMP_MAX_DOF; }
+
+constexpr int kTile = 256;  // edges per pre-pass tile (one block, one edge per thread)
+
+struct EdgePlan {
+    // sizes
+    int d, M, N, G, H;
+    float penalty, max_len;
+    // derived
+    uint32_t n_vertices;     // 1 + M N + G
+    uint32_t rows;           // 1 + (M-1) N + G
+    uint32_t tiles_per_row;  // ceil(N / kTile)
+    uint32_t n_tiles;
+    // workspace carve-up (byte offsets)
+    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_counter, total;
+};
+
+EdgePlan make_edge_plan(const gtmp_problem &p);
+
+struct EdgeBuffers {
+    const float *q0, *goals, *Q;
+    float *C_s, *C_h, *C_l;
+    float *minsd;
+    uint8_t *flags;
+    const uint8_t *prune;
+    void *workspace;
+};
+
+hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm /* NULL = point robot */,
+                             const SceneParams &scene, int wdim, const EdgeBuffers &b, const gtmp_edge_opts &o,
+                             hipStream_t s);
+
+hipError_t launch_state_check(const ArmParams *arm, const SceneParams &scene, int wdim, int d, int64_t n,
+                              const float *X, float *sd, uint8_t *coll, hipStream_t s);
+
+hipError_t launch_sample_layers(const gtmp_problem &p, uint64_t seed, uint64_t stage, float *Q, hipStream_t s);
+
+hipError_t launch_minplus(int M, int N, int G, const float *C_s, const float *C_h, const float *C_l,
+                          const float *Vg, float *V, int32_t *A, float *V_s, int32_t *a_s, hipStream_t s);
+
+hipError_t launch_extract(int M, int N, int G, int d, const int32_t *a_s, const int32_t *A, const float *V_s,
+                          const float *Q, const float *q0, const float *goals, int32_t *idx, float *wp,
+                          float *cost, hipStream_t s);
+
+// Bisection order of the interior states 1..H-2 (midpoint first, then the
+// midpoints of the remaining halves, breadth first).  Returns the count.
+int interior_order(int H, uint8_t *order_out);
+
+}  // namespace gtmp

@@ -1,0 +1,300 @@
+"""Python binding of libgtmp.so (include/gtmp.h).
+
+Argument marshalling only: every step of the planner runs in the library's
+HIP kernels.  PyTorch provides device memory and the current HIP stream.  The
+functions named ``gtmp_*`` map one to one onto the C entry points; ``Planner``
+strings them together for one plan (sample -> edge check -> min-plus sweep ->
+extraction) without any host synchronisation until results are read.
+
+If the shared library is missing, importing this module raises: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgtmp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2608_25830_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+GTMP_OK, GTMP_ENOPATH, GTMP_EINVAL, GTMP_EHIP, GTMP_EWORKSPACE = 0, 1, -1, -2, -3
+GTMP_MAX_DOF, GTMP_MAX_JOINTS, GTMP_MAX_ROBOT_SPHERES, GTMP_MAX_H = 8, 8, 64, 256
+GTMP_ROBOT_POINT, GTMP_ROBOT_DH_ARM = 0, 1
+GTMP_CHECK_FAST, GTMP_CHECK_FULL = 0, 1
+
+
+class GtmpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.gtmp_status_string(status).decode()}: {msg}")
+        self.status = status
+
+
+class gtmp_problem(C.Structure):
+    _fields_ = [("d", C.c_int32), ("M", C.c_int32), ("N", C.c_int32), ("G", C.c_int32), ("H", C.c_int32),
+                ("lo", C.c_float * GTMP_MAX_DOF), ("hi", C.c_float * GTMP_MAX_DOF),
+                ("penalty", C.c_float), ("max_edge_len", C.c_float)]
+
+
+class gtmp_robot(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_joints", C.c_int32), ("n_spheres", C.c_int32), ("reserved", C.c_int32),
+                ("dh", (C.c_float * 4) * GTMP_MAX_JOINTS),
+                ("sph_link", C.c_int32 * GTMP_MAX_ROBOT_SPHERES),
+                ("sph_t", C.c_float * GTMP_MAX_ROBOT_SPHERES),
+                ("sph_r", C.c_float * GTMP_MAX_ROBOT_SPHERES)]
+
+
+class gtmp_scene(C.Structure):
+    _fields_ = [("wdim", C.c_int32), ("n_spheres", C.c_int32), ("spheres", C.c_void_p),
+                ("n_boxes", C.c_int32), ("boxes", C.c_void_p)]
+
+
+class gtmp_edge_opts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("states_per_iter", C.c_int32), ("block", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("chunk", C.c_int32), ("reserved", C.c_int32 * 3),
+                ("stats", C.c_void_p), ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
+
+
+_vp = C.c_void_p
+_lib.gtmp_status_string.restype = C.c_char_p
+_lib.gtmp_status_string.argtypes = [C.c_int]
+_lib.gtmp_last_error.restype = C.c_char_p
+_lib.gtmp_version.restype = C.c_char_p
+_lib.gtmp_sample_layers.argtypes = [C.POINTER(gtmp_problem), C.c_uint64, C.c_uint64, _vp, _vp]
+_lib.gtmp_edge_check_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(C.c_size_t)]
+_lib.gtmp_edge_check_cost.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot), C.POINTER(gtmp_scene),
+                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
+                                      C.POINTER(gtmp_edge_opts), _vp]
+_lib.gtmp_state_check.argtypes = [C.POINTER(gtmp_robot), C.POINTER(gtmp_scene), C.c_int32, C.c_int64, _vp, _vp,
+                                  _vp, _vp]
+_lib.gtmp_minplus_sweep.argtypes = [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.gtmp_extract_path.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, _vp, _vp]
+
+EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample_layers",
+           "gtmp_edge_check_workspace_size", "gtmp_edge_check_cost", "gtmp_state_check", "gtmp_minplus_sweep",
+           "gtmp_extract_path"]
+
+
+def _check(st):
+    if st < 0:
+        raise GtmpError(st, _lib.gtmp_last_error().decode())
+    return st
+
+
+def _p(t):
+    """Device pointer of a tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def version() -> str:
+    return _lib.gtmp_version().decode()
+
+
+# --------------------------------------------------------------------------- #
+# struct builders
+# --------------------------------------------------------------------------- #
+def make_problem(d, M, N, G, H, lo, hi, penalty=1e3, max_edge_len=math.inf) -> gtmp_problem:
+    p = gtmp_problem()
+    p.d, p.M, p.N, p.G, p.H = int(d), int(M), int(N), int(G), int(H)
+    for j in range(min(int(d), GTMP_MAX_DOF)):
+        p.lo[j] = float(lo[j])
+        p.hi[j] = float(hi[j])
+    p.penalty = float(penalty)
+    p.max_edge_len = float(max_edge_len)
+    return p
+
+
+def make_point_robot() -> gtmp_robot:
+    r = gtmp_robot()
+    r.kind = GTMP_ROBOT_POINT
+    return r
+
+
+def make_arm_robot(dh, sph_link, sph_t, sph_r) -> gtmp_robot:
+    r = gtmp_robot()
+    r.kind = GTMP_ROBOT_DH_ARM
+    dh = np.asarray(dh, np.float32)
+    r.n_joints = dh.shape[0]
+    r.n_spheres = len(sph_link)
+    for i in range(dh.shape[0]):
+        for c in range(4):
+            r.dh[i][c] = float(dh[i, c])
+    for k in range(len(sph_link)):
+        r.sph_link[k] = int(sph_link[k])
+        r.sph_t[k] = float(sph_t[k])
+        r.sph_r[k] = float(sph_r[k])
+    return r
+
+
+class Scene:
+    """Obstacles resident on the device (keeps the tensors alive)."""
+
+    def __init__(self, wdim, spheres, boxes, device="cuda"):
+        self.wdim = int(wdim)
+        sp = np.ascontiguousarray(spheres, np.float32).reshape(-1, self.wdim + 1)
+        bx = np.ascontiguousarray(boxes, np.float32).reshape(-1, 2 * self.wdim)
+        # one extra element keeps a valid pointer for empty sets
+        self.spheres = torch.from_numpy(np.concatenate([sp.ravel(), np.zeros(4, np.float32)])).to(device)
+        self.boxes = torch.from_numpy(np.concatenate([bx.ravel(), np.zeros(4, np.float32)])).to(device)
+        self.c = gtmp_scene()
+        self.c.wdim = self.wdim
+        self.c.n_spheres = sp.shape[0]
+        self.c.spheres = self.spheres.data_ptr()
+        self.c.n_boxes = bx.shape[0]
+        self.c.boxes = self.boxes.data_ptr()
+
+
+# --------------------------------------------------------------------------- #
+# entry points (same names as the C ABI)
+# --------------------------------------------------------------------------- #
+def gtmp_sample_layers(prob: gtmp_problem, seed: int, stage: int, Q: torch.Tensor, stream=None):
+    return _check(_lib.gtmp_sample_layers(C.byref(prob), seed, stage, _p(Q), _stream(stream)))
+
+
+def gtmp_edge_check_workspace_size(prob: gtmp_problem) -> int:
+    n = C.c_size_t()
+    _check(_lib.gtmp_edge_check_workspace_size(C.byref(prob), C.byref(n)))
+    return n.value
+
+
+def gtmp_edge_check_cost(prob, robot, scene: Scene, q0, goals, Q, C_s, C_h, C_l, workspace, minsd=None, flags=None,
+                         prune=None, opts: gtmp_edge_opts | None = None, stream=None):
+    return _check(_lib.gtmp_edge_check_cost(
+        C.byref(prob), C.byref(robot), C.byref(scene.c), _p(q0), _p(goals), _p(Q), _p(C_s), _p(C_h), _p(C_l),
+        _p(minsd), _p(flags), _p(prune), _p(workspace), workspace.numel() * workspace.element_size(),
+        C.byref(opts) if opts is not None else None, _stream(stream)))
+
+
+def gtmp_state_check(robot, scene: Scene, d, X, sd=None, coll=None, stream=None):
+    n = X.shape[0] if X is not None else 0
+    return _check(_lib.gtmp_state_check(C.byref(robot), C.byref(scene.c), int(d), int(n), _p(X), _p(sd), _p(coll),
+                                        _stream(stream)))
+
+
+def gtmp_minplus_sweep(M, N, G, C_s, C_h, C_l, V, A, V_s, a_s, Vg=None, stream=None):
+    return _check(_lib.gtmp_minplus_sweep(int(M), int(N), int(G), _p(C_s), _p(C_h), _p(C_l), _p(Vg), _p(V), _p(A),
+                                          _p(V_s), _p(a_s), _stream(stream)))
+
+
+def gtmp_extract_path(M, N, G, d, a_s, A, V_s, Q, q0, goals, idx, wp, cost, stream=None):
+    return _check(_lib.gtmp_extract_path(int(M), int(N), int(G), int(d), _p(a_s), _p(A), _p(V_s), _p(Q), _p(q0),
+                                         _p(goals), _p(idx), _p(wp), _p(cost), _stream(stream)))
+
+
+# --------------------------------------------------------------------------- #
+# one plan
+# --------------------------------------------------------------------------- #
+@dataclass
+class PlanResult:
+    Q: torch.Tensor
+    C_s: torch.Tensor
+    C_h: torch.Tensor
+    C_l: torch.Tensor
+    V: torch.Tensor
+    A: torch.Tensor
+    V_s: torch.Tensor
+    a_s: torch.Tensor
+    idx: torch.Tensor
+    wp: torch.Tensor
+    cost: torch.Tensor
+    flags: torch.Tensor | None = None
+    minsd: torch.Tensor | None = None
+
+
+class Planner:
+    """Device buffers and structs for repeated plans on one workload.
+
+    ``w`` is a workload dict (see ``workloads.make_workload``): sizes, box,
+    penalty, start/goals and either 2D obstacles or an arm model with 3D
+    obstacles."""
+
+    def __init__(self, w, device="cuda", flags=False, minsd=False, max_edge_len=math.inf):
+        self.w = w
+        d, M, N, G, H = (int(w[k]) for k in ("d", "M", "N", "G", "H"))
+        self.d, self.M, self.N, self.G, self.H = d, M, N, G, H
+        self.prob = make_problem(d, M, N, G, H, w["lo"], w["hi"], w["penalty"], max_edge_len)
+        if w["kind"] == "point2d":
+            self.robot = make_point_robot()
+            self.scene = Scene(2, w["circles"], w["boxes"], device)
+        else:
+            self.robot = make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"])
+            self.scene = Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+        f32 = dict(device=device, dtype=torch.float32)
+        self.q0 = torch.from_numpy(np.asarray(w["q0"], np.float32)).to(device)
+        self.goals = torch.from_numpy(np.asarray(w["goals"], np.float32).reshape(G, d)).to(device)
+        self.Q = torch.empty((M, N, d), **f32)
+        self.C_s = torch.empty((N,), **f32)
+        self.C_h = torch.empty((max(M - 1, 1), N, N), **f32)
+        self.C_l = torch.empty((N, G), **f32)
+        self.V = torch.empty((M, N), **f32)
+        self.A = torch.empty((M, N), device=device, dtype=torch.int32)
+        self.V_s = torch.empty((1,), **f32)
+        self.a_s = torch.empty((1,), device=device, dtype=torch.int32)
+        self.idx = torch.empty((M + 1,), device=device, dtype=torch.int32)
+        self.wp = torch.empty((M + 2, d), **f32)
+        self.cost = torch.empty((1,), **f32)
+        E = N + (M - 1) * N * N + N * G
+        self.E = E
+        self.flags = torch.empty((E,), device=device, dtype=torch.uint8) if flags else None
+        self.minsd = torch.empty((E,), **f32) if minsd else None
+        ws = gtmp_edge_check_workspace_size(self.prob)
+        self.workspace = torch.empty((ws + 255,), device=device, dtype=torch.uint8)
+        off = (-self.workspace.data_ptr()) % 256
+        self.workspace = self.workspace[off:off + ws]
+        self.stats = torch.zeros((4,), device=device, dtype=torch.int64)
+        self.opts = gtmp_edge_opts()
+        self.opts.stats = self.stats.data_ptr()
+
+    def sample(self, seed, stage=0, stream=None):
+        gtmp_sample_layers(self.prob, seed, stage, self.Q, stream)
+
+    def check(self, stream=None, prune=None):
+        gtmp_edge_check_cost(self.prob, self.robot, self.scene, self.q0, self.goals, self.Q, self.C_s,
+                             self.C_h if self.M > 1 else None, self.C_l, self.workspace, self.minsd, self.flags,
+                             prune, self.opts, stream)
+
+    def sweep(self, stream=None):
+        gtmp_minplus_sweep(self.M, self.N, self.G, self.C_s, self.C_h if self.M > 1 else None, self.C_l, self.V,
+                           self.A, self.V_s, self.a_s, None, stream)
+
+    def extract(self, stream=None):
+        gtmp_extract_path(self.M, self.N, self.G, self.d, self.a_s, self.A, self.V_s, self.Q, self.q0, self.goals,
+                          self.idx, self.wp, self.cost, stream)
+
+    def plan(self, seed, stage=0, Q=None, stream=None):
+        """One whole plan; with ``Q`` given the samples are copied in instead
+        of drawn (warm-start samples, Alg. 1 optional input)."""
+        if Q is None:
+            self.sample(seed, stage, stream)
+        else:
+            self.Q.copy_(Q)
+        self.check(stream)
+        self.sweep(stream)
+        self.extract(stream)
+        return self.result()
+
+    def result(self) -> PlanResult:
+        return PlanResult(self.Q, self.C_s, self.C_h, self.C_l, self.V, self.A, self.V_s, self.a_s, self.idx, self.wp,
+                          self.cost, self.flags, self.minsd)
