@@ -29,6 +29,23 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
 
+# HBM bytes per launch of the interior checker on each workload, from the
+# FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/ (scaled by the
+# plain-copy calibration).  A value is only reported while the kernel sources
+# still hash to the fingerprint it was measured on.
+MEASURED_TRAFFIC = {"arm7": (52.38e6, "183f662d58bceb9f", "profiles/k_interior_arm7.md")}
+KERNEL_SOURCES = ["paper_2608_25830_amd/csrc/edge.hip", "paper_2608_25830_amd/csrc/gtmp_device.hpp",
+                  "paper_2608_25830_amd/csrc/gtmp_launch.hpp"]
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def arm_state_flops(n_joints, n_spheres, n_obs_sph, n_obs_box, d):
     """Algorithmic FP32 operations of one state evaluation in the interior
@@ -81,6 +98,11 @@ def main():
     ap.add_argument("--scene", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--opt", action="append", default=[],
+                    help="edge-check option as field=value (fields of gtmp_edge_opts, e.g. sphere_chunks=1)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="before the plans, copy a buffer of this many MiB once (reference kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the planner is not built for "
@@ -94,8 +116,18 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = wl.make_workload(args.workload, args.scene)
     pl = gtmp.Planner(w)
+    for kv in args.opt:
+        k, v = kv.split("=")
+        setattr(pl.opts, k, int(v))
     M, N, G, H, d = pl.M, pl.N, pl.G, pl.H, pl.d
     E = pl.E
     def make_events(n):
@@ -141,6 +173,11 @@ def main():
     k_ms = float(np.mean(kernel_ms))
     st = float(np.mean(states))
     achieved = st * f_state / (k_ms / 1e3) / 1e12
+    traffic, traffic_src = None, None
+    if args.workload in MEASURED_TRAFFIC and not args.opt:
+        tb, fp, src = MEASURED_TRAFFIC[args.workload]
+        if fp == kernel_fingerprint():
+            traffic, traffic_src = tb, src
     out = {
         "metric": "edge-states checked/sec (7-DoF, N=2048)",
         "value": value,
@@ -159,10 +196,13 @@ def main():
                                f"{w['seed']}", "M": M, "N": N, "H": H, "d": d, "edges": E,
                    "edge_states": E * H},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic, "traffic_unit": "bytes/launch",
+                     "traffic_source": traffic_src,
                      "kernel": "k_interior (early-exit interior edge checker)",
                      "kernel_ms": k_ms, "states_evaluated_per_launch": st, "flop_per_state": f_state,
                      "states_evaluated_frac": st / (E * H)},
+        "edge_opts": {k: int(getattr(pl.opts, k)) for k in ("mode", "states_per_iter", "blocks_per_cu",
+                                                               "sphere_chunks")},
         "mean_path_cost": float(np.mean(costs)),
         "wall_s": wall,
     }

@@ -135,7 +135,8 @@ typedef struct gtmp_edge_opts {
     int32_t states_per_iter;  /* point robots: interior states per lane and iteration (1,2,4,8; 0 = auto) */
     int32_t block;            /* threads per block for the interior kernel (64..1024, multiple of 64; 0 = auto) */
     int32_t blocks_per_cu;    /* resident blocks per CU for the persistent interior kernel (0 = auto) */
-    int32_t chunk;            /* work-list items a wave takes per refill (0 = auto) */
+    int32_t sphere_chunks;    /* arms: the collision spheres of a state are tested in this many
+                                 chunks (1 or 2; 0 = auto = 2) */
     int32_t reserved[3];
     unsigned long long *stats; /* optional device [4]: states evaluated, edges checked in the
                                   interior pass, reserved, reserved.  Added to. */

@@ -11,8 +11,8 @@ with ctypes and adds the few pieces that are clearer in Python (brute-force
 enumeration of every chain on tiny graphs).
 
 Every function here is pinned by a test in ``tests/test_oracle_*.py`` against
-something other than itself: published Philox known-answer vectors and
-rocRAND's host generator, closed-form signed distances, a DH chain built from
+something other than itself: published Philox known-answer vectors,
+closed-form signed distances, a DH chain built from
 SciPy rotations, brute-force enumeration of all chains, SciPy's graph shortest
 path, and closed forms in obstacle-free space.
 """

@@ -167,6 +167,7 @@ gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *rob
     if (o.mode != GTMP_CHECK_FAST && o.mode != GTMP_CHECK_FULL) return fail(GTMP_EINVAL, "unknown mode %d", o.mode);
     if (o.states_per_iter < 0 || o.states_per_iter > 8) return fail(GTMP_EINVAL, "states_per_iter=%d", o.states_per_iter);
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 32) return fail(GTMP_EINVAL, "blocks_per_cu=%d", o.blocks_per_cu);
+    if (o.sphere_chunks < 0 || o.sphere_chunks > 2) return fail(GTMP_EINVAL, "sphere_chunks=%d", o.sphere_chunks);
     gtmp::EdgeBuffers b{q0, goals, Q, C_s, C_h, C_l, minsd, flags, prune, workspace};
     return hip_status(gtmp::launch_edge_check(plan, is_arm ? &arm : nullptr, sp, scene->wdim, b, o, (hipStream_t)stream),
                       "gtmp_edge_check_cost");

@@ -40,6 +40,7 @@ EdgePlan make_edge_plan(const gtmp_problem &p) {
     e.off_tile_off = o; o = up(o + (size_t)e.n_tiles * kTile);
     e.off_tile_cnt = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
     e.off_counter = o; o = up(o + 256);
+    e.off_params = o; o = up(o + sizeof(ArmParams));
     e.total = o;
     return e;
 }
@@ -76,6 +77,7 @@ struct EdgeArgs {
     uint32_t *tile_cnt;
     uint32_t *counter;  // [0] tile cursor of the interior kernel
     unsigned long long *stats;
+    size_t off_params;  // workspace byte offset of the device copy of the robot table
     int n_int;
     float tord[GTMP_MAX_H];  // t = h / (H-1) of the interior states, in check order
 };
@@ -166,6 +168,14 @@ struct ArmModel {
     static constexpr int D = GTMP_MAX_JOINTS;
     static constexpr int KP = KPm;
 };
+
+// Copy of the robot table (a kernel argument) into device memory.
+__global__ void k_store_params(ArmParams R, ArmParams *dst) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&R);
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+    constexpr int n = sizeof(ArmParams) / 4;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = src[i];
+}
 
 __global__ void k_zero_u32(uint32_t *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,14 +270,27 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
 
 // ------------------------------------------------------------------ 3. interior
 // Persistent: blocks loop until the tile cursor runs past n_tiles.  Every
-// wave owns its tile cursor state; lanes own edges.
-template <class Model, bool UNIFORM_R>
-__global__ void __launch_bounds__(256, 3) k_interior(EdgeArgs A, ArmParams R, SceneParams S) {
+// wave owns its tile cursor state; lanes own edges.  For an arm the KP
+// collision spheres of a state are tested in NCH chunks of KP / NCH spheres:
+// fewer live probe registers buy a higher occupancy for a few per-obstacle
+// set-up instructions more.
+__device__ __forceinline__ float *cost_slot(const EdgeArgs &A, uint32_t e) {
+    const uint32_t N = (uint32_t)A.N;
+    const uint32_t inner_end = N + (uint32_t)(A.M - 1) * N * N;
+    if (e < N) return A.C_s + e;
+    if (e < inner_end) return A.C_h + (e - N);
+    return A.C_l + (e - inner_end);
+}
+
+template <class Model, bool UNIFORM_R, int NCH>
+__global__ void __launch_bounds__(256, NCH == 1 ? 3 : 4) k_interior(EdgeArgs A, const ArmParams *Rg, SceneParams S) {
     constexpr int D = Model::D;
     constexpr int KP = Model::KP;
     constexpr bool ARM = Model::kArm;
     constexpr int W = ARM ? 3 : D;
     constexpr int SP = ARM ? 1 : KP;  // interior states per evaluation
+    constexpr int KC = ARM ? KP / NCH : KP;
+    static_assert(!ARM || KP % NCH == 0, "chunking must divide the sphere slots");
     __shared__ float tord[GTMP_MAX_H];
     for (int i = threadIdx.x; i < A.n_int; i += blockDim.x) tord[i] = A.tord[i];
     __syncthreads();
@@ -280,19 +303,14 @@ __global__ void __launch_bounds__(256, 3) k_interior(EdgeArgs A, ArmParams R, Sc
     bool exhausted = false;
     unsigned long long n_states = 0, n_edges = 0;
 
-    // lane state
+    // lane state: the edge (flat id), its start and direction, next state
     bool has = false;
-    float u[D], dv[D], len = 0.f;
-    float *cptr = nullptr;
-    uint64_t e = 0;
+    float u[D], dv[D];
+    uint32_t e = 0;
     int j = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) { u[i] = 0.f; dv[i] = 0.f; }
-
-    float pr[KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) pr[k] = ARM ? (k < R.n_spheres ? R.r[k] : 0.f) : 0.f;
-    const float r0 = ARM ? R.r0 : 0.f;
+    const float r0 = ARM ? Rg->r0 : 0.f;
 
     while (true) {
         // ---- refill idle lanes from the current tile, taking new tiles as needed
@@ -309,8 +327,7 @@ __global__ void __launch_bounds__(256, 3) k_interior(EdgeArgs A, ArmParams R, Sc
                     break;
                 }
                 tile = t;
-                const uint32_t row = t / A.tiles_per_row;
-                ri = decode_row(A, row);
+                ri = decode_row(A, t / A.tiles_per_row);
                 cnt = uniform(A.tile_cnt[t]);
                 pos = 0;
                 continue;
@@ -320,15 +337,12 @@ __global__ void __launch_bounds__(256, 3) k_interior(EdgeArgs A, ArmParams R, Sc
             if (!has && (uint32_t)r < take) {
                 const uint32_t seg = tile - (tile / A.tiles_per_row) * A.tiles_per_row;
                 const uint32_t n = seg * kTile + A.tile_off[(size_t)tile * kTile + pos + r];
-                const uint32_t uid = ri.u_base + n * ri.u_step, vid = ri.v_base + n * ri.v_step;
                 float v[D];
-                load_vertex<D>(A, uid, u);
-                load_vertex<D>(A, vid, v);
-                len = edge_len<D>(u, v, A.d);
+                load_vertex<D>(A, ri.u_base + n * ri.u_step, u);
+                load_vertex<D>(A, ri.v_base + n * ri.v_step, v);
 #pragma unroll
                 for (int i = 0; i < D; ++i) dv[i] = v[i] - u[i];
-                cptr = ri.c_base + (size_t)n * ri.c_step;
-                e = ri.e_base + (uint64_t)n * ri.e_step;
+                e = (uint32_t)(ri.e_base + (uint64_t)n * ri.e_step);
                 j = 0;
                 has = true;
             }
@@ -342,15 +356,36 @@ __global__ void __launch_bounds__(256, 3) k_interior(EdgeArgs A, ArmParams R, Sc
         n_states += (unsigned long long)__popcll(busy) * SP;
 
         // ---- evaluate the next interior state(s) of every busy lane
-        Probes<W, KP> P;
+        float gap;
         if constexpr (ARM) {
             float q[D];
             const float t = tord[has ? j : 0];
 #pragma unroll
             for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, dv[i], u[i]);
+            // The robot table is re-read through a pointer the compiler cannot
+            // see through, so each value is a short-lived scalar load at its
+            // use instead of a register held (and spilled) across the loop.
+            carm Rp = (carm)Rg;
+            asm volatile("" : "+s"(Rp));
+            const auto &R = *Rp;
             const v32f o = arm_fk<D>(R, q);
-            arm_spheres<KP>(R, o, P);
+            float pr[KC];
+            {
+                Probes<3, KC> P;
+                arm_spheres<KC, 0>(R, o, P);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) pr[k] = UNIFORM_R ? 0.f : (k < R.n_spheres ? R.r[k] : 0.f);
+                gap = probes_min_gap<3, KC, UNIFORM_R>(P, pr, r0, S);
+            }
+            if constexpr (NCH > 1) {
+                Probes<3, KC> P;
+                arm_spheres<KC, KC>(R, o, P);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) pr[k] = UNIFORM_R ? 0.f : (KC + k < R.n_spheres ? R.r[KC + k] : 0.f);
+                gap = __builtin_fminf(gap, probes_min_gap<3, KC, UNIFORM_R>(P, pr, r0, S));
+            }
         } else {
+            Probes<W, KP> P;
 #pragma unroll
             for (int s = 0; s < SP; ++s) {
                 int jj = j + s;
@@ -359,15 +394,23 @@ __global__ void __launch_bounds__(256, 3) k_interior(EdgeArgs A, ArmParams R, Sc
 #pragma unroll
                 for (int i = 0; i < W; ++i) P.p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
             }
+            float pr[KP];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) pr[k] = 0.f;
+            gap = probes_min_gap<W, KP, true>(P, pr, 0.f, S);
         }
-        const float gap = probes_min_gap<W, KP, UNIFORM_R>(P, pr, r0, S);
         if (has) {
             if (gap <= 0.f) {
                 has = false;  // failed: provisional cost and flag stand
             } else {
                 j += SP;
                 if (j >= A.n_int) {
-                    *cptr = len;
+                    // free edge: its cost is the length, computed as in the pre-pass
+                    float acc = 0.f;
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        if (i < A.d) acc = __builtin_fmaf(dv[i], dv[i], acc);
+                    *cost_slot(A, e) = __builtin_sqrtf(acc);
                     if (A.flags) A.flags[e] = 0;
                     has = false;
                 }
@@ -534,20 +577,22 @@ __global__ void __launch_bounds__(256) k_state_check(ArmParams R, SceneParams S,
 // ------------------------------------------------------------------ launchers
 static int round_kp(int k) { return ((k + 7) / 8) * 8; }
 
-template <int KP>
+template <int KP, int NCH>
 static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, const EdgeBuffers &b,
                                 const gtmp_edge_opts &o, int grid_persist, hipStream_t s, const float *q0,
                                 const float *goals, const float *Q, float *verts, uint8_t *vflag) {
     const unsigned vb = (A.n_vertices + 255) / 256;
     hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
     hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    ArmParams *Rg = reinterpret_cast<ArmParams *>(static_cast<char *>(b.workspace) + A.off_params);
+    hipLaunchKernelGGL(k_store_params, dim3(1), dim3(64), 0, s, R, Rg);
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
     } else if (R.uniform_r) {
-        hipLaunchKernelGGL((k_interior<ArmModel<KP>, true>), dim3(grid_persist), dim3(256), 0, s, A, R, S);
+        hipLaunchKernelGGL((k_interior<ArmModel<KP>, true, NCH>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     } else {
-        hipLaunchKernelGGL((k_interior<ArmModel<KP>, false>), dim3(grid_persist), dim3(256), 0, s, A, R, S);
+        hipLaunchKernelGGL((k_interior<ArmModel<KP>, false, NCH>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     }
     if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
     (void)b;
@@ -561,7 +606,8 @@ static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const Sc
     if (A.n_int == 0)
         hipLaunchKernelGGL(k_finalize_no_interior<W>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
     else
-        hipLaunchKernelGGL((k_interior<PointModel<W, SPI>, true>), dim3(grid_persist), dim3(256), 0, s, A, R, S);
+        hipLaunchKernelGGL((k_interior<PointModel<W, SPI>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A,
+                           (const ArmParams *)nullptr, S);
     if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
     return hipGetLastError();
 }
@@ -611,6 +657,7 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
     A.tile_cnt = reinterpret_cast<uint32_t *>(ws + plan.off_tile_cnt);
     A.counter = reinterpret_cast<uint32_t *>(ws + plan.off_counter);
     A.stats = o.stats;
+    A.off_params = plan.off_params;
     uint8_t order[GTMP_MAX_H];
     A.n_int = interior_order(plan.H, order);
     for (int i = 0; i < A.n_int; ++i) A.tord[i] = (float)order[i] / (float)(plan.H - 1);
@@ -660,17 +707,20 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, A.counter, 1);
     if (arm) {
         const int kp = round_kp(R.n_spheres);
+        const int nch = o.sphere_chunks == 1 ? 1 : 2;
         const void *kern = nullptr;
-        switch (kp) {
-#define GTMP_KK(K) case K: kern = R.uniform_r ? (const void *)k_interior<ArmModel<K>, true> : (const void *)k_interior<ArmModel<K>, false>; break;
-            GTMP_KK(8) GTMP_KK(16) GTMP_KK(24) GTMP_KK(32) GTMP_KK(40) GTMP_KK(48) GTMP_KK(56) GTMP_KK(64)
+        switch (kp * 4 + nch) {
+#define GTMP_KK(K, C) case K * 4 + C: kern = R.uniform_r ? (const void *)k_interior<ArmModel<K>, true, C> : (const void *)k_interior<ArmModel<K>, false, C>; break;
+            GTMP_KK(8, 1) GTMP_KK(16, 1) GTMP_KK(24, 1) GTMP_KK(32, 1) GTMP_KK(40, 1) GTMP_KK(48, 1) GTMP_KK(56, 1) GTMP_KK(64, 1)
+            GTMP_KK(8, 2) GTMP_KK(16, 2) GTMP_KK(24, 2) GTMP_KK(32, 2) GTMP_KK(40, 2) GTMP_KK(48, 2) GTMP_KK(56, 2) GTMP_KK(64, 2)
 #undef GTMP_KK
             default: return hipErrorInvalidValue;
         }
         const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
-        switch (kp) {
-#define GTMP_LA(K) case K: return launch_arm_kp<K>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag);
-            GTMP_LA(8) GTMP_LA(16) GTMP_LA(24) GTMP_LA(32) GTMP_LA(40) GTMP_LA(48) GTMP_LA(56) GTMP_LA(64)
+        switch (kp * 4 + nch) {
+#define GTMP_LA(K, C) case K * 4 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag);
+            GTMP_LA(8, 1) GTMP_LA(16, 1) GTMP_LA(24, 1) GTMP_LA(32, 1) GTMP_LA(40, 1) GTMP_LA(48, 1) GTMP_LA(56, 1) GTMP_LA(64, 1)
+            GTMP_LA(8, 2) GTMP_LA(16, 2) GTMP_LA(24, 2) GTMP_LA(32, 2) GTMP_LA(40, 2) GTMP_LA(48, 2) GTMP_LA(56, 2) GTMP_LA(64, 2)
 #undef GTMP_LA
             default: return hipErrorInvalidValue;
         }
@@ -679,17 +729,17 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
     if (spi <= 0) spi = 4;
     if (spi != 1 && spi != 2 && spi != 4) spi = 8;
     if (wdim == 2) {
-        const void *kern = spi == 1 ? (const void *)k_interior<PointModel<2, 1>, true>
-                         : spi == 2 ? (const void *)k_interior<PointModel<2, 2>, true>
-                         : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true>
-                                    : (const void *)k_interior<PointModel<2, 8>, true>;
+        const void *kern = spi == 1 ? (const void *)k_interior<PointModel<2, 1>, true, 1>
+                         : spi == 2 ? (const void *)k_interior<PointModel<2, 2>, true, 1>
+                         : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true, 1>
+                                    : (const void *)k_interior<PointModel<2, 8>, true, 1>;
         const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
         return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag);
     }
-    const void *kern = spi == 1 ? (const void *)k_interior<PointModel<3, 1>, true>
-                     : spi == 2 ? (const void *)k_interior<PointModel<3, 2>, true>
-                     : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true>
-                                : (const void *)k_interior<PointModel<3, 8>, true>;
+    const void *kern = spi == 1 ? (const void *)k_interior<PointModel<3, 1>, true, 1>
+                     : spi == 2 ? (const void *)k_interior<PointModel<3, 2>, true, 1>
+                     : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true, 1>
+                                : (const void *)k_interior<PointModel<3, 8>, true, 1>;
     const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
     return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag);
 }

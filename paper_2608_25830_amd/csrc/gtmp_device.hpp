@@ -64,6 +64,8 @@ struct SceneParams {
 
 __device__ __forceinline__ cfp as_const(const float *p) { return (cfp)(p); }
 
+typedef const __attribute__((address_space(4))) struct ArmParams *carm;
+
 // ---------------------------------------------------------------------------
 // Collision test of a set of KP probe spheres against every obstacle.
 // Returns min over (probe, obstacle) of |p - closest point|^2 - R^2, so the
@@ -77,60 +79,98 @@ struct Probes {
     float p[W][KP];
 };
 
+// Copy a wave-uniform value into a vector register (a plain v_mov; keeps the
+// compiler from folding the scalar operand back into every use).
+__device__ __forceinline__ float to_vgpr(float s) {
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+// s_waitcnt immediate for gfx9: lgkmcnt(0), vmcnt and expcnt left at their maxima
+constexpr int kWaitLgkm0 = 0xC07F;
+
 template <int W, int KP, bool UNIFORM_R>
 __device__ __forceinline__ float probes_min_gap(const Probes<W, KP> &P, const float (&pr)[KP], float r0,
                                                 const SceneParams &S) {
     float m0 = __builtin_inff(), m1 = __builtin_inff();
-    const int ssph = W + 1;
     const cfp sph = as_const(S.sph);
     const cfp box = as_const(S.box);
-    for (int o = 0; o < S.n_sph; ++o) {
-        float c[W];
+    // Scalar loads are software pipelined: the data of obstacle o + 1 is
+    // requested before obstacle o is tested, so the scalar-cache latency hides
+    // behind the vector work of the current obstacle.
+    if (S.n_sph > 0) {
+        float c[W + 1];
 #pragma unroll
-        for (int i = 0; i < W; ++i) c[i] = sph[o * ssph + i];
-        const float ro = sph[o * ssph + W];
-        const float R = ro + r0;
-        const float nR2 = -R * R;
+        for (int i = 0; i <= W; ++i) c[i] = sph[i];
+        // drain every scalar load issued so far, so that the only scalar load
+        // in flight inside the loop is the prefetch of the next obstacle
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        for (int o = 0; o < S.n_sph; ++o) {
+            const int on = o + 1 < S.n_sph ? o + 1 : o;
+            float cn[W + 1];
 #pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            float g;
-            if (UNIFORM_R) {
-                g = nR2;
-            } else {
-                const float Rk = ro + pr[k];
-                g = -Rk * Rk;
+            for (int i = 0; i <= W; ++i) cn[i] = sph[on * (W + 1) + i];
+            __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the tests
+            const float ro = c[W];
+            const float R = ro + r0;
+            const float nR2 = -R * R;
+            float cv[W];  // VGPR copies: the per-probe subtractions then read no SGPR
+#pragma unroll
+            for (int i = 0; i < W; ++i) cv[i] = to_vgpr(c[i]);
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                float g;
+                if (UNIFORM_R) {
+                    g = nR2;
+                } else {
+                    const float Rk = ro + pr[k];
+                    g = -Rk * Rk;
+                }
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    const float dlt = P.p[i][k] - cv[i];
+                    g = __builtin_fmaf(dlt, dlt, g);
+                }
+                if (k & 1) m1 = __builtin_fminf(m1, g);
+                else m0 = __builtin_fminf(m0, g);
             }
 #pragma unroll
-            for (int i = 0; i < W; ++i) {
-                const float dlt = P.p[i][k] - c[i];
-                g = __builtin_fmaf(dlt, dlt, g);
-            }
-            if (k & 1) m1 = __builtin_fminf(m1, g);
-            else m0 = __builtin_fminf(m0, g);
+            for (int i = 0; i <= W; ++i) c[i] = cn[i];
         }
     }
-    const int sbox = 2 * W;
-    for (int o = 0; o < S.n_box; ++o) {
-        float lo[W], hi[W];
+    if (S.n_box > 0) {
+        float b[2 * W];
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            const float c = box[o * sbox + i];
-            const float h = box[o * sbox + W + i];
-            lo[i] = c - h;
-            hi[i] = c + h;
-        }
-        const float nr2 = -r0 * r0;
+        for (int i = 0; i < 2 * W; ++i) b[i] = box[i];
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        for (int o = 0; o < S.n_box; ++o) {
+            const int on = o + 1 < S.n_box ? o + 1 : o;
+            float bn[2 * W];
 #pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            float g = UNIFORM_R ? nr2 : -pr[k] * pr[k];
+            for (int i = 0; i < 2 * W; ++i) bn[i] = box[on * 2 * W + i];
+            __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the tests
+            float lo[W], hi[W];
 #pragma unroll
             for (int i = 0; i < W; ++i) {
-                const float x = P.p[i][k];
-                const float dlt = x - __builtin_amdgcn_fmed3f(x, lo[i], hi[i]);
-                g = __builtin_fmaf(dlt, dlt, g);
+                lo[i] = b[i] - b[W + i];
+                hi[i] = b[i] + b[W + i];
             }
-            if (k & 1) m1 = __builtin_fminf(m1, g);
-            else m0 = __builtin_fminf(m0, g);
+            const float nr2 = -r0 * r0;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                float g = UNIFORM_R ? nr2 : -pr[k] * pr[k];
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    const float x = P.p[i][k];
+                    const float dlt = x - __builtin_amdgcn_fmed3f(x, lo[i], hi[i]);
+                    g = __builtin_fmaf(dlt, dlt, g);
+                }
+                if (k & 1) m1 = __builtin_fminf(m1, g);
+                else m0 = __builtin_fminf(m0, g);
+            }
+#pragma unroll
+            for (int i = 0; i < 2 * W; ++i) b[i] = bn[i];
         }
     }
     return __builtin_fminf(m0, m1);
@@ -174,9 +214,12 @@ __device__ __forceinline__ float point_sd(const float (&p)[W], const SceneParams
 // ---------------------------------------------------------------------------
 typedef float v32f __attribute__((ext_vector_type(32)));
 
-template <int D>
-__device__ __forceinline__ v32f arm_fk(const ArmParams &A, const float (&q)[D]) {
-    v32f o = (v32f)(0.f);
+template <int D, class AP>
+__device__ __forceinline__ v32f arm_fk(const AP &A, const float (&q)[D]) {
+    v32f o;  // only o_0 .. o_J are written and read
+    o[0] = 0.f;
+    o[1] = 0.f;
+    o[2] = 0.f;
     float x0 = 1.f, x1 = 0.f, x2 = 0.f;
     float y0 = 0.f, y1 = 1.f, y2 = 0.f;
     float z0 = 0.f, z1 = 0.f, z2 = 1.f;
@@ -204,12 +247,14 @@ __device__ __forceinline__ v32f arm_fk(const ArmParams &A, const float (&q)[D]) 
     return o;
 }
 
-// Collision sphere centres c_k = o_{L-1} + t_k (o_L - o_{L-1}); slots beyond
-// n_spheres are parked far away so that they can never collide.
-template <int KP>
-__device__ __forceinline__ void arm_spheres(const ArmParams &A, const v32f &o, Probes<3, KP> &P) {
+// Collision sphere centres c_k = o_{L-1} + t_k (o_L - o_{L-1}) for spheres
+// BASE .. BASE+KC-1; slots beyond n_spheres are parked far away so that they
+// can never collide.
+template <int KC, int BASE = 0, class AP>
+__device__ __forceinline__ void arm_spheres(const AP &A, const v32f &o, Probes<3, KC> &P) {
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
+    for (int kk = 0; kk < KC; ++kk) {
+        const int k = BASE + kk;
         if (k < A.n_spheres) {
             const int b = 3 * A.link[k];
             const float t = A.t[k];
@@ -217,11 +262,11 @@ __device__ __forceinline__ void arm_spheres(const ArmParams &A, const v32f &o, P
             for (int i = 0; i < 3; ++i) {
                 const float lo = o[b - 3 + i];
                 const float hi = o[b + i];
-                P.p[i][k] = __builtin_fmaf(t, hi - lo, lo);
+                P.p[i][kk] = __builtin_fmaf(t, hi - lo, lo);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) P.p[i][k] = 1.0e18f;
+            for (int i = 0; i < 3; ++i) P.p[i][kk] = 1.0e18f;
         }
     }
 }

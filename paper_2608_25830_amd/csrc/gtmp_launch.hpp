@@ -28,7 +28,7 @@ struct EdgePlan {
     uint32_t tiles_per_row;  // ceil(N / kTile)
     uint32_t n_tiles;
     // workspace carve-up (byte offsets)
-    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_counter, total;
+    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_counter, off_params, total;
 };
 
 EdgePlan make_edge_plan(const gtmp_problem &p);

@@ -60,7 +60,7 @@ class gtmp_scene(C.Structure):
 
 class gtmp_edge_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("states_per_iter", C.c_int32), ("block", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("chunk", C.c_int32), ("reserved", C.c_int32 * 3),
+                ("blocks_per_cu", C.c_int32), ("sphere_chunks", C.c_int32), ("reserved", C.c_int32 * 3),
                 ("stats", C.c_void_p), ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
 
 
