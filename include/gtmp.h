@@ -206,6 +206,83 @@ gtmp_status gtmp_extract_path(int32_t M, int32_t N, int32_t G, int32_t d, const 
                               const int32_t *A, const float *V_s, const float *Q, const float *q0,
                               const float *goals, int32_t *idx, float *wp, float *cost, void *stream);
 
+/* --------------------------------------- a7 growing-budget sampler */
+/* Alg. 1 expand-samples (Sec. IV-E): grow every layer from n_old to N samples,
+ * layer by layer in increasing m.  Each new slot (m, n) flips the coin of the
+ * sample mixture (Sec. III-A): heuristic half iff the top bit of word 0 of
+ * Philox at counter (n, m, stage, 2 << 16) is set, and only when a bound
+ * exists and both neighbour layers are non-empty (layer -1 = {q0}, layer M =
+ * the goals; layer m-1 as already expanded, layer m+1 at its old size).  The
+ * h-th heuristic slot of a layer takes the midpoint of the h-th closest
+ * (layer m-1, layer m+1) pair, ranked by FP32 squared distance summed in
+ * coordinate order without fused multiply-add, ties by (u, v) index; with
+ * fewer pairs it falls back to the uniform half.  The uniform half draws
+ * from the informed set {x : |x-q0| + |x-q_g| <= c} (goal 0) intersected with
+ * the box, c = *c_best; see gtmp_sample_informed.  Without a bound (c = +inf
+ * or c >= penalty) the uniform half is uniform in the box.
+ *   Q_old  device float32 [M][n_old][d] (ignored when n_old == 0)
+ *   Q_new  device float32 [M][N][d], written (the old samples are copied in)
+ *   c_best device float32 [1]
+ * Q_old and Q_new must not overlap. */
+gtmp_status gtmp_expand_workspace_size(const gtmp_problem *prob, size_t *bytes);
+gtmp_status gtmp_expand_samples(const gtmp_problem *prob, const float *q0, const float *goals, const float *Q_old,
+                                int32_t n_old, float *Q_new, const float *c_best, uint64_t seed, uint64_t stage,
+                                void *workspace, size_t ws_bytes, void *stream);
+
+/* Draws of the uniform half of the growing-budget sampler for slots
+ * (m, 0..count-1) at `stage`.  Informed set of Sec. IV-E by the direct method
+ * of Gammell et al. (2018), as an FP32 computation with a fixed operation
+ * order: y_i = (w_i >> 8) 2^-23 - 1 from Philox words at counter
+ * (n, m, stage, (1 << 16) | (2 a + j div 4)) for attempt a; accept iff
+ * sum y_i^2 < 1; z = (c/2 y_1, r2 y_2, ...) with r2 = sqrt(c^2 - c_min^2)/2,
+ * c_min = |q_g - q0|; x = (q0 + q_g)/2 + H z with the Householder reflection
+ * H = I - (2/w.w) w w^T, w = e_1 - (q_g - q0)/c_min; reject x outside the box.
+ * After 4096 attempts (or without a bound) x is the box sample of attempt 0.
+ *   X         device float32 [count][d]
+ *   attempts  device int32 [count] or NULL: attempts used, 0 unbounded, -1 fallback
+ *   workspace device, at least 1024 bytes */
+gtmp_status gtmp_sample_informed(const gtmp_problem *prob, const float *q0, const float *goals, const float *c_best,
+                                 uint64_t seed, uint64_t stage, int32_t m, int32_t count, float *X, int32_t *attempts,
+                                 void *workspace, void *stream);
+
+/* ------------------------------------------------- a7 anytime policies */
+#define GTMP_ANYTIME_RESTART 0 /* Anytime-GTMP: fixed (M, N), fresh samples every stage (Sec. IV-D) */
+#define GTMP_ANYTIME_GROWING 1 /* AO-GTMP: growing (M, N), informed expansion (Sec. IV-E) */
+
+typedef struct gtmp_anytime_opts {
+    int32_t mode;
+    int32_t max_stages;         /* stage cap (restart: the number of stages) */
+    int32_t M_min, M_max;       /* growing: layer schedule */
+    int32_t N_min, N_max;       /* growing: samples per layer */
+    int32_t use_graph;          /* restart: capture one stage as a hipGraph and replay it */
+    int32_t reserved;
+} gtmp_anytime_opts;
+
+/* Bytes of device workspace gtmp_plan_anytime needs (sizes of prob for a
+ * restart plan, of (M_max, N_max) for a growing one). */
+gtmp_status gtmp_anytime_workspace_size(const gtmp_problem *prob, const gtmp_anytime_opts *opts, size_t *bytes);
+
+/* Anytime policies with one homotopy class (|K| = 1): the archive keeps the
+ * lowest-cost path, a later stage replaces it only with a strictly lower
+ * cost (Alg. 1 anytime-gtmp / ao-gtmp; Sec. IV-C..E).
+ * Restart: stage s plans (M, N) of prob on samples drawn with key `seed` at
+ * stage s (gtmp_sample_layers).  Growing: starts at (M_min, N_min); after
+ * each stage N doubles (capped at N_max) while N < N_max, after which M grows
+ * by one per stage with every layer resampled (a new epoch); the loop ends
+ * after the stage run at (M_max, N_max) or after max_stages stages.  Each
+ * growing stage expands the samples with gtmp_expand_samples at stage s,
+ * bounded by the archive's cost.
+ * Outputs (device): best_cost [1]; best_idx [M_max + 1] and best_wp
+ * [(M_max + 2) d] for the best stage's (M); best_meta [4] = (best stage, its
+ * M, its N, stages run); stage_costs [max_stages].  prob->M, N give the
+ * restart sizes; prob->G, H, d, box and penalty apply to both.  The whole
+ * loop is enqueued on `stream` with no host synchronisation. */
+gtmp_status gtmp_plan_anytime(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                              const float *q0, const float *goals, uint64_t seed, const gtmp_anytime_opts *opts,
+                              float *best_cost, int32_t *best_idx, float *best_wp, int32_t *best_meta,
+                              float *stage_costs, void *workspace, size_t ws_bytes, const gtmp_edge_opts *edge_opts,
+                              void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,13 @@ def _declare(L):
     L.or_extract.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _ip, C.c_double, _fp, _fp, _fp,
                              _ip, _dp, _dp]
     L.or_extract.restype = C.c_int
+    L.or_informed_params.argtypes = [C.c_int, _fp, _fp, C.c_float, _fp, _fp, _fp, _fp, _fp]
+    L.or_sample_informed.argtypes = [C.c_int, _fp, _fp, _fp, _fp, C.c_float, C.c_float, C.c_uint64, C.c_uint64,
+                                     C.c_uint32, C.c_uint32, C.c_int, _fp]
+    L.or_sample_informed.restype = C.c_int
+    L.or_coin_heuristic.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]
+    L.or_coin_heuristic.restype = C.c_int
+    L.or_pair_d2_all.argtypes = [C.c_int, C.c_int, _fp, C.c_int, _fp, _fp]
 
 
 def threads() -> int:

@@ -1,0 +1,154 @@
+"""Oracle of the two anytime policies (Alg. 1 anytime-gtmp and ao-gtmp;
+Sec. IV-C..E) with one homotopy class (|K| = 1), and of the growing-budget
+sampler (Alg. 1 expand-samples).
+
+TEST INFRASTRUCTURE (see the package docstring).  Plain Python loops over
+stages, layers and slots; the arithmetic of each step is the C oracle's.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+
+MAX_ATTEMPTS = 4096
+
+
+def _bound(c, penalty):
+    """The cost bound of the informed set as the FP32 value the sampler uses;
+    None when there is no bound yet (no path, or only paths through a failed
+    edge)."""
+    c32 = np.float32(c)
+    if not np.isfinite(c32) or c32 >= np.float32(penalty):
+        return None
+    return c32
+
+
+def informed_draw(w, c, seed, stage, m, n):
+    """One draw of the uniform half for slot (m, n): the informed set
+    X_f(c) (Sec. IV-E) intersected with the box; uniform in the box without a
+    bound.  Returns (x float32[d], attempts)."""
+    d = w["d"]
+    out = np.zeros(d, np.float32)
+    lo, hi = O._f32(w["lo"]), O._f32(w["hi"])
+    q0, qg = O._f32(w["q0"]), O._f32(np.asarray(w["goals"])[0])
+    cc = np.inf if c is None else float(c)
+    a = O.lib().or_sample_informed(d, O._ptr(lo, O._fp), O._ptr(hi, O._fp), O._ptr(q0, O._fp), O._ptr(qg, O._fp),
+                                   cc, float(w["penalty"]), seed, stage, m, n, MAX_ATTEMPTS, O._ptr(out, O._fp))
+    return out, a
+
+
+def informed_params(d, q0, qg, c):
+    centre = np.zeros(d, np.float32)
+    H = np.zeros(d * d, np.float32)
+    r1, r2, cmin = (np.zeros(1, np.float32) for _ in range(3))
+    q0, qg = O._f32(q0), O._f32(qg)
+    O.lib().or_informed_params(d, O._ptr(q0, O._fp), O._ptr(qg, O._fp), float(c), O._ptr(centre, O._fp),
+                               O._ptr(H, O._fp), O._ptr(r1, O._fp), O._ptr(r2, O._fp), O._ptr(cmin, O._fp))
+    return centre, H.reshape(d, d), float(r1[0]), float(r2[0]), float(cmin[0])
+
+
+def coin_heuristic(seed, stage, m, n):
+    return bool(O.lib().or_coin_heuristic(seed, stage, m, n))
+
+
+def pair_order(prev, nxt):
+    """Pairs (a, b) of prev x nxt ranked by FP32 squared distance, ties by
+    (a, b): indices a * len(nxt) + b in rank order."""
+    prev, nxt = O._f32(prev), O._f32(nxt)
+    nu, nv = prev.shape[0], nxt.shape[0]
+    d2 = np.zeros((nu, nv), np.float32)
+    O.lib().or_pair_d2_all(prev.shape[1], nu, O._ptr(prev, O._fp), nv, O._ptr(nxt, O._fp), O._ptr(d2, O._fp))
+    return np.argsort(d2.ravel(), kind="stable")
+
+
+def expand_samples(w, Q, M, N, c_best, seed, stage):
+    """Alg. 1 expand-samples.  Q is a list of M float32 arrays [n_m][d]
+    (layers may be empty); returns the list grown to N samples per layer,
+    layers processed in increasing m."""
+    d = w["d"]
+    q0 = O._f32(w["q0"]).reshape(1, d)
+    goals = O._f32(w["goals"]).reshape(-1, d)
+    c = _bound(c_best, w["penalty"])
+    Q = [np.asarray(q, np.float32).reshape(-1, d).copy() for q in Q]
+    for m in range(M):
+        prev = q0 if m == 0 else Q[m - 1]
+        nxt = goals if m == M - 1 else Q[m + 1]
+        heuristic_ok = c is not None and prev.shape[0] > 0 and nxt.shape[0] > 0
+        order = pair_order(prev, nxt) if heuristic_ok else None
+        nv = nxt.shape[0]
+        n_old = Q[m].shape[0]
+        new = []
+        h = 0
+        for n in range(n_old, N):
+            heur = heuristic_ok and coin_heuristic(seed, stage, m, n)
+            if heur:
+                rank = h
+                h += 1
+                if rank < order.size:
+                    a, b = divmod(int(order[rank]), nv)
+                    new.append((prev[a] + nxt[b]) * np.float32(0.5))
+                    continue
+            x, _ = informed_draw(w, c, seed, stage, m, n)
+            new.append(x)
+        if new:
+            Q[m] = np.concatenate([Q[m], np.stack(new).astype(np.float32)], axis=0)
+    return Q
+
+
+def _plan_on(w, Qarr):
+    ww = dict(w)
+    ww["M"], ww["N"] = Qarr.shape[0], Qarr.shape[1]
+    return O.plan(ww, Q=Qarr)
+
+
+def plan_restart(w, stages, seed):
+    """Anytime-GTMP (Alg. 1; Sec. IV-D) with |K| = 1: stage s plans on the
+    samples of key (seed, s); the archive keeps the lowest cost (strictly
+    lower replaces, so ties keep the earlier stage)."""
+    best = dict(cost=np.inf, stage=-1, idx=None)
+    per_stage = []
+    for s in range(stages):
+        Q = O.sample_layers(w["M"], w["N"], w["d"], w["lo"], w["hi"], seed, s)
+        r = _plan_on(w, Q)
+        per_stage.append(r["path_cost"])
+        if r["path_cost"] < best["cost"]:
+            best = dict(cost=r["path_cost"], stage=s, idx=r["idx"].copy(), M=w["M"], N=w["N"])
+    return best, per_stage
+
+
+def growing_schedule(M_min, M_max, N_min, N_max, max_stages):
+    """(M, N, n_old) of each stage: N doubles (capped) while N < N_max, then M
+    grows by one per stage with a fresh epoch (n_old = 0); the loop ends after
+    the stage at (M_max, N_max) or at the stage cap."""
+    out = []
+    M, N, n_old = M_min, N_min, 0
+    for _ in range(max_stages):
+        out.append((M, N, n_old))
+        if M >= M_max and N >= N_max:
+            break
+        if N < N_max:
+            n_old, N = N, min(2 * N, N_max)
+        else:
+            M, n_old = M + 1, 0
+    return out
+
+
+def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed):
+    """AO-GTMP (Alg. 1; Sec. IV-E): expand the samples under the current
+    cost bound, plan, keep the best, grow the budget."""
+    d = w["d"]
+    best = dict(cost=np.inf, stage=-1, idx=None)
+    per_stage, stages = [], []
+    Q = None
+    for s, (M, N, n_old) in enumerate(growing_schedule(M_min, M_max, N_min, N_max, max_stages)):
+        if n_old == 0:
+            Q = [np.zeros((0, d), np.float32) for _ in range(M)]
+        Q = expand_samples(w, Q, M, N, best["cost"], seed, s)
+        Qarr = np.stack(Q).astype(np.float32)
+        r = _plan_on(w, Qarr)
+        per_stage.append(r["path_cost"])
+        stages.append(dict(M=M, N=N, Q=Qarr, cost=r["path_cost"], bound=best["cost"]))
+        if r["path_cost"] < best["cost"]:
+            best = dict(cost=r["path_cost"], stage=s, idx=r["idx"].copy(), M=M, N=N)
+    return best, per_stage, stages

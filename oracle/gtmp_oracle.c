@@ -374,3 +374,135 @@ int or_extract(int M, int N, int G, int d, int as, const int *A, double Vs, cons
     for (int j = 0; j < d; ++j) wp[(size_t)(M + 1) * d + j] = goals[(size_t)i * d + j];
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* a7: growing-budget sampler (Alg. 1 expand-samples; Sec. IV-E).           */
+/*                                                                          */
+/* Uniform half: a uniform draw from the informed set                       */
+/*   X_f(c) = {x : |x - q0| + |x - q_g| <= c}   (Sec. IV-E)                  */
+/* intersected with the sampling box, by the direct method of Gammell et    */
+/* al. (2018): a uniform point y of the unit d-ball, scaled per axis to the */
+/* hyperspheroid radii (c/2, sqrt(c^2 - c_min^2)/2, ...), rotated so that   */
+/* the first axis points from q0 to q_g, and moved to the centre            */
+/* (q0 + q_g)/2.  The ball point is drawn by rejection from the cube        */
+/* [-1, 1]^d; a transformed point outside the box is rejected as well.      */
+/* Without a bound (c = +inf or c >= the edge penalty) the draw is uniform  */
+/* in the box.                                                              */
+/*                                                                          */
+/* The sample is defined as an FP32 computation with a fixed operation     */
+/* order (no fused multiply-add), which this file reproduces with float     */
+/* arithmetic (compiled with -ffp-contract=off):                            */
+/*   y_i = (w_i >> 8) * 2^-23 - 1, accept iff sum_i y_i^2 < 1 (summed in i) */
+/*   z = (r1 y_1, r2 y_2, ..., r2 y_d)                                      */
+/*   x_i = centre_i + sum_j H_ij z_j (summed in j)                          */
+/* with the Householder reflection H = I - s w w^T, w = e_1 - a_1,          */
+/* s = 2 / (w^T w), a_1 = (q_g - q0)/c_min, H = I when w = 0.                */
+/* Random words: key (seed lo, seed hi), counter                            */
+/*   (n, m, stage, (1 << 16) | (2 * attempt + block)), block = j div 4.     */
+/* After max_attempts rejections the draw falls back to a uniform box       */
+/* sample from attempt 0's words.                                           */
+/* ------------------------------------------------------------------------ */
+void or_informed_params(int d, const float *q0, const float *qg, float c, float *centre, float *H,
+                        float *r1, float *r2, float *cmin_out)
+{
+    float acc = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        float t = qg[i] - q0[i];
+        acc = acc + t * t;
+    }
+    float cmin = sqrtf(acc);
+    *cmin_out = cmin;
+    for (int i = 0; i < d; ++i) centre[i] = (q0[i] + qg[i]) * 0.5f;
+    *r1 = c * 0.5f;
+    float sq = c * c - cmin * cmin;
+    *r2 = sqrtf(sq > 0.0f ? sq : 0.0f) * 0.5f;
+    float w[16];
+    float ww = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        float a = (qg[i] - q0[i]) / cmin;
+        w[i] = (i == 0 ? 1.0f : 0.0f) - a;
+        ww = ww + w[i] * w[i];
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            float delta = i == j ? 1.0f : 0.0f;
+            if (ww == 0.0f) {
+                H[i * d + j] = delta;
+            } else {
+                float s = 2.0f / ww;
+                H[i * d + j] = delta - (s * w[i]) * w[j];
+            }
+        }
+}
+
+/* Returns the number of attempts used, or -1 for the box fallback. */
+int or_sample_informed(int d, const float *lo, const float *hi, const float *q0, const float *qg, float c,
+                       float penalty, uint64_t seed, uint64_t stage, uint32_t m, uint32_t n, int max_attempts,
+                       float *out)
+{
+    int bounded = !(isinf(c) || c >= penalty);
+    if (bounded) {
+        float centre[16], H[256], r1, r2, cmin;
+        or_informed_params(d, q0, qg, c, centre, H, &r1, &r2, &cmin);
+        for (int a = 0; a < max_attempts; ++a) {
+            float y[16];
+            float s2 = 0.0f;
+            for (int i = 0; i < d; ++i) {
+                uint32_t w[4];
+                or_words(seed, stage, 1u, n, m, (uint32_t)(2 * a + i / 4), w);
+                y[i] = (float)(w[i % 4] >> 8) * (1.0f / 8388608.0f) - 1.0f;
+                s2 = s2 + y[i] * y[i];
+            }
+            if (!(s2 < 1.0f)) continue;
+            float z[16], x[16];
+            for (int i = 0; i < d; ++i) z[i] = (i == 0 ? r1 : r2) * y[i];
+            int inside = 1;
+            for (int i = 0; i < d; ++i) {
+                float acc = 0.0f;
+                for (int j = 0; j < d; ++j) acc = acc + H[i * d + j] * z[j];
+                x[i] = centre[i] + acc;
+                if (!(x[i] >= lo[i] && x[i] <= hi[i])) inside = 0;
+            }
+            if (!inside) continue;
+            for (int i = 0; i < d; ++i) out[i] = x[i];
+            return a + 1;
+        }
+    }
+    for (int i = 0; i < d; ++i) {
+        uint32_t w[4];
+        or_words(seed, stage, 1u, n, m, (uint32_t)(i / 4), w);
+        double u = or_unit_from_word(w[i % 4]);
+        double width = (double)(float)((double)hi[i] - (double)lo[i]);
+        out[i] = (float)((double)lo[i] + u * width);
+    }
+    return bounded ? -1 : 0;
+}
+
+/* Coin of the sample mixture (Sec. III-A): heuristic half iff the top bit of
+ * word 0 at counter (n, m, stage, 2 << 16) is set. */
+int or_coin_heuristic(uint64_t seed, uint64_t stage, uint32_t m, uint32_t n)
+{
+    uint32_t w[4];
+    or_words(seed, stage, 2u, n, m, 0u, w);
+    return (int)(w[0] >> 31);
+}
+
+/* Squared distance between two configurations, FP32, summed in coordinate
+ * order without fused multiply-add: the ranking of sample pairs by it is an
+ * integer decision both sides take in the same precision. */
+float or_pair_d2(int d, const float *u, const float *v)
+{
+    float acc = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        float t = u[i] - v[i];
+        acc = acc + t * t;
+    }
+    return acc;
+}
+
+void or_pair_d2_all(int d, int nu, const float *U, int nv, const float *V, float *out /* [nu][nv] */)
+{
+#pragma omp parallel for schedule(static)
+    for (int a = 0; a < nu; ++a)
+        for (int b = 0; b < nv; ++b) out[(size_t)a * nv + b] = or_pair_d2(d, U + (size_t)a * d, V + (size_t)b * d);
+}

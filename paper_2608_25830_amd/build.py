@@ -30,12 +30,15 @@ FLAGS = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
-SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip"]
+SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip"]
+# the growing-budget sampler is defined as an FP32 computation with a fixed
+# operation order: no contraction into fused multiply-adds in that file
+EXTRA = {"anytime.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -44,7 +47,7 @@ def _compile(src: str) -> str:
 
 def _asm(src: str) -> None:
     out = os.path.join(BUILD, os.path.splitext(src)[0] + f"-{ARCH}.s")
-    cmd = [HIPCC, *FLAGS, "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
 
 

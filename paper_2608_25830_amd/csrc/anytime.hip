@@ -1,0 +1,535 @@
+// anytime.hip -- the two iteration policies on top of one plan (Alg. 1
+// anytime-gtmp and ao-gtmp; Sec. IV-C..E) and the growing-budget sampler
+// (Alg. 1 expand-samples).
+//
+// This file is compiled without floating-point contraction: the informed
+// sampler and the ranking of sample pairs are defined as FP32 computations
+// with a fixed operation order (see include/gtmp.h), so that the decisions
+// they take (ball rejection, box rejection, pair order) are reproducible.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "gtmp_launch.hpp"
+
+namespace gtmp {
+
+constexpr int kMaxAttempts = 4096;
+
+// ------------------------------------------------------------------ informed set
+struct Informed {
+    float centre[GTMP_MAX_DOF];
+    float H[GTMP_MAX_DOF * GTMP_MAX_DOF];
+    float r1, r2;
+    int bounded;
+};
+
+// Hyperspheroid of the informed set X_f(c) (Sec. IV-E; Gammell et al. 2018):
+// centre (q0 + q_g)/2, radii c/2 along q_g - q0 and sqrt(c^2 - c_min^2)/2
+// across, orientation by the Householder reflection mapping e_1 to the unit
+// vector from q0 to q_g.  Without a bound (c = +inf or c >= penalty) the
+// draws are uniform in the box.
+__global__ void k_informed_prep(int d, const float *q0, const float *goals, const float *c_dev, float penalty,
+                                Informed *out) {
+    if (threadIdx.x != 0) return;
+    const float c = *c_dev;
+    Informed I;
+    I.bounded = !(__builtin_isinf(c) || c >= penalty || c != c);
+    float acc = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        const float t = goals[i] - q0[i];
+        acc = acc + t * t;
+    }
+    const float cmin = __builtin_sqrtf(acc);
+    for (int i = 0; i < d; ++i) I.centre[i] = (q0[i] + goals[i]) * 0.5f;
+    I.r1 = c * 0.5f;
+    const float sq = c * c - cmin * cmin;
+    I.r2 = __builtin_sqrtf(sq > 0.0f ? sq : 0.0f) * 0.5f;
+    float w[GTMP_MAX_DOF];
+    float ww = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        const float a = (goals[i] - q0[i]) / cmin;
+        w[i] = (i == 0 ? 1.0f : 0.0f) - a;
+        ww = ww + w[i] * w[i];
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            const float delta = i == j ? 1.0f : 0.0f;
+            if (ww == 0.0f) {
+                I.H[i * d + j] = delta;
+            } else {
+                const float s = 2.0f / ww;
+                I.H[i * d + j] = delta - (s * w[i]) * w[j];
+            }
+        }
+    *out = I;
+}
+
+__device__ __forceinline__ uint4 words(uint32_t k0, uint32_t k1, uint32_t n, uint32_t m, uint32_t stage,
+                                       uint32_t stream, uint32_t blk) {
+    return philox4x32_10(make_uint4(n, m, stage, (stream << 16) | blk), k0, k1);
+}
+
+__device__ __forceinline__ uint32_t pick(const uint4 &w, int i) {
+    return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
+}
+
+// One draw of the uniform half for slot (m, n).  Returns attempts used
+// (0 for an unbounded draw, -1 for the box fallback).
+__device__ int informed_draw(int d, const float *lo, const float *wd, const float *hi, const Informed &I,
+                             uint32_t k0, uint32_t k1, uint32_t stage, uint32_t m, uint32_t n, float *x) {
+    if (I.bounded) {
+        for (int a = 0; a < kMaxAttempts; ++a) {
+            float y[GTMP_MAX_DOF];
+            float s2 = 0.0f;
+            uint4 w0 = words(k0, k1, n, m, stage, 1u, (uint32_t)(2 * a));
+            uint4 w1 = words(k0, k1, n, m, stage, 1u, (uint32_t)(2 * a + 1));
+            for (int i = 0; i < d; ++i) {
+                const uint32_t wi = i < 4 ? pick(w0, i) : pick(w1, i - 4);
+                y[i] = (float)(wi >> 8) * (1.0f / 8388608.0f) - 1.0f;
+                s2 = s2 + y[i] * y[i];
+            }
+            if (!(s2 < 1.0f)) continue;
+            float z[GTMP_MAX_DOF];
+            for (int i = 0; i < d; ++i) z[i] = (i == 0 ? I.r1 : I.r2) * y[i];
+            bool inside = true;
+            float xx[GTMP_MAX_DOF];
+            for (int i = 0; i < d; ++i) {
+                float acc = 0.0f;
+                for (int j = 0; j < d; ++j) acc = acc + I.H[i * d + j] * z[j];
+                xx[i] = I.centre[i] + acc;
+                if (!(xx[i] >= lo[i] && xx[i] <= hi[i])) inside = false;
+            }
+            if (!inside) continue;
+            for (int i = 0; i < d; ++i) x[i] = xx[i];
+            return a + 1;
+        }
+    }
+    const uint4 w0 = words(k0, k1, n, m, stage, 1u, 0u);
+    const uint4 w1 = words(k0, k1, n, m, stage, 1u, 1u);
+    for (int i = 0; i < d; ++i) {
+        const uint32_t wi = i < 4 ? pick(w0, i) : pick(w1, i - 4);
+        x[i] = __builtin_fmaf(unit_from_word(wi), wd[i], lo[i]);
+    }
+    return I.bounded ? -1 : 0;
+}
+
+// ------------------------------------------------------------------ expansion
+struct BoxArgs {
+    float lo[GTMP_MAX_DOF], hi[GTMP_MAX_DOF], wd[GTMP_MAX_DOF];
+};
+
+// Copy the old samples of every layer into the new (wider) layout.
+__global__ void k_relayout(int M, int n_old, int N, int d, const float *Q_old, float *Q_new) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t total = (uint64_t)M * n_old * d;
+    if (t >= total) return;
+    const uint64_t j = t % d, mn = t / d;
+    const uint64_t n = mn % n_old, m = mn / n_old;
+    Q_new[(m * N + n) * d + j] = Q_old[t];
+}
+
+// Mixture coin and heuristic rank of the new slots of one layer (Sec. III-A
+// coin flip; Alg. 1 expand-samples): rank[n] = index among this layer's
+// heuristic draws, -1 for a uniform-half draw.  One block.
+__global__ void __launch_bounds__(1024) k_coin_rank(int m, int n_old, int N, uint32_t k0, uint32_t k1, uint32_t stage,
+                                                    const Informed *I, int heuristic_ok, int32_t *rank) {
+    __shared__ int wsum[1024 / kWave];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const bool allow = heuristic_ok && I->bounded;
+    for (int base = n_old; base < N; base += blockDim.x) {
+        const int n = base + threadIdx.x;
+        bool heur = false;
+        if (n < N && allow) {
+            const uint4 w = words(k0, k1, (uint32_t)n, (uint32_t)m, stage, 2u, 0u);
+            heur = (w.x >> 31) != 0;
+        }
+        const uint64_t mask = ballot(heur);
+        const int wv = threadIdx.x / kWave;
+        if (lane_id() == 0) wsum[wv] = __popcll(mask);
+        __syncthreads();
+        int before = carry;
+        for (int k = 0; k < wv; ++k) before += wsum[k];
+        if (n < N) rank[n] = heur ? before + rank_in(mask) : -1;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int k = 0; k < (int)(blockDim.x / kWave); ++k) tot += wsum[k];
+            carry += tot;
+        }
+        __syncthreads();
+    }
+}
+
+// Keys of all (u, v) pairs, u in the previous layer, v in the next one:
+// FP32 squared distance summed in coordinate order (no contraction), as
+// its bit pattern (monotone for non-negative floats); value = u * nv + v.
+__global__ void k_pair_keys(int d, int nu, const float *U, int nv, const float *Vv, uint32_t *keys, uint32_t *vals) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (uint64_t)nu * nv) return;
+    const uint32_t a = (uint32_t)(t / nv), b = (uint32_t)(t % nv);
+    float acc = 0.0f;
+    for (int i = 0; i < d; ++i) {
+        const float x = U[(size_t)a * d + i] - Vv[(size_t)b * d + i];
+        acc = acc + x * x;
+    }
+    keys[t] = __float_as_uint(acc);
+    vals[t] = (uint32_t)t;
+}
+
+// Fill the new slots of layer m: a heuristic slot of rank h takes the
+// midpoint of the h-th closest pair (a uniform draw when fewer pairs exist),
+// every other slot a draw of the uniform half.
+__global__ void __launch_bounds__(256) k_expand_layer(int m, int n_old, int N, int d, BoxArgs B, uint32_t k0,
+                                                      uint32_t k1, uint32_t stage, const Informed *Ip,
+                                                      const int32_t *rank, const uint32_t *sorted_pairs,
+                                                      uint64_t n_pairs, int nv, const float *U, const float *Vv,
+                                                      float *Qm) {
+    const int n = n_old + blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const Informed I = *Ip;
+    float x[GTMP_MAX_DOF];
+    const int h = rank[n];
+    if (h >= 0 && (uint64_t)h < n_pairs) {
+        const uint32_t p = sorted_pairs[h];
+        const uint32_t a = p / (uint32_t)nv, b = p % (uint32_t)nv;
+        for (int i = 0; i < d; ++i) x[i] = (U[(size_t)a * d + i] + Vv[(size_t)b * d + i]) * 0.5f;
+    } else {
+        informed_draw(d, B.lo, B.wd, B.hi, I, k0, k1, stage, (uint32_t)m, (uint32_t)n, x);
+    }
+    for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
+}
+
+// Standalone informed draws (for tests of the sampler): X[n][d] for slots
+// (m, n), n = 0..count-1, attempts[n] as informed_draw returns it.
+__global__ void k_informed_batch(int d, BoxArgs B, uint32_t k0, uint32_t k1, uint32_t stage, uint32_t m, int count,
+                                 const Informed *Ip, float *X, int32_t *attempts) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= count) return;
+    const Informed I = *Ip;
+    float x[GTMP_MAX_DOF];
+    const int a = informed_draw(d, B.lo, B.wd, B.hi, I, k0, k1, stage, m, (uint32_t)n, x);
+    for (int i = 0; i < d; ++i) X[(size_t)n * d + i] = x[i];
+    if (attempts) attempts[n] = a;
+}
+
+static BoxArgs box_args(const gtmp_problem &p) {
+    BoxArgs B{};
+    for (int j = 0; j < p.d; ++j) {
+        B.lo[j] = p.lo[j];
+        B.hi[j] = p.hi[j];
+        B.wd[j] = p.hi[j] - p.lo[j];
+    }
+    return B;
+}
+
+// ------------------------------------------------------------------ workspace of the expansion
+static size_t sort_temp_bytes(uint64_t n) {
+    size_t bytes = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                    (const uint32_t *)nullptr, (uint32_t *)nullptr, (unsigned int)n, 0, 32,
+                                    (hipStream_t)0);
+    return bytes;
+}
+
+static size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+ExpandPlan make_expand_plan(const gtmp_problem &p) {
+    ExpandPlan e{};
+    const uint64_t Nn = (uint64_t)p.N;
+    const uint64_t G = (uint64_t)p.G;
+    const uint64_t maxpairs = Nn * (Nn > G ? Nn : G);
+    e.max_pairs = maxpairs;
+    size_t o = 0;
+    e.off_informed = o; o = up256(o + sizeof(Informed));
+    e.off_rank = o; o = up256(o + sizeof(int32_t) * Nn);
+    e.off_keys = o; o = up256(o + sizeof(uint32_t) * maxpairs);
+    e.off_keys2 = o; o = up256(o + sizeof(uint32_t) * maxpairs);
+    e.off_vals = o; o = up256(o + sizeof(uint32_t) * maxpairs);
+    e.off_vals2 = o; o = up256(o + sizeof(uint32_t) * maxpairs);
+    e.sort_bytes = sort_temp_bytes(maxpairs);
+    e.off_sort = o; o = up256(o + e.sort_bytes);
+    e.total = o;
+    return e;
+}
+
+hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *goals, const float *Q_old, int n_old,
+                         float *Q_new, const float *c_dev, uint64_t seed, uint64_t stage, void *workspace,
+                         hipStream_t s) {
+    const ExpandPlan e = make_expand_plan(p);
+    char *ws = static_cast<char *>(workspace);
+    Informed *I = reinterpret_cast<Informed *>(ws + e.off_informed);
+    int32_t *rank = reinterpret_cast<int32_t *>(ws + e.off_rank);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(ws + e.off_keys);
+    uint32_t *keys2 = reinterpret_cast<uint32_t *>(ws + e.off_keys2);
+    uint32_t *vals = reinterpret_cast<uint32_t *>(ws + e.off_vals);
+    uint32_t *vals2 = reinterpret_cast<uint32_t *>(ws + e.off_vals2);
+    void *sort_tmp = ws + e.off_sort;
+    const int M = p.M, N = p.N, d = p.d;
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32), st = (uint32_t)stage;
+    hipLaunchKernelGGL(k_informed_prep, dim3(1), dim3(64), 0, s, d, q0, goals, c_dev, p.penalty, I);
+    if (n_old > 0) {
+        const uint64_t total = (uint64_t)M * n_old * d;
+        hipLaunchKernelGGL(k_relayout, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, M, n_old, N, d, Q_old,
+                           Q_new);
+    }
+    if (n_old >= N) return hipGetLastError();
+    const BoxArgs B = box_args(p);
+    for (int m = 0; m < M; ++m) {
+        // neighbours as Alg. 1 sees them when it reaches layer m: layer m-1
+        // already expanded (q0 for m = 0), layer m+1 still at its old size
+        // (the goals for m = M-1)
+        const float *U = m == 0 ? q0 : Q_new + (size_t)(m - 1) * N * d;
+        const int nu = m == 0 ? 1 : N;
+        const float *Vv = m == M - 1 ? goals : Q_new + (size_t)(m + 1) * N * d;
+        const int nv = m == M - 1 ? p.G : n_old;
+        const uint64_t npairs = (uint64_t)nu * (uint64_t)nv;
+        const int heuristic_ok = npairs > 0;
+        hipLaunchKernelGGL(k_coin_rank, dim3(1), dim3(1024), 0, s, m, n_old, N, k0, k1, st, I, heuristic_ok, rank);
+        const uint32_t *sorted = vals;
+        if (heuristic_ok) {
+            hipLaunchKernelGGL(k_pair_keys, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, d, nu, U, nv, Vv,
+                               keys, vals);
+            size_t tb = e.sort_bytes;
+            hipError_t err = rocprim::radix_sort_pairs(sort_tmp, tb, keys, keys2, vals, vals2, (unsigned int)npairs, 0,
+                                                       32, s);
+            if (err != hipSuccess) return err;
+            sorted = vals2;
+        }
+        hipLaunchKernelGGL(k_expand_layer, dim3((unsigned)((N - n_old + 255) / 256)), dim3(256), 0, s, m, n_old, N, d,
+                           B, k0, k1, st, I, rank, sorted, heuristic_ok ? npairs : 0, nv, U, Vv,
+                           Q_new + (size_t)m * N * d);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_informed_batch(const gtmp_problem &p, const float *q0, const float *goals, const float *c_dev,
+                                 uint64_t seed, uint64_t stage, uint32_t m, int count, float *X, int32_t *attempts,
+                                 void *workspace, hipStream_t s) {
+    Informed *I = reinterpret_cast<Informed *>(workspace);
+    hipLaunchKernelGGL(k_informed_prep, dim3(1), dim3(64), 0, s, p.d, q0, goals, c_dev, p.penalty, I);
+    if (count > 0)
+        hipLaunchKernelGGL(k_informed_batch, dim3((count + 255) / 256), dim3(256), 0, s, p.d, box_args(p),
+                           (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)stage, m, count, I, X,
+                           attempts);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ one stage of a plan
+// Uniform layer samples with the stage number read from device memory
+// (stage = base + *counter), so that a captured stage can be replayed.
+__global__ void __launch_bounds__(256) k_sample_dev_stage(int M, int N, int d, uint32_t k0, uint32_t k1,
+                                                          const uint32_t *counter, uint32_t base, BoxArgs B,
+                                                          float *__restrict__ Q) {
+    const int nblk = (d + 3) >> 2;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (uint64_t)M * N * nblk) return;
+    const uint32_t stage = base + *counter;
+    const uint32_t blk = (uint32_t)(tid % nblk);
+    const uint64_t mn = tid / nblk;
+    const uint32_t n = (uint32_t)(mn % N), m = (uint32_t)(mn / N);
+    const uint4 w = philox4x32_10(make_uint4(n, m, stage, blk), k0, k1);
+    float *dst = Q + mn * d;
+    for (int i = 0; i < 4; ++i) {
+        const int j = (int)blk * 4 + i;
+        if (j < d) dst[j] = __builtin_fmaf(unit_from_word(pick(w, i)), B.wd[j], B.lo[j]);
+    }
+}
+
+// Archive update of the anytime policies with |K| = 1 (Alg. 1; Sec. IV-D):
+// the best path so far; strictly better costs replace it, so ties keep the
+// earlier stage.  Also records the stage's cost and advances the counter.
+__global__ void k_archive(int M, int N, int d, const float *cost, const int32_t *idx, const float *wp,
+                          float *best_cost, int32_t *best_idx, float *best_wp, int32_t *best_meta, float *stage_costs,
+                          uint32_t *counter, int max_stages) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t stage = *counter;
+    const float c = *cost;
+    if ((int)stage < max_stages) stage_costs[stage] = c;
+    if (c < *best_cost) {
+        *best_cost = c;
+        for (int m = 0; m <= M; ++m) best_idx[m] = idx[m];
+        for (int k = 0; k < (M + 2) * d; ++k) best_wp[k] = wp[k];
+        best_meta[0] = (int32_t)stage;
+        best_meta[1] = M;
+        best_meta[2] = N;
+    }
+    best_meta[3] = (int32_t)stage + 1;
+    *counter = stage + 1;
+}
+
+__global__ void k_anytime_init(float *best_cost, int32_t *best_meta, uint32_t *counter) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    *best_cost = __builtin_inff();
+    best_meta[0] = -1;
+    best_meta[1] = 0;
+    best_meta[2] = 0;
+    best_meta[3] = 0;
+    *counter = 0;
+}
+
+// ------------------------------------------------------------------ drivers
+AnytimePlan make_anytime_plan(const gtmp_problem &p, const gtmp_anytime_opts &o) {
+    AnytimePlan a{};
+    gtmp_problem big = p;
+    if (o.mode == GTMP_ANYTIME_GROWING) {
+        big.M = o.M_max;
+        big.N = o.N_max;
+    }
+    a.big = big;
+    const uint64_t M = big.M, N = big.N, d = big.d, G = big.G;
+    size_t off = 0;
+    a.off_Q = off; off = up256(off + sizeof(float) * M * N * d);
+    a.off_Q2 = off; off = up256(off + sizeof(float) * M * N * d);
+    a.off_Cs = off; off = up256(off + sizeof(float) * N);
+    a.off_Ch = off; off = up256(off + sizeof(float) * (M > 1 ? M - 1 : 1) * N * N);
+    a.off_Cl = off; off = up256(off + sizeof(float) * N * G);
+    a.off_V = off; off = up256(off + sizeof(float) * M * N);
+    a.off_A = off; off = up256(off + sizeof(int32_t) * M * N);
+    a.off_small = off; off = up256(off + 256 + sizeof(int32_t) * (M + 1) + sizeof(float) * (M + 2) * d);
+    a.off_counter = off; off = up256(off + 64);
+    const EdgePlan ep = make_edge_plan(big);
+    a.off_edge = off; off = up256(off + ep.total);
+    if (o.mode == GTMP_ANYTIME_GROWING) {
+        const ExpandPlan xp = make_expand_plan(big);
+        a.off_expand = off; off = up256(off + xp.total);
+    }
+    a.total = off;
+    return a;
+}
+
+namespace {
+struct GraphKey {
+    std::tuple<const void *, const void *, const void *, const void *, uint64_t, int, int, int, int, int, hipStream_t>
+        k;
+    bool operator<(const GraphKey &o) const { return k < o.k; }
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;  // kept for the life of the process
+}  // namespace
+
+hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const SceneParams &scene, int wdim,
+                          const float *q0, const float *goals, uint64_t seed, const gtmp_anytime_opts &o,
+                          const gtmp_edge_opts &eo_in, const AnytimeOut &out, void *workspace, hipStream_t s) {
+    const AnytimePlan a = make_anytime_plan(p, o);
+    char *ws = static_cast<char *>(workspace);
+    float *Q = reinterpret_cast<float *>(ws + a.off_Q);
+    float *Q2 = reinterpret_cast<float *>(ws + a.off_Q2);
+    float *Cs = reinterpret_cast<float *>(ws + a.off_Cs);
+    float *Ch = reinterpret_cast<float *>(ws + a.off_Ch);
+    float *Cl = reinterpret_cast<float *>(ws + a.off_Cl);
+    float *V = reinterpret_cast<float *>(ws + a.off_V);
+    int32_t *A = reinterpret_cast<int32_t *>(ws + a.off_A);
+    char *small = ws + a.off_small;
+    float *Vs = reinterpret_cast<float *>(small);
+    int32_t *as = reinterpret_cast<int32_t *>(small + 4);
+    float *cost = reinterpret_cast<float *>(small + 8);
+    int32_t *idx = reinterpret_cast<int32_t *>(small + 256);
+    float *wp = reinterpret_cast<float *>(small + 256 + sizeof(int32_t) * (a.big.M + 1));
+    uint32_t *counter = reinterpret_cast<uint32_t *>(ws + a.off_counter);
+    void *edge_ws = ws + a.off_edge;
+    gtmp_edge_opts eo = eo_in;
+    eo.ev_begin = nullptr;
+    eo.ev_end = nullptr;
+    const int d = p.d;
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+
+    hipLaunchKernelGGL(k_anytime_init, dim3(1), dim3(64), 0, s, out.best_cost, out.best_meta, counter);
+
+    auto one_plan = [&](const gtmp_problem &pp, const float *Qp, hipStream_t st) -> hipError_t {
+        const EdgePlan ep = make_edge_plan(pp);
+        EdgeBuffers b{q0, goals, Qp, Cs, Ch, Cl, nullptr, nullptr, nullptr, edge_ws};
+        hipError_t e = launch_edge_check(ep, arm, scene, wdim, b, eo, st);
+        if (e != hipSuccess) return e;
+        e = launch_minplus(pp.M, pp.N, pp.G, Cs, Ch, Cl, nullptr, V, A, Vs, as, st);
+        if (e != hipSuccess) return e;
+        e = launch_extract(pp.M, pp.N, pp.G, d, as, A, Vs, Qp, q0, goals, idx, wp, cost, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_archive, dim3(1), dim3(64), 0, st, pp.M, pp.N, d, cost, idx, wp, out.best_cost,
+                           out.best_idx, out.best_wp, out.best_meta, out.stage_costs, counter, o.max_stages);
+        return hipGetLastError();
+    };
+
+    if (o.mode == GTMP_ANYTIME_RESTART) {
+        const BoxArgs B = box_args(p);
+        const uint64_t total = (uint64_t)p.M * p.N * ((d + 3) / 4);
+        const unsigned sblocks = (unsigned)((total + 255) / 256);
+        auto stage_ops = [&](hipStream_t st) -> hipError_t {
+            hipLaunchKernelGGL(k_sample_dev_stage, dim3(sblocks), dim3(256), 0, st, p.M, p.N, d, k0, k1, counter, 0u, B,
+                               Q);
+            return one_plan(p, Q, st);
+        };
+        if (!o.use_graph) {
+            for (int r = 0; r < o.max_stages; ++r) {
+                hipError_t e = stage_ops(s);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        }
+        // one stage captured on a private stream, instantiated once per
+        // (buffers, sizes, stream) and replayed max_stages times on `s`
+        GraphKey key{std::make_tuple((const void *)workspace, (const void *)q0, (const void *)goals,
+                                     (const void *)out.best_cost, seed, p.M, p.N, p.H, (int)eo.mode,
+                                     eo.sphere_chunks * 16 + eo.states_per_iter, s)};
+        hipGraphExec_t exec = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            auto it = g_graphs.find(key);
+            if (it != g_graphs.end()) exec = it->second;
+        }
+        if (!exec) {
+            hipStream_t cs;
+            hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) { (void)hipStreamDestroy(cs); return e; }
+            hipError_t e_ops = stage_ops(cs);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(cs, &g);
+            (void)hipStreamDestroy(cs);
+            if (e_ops != hipSuccess) { if (g) (void)hipGraphDestroy(g); return e_ops; }
+            if (e != hipSuccess) return e;
+            e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            g_graphs[key] = exec;
+        }
+        for (int r = 0; r < o.max_stages; ++r) {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+
+    // growing budget (Alg. 1 ao-gtmp): the schedule is fixed, so the whole
+    // loop is enqueued without reading anything back.
+    int M = o.M_min, N = o.N_min, n_old = 0;
+    float *cur = Q, *nxt = Q2;
+    void *xws = ws + a.off_expand;
+    for (int stage = 0; stage < o.max_stages; ++stage) {
+        gtmp_problem pp = p;
+        pp.M = M;
+        pp.N = N;
+        hipError_t e = launch_expand(pp, q0, goals, cur, n_old, nxt, out.best_cost, seed, (uint64_t)stage, xws, s);
+        if (e != hipSuccess) return e;
+        float *t = cur; cur = nxt; nxt = t;
+        e = one_plan(pp, cur, s);
+        if (e != hipSuccess) return e;
+        if (M >= o.M_max && N >= o.N_max) break;  // the stage at the full budget has run
+        if (N < o.N_max) {
+            n_old = N;
+            N = 2 * N < o.N_max ? 2 * N : o.N_max;
+        } else {
+            ++M;  // new epoch: more layers, every layer resampled
+            n_old = 0;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace gtmp

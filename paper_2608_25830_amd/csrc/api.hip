@@ -211,4 +211,103 @@ gtmp_status gtmp_extract_path(int32_t M, int32_t N, int32_t G, int32_t d, const 
                       "gtmp_extract_path");
 }
 
+gtmp_status gtmp_expand_workspace_size(const gtmp_problem *prob, size_t *bytes) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    const uint64_t G = (uint64_t)prob->G, N = (uint64_t)prob->N;
+    if (N * (N > G ? N : G) >= (1ull << 32)) return fail(GTMP_EINVAL, "too many sample pairs");
+    *bytes = gtmp::make_expand_plan(*prob).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_expand_samples(const gtmp_problem *prob, const float *q0, const float *goals, const float *Q_old,
+                                int32_t n_old, float *Q_new, const float *c_best, uint64_t seed, uint64_t stage,
+                                void *workspace, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    size_t need = 0;
+    gtmp_status st = gtmp_expand_workspace_size(prob, &need);
+    if (st != GTMP_OK) return st;
+    if (n_old < 0 || n_old > prob->N) return fail(GTMP_EINVAL, "n_old=%d outside 0..N", n_old);
+    if (!q0 || !goals || !Q_new || !c_best || !workspace) return fail(GTMP_EINVAL, "NULL buffer");
+    if (n_old > 0 && !Q_old) return fail(GTMP_EINVAL, "Q_old is NULL with n_old > 0");
+    if (ws_bytes < need) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    if (n_old > 0) {
+        const char *a = reinterpret_cast<const char *>(Q_old), *b = reinterpret_cast<const char *>(Q_new);
+        const size_t la = sizeof(float) * (size_t)prob->M * n_old * prob->d, lb = sizeof(float) * (size_t)prob->M * prob->N * prob->d;
+        if (a < b + lb && b < a + la) return fail(GTMP_EINVAL, "Q_old and Q_new overlap");
+    }
+    return hip_status(gtmp::launch_expand(*prob, q0, goals, Q_old, n_old, Q_new, c_best, seed, stage, workspace,
+                                          (hipStream_t)stream),
+                      "gtmp_expand_samples");
+}
+
+gtmp_status gtmp_sample_informed(const gtmp_problem *prob, const float *q0, const float *goals, const float *c_best,
+                                 uint64_t seed, uint64_t stage, int32_t m, int32_t count, float *X, int32_t *attempts,
+                                 void *workspace, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (count < 0 || m < 0) return fail(GTMP_EINVAL, "count and m must be >= 0");
+    if (!q0 || !goals || !c_best || !workspace || (count > 0 && !X)) return fail(GTMP_EINVAL, "NULL buffer");
+    return hip_status(gtmp::launch_informed_batch(*prob, q0, goals, c_best, seed, stage, (uint32_t)m, count, X,
+                                                  attempts, workspace, (hipStream_t)stream),
+                      "gtmp_sample_informed");
+}
+
+static gtmp_status check_anytime(const gtmp_problem *prob, const gtmp_anytime_opts *o) {
+    if (!o) return fail(GTMP_EINVAL, "opts is NULL");
+    if (o->max_stages < 1) return fail(GTMP_EINVAL, "max_stages=%d < 1", o->max_stages);
+    if (o->mode == GTMP_ANYTIME_RESTART) return check_problem(prob);
+    if (o->mode != GTMP_ANYTIME_GROWING) return fail(GTMP_EINVAL, "unknown anytime mode %d", o->mode);
+    if (o->M_min < 1 || o->M_min > o->M_max) return fail(GTMP_EINVAL, "need 1 <= M_min <= M_max");
+    if (o->N_min < 1 || o->N_min > o->N_max) return fail(GTMP_EINVAL, "need 1 <= N_min <= N_max");
+    gtmp_problem big = *prob;
+    big.M = o->M_max;
+    big.N = o->N_max;
+    gtmp_status st = check_problem(&big);
+    if (st != GTMP_OK) return st;
+    size_t tmp = 0;
+    return gtmp_expand_workspace_size(&big, &tmp);
+}
+
+gtmp_status gtmp_anytime_workspace_size(const gtmp_problem *prob, const gtmp_anytime_opts *opts, size_t *bytes) {
+    g_err[0] = 0;
+    if (!prob) return fail(GTMP_EINVAL, "problem is NULL");
+    gtmp_status st = check_anytime(prob, opts);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::make_anytime_plan(*prob, *opts).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_plan_anytime(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                              const float *q0, const float *goals, uint64_t seed, const gtmp_anytime_opts *opts,
+                              float *best_cost, int32_t *best_idx, float *best_wp, int32_t *best_meta,
+                              float *stage_costs, void *workspace, size_t ws_bytes, const gtmp_edge_opts *edge_opts,
+                              void *stream) {
+    g_err[0] = 0;
+    size_t need = 0;
+    gtmp_status st = gtmp_anytime_workspace_size(prob, opts, &need);
+    if (st != GTMP_OK) return st;
+    gtmp::ArmParams arm{};
+    gtmp::SceneParams sp{};
+    bool is_arm = false;
+    st = check_model(robot, scene, prob->d, &arm, &is_arm, &sp);
+    if (st != GTMP_OK) return st;
+    if (!q0 || !goals || !best_cost || !best_idx || !best_wp || !best_meta || !stage_costs || !workspace)
+        return fail(GTMP_EINVAL, "NULL buffer");
+    if (ws_bytes < need) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    gtmp_edge_opts eo{};
+    if (edge_opts) eo = *edge_opts;
+    if (eo.mode != GTMP_CHECK_FAST && eo.mode != GTMP_CHECK_FULL) return fail(GTMP_EINVAL, "unknown edge mode");
+    gtmp::AnytimeOut out{best_cost, best_idx, best_wp, best_meta, stage_costs};
+    return hip_status(gtmp::launch_anytime(*prob, is_arm ? &arm : nullptr, sp, scene->wdim, q0, goals, seed, *opts, eo,
+                                           out, workspace, (hipStream_t)stream),
+                      "gtmp_plan_anytime");
+}
+
 }  // extern "C"

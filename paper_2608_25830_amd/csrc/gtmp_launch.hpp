@@ -58,6 +58,36 @@ hipError_t launch_extract(int M, int N, int G, int d, const int32_t *a_s, const 
                           const float *Q, const float *q0, const float *goals, int32_t *idx, float *wp,
                           float *cost, hipStream_t s);
 
+// ---- growing-budget sampler and anytime drivers (anytime.hip)
+struct ExpandPlan {
+    uint64_t max_pairs;
+    size_t off_informed, off_rank, off_keys, off_keys2, off_vals, off_vals2, off_sort, sort_bytes, total;
+};
+ExpandPlan make_expand_plan(const gtmp_problem &p);
+hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *goals, const float *Q_old, int n_old,
+                         float *Q_new, const float *c_dev, uint64_t seed, uint64_t stage, void *workspace,
+                         hipStream_t s);
+hipError_t launch_informed_batch(const gtmp_problem &p, const float *q0, const float *goals, const float *c_dev,
+                                 uint64_t seed, uint64_t stage, uint32_t m, int count, float *X, int32_t *attempts,
+                                 void *workspace, hipStream_t s);
+
+struct AnytimePlan {
+    gtmp_problem big;  // sizes the buffers are carved for
+    size_t off_Q, off_Q2, off_Cs, off_Ch, off_Cl, off_V, off_A, off_small, off_counter, off_edge, off_expand, total;
+};
+AnytimePlan make_anytime_plan(const gtmp_problem &p, const gtmp_anytime_opts &o);
+
+struct AnytimeOut {
+    float *best_cost;
+    int32_t *best_idx;
+    float *best_wp;
+    int32_t *best_meta;
+    float *stage_costs;
+};
+hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const SceneParams &scene, int wdim,
+                          const float *q0, const float *goals, uint64_t seed, const gtmp_anytime_opts &o,
+                          const gtmp_edge_opts &eo, const AnytimeOut &out, void *workspace, hipStream_t s);
+
 // Bisection order of the interior states 1..H-2 (midpoint first, then the
 // midpoints of the remaining halves, breadth first).  Returns the count.
 int interior_order(int H, uint8_t *order_out);

@@ -80,9 +80,28 @@ _lib.gtmp_minplus_sweep.argtypes = [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _
 _lib.gtmp_extract_path.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    _vp, _vp, _vp]
 
+class gtmp_anytime_opts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("max_stages", C.c_int32), ("M_min", C.c_int32), ("M_max", C.c_int32),
+                ("N_min", C.c_int32), ("N_max", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+
+
+GTMP_ANYTIME_RESTART, GTMP_ANYTIME_GROWING = 0, 1
+
+_lib.gtmp_expand_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(C.c_size_t)]
+_lib.gtmp_expand_samples.argtypes = [C.POINTER(gtmp_problem), _vp, _vp, _vp, C.c_int32, _vp, _vp, C.c_uint64,
+                                     C.c_uint64, _vp, C.c_size_t, _vp]
+_lib.gtmp_sample_informed.argtypes = [C.POINTER(gtmp_problem), _vp, _vp, _vp, C.c_uint64, C.c_uint64, C.c_int32,
+                                      C.c_int32, _vp, _vp, _vp, _vp]
+_lib.gtmp_anytime_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_anytime_opts),
+                                             C.POINTER(C.c_size_t)]
+_lib.gtmp_plan_anytime.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot), C.POINTER(gtmp_scene), _vp, _vp,
+                                   C.c_uint64, C.POINTER(gtmp_anytime_opts), _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
+                                   C.POINTER(gtmp_edge_opts), _vp]
+
 EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample_layers",
            "gtmp_edge_check_workspace_size", "gtmp_edge_check_cost", "gtmp_state_check", "gtmp_minplus_sweep",
-           "gtmp_extract_path"]
+           "gtmp_extract_path", "gtmp_expand_workspace_size", "gtmp_expand_samples", "gtmp_sample_informed",
+           "gtmp_anytime_workspace_size", "gtmp_plan_anytime"]
 
 
 def _check(st):
@@ -203,6 +222,47 @@ def gtmp_extract_path(M, N, G, d, a_s, A, V_s, Q, q0, goals, idx, wp, cost, stre
                                          _p(goals), _p(idx), _p(wp), _p(cost), _stream(stream)))
 
 
+def _aligned_workspace(nbytes, device="cuda"):
+    buf = torch.empty((nbytes + 256,), device=device, dtype=torch.uint8)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+def gtmp_expand_workspace_size(prob) -> int:
+    n = C.c_size_t()
+    _check(_lib.gtmp_expand_workspace_size(C.byref(prob), C.byref(n)))
+    return n.value
+
+
+def gtmp_expand_samples(prob, q0, goals, Q_old, n_old, Q_new, c_best, seed, stage, workspace, stream=None):
+    return _check(_lib.gtmp_expand_samples(C.byref(prob), _p(q0), _p(goals), _p(Q_old), int(n_old), _p(Q_new),
+                                           _p(c_best), seed, stage, _p(workspace),
+                                           workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def gtmp_sample_informed(prob, q0, goals, c_best, seed, stage, m, X, attempts=None, workspace=None, stream=None):
+    if workspace is None:
+        workspace = _aligned_workspace(1024)
+    count = X.shape[0]
+    return _check(_lib.gtmp_sample_informed(C.byref(prob), _p(q0), _p(goals), _p(c_best), seed, stage, int(m),
+                                            int(count), _p(X), _p(attempts), _p(workspace), _stream(stream)))
+
+
+def gtmp_anytime_workspace_size(prob, opts) -> int:
+    n = C.c_size_t()
+    _check(_lib.gtmp_anytime_workspace_size(C.byref(prob), C.byref(opts), C.byref(n)))
+    return n.value
+
+
+def gtmp_plan_anytime(prob, robot, scene: Scene, q0, goals, seed, opts, best_cost, best_idx, best_wp, best_meta,
+                      stage_costs, workspace, edge_opts=None, stream=None):
+    return _check(_lib.gtmp_plan_anytime(
+        C.byref(prob), C.byref(robot), C.byref(scene.c), _p(q0), _p(goals), seed, C.byref(opts), _p(best_cost),
+        _p(best_idx), _p(best_wp), _p(best_meta), _p(stage_costs), _p(workspace),
+        workspace.numel() * workspace.element_size(), C.byref(edge_opts) if edge_opts is not None else None,
+        _stream(stream)))
+
+
 # --------------------------------------------------------------------------- #
 # one plan
 # --------------------------------------------------------------------------- #
@@ -259,10 +319,7 @@ class Planner:
         self.E = E
         self.flags = torch.empty((E,), device=device, dtype=torch.uint8) if flags else None
         self.minsd = torch.empty((E,), **f32) if minsd else None
-        ws = gtmp_edge_check_workspace_size(self.prob)
-        self.workspace = torch.empty((ws + 255,), device=device, dtype=torch.uint8)
-        off = (-self.workspace.data_ptr()) % 256
-        self.workspace = self.workspace[off:off + ws]
+        self.workspace = _aligned_workspace(gtmp_edge_check_workspace_size(self.prob), device)
         self.stats = torch.zeros((4,), device=device, dtype=torch.int64)
         self.opts = gtmp_edge_opts()
         self.opts.stats = self.stats.data_ptr()
@@ -298,3 +355,42 @@ class Planner:
     def result(self) -> PlanResult:
         return PlanResult(self.Q, self.C_s, self.C_h, self.C_l, self.V, self.A, self.V_s, self.a_s, self.idx, self.wp,
                           self.cost, self.flags, self.minsd)
+
+
+class AnytimePlanner:
+    """Device buffers for the anytime policies on one workload (restart:
+    the workload's M, N; growing: the schedule's maxima)."""
+
+    def __init__(self, w, mode, max_stages, M_min=None, M_max=None, N_min=None, N_max=None, use_graph=False,
+                 device="cuda"):
+        self.w = w
+        d, M, N, G, H = (int(w[k]) for k in ("d", "M", "N", "G", "H"))
+        self.d = d
+        self.opts = gtmp_anytime_opts()
+        self.opts.mode = mode
+        self.opts.max_stages = max_stages
+        self.opts.M_min, self.opts.M_max = M_min or M, M_max or M
+        self.opts.N_min, self.opts.N_max = N_min or N, N_max or N
+        self.opts.use_graph = int(use_graph)
+        self.prob = make_problem(d, M, N, G, H, w["lo"], w["hi"], w["penalty"])
+        if w["kind"] == "point2d":
+            self.robot = make_point_robot()
+            self.scene = Scene(2, w["circles"], w["boxes"], device)
+        else:
+            self.robot = make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"])
+            self.scene = Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+        self.q0 = torch.from_numpy(np.asarray(w["q0"], np.float32)).to(device)
+        self.goals = torch.from_numpy(np.asarray(w["goals"], np.float32).reshape(G, d)).to(device)
+        Mx = self.opts.M_max if mode == GTMP_ANYTIME_GROWING else M
+        self.best_cost = torch.empty((1,), device=device)
+        self.best_idx = torch.empty((Mx + 1,), device=device, dtype=torch.int32)
+        self.best_wp = torch.empty((Mx + 2, d), device=device)
+        self.best_meta = torch.empty((4,), device=device, dtype=torch.int32)
+        self.stage_costs = torch.full((max_stages,), float("nan"), device=device)
+        self.workspace = _aligned_workspace(gtmp_anytime_workspace_size(self.prob, self.opts), device)
+        self.edge_opts = gtmp_edge_opts()
+
+    def run(self, seed, stream=None):
+        gtmp_plan_anytime(self.prob, self.robot, self.scene, self.q0, self.goals, seed, self.opts, self.best_cost,
+                          self.best_idx, self.best_wp, self.best_meta, self.stage_costs, self.workspace,
+                          self.edge_opts, stream)

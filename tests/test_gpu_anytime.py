@@ -1,0 +1,130 @@
+"""Parity of the anytime policies and the growing-budget sampler (HIP path
+through the C ABI) with the oracle (Alg. 1 anytime-gtmp / ao-gtmp /
+expand-samples; Sec. IV-C..E)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.anytime as OA
+import workloads as wl
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.cuda() if dtype is None else t.to("cuda", dtype)
+
+
+@pytest.mark.parametrize("name,scale", [("2d-small", 1.02), ("2d-small", 1.3), ("arm7", 1.05), ("arm7", 2.0),
+                                        ("2d-small", None)])
+def test_informed_draws_bit_exact(gt, name, scale):
+    w = wl.make_workload(name, 0)
+    _say("informed", name, scale)
+    d = w["d"]
+    q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)
+    c = np.float32(np.inf) if scale is None else np.float32(np.linalg.norm(qg - q0) * scale)
+    prob = gt.make_problem(d, 3, 64, 1, 8, w["lo"], w["hi"], w["penalty"])
+    X = torch.empty((300, d), device="cuda")
+    att = torch.empty((300,), device="cuda", dtype=torch.int32)
+    gt.gtmp_sample_informed(prob, _dev(w["q0"]), _dev(w["goals"]), _dev(np.array([c], np.float32)), 21, 5, 2, X, att)
+    torch.cuda.synchronize()
+    Xg, Ag = X.cpu().numpy(), att.cpu().numpy()
+    for n in range(300):
+        x, a = OA.informed_draw(w, None if scale is None else c, 21, 5, 2, n)
+        assert a == Ag[n], (n, a, Ag[n])
+        assert np.array_equal(x.view(np.uint32), Xg[n].view(np.uint32)), (n, x, Xg[n])
+
+
+@pytest.mark.parametrize("name,M,N,n_old,cscale", [("2d-small", 4, 64, 32, 1.3), ("2d-small", 3, 40, 0, 1.5),
+                                                   ("arm7", 3, 48, 24, 1.5), ("2d-large", 5, 256, 128, 1.2),
+                                                   ("2d-small", 4, 64, 32, None)])
+def test_expand_samples_bit_exact(gt, name, M, N, n_old, cscale):
+    w = wl.make_workload(name, 1, M=M, N=N)
+    _say("expand", name, M, N, n_old, cscale)
+    d = w["d"]
+    q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)
+    c = np.float32(np.inf) if cscale is None else np.float32(np.linalg.norm(qg - q0) * cscale)
+    Q_old = oracle.sample_layers(M, max(n_old, 1), d, w["lo"], w["hi"], 3, 1)[:, :n_old]
+    want = OA.expand_samples(w, [Q_old[m] for m in range(M)], M, N, None if cscale is None else c, 13, 6)
+    prob = gt.make_problem(d, M, N, 1, w["H"], w["lo"], w["hi"], w["penalty"])
+    ws = gt._aligned_workspace(gt.gtmp_expand_workspace_size(prob))
+    Qn = torch.empty((M, N, d), device="cuda")
+    Qo = _dev(Q_old) if n_old > 0 else None
+    gt.gtmp_expand_samples(prob, _dev(w["q0"]), _dev(w["goals"]), Qo, n_old, Qn, _dev(np.array([c], np.float32)),
+                           13, 6, ws)
+    torch.cuda.synchronize()
+    got = Qn.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), np.stack(want).view(np.uint32))
+
+
+def _anytime(gt, w, mode, stages, **kw):
+    ap = gt.AnytimePlanner(w, mode, stages, **kw)
+    ap.run(w["seed"])
+    torch.cuda.synchronize()
+    return ap
+
+
+@pytest.mark.parametrize("name,kw", [("2d-small", {}), ("arm7", dict(N=96, M=3)), ("2d-large", dict(N=128, M=4))])
+@pytest.mark.parametrize("graph", [False, True])
+def test_restart_matches_oracle(gt, name, kw, graph):
+    w = wl.make_workload(name, 0, **kw)
+    _say("restart", name, kw, "graph", graph)
+    S = 5
+    ap = _anytime(gt, w, gt.GTMP_ANYTIME_RESTART, S, use_graph=graph)
+    best, costs = OA.plan_restart(w, S, w["seed"])
+    got = ap.stage_costs.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, costs, rtol=P.REL)
+    meta = ap.best_meta.cpu().numpy()
+    assert meta[3] == S
+    assert float(ap.best_cost.item()) == pytest.approx(best["cost"], rel=P.REL)
+    srt = np.sort(costs)
+    if srt[1] - srt[0] > P.REL * srt[0]:
+        assert meta[0] == best["stage"]
+        assert list(ap.best_idx.cpu().numpy()) == list(best["idx"])
+
+
+def test_restart_graph_replays_match_eager(gt):
+    """The captured stage replayed several times, with eager work and
+    synchronisations between the calls, gives the eager results each time."""
+    w = wl.make_workload("2d-small", 2)
+    _say("graph replays")
+    eager = _anytime(gt, w, gt.GTMP_ANYTIME_RESTART, 6, use_graph=False)
+    ref = eager.stage_costs.clone()
+    g = gt.AnytimePlanner(w, gt.GTMP_ANYTIME_RESTART, 6, use_graph=True)
+    for rep in range(3):
+        g.run(w["seed"])
+        torch.cuda.synchronize()
+        assert torch.equal(g.stage_costs, ref), rep
+        assert torch.equal(g.best_idx, eager.best_idx)
+        x = torch.randn(1000, device="cuda").sum()  # eager work in between
+        torch.cuda.synchronize()
+        del x
+
+
+@pytest.mark.parametrize("name,sched,kw", [("2d-small", (3, 5, 16, 64, 8), {}), ("2d-large", (4, 5, 64, 256, 6), {}),
+                                           ("arm7", (3, 4, 32, 64, 5), {})])
+def test_growing_matches_oracle(gt, name, sched, kw):
+    w = wl.make_workload(name, 1, **kw)
+    M_min, M_max, N_min, N_max, S = sched
+    _say("growing", name, sched)
+    ap = gt.AnytimePlanner(w, gt.GTMP_ANYTIME_GROWING, S, M_min=M_min, M_max=M_max, N_min=N_min, N_max=N_max)
+    ap.run(w["seed"])
+    torch.cuda.synchronize()
+    best, costs, stages = OA.plan_growing(w, M_min, M_max, N_min, N_max, S, w["seed"])
+    got = ap.stage_costs.cpu().numpy().astype(np.float64)[:len(costs)]
+    # both sides run their own trajectory: FP32 and FP64 bounds give
+    # informed draws that agree to rounding, so stage costs agree to 1e-5
+    np.testing.assert_allclose(got, costs, rtol=P.REL)
+    meta = ap.best_meta.cpu().numpy()
+    assert meta[3] == len(costs)
+    assert float(ap.best_cost.item()) == pytest.approx(best["cost"], rel=P.REL)
+    assert (meta[1], meta[2]) == (best["M"], best["N"]) or abs(sorted(costs)[1] - sorted(costs)[0]) <= P.REL * best["cost"]

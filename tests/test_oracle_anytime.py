@@ -1,0 +1,168 @@
+"""Pins of the oracle's anytime policies (Alg. 1 anytime-gtmp / ao-gtmp;
+Sec. IV-C..E) and of the growing-budget sampler (Alg. 1 expand-samples):
+informed-set membership (Sec. IV-E), uniformity of the ellipsoid draws
+(radial law of a uniform d-ball), the Householder frame against NumPy, the
+d-ball acceptance rate, the mixture coin, the closest-pair property of the
+midpoints, monotone archives and the free-space convergence of Thm. 3."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+from scipy.special import gamma
+
+import oracle
+import oracle.anytime as OA
+import workloads as wl
+
+
+def ellipsoid_coords(w, c, X):
+    """Map draws back to the unit ball with an independently built frame:
+    a1 = (q_g - q0)/|q_g - q0|, any orthonormal completion."""
+    q0 = w["q0"].astype(np.float64)
+    qg = np.asarray(w["goals"], np.float64)[0]
+    d = q0.size
+    cmin = np.linalg.norm(qg - q0)
+    a1 = (qg - q0) / cmin
+    Qm, _ = np.linalg.qr(np.column_stack([a1, np.eye(d)[:, :d - 1] + 1e-3]))
+    Qm[:, 0] = a1
+    r = np.array([c / 2] + [math.sqrt(c * c - cmin * cmin) / 2] * (d - 1))
+    Y = ((X.astype(np.float64) - (q0 + qg) / 2) @ Qm) / r
+    return Y
+
+
+def test_householder_frame():
+    w = wl.make_workload("arm7", 0)
+    centre, H, r1, r2, cmin = OA.informed_params(7, w["q0"], w["goals"][0], 9.0)
+    a1 = (w["goals"][0].astype(np.float64) - w["q0"]) / np.linalg.norm(w["goals"][0].astype(np.float64) - w["q0"])
+    np.testing.assert_allclose(H @ H.T, np.eye(7), atol=1e-6)
+    np.testing.assert_allclose(H[:, 0], a1, atol=1e-6)
+    assert r1 == pytest.approx(4.5) and r2 == pytest.approx(math.sqrt(81 - cmin ** 2) / 2, rel=1e-6)
+
+
+def test_informed_draws_in_set_and_uniform_2d():
+    w = wl.make_workload("2d-small", 0)
+    c = 26.0  # c_min = 25.456; the ellipse stays inside the box
+    X = np.stack([OA.informed_draw(w, np.float32(c), 7, 3, 1, n)[0] for n in range(3000)])
+    q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)
+    s = np.linalg.norm(X - q0, axis=1) + np.linalg.norm(X - qg, axis=1)
+    assert np.all(s <= c * (1 + 1e-6))
+    Y = ellipsoid_coords(w, c, X)
+    rad = np.linalg.norm(Y, axis=1)
+    assert rad.max() <= 1 + 1e-5
+    # uniform in the d-ball: |y|^d ~ U(0, 1), angle ~ U(-pi, pi)
+    assert stats.kstest(rad ** 2, "uniform").pvalue > 1e-3
+    ang = np.arctan2(Y[:, 1], Y[:, 0])
+    assert stats.kstest(ang, stats.uniform(loc=-np.pi, scale=2 * np.pi).cdf).pvalue > 1e-3
+
+
+def test_informed_draws_arm_in_set_box_and_acceptance():
+    w = wl.make_workload("arm7", 0)
+    q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)
+    cmin = np.linalg.norm(qg - q0)
+    c = float(np.float32(cmin * 1.05))
+    draws = [OA.informed_draw(w, np.float32(c), 11, 0, 2, n) for n in range(400)]
+    X = np.stack([x for x, _ in draws])
+    att = np.array([a for _, a in draws])
+    assert np.all(att > 0)
+    s = np.linalg.norm(X - q0, axis=1) + np.linalg.norm(X - qg, axis=1)
+    assert np.all(s <= c * (1 + 1e-6))
+    assert np.all(X >= w["lo"]) and np.all(X <= w["hi"])
+    # acceptance of the cube -> ball rejection: volume ratio of the 7-ball
+    p_ball = math.pi ** 3.5 / gamma(4.5) / 2 ** 7
+    rate = len(att) / att.sum()
+    assert rate <= p_ball * 1.3  # box rejections can only lower it
+
+
+def test_unbounded_draw_is_box_sample():
+    w = wl.make_workload("2d-small", 0)
+    x, a = OA.informed_draw(w, None, 5, 2, 1, 9)
+    assert a == 0
+    words = oracle.sample_words(5, 2, 1, 9, 1, 0)
+    want = np.array([np.float32(-10 + ((int(words[i]) >> 8) * 2.0 ** -24) * 20) for i in range(2)], np.float32)
+    np.testing.assert_array_equal(x, want)
+
+
+def test_coin_is_fair():
+    n = sum(OA.coin_heuristic(3, 1, 2, k) for k in range(4000))
+    assert stats.binomtest(n, 4000, 0.5).pvalue > 1e-3
+
+
+def test_expand_midpoints_are_the_closest_pairs():
+    w = wl.make_workload("2d-small", 0, M=3, N=40)
+    d = 2
+    Q0 = oracle.sample_layers(3, 20, d, w["lo"], w["hi"], 9, 0)
+    c = np.float32(40.0)
+    Q = OA.expand_samples(w, list(Q0), 3, 40, c, 9, 4)
+    assert all(q.shape == (40, d) for q in Q)
+    for m in range(3):
+        np.testing.assert_array_equal(Q[m][:20], Q0[m])  # old samples kept
+    # layer 1: neighbours = expanded layer 0 (40) and old layer 2 (20)
+    prev, nxt = Q[0].astype(np.float64), Q0[2].astype(np.float64)
+    heur = [n for n in range(20, 40) if OA.coin_heuristic(9, 4, 1, n)]
+    assert len(heur) > 3
+    D = np.linalg.norm(prev[:, None, :] - nxt[None, :, :], axis=-1)
+    used = []
+    for n in heur:
+        x = Q[1][n].astype(np.float64)
+        mid = (prev[:, None, :] + nxt[None, :, :]) / 2
+        a, b = np.unravel_index(np.argmin(np.linalg.norm(mid - x, axis=-1)), D.shape)
+        assert np.linalg.norm(mid[a, b] - x) < 1e-5
+        used.append(D[a, b])
+    # the used pairs are the k closest ones
+    k = len(used)
+    assert max(used) <= np.sort(D.ravel())[k - 1] + 1e-5
+    assert sorted(used) == pytest.approx(list(np.sort(D.ravel())[:k]), abs=1e-5)
+
+
+def test_growing_schedule_rule():
+    s = OA.growing_schedule(2, 4, 16, 64, 20)
+    assert s == [(2, 16, 0), (2, 32, 16), (2, 64, 32), (3, 64, 0), (4, 64, 0)]
+    assert OA.growing_schedule(8, 8, 512, 2048, 10) == [(8, 512, 0), (8, 1024, 512), (8, 2048, 1024)]
+    assert len(OA.growing_schedule(1, 50, 8, 8, 5)) == 5
+
+
+def test_restart_archive_monotone_and_min():
+    w = wl.make_workload("2d-small", 1)
+    best, costs = OA.plan_restart(w, 6, w["seed"])
+    assert best["cost"] == min(costs)
+    assert best["stage"] == int(np.argmin(costs))
+    running = np.minimum.accumulate(costs)
+    assert np.all(np.diff(running) <= 0)
+    # a stage is the plain planner on the samples of key (seed, stage)
+    r = oracle.plan(w, stage=3)
+    assert costs[3] == r["path_cost"]
+
+
+def test_growing_bounds_and_informed_membership():
+    w = wl.make_workload("2d-small", 2)
+    best, costs, stages = OA.plan_growing(w, 3, 5, 16, 64, 8, 77)
+    bounds = [st["bound"] for st in stages]
+    assert all(b2 <= b1 for b1, b2 in zip(bounds, bounds[1:]))  # c_min never increases
+    q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)
+    sched = OA.growing_schedule(3, 5, 16, 64, 8)
+    checked = 0
+    for si, (st, (M, N, n_old)) in enumerate(zip(stages, sched)):
+        if not (np.isfinite(st["bound"]) and st["bound"] < w["penalty"]):
+            continue
+        # the new uniform-half draws of this stage lie in X_f(c_min)
+        for m in range(M):
+            for n in range(n_old, N):
+                if OA.coin_heuristic(77, si, m, n):
+                    continue
+                x = st["Q"][m, n].astype(np.float64)
+                assert np.linalg.norm(x - q0) + np.linalg.norm(x - qg) <= np.float32(st["bound"]) * (1 + 1e-5)
+                checked += 1
+    assert checked > 50
+
+
+def test_growing_free_space_converges_to_straight_line():
+    """Thm. 3: in free space the best cost tends to |q_g - q0|."""
+    w = wl.make_workload("2d-small", 0)
+    w["circles"] = np.zeros((0, 3), np.float32)
+    direct = float(np.linalg.norm(w["goals"][0].astype(np.float64) - w["q0"]))
+    best, costs, _ = OA.plan_growing(w, 2, 4, 8, 64, 10, 5)
+    running = np.minimum.accumulate(costs)
+    assert running[-1] >= direct
+    assert (running[-1] - direct) < 0.5 * (running[0] - direct) + 1e-9
+    assert (running[-1] - direct) / direct < 0.01
