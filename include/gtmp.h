@@ -283,6 +283,59 @@ gtmp_status gtmp_plan_anytime(const gtmp_problem *prob, const gtmp_robot *robot,
                               float *stage_costs, void *workspace, size_t ws_bytes, const gtmp_edge_opts *edge_opts,
                               void *stream);
 
+/* ------------------------------------------------------ a8 batched plans */
+/* One independent plan of a batch.  Robot by value (host memory); scene,
+ * q0 and goals are device pointers.  mode GTMP_ANYTIME_RESTART runs
+ * `stages` restart stages at (problem.M, problem.N) (stages = 1 is the plain
+ * planner); GTMP_ANYTIME_GROWING runs the growing schedule of
+ * gtmp_plan_anytime from (M_min, N_min) to (problem.M, problem.N). */
+typedef struct gtmp_plan_desc {
+    gtmp_problem problem;
+    gtmp_robot robot;
+    gtmp_scene scene;
+    const float *q0;
+    const float *goals;
+    uint64_t seed;
+    int32_t mode;
+    int32_t stages;
+    int32_t M_min;
+    int32_t N_min;
+} gtmp_plan_desc;
+
+typedef struct gtmp_batch_opts {
+    int32_t use_graph;        /* capture the whole batch (every stage) as one hipGraph and launch it;
+                                 ignored (stages enqueued directly) when a plan uses the growing policy,
+                                 whose sample expansion sorts with a library routine that clears memory
+                                 with memset nodes, which are kept out of graphs */
+    int32_t states_per_iter;  /* interior states per lane and iteration for point robots (0 = auto) */
+    int32_t sphere_chunks;    /* arms: spheres tested in 1 or 2 chunks (0 = auto) */
+    int32_t blocks_per_cu;    /* resident blocks per CU of the persistent kernels (0 = auto) */
+    unsigned long long *stats; /* optional device [4], as gtmp_edge_opts.stats */
+} gtmp_batch_opts;
+
+/* Bytes of device workspace gtmp_plan_batch needs for these plans. */
+gtmp_status gtmp_batch_workspace_size(const gtmp_plan_desc *plans, int32_t n, const gtmp_batch_opts *opts,
+                                      size_t *bytes);
+
+/* Run n independent plans through batched kernels: per stage one sampling
+ * launch, one vertex launch per robot group (2D points, 3D points, arms),
+ * one edge pre-pass launch, one persistent interior launch per robot group
+ * over the tiles of all its plans, max-M sweep launches covering every plan
+ * and one finishing launch (start row, extraction, archive).  Each plan's
+ * results equal those of gtmp_plan_anytime (or of one plain plan) with the
+ * same seed.  Outputs (device), plans concatenated in order:
+ *   best_cost   [n]
+ *   best_idx    [sum_p (M_p + 1)]        M_p = plans[p].problem.M
+ *   best_wp     [sum_p (M_p + 2) d_p]
+ *   best_meta   [n][4] = (best stage, its M, its N, stages run)
+ *   stage_costs [n][stage_stride], stage_stride >= the largest stage count
+ * The call writes its tables into the workspace with a synchronous copy
+ * after waiting for `stream`, then enqueues (or, with use_graph, launches the
+ * captured graph and waits for it). */
+gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_batch_opts *opts, float *best_cost,
+                            int32_t *best_idx, float *best_wp, int32_t *best_meta, float *stage_costs,
+                            int32_t stage_stride, void *workspace, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -310,4 +310,83 @@ gtmp_status gtmp_plan_anytime(const gtmp_problem *prob, const gtmp_robot *robot,
                       "gtmp_plan_anytime");
 }
 
+gtmp_status gtmp_batch_workspace_size(const gtmp_plan_desc *plans, int32_t n, const gtmp_batch_opts *opts,
+                                      size_t *bytes);
+
+static gtmp_status check_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_batch_opts *opts,
+                               std::vector<gtmp::ArmParams> *arms) {
+    if (!plans || n < 1) return fail(GTMP_EINVAL, "need at least one plan");
+    if (!opts) return fail(GTMP_EINVAL, "opts is NULL");
+    if (opts->sphere_chunks < 0 || opts->sphere_chunks > 2 || opts->states_per_iter < 0 || opts->states_per_iter > 8 ||
+        opts->blocks_per_cu < 0 || opts->blocks_per_cu > 32)
+        return fail(GTMP_EINVAL, "bad batch options");
+    arms->assign(n, gtmp::ArmParams{});
+    for (int p = 0; p < n; ++p) {
+        const gtmp_plan_desc &D = plans[p];
+        gtmp_status st = check_problem(&D.problem);
+        if (st != GTMP_OK) return fail(st, "plan %d: %s", p, g_err);
+        gtmp::SceneParams sp{};
+        bool is_arm = false;
+        st = check_model(&D.robot, &D.scene, D.problem.d, &(*arms)[p], &is_arm, &sp);
+        if (st != GTMP_OK) return fail(st, "plan %d: %s", p, g_err);
+        if (!D.q0 || !D.goals) return fail(GTMP_EINVAL, "plan %d: q0 or goals is NULL", p);
+        if (D.stages < 1) return fail(GTMP_EINVAL, "plan %d: stages < 1", p);
+        if (D.mode == GTMP_ANYTIME_GROWING) {
+            if (D.M_min < 1 || D.M_min > D.problem.M || D.N_min < 1 || D.N_min > D.problem.N)
+                return fail(GTMP_EINVAL, "plan %d: need 1 <= M_min <= M and 1 <= N_min <= N", p);
+            size_t tmp = 0;
+            st = gtmp_expand_workspace_size(&D.problem, &tmp);
+            if (st != GTMP_OK) return fail(st, "plan %d: %s", p, g_err);
+        } else if (D.mode != GTMP_ANYTIME_RESTART) {
+            return fail(GTMP_EINVAL, "plan %d: unknown mode %d", p, D.mode);
+        }
+    }
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_batch_workspace_size(const gtmp_plan_desc *plans, int32_t n, const gtmp_batch_opts *opts,
+                                      size_t *bytes) {
+    g_err[0] = 0;
+    std::vector<gtmp::ArmParams> arms;
+    gtmp_status st = check_batch(plans, n, opts, &arms);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::make_batch_layout(plans, n, *opts).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_batch_opts *opts, float *best_cost,
+                            int32_t *best_idx, float *best_wp, int32_t *best_meta, float *stage_costs,
+                            int32_t stage_stride, void *workspace, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    std::vector<gtmp::ArmParams> arms;
+    gtmp_status st = check_batch(plans, n, opts, &arms);
+    if (st != GTMP_OK) return st;
+    if (!best_cost || !best_idx || !best_wp || !best_meta || !stage_costs || !workspace)
+        return fail(GTMP_EINVAL, "NULL buffer");
+    const gtmp::BatchLayout L = gtmp::make_batch_layout(plans, n, *opts);
+    if (stage_stride < L.max_stages) return fail(GTMP_EINVAL, "stage_stride=%d < %d stages", stage_stride, L.max_stages);
+    if (ws_bytes < L.total) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    gtmp::BatchOut out;
+    out.best_cost = best_cost;
+    out.best_idx = best_idx;
+    out.best_wp = best_wp;
+    out.best_meta = best_meta;
+    out.stage_costs = stage_costs;
+    out.stage_stride = stage_stride;
+    out.stats = opts->stats;
+    out.idx_offset.resize(n);
+    out.wp_offset.resize(n);
+    size_t io = 0, wo = 0;
+    for (int p = 0; p < n; ++p) {
+        out.idx_offset[p] = io;
+        out.wp_offset[p] = wo;
+        io += (size_t)plans[p].problem.M + 1;
+        wo += (size_t)(plans[p].problem.M + 2) * plans[p].problem.d;
+    }
+    return hip_status(gtmp::launch_batch(plans, arms.data(), n, *opts, L, out, workspace, (hipStream_t)stream),
+                      "gtmp_plan_batch");
+}
+
 }  // extern "C"

@@ -1,0 +1,871 @@
+// batch.hip -- many independent plans (uneven N, M, d, robots and anytime
+// policies) through batched kernels: one launch per step for every plan of
+// the batch, and one persistent edge-interior launch per robot group over the
+// tiles of all its plans.  A plan's stages follow the single-plan policies
+// (Alg. 1 gtmp / anytime-gtmp / ao-gtmp), and every result equals the
+// single-plan call with the same seed: the kernels run the same per-edge,
+// per-row and per-plan code as the single-plan ones.
+#include "edge_common.hpp"
+
+namespace gtmp {
+
+// Per-plan, per-stage descriptor (device table, read-only during a stage).
+struct BPlan {
+    EdgeArgs A;          // edge check of this plan's stage (workspace, costs, tiles, t order)
+    SceneParams S;
+    const ArmParams *arm;  // device copy of the robot table (arms), null for points
+    int group;           // 0: 2D point, 1: 3D point, 2: arm
+    uint32_t vert_base;  // first vertex of this plan in its group's vertex space
+    uint32_t tile_base;  // first tile of this plan in the batch's tile space
+    uint32_t gtile_base; // first tile of this plan in its group's tile space
+    uint32_t row_base;   // first row (layer vertex) in the batch's row space
+    const float *Q, *q0, *goals;
+    float *V;
+    int32_t *Aidx;
+    float *Vs;
+    int32_t *as;
+    int32_t *idx;
+    float *wp;
+    float *cost;
+    // archive of the plan's anytime policy
+    float *best_cost;
+    int32_t *best_idx;
+    float *best_wp;
+    int32_t *best_meta;
+    float *stage_costs;
+    uint32_t *counter;
+    int max_stages;
+    // uniform sampling of this stage (restart policy); 0 = samples come from elsewhere
+    int sample;
+    uint32_t k0, k1, stage;
+    float lo[GTMP_MAX_DOF], wd[GTMP_MAX_DOF];
+};
+
+typedef const __attribute__((address_space(4))) BPlan *cplan;
+
+// Largest p with base(p) <= x over plans [lo, hi) (bases non-decreasing).
+template <class F>
+__device__ __forceinline__ int find_plan(int lo, int hi, uint64_t x, F base) {
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((uint64_t)base(mid) <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ sampling
+__global__ void __launch_bounds__(256) k_batch_sample(const BPlan *plans, int n_plans, const uint64_t *sample_base,
+                                                      uint64_t total) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int p = find_plan(0, n_plans, g, [&](int i) { return sample_base[i]; });
+    const BPlan &P = plans[p];
+    if (!P.sample) return;
+    const int d = P.A.d;
+    const int nblk = (d + 3) >> 2;
+    const uint64_t t = g - sample_base[p];
+    const uint32_t blk = (uint32_t)(t % nblk);
+    const uint64_t mn = t / nblk;
+    const uint32_t n = (uint32_t)(mn % P.A.N), m = (uint32_t)(mn / P.A.N);
+    const uint4 w = philox4x32_10(make_uint4(n, m, P.stage, blk), P.k0, P.k1);
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    float *dst = const_cast<float *>(P.Q) + mn * d;
+    for (int i = 0; i < 4; ++i) {
+        const int j = (int)blk * 4 + i;
+        if (j < d) dst[j] = __builtin_fmaf(unit_from_word(words[i]), P.wd[j], P.lo[j]);
+    }
+}
+
+// ------------------------------------------------------------------ vertices
+template <int GROUP, int KP>
+__global__ void __launch_bounds__(256) k_batch_vertices(const BPlan *plans, int p0, int p1, uint32_t total) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = g < total;
+    const int p = find_plan(p0, p1, live ? g : 0, [&](int i) { return plans[i].vert_base; });
+    const BPlan &P = plans[p];
+    const EdgeArgs &A = P.A;
+    const uint32_t i = (live ? g : 0) - P.vert_base;
+    const bool valid = live && i < A.n_vertices;
+    const uint32_t MN = (uint32_t)A.M * (uint32_t)A.N;
+    float *verts = const_cast<float *>(A.verts);
+    uint8_t *vflag = const_cast<uint8_t *>(A.vflag);
+    if constexpr (GROUP == 2) {
+        float q[GTMP_MAX_JOINTS];
+#pragma unroll
+        for (int j = 0; j < GTMP_MAX_JOINTS; ++j) q[j] = 0.f;
+        if (valid) {
+            const float *src = i == 0 ? P.q0 : (i <= MN ? P.Q + (size_t)(i - 1) * A.d : P.goals + (size_t)(i - 1 - MN) * A.d);
+#pragma unroll
+            for (int j = 0; j < GTMP_MAX_JOINTS; ++j)
+                if (j < A.d) q[j] = src[j];
+#pragma unroll
+            for (int j = 0; j < GTMP_MAX_JOINTS; ++j) verts[(size_t)i * A.dp + j] = q[j];
+        }
+        // plans of one block may differ: the robot and the scene are per lane here
+        const ArmParams &R = *P.arm;
+        if (valid) {
+            const v32f o = arm_fk<GTMP_MAX_JOINTS>(R, q);
+            float best = __builtin_inff();
+            for (int k = 0; k < R.n_spheres; ++k) {
+                const int b = 3 * R.link[k];
+                float c[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) c[a] = __builtin_fmaf(R.t[k], o[b + a] - o[b - 3 + a], o[b - 3 + a]);
+                const float r = R.r[k];
+                for (int oo = 0; oo < P.S.n_sph; ++oo) {
+                    const float *sp = P.S.sph + oo * 4;
+                    float g2 = -(sp[3] + r) * (sp[3] + r);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float dl = c[a] - sp[a];
+                        g2 = __builtin_fmaf(dl, dl, g2);
+                    }
+                    best = __builtin_fminf(best, g2);
+                }
+                for (int oo = 0; oo < P.S.n_box; ++oo) {
+                    const float *bx = P.S.box + oo * 6;
+                    float g2 = -r * r;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float dl = c[a] - __builtin_amdgcn_fmed3f(c[a], bx[a] - bx[3 + a], bx[a] + bx[3 + a]);
+                        g2 = __builtin_fmaf(dl, dl, g2);
+                    }
+                    best = __builtin_fminf(best, g2);
+                }
+            }
+            vflag[i] = best <= 0.f ? 1 : 0;
+        }
+    } else {
+        constexpr int W = GROUP == 0 ? 2 : 3;
+        if (!valid) return;
+        const float *src = i == 0 ? P.q0 : (i <= MN ? P.Q + (size_t)(i - 1) * W : P.goals + (size_t)(i - 1 - MN) * W);
+        Probes<W, 1> Pr;
+        for (int j = 0; j < GTMP_MAX_DOF; ++j) verts[(size_t)i * A.dp + j] = j < W ? src[j] : 0.f;
+#pragma unroll
+        for (int j = 0; j < W; ++j) Pr.p[j][0] = src[j];
+        float best = __builtin_inff();
+        for (int oo = 0; oo < P.S.n_sph; ++oo) {
+            const float *sp = P.S.sph + oo * (W + 1);
+            float g2 = -sp[W] * sp[W];
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                const float dl = Pr.p[a][0] - sp[a];
+                g2 = __builtin_fmaf(dl, dl, g2);
+            }
+            best = __builtin_fminf(best, g2);
+        }
+        for (int oo = 0; oo < P.S.n_box; ++oo) {
+            const float *bx = P.S.box + oo * 2 * W;
+            float g2 = 0.f;
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                const float x = Pr.p[a][0];
+                const float dl = x - __builtin_amdgcn_fmed3f(x, bx[a] - bx[W + a], bx[a] + bx[W + a]);
+                g2 = __builtin_fmaf(dl, dl, g2);
+            }
+            best = __builtin_fminf(best, g2);
+        }
+        vflag[i] = best <= 0.f ? 1 : 0;
+        (void)KP;
+    }
+}
+
+// ------------------------------------------------------------------ pre-pass
+__global__ void __launch_bounds__(kTile) k_batch_prepass(const BPlan *plans, int n_plans) {
+    __shared__ uint32_t wave_cnt[kTile / kWave];
+    const uint32_t g = blockIdx.x;
+    const int p = find_plan(0, n_plans, g, [&](int i) { return plans[i].tile_base; });
+    const EdgeArgs &A = plans[p].A;
+    const uint32_t tile = g - plans[p].tile_base;
+    const uint32_t row = tile / A.tiles_per_row;
+    const uint32_t seg = tile - row * A.tiles_per_row;
+    const RowInfo ri = decode_row(A, row);
+    const uint32_t n = seg * kTile + threadIdx.x;
+    const bool valid = n < (uint32_t)A.N;
+    bool cand = false;
+    if (valid) {
+        const uint32_t uid = ri.u_base + n * ri.u_step, vid = ri.v_base + n * ri.v_step;
+        float u[GTMP_MAX_DOF], v[GTMP_MAX_DOF];
+        load_vertex<GTMP_MAX_DOF>(A, uid, u);
+        load_vertex<GTMP_MAX_DOF>(A, vid, v);
+        const float len = edge_len<GTMP_MAX_DOF>(u, v, A.d);
+        const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
+        bool failed = (A.vflag[uid] | A.vflag[vid]) != 0 || len > A.max_len;
+        if (A.prune) failed = failed || A.prune[e] != 0;
+        ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
+        if (A.flags) A.flags[e] = 1;
+        cand = !failed;
+    }
+    const uint64_t mask = ballot(cand);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) wave_cnt[w] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kTile / kWave; ++k) {
+        if (k < w) base += wave_cnt[k];
+        total += wave_cnt[k];
+    }
+    if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
+    if (threadIdx.x == 0) A.tile_cnt[tile] = total;
+}
+
+// ------------------------------------------------------------------ interior (persistent)
+// Lanes of a wave always hold edges of one plan: obstacles and the robot
+// table are read with wave-uniform addresses.  A wave that draws a tile of
+// another plan finishes its edges before it switches.
+template <class Model, bool UNIFORM_R, int NCH>
+__global__ void __launch_bounds__(256, NCH == 1 ? 3 : 4)
+    k_batch_interior(const BPlan *plans, int p0, int p1, uint32_t n_gtiles, uint32_t *gcounter,
+                     unsigned long long *stats) {
+    constexpr int D = Model::D;
+    constexpr int KP = Model::KP;
+    constexpr bool ARM = Model::kArm;
+    constexpr int W = ARM ? 3 : D;
+    constexpr int SP = ARM ? 1 : KP;
+    constexpr int KC = ARM ? KP / NCH : KP;
+    __shared__ float tord[4][GTMP_MAX_H];
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+
+    int cur = -1;               // plan of the lanes' edges (wave uniform)
+    uint32_t tile = 0, cnt = 0, pos = 0, pending = 0xffffffffu;
+    int pend_plan = -1;
+    RowInfo ri{};
+    bool exhausted = false;
+    unsigned long long n_states = 0, n_edges = 0;
+    bool has = false;
+    float u[D], dv[D];
+    uint32_t e = 0;
+    int j = 0;
+    int n_int = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) { u[i] = 0.f; dv[i] = 0.f; }
+
+    while (true) {
+        uint64_t need = ballot(!has);
+        int n_need = __popcll(need);
+        while (n_need > 0 && !exhausted) {
+            const uint32_t avail = cnt - pos;
+            if (avail == 0 && pending == 0xffffffffu) {
+                uint32_t t = 0;
+                if (lane == 0) t = atomicAdd(gcounter, 1u);
+                t = uniform(t);
+                if (t >= n_gtiles) {
+                    exhausted = true;
+                    break;
+                }
+                pending = t;
+                pend_plan = find_plan(p0, p1, t, [&](int i) { return plans[i].gtile_base; });
+            }
+            if (avail == 0 && pending != 0xffffffffu) {
+                if (pend_plan != cur) {
+                    if (ballot(has) != 0) break;  // finish the current plan's edges first
+                    cur = pend_plan;
+                    n_int = plans[cur].A.n_int;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    for (int i = lane; i < n_int; i += kWave) tord[wv][i] = plans[cur].A.tord[i];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+                const EdgeArgs &A = plans[cur].A;
+                tile = pending - plans[cur].gtile_base;
+                pending = 0xffffffffu;
+                ri = decode_row(A, tile / A.tiles_per_row);
+                cnt = uniform(A.tile_cnt[tile]);
+                pos = 0;
+                continue;
+            }
+            const EdgeArgs &A = plans[cur].A;
+            const uint32_t take = avail < (uint32_t)n_need ? avail : (uint32_t)n_need;
+            const int r = rank_in(need);
+            if (!has && (uint32_t)r < take) {
+                const uint32_t seg = tile - (tile / A.tiles_per_row) * A.tiles_per_row;
+                const uint32_t n = seg * kTile + A.tile_off[(size_t)tile * kTile + pos + r];
+                float v[D];
+                load_vertex<D>(A, ri.u_base + n * ri.u_step, u);
+                load_vertex<D>(A, ri.v_base + n * ri.v_step, v);
+#pragma unroll
+                for (int i = 0; i < D; ++i) dv[i] = v[i] - u[i];
+                e = (uint32_t)(ri.e_base + (uint64_t)n * ri.e_step);
+                j = 0;
+                has = true;
+            }
+            pos += take;
+            n_edges += take;
+            need = ballot(!has);
+            n_need = __popcll(need);
+        }
+        const uint64_t busy = ballot(has);
+        if (busy == 0) {
+            if (exhausted) break;
+            continue;  // drained: switch plans at the top of the loop
+        }
+        n_states += (unsigned long long)__popcll(busy) * SP;
+
+        cplan Pp = (cplan)(plans + cur);
+        asm volatile("" : "+s"(Pp));
+        const SceneParams S{Pp->S.sph, Pp->S.box, Pp->S.n_sph, Pp->S.n_box};
+        float gap;
+        if constexpr (ARM) {
+            float q[D];
+            const float t = tord[wv][has ? j : 0];
+#pragma unroll
+            for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, dv[i], u[i]);
+            carm Rp = (carm)Pp->arm;
+            asm volatile("" : "+s"(Rp));
+            const auto &R = *Rp;
+            const float r0 = R.r0;
+            const v32f o = arm_fk<D>(R, q);
+            float pr[KC];
+            {
+                Probes<3, KC> P;
+                arm_spheres<KC, 0>(R, o, P);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) pr[k] = UNIFORM_R ? 0.f : (k < R.n_spheres ? R.r[k] : 0.f);
+                gap = probes_min_gap<3, KC, UNIFORM_R>(P, pr, r0, S);
+            }
+            if constexpr (NCH > 1) {
+                Probes<3, KC> P;
+                arm_spheres<KC, KC>(R, o, P);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) pr[k] = UNIFORM_R ? 0.f : (KC + k < R.n_spheres ? R.r[KC + k] : 0.f);
+                gap = __builtin_fminf(gap, probes_min_gap<3, KC, UNIFORM_R>(P, pr, r0, S));
+            }
+        } else {
+            Probes<W, KP> P;
+#pragma unroll
+            for (int s = 0; s < SP; ++s) {
+                int jj = j + s;
+                jj = jj < n_int ? jj : n_int - 1;
+                const float t = tord[wv][has ? jj : 0];
+#pragma unroll
+                for (int i = 0; i < W; ++i) P.p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
+            }
+            float pr[KP];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) pr[k] = 0.f;
+            gap = probes_min_gap<W, KP, true>(P, pr, 0.f, S);
+        }
+        if (has) {
+            if (gap <= 0.f) {
+                has = false;
+            } else {
+                j += SP;
+                if (j >= n_int) {
+                    const EdgeArgs &A = plans[cur].A;
+                    float acc = 0.f;
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        if (i < A.d) acc = __builtin_fmaf(dv[i], dv[i], acc);
+                    *cost_slot(A, e) = __builtin_sqrtf(acc);
+                    if (A.flags) A.flags[e] = 0;
+                    has = false;
+                }
+            }
+        }
+    }
+    if (stats && lane == 0) {
+        atomicAdd(&stats[0], n_states);
+        atomicAdd(&stats[1], n_edges);
+    }
+}
+
+// Edges with H == 2: every candidate is free.
+__global__ void __launch_bounds__(kTile) k_batch_no_interior(const BPlan *plans, int n_plans) {
+    const uint32_t g = blockIdx.x;
+    const int p = find_plan(0, n_plans, g, [&](int i) { return plans[i].tile_base; });
+    const EdgeArgs &A = plans[p].A;
+    if (A.n_int != 0) return;
+    const uint32_t tile = g - plans[p].tile_base;
+    if (threadIdx.x >= A.tile_cnt[tile]) return;
+    const uint32_t row = tile / A.tiles_per_row;
+    const uint32_t seg = tile - row * A.tiles_per_row;
+    const RowInfo ri = decode_row(A, row);
+    const uint32_t n = seg * kTile + A.tile_off[(size_t)tile * kTile + threadIdx.x];
+    float u[GTMP_MAX_DOF], v[GTMP_MAX_DOF];
+    load_vertex<GTMP_MAX_DOF>(A, ri.u_base + n * ri.u_step, u);
+    load_vertex<GTMP_MAX_DOF>(A, ri.v_base + n * ri.v_step, v);
+    ri.c_base[(size_t)n * ri.c_step] = edge_len<GTMP_MAX_DOF>(u, v, A.d);
+    if (A.flags) A.flags[ri.e_base + (uint64_t)n * ri.e_step] = 0;
+}
+
+// ------------------------------------------------------------------ sweep
+struct BBest {
+    float v;
+    int i;
+};
+__device__ __forceinline__ void btake(BBest &b, float v, int i) {
+    if (v < b.v) { b.v = v; b.i = i; }
+}
+__device__ __forceinline__ BBest bwave_argmin(BBest b) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(b.v, off);
+        const int oi = __shfl_xor(b.i, off);
+        if (ov < b.v || (ov == b.v && (unsigned)oi < (unsigned)b.i)) { b.v = ov; b.i = oi; }
+    }
+    return b;
+}
+
+// Step k of the backward recursion for every plan: k = 0 is the goal layer,
+// k >= 1 the inner layer m = M - 1 - k (plans with fewer layers idle).
+// One wave per (plan, row).
+__global__ void __launch_bounds__(256) k_batch_layer(const BPlan *plans, int n_plans, int k, uint32_t total_rows) {
+    const uint32_t wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (wave >= total_rows) return;
+    const int p = find_plan(0, n_plans, wave, [&](int i) { return plans[i].row_base; });
+    const BPlan &P = plans[p];
+    const EdgeArgs &A = P.A;
+    const int u = (int)(wave - P.row_base);
+    if (u >= A.N) return;
+    const int lane = lane_id();
+    const int N = A.N, M = A.M;
+    if (k == 0) {
+        if (lane == 0) {
+            BBest b{__builtin_inff(), -1};
+            for (int g = 0; g < A.G; ++g) btake(b, A.C_l[(size_t)u * A.G + g], g);
+            P.V[(size_t)(M - 1) * N + u] = b.v;
+            P.Aidx[(size_t)(M - 1) * N + u] = b.i;
+        }
+        return;
+    }
+    const int m = M - 1 - k;
+    if (m < 0) return;
+    const float *row = A.C_h + ((size_t)m * N + u) * N;
+    const float *vn = P.V + (size_t)(m + 1) * N;
+    BBest b{__builtin_inff(), -1};
+    for (int v = lane; v < N; v += kWave) btake(b, row[v] + vn[v], v);
+    b = bwave_argmin(b);
+    if (lane == 0) {
+        P.V[(size_t)m * N + u] = b.v;
+        P.Aidx[(size_t)m * N + u] = b.i;
+    }
+}
+
+// Start row, extraction and archive of every plan: one block per plan.
+__global__ void __launch_bounds__(256) k_batch_finish(const BPlan *plans, int n_plans) {
+    __shared__ float sv[4];
+    __shared__ int si[4];
+    const int p = blockIdx.x;
+    if (p >= n_plans) return;
+    const BPlan &P = plans[p];
+    const EdgeArgs &A = P.A;
+    const int N = A.N, M = A.M, d = A.d;
+    BBest b{__builtin_inff(), -1};
+    for (int u = threadIdx.x; u < N; u += blockDim.x) btake(b, A.C_s[u] + P.V[u], u);
+    b = bwave_argmin(b);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { sv[w] = b.v; si[w] = b.i; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    BBest r{__builtin_inff(), -1};
+    for (int kk = 0; kk < 4; ++kk)
+        if (sv[kk] < r.v || (sv[kk] == r.v && (unsigned)si[kk] < (unsigned)r.i)) { r.v = sv[kk]; r.i = si[kk]; }
+    *P.Vs = r.v;
+    *P.as = r.i;
+    // extraction (Alg. 1), as k_extract
+    float c = r.v;
+    int i = r.i;
+    bool ok = i >= 0 && i < N && c < __builtin_inff();
+    int ii = i;
+    for (int m = 0; m < M && ok; ++m) {
+        const int nx = P.Aidx[(size_t)m * N + ii];
+        ok = nx >= 0 && nx < (m + 1 < M ? N : A.G);
+        ii = ok ? nx : 0;
+    }
+    if (!ok) {
+        for (int m = 0; m <= M; ++m) P.idx[m] = -1;
+        for (int kk = 0; kk < (M + 2) * d; ++kk) P.wp[kk] = __builtin_nanf("");
+        c = __builtin_inff();
+    } else {
+        for (int jj = 0; jj < d; ++jj) P.wp[jj] = P.q0[jj];
+        for (int m = 0; m < M; ++m) {
+            P.idx[m] = i;
+            for (int jj = 0; jj < d; ++jj) P.wp[(size_t)(m + 1) * d + jj] = P.Q[((size_t)m * N + i) * d + jj];
+            i = P.Aidx[(size_t)m * N + i];
+        }
+        P.idx[M] = i;
+        for (int jj = 0; jj < d; ++jj) P.wp[(size_t)(M + 1) * d + jj] = P.goals[(size_t)i * d + jj];
+    }
+    *P.cost = c;
+    // archive (|K| = 1): strictly lower cost replaces
+    const uint32_t stage = *P.counter;
+    if ((int)stage < P.max_stages) P.stage_costs[stage] = c;
+    if (c < *P.best_cost) {
+        *P.best_cost = c;
+        for (int m = 0; m <= M; ++m) P.best_idx[m] = P.idx[m];
+        for (int kk = 0; kk < (M + 2) * d; ++kk) P.best_wp[kk] = P.wp[kk];
+        P.best_meta[0] = (int32_t)stage;
+        P.best_meta[1] = M;
+        P.best_meta[2] = N;
+    }
+    P.best_meta[3] = (int32_t)stage + 1;
+    *P.counter = stage + 1;
+}
+
+__global__ void k_batch_init(const BPlan *plans, int n_plans) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_plans) return;
+    const BPlan &P = plans[p];
+    *P.best_cost = __builtin_inff();
+    P.best_meta[0] = -1;
+    P.best_meta[1] = 0;
+    P.best_meta[2] = 0;
+    P.best_meta[3] = 0;
+    *P.counter = 0;
+}
+
+__global__ void k_batch_zero(uint32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void k_store_params_n(const ArmParams *src, ArmParams *dst, int n) {
+    // src is a kernel-argument-free copy path: words of n structs
+    const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
+    uint32_t *dd = reinterpret_cast<uint32_t *>(dst);
+    const size_t words = (size_t)n * (sizeof(ArmParams) / 4);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+        dd[i] = s[i];
+}
+
+// ------------------------------------------------------------------ host side
+static int persistent_blocks(const void *kernel, int per_cu_req) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    int per_cu = per_cu_req;
+    if (per_cu <= 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, 0) != hipSuccess || occ <= 0) occ = 2;
+        per_cu = occ;
+    }
+    return cus * per_cu;
+}
+
+size_t batch_table_bytes() { return sizeof(BPlan); }
+
+BatchLayout make_batch_layout(const gtmp_plan_desc *plans, int n, const gtmp_batch_opts &o) {
+    BatchLayout L{};
+    L.n = n;
+    size_t off = 0;
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    L.plan_off.resize(n);
+    L.schedules.resize(n);
+    int max_stages = 0;
+    for (int p = 0; p < n; ++p) {
+        const gtmp_plan_desc &D = plans[p];
+        std::vector<StageShape> &S = L.schedules[p];
+        if (D.mode == GTMP_ANYTIME_GROWING) {
+            int M = D.M_min, N = D.N_min, n_old = 0;
+            for (int s = 0; s < D.stages; ++s) {
+                S.push_back({M, N, n_old});
+                if (M >= D.problem.M && N >= D.problem.N) break;
+                if (N < D.problem.N) {
+                    n_old = N;
+                    N = 2 * N < D.problem.N ? 2 * N : D.problem.N;
+                } else {
+                    ++M;
+                    n_old = 0;
+                }
+            }
+        } else {
+            for (int s = 0; s < D.stages; ++s) S.push_back({D.problem.M, D.problem.N, 0});
+        }
+        if ((int)S.size() > max_stages) max_stages = (int)S.size();
+        const uint64_t M = D.problem.M, N = D.problem.N, d = D.problem.d, G = D.problem.G;
+        PlanOffsets &P = L.plan_off[p];
+        P.Q = off; off = up(off + sizeof(float) * M * N * d);
+        P.Q2 = off; off = up(off + (D.mode == GTMP_ANYTIME_GROWING ? sizeof(float) * M * N * d : 0));
+        P.Cs = off; off = up(off + sizeof(float) * N);
+        P.Ch = off; off = up(off + sizeof(float) * (M > 1 ? M - 1 : 1) * N * N);
+        P.Cl = off; off = up(off + sizeof(float) * N * G);
+        P.V = off; off = up(off + sizeof(float) * M * N);
+        P.A = off; off = up(off + sizeof(int32_t) * M * N);
+        P.small = off; off = up(off + 256 + sizeof(int32_t) * (M + 1) + sizeof(float) * (M + 2) * d);
+        const EdgePlan ep = make_edge_plan(D.problem);
+        P.edge = off; off = up(off + ep.total);
+        if (D.mode == GTMP_ANYTIME_GROWING) {
+            const ExpandPlan xp = make_expand_plan(D.problem);
+            P.expand = off; off = up(off + xp.total);
+        } else {
+            P.expand = 0;
+        }
+    }
+    L.max_stages = max_stages;
+    L.off_arm = off; off = up(off + sizeof(ArmParams) * (size_t)n);
+    L.off_tables = off; off = up(off + sizeof(BPlan) * (size_t)n * (size_t)max_stages);
+    L.off_bases = off; off = up(off + sizeof(uint64_t) * (size_t)n * (size_t)max_stages);
+    L.off_counters = off; off = up(off + sizeof(uint32_t) * 8 * (size_t)max_stages + 256);
+    L.total = off;
+    (void)o;
+    return L;
+}
+
+hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host, int n, const gtmp_batch_opts &o,
+                        const BatchLayout &L, const BatchOut &out, void *workspace, hipStream_t s) {
+    char *ws = static_cast<char *>(workspace);
+    ArmParams *arm_dev = reinterpret_cast<ArmParams *>(ws + L.off_arm);
+    BPlan *tables = reinterpret_cast<BPlan *>(ws + L.off_tables);
+    uint64_t *bases = reinterpret_cast<uint64_t *>(ws + L.off_bases);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(ws + L.off_counters);
+
+    // ---- host tables of every stage (plans grouped: 2D points, 3D points, arms)
+    std::vector<ArmParams> arms(arms_host, arms_host + n);
+    std::vector<int> group(n);
+    for (int p = 0; p < n; ++p) {
+        const gtmp_plan_desc &D = plans[p];
+        group[p] = D.robot.kind == GTMP_ROBOT_DH_ARM ? 2 : (D.scene.wdim == 2 ? 0 : 1);
+    }
+    std::vector<int> order(n);
+    for (int p = 0; p < n; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return group[a] < group[b]; });
+    int kp = 8;
+    for (int p = 0; p < n; ++p)
+        if (group[p] == 2) kp = std::max(kp, ((arms[p].n_spheres + 7) / 8) * 8);
+    bool uniform_r = true;
+    for (int p = 0; p < n; ++p)
+        if (group[p] == 2 && !arms[p].uniform_r) uniform_r = false;
+
+    struct StageInfo {
+        int count;
+        int g0, g1, g2, g3;       // plan index ranges per group: [g0,g1) 2D, [g1,g2) 3D, [g2,g3) arms
+        uint32_t verts[3];
+        uint32_t gtiles[3];
+        uint32_t tiles;
+        uint32_t rows;
+        uint64_t samples;
+        int maxM;
+        bool any_interior;
+    };
+    std::vector<StageInfo> info(L.max_stages);
+    std::vector<BPlan> host(n * (size_t)L.max_stages);
+    std::vector<uint64_t> host_bases(n * (size_t)L.max_stages);
+    for (int st = 0; st < L.max_stages; ++st) {
+        StageInfo I{};
+        uint32_t vb[3] = {0, 0, 0}, gb[3] = {0, 0, 0}, tb = 0, rb = 0;
+        uint64_t sb = 0;
+        int cnt = 0;
+        int gstart[4] = {0, 0, 0, 0};
+        for (int gi = 0; gi < 3; ++gi) {
+            gstart[gi] = cnt;
+            for (int p : order) {
+                if (group[p] != gi || st >= (int)L.schedules[p].size()) continue;
+                const gtmp_plan_desc &D = plans[p];
+                const StageShape sh = L.schedules[p][st];
+                gtmp_problem pp = D.problem;
+                pp.M = sh.M;
+                pp.N = sh.N;
+                const EdgePlan ep = make_edge_plan(pp);
+                const PlanOffsets &PO = L.plan_off[p];
+                BPlan B{};
+                char *ews = ws + PO.edge;
+                EdgeArgs &A = B.A;
+                A.d = pp.d; A.M = pp.M; A.N = pp.N; A.G = pp.G; A.H = pp.H; A.dp = vertex_stride(pp.d);
+                A.penalty = pp.penalty; A.max_len = pp.max_edge_len;
+                A.tiles_per_row = ep.tiles_per_row; A.n_tiles = ep.n_tiles; A.n_vertices = ep.n_vertices;
+                A.verts = reinterpret_cast<float *>(ews + ep.off_verts);
+                A.vflag = reinterpret_cast<uint8_t *>(ews + ep.off_vflag);
+                A.C_s = reinterpret_cast<float *>(ws + PO.Cs);
+                A.C_h = reinterpret_cast<float *>(ws + PO.Ch);
+                A.C_l = reinterpret_cast<float *>(ws + PO.Cl);
+                A.flags = nullptr;
+                A.prune = nullptr;
+                A.tile_off = reinterpret_cast<uint8_t *>(ews + ep.off_tile_off);
+                A.tile_cnt = reinterpret_cast<uint32_t *>(ews + ep.off_tile_cnt);
+                A.counter = nullptr;
+                A.stats = nullptr;
+                uint8_t ordr[GTMP_MAX_H];
+                A.n_int = interior_order(pp.H, ordr);
+                for (int i = 0; i < A.n_int; ++i) A.tord[i] = (float)ordr[i] / (float)(pp.H - 1);
+                B.S = SceneParams{D.scene.spheres, D.scene.boxes, D.scene.n_spheres, D.scene.n_boxes};
+                B.arm = gi == 2 ? arm_dev + p : nullptr;
+                B.group = gi;
+                B.vert_base = vb[gi]; vb[gi] += ep.n_vertices;
+                B.gtile_base = gb[gi]; gb[gi] += ep.n_tiles;
+                B.tile_base = tb; tb += ep.n_tiles;
+                B.row_base = rb; rb += (uint32_t)pp.N;
+                // samples: restart stages draw uniform samples into Q; growing
+                // stages expand into Q / Q2 alternately (stage parity)
+                float *Qa = reinterpret_cast<float *>(ws + PO.Q);
+                float *Qb = reinterpret_cast<float *>(ws + PO.Q2);
+                const bool grow = D.mode == GTMP_ANYTIME_GROWING;
+                B.Q = grow ? ((st & 1) ? Qb : Qa) : Qa;
+                B.q0 = D.q0;
+                B.goals = D.goals;
+                char *small = ws + PO.small;
+                B.V = reinterpret_cast<float *>(ws + PO.V);
+                B.Aidx = reinterpret_cast<int32_t *>(ws + PO.A);
+                B.Vs = reinterpret_cast<float *>(small);
+                B.as = reinterpret_cast<int32_t *>(small + 4);
+                B.cost = reinterpret_cast<float *>(small + 8);
+                B.idx = reinterpret_cast<int32_t *>(small + 256);
+                B.wp = reinterpret_cast<float *>(small + 256 + sizeof(int32_t) * (D.problem.M + 1));
+                B.best_cost = out.best_cost + p;
+                B.best_idx = out.best_idx + out.idx_offset[p];
+                B.best_wp = out.best_wp + out.wp_offset[p];
+                B.best_meta = out.best_meta + 4 * (size_t)p;
+                B.stage_costs = out.stage_costs + (size_t)p * out.stage_stride;
+                B.max_stages = out.stage_stride;
+                B.counter = reinterpret_cast<uint32_t *>(small + 12);
+                B.sample = grow ? 0 : 1;
+                B.k0 = (uint32_t)(D.seed & 0xffffffffu);
+                B.k1 = (uint32_t)(D.seed >> 32);
+                B.stage = (uint32_t)st;
+                for (int j = 0; j < pp.d; ++j) {
+                    B.lo[j] = pp.lo[j];
+                    B.wd[j] = pp.hi[j] - pp.lo[j];
+                }
+                host[(size_t)st * n + cnt] = B;
+                host_bases[(size_t)st * n + cnt] = sb;
+                sb += grow ? 0 : (uint64_t)pp.M * pp.N * ((pp.d + 3) / 4);
+                if (A.n_int > 0) I.any_interior = true;
+                if (pp.M > I.maxM) I.maxM = pp.M;
+                ++cnt;
+            }
+        }
+        gstart[3] = cnt;
+        I.count = cnt;
+        I.g0 = gstart[0]; I.g1 = gstart[1]; I.g2 = gstart[2]; I.g3 = gstart[3];
+        for (int gi = 0; gi < 3; ++gi) {
+            I.verts[gi] = vb[gi];
+            I.gtiles[gi] = gb[gi];
+        }
+        I.tiles = tb;
+        I.rows = rb;
+        I.samples = sb;
+        info[st] = I;
+    }
+    // tables are written once, before any work is enqueued, after the work
+    // already on the stream (which may still read an earlier table) is done
+    hipError_t err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return err;
+    err = hipMemcpy(arm_dev, arms.data(), sizeof(ArmParams) * n, hipMemcpyHostToDevice);
+    if (err != hipSuccess) return err;
+    err = hipMemcpy(tables, host.data(), sizeof(BPlan) * host.size(), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return err;
+    err = hipMemcpy(bases, host_bases.data(), sizeof(uint64_t) * host_bases.size(), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return err;
+
+    const int spi = o.states_per_iter == 1 || o.states_per_iter == 2 || o.states_per_iter == 8 ? o.states_per_iter : 4;
+    const int nch = o.sphere_chunks == 1 ? 1 : 2;
+
+    auto enqueue = [&](hipStream_t st_) -> hipError_t {
+        if (info.empty()) return hipSuccess;
+        // archive init over the plans of stage 0 (every plan has a stage 0)
+        hipLaunchKernelGGL(k_batch_init, dim3((info[0].count + 255) / 256), dim3(256), 0, st_, tables, info[0].count);
+        for (int st = 0; st < L.max_stages; ++st) {
+            const StageInfo &I = info[st];
+            const BPlan *T = tables + (size_t)st * n;
+            const uint64_t *Bs = bases + (size_t)st * n;
+            uint32_t *ctr = counters + 8 * st;
+            hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(64), 0, st_, ctr, 8);
+            // samples
+            if (I.samples > 0)
+                hipLaunchKernelGGL(k_batch_sample, dim3((unsigned)((I.samples + 255) / 256)), dim3(256), 0, st_, T,
+                                   I.count, Bs, I.samples);
+            for (int p = 0; p < n; ++p) {
+                if (plans[p].mode != GTMP_ANYTIME_GROWING || st >= (int)L.schedules[p].size()) continue;
+                const StageShape sh = L.schedules[p][st];
+                gtmp_problem pp = plans[p].problem;
+                pp.M = sh.M;
+                pp.N = sh.N;
+                const PlanOffsets &PO = L.plan_off[p];
+                float *Qa = reinterpret_cast<float *>(ws + PO.Q);
+                float *Qb = reinterpret_cast<float *>(ws + PO.Q2);
+                float *dst = (st & 1) ? Qb : Qa;
+                float *src = (st & 1) ? Qa : Qb;
+                hipError_t e = launch_expand(pp, plans[p].q0, plans[p].goals, src, sh.n_old, dst, out.best_cost + p,
+                                             plans[p].seed, (uint64_t)st, ws + PO.expand, st_);
+                if (e != hipSuccess) return e;
+            }
+            // vertices per group
+            if (I.verts[0] > 0)
+                hipLaunchKernelGGL((k_batch_vertices<0, 1>), dim3((I.verts[0] + 255) / 256), dim3(256), 0, st_, T,
+                                   I.g0, I.g1, I.verts[0]);
+            if (I.verts[1] > 0)
+                hipLaunchKernelGGL((k_batch_vertices<1, 1>), dim3((I.verts[1] + 255) / 256), dim3(256), 0, st_, T,
+                                   I.g1, I.g2, I.verts[1]);
+            if (I.verts[2] > 0)
+                hipLaunchKernelGGL((k_batch_vertices<2, 8>), dim3((I.verts[2] + 255) / 256), dim3(256), 0, st_, T,
+                                   I.g2, I.g3, I.verts[2]);
+            hipLaunchKernelGGL(k_batch_prepass, dim3(I.tiles), dim3(kTile), 0, st_, T, I.count);
+            hipLaunchKernelGGL(k_batch_no_interior, dim3(I.tiles), dim3(kTile), 0, st_, T, I.count);
+            // persistent interior per group
+            if (I.gtiles[0] > 0) {
+                const void *k = spi == 1 ? (const void *)k_batch_interior<PointModel<2, 1>, true, 1>
+                              : spi == 2 ? (const void *)k_batch_interior<PointModel<2, 2>, true, 1>
+                              : spi == 8 ? (const void *)k_batch_interior<PointModel<2, 8>, true, 1>
+                                         : (const void *)k_batch_interior<PointModel<2, 4>, true, 1>;
+                const int grid = persistent_blocks(k, o.blocks_per_cu);
+                void *args[] = {(void *)&T, (void *)&I.g0, (void *)&I.g1, (void *)&I.gtiles[0], (void *)&ctr,
+                                (void *)&out.stats};
+                hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, st_);
+                if (e != hipSuccess) return e;
+            }
+            if (I.gtiles[1] > 0) {
+                const void *k = (const void *)k_batch_interior<PointModel<3, 4>, true, 1>;
+                const int grid = persistent_blocks(k, o.blocks_per_cu);
+                uint32_t *c1 = ctr + 1;
+                void *args[] = {(void *)&T, (void *)&I.g1, (void *)&I.g2, (void *)&I.gtiles[1], (void *)&c1,
+                                (void *)&out.stats};
+                hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, st_);
+                if (e != hipSuccess) return e;
+            }
+            if (I.gtiles[2] > 0) {
+                const void *k = nullptr;
+#define GTMP_BK(K) \
+    if (kp == K) k = nch == 1 ? (uniform_r ? (const void *)k_batch_interior<ArmModel<K>, true, 1> : (const void *)k_batch_interior<ArmModel<K>, false, 1>) \
+                              : (uniform_r ? (const void *)k_batch_interior<ArmModel<K>, true, 2> : (const void *)k_batch_interior<ArmModel<K>, false, 2>);
+                GTMP_BK(8) GTMP_BK(16) GTMP_BK(24) GTMP_BK(32) GTMP_BK(40) GTMP_BK(48) GTMP_BK(56) GTMP_BK(64)
+#undef GTMP_BK
+                if (!k) return hipErrorInvalidValue;
+                const int grid = persistent_blocks(k, o.blocks_per_cu);
+                uint32_t *c2 = ctr + 2;
+                void *args[] = {(void *)&T, (void *)&I.g2, (void *)&I.g3, (void *)&I.gtiles[2], (void *)&c2,
+                                (void *)&out.stats};
+                hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, st_);
+                if (e != hipSuccess) return e;
+            }
+            // backward sweep: step 0 = goal layer, step k = layer M-1-k
+            const unsigned lblocks = (I.rows + 3) / 4;
+            for (int k = 0; k < I.maxM; ++k)
+                hipLaunchKernelGGL(k_batch_layer, dim3(lblocks), dim3(256), 0, st_, T, I.count, k, I.rows);
+            hipLaunchKernelGGL(k_batch_finish, dim3(I.count), dim3(256), 0, st_, T, I.count);
+        }
+        return hipGetLastError();
+    };
+
+    // the sample expansion of growing plans sorts with a library routine
+    // that clears memory with hipMemsetAsync: such batches are not captured
+    bool any_growing = false;
+    for (int p = 0; p < n; ++p) any_growing = any_growing || plans[p].mode == GTMP_ANYTIME_GROWING;
+    if (!o.use_graph || any_growing) return enqueue(s);
+    hipStream_t cs;
+    err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (err != hipSuccess) return err;
+    err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) { (void)hipStreamDestroy(cs); return err; }
+    hipError_t e_ops = enqueue(cs);
+    hipGraph_t g = nullptr;
+    err = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (e_ops != hipSuccess) { if (g) (void)hipGraphDestroy(g); return e_ops; }
+    if (err != hipSuccess) return err;
+    hipGraphExec_t exec = nullptr;
+    err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) return err;
+    err = hipGraphLaunch(exec, s);
+    // the executable graph is released once the stream has run it
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    (void)hipGraphExecDestroy(exec);
+    return err;
+}
+
+}  // namespace gtmp

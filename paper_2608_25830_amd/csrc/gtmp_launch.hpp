@@ -7,6 +7,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "gtmp.h"
 #include "gtmp_device.hpp"
 
@@ -87,6 +90,33 @@ struct AnytimeOut {
 hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const SceneParams &scene, int wdim,
                           const float *q0, const float *goals, uint64_t seed, const gtmp_anytime_opts &o,
                           const gtmp_edge_opts &eo, const AnytimeOut &out, void *workspace, hipStream_t s);
+
+// ---- batched plans (batch.hip)
+struct StageShape {
+    int M, N, n_old;
+};
+struct PlanOffsets {
+    size_t Q, Q2, Cs, Ch, Cl, V, A, small, edge, expand;
+};
+struct BatchLayout {
+    int n, max_stages;
+    std::vector<PlanOffsets> plan_off;
+    std::vector<std::vector<StageShape>> schedules;
+    size_t off_arm, off_tables, off_bases, off_counters, total;
+};
+BatchLayout make_batch_layout(const gtmp_plan_desc *plans, int n, const gtmp_batch_opts &o);
+struct BatchOut {
+    float *best_cost;
+    int32_t *best_idx;
+    float *best_wp;
+    int32_t *best_meta;
+    float *stage_costs;
+    int stage_stride;
+    std::vector<size_t> idx_offset, wp_offset;
+    unsigned long long *stats;
+};
+hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host, int n, const gtmp_batch_opts &o,
+                        const BatchLayout &L, const BatchOut &out, void *workspace, hipStream_t s);
 
 // Bisection order of the interior states 1..H-2 (midpoint first, then the
 // midpoints of the remaining halves, breadth first).  Returns the count.

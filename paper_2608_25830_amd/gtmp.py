@@ -87,6 +87,23 @@ class gtmp_anytime_opts(C.Structure):
 
 GTMP_ANYTIME_RESTART, GTMP_ANYTIME_GROWING = 0, 1
 
+
+class gtmp_plan_desc(C.Structure):
+    _fields_ = [("problem", gtmp_problem), ("robot", gtmp_robot), ("scene", gtmp_scene), ("q0", C.c_void_p),
+                ("goals", C.c_void_p), ("seed", C.c_uint64), ("mode", C.c_int32), ("stages", C.c_int32),
+                ("M_min", C.c_int32), ("N_min", C.c_int32)]
+
+
+class gtmp_batch_opts(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("states_per_iter", C.c_int32), ("sphere_chunks", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("stats", C.c_void_p)]
+
+
+_lib.gtmp_batch_workspace_size.argtypes = [C.POINTER(gtmp_plan_desc), C.c_int32, C.POINTER(gtmp_batch_opts),
+                                           C.POINTER(C.c_size_t)]
+_lib.gtmp_plan_batch.argtypes = [C.POINTER(gtmp_plan_desc), C.c_int32, C.POINTER(gtmp_batch_opts), _vp, _vp, _vp,
+                                 _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+
 _lib.gtmp_expand_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(C.c_size_t)]
 _lib.gtmp_expand_samples.argtypes = [C.POINTER(gtmp_problem), _vp, _vp, _vp, C.c_int32, _vp, _vp, C.c_uint64,
                                      C.c_uint64, _vp, C.c_size_t, _vp]
@@ -101,7 +118,7 @@ _lib.gtmp_plan_anytime.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot
 EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample_layers",
            "gtmp_edge_check_workspace_size", "gtmp_edge_check_cost", "gtmp_state_check", "gtmp_minplus_sweep",
            "gtmp_extract_path", "gtmp_expand_workspace_size", "gtmp_expand_samples", "gtmp_sample_informed",
-           "gtmp_anytime_workspace_size", "gtmp_plan_anytime"]
+           "gtmp_anytime_workspace_size", "gtmp_plan_anytime", "gtmp_batch_workspace_size", "gtmp_plan_batch"]
 
 
 def _check(st):
@@ -394,3 +411,76 @@ class AnytimePlanner:
         gtmp_plan_anytime(self.prob, self.robot, self.scene, self.q0, self.goals, seed, self.opts, self.best_cost,
                           self.best_idx, self.best_wp, self.best_meta, self.stage_costs, self.workspace,
                           self.edge_opts, stream)
+
+
+def gtmp_batch_workspace_size(descs, opts) -> int:
+    n = C.c_size_t()
+    _check(_lib.gtmp_batch_workspace_size(descs, len(descs), C.byref(opts), C.byref(n)))
+    return n.value
+
+
+def gtmp_plan_batch(descs, opts, best_cost, best_idx, best_wp, best_meta, stage_costs, stage_stride, workspace,
+                    stream=None):
+    return _check(_lib.gtmp_plan_batch(descs, len(descs), C.byref(opts), _p(best_cost), _p(best_idx), _p(best_wp),
+                                       _p(best_meta), _p(stage_costs), int(stage_stride), _p(workspace),
+                                       workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+class BatchPlanner:
+    """A batch of independent plans.  ``specs`` is a list of dicts with keys
+    ``w`` (workload dict), ``mode`` (GTMP_ANYTIME_RESTART / GROWING),
+    ``stages`` and, for growing plans, ``M_min`` / ``N_min`` (the workload's
+    M, N are the maxima)."""
+
+    def __init__(self, specs, use_graph=False, device="cuda"):
+        self.specs = specs
+        n = len(specs)
+        self.descs = (gtmp_plan_desc * n)()
+        self.keep = []
+        idx_off, wp_off = [], []
+        io = wo = 0
+        for i, sp in enumerate(specs):
+            w = sp["w"]
+            d, M, N, G, H = (int(w[k]) for k in ("d", "M", "N", "G", "H"))
+            D = self.descs[i]
+            D.problem = make_problem(d, M, N, G, H, w["lo"], w["hi"], w["penalty"])
+            if w["kind"] == "point2d":
+                D.robot = make_point_robot()
+                scene = Scene(2, w["circles"], w["boxes"], device)
+            else:
+                D.robot = make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"])
+                scene = Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+            q0 = torch.from_numpy(np.asarray(w["q0"], np.float32)).to(device)
+            goals = torch.from_numpy(np.asarray(w["goals"], np.float32).reshape(G, d)).to(device)
+            self.keep += [scene, q0, goals]
+            D.scene = scene.c
+            D.q0, D.goals = q0.data_ptr(), goals.data_ptr()
+            D.seed = int(sp.get("seed", w["seed"]))
+            D.mode = int(sp.get("mode", GTMP_ANYTIME_RESTART))
+            D.stages = int(sp.get("stages", 1))
+            D.M_min = int(sp.get("M_min", M))
+            D.N_min = int(sp.get("N_min", N))
+            idx_off.append(io)
+            wp_off.append(wo)
+            io += M + 1
+            wo += (M + 2) * d
+        self.idx_off, self.wp_off = idx_off, wp_off
+        self.opts = gtmp_batch_opts()
+        self.opts.use_graph = int(use_graph)
+        self.stats = torch.zeros((4,), device=device, dtype=torch.int64)
+        self.opts.stats = self.stats.data_ptr()
+        self.stage_stride = max(int(sp.get("stages", 1)) for sp in specs)
+        self.best_cost = torch.empty((n,), device=device)
+        self.best_idx = torch.empty((io,), device=device, dtype=torch.int32)
+        self.best_wp = torch.empty((wo,), device=device)
+        self.best_meta = torch.empty((n, 4), device=device, dtype=torch.int32)
+        self.stage_costs = torch.full((n, self.stage_stride), float("nan"), device=device)
+        self.workspace = _aligned_workspace(gtmp_batch_workspace_size(self.descs, self.opts), device)
+
+    def run(self, stream=None):
+        gtmp_plan_batch(self.descs, self.opts, self.best_cost, self.best_idx, self.best_wp, self.best_meta,
+                        self.stage_costs, self.stage_stride, self.workspace, stream)
+
+    def plan_idx(self, i):
+        M = self.descs[i].problem.M
+        return self.best_idx[self.idx_off[i]:self.idx_off[i] + M + 1]
