@@ -13,6 +13,13 @@ stream it runs on, and the FP64 oracle timed on the host cores on a bounded
 sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload arm7]
+    python bench.py --form batch [--steps 2] [--warmup 1]
+
+``--form batch`` times the batched form instead: 512 independent plans
+(2D point robot and 7-DoF arm mixed, N in {128..2048}, M in 4..16, H = 16,
+plain / restart / growing policies) through gtmp_plan_batch, one step = the
+whole batch, next to the same plans run one by one through the single-plan
+entry point; every plan's result must be bit-identical between the two.
 """
 from __future__ import annotations
 
@@ -89,12 +96,82 @@ def cpu_baseline(w, min_seconds=10.0, max_seconds=30.0):
                        f"all {H} states each, {el:.1f} s wall", plans_per_s=rate / (E * H))
 
 
+def bench_batch(args, torch, wl, gtmp):
+    specs = wl.batch_specs(n=args.batch_plans)
+    opts = {}
+    if args.tune:
+        from paper_2608_25830_amd import autotune
+        opts = autotune.tune_batch(specs)
+    print(f"[bench] batch of {len(specs)} plans, opts {opts}", file=sys.stderr, flush=True)
+    bp = gtmp.BatchPlanner(specs, opts=opts)
+    for _ in range(args.warmup):
+        bp.run()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        bp.run()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_batch = start.elapsed_time(stop) / args.steps
+    print(f"[bench] batch {ms_batch:.1f} ms/step", file=sys.stderr, flush=True)
+    best_b = bp.best_cost.cpu().numpy()
+    stages_b = bp.best_meta[:, 3].cpu().numpy()
+    # the same plans, one single-plan call each (each warmed once, then timed)
+    ms_single = 0.0
+    same = 0
+    for i, sp in enumerate(specs):
+        ap = gtmp.single_planner(sp)
+        seed = int(sp.get("seed", sp["w"]["seed"]))
+        ap.run(seed)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ap.run(seed)
+        b.record()
+        b.synchronize()
+        ms_single += a.elapsed_time(b)
+        same += int(float(ap.best_cost.item()) == float(best_b[i]) or
+                    (not np.isfinite(best_b[i]) and not np.isfinite(float(ap.best_cost.item()))))
+        del ap
+    print(f"[bench] single-plan calls {ms_single:.1f} ms", file=sys.stderr, flush=True)
+    n = len(specs)
+    n_arm = sum(sp["w"]["kind"] != "point2d" for sp in specs)
+    out = {
+        "metric": "plans/s (batched, mixed 2D / 7-DoF plans)",
+        "value": n / (ms_batch / 1e3),
+        "unit": "plans/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_batch,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {n} plans ({n_arm} arm, {n - n_arm} 2D point), N in 128..2048, "
+                               f"M in 4..16, H=16, plain / restart(4) / growing policies",
+                   "plans": n, "stages_run": int(stages_b.sum())},
+        "single_plan_calls": {"ms": ms_single, "plans_per_s": n / (ms_single / 1e3)},
+        "speedup_vs_single": ms_single / ms_batch,
+        "equal_cost_frac": same / n,
+        "batch_opts": opts,
+        "wall_s": wall,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="arm7")
+    ap.add_argument("--form", default="plain", choices=["plain", "batch"])
+    ap.add_argument("--batch-plans", type=int, default=512)
+    ap.add_argument("--tune", action="store_true", help="batch: pick launch shapes with the autotuner first")
     ap.add_argument("--scene", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -123,6 +200,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.form == "batch":
+        return bench_batch(args, torch, wl, gtmp)
     w = wl.make_workload(args.workload, args.scene)
     pl = gtmp.Planner(w)
     for kv in args.opt:

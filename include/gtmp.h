@@ -329,6 +329,8 @@ gtmp_status gtmp_batch_workspace_size(const gtmp_plan_desc *plans, int32_t n, co
  *   best_wp     [sum_p (M_p + 2) d_p]
  *   best_meta   [n][4] = (best stage, its M, its N, stages run)
  *   stage_costs [n][stage_stride], stage_stride >= the largest stage count
+ * A plan's best_idx / best_wp hold the best stage's chain in their first
+ * M + 1 / (M + 2) d entries (M = best_meta[1]); the rest is left as it was.
  * The call writes its tables into the workspace with a synchronous copy
  * after waiting for `stream`, then enqueues (or, with use_graph, launches the
  * captured graph and waits for it). */

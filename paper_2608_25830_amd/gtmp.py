@@ -426,13 +426,31 @@ def gtmp_plan_batch(descs, opts, best_cost, best_idx, best_wp, best_meta, stage_
                                        workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
+_MODES = {"plain": GTMP_ANYTIME_RESTART, "restart": GTMP_ANYTIME_RESTART, "growing": GTMP_ANYTIME_GROWING}
+
+
+def spec_mode(sp) -> int:
+    m = sp.get("mode", GTMP_ANYTIME_RESTART)
+    return _MODES[m] if isinstance(m, str) else int(m)
+
+
+def single_planner(sp, device="cuda", use_graph=False) -> "AnytimePlanner":
+    """The single-plan equivalent of one batch entry (same policy and sizes)."""
+    w = sp["w"]
+    if spec_mode(sp) == GTMP_ANYTIME_GROWING:
+        return AnytimePlanner(w, GTMP_ANYTIME_GROWING, int(sp["stages"]), M_min=int(sp["M_min"]),
+                              N_min=int(sp["N_min"]), use_graph=use_graph, device=device)
+    return AnytimePlanner(w, GTMP_ANYTIME_RESTART, int(sp.get("stages", 1)), use_graph=use_graph, device=device)
+
+
 class BatchPlanner:
     """A batch of independent plans.  ``specs`` is a list of dicts with keys
-    ``w`` (workload dict), ``mode`` (GTMP_ANYTIME_RESTART / GROWING),
-    ``stages`` and, for growing plans, ``M_min`` / ``N_min`` (the workload's
-    M, N are the maxima)."""
+    ``w`` (workload dict), ``mode`` (GTMP_ANYTIME_RESTART / GROWING, or one of
+    "plain", "restart", "growing"), ``stages``, optionally ``seed`` (default:
+    the workload's) and, for growing plans, ``M_min`` / ``N_min`` (the
+    workload's M, N are the maxima)."""
 
-    def __init__(self, specs, use_graph=False, device="cuda"):
+    def __init__(self, specs, use_graph=False, device="cuda", opts=None):
         self.specs = specs
         n = len(specs)
         self.descs = (gtmp_plan_desc * n)()
@@ -456,7 +474,7 @@ class BatchPlanner:
             D.scene = scene.c
             D.q0, D.goals = q0.data_ptr(), goals.data_ptr()
             D.seed = int(sp.get("seed", w["seed"]))
-            D.mode = int(sp.get("mode", GTMP_ANYTIME_RESTART))
+            D.mode = spec_mode(sp)
             D.stages = int(sp.get("stages", 1))
             D.M_min = int(sp.get("M_min", M))
             D.N_min = int(sp.get("N_min", N))
@@ -467,6 +485,10 @@ class BatchPlanner:
         self.idx_off, self.wp_off = idx_off, wp_off
         self.opts = gtmp_batch_opts()
         self.opts.use_graph = int(use_graph)
+        if opts:
+            for k in ("states_per_iter", "sphere_chunks", "blocks_per_cu"):
+                if k in opts:
+                    setattr(self.opts, k, int(opts[k]))
         self.stats = torch.zeros((4,), device=device, dtype=torch.int64)
         self.opts.stats = self.stats.data_ptr()
         self.stage_stride = max(int(sp.get("stages", 1)) for sp in specs)

@@ -211,3 +211,39 @@ def make_workload(name: str, scene: int = 0, *, seed: int | None = None, sg: int
                  q0=q0, goals=qg.reshape(1, d))
     return w
 
+
+
+# --------------------------------------------------------------------------- #
+# batches of independent plans
+# --------------------------------------------------------------------------- #
+BATCH = dict(n=512, N=(128, 256, 512, 1024, 2048), M=(4, 16), H=16, restart_stages=4)
+
+
+def batch_specs(n: int = BATCH["n"], seed: int = 0, N_choices=BATCH["N"], M_range=BATCH["M"], H: int = BATCH["H"],
+                restart_stages: int = BATCH["restart_stages"]):
+    """A seeded batch of independent plans: robot by a fair coin (2D point
+    robot on the large 2D scenes, or the 7-DoF arm on its scenes), scene
+    uniform over the five validated ones, N uniform over ``N_choices``, M
+    uniform over ``M_range`` (inclusive), and the policy uniform over
+    ``plain`` (one stage), ``restart`` (``restart_stages`` stages) and
+    ``growing`` (from (M-2, N/4) to (M, N): the stages at N/4, N/2 and N,
+    then M-1 and M).  Each plan draws its samples with its own key
+    (``seed`` field)."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x6A7C, seed]))
+    specs = []
+    for i in range(n):
+        arm = bool(rng.integers(0, 2))
+        scene = int(rng.integers(0, 5))
+        N = int(N_choices[int(rng.integers(0, len(N_choices)))])
+        M = int(rng.integers(M_range[0], M_range[1] + 1))
+        mode = ("plain", "restart", "growing")[int(rng.integers(0, 3))]
+        w = make_workload("arm7" if arm else "2d-large", scene, M=M, N=N, H=H)
+        sp = dict(w=w, mode=mode, seed=1000003 * (seed + 1) + i)
+        if mode == "plain":
+            sp["stages"] = 1
+        elif mode == "restart":
+            sp["stages"] = restart_stages
+        else:
+            sp.update(M_min=max(1, M - 2), N_min=max(1, N // 4), stages=5)
+        specs.append(sp)
+    return specs
