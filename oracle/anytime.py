@@ -12,6 +12,9 @@ import numpy as np
 import oracle as O
 
 MAX_ATTEMPTS = 4096
+# biased heuristic half: the closest pairs scored by the surrogate per new
+# slot of a layer
+BIAS_CANDIDATES = 4
 
 
 def _bound(c, penalty):
@@ -62,10 +65,26 @@ def pair_order(prev, nxt):
     return np.argsort(d2.ravel(), kind="stable")
 
 
-def expand_samples(w, Q, M, N, c_best, seed, stage):
+def _free_candidates(order, prev, nxt, n_new, bias):
+    """Biased heuristic half: of the BIAS_CANDIDATES * n_new closest pairs,
+    the ones whose FP32 midpoint the surrogate scores at or below the
+    threshold (logit <= tau), in rank order."""
+    import oracle.surrogate as S
+    P, Bf, tau = bias
+    nv = nxt.shape[0]
+    k = min(order.size, BIAS_CANDIDATES * n_new)
+    ab = [divmod(int(order[r]), nv) for r in range(k)]
+    X = np.stack([(prev[a] + nxt[b]) * np.float32(0.5) for a, b in ab]) if ab else np.zeros((0, prev.shape[1]))
+    z = S.logits_of_states(P, Bf, X.astype(np.float64)) if ab else np.zeros(0)
+    return [int(order[r]) for r in range(k) if z[r] <= tau]
+
+
+def expand_samples(w, Q, M, N, c_best, seed, stage, bias=None):
     """Alg. 1 expand-samples.  Q is a list of M float32 arrays [n_m][d]
     (layers may be empty); returns the list grown to N samples per layer,
-    layers processed in increasing m."""
+    layers processed in increasing m.  ``bias`` = (params, fourier, tau):
+    the heuristic half takes, in rank order, only pairs whose midpoint the
+    surrogate predicts free (see _free_candidates)."""
     d = w["d"]
     q0 = O._f32(w["q0"]).reshape(1, d)
     goals = O._f32(w["goals"]).reshape(-1, d)
@@ -78,6 +97,8 @@ def expand_samples(w, Q, M, N, c_best, seed, stage):
         order = pair_order(prev, nxt) if heuristic_ok else None
         nv = nxt.shape[0]
         n_old = Q[m].shape[0]
+        if heuristic_ok and bias is not None:
+            order = np.asarray(_free_candidates(order, prev, nxt, N - n_old, bias), np.int64)
         new = []
         h = 0
         for n in range(n_old, N):
@@ -134,9 +155,10 @@ def growing_schedule(M_min, M_max, N_min, N_max, max_stages):
     return out
 
 
-def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed):
+def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None):
     """AO-GTMP (Alg. 1; Sec. IV-E): expand the samples under the current
-    cost bound, plan, keep the best, grow the budget."""
+    cost bound, plan, keep the best, grow the budget (``bias`` as in
+    expand_samples)."""
     d = w["d"]
     best = dict(cost=np.inf, stage=-1, idx=None)
     per_stage, stages = [], []
@@ -144,7 +166,7 @@ def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed):
     for s, (M, N, n_old) in enumerate(growing_schedule(M_min, M_max, N_min, N_max, max_stages)):
         if n_old == 0:
             Q = [np.zeros((0, d), np.float32) for _ in range(M)]
-        Q = expand_samples(w, Q, M, N, best["cost"], seed, s)
+        Q = expand_samples(w, Q, M, N, best["cost"], seed, s, bias)
         Qarr = np.stack(Q).astype(np.float32)
         r = _plan_on(w, Qarr)
         per_stage.append(r["path_cost"])

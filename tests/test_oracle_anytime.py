@@ -166,3 +166,32 @@ def test_growing_free_space_converges_to_straight_line():
     assert running[-1] >= direct
     assert (running[-1] - direct) < 0.5 * (running[0] - direct) + 1e-9
     assert (running[-1] - direct) / direct < 0.01
+
+
+def test_biased_heuristic_half_takes_closest_predicted_free_pairs():
+    """Surrogate bias with a selector network whose logit is the closed form
+    3 relu(x_0 / pi) - 1: with tau = 0 a midpoint counts as free iff
+    x_0 <= pi / 3.  The heuristic draws must be, in order, the candidate pairs
+    (the BIAS_CANDIDATES * n_new closest) whose midpoint passes that test."""
+    import oracle.surrogate as S
+    w = wl.make_workload("2d-small", 0, M=3, N=40)
+    d = 2
+    P = {k: np.zeros(s) for k, s in S.shapes().items()}
+    P["W1"][0, 0] = 1.0
+    for l in (2, 3, 4):
+        P[f"W{l}"][0, 0] = 1.0
+    P["w5"][0] = 3.0
+    P["b5"][0] = -1.0
+    _, Bf = wl.surrogate_init(0, d)
+    Q0 = oracle.sample_layers(3, 20, d, w["lo"], w["hi"], 9, 0)
+    c = np.float32(40.0)
+    Q = OA.expand_samples(w, list(Q0), 3, 40, c, 9, 4, bias=(P, Bf, 0.0))
+    prev, nxt = Q[0], Q0[2]
+    order = OA.pair_order(prev, nxt)[:OA.BIAS_CANDIDATES * 20]
+    mids = [(prev[a] + nxt[b]) * np.float32(0.5) for a, b in (divmod(int(p), nxt.shape[0]) for p in order)]
+    free = [x for x in mids if float(x[0]) / np.pi <= 1 / 3]
+    heur = [n for n in range(20, 40) if OA.coin_heuristic(9, 4, 1, n)]
+    assert 3 < len(heur) <= len(free)
+    for h, n in enumerate(heur):
+        np.testing.assert_array_equal(Q[1][n], free[h])
+    assert all(float(Q[1][n][0]) <= np.pi / 3 for n in heur)

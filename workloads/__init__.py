@@ -247,3 +247,30 @@ def batch_specs(n: int = BATCH["n"], seed: int = 0, N_choices=BATCH["N"], M_rang
             sp.update(M_min=max(1, M - 2), N_min=max(1, N // 4), stages=5)
         specs.append(sp)
     return specs
+
+
+# --------------------------------------------------------------------------- #
+# learned collision surrogate: initial parameters and Fourier frequencies
+# --------------------------------------------------------------------------- #
+SURROGATE = dict(width=256, depth=4, n_freq=16, in_pad=64, batch=8192, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 n_labels=2_000_000, recall=0.999)
+
+
+def surrogate_init(seed: int, d: int = 7):
+    """Seeded initial parameters of the surrogate MLP (He-normal hidden
+    weights, N(0, 1/width) output weights, zero biases) as float32 arrays
+    keyed W1, b1, ..., W4, b4, w5, b5, and the Fourier frequency matrix
+    B [n_freq][d] ~ N(0, 1)."""
+    S = SURROGATE
+    rng = _rng(0x5AE, seed)
+    W, D, F, I = S["width"], S["depth"], S["n_freq"], S["in_pad"]
+    P = {}
+    fan = I
+    for l in range(1, D + 1):
+        P[f"W{l}"] = (rng.standard_normal((W, fan)) * np.sqrt(2.0 / fan)).astype(np.float32)
+        P[f"b{l}"] = np.zeros(W, np.float32)
+        fan = W
+    P["w5"] = (rng.standard_normal(W) * np.sqrt(1.0 / W)).astype(np.float32)
+    P["b5"] = np.zeros(1, np.float32)
+    Bf = rng.standard_normal((F, d)).astype(np.float32)
+    return P, Bf
