@@ -229,6 +229,20 @@ gtmp_status gtmp_expand_samples(const gtmp_problem *prob, const float *q0, const
                                 int32_t n_old, float *Q_new, const float *c_best, uint64_t seed, uint64_t stage,
                                 void *workspace, size_t ws_bytes, void *stream);
 
+/* The same expansion with the heuristic half biased by the learned
+ * surrogate (gtmp_surrogate below): of the 4 (N - n_old) closest pairs of a
+ * layer (all pairs if fewer), only those whose FP32 midpoint gets a logit
+ * <= tau_logit are used, in rank order; heuristic slots beyond them take
+ * their uniform-half draw.  The uniform half is unchanged, so the coverage
+ * and convergence results, which use only that half, still hold (Sec. III
+ * Layered Sampling Model).  net->d must equal prob->d. */
+struct gtmp_surrogate;
+gtmp_status gtmp_expand_biased_workspace_size(const gtmp_problem *prob, size_t *bytes);
+gtmp_status gtmp_expand_samples_biased(const gtmp_problem *prob, const float *q0, const float *goals,
+                                       const float *Q_old, int32_t n_old, float *Q_new, const float *c_best,
+                                       uint64_t seed, uint64_t stage, const struct gtmp_surrogate *net,
+                                       float tau_logit, void *workspace, size_t ws_bytes, void *stream);
+
 /* Draws of the uniform half of the growing-budget sampler for slots
  * (m, 0..count-1) at `stage`.  Informed set of Sec. IV-E by the direct method
  * of Gammell et al. (2018), as an FP32 computation with a fixed operation
@@ -255,7 +269,9 @@ typedef struct gtmp_anytime_opts {
     int32_t M_min, M_max;       /* growing: layer schedule */
     int32_t N_min, N_max;       /* growing: samples per layer */
     int32_t use_graph;          /* restart: capture one stage as a hipGraph and replay it */
-    int32_t reserved;
+    float bias_tau;             /* growing: logit threshold of the surrogate bias */
+    const struct gtmp_surrogate *bias_net; /* growing: surrogate biasing the heuristic half
+                                              (gtmp_expand_samples_biased), NULL = off */
 } gtmp_anytime_opts;
 
 /* Bytes of device workspace gtmp_plan_anytime needs (sizes of prob for a
@@ -337,6 +353,82 @@ gtmp_status gtmp_batch_workspace_size(const gtmp_plan_desc *plans, int32_t n, co
 gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_batch_opts *opts, float *best_cost,
                             int32_t *best_idx, float *best_wp, int32_t *best_meta, float *stage_costs,
                             int32_t stage_stride, void *workspace, size_t ws_bytes, void *stream);
+
+
+/* ------------------------------------------------- a9 learned surrogate */
+/* A small ReLU MLP that predicts whether a configuration collides, used only
+ * to prune edges before the exact check and to bias the heuristic half of
+ * the sample mixture (the paper leaves that half to any history-dependent
+ * sampler, Sec. III Layered Sampling Model; it names learned functions among
+ * possible local planners, Sec. II).  Every edge it does not prune is still
+ * checked exactly.
+ *
+ * Network: features x = [q/pi, sin(2 pi B q/pi), cos(2 pi B q/pi)] with
+ * B = fourier [16][d], computed in FP64, rounded once to BF16 and
+ * zero-padded to 64; four hidden
+ * layers a_l = bf16(relu(bf16(W_l) a_{l-1} + b_l)) of width 256 with FP32
+ * accumulation; logit z = bf16(w5) . a_4 + b5 (FP32).  Loss: mean BCE with
+ * logits.  Backward with the same rounding points: dz = (sigmoid(z) - y)/n,
+ * dZ_l = bf16(dA_l * [a_l > 0]), dW_l = dZ_l^T a_{l-1}, db_l = sum_b dZ_l,
+ * dA_{l-1} = dZ_l bf16(W_l), all sums FP32.
+ *
+ * Parameters live in caller buffers: FP32 master values `params` and their
+ * BF16 copy `params_bf16` (round to nearest even), one flat array each, in
+ * the order W1 [256][64], b1 [256], W2 [256][256], b2, W3, b3, W4, b4,
+ * w5 [256], b5 [1]; gtmp_surrogate_layout gives the offsets. */
+#define GTMP_SUR_WIDTH 256
+#define GTMP_SUR_IN 64
+#define GTMP_SUR_FREQ 16
+
+typedef struct gtmp_surrogate {
+    int32_t d;               /* configuration dimension, 1..GTMP_MAX_DOF */
+    const float *fourier;    /* device [16][d] */
+    float *params;           /* device FP32 [total] */
+    uint16_t *params_bf16;   /* device BF16 bits [total] */
+} gtmp_surrogate;
+
+/* offsets[0..9] = W1 b1 W2 b2 W3 b3 W4 b4 w5 b5 (elements), offsets[10] = total. */
+gtmp_status gtmp_surrogate_layout(int32_t offsets[11]);
+
+/* params_bf16 <- bf16(params) (after the caller writes new FP32 values). */
+gtmp_status gtmp_surrogate_refresh_bf16(const gtmp_surrogate *net, void *stream);
+
+/* Workspace for gtmp_surrogate_grad with a batch of n rows, and for the
+ * inference calls processing up to n rows per chunk. */
+gtmp_status gtmp_surrogate_workspace_size(int64_t n, size_t *bytes);
+
+/* Logits of n configurations X [n][d] (device) -> logits [n] (device).
+ * Any n >= 0; processed in chunks that fit the workspace. */
+gtmp_status gtmp_surrogate_infer(const gtmp_surrogate *net, int64_t n, const float *X, float *logits,
+                                 void *workspace, size_t ws_bytes, void *stream);
+
+/* Loss and gradient of the mean BCE on one batch: X [n][d], y [n] (0/1,
+ * uint8), n a positive multiple of 256.  grad [total] FP32 in the parameter
+ * layout (overwritten); loss [1]; logits [n] or NULL.  Deterministic: every
+ * sum runs in a fixed order. */
+gtmp_status gtmp_surrogate_grad(const gtmp_surrogate *net, int32_t n, const float *X, const uint8_t *y, float *grad,
+                                float *loss, float *logits, void *workspace, size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba 2015) on params with moments m, v (FP32
+ * [total], caller-zeroed before step t = 1), then params_bf16 refreshed. */
+gtmp_status gtmp_surrogate_adam(const gtmp_surrogate *net, const float *grad, float *m, float *v, int32_t t, float lr,
+                                float beta1, float beta2, float eps, void *stream);
+
+/* Training states for labels: X [2n][d].  Rows 0..n-1 are uniform in the
+ * box (layer 0 of gtmp_sample_layers with M = 3, N = n, key (seed, stage));
+ * row n + j is the interior state h = 1 + j mod (H - 2) of the edge from
+ * layer-1 sample j to layer-2 sample j (t = h / (H - 1)), H = prob->H >= 3.
+ * Only prob->d, the box and H are used.  Labels come from gtmp_state_check. */
+gtmp_status gtmp_surrogate_label_states(const gtmp_problem *prob, uint64_t seed, uint64_t stage, int64_t n, float *X,
+                                        void *stream);
+
+/* Prune mask of every edge of a plan: prune[e] = 1 iff the logit at the
+ * edge's midpoint (u + v) / 2 (FP32) exceeds tau_logit.  Edge order as
+ * gtmp_edge_check_cost (C_s | C_h | C_l).  logits [E] or NULL.  Pass the
+ * mask to gtmp_edge_check_cost, which checks every unpruned edge exactly. */
+gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate *net, const float *q0,
+                                 const float *goals, const float *Q, float tau_logit, uint8_t *prune, float *logits,
+                                 void *workspace, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -65,7 +65,7 @@ def pair_order(prev, nxt):
     return np.argsort(d2.ravel(), kind="stable")
 
 
-def _free_candidates(order, prev, nxt, n_new, bias):
+def _free_candidates(order, prev, nxt, n_new, bias, trace=None):
     """Biased heuristic half: of the BIAS_CANDIDATES * n_new closest pairs,
     the ones whose FP32 midpoint the surrogate scores at or below the
     threshold (logit <= tau), in rank order."""
@@ -76,15 +76,18 @@ def _free_candidates(order, prev, nxt, n_new, bias):
     ab = [divmod(int(order[r]), nv) for r in range(k)]
     X = np.stack([(prev[a] + nxt[b]) * np.float32(0.5) for a, b in ab]) if ab else np.zeros((0, prev.shape[1]))
     z = S.logits_of_states(P, Bf, X.astype(np.float64)) if ab else np.zeros(0)
+    if trace is not None:
+        trace.append(z)
     return [int(order[r]) for r in range(k) if z[r] <= tau]
 
 
-def expand_samples(w, Q, M, N, c_best, seed, stage, bias=None):
+def expand_samples(w, Q, M, N, c_best, seed, stage, bias=None, trace=None):
     """Alg. 1 expand-samples.  Q is a list of M float32 arrays [n_m][d]
     (layers may be empty); returns the list grown to N samples per layer,
     layers processed in increasing m.  ``bias`` = (params, fourier, tau):
     the heuristic half takes, in rank order, only pairs whose midpoint the
-    surrogate predicts free (see _free_candidates)."""
+    surrogate predicts free (see _free_candidates); ``trace`` (a list)
+    collects the candidates' logits of each layer."""
     d = w["d"]
     q0 = O._f32(w["q0"]).reshape(1, d)
     goals = O._f32(w["goals"]).reshape(-1, d)
@@ -98,7 +101,7 @@ def expand_samples(w, Q, M, N, c_best, seed, stage, bias=None):
         nv = nxt.shape[0]
         n_old = Q[m].shape[0]
         if heuristic_ok and bias is not None:
-            order = np.asarray(_free_candidates(order, prev, nxt, N - n_old, bias), np.int64)
+            order = np.asarray(_free_candidates(order, prev, nxt, N - n_old, bias, trace), np.int64)
         new = []
         h = 0
         for n in range(n_old, N):
@@ -155,7 +158,7 @@ def growing_schedule(M_min, M_max, N_min, N_max, max_stages):
     return out
 
 
-def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None):
+def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None, trace=None):
     """AO-GTMP (Alg. 1; Sec. IV-E): expand the samples under the current
     cost bound, plan, keep the best, grow the budget (``bias`` as in
     expand_samples)."""
@@ -166,7 +169,7 @@ def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None):
     for s, (M, N, n_old) in enumerate(growing_schedule(M_min, M_max, N_min, N_max, max_stages)):
         if n_old == 0:
             Q = [np.zeros((0, d), np.float32) for _ in range(M)]
-        Q = expand_samples(w, Q, M, N, best["cost"], seed, s, bias)
+        Q = expand_samples(w, Q, M, N, best["cost"], seed, s, bias, trace)
         Qarr = np.stack(Q).astype(np.float32)
         r = _plan_on(w, Qarr)
         per_stage.append(r["path_cost"])

@@ -30,7 +30,7 @@ FLAGS = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
-SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip", "batch.hip"]
+SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip", "batch.hip", "surrogate.hip"]
 # the growing-budget sampler is defined as an FP32 computation with a fixed
 # operation order: no contraction into fused multiply-adds in that file
 EXTRA = {"anytime.hip": ["-ffp-contract=off"]}

@@ -13,6 +13,7 @@
 #include <tuple>
 
 #include "gtmp_launch.hpp"
+#include "surrogate.hpp"
 
 namespace gtmp {
 
@@ -183,18 +184,21 @@ __global__ void k_pair_keys(int d, int nu, const float *U, int nv, const float *
 
 // Fill the new slots of layer m: a heuristic slot of rank h takes the
 // midpoint of the h-th closest pair (a uniform draw when fewer pairs exist),
-// every other slot a draw of the uniform half.
+// every other slot a draw of the uniform half.  With the surrogate bias the
+// pair list is the compacted list of candidates predicted free and its length
+// is read from n_avail.
 __global__ void __launch_bounds__(256) k_expand_layer(int m, int n_old, int N, int d, BoxArgs B, uint32_t k0,
                                                       uint32_t k1, uint32_t stage, const Informed *Ip,
                                                       const int32_t *rank, const uint32_t *sorted_pairs,
-                                                      uint64_t n_pairs, int nv, const float *U, const float *Vv,
-                                                      float *Qm) {
+                                                      uint64_t n_pairs, const uint32_t *n_avail, int nv,
+                                                      const float *U, const float *Vv, float *Qm) {
     const int n = n_old + blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const Informed I = *Ip;
     float x[GTMP_MAX_DOF];
     const int h = rank[n];
-    if (h >= 0 && (uint64_t)h < n_pairs) {
+    const uint64_t avail = n_avail ? (uint64_t)*n_avail : n_pairs;
+    if (h >= 0 && (uint64_t)h < avail) {
         const uint32_t p = sorted_pairs[h];
         const uint32_t a = p / (uint32_t)nv, b = p % (uint32_t)nv;
         for (int i = 0; i < d; ++i) x[i] = (U[(size_t)a * d + i] + Vv[(size_t)b * d + i]) * 0.5f;
@@ -202,6 +206,46 @@ __global__ void __launch_bounds__(256) k_expand_layer(int m, int n_old, int N, i
         informed_draw(d, B.lo, B.wd, B.hi, I, k0, k1, stage, (uint32_t)m, (uint32_t)n, x);
     }
     for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
+}
+
+// Surrogate bias of the heuristic half: midpoints of the K closest pairs
+// (the same FP32 expression as the expansion), scored by the surrogate, and
+// the pairs whose logit is at most tau compacted in rank order.
+__global__ void __launch_bounds__(256) k_bias_midpoints(int d, uint64_t K, const uint32_t *sorted_pairs, int nv,
+                                                        const float *U, const float *Vv, float *X) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= K) return;
+    const uint32_t p = sorted_pairs[c];
+    const uint32_t a = p / (uint32_t)nv, b = p % (uint32_t)nv;
+    for (int i = 0; i < d; ++i) X[c * d + i] = (U[(size_t)a * d + i] + Vv[(size_t)b * d + i]) * 0.5f;
+}
+
+__global__ void __launch_bounds__(1024) k_bias_compact(uint64_t K, const float *z, float tau,
+                                                       const uint32_t *sorted_pairs, uint32_t *free_pairs,
+                                                       uint32_t *count) {
+    __shared__ uint32_t wsum[1024 / kWave];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < K; base += blockDim.x) {
+        const uint64_t c = base + threadIdx.x;
+        const bool keep = c < K && z[c] <= tau;
+        const uint64_t mask = ballot(keep);
+        const int wv = threadIdx.x / kWave;
+        if (lane_id() == 0) wsum[wv] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        uint32_t before = carry;
+        for (int k = 0; k < wv; ++k) before += wsum[k];
+        if (keep) free_pairs[before + rank_in(mask)] = sorted_pairs[c];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int k = 0; k < (int)(blockDim.x / kWave); ++k) tot += wsum[k];
+            carry += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = carry;
 }
 
 // Standalone informed draws (for tests of the sampler): X[n][d] for slots
@@ -238,7 +282,7 @@ static size_t sort_temp_bytes(uint64_t n) {
 
 static size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-ExpandPlan make_expand_plan(const gtmp_problem &p) {
+ExpandPlan make_expand_plan(const gtmp_problem &p, bool bias) {
     ExpandPlan e{};
     const uint64_t Nn = (uint64_t)p.N;
     const uint64_t G = (uint64_t)p.G;
@@ -253,14 +297,24 @@ ExpandPlan make_expand_plan(const gtmp_problem &p) {
     e.off_vals2 = o; o = up256(o + sizeof(uint32_t) * maxpairs);
     e.sort_bytes = sort_temp_bytes(maxpairs);
     e.off_sort = o; o = up256(o + e.sort_bytes);
+    if (bias) {
+        const uint64_t K = (uint64_t)kBiasCandidates * Nn;
+        e.bias_rows = K;
+        e.off_bX = o; o = up256(o + sizeof(float) * K * p.d);
+        e.off_bz = o; o = up256(o + sizeof(float) * K);
+        e.off_bfree = o; o = up256(o + sizeof(uint32_t) * K);
+        e.off_bcount = o; o = up256(o + 64);
+        e.bws_bytes = sur_workspace_bytes((int64_t)((K + 255) / 256 * 256));
+        e.off_bws = o; o = up256(o + e.bws_bytes);
+    }
     e.total = o;
     return e;
 }
 
 hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *goals, const float *Q_old, int n_old,
                          float *Q_new, const float *c_dev, uint64_t seed, uint64_t stage, void *workspace,
-                         hipStream_t s) {
-    const ExpandPlan e = make_expand_plan(p);
+                         hipStream_t s, const SurNet *bias, float bias_tau) {
+    const ExpandPlan e = make_expand_plan(p, bias != nullptr);
     char *ws = static_cast<char *>(workspace);
     Informed *I = reinterpret_cast<Informed *>(ws + e.off_informed);
     int32_t *rank = reinterpret_cast<int32_t *>(ws + e.off_rank);
@@ -300,8 +354,24 @@ hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *go
             if (err != hipSuccess) return err;
             sorted = vals2;
         }
+        const uint32_t *n_avail = nullptr;
+        if (heuristic_ok && bias) {
+            const uint64_t cap = (uint64_t)kBiasCandidates * (uint64_t)(N - n_old);
+            const uint64_t K = npairs < cap ? npairs : cap;
+            float *bX = reinterpret_cast<float *>(ws + e.off_bX);
+            float *bz = reinterpret_cast<float *>(ws + e.off_bz);
+            uint32_t *bfree = reinterpret_cast<uint32_t *>(ws + e.off_bfree);
+            uint32_t *bcount = reinterpret_cast<uint32_t *>(ws + e.off_bcount);
+            hipLaunchKernelGGL(k_bias_midpoints, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, d, K, sorted, nv, U,
+                               Vv, bX);
+            hipError_t err = launch_sur_infer(*bias, (int64_t)K, bX, bz, ws + e.off_bws, e.bws_bytes, s);
+            if (err != hipSuccess) return err;
+            hipLaunchKernelGGL(k_bias_compact, dim3(1), dim3(1024), 0, s, K, bz, bias_tau, sorted, bfree, bcount);
+            sorted = bfree;
+            n_avail = bcount;
+        }
         hipLaunchKernelGGL(k_expand_layer, dim3((unsigned)((N - n_old + 255) / 256)), dim3(256), 0, s, m, n_old, N, d,
-                           B, k0, k1, st, I, rank, sorted, heuristic_ok ? npairs : 0, nv, U, Vv,
+                           B, k0, k1, st, I, rank, sorted, heuristic_ok ? npairs : 0, n_avail, nv, U, Vv,
                            Q_new + (size_t)m * N * d);
     }
     return hipGetLastError();
@@ -395,7 +465,7 @@ AnytimePlan make_anytime_plan(const gtmp_problem &p, const gtmp_anytime_opts &o)
     const EdgePlan ep = make_edge_plan(big);
     a.off_edge = off; off = up256(off + ep.total);
     if (o.mode == GTMP_ANYTIME_GROWING) {
-        const ExpandPlan xp = make_expand_plan(big);
+        const ExpandPlan xp = make_expand_plan(big, o.bias_net != nullptr);
         a.off_expand = off; off = up256(off + xp.total);
     }
     a.total = off;
@@ -414,7 +484,8 @@ std::map<GraphKey, hipGraphExec_t> g_graphs;  // kept for the life of the proces
 
 hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const SceneParams &scene, int wdim,
                           const float *q0, const float *goals, uint64_t seed, const gtmp_anytime_opts &o,
-                          const gtmp_edge_opts &eo_in, const AnytimeOut &out, void *workspace, hipStream_t s) {
+                          const gtmp_edge_opts &eo_in, const AnytimeOut &out, void *workspace, hipStream_t s,
+                          const SurNet *bias) {
     const AnytimePlan a = make_anytime_plan(p, o);
     char *ws = static_cast<char *>(workspace);
     float *Q = reinterpret_cast<float *>(ws + a.off_Q);
@@ -515,7 +586,8 @@ hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const Sce
         gtmp_problem pp = p;
         pp.M = M;
         pp.N = N;
-        hipError_t e = launch_expand(pp, q0, goals, cur, n_old, nxt, out.best_cost, seed, (uint64_t)stage, xws, s);
+        hipError_t e = launch_expand(pp, q0, goals, cur, n_old, nxt, out.best_cost, seed, (uint64_t)stage, xws, s,
+                                     bias, o.bias_tau);
         if (e != hipSuccess) return e;
         float *t = cur; cur = nxt; nxt = t;
         e = one_plan(pp, cur, s);

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include "gtmp_launch.hpp"
+#include "surrogate.hpp"
 
 namespace {
 
@@ -257,6 +258,43 @@ gtmp_status gtmp_sample_informed(const gtmp_problem *prob, const float *q0, cons
                       "gtmp_sample_informed");
 }
 
+static gtmp_status check_net(const gtmp_surrogate *net, bool writable, gtmp::SurNet *out);
+
+gtmp_status gtmp_expand_biased_workspace_size(const gtmp_problem *prob, size_t *bytes) {
+    g_err[0] = 0;
+    gtmp_status st = gtmp_expand_workspace_size(prob, bytes);
+    if (st != GTMP_OK) return st;
+    *bytes = gtmp::make_expand_plan(*prob, true).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_expand_samples_biased(const gtmp_problem *prob, const float *q0, const float *goals,
+                                       const float *Q_old, int32_t n_old, float *Q_new, const float *c_best,
+                                       uint64_t seed, uint64_t stage, const gtmp_surrogate *net, float tau_logit,
+                                       void *workspace, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    size_t need = 0;
+    gtmp_status st = gtmp_expand_biased_workspace_size(prob, &need);
+    if (st != GTMP_OK) return st;
+    gtmp::SurNet sn{};
+    st = check_net(net, false, &sn);
+    if (st != GTMP_OK) return st;
+    if (net->d != prob->d) return fail(GTMP_EINVAL, "net d=%d differs from problem d=%d", net->d, prob->d);
+    if (n_old < 0 || n_old > prob->N) return fail(GTMP_EINVAL, "n_old=%d outside 0..N", n_old);
+    if (!q0 || !goals || !Q_new || !c_best || !workspace) return fail(GTMP_EINVAL, "NULL buffer");
+    if (n_old > 0 && !Q_old) return fail(GTMP_EINVAL, "Q_old is NULL with n_old > 0");
+    if (ws_bytes < need) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    if (n_old > 0) {
+        const char *a = reinterpret_cast<const char *>(Q_old), *b = reinterpret_cast<const char *>(Q_new);
+        const size_t la = sizeof(float) * (size_t)prob->M * n_old * prob->d, lb = sizeof(float) * (size_t)prob->M * prob->N * prob->d;
+        if (a < b + lb && b < a + la) return fail(GTMP_EINVAL, "Q_old and Q_new overlap");
+    }
+    return hip_status(gtmp::launch_expand(*prob, q0, goals, Q_old, n_old, Q_new, c_best, seed, stage, workspace,
+                                          (hipStream_t)stream, &sn, tau_logit),
+                      "gtmp_expand_samples_biased");
+}
+
 static gtmp_status check_anytime(const gtmp_problem *prob, const gtmp_anytime_opts *o) {
     if (!o) return fail(GTMP_EINVAL, "opts is NULL");
     if (o->max_stages < 1) return fail(GTMP_EINVAL, "max_stages=%d < 1", o->max_stages);
@@ -270,7 +308,15 @@ static gtmp_status check_anytime(const gtmp_problem *prob, const gtmp_anytime_op
     gtmp_status st = check_problem(&big);
     if (st != GTMP_OK) return st;
     size_t tmp = 0;
-    return gtmp_expand_workspace_size(&big, &tmp);
+    st = gtmp_expand_workspace_size(&big, &tmp);
+    if (st != GTMP_OK) return st;
+    if (o->bias_net) {
+        gtmp::SurNet sn{};
+        st = check_net(o->bias_net, false, &sn);
+        if (st != GTMP_OK) return st;
+        if (o->bias_net->d != prob->d) return fail(GTMP_EINVAL, "bias net d=%d differs from d=%d", o->bias_net->d, prob->d);
+    }
+    return GTMP_OK;
 }
 
 gtmp_status gtmp_anytime_workspace_size(const gtmp_problem *prob, const gtmp_anytime_opts *opts, size_t *bytes) {
@@ -305,8 +351,11 @@ gtmp_status gtmp_plan_anytime(const gtmp_problem *prob, const gtmp_robot *robot,
     if (edge_opts) eo = *edge_opts;
     if (eo.mode != GTMP_CHECK_FAST && eo.mode != GTMP_CHECK_FULL) return fail(GTMP_EINVAL, "unknown edge mode");
     gtmp::AnytimeOut out{best_cost, best_idx, best_wp, best_meta, stage_costs};
+    gtmp::SurNet sn{};
+    const bool biased = opts->mode == GTMP_ANYTIME_GROWING && opts->bias_net;
+    if (biased) (void)check_net(opts->bias_net, false, &sn);
     return hip_status(gtmp::launch_anytime(*prob, is_arm ? &arm : nullptr, sp, scene->wdim, q0, goals, seed, *opts, eo,
-                                           out, workspace, (hipStream_t)stream),
+                                           out, workspace, (hipStream_t)stream, biased ? &sn : nullptr),
                       "gtmp_plan_anytime");
 }
 
@@ -387,6 +436,137 @@ gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_b
     }
     return hip_status(gtmp::launch_batch(plans, arms.data(), n, *opts, L, out, workspace, (hipStream_t)stream),
                       "gtmp_plan_batch");
+}
+
+// ------------------------------------------------------------------ a9 surrogate
+static gtmp_status check_net(const gtmp_surrogate *net, bool writable, gtmp::SurNet *out) {
+    if (!net) return fail(GTMP_EINVAL, "net is NULL");
+    if (net->d < 1 || net->d > GTMP_MAX_DOF) return fail(GTMP_EINVAL, "net d=%d outside 1..%d", net->d, GTMP_MAX_DOF);
+    if (!net->fourier || !net->params || !net->params_bf16) return fail(GTMP_EINVAL, "net has a NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(net->params_bf16) & 15) != 0 || (reinterpret_cast<uintptr_t>(net->params) & 3) != 0)
+        return fail(GTMP_EINVAL, "params_bf16 must be 16-byte aligned");
+    (void)writable;
+    out->d = net->d;
+    out->fourier = net->fourier;
+    out->p32 = net->params;
+    out->p16 = net->params_bf16;
+    return GTMP_OK;
+}
+
+static gtmp_status check_ws(void *workspace, size_t ws_bytes, size_t need) {
+    if (!workspace) return fail(GTMP_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_surrogate_layout(int32_t offsets[11]) {
+    g_err[0] = 0;
+    if (!offsets) return fail(GTMP_EINVAL, "offsets is NULL");
+    const gtmp::SurLayout L = gtmp::sur_layout();
+    for (int l = 0; l < 4; ++l) {
+        offsets[2 * l] = L.W[l];
+        offsets[2 * l + 1] = L.b[l];
+    }
+    offsets[8] = L.w5;
+    offsets[9] = L.b5;
+    offsets[10] = L.total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_surrogate_refresh_bf16(const gtmp_surrogate *net, void *stream) {
+    g_err[0] = 0;
+    gtmp::SurNet sn{};
+    gtmp_status st = check_net(net, true, &sn);
+    if (st != GTMP_OK) return st;
+    return hip_status(gtmp::launch_sur_refresh(sn, (hipStream_t)stream), "gtmp_surrogate_refresh_bf16");
+}
+
+gtmp_status gtmp_surrogate_workspace_size(int64_t n, size_t *bytes) {
+    g_err[0] = 0;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    if (n < 1 || n > (1ll << 30)) return fail(GTMP_EINVAL, "n=%lld outside 1..2^30", (long long)n);
+    const int64_t rows = (n + 255) / 256 * 256;
+    *bytes = gtmp::sur_workspace_bytes(rows);
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_surrogate_infer(const gtmp_surrogate *net, int64_t n, const float *X, float *logits, void *workspace,
+                                 size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    gtmp::SurNet sn{};
+    gtmp_status st = check_net(net, false, &sn);
+    if (st != GTMP_OK) return st;
+    if (n < 0) return fail(GTMP_EINVAL, "n=%lld < 0", (long long)n);
+    if (n == 0) return GTMP_OK;
+    if (!X || !logits) return fail(GTMP_EINVAL, "NULL buffer");
+    st = check_ws(workspace, ws_bytes, gtmp::sur_workspace_bytes(256));
+    if (st != GTMP_OK) return st;
+    return hip_status(gtmp::launch_sur_infer(sn, n, X, logits, workspace, ws_bytes, (hipStream_t)stream),
+                      "gtmp_surrogate_infer");
+}
+
+gtmp_status gtmp_surrogate_grad(const gtmp_surrogate *net, int32_t n, const float *X, const uint8_t *y, float *grad,
+                                float *loss, float *logits, void *workspace, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    gtmp::SurNet sn{};
+    gtmp_status st = check_net(net, false, &sn);
+    if (st != GTMP_OK) return st;
+    if (n < 256 || n % 256 != 0) return fail(GTMP_EINVAL, "n=%d must be a positive multiple of 256", n);
+    if (!X || !y || !grad || !loss) return fail(GTMP_EINVAL, "NULL buffer");
+    st = check_ws(workspace, ws_bytes, gtmp::sur_workspace_bytes(n));
+    if (st != GTMP_OK) return st;
+    return hip_status(gtmp::launch_sur_grad(sn, n, X, y, grad, loss, logits, workspace, (hipStream_t)stream),
+                      "gtmp_surrogate_grad");
+}
+
+gtmp_status gtmp_surrogate_adam(const gtmp_surrogate *net, const float *grad, float *m, float *v, int32_t t, float lr,
+                                float beta1, float beta2, float eps, void *stream) {
+    g_err[0] = 0;
+    gtmp::SurNet sn{};
+    gtmp_status st = check_net(net, true, &sn);
+    if (st != GTMP_OK) return st;
+    if (!grad || !m || !v) return fail(GTMP_EINVAL, "NULL buffer");
+    if (t < 1) return fail(GTMP_EINVAL, "t=%d < 1", t);
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(GTMP_EINVAL, "bad Adam hyper-parameters");
+    return hip_status(gtmp::launch_sur_adam(sn, grad, m, v, t, lr, beta1, beta2, eps, (hipStream_t)stream),
+                      "gtmp_surrogate_adam");
+}
+
+gtmp_status gtmp_surrogate_label_states(const gtmp_problem *prob, uint64_t seed, uint64_t stage, int64_t n, float *X,
+                                        void *stream) {
+    g_err[0] = 0;
+    if (!prob) return fail(GTMP_EINVAL, "problem is NULL");
+    gtmp_problem q = *prob;  // only d, the box and H are used
+    q.M = 1;
+    q.N = 1;
+    q.G = 1;
+    gtmp_status st = check_problem(&q);
+    if (st != GTMP_OK) return st;
+    if (prob->H < 3) return fail(GTMP_EINVAL, "H=%d: label states need interior states (H >= 3)", prob->H);
+    if (n < 0 || n > (1ll << 31) - 1) return fail(GTMP_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
+    if (n > 0 && !X) return fail(GTMP_EINVAL, "X is NULL");
+    return hip_status(gtmp::launch_sur_label_states(*prob, seed, stage, n, X, (hipStream_t)stream),
+                      "gtmp_surrogate_label_states");
+}
+
+gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate *net, const float *q0,
+                                 const float *goals, const float *Q, float tau_logit, uint8_t *prune, float *logits,
+                                 void *workspace, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    gtmp::SurNet sn{};
+    st = check_net(net, false, &sn);
+    if (st != GTMP_OK) return st;
+    if (net->d != prob->d) return fail(GTMP_EINVAL, "net d=%d differs from problem d=%d", net->d, prob->d);
+    if (!q0 || !goals || !Q || !prune) return fail(GTMP_EINVAL, "NULL buffer");
+    st = check_ws(workspace, ws_bytes, gtmp::sur_workspace_bytes(256));
+    if (st != GTMP_OK) return st;
+    return hip_status(gtmp::launch_sur_prune(*prob, sn, q0, goals, Q, tau_logit, prune, logits, workspace, ws_bytes,
+                                             (hipStream_t)stream),
+                      "gtmp_surrogate_prune");
 }
 
 }  // extern "C"

@@ -64,12 +64,19 @@ hipError_t launch_extract(int M, int N, int G, int d, const int32_t *a_s, const 
 // ---- growing-budget sampler and anytime drivers (anytime.hip)
 struct ExpandPlan {
     uint64_t max_pairs;
-    size_t off_informed, off_rank, off_keys, off_keys2, off_vals, off_vals2, off_sort, sort_bytes, total;
+    size_t off_informed, off_rank, off_keys, off_keys2, off_vals, off_vals2, off_sort, sort_bytes;
+    // surrogate-biased heuristic half (when planned with bias)
+    uint64_t bias_rows;
+    size_t off_bX, off_bz, off_bfree, off_bcount, off_bws, bws_bytes;
+    size_t total;
 };
-ExpandPlan make_expand_plan(const gtmp_problem &p);
+// closest pairs scored by the surrogate per new slot of a layer
+constexpr int kBiasCandidates = 4;
+struct SurNet;
+ExpandPlan make_expand_plan(const gtmp_problem &p, bool bias = false);
 hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *goals, const float *Q_old, int n_old,
                          float *Q_new, const float *c_dev, uint64_t seed, uint64_t stage, void *workspace,
-                         hipStream_t s);
+                         hipStream_t s, const SurNet *bias = nullptr, float bias_tau = 0.f);
 hipError_t launch_informed_batch(const gtmp_problem &p, const float *q0, const float *goals, const float *c_dev,
                                  uint64_t seed, uint64_t stage, uint32_t m, int count, float *X, int32_t *attempts,
                                  void *workspace, hipStream_t s);
@@ -89,7 +96,8 @@ struct AnytimeOut {
 };
 hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const SceneParams &scene, int wdim,
                           const float *q0, const float *goals, uint64_t seed, const gtmp_anytime_opts &o,
-                          const gtmp_edge_opts &eo, const AnytimeOut &out, void *workspace, hipStream_t s);
+                          const gtmp_edge_opts &eo, const AnytimeOut &out, void *workspace, hipStream_t s,
+                          const SurNet *bias = nullptr);
 
 // ---- batched plans (batch.hip)
 struct StageShape {

@@ -1,0 +1,546 @@
+// surrogate.hip -- the learned collision surrogate: a ReLU MLP on Fourier
+// features of the configuration, with BF16 weights and activations and FP32
+// accumulation on the matrix cores (v_mfma_f32_32x32x16_bf16), its BCE loss,
+// backward pass and Adam update, and its two uses: edge pruning at the
+// midpoint probe and scoring of heuristic sample candidates.
+//
+// Every reduction runs in a fixed order (split-K partials summed in split
+// order, column sums over fixed row chunks, wave reductions by butterfly), so
+// results are reproducible run to run.
+#include "surrogate.hpp"
+
+namespace gtmp {
+
+// ------------------------------------------------------------------ layout
+SurLayout sur_layout() {
+    SurLayout L{};
+    int o = 0;
+    const int W = GTMP_SUR_WIDTH, I = GTMP_SUR_IN;
+    L.W[0] = o; o += W * I;
+    L.b[0] = o; o += W;
+    for (int l = 1; l < 4; ++l) {
+        L.W[l] = o; o += W * W;
+        L.b[l] = o; o += W;
+    }
+    L.w5 = o; o += W;
+    L.b5 = o; o += 1;
+    L.total = o;
+    return L;
+}
+
+// ------------------------------------------------------------------ BF16
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    // round to nearest, ties to even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ------------------------------------------------------------------ features
+// Round a double to the nearest BF16 value, ties to even, in one step (no
+// intermediate FP32 rounding): keep 7 of the 52 mantissa bits.  Finite
+// inputs inside the FP32 normal range or zero.
+__device__ __forceinline__ uint16_t d2bf(double x) {
+    uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t drop = 45;  // 52 - 7 mantissa bits
+    u += ((1ull << (drop - 1)) - 1) + ((u >> drop) & 1ull);
+    u &= ~((1ull << drop) - 1);
+    return (uint16_t)(__float_as_uint((float)__longlong_as_double((long long)u)) >> 16);
+}
+
+// One thread per configuration: [q/pi, sin(2 pi B q/pi), cos(2 pi B q/pi), 0...]
+// in FP64, rounded to BF16 once, 64 values.  FP64 keeps the phases (up to a
+// few tens of radians) accurate enough that the BF16 rounding of a feature
+// does not depend on how its value was computed.
+__global__ void __launch_bounds__(256) k_features(int d, int64_t n, const float *__restrict__ X,
+                                                  const float *__restrict__ Bf, uint16_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    constexpr double kPi = 3.14159265358979323846;
+    double qh[GTMP_MAX_DOF];
+    for (int j = 0; j < GTMP_MAX_DOF; ++j) qh[j] = j < d ? (double)X[i * d + j] / kPi : 0.0;
+    uint16_t v[GTMP_SUR_IN];
+#pragma unroll
+    for (int k = 0; k < GTMP_SUR_IN; ++k) v[k] = 0;
+    for (int j = 0; j < d; ++j) v[j] = d2bf(qh[j]);
+    for (int f = 0; f < GTMP_SUR_FREQ; ++f) {
+        double s = 0.0;
+        for (int j = 0; j < d; ++j) s += (double)Bf[f * d + j] * qh[j];
+        s *= 2.0 * kPi;
+        double sn, cs;
+        sincos(s, &sn, &cs);
+        v[d + f] = d2bf(sn);
+        v[d + GTMP_SUR_FREQ + f] = d2bf(cs);
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(out + i * GTMP_SUR_IN);
+#pragma unroll
+    for (int q = 0; q < GTMP_SUR_IN / 8; ++q) {
+        uint4 w;
+        w.x = v[8 * q + 0] | ((uint32_t)v[8 * q + 1] << 16);
+        w.y = v[8 * q + 2] | ((uint32_t)v[8 * q + 3] << 16);
+        w.z = v[8 * q + 4] | ((uint32_t)v[8 * q + 5] << 16);
+        w.w = v[8 * q + 6] | ((uint32_t)v[8 * q + 7] << 16);
+        dst[q] = w;
+    }
+}
+
+// ------------------------------------------------------------------ GEMM (NT)
+// C[m][n] = sum_k A[m][k] B[n][k], A and B BF16 row-major with K contiguous,
+// K a multiple of 32 (per split).  Block tile 128 x 128, four waves of
+// 64 x 64 (2 x 2 MFMA 32x32x16 tiles), K step 32 staged through LDS.
+enum GemmEpi { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_MASK_BF16 = 2 };
+
+constexpr int kBM = 128, kBN = 128, kBK = 32, kLdsPad = 8;
+constexpr int kLdsRow = kBK + kLdsPad;  // 40 BF16 = 80 bytes per row
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K_split, const uint16_t *__restrict__ A, int lda,
+                                                 const uint16_t *__restrict__ B, int ldb, void *__restrict__ Cout,
+                                                 int ldc, const float *__restrict__ bias,
+                                                 const uint16_t *__restrict__ mask, int ldm, size_t c_split_stride) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM * kLdsRow];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN * kLdsRow];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int k_begin = blockIdx.z * K_split;
+    // global -> LDS: thread loads 16 BF16 (2 x 16 B) of one row of A and of B
+    const int lr = tid >> 1, lk = (tid & 1) * 16;
+    const bool a_ok = m0 + lr < M, b_ok = n0 + lr < N;
+    const uint16_t *a_src = A + (size_t)(a_ok ? m0 + lr : 0) * lda + k_begin + lk;
+    const uint16_t *b_src = B + (size_t)(b_ok ? n0 + lr : 0) * ldb + k_begin + lk;
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+    for (int k0 = 0; k0 < K_split; k0 += kBK) {
+        const uint4 a0 = a_ok ? *reinterpret_cast<const uint4 *>(a_src + k0) : zero4;
+        const uint4 a1 = a_ok ? *reinterpret_cast<const uint4 *>(a_src + k0 + 8) : zero4;
+        const uint4 b0 = b_ok ? *reinterpret_cast<const uint4 *>(b_src + k0) : zero4;
+        const uint4 b1 = b_ok ? *reinterpret_cast<const uint4 *>(b_src + k0 + 8) : zero4;
+        __syncthreads();  // previous tile fully consumed
+        *reinterpret_cast<uint4 *>(&As[lr * kLdsRow + lk]) = a0;
+        *reinterpret_cast<uint4 *>(&As[lr * kLdsRow + lk + 8]) = a1;
+        *reinterpret_cast<uint4 *>(&Bs[lr * kLdsRow + lk]) = b0;
+        *reinterpret_cast<uint4 *>(&Bs[lr * kLdsRow + lk + 8]) = b1;
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kBK / 16; ++s) {
+            const int kk = 16 * s + 8 * (lane >> 5);
+            bf16x8 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm * 64 + 32 * i + (lane & 31);
+                af[i] = *reinterpret_cast<const bf16x8 *>(&As[r * kLdsRow + kk]);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int r = wn * 64 + 32 * j + (lane & 31);
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[r * kLdsRow + kk]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // epilogue: element v of tile (i, j) is row 8 (v/4) + 4 (lane/32) + v%4, column lane%32
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + wn * 64 + 32 * j + (lane & 31);
+            if (col >= N) continue;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = m0 + wm * 64 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                if (row >= M) continue;
+                const float x = acc[i][j][v];
+                if constexpr (EPI == EPI_F32) {
+                    float *C = static_cast<float *>(Cout) + blockIdx.z * c_split_stride;
+                    C[(size_t)row * ldc + col] = x;
+                } else if constexpr (EPI == EPI_BIAS_RELU_BF16) {
+                    const float z = x + bias[col];
+                    static_cast<uint16_t *>(Cout)[(size_t)row * ldc + col] = f2bf(z > 0.f ? z : 0.f);
+                } else {
+                    const bool on = bf2f(mask[(size_t)row * ldm + col]) > 0.f;
+                    static_cast<uint16_t *>(Cout)[(size_t)row * ldc + col] = f2bf(on ? x : 0.f);
+                }
+            }
+        }
+}
+
+// ------------------------------------------------------------------ small kernels
+// out [C][R] = in [R][C]^T, BF16, R and C multiples of 64.
+__global__ void __launch_bounds__(256) k_transpose_bf16(int R, int C, const uint16_t *__restrict__ in,
+                                                        uint16_t *__restrict__ out) {
+    __shared__ uint16_t t[64][65];
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) t[r][tx] = in[(size_t)(r0 + r) * C + c0 + tx];
+    __syncthreads();
+    for (int c = ty; c < 64; c += 4) out[(size_t)(c0 + c) * R + r0 + tx] = t[tx][c];
+}
+
+// Output layer, loss and its gradient: one wave per row.
+//   z = sum_k bf16(w5)[k] a4[k] + b5;  loss_b = max(z,0) - y z + log1p(exp(-|z|));
+//   dz = (sigmoid(z) - y) / n
+__global__ void __launch_bounds__(256) k_head(int64_t n, const uint16_t *__restrict__ A4,
+                                              const uint16_t *__restrict__ w5, const float *__restrict__ b5,
+                                              const uint8_t *__restrict__ y, float inv_n, float *__restrict__ logits,
+                                              float *__restrict__ loss_terms, float *__restrict__ dz) {
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (row >= n) return;
+    const int lane = lane_id();
+    const uint16_t *a = A4 + row * GTMP_SUR_WIDTH;
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < GTMP_SUR_WIDTH / kWave; ++q) {
+        const int k = lane * (GTMP_SUR_WIDTH / kWave) + q;
+        s = __builtin_fmaf(bf2f(w5[k]), bf2f(a[k]), s);
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane != 0) return;
+    const float z = s + b5[0];
+    if (logits) logits[row] = z;
+    if (y) {
+        const float yy = y[row] ? 1.f : 0.f;
+        const float az = __builtin_fabsf(z);
+        const float e = __expf(-az);
+        loss_terms[row] = (z > 0.f ? z : 0.f) - yy * z + log1pf(e);
+        const float sig = z >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
+        dz[row] = (sig - yy) * inv_n;
+    }
+}
+
+// dZ4 = bf16(dz[b] bf16(w5)[k] [a4 > 0])
+__global__ void __launch_bounds__(256) k_head_back(int64_t n, const float *__restrict__ dz,
+                                                   const uint16_t *__restrict__ w5, const uint16_t *__restrict__ A4,
+                                                   uint16_t *__restrict__ dZ) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * GTMP_SUR_WIDTH) return;
+    const int64_t b = i / GTMP_SUR_WIDTH;
+    const int k = (int)(i % GTMP_SUR_WIDTH);
+    const float g = dz[b] * bf2f(w5[k]);
+    dZ[i] = f2bf(bf2f(A4[i]) > 0.f ? g : 0.f);
+}
+
+// Column sums over fixed row chunks: part[p][c] = sum_{r in chunk p} scale[r] X[r][c]
+template <typename T>
+__device__ __forceinline__ float load_val(const T *p);
+template <>
+__device__ __forceinline__ float load_val<uint16_t>(const uint16_t *p) { return bf2f(*p); }
+template <>
+__device__ __forceinline__ float load_val<float>(const float *p) { return *p; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_colsum_part(int64_t rows, int cols, int rows_per_part, const T *__restrict__ X,
+                                                     const float *__restrict__ scale, float *__restrict__ part) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_part;
+    const int64_t r1 = r0 + rows_per_part < rows ? r0 + rows_per_part : rows;
+    float s = 0.f;
+    for (int64_t r = r0; r < r1; ++r) {
+        const float x = load_val<T>(X + r * cols + c);
+        s = scale ? __builtin_fmaf(scale[r], x, s) : s + x;
+    }
+    part[(size_t)blockIdx.y * cols + c] = s;
+}
+
+// out[i] = sum_p part[p][i] in p order
+__global__ void __launch_bounds__(256) k_sum_parts(int parts, int64_t len, const float *__restrict__ part,
+                                                   float *__restrict__ out, float scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int p = 0; p < parts; ++p) s += part[(size_t)p * len + i];
+    out[i] = s * scale;
+}
+
+__global__ void __launch_bounds__(256) k_adam(int total, float *__restrict__ P, uint16_t *__restrict__ P16,
+                                              const float *__restrict__ g, float *__restrict__ m,
+                                              float *__restrict__ v, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float p = P[i] - lr * (mi * c1) / (__builtin_sqrtf(vi * c2) + eps);
+    P[i] = p;
+    P16[i] = f2bf(p);
+}
+
+__global__ void __launch_bounds__(256) k_to_bf16(int total, const float *__restrict__ P, uint16_t *__restrict__ P16) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < total) P16[i] = f2bf(P[i]);
+}
+
+// Training states: rows [0, n) uniform (layer 0), rows [n, 2n) interior
+// lerp states of the edge (layer-1 sample j, layer-2 sample j).
+__global__ void __launch_bounds__(256) k_label_states(int d, int64_t n, int H, uint32_t k0, uint32_t k1,
+                                                      uint32_t stage, SurBox B, float *__restrict__ X) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * n) return;
+    const int nblk = (d + 3) >> 2;
+    auto sample = [&](uint32_t m, uint32_t s, float *x) {
+        for (int blk = 0; blk < nblk; ++blk) {
+            const uint4 w = philox4x32_10(make_uint4(s, m, stage, (uint32_t)blk), k0, k1);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+            for (int q = 0; q < 4; ++q) {
+                const int j = blk * 4 + q;
+                if (j < d) x[j] = __builtin_fmaf(unit_from_word(ws[q]), B.wd[j], B.lo[j]);
+            }
+        }
+    };
+    float x[GTMP_MAX_DOF];
+    if (i < n) {
+        sample(0u, (uint32_t)i, x);
+    } else {
+        const int64_t j = i - n;
+        float u[GTMP_MAX_DOF], v[GTMP_MAX_DOF];
+        sample(1u, (uint32_t)j, u);
+        sample(2u, (uint32_t)j, v);
+        const int h = 1 + (int)(j % (H - 2));
+        const float t = (float)h / (float)(H - 1);
+        for (int q = 0; q < d; ++q) x[q] = __builtin_fmaf(t, v[q] - u[q], u[q]);
+    }
+    for (int q = 0; q < d; ++q) X[i * d + q] = x[q];
+}
+
+// Midpoints (u + v) * 0.5 of edges [e0, e0 + count) in edge order C_s | C_h | C_l.
+__global__ void __launch_bounds__(256) k_edge_midpoints(int d, int M, int N, int G, int64_t e0, int64_t count,
+                                                        const float *__restrict__ q0, const float *__restrict__ goals,
+                                                        const float *__restrict__ Q, float *__restrict__ X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int64_t e = e0 + t;
+    const int64_t NN = (int64_t)N * N;
+    const int64_t n_h = (int64_t)(M - 1) * NN;
+    const float *u, *v;
+    if (e < N) {
+        u = q0;
+        v = Q + e * d;
+    } else if (e < N + n_h) {
+        const int64_t r = e - N;
+        const int64_t m = r / NN, uv = r % NN;
+        u = Q + (m * N + uv / N) * d;
+        v = Q + ((m + 1) * N + uv % N) * d;
+    } else {
+        const int64_t r = e - N - n_h;
+        u = Q + ((int64_t)(M - 1) * N + r / G) * d;
+        v = goals + (r % G) * d;
+    }
+    for (int q = 0; q < d; ++q) X[t * d + q] = (u[q] + v[q]) * 0.5f;
+}
+
+__global__ void __launch_bounds__(256) k_threshold(int64_t count, const float *__restrict__ z, float tau,
+                                                   uint8_t *__restrict__ out, float *__restrict__ z_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    out[i] = z[i] > tau ? 1 : 0;
+    if (z_out) z_out[i] = z[i];
+}
+
+// ------------------------------------------------------------------ host side
+static unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
+
+template <int EPI>
+static void gemm(int M, int N, int K, int splits, const uint16_t *A, int lda, const uint16_t *B, int ldb, void *C,
+                 int ldc, const float *bias, const uint16_t *mask, int ldm, hipStream_t s) {
+    const dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM), (unsigned)splits);
+    hipLaunchKernelGGL(k_gemm_nt<EPI>, grid, dim3(256), 0, s, M, N, K / splits, A, lda, B, ldb, C, ldc, bias, mask,
+                       ldm, (size_t)M * ldc);
+}
+
+// Workspace carve-up for n rows.
+struct SurWs {
+    uint16_t *X0, *A[4], *dZa, *dZb, *T1, *T2, *WT;
+    float *part, *loss_terms, *dz, *logit_tmp, *Xf;
+    size_t total;
+};
+static size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr int kSplitsMax = 32;      // split-K partials of the weight gradients
+constexpr int kColParts = 64;       // row chunks of the column sums
+
+static SurWs carve(int64_t n, void *base) {
+    SurWs w{};
+    char *p = static_cast<char *>(base);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char *q = p ? p + o : nullptr; o = up256(o + bytes); return q; };
+    const size_t W = GTMP_SUR_WIDTH;
+    w.X0 = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * GTMP_SUR_IN));
+    for (int l = 0; l < 4; ++l) w.A[l] = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * W));
+    w.dZa = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * W));
+    w.dZb = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * W));
+    w.T1 = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * W));
+    w.T2 = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * W));
+    w.WT = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * W * W));
+    const size_t part_floats = std::max((size_t)kSplitsMax * W * W, (size_t)kColParts * W);
+    w.part = reinterpret_cast<float *>(take(sizeof(float) * part_floats));
+    w.loss_terms = reinterpret_cast<float *>(take(sizeof(float) * n));
+    w.dz = reinterpret_cast<float *>(take(sizeof(float) * n));
+    w.logit_tmp = reinterpret_cast<float *>(take(sizeof(float) * n));
+    w.Xf = reinterpret_cast<float *>(take(sizeof(float) * n * GTMP_MAX_DOF));
+    w.total = o;
+    return w;
+}
+
+size_t sur_workspace_bytes(int64_t n) { return carve(n, nullptr).total; }
+
+int64_t sur_rows_for(size_t bytes) {
+    // largest multiple of 256 rows whose carve-up fits
+    int64_t lo = 0, hi = 1 << 24;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (sur_workspace_bytes(mid * 256) <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo * 256;
+}
+
+// forward of rows [0, n) of X (FP32 [n][d]) into logits; activations kept in ws
+static void forward(const SurNet &net, int64_t n, const float *X, const SurWs &w, float *logits, const uint8_t *y,
+                    float inv_n, hipStream_t s) {
+    const SurLayout L = sur_layout();
+    hipLaunchKernelGGL(k_features, dim3(blocks_for(n)), dim3(256), 0, s, net.d, n, X, net.fourier, w.X0);
+    const uint16_t *in = w.X0;
+    int K = GTMP_SUR_IN;
+    for (int l = 0; l < 4; ++l) {
+        gemm<EPI_BIAS_RELU_BF16>((int)n, GTMP_SUR_WIDTH, K, 1, in, K, net.p16 + L.W[l], K, w.A[l], GTMP_SUR_WIDTH,
+                                 net.p32 + L.b[l], nullptr, 0, s);
+        in = w.A[l];
+        K = GTMP_SUR_WIDTH;
+    }
+    hipLaunchKernelGGL(k_head, dim3(blocks_for(n, 4)), dim3(256), 0, s, n, w.A[3], net.p16 + L.w5, net.p32 + L.b5, y,
+                       inv_n, logits, w.loss_terms, w.dz);
+}
+
+hipError_t launch_sur_infer(const SurNet &net, int64_t n, const float *X, float *logits, void *ws, size_t ws_bytes,
+                            hipStream_t s) {
+    const int64_t cap = sur_rows_for(ws_bytes);
+    if (cap <= 0) return hipErrorInvalidValue;
+    const SurWs w = carve(cap, ws);
+    for (int64_t r = 0; r < n; r += cap) {
+        const int64_t c = n - r < cap ? n - r : cap;
+        forward(net, c, X + r * net.d, w, logits + r, nullptr, 0.f, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_grad(const SurNet &net, int n, const float *X, const uint8_t *y, float *grad, float *loss,
+                           float *logits, void *ws, hipStream_t s) {
+    const SurLayout L = sur_layout();
+    const SurWs w = carve(n, ws);
+    const int W = GTMP_SUR_WIDTH;
+    forward(net, n, X, w, logits ? logits : w.logit_tmp, y, 1.f / (float)n, s);
+    // loss = mean of the per-row terms (fixed-order sums)
+    {
+        const int rpp = (n + kColParts - 1) / kColParts;
+        hipLaunchKernelGGL(k_colsum_part<float>, dim3(1, kColParts), dim3(256), 0, s, (int64_t)n, 1, rpp,
+                           w.loss_terms, (const float *)nullptr, w.part);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, kColParts, (int64_t)1, w.part, loss,
+                           1.f / (float)n);
+    }
+    // output layer: dW5 = sum_b dz a4, db5 = sum_b dz
+    const int rpp = (n + kColParts - 1) / kColParts;
+    hipLaunchKernelGGL(k_colsum_part<uint16_t>, dim3(1, kColParts), dim3(256), 0, s, (int64_t)n, W, rpp, w.A[3],
+                       w.dz, w.part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, kColParts, (int64_t)W, w.part, grad + L.w5, 1.f);
+    hipLaunchKernelGGL(k_colsum_part<float>, dim3(1, kColParts), dim3(256), 0, s, (int64_t)n, 1, rpp, w.dz,
+                       (const float *)nullptr, w.part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, kColParts, (int64_t)1, w.part, grad + L.b5, 1.f);
+    // dZ4
+    uint16_t *dZ = w.dZa, *dZn = w.dZb;
+    hipLaunchKernelGGL(k_head_back, dim3(blocks_for((int64_t)n * W)), dim3(256), 0, s, (int64_t)n, w.dz,
+                       net.p16 + L.w5, w.A[3], dZ);
+    int splits = 1;
+    while (splits < kSplitsMax && n / (splits * 2) >= 256 && (n % (splits * 2 * kBK)) == 0) splits *= 2;
+    for (int l = 3; l >= 0; --l) {
+        const int K_in = l == 0 ? GTMP_SUR_IN : W;
+        const uint16_t *A_prev = l == 0 ? w.X0 : w.A[l - 1];
+        // dW_l = dZ^T A_prev: transposes put the batch dimension last
+        hipLaunchKernelGGL(k_transpose_bf16, dim3(W / 64, n / 64), dim3(256), 0, s, n, W, dZ, w.T1);
+        hipLaunchKernelGGL(k_transpose_bf16, dim3(K_in / 64, n / 64), dim3(256), 0, s, n, K_in, A_prev, w.T2);
+        gemm<EPI_F32>(W, K_in, n, splits, w.T1, n, w.T2, n, w.part, K_in, nullptr, nullptr, 0, s);
+        hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for((int64_t)W * K_in)), dim3(256), 0, s, splits,
+                           (int64_t)W * K_in, w.part, grad + L.W[l], 1.f);
+        // db_l = column sums of dZ (after the split-K partials are consumed)
+        hipLaunchKernelGGL(k_colsum_part<uint16_t>, dim3(1, kColParts), dim3(256), 0, s, (int64_t)n, W, rpp, dZ,
+                           (const float *)nullptr, w.part);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, kColParts, (int64_t)W, w.part, grad + L.b[l], 1.f);
+        if (l > 0) {
+            // dZ_{l-1} = bf16((dZ_l W_l) * [a_{l-1} > 0]): B operand W_l^T [K_in][W]
+            hipLaunchKernelGGL(k_transpose_bf16, dim3(K_in / 64, W / 64), dim3(256), 0, s, W, K_in,
+                               net.p16 + L.W[l], w.WT);
+            gemm<EPI_MASK_BF16>(n, K_in, W, 1, dZ, W, w.WT, W, dZn, K_in, nullptr, A_prev, K_in, s);
+            std::swap(dZ, dZn);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_adam(const SurNet &net, const float *grad, float *m, float *v, int t, float lr, float b1,
+                           float b2, float eps, hipStream_t s) {
+    const int total = sur_layout().total;
+    const double c1 = 1.0 / (1.0 - std::pow((double)b1, (double)t));
+    const double c2 = 1.0 / (1.0 - std::pow((double)b2, (double)t));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(total)), dim3(256), 0, s, total, net.p32, net.p16, grad, m, v, lr, b1,
+                       b2, eps, (float)c1, (float)c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_refresh(const SurNet &net, hipStream_t s) {
+    const int total = sur_layout().total;
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(total)), dim3(256), 0, s, total, net.p32, net.p16);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_label_states(const gtmp_problem &p, uint64_t seed, uint64_t stage, int64_t n, float *X,
+                                   hipStream_t s) {
+    SurBox B{};
+    for (int j = 0; j < p.d; ++j) {
+        B.lo[j] = p.lo[j];
+        B.wd[j] = p.hi[j] - p.lo[j];
+    }
+    if (n > 0)
+        hipLaunchKernelGGL(k_label_states, dim3(blocks_for(2 * n)), dim3(256), 0, s, p.d, n, p.H,
+                           (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)stage, B, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_prune(const gtmp_problem &p, const SurNet &net, const float *q0, const float *goals,
+                            const float *Q, float tau, uint8_t *prune, float *logits, void *ws, size_t ws_bytes,
+                            hipStream_t s) {
+    const int64_t E = (int64_t)p.N + (int64_t)(p.M - 1) * p.N * p.N + (int64_t)p.N * p.G;
+    const int64_t cap = sur_rows_for(ws_bytes);
+    if (cap <= 0) return hipErrorInvalidValue;
+    const SurWs w = carve(cap, ws);
+    for (int64_t e0 = 0; e0 < E; e0 += cap) {
+        const int64_t c = E - e0 < cap ? E - e0 : cap;
+        hipLaunchKernelGGL(k_edge_midpoints, dim3(blocks_for(c)), dim3(256), 0, s, p.d, p.M, p.N, p.G, e0, c, q0, goals,
+                           Q, w.Xf);
+        forward(net, c, w.Xf, w, w.logit_tmp, nullptr, 0.f, s);
+        hipLaunchKernelGGL(k_threshold, dim3(blocks_for(c)), dim3(256), 0, s, c, w.logit_tmp, tau, prune + e0,
+                           logits ? logits + e0 : nullptr);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gtmp

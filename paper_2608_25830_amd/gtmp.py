@@ -82,7 +82,8 @@ _lib.gtmp_extract_path.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _
 
 class gtmp_anytime_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_stages", C.c_int32), ("M_min", C.c_int32), ("M_max", C.c_int32),
-                ("N_min", C.c_int32), ("N_max", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("N_min", C.c_int32), ("N_max", C.c_int32), ("use_graph", C.c_int32), ("bias_tau", C.c_float),
+                ("bias_net", C.c_void_p)]
 
 
 GTMP_ANYTIME_RESTART, GTMP_ANYTIME_GROWING = 0, 1
@@ -107,6 +108,9 @@ _lib.gtmp_plan_batch.argtypes = [C.POINTER(gtmp_plan_desc), C.c_int32, C.POINTER
 _lib.gtmp_expand_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(C.c_size_t)]
 _lib.gtmp_expand_samples.argtypes = [C.POINTER(gtmp_problem), _vp, _vp, _vp, C.c_int32, _vp, _vp, C.c_uint64,
                                      C.c_uint64, _vp, C.c_size_t, _vp]
+_lib.gtmp_expand_biased_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(C.c_size_t)]
+_lib.gtmp_expand_samples_biased.argtypes = [C.POINTER(gtmp_problem), _vp, _vp, _vp, C.c_int32, _vp, _vp, C.c_uint64,
+                                            C.c_uint64, _vp, C.c_float, _vp, C.c_size_t, _vp]
 _lib.gtmp_sample_informed.argtypes = [C.POINTER(gtmp_problem), _vp, _vp, _vp, C.c_uint64, C.c_uint64, C.c_int32,
                                       C.c_int32, _vp, _vp, _vp, _vp]
 _lib.gtmp_anytime_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_anytime_opts),
@@ -115,10 +119,29 @@ _lib.gtmp_plan_anytime.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot
                                    C.c_uint64, C.POINTER(gtmp_anytime_opts), _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
                                    C.POINTER(gtmp_edge_opts), _vp]
 
+class gtmp_surrogate(C.Structure):
+    _fields_ = [("d", C.c_int32), ("fourier", C.c_void_p), ("params", C.c_void_p), ("params_bf16", C.c_void_p)]
+
+
+_lib.gtmp_surrogate_layout.argtypes = [C.POINTER(C.c_int32)]
+_lib.gtmp_surrogate_refresh_bf16.argtypes = [C.POINTER(gtmp_surrogate), _vp]
+_lib.gtmp_surrogate_workspace_size.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+_lib.gtmp_surrogate_infer.argtypes = [C.POINTER(gtmp_surrogate), C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]
+_lib.gtmp_surrogate_grad.argtypes = [C.POINTER(gtmp_surrogate), C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
+                                     _vp]
+_lib.gtmp_surrogate_adam.argtypes = [C.POINTER(gtmp_surrogate), _vp, _vp, _vp, C.c_int32, C.c_float, C.c_float,
+                                     C.c_float, C.c_float, _vp]
+_lib.gtmp_surrogate_label_states.argtypes = [C.POINTER(gtmp_problem), C.c_uint64, C.c_uint64, C.c_int64, _vp, _vp]
+_lib.gtmp_surrogate_prune.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_surrogate), _vp, _vp, _vp, C.c_float,
+                                      _vp, _vp, _vp, C.c_size_t, _vp]
+
 EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample_layers",
            "gtmp_edge_check_workspace_size", "gtmp_edge_check_cost", "gtmp_state_check", "gtmp_minplus_sweep",
            "gtmp_extract_path", "gtmp_expand_workspace_size", "gtmp_expand_samples", "gtmp_sample_informed",
-           "gtmp_anytime_workspace_size", "gtmp_plan_anytime", "gtmp_batch_workspace_size", "gtmp_plan_batch"]
+           "gtmp_anytime_workspace_size", "gtmp_plan_anytime", "gtmp_batch_workspace_size", "gtmp_plan_batch",
+           "gtmp_surrogate_layout", "gtmp_surrogate_refresh_bf16", "gtmp_surrogate_workspace_size",
+           "gtmp_surrogate_infer", "gtmp_surrogate_grad", "gtmp_surrogate_adam", "gtmp_surrogate_label_states",
+           "gtmp_surrogate_prune", "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased"]
 
 
 def _check(st):
@@ -379,7 +402,7 @@ class AnytimePlanner:
     the workload's M, N; growing: the schedule's maxima)."""
 
     def __init__(self, w, mode, max_stages, M_min=None, M_max=None, N_min=None, N_max=None, use_graph=False,
-                 device="cuda"):
+                 device="cuda", bias=None, bias_tau=0.0):
         self.w = w
         d, M, N, G, H = (int(w[k]) for k in ("d", "M", "N", "G", "H"))
         self.d = d
@@ -389,6 +412,10 @@ class AnytimePlanner:
         self.opts.M_min, self.opts.M_max = M_min or M, M_max or M
         self.opts.N_min, self.opts.N_max = N_min or N, N_max or N
         self.opts.use_graph = int(use_graph)
+        self.bias = bias  # a Surrogate (kept alive for the struct's pointer)
+        if bias is not None:
+            self.opts.bias_net = C.cast(C.pointer(bias.c), C.c_void_p).value
+            self.opts.bias_tau = float(bias_tau)
         self.prob = make_problem(d, M, N, G, H, w["lo"], w["hi"], w["penalty"])
         if w["kind"] == "point2d":
             self.robot = make_point_robot()
@@ -506,3 +533,145 @@ class BatchPlanner:
     def plan_idx(self, i):
         M = self.descs[i].problem.M
         return self.best_idx[self.idx_off[i]:self.idx_off[i] + M + 1]
+
+
+# --------------------------------------------------------------------------- #
+# learned collision surrogate
+# --------------------------------------------------------------------------- #
+SUR_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4", "w5", "b5")
+
+
+def gtmp_surrogate_layout():
+    off = (C.c_int32 * 11)()
+    _check(_lib.gtmp_surrogate_layout(off))
+    return list(off)
+
+
+def gtmp_surrogate_workspace_size(n) -> int:
+    b = C.c_size_t()
+    _check(_lib.gtmp_surrogate_workspace_size(int(n), C.byref(b)))
+    return b.value
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+class Surrogate:
+    """Device parameters, Adam moments and workspace of the collision
+    surrogate.  ``P`` maps W1, b1, ..., w5, b5 to arrays (float32) and ``Bf``
+    is the Fourier matrix [16][d]."""
+
+    def __init__(self, P, Bf, batch=8192, device="cuda"):
+        self.d = int(np.asarray(Bf).shape[1])
+        self.offsets = gtmp_surrogate_layout()
+        self.total = self.offsets[10]
+        flat = np.zeros(self.total, np.float32)
+        for i, k in enumerate(SUR_NAMES):
+            a = np.asarray(P[k], np.float32).reshape(-1)
+            end = self.offsets[i + 1] if i + 1 < 10 else self.total
+            assert a.size == end - self.offsets[i], k
+            flat[self.offsets[i]:end] = a
+        self.params = torch.from_numpy(flat).to(device)
+        self.params_bf16 = torch.zeros(self.total, device=device, dtype=torch.int16)
+        self.fourier = torch.from_numpy(np.asarray(Bf, np.float32).copy()).to(device)
+        self.c = gtmp_surrogate(self.d, self.fourier.data_ptr(), self.params.data_ptr(), self.params_bf16.data_ptr())
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad_buf = torch.zeros_like(self.params)
+        self.loss_buf = torch.zeros(1, device=device)
+        self.t = 0
+        self.batch = int(batch)
+        self.workspace = _aligned_workspace(gtmp_surrogate_workspace_size(self.batch), device)
+        _check(_lib.gtmp_surrogate_refresh_bf16(C.byref(self.c), _stream(None)))
+
+    def to_dict(self):
+        flat = self.params.cpu().numpy()
+        out = {}
+        for i, k in enumerate(SUR_NAMES):
+            end = self.offsets[i + 1] if i + 1 < 10 else self.total
+            out[k] = flat[self.offsets[i]:end].copy()
+        shapes = {"W1": (256, 64), "W2": (256, 256), "W3": (256, 256), "W4": (256, 256)}
+        for k, sh in shapes.items():
+            out[k] = out[k].reshape(sh)
+        return out
+
+    def infer(self, X, logits=None, stream=None):
+        n = X.shape[0]
+        if logits is None:
+            logits = torch.empty(n, device=X.device)
+        _check(_lib.gtmp_surrogate_infer(C.byref(self.c), n, _p(X), _p(logits), _p(self.workspace),
+                                         _nbytes(self.workspace), _stream(stream)))
+        return logits
+
+    def grad(self, X, y, logits=None, stream=None):
+        """Loss and gradient of one batch (rows a multiple of 256): fills
+        ``grad_buf`` and ``loss_buf``."""
+        n = X.shape[0]
+        _check(_lib.gtmp_surrogate_grad(C.byref(self.c), n, _p(X), _p(y), _p(self.grad_buf), _p(self.loss_buf),
+                                        _p(logits), _p(self.workspace), _nbytes(self.workspace), _stream(stream)))
+        return self.loss_buf
+
+    def adam(self, grad=None, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self.t += 1
+        g = self.grad_buf if grad is None else grad
+        _check(_lib.gtmp_surrogate_adam(C.byref(self.c), _p(g), _p(self.m), _p(self.v), self.t, lr, b1, b2, eps,
+                                        _stream(stream)))
+
+    def train(self, X, y, epochs=1, lr=1e-3, seed=0, stream=None):
+        """Mini-batch Adam over (X, y) for some epochs; batches of
+        ``self.batch`` rows in a seeded order (the tail that does not fill a
+        batch is left out of that epoch).  Returns the per-step losses (device)."""
+        n = X.shape[0]
+        steps = n // self.batch
+        g = torch.Generator(device="cpu")
+        g.manual_seed(seed)
+        losses = torch.empty(epochs * steps, device=X.device)
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=g).to(X.device)
+            Xs, ys = X[perm].contiguous(), y[perm].contiguous()
+            for s in range(steps):
+                lo = s * self.batch
+                self.grad(Xs[lo:lo + self.batch], ys[lo:lo + self.batch], stream=stream)
+                self.adam(lr=lr, stream=stream)
+                losses[ep * steps + s].copy_(self.loss_buf[0])
+        return losses
+
+    def prune(self, prob, q0, goals, Q, tau_logit, prune, logits=None, stream=None):
+        _check(_lib.gtmp_surrogate_prune(C.byref(prob), C.byref(self.c), _p(q0), _p(goals), _p(Q), float(tau_logit),
+                                         _p(prune), _p(logits), _p(self.workspace), _nbytes(self.workspace),
+                                         _stream(stream)))
+
+
+def gtmp_surrogate_label_states(prob, seed, stage, n, X, stream=None):
+    _check(_lib.gtmp_surrogate_label_states(C.byref(prob), seed, stage, int(n), _p(X), _stream(stream)))
+
+
+def make_labels(w, n, seed, stage, device="cuda"):
+    """2n training states of workload ``w`` and their exact collision labels
+    (uniform half, then interior states of random edges)."""
+    d = int(w["d"])
+    prob = make_problem(d, 3, max(int(n), 1), 1, int(w["H"]), w["lo"], w["hi"], w["penalty"])
+    X = torch.empty((2 * n, d), device=device)
+    gtmp_surrogate_label_states(prob, seed, stage, n, X)
+    if w["kind"] == "point2d":
+        robot, scene = make_point_robot(), Scene(2, w["circles"], w["boxes"], device)
+    else:
+        robot = make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"])
+        scene = Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+    y = torch.empty(2 * n, device=device, dtype=torch.uint8)
+    gtmp_state_check(robot, scene, d, X, None, y)
+    return X, y
+
+
+def gtmp_expand_biased_workspace_size(prob) -> int:
+    n = C.c_size_t()
+    _check(_lib.gtmp_expand_biased_workspace_size(C.byref(prob), C.byref(n)))
+    return n.value
+
+
+def gtmp_expand_samples_biased(prob, q0, goals, Q_old, n_old, Q_new, c_best, seed, stage, net: "Surrogate", tau_logit,
+                               workspace, stream=None):
+    return _check(_lib.gtmp_expand_samples_biased(C.byref(prob), _p(q0), _p(goals), _p(Q_old), int(n_old), _p(Q_new),
+                                                  _p(c_best), seed, stage, C.byref(net.c), float(tau_logit),
+                                                  _p(workspace), _nbytes(workspace), _stream(stream)))
