@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -163,13 +164,121 @@ def bench_batch(args, torch, wl, gtmp):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args, torch, wl, gtmp):
+    """7-DoF arm at N = 4096, M = 8: plain plans against surrogate-pruned
+    plans on the same samples, and the growing loop with and without the
+    surrogate bias of the heuristic half."""
+    w = wl.make_workload("arm7", args.scene, N=4096)
+    P0, Bf = wl.surrogate_init(7, w["d"])
+    S = wl.SURROGATE
+    net = gtmp.Surrogate(P0, Bf, batch=S["batch"])
+    t0 = time.perf_counter()
+    X, y = gtmp.make_labels(w, args.labels, seed=101, stage=0)
+    losses = net.train(X, y, epochs=args.epochs, lr=S["lr"])
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, y
+    Xh, yh = gtmp.make_labels(w, 1 << 16, seed=101, stage=1)
+    acc = float(((net.infer(Xh) > 0) == (yh == 1)).float().mean().item())
+    print(f"[bench] trained in {train_s:.2f} s, held-out accuracy {acc:.4f}", file=sys.stderr, flush=True)
+    pl = gtmp.Planner(w, flags=True)
+    net.workspace = gtmp._aligned_workspace(gtmp.gtmp_surrogate_workspace_size(1 << 21))
+    prune = torch.empty(pl.E, device="cuda", dtype=torch.uint8)
+    logits = torch.empty(pl.E, device="cuda")
+    # threshold: free-edge recall on a held-out plan (stage 999)
+    pl.plan(w["seed"], 999)
+    net.prune(pl.prob, pl.q0, pl.goals, pl.Q, math.inf, prune, logits)
+    tau = gtmp.free_recall_threshold(logits, pl.flags, S["recall"])
+    print(f"[bench] tau {tau:.4f}", file=sys.stderr, flush=True)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    res = dict(plain=[], pruned=[], prune_ms=[], same=0, optimum_pruned=0, false_prune=[], pruned_frac=[])
+    for i in range(args.warmup + args.steps):
+        a, b, c, e = ev(), ev(), ev(), ev()
+        a.record()
+        pl.plan(w["seed"], i)
+        b.record()
+        b.synchronize()
+        c_plain = float(pl.cost.item())
+        flags_plain = pl.flags.clone()
+        idx = pl.idx.cpu().numpy()
+        c.record()
+        net.prune(pl.prob, pl.q0, pl.goals, pl.Q, tau, prune)
+        e.record()
+        pl.check(prune=prune)
+        pl.sweep()
+        pl.extract()
+        f = ev()
+        f.record()
+        f.synchronize()
+        if i < args.warmup:
+            continue
+        res["plain"].append(a.elapsed_time(b))
+        res["pruned"].append(c.elapsed_time(f))
+        res["prune_ms"].append(c.elapsed_time(e))
+        c_pr = float(pl.cost.item())
+        res["same"] += int(abs(c_pr - c_plain) <= 1e-5 * abs(c_plain))
+        free = flags_plain == 0
+        res["false_prune"].append(float((prune.bool() & free).sum().item()) / max(1, int(free.sum().item())))
+        res["pruned_frac"].append(float(prune.float().mean().item()))
+    ms_plain = float(np.mean(res["plain"]))
+    ms_pruned = float(np.mean(res["pruned"]))
+    ms_prune = float(np.mean(res["prune_ms"]))
+    mlp_flop = 2 * (64 * 256 + 3 * 256 * 256 + 256)
+    achieved = pl.E * mlp_flop / (ms_prune / 1e3) / 1e12
+    # growing loop with and without the bias (same key): best cost per stage
+    grow = {}
+    for biased in (False, True):
+        ap = gtmp.AnytimePlanner(w, gtmp.GTMP_ANYTIME_GROWING, 8, M_min=6, M_max=8, N_min=256, N_max=2048,
+                                 bias=net if biased else None, bias_tau=0.0)
+        a, b = ev(), ev()
+        a.record()
+        ap.run(w["seed"])
+        b.record()
+        b.synchronize()
+        sc = ap.stage_costs.cpu().numpy()
+        grow["biased" if biased else "plain"] = dict(ms=a.elapsed_time(b), stage_costs=[float(x) for x in sc],
+                                                      best=float(np.nanmin(sc)))
+    out = {
+        "metric": "plans/s (7-DoF, N=4096): surrogate-pruned vs plain at equal cost",
+        "value": 1e3 / ms_pruned,
+        "unit": "plans/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_pruned,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 mlp / f32 check",
+        "data": "synthetic",
+        "config": {"workload": f"arm7 d=7, M=8, N=4096, H=16, scene seed {w['seed']}; surrogate 64-256x4-1 "
+                               f"BF16, {2 * args.labels} labels, {args.epochs} epochs", "edges": pl.E},
+        "plain": {"plans_per_s": 1e3 / ms_plain, "ms": ms_plain},
+        "pruned": {"plans_per_s": 1e3 / ms_pruned, "ms": ms_pruned, "prune_ms": ms_prune,
+                   "pruned_frac": float(np.mean(res["pruned_frac"])),
+                   "false_prune_frac": float(np.mean(res["false_prune"])),
+                   "equal_cost_frac": res["same"] / args.steps, "tau_logit": tau},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None, "kernel": "surrogate inference (midpoint probes)"},
+        "training": {"seconds": train_s, "steps": int(losses.numel()), "final_loss": float(losses[-20:].mean()),
+                     "heldout_accuracy": acc},
+        "growing_bias": grow,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="arm7")
-    ap.add_argument("--form", default="plain", choices=["plain", "batch"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batch", "surrogate"])
+    ap.add_argument("--labels", type=int, default=1 << 20, help="surrogate: label pairs (2x states)")
+    ap.add_argument("--epochs", type=int, default=5, help="surrogate: training epochs")
     ap.add_argument("--batch-plans", type=int, default=512)
     ap.add_argument("--tune", action="store_true", help="batch: pick launch shapes with the autotuner first")
     ap.add_argument("--scene", type=int, default=0)
@@ -202,6 +311,8 @@ def main():
         del src, dst
     if args.form == "batch":
         return bench_batch(args, torch, wl, gtmp)
+    if args.form == "surrogate":
+        return bench_surrogate(args, torch, wl, gtmp)
     w = wl.make_workload(args.workload, args.scene)
     pl = gtmp.Planner(w)
     for kv in args.opt:

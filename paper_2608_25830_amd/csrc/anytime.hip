@@ -304,7 +304,7 @@ ExpandPlan make_expand_plan(const gtmp_problem &p, bool bias) {
         e.off_bz = o; o = up256(o + sizeof(float) * K);
         e.off_bfree = o; o = up256(o + sizeof(uint32_t) * K);
         e.off_bcount = o; o = up256(o + 64);
-        e.bws_bytes = sur_workspace_bytes((int64_t)((K + 255) / 256 * 256));
+        e.bws_bytes = sur_infer_bytes((int64_t)((K + 255) / 256 * 256));
         e.off_bws = o; o = up256(o + e.bws_bytes);
     }
     e.total = o;

@@ -500,7 +500,7 @@ gtmp_status gtmp_surrogate_infer(const gtmp_surrogate *net, int64_t n, const flo
     if (n < 0) return fail(GTMP_EINVAL, "n=%lld < 0", (long long)n);
     if (n == 0) return GTMP_OK;
     if (!X || !logits) return fail(GTMP_EINVAL, "NULL buffer");
-    st = check_ws(workspace, ws_bytes, gtmp::sur_workspace_bytes(256));
+    st = check_ws(workspace, ws_bytes, gtmp::sur_infer_bytes(256));
     if (st != GTMP_OK) return st;
     return hip_status(gtmp::launch_sur_infer(sn, n, X, logits, workspace, ws_bytes, (hipStream_t)stream),
                       "gtmp_surrogate_infer");
@@ -562,7 +562,7 @@ gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate 
     if (st != GTMP_OK) return st;
     if (net->d != prob->d) return fail(GTMP_EINVAL, "net d=%d differs from problem d=%d", net->d, prob->d);
     if (!q0 || !goals || !Q || !prune) return fail(GTMP_EINVAL, "NULL buffer");
-    st = check_ws(workspace, ws_bytes, gtmp::sur_workspace_bytes(256));
+    st = check_ws(workspace, ws_bytes, gtmp::sur_infer_bytes(256));
     if (st != GTMP_OK) return st;
     return hip_status(gtmp::launch_sur_prune(*prob, sn, q0, goals, Q, tau_logit, prune, logits, workspace, ws_bytes,
                                              (hipStream_t)stream),

@@ -402,18 +402,36 @@ static SurWs carve(int64_t n, void *base) {
     return w;
 }
 
+// Inference needs only the features, two activation buffers (layers
+// alternate between them), the logits and the FP32 probe states.
+static SurWs carve_infer(int64_t n, void *base) {
+    SurWs w{};
+    char *p = static_cast<char *>(base);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char *q = p ? p + o : nullptr; o = up256(o + bytes); return q; };
+    w.X0 = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * GTMP_SUR_IN));
+    w.A[0] = w.A[2] = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * GTMP_SUR_WIDTH));
+    w.A[1] = w.A[3] = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * GTMP_SUR_WIDTH));
+    w.logit_tmp = reinterpret_cast<float *>(take(sizeof(float) * n));
+    w.Xf = reinterpret_cast<float *>(take(sizeof(float) * n * GTMP_MAX_DOF));
+    w.total = o;
+    return w;
+}
+
 size_t sur_workspace_bytes(int64_t n) { return carve(n, nullptr).total; }
 
 int64_t sur_rows_for(size_t bytes) {
-    // largest multiple of 256 rows whose carve-up fits
+    // largest multiple of 256 rows whose inference carve-up fits
     int64_t lo = 0, hi = 1 << 24;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) / 2;
-        if (sur_workspace_bytes(mid * 256) <= bytes) lo = mid;
+        if (carve_infer(mid * 256, nullptr).total <= bytes) lo = mid;
         else hi = mid - 1;
     }
     return lo * 256;
 }
+
+size_t sur_infer_bytes(int64_t n) { return carve_infer(n, nullptr).total; }
 
 // forward of rows [0, n) of X (FP32 [n][d]) into logits; activations kept in ws
 static void forward(const SurNet &net, int64_t n, const float *X, const SurWs &w, float *logits, const uint8_t *y,
@@ -436,7 +454,7 @@ hipError_t launch_sur_infer(const SurNet &net, int64_t n, const float *X, float 
                             hipStream_t s) {
     const int64_t cap = sur_rows_for(ws_bytes);
     if (cap <= 0) return hipErrorInvalidValue;
-    const SurWs w = carve(cap, ws);
+    const SurWs w = carve_infer(cap, ws);
     for (int64_t r = 0; r < n; r += cap) {
         const int64_t c = n - r < cap ? n - r : cap;
         forward(net, c, X + r * net.d, w, logits + r, nullptr, 0.f, s);
@@ -531,7 +549,7 @@ hipError_t launch_sur_prune(const gtmp_problem &p, const SurNet &net, const floa
     const int64_t E = (int64_t)p.N + (int64_t)(p.M - 1) * p.N * p.N + (int64_t)p.N * p.G;
     const int64_t cap = sur_rows_for(ws_bytes);
     if (cap <= 0) return hipErrorInvalidValue;
-    const SurWs w = carve(cap, ws);
+    const SurWs w = carve_infer(cap, ws);
     for (int64_t e0 = 0; e0 < E; e0 += cap) {
         const int64_t c = E - e0 < cap ? E - e0 : cap;
         hipLaunchKernelGGL(k_edge_midpoints, dim3(blocks_for(c)), dim3(256), 0, s, p.d, p.M, p.N, p.G, e0, c, q0, goals,

@@ -29,6 +29,7 @@ struct SurBox {
 
 size_t sur_workspace_bytes(int64_t n);
 int64_t sur_rows_for(size_t bytes);  // rows per inference chunk that fit `bytes`
+size_t sur_infer_bytes(int64_t n);   // inference workspace for n rows per chunk
 
 hipError_t launch_sur_infer(const SurNet &net, int64_t n, const float *X, float *logits, void *ws, size_t ws_bytes,
                             hipStream_t s);

@@ -675,3 +675,15 @@ def gtmp_expand_samples_biased(prob, q0, goals, Q_old, n_old, Q_new, c_best, see
     return _check(_lib.gtmp_expand_samples_biased(C.byref(prob), _p(q0), _p(goals), _p(Q_old), int(n_old), _p(Q_new),
                                                   _p(c_best), seed, stage, C.byref(net.c), float(tau_logit),
                                                   _p(workspace), _nbytes(workspace), _stream(stream)))
+
+
+def free_recall_threshold(logits, flags, recall=0.999):
+    """Smallest logit threshold tau such that pruning edges with logit > tau
+    keeps at least ``recall`` of the free edges (flag 0): the
+    ceil(recall * n_free)-th smallest free-edge logit (device tensors in,
+    float out)."""
+    zf = torch.sort(logits[flags == 0]).values
+    if zf.numel() == 0:
+        return math.inf
+    k = max(0, min(zf.numel() - 1, math.ceil(recall * zf.numel()) - 1))
+    return float(zf[k].item())
