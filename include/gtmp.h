@@ -133,10 +133,10 @@ gtmp_status gtmp_sample_layers(const gtmp_problem *prob, uint64_t seed, uint64_t
 typedef struct gtmp_edge_opts {
     int32_t mode;             /* GTMP_CHECK_FAST (default) or GTMP_CHECK_FULL */
     int32_t states_per_iter;  /* point robots: interior states per lane and iteration (1,2,4,8; 0 = auto) */
-    int32_t block;            /* threads per block for the interior kernel (64..1024, multiple of 64; 0 = auto) */
+    int32_t block;            /* ignored: the interior kernels run 256-thread blocks */
     int32_t blocks_per_cu;    /* resident blocks per CU for the persistent interior kernel (0 = auto) */
     int32_t sphere_chunks;    /* arms: the collision spheres of a state are tested in this many
-                                 chunks (1 or 2; 0 = auto = 2) */
+                                 chunks (1, 2 or 4; 0 = auto = 4) */
     int32_t reserved[3];
     unsigned long long *stats; /* optional device [4]: states evaluated, edges checked in the
                                   interior pass, reserved, reserved.  Added to. */

@@ -11,7 +11,7 @@ file keyed by robot group and problem-size bucket.
 Knobs:
   point robots: states_per_iter in {1, 2, 4, 8}  (interior states per lane
                 and iteration), blocks_per_cu in {0 (occupancy), 1, 2, 4, 8}
-  arms:         sphere_chunks in {1, 2}  (robot spheres tested in one pass at
+  arms:         sphere_chunks in {1, 2, 4}  (robot spheres tested in one pass at
                 128+ VGPRs, or two passes at fewer registers and higher
                 occupancy), blocks_per_cu in {0, 1, 2, 3, 4}
 """
@@ -55,7 +55,7 @@ def candidates(w) -> list[dict]:
     if w["kind"] == "point2d":
         return [dict(states_per_iter=s, sphere_chunks=0, blocks_per_cu=b) for s in (1, 2, 4, 8)
                 for b in (0, 1, 2, 4, 8)]
-    return [dict(states_per_iter=0, sphere_chunks=c, blocks_per_cu=b) for c in (1, 2) for b in (0, 1, 2, 3, 4)]
+    return [dict(states_per_iter=0, sphere_chunks=c, blocks_per_cu=b) for c in (1, 2, 4) for b in (0, 1, 2, 3, 4)]
 
 
 def apply(opts, cand: dict):

@@ -79,6 +79,14 @@ gtmp_status to_arm(const gtmp_robot *r, int d, gtmp::ArmParams *out) {
         a.r[k] = r->sph_r[k];
         if (r->sph_r[k] != a.r0) a.uniform_r = 0;
     }
+    // |sphere centre| <= max(1, max |t|) * sum of link lengths: frame origins
+    // are at most the summed lengths sqrt(a^2 + d^2) from the base
+    double len = 0.0, tmax = 1.0;
+    for (int j = 0; j < r->n_joints; ++j)
+        len += sqrt((double)r->dh[j][0] * r->dh[j][0] + (double)r->dh[j][2] * r->dh[j][2]);
+    for (int k = 0; k < r->n_spheres; ++k) tmax = fmax(tmax, fabs((double)r->sph_t[k]));
+    a.reach = (float)(len * tmax * (1.0 + 1e-6));
+    a.sph_tol = 0.f;
     *out = a;
     return GTMP_OK;
 }
@@ -168,7 +176,8 @@ gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *rob
     if (o.mode != GTMP_CHECK_FAST && o.mode != GTMP_CHECK_FULL) return fail(GTMP_EINVAL, "unknown mode %d", o.mode);
     if (o.states_per_iter < 0 || o.states_per_iter > 8) return fail(GTMP_EINVAL, "states_per_iter=%d", o.states_per_iter);
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 32) return fail(GTMP_EINVAL, "blocks_per_cu=%d", o.blocks_per_cu);
-    if (o.sphere_chunks < 0 || o.sphere_chunks > 2) return fail(GTMP_EINVAL, "sphere_chunks=%d", o.sphere_chunks);
+    if (o.sphere_chunks != 0 && o.sphere_chunks != 1 && o.sphere_chunks != 2 && o.sphere_chunks != 4)
+        return fail(GTMP_EINVAL, "sphere_chunks=%d (0, 1, 2 or 4)", o.sphere_chunks);
     gtmp::EdgeBuffers b{q0, goals, Q, C_s, C_h, C_l, minsd, flags, prune, workspace};
     return hip_status(gtmp::launch_edge_check(plan, is_arm ? &arm : nullptr, sp, scene->wdim, b, o, (hipStream_t)stream),
                       "gtmp_edge_check_cost");

@@ -77,6 +77,30 @@ __global__ void k_store_params(ArmParams R, ArmParams *dst) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = src[i];
 }
 
+// The robot table for the interior kernel plus the tolerance of the expanded
+// sphere test: tol = 2^-19 ((reach + max|c|)^2 + (max r_o + r0)^2) over the
+// sphere obstacles (one wave).
+__global__ void k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
+    float cmax = 0.f, rmax = 0.f;
+    for (int o = threadIdx.x; o < S.n_sph; o += blockDim.x) {
+        const float *c = S.sph + 4 * o;
+        cmax = __builtin_fmaxf(cmax, __builtin_sqrtf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]));
+        rmax = __builtin_fmaxf(rmax, __builtin_fabsf(c[3]));
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cmax = __builtin_fmaxf(cmax, __shfl_xor(cmax, off));
+        rmax = __builtin_fmaxf(rmax, __shfl_xor(rmax, off));
+    }
+    // rounding of the bound itself: inflate by 1e-3 relative
+    const float pc = (R.reach + cmax) * 1.001f, rr = (rmax + R.r0) * 1.001f;
+    R.sph_tol = 0x1p-19f * (pc * pc + rr * rr);
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&R);
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+    constexpr int n = sizeof(ArmParams) / 4;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = src[i];
+}
+
 __global__ void k_zero_u32(uint32_t *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -176,7 +200,8 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
 // set-up instructions more.
 
 template <class Model, bool UNIFORM_R, int NCH>
-__global__ void __launch_bounds__(256, NCH == 1 ? 3 : 4) k_interior(EdgeArgs A, const ArmParams *Rg, SceneParams S) {
+__global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interior(EdgeArgs A, const ArmParams *Rg,
+                                                                               SceneParams S) {
     constexpr int D = Model::D;
     constexpr int KP = Model::KP;
     constexpr bool ARM = Model::kArm;
@@ -263,19 +288,43 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : 4) k_interior(EdgeArgs A, 
             const auto &R = *Rp;
             const v32f o = arm_fk<D>(R, q);
             float pr[KC];
-            {
-                Probes<3, KC> P;
-                arm_spheres<KC, 0>(R, o, P);
+            if constexpr (UNIFORM_R) {
+                // sphere obstacles in the expanded form, re-evaluated in the
+                // difference form for the lanes whose result is within the
+                // rounding bound of zero; boxes in the difference form
+                const float tol = R.sph_tol;
 #pragma unroll
-                for (int k = 0; k < KC; ++k) pr[k] = UNIFORM_R ? 0.f : (k < R.n_spheres ? R.r[k] : 0.f);
-                gap = probes_min_gap<3, KC, UNIFORM_R>(P, pr, r0, S);
-            }
-            if constexpr (NCH > 1) {
-                Probes<3, KC> P;
-                arm_spheres<KC, KC>(R, o, P);
+                for (int k = 0; k < KC; ++k) pr[k] = 0.f;
 #pragma unroll
-                for (int k = 0; k < KC; ++k) pr[k] = UNIFORM_R ? 0.f : (KC + k < R.n_spheres ? R.r[KC + k] : 0.f);
-                gap = __builtin_fminf(gap, probes_min_gap<3, KC, UNIFORM_R>(P, pr, r0, S));
+                for (int ch = 0; ch < NCH; ++ch) {
+                    Probes<3, KC> P;
+                    if (ch == 0) arm_spheres<KC, 0>(R, o, P);
+                    else if (ch == 1) arm_spheres<KC, (NCH > 1 ? KC : 0)>(R, o, P);
+                    else if (ch == 2) arm_spheres<KC, (NCH > 2 ? 2 * KC : 0)>(R, o, P);
+                    else arm_spheres<KC, (NCH > 3 ? 3 * KC : 0)>(R, o, P);
+                    float gs = sph_min_gap_expanded<KC>(P, r0, S);
+                    const bool near = __builtin_fabsf(gs) <= tol;
+                    if (ballot(near) != 0) {
+                        const float ex = probes_min_gap<3, KC, true, true, false>(P, pr, r0, S);
+                        if (near) gs = ex;
+                    }
+                    const float gb = probes_min_gap<3, KC, true, false, true>(P, pr, r0, S);
+                    const float g = __builtin_fminf(gs, gb);
+                    gap = ch == 0 ? g : __builtin_fminf(gap, g);
+                }
+            } else {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    Probes<3, KC> P;
+                    if (ch == 0) arm_spheres<KC, 0>(R, o, P);
+                    else if (ch == 1) arm_spheres<KC, (NCH > 1 ? KC : 0)>(R, o, P);
+                    else if (ch == 2) arm_spheres<KC, (NCH > 2 ? 2 * KC : 0)>(R, o, P);
+                    else arm_spheres<KC, (NCH > 3 ? 3 * KC : 0)>(R, o, P);
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) pr[k] = ch * KC + k < R.n_spheres ? R.r[ch * KC + k] : 0.f;
+                    const float g = probes_min_gap<3, KC, false>(P, pr, r0, S);
+                    gap = ch == 0 ? g : __builtin_fminf(gap, g);
+                }
             }
         } else {
             Probes<W, KP> P;
@@ -478,7 +527,7 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
     hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
     hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
     ArmParams *Rg = reinterpret_cast<ArmParams *>(static_cast<char *>(b.workspace) + A.off_params);
-    hipLaunchKernelGGL(k_store_params, dim3(1), dim3(64), 0, s, R, Rg);
+    hipLaunchKernelGGL(k_store_params_tol, dim3(1), dim3(64), 0, s, R, Rg, S);
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
@@ -600,20 +649,22 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, A.counter, 1);
     if (arm) {
         const int kp = round_kp(R.n_spheres);
-        const int nch = o.sphere_chunks == 1 ? 1 : 2;
+        const int nch = o.sphere_chunks == 1 ? 1 : o.sphere_chunks == 4 ? 4 : 2;
         const void *kern = nullptr;
-        switch (kp * 4 + nch) {
-#define GTMP_KK(K, C) case K * 4 + C: kern = R.uniform_r ? (const void *)k_interior<ArmModel<K>, true, C> : (const void *)k_interior<ArmModel<K>, false, C>; break;
-            GTMP_KK(8, 1) GTMP_KK(16, 1) GTMP_KK(24, 1) GTMP_KK(32, 1) GTMP_KK(40, 1) GTMP_KK(48, 1) GTMP_KK(56, 1) GTMP_KK(64, 1)
-            GTMP_KK(8, 2) GTMP_KK(16, 2) GTMP_KK(24, 2) GTMP_KK(32, 2) GTMP_KK(40, 2) GTMP_KK(48, 2) GTMP_KK(56, 2) GTMP_KK(64, 2)
+        switch (kp * 8 + nch) {
+#define GTMP_KK(K, C) case K * 8 + C: kern = R.uniform_r ? (const void *)k_interior<ArmModel<K>, true, C> : (const void *)k_interior<ArmModel<K>, false, C>; break;
+#define GTMP_KK3(K) GTMP_KK(K, 1) GTMP_KK(K, 2) GTMP_KK(K, 4)
+            GTMP_KK3(8) GTMP_KK3(16) GTMP_KK3(24) GTMP_KK3(32) GTMP_KK3(40) GTMP_KK3(48) GTMP_KK3(56) GTMP_KK3(64)
+#undef GTMP_KK3
 #undef GTMP_KK
             default: return hipErrorInvalidValue;
         }
         const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
-        switch (kp * 4 + nch) {
-#define GTMP_LA(K, C) case K * 4 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag);
-            GTMP_LA(8, 1) GTMP_LA(16, 1) GTMP_LA(24, 1) GTMP_LA(32, 1) GTMP_LA(40, 1) GTMP_LA(48, 1) GTMP_LA(56, 1) GTMP_LA(64, 1)
-            GTMP_LA(8, 2) GTMP_LA(16, 2) GTMP_LA(24, 2) GTMP_LA(32, 2) GTMP_LA(40, 2) GTMP_LA(48, 2) GTMP_LA(56, 2) GTMP_LA(64, 2)
+        switch (kp * 8 + nch) {
+#define GTMP_LA(K, C) case K * 8 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag);
+#define GTMP_LA3(K) GTMP_LA(K, 1) GTMP_LA(K, 2) GTMP_LA(K, 4)
+            GTMP_LA3(8) GTMP_LA3(16) GTMP_LA3(24) GTMP_LA3(32) GTMP_LA3(40) GTMP_LA3(48) GTMP_LA3(56) GTMP_LA3(64)
+#undef GTMP_LA3
 #undef GTMP_LA
             default: return hipErrorInvalidValue;
         }

@@ -47,6 +47,8 @@ struct ArmParams {
     int link[GTMP_MAX_ROBOT_SPHERES];
     float t[GTMP_MAX_ROBOT_SPHERES];
     float r[GTMP_MAX_ROBOT_SPHERES];
+    float reach;    // bound on |sphere centre|: sum of the link lengths sqrt(a^2 + d^2), rounded up
+    float sph_tol;  // rounding bound of the expanded sphere test (set on the device per launch)
 };
 
 // Obstacles: raw device arrays of the scene, spheres [n][wdim+1], boxes
@@ -90,7 +92,8 @@ __device__ __forceinline__ float to_vgpr(float s) {
 // s_waitcnt immediate for gfx9: lgkmcnt(0), vmcnt and expcnt left at their maxima
 constexpr int kWaitLgkm0 = 0xC07F;
 
-template <int W, int KP, bool UNIFORM_R>
+// SPH / BOX select the obstacle kinds tested (both by default).
+template <int W, int KP, bool UNIFORM_R, bool SPH = true, bool BOX = true>
 __device__ __forceinline__ float probes_min_gap(const Probes<W, KP> &P, const float (&pr)[KP], float r0,
                                                 const SceneParams &S) {
     float m0 = __builtin_inff(), m1 = __builtin_inff();
@@ -99,7 +102,7 @@ __device__ __forceinline__ float probes_min_gap(const Probes<W, KP> &P, const fl
     // Scalar loads are software pipelined: the data of obstacle o + 1 is
     // requested before obstacle o is tested, so the scalar-cache latency hides
     // behind the vector work of the current obstacle.
-    if (S.n_sph > 0) {
+    if (SPH && S.n_sph > 0) {
         float c[W + 1];
 #pragma unroll
         for (int i = 0; i <= W; ++i) c[i] = sph[i];
@@ -139,7 +142,7 @@ __device__ __forceinline__ float probes_min_gap(const Probes<W, KP> &P, const fl
             for (int i = 0; i <= W; ++i) c[i] = cn[i];
         }
     }
-    if (S.n_box > 0) {
+    if (BOX && S.n_box > 0) {
         float b[2 * W];
 #pragma unroll
         for (int i = 0; i < 2 * W; ++i) b[i] = box[i];
@@ -174,6 +177,76 @@ __device__ __forceinline__ float probes_min_gap(const Probes<W, KP> &P, const fl
         }
     }
     return __builtin_fminf(m0, m1);
+}
+
+// Sphere obstacles only, in the expanded form
+//   |p - c|^2 - R^2 = |p|^2 + p.(-2c) + (|c|^2 - R^2),
+// for KC probes of the uniform radius r0: per (probe, obstacle) pair three
+// FMAs and half a three-way min (two obstacles per iteration, one running
+// minimum per probe); |p|^2 is added once per probe at the end.  Compared with
+// the difference form this loses accuracy by cancellation when |p| and |c| are
+// large against |p - c|.  With u = 2^-24 and B = (|p| + |c|)^2 + R^2 the
+// rounding error of this form is below 8.1 u B and that of the difference form
+// below 4 u B, so whenever the result exceeds tol = 32 u B_max in magnitude
+// both forms give the same sign; callers re-evaluate the difference form for
+// results within tol (B_max from a bound on |p| and the largest |c| and R).
+template <int KC>
+__device__ __forceinline__ float sph_min_gap_expanded(const Probes<3, KC> &P, float r0, const SceneParams &S) {
+    float acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = __builtin_inff();
+    const cfp sph = as_const(S.sph);
+    const int n = S.n_sph;
+    if (n > 0) {
+        float c[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            c[i] = sph[i];
+            c[4 + i] = sph[(n > 1 ? 4 : 0) + i];
+        }
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        for (int o = 0; o < n; o += 2) {
+            // the next pair (the last obstacle repeats when n is odd: a
+            // repeated minimum changes nothing)
+            const int o1 = o + 2 < n ? o + 2 : o;
+            const int o2 = o + 3 < n ? o + 3 : o1;
+            float cn[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                cn[i] = sph[o1 * 4 + i];
+                cn[4 + i] = sph[o2 * 4 + i];
+            }
+            __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the tests
+            float a[2][3], t[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float cx = c[4 * h], cy = c[4 * h + 1], cz = c[4 * h + 2];
+                const float R = c[4 * h + 3] + r0;
+                a[h][0] = -2.f * cx;
+                a[h][1] = -2.f * cy;
+                a[h][2] = -2.f * cz;
+                const float c2 = __builtin_fmaf(cz, cz, __builtin_fmaf(cy, cy, cx * cx));
+                t[h] = c2 - R * R;
+            }
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const float x = P.p[0][k], y = P.p[1][k], z = P.p[2][k];
+                const float v0 = __builtin_fmaf(x, a[0][0], __builtin_fmaf(y, a[0][1], __builtin_fmaf(z, a[0][2], t[0])));
+                const float v1 = __builtin_fmaf(x, a[1][0], __builtin_fmaf(y, a[1][1], __builtin_fmaf(z, a[1][2], t[1])));
+                acc[k] = __builtin_fminf(acc[k], __builtin_fminf(v0, v1));
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) c[i] = cn[i];
+        }
+    }
+    float gap = __builtin_inff();
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const float x = P.p[0][k], y = P.p[1][k], z = P.p[2][k];
+        const float s2 = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+        gap = __builtin_fminf(gap, s2 + acc[k]);
+    }
+    return gap;
 }
 
 // Exact signed distance of one workspace point to the obstacle set:
