@@ -383,8 +383,8 @@ gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_b
 typedef struct gtmp_surrogate {
     int32_t d;               /* configuration dimension, 1..GTMP_MAX_DOF */
     const float *fourier;    /* device [16][d] */
-    float *params;           /* device FP32 [total] */
-    uint16_t *params_bf16;   /* device BF16 bits [total] */
+    float *params;           /* device FP32 [total], 16-byte aligned */
+    uint16_t *params_bf16;   /* device BF16 bits [total], 16-byte aligned */
 } gtmp_surrogate;
 
 /* offsets[0..9] = W1 b1 W2 b2 W3 b3 W4 b4 w5 b5 (elements), offsets[10] = total. */

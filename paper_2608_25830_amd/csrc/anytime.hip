@@ -77,43 +77,57 @@ __device__ __forceinline__ uint32_t pick(const uint4 &w, int i) {
     return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
 }
 
-// One draw of the uniform half for slot (m, n).  Returns attempts used
-// (0 for an unbounded draw, -1 for the box fallback).
-__device__ int informed_draw(int d, const float *lo, const float *wd, const float *hi, const Informed &I,
-                             uint32_t k0, uint32_t k1, uint32_t stage, uint32_t m, uint32_t n, float *x) {
-    if (I.bounded) {
-        for (int a = 0; a < kMaxAttempts; ++a) {
-            float y[GTMP_MAX_DOF];
-            float s2 = 0.0f;
-            uint4 w0 = words(k0, k1, n, m, stage, 1u, (uint32_t)(2 * a));
-            uint4 w1 = words(k0, k1, n, m, stage, 1u, (uint32_t)(2 * a + 1));
-            for (int i = 0; i < d; ++i) {
-                const uint32_t wi = i < 4 ? pick(w0, i) : pick(w1, i - 4);
-                y[i] = (float)(wi >> 8) * (1.0f / 8388608.0f) - 1.0f;
-                s2 = s2 + y[i] * y[i];
-            }
-            if (!(s2 < 1.0f)) continue;
-            float z[GTMP_MAX_DOF];
-            for (int i = 0; i < d; ++i) z[i] = (i == 0 ? I.r1 : I.r2) * y[i];
-            bool inside = true;
-            float xx[GTMP_MAX_DOF];
-            for (int i = 0; i < d; ++i) {
-                float acc = 0.0f;
-                for (int j = 0; j < d; ++j) acc = acc + I.H[i * d + j] * z[j];
-                xx[i] = I.centre[i] + acc;
-                if (!(xx[i] >= lo[i] && xx[i] <= hi[i])) inside = false;
-            }
-            if (!inside) continue;
-            for (int i = 0; i < d; ++i) x[i] = xx[i];
-            return a + 1;
-        }
+// Attempt a of the uniform-half draw for slot (m, n): true iff accepted
+// (inside the unit ball, and the mapped point inside the box), the point in x.
+__device__ __forceinline__ bool informed_attempt(int d, const float *lo, const float *hi, const Informed &I,
+                                                 uint32_t k0, uint32_t k1, uint32_t stage, uint32_t m, uint32_t n,
+                                                 int a, float *x) {
+    float y[GTMP_MAX_DOF];
+    float s2 = 0.0f;
+    const uint4 w0 = words(k0, k1, n, m, stage, 1u, (uint32_t)(2 * a));
+    const uint4 w1 = words(k0, k1, n, m, stage, 1u, (uint32_t)(2 * a + 1));
+    for (int i = 0; i < d; ++i) {
+        const uint32_t wi = i < 4 ? pick(w0, i) : pick(w1, i - 4);
+        y[i] = (float)(wi >> 8) * (1.0f / 8388608.0f) - 1.0f;
+        s2 = s2 + y[i] * y[i];
     }
+    if (!(s2 < 1.0f)) return false;
+    float z[GTMP_MAX_DOF];
+    for (int i = 0; i < d; ++i) z[i] = (i == 0 ? I.r1 : I.r2) * y[i];
+    bool inside = true;
+    for (int i = 0; i < d; ++i) {
+        float acc = 0.0f;
+        for (int j = 0; j < d; ++j) acc = acc + I.H[i * d + j] * z[j];
+        x[i] = I.centre[i] + acc;
+        if (!(x[i] >= lo[i] && x[i] <= hi[i])) inside = false;
+    }
+    return inside;
+}
+
+// Box sample of slot (m, n): the words of attempt 0 mapped to the box.
+__device__ __forceinline__ void box_draw(int d, const float *lo, const float *wd, uint32_t k0, uint32_t k1,
+                                         uint32_t stage, uint32_t m, uint32_t n, float *x) {
     const uint4 w0 = words(k0, k1, n, m, stage, 1u, 0u);
     const uint4 w1 = words(k0, k1, n, m, stage, 1u, 1u);
     for (int i = 0; i < d; ++i) {
         const uint32_t wi = i < 4 ? pick(w0, i) : pick(w1, i - 4);
         x[i] = __builtin_fmaf(unit_from_word(wi), wd[i], lo[i]);
     }
+}
+
+// One draw of the uniform half for slot (m, n): the first accepted attempt.
+// Returns attempts used (0 for an unbounded draw, -1 for the box fallback).
+__device__ int informed_draw(int d, const float *lo, const float *wd, const float *hi, const Informed &I,
+                             uint32_t k0, uint32_t k1, uint32_t stage, uint32_t m, uint32_t n, float *x) {
+    if (I.bounded) {
+        for (int a = 0; a < kMaxAttempts; ++a) {
+            float xx[GTMP_MAX_DOF];
+            if (!informed_attempt(d, lo, hi, I, k0, k1, stage, m, n, a, xx)) continue;
+            for (int i = 0; i < d; ++i) x[i] = xx[i];
+            return a + 1;
+        }
+    }
+    box_draw(d, lo, wd, k0, k1, stage, m, n, x);
     return I.bounded ? -1 : 0;
 }
 
@@ -182,30 +196,49 @@ __global__ void k_pair_keys(int d, int nu, const float *U, int nv, const float *
     vals[t] = (uint32_t)t;
 }
 
-// Fill the new slots of layer m: a heuristic slot of rank h takes the
-// midpoint of the h-th closest pair (a uniform draw when fewer pairs exist),
-// every other slot a draw of the uniform half.  With the surrogate bias the
-// pair list is the compacted list of candidates predicted free and its length
-// is read from n_avail.
+// Fill the new slots of layer m, one wave per slot: a heuristic slot of
+// rank h takes the midpoint of the h-th closest pair (a uniform draw when
+// fewer pairs exist), every other slot a draw of the uniform half.  The
+// draw's attempts are tested 64 at a time, one per lane, and the lowest
+// accepted attempt index wins, so the result is the sequential first accepted
+// attempt.  With the surrogate bias the pair list is the compacted list of
+// candidates predicted free and its length is read from n_avail.
 __global__ void __launch_bounds__(256) k_expand_layer(int m, int n_old, int N, int d, BoxArgs B, uint32_t k0,
                                                       uint32_t k1, uint32_t stage, const Informed *Ip,
                                                       const int32_t *rank, const uint32_t *sorted_pairs,
                                                       uint64_t n_pairs, const uint32_t *n_avail, int nv,
                                                       const float *U, const float *Vv, float *Qm) {
-    const int n = n_old + blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+    const int n = n_old + (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    if (n >= N) return;  // whole wave
+    const int lane = lane_id();
     const Informed I = *Ip;
-    float x[GTMP_MAX_DOF];
     const int h = rank[n];
     const uint64_t avail = n_avail ? (uint64_t)*n_avail : n_pairs;
     if (h >= 0 && (uint64_t)h < avail) {
-        const uint32_t p = sorted_pairs[h];
-        const uint32_t a = p / (uint32_t)nv, b = p % (uint32_t)nv;
-        for (int i = 0; i < d; ++i) x[i] = (U[(size_t)a * d + i] + Vv[(size_t)b * d + i]) * 0.5f;
-    } else {
-        informed_draw(d, B.lo, B.wd, B.hi, I, k0, k1, stage, (uint32_t)m, (uint32_t)n, x);
+        if (lane == 0) {
+            const uint32_t p = sorted_pairs[h];
+            const uint32_t a = p / (uint32_t)nv, b = p % (uint32_t)nv;
+            for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = (U[(size_t)a * d + i] + Vv[(size_t)b * d + i]) * 0.5f;
+        }
+        return;
     }
-    for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
+    if (I.bounded) {
+        for (int base = 0; base < kMaxAttempts; base += kWave) {
+            float x[GTMP_MAX_DOF];
+            const bool ok = informed_attempt(d, B.lo, B.hi, I, k0, k1, stage, (uint32_t)m, (uint32_t)n, base + lane, x);
+            const uint64_t acc = ballot(ok);
+            if (acc != 0) {
+                if (lane == __builtin_ctzll(acc))
+                    for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
+                return;
+            }
+        }
+    }
+    if (lane == 0) {
+        float x[GTMP_MAX_DOF];
+        box_draw(d, B.lo, B.wd, k0, k1, stage, (uint32_t)m, (uint32_t)n, x);
+        for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
+    }
 }
 
 // Surrogate bias of the heuristic half: midpoints of the K closest pairs
@@ -370,9 +403,9 @@ hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *go
             sorted = bfree;
             n_avail = bcount;
         }
-        hipLaunchKernelGGL(k_expand_layer, dim3((unsigned)((N - n_old + 255) / 256)), dim3(256), 0, s, m, n_old, N, d,
-                           B, k0, k1, st, I, rank, sorted, heuristic_ok ? npairs : 0, n_avail, nv, U, Vv,
-                           Q_new + (size_t)m * N * d);
+        const unsigned slots = (unsigned)(N - n_old);  // one wave per new slot, four per block
+        hipLaunchKernelGGL(k_expand_layer, dim3((slots + 3) / 4), dim3(256), 0, s, m, n_old, N, d, B, k0, k1, st, I,
+                           rank, sorted, heuristic_ok ? npairs : 0, n_avail, nv, U, Vv, Q_new + (size_t)m * N * d);
     }
     return hipGetLastError();
 }

@@ -452,8 +452,8 @@ static gtmp_status check_net(const gtmp_surrogate *net, bool writable, gtmp::Sur
     if (!net) return fail(GTMP_EINVAL, "net is NULL");
     if (net->d < 1 || net->d > GTMP_MAX_DOF) return fail(GTMP_EINVAL, "net d=%d outside 1..%d", net->d, GTMP_MAX_DOF);
     if (!net->fourier || !net->params || !net->params_bf16) return fail(GTMP_EINVAL, "net has a NULL buffer");
-    if ((reinterpret_cast<uintptr_t>(net->params_bf16) & 15) != 0 || (reinterpret_cast<uintptr_t>(net->params) & 3) != 0)
-        return fail(GTMP_EINVAL, "params_bf16 must be 16-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(net->params_bf16) & 15) != 0 || (reinterpret_cast<uintptr_t>(net->params) & 15) != 0)
+        return fail(GTMP_EINVAL, "params and params_bf16 must be 16-byte aligned");
     (void)writable;
     out->d = net->d;
     out->fourier = net->fourier;

@@ -182,6 +182,135 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K_split, cons
         }
 }
 
+// ------------------------------------------------------------------ fused inference
+// Whole network for 128 rows per block (inference only): features computed in
+// FP64 straight into LDS, then four hidden layers whose BF16 activations stay
+// in LDS (one 128 x 256 tile, written back in place after a barrier), then the
+// FP32 head.  Wave w owns output columns [64 w, 64 w + 64) of every layer:
+// 4 x 2 tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16, 128 accumulators per
+// lane); activation fragments come from LDS, weight fragments from global
+// memory (L2-resident, each block reads every weight once per layer).  Two
+// blocks share a CU (2 x 68 KB of LDS), so one block's feature or epilogue
+// phase overlaps the other's MFMAs.  Sums run in K order as in k_gemm_nt.
+constexpr int kFR = 128;                              // rows per block
+constexpr int kFRow = GTMP_SUR_WIDTH + 8;             // LDS row stride (BF16), 528 bytes
+
+// One hidden layer on the block's LDS tile: K input columns -> 256 outputs,
+// bias + ReLU, BF16, written back in place.  The MFMA computes the transposed
+// product (weights as the A operand, activations as B), so each lane's
+// accumulators hold four consecutive output columns of one row: they are
+// converted with one packed instruction per pair and stored with one 8-byte
+// LDS write.  Weight fragments are requested one K slice ahead.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+template <int K>
+__device__ __forceinline__ void mlp_layer(const uint16_t *__restrict__ W, const float *__restrict__ bias,
+                                          uint16_t *act, int wave, int lane) {
+    constexpr int S = K / 16;
+    const int cl = lane & 31, kh = 8 * (lane >> 5);
+    const int c0 = wave * 64;
+    f32x16 acc[4][2];  // [row tile i][column tile j]
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+    const uint16_t *wr0 = W + (size_t)(c0 + cl) * K + kh;
+    const uint16_t *wr1 = W + (size_t)(c0 + 32 + cl) * K + kh;
+    bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(wr0);
+    bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(wr1);
+#pragma unroll
+    for (int ks = 0; ks < S; ++ks) {
+        bf16x8 nw0 = w0, nw1 = w1;
+        if (ks + 1 < S) {
+            nw0 = *reinterpret_cast<const bf16x8 *>(wr0 + 16 * (ks + 1));
+            nw1 = *reinterpret_cast<const bf16x8 *>(wr1 + 16 * (ks + 1));
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[(32 * i + cl) * kFRow + 16 * ks + kh]);
+            acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, a, acc[i][0], 0, 0, 0);
+            acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, a, acc[i][1], 0, 0, 0);
+        }
+        w0 = nw0;
+        w1 = nw1;
+    }
+    // element v of tile (i, j): output column c0 + 32 j + 8 (v/4) + 4 (lane/32) + v%4, row 32 i + lane%32
+    f32x4v bq[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            bq[j][g] = *reinterpret_cast<const f32x4v *>(bias + c0 + 32 * j + 8 * g + 4 * (lane >> 5));
+    __syncthreads();  // every wave has read this layer's input
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                f32x4v z;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float t = acc[i][j][4 * g + r] + bq[j][g][r];
+                    z[r] = t > 0.f ? t : 0.f;
+                }
+                const bf16x4 o = __builtin_convertvector(z, bf16x4);
+                const int col = c0 + 32 * j + 8 * g + 4 * (lane >> 5);
+                *reinterpret_cast<bf16x4 *>(&act[(32 * i + cl) * kFRow + col]) = o;
+            }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256, 2) k_mlp_infer(int d, int64_t n, const float *__restrict__ X,
+                                                     const float *__restrict__ Bf, const uint16_t *__restrict__ P16,
+                                                     const float *__restrict__ P32, SurLayout L,
+                                                     float *__restrict__ logits) {
+    __shared__ __attribute__((aligned(16))) uint16_t act[kFR * kFRow];
+    __shared__ float w5s[GTMP_SUR_WIDTH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * kFR;
+
+    // ---- features: two threads per row, each half of the frequencies
+    {
+        const int r = tid & (kFR - 1), half = tid >> 7;
+        const int64_t gr = row0 + r;
+        uint16_t *dst = act + r * kFRow;
+        constexpr double kPi = 3.14159265358979323846;
+        double qh[GTMP_MAX_DOF];
+        for (int j = 0; j < GTMP_MAX_DOF; ++j) qh[j] = (gr < n && j < d) ? (double)X[gr * d + j] / kPi : 0.0;
+        if (half == 0) {
+            for (int j = 0; j < d; ++j) dst[j] = d2bf(qh[j]);
+            for (int k = d + 2 * GTMP_SUR_FREQ; k < GTMP_SUR_IN; ++k) dst[k] = 0;
+        }
+        for (int f = half * (GTMP_SUR_FREQ / 2); f < (half + 1) * (GTMP_SUR_FREQ / 2); ++f) {
+            double sarg = 0.0;
+            for (int j = 0; j < d; ++j) sarg += (double)Bf[f * d + j] * qh[j];
+            sarg *= 2.0 * kPi;
+            double sn, cs;
+            sincos(sarg, &sn, &cs);
+            dst[d + f] = d2bf(sn);
+            dst[d + GTMP_SUR_FREQ + f] = d2bf(cs);
+        }
+        if (tid < GTMP_SUR_WIDTH) w5s[tid] = bf2f(P16[L.w5 + tid]);
+    }
+    __syncthreads();
+
+    mlp_layer<GTMP_SUR_IN>(P16 + L.W[0], P32 + L.b[0], act, wave, lane);
+    mlp_layer<GTMP_SUR_WIDTH>(P16 + L.W[1], P32 + L.b[1], act, wave, lane);
+    mlp_layer<GTMP_SUR_WIDTH>(P16 + L.W[2], P32 + L.b[2], act, wave, lane);
+    mlp_layer<GTMP_SUR_WIDTH>(P16 + L.W[3], P32 + L.b[3], act, wave, lane);
+    // ---- head: one thread per row, FP32 in K order
+    if (tid < kFR && row0 + tid < n) {
+        const uint16_t *a = act + tid * kFRow;
+        float z = 0.f;
+        for (int k = 0; k < GTMP_SUR_WIDTH; ++k) z = __builtin_fmaf(w5s[k], bf2f(a[k]), z);
+        logits[row0 + tid] = z + P32[L.b5];
+    }
+}
+
 // ------------------------------------------------------------------ small kernels
 // out [C][R] = in [R][C]^T, BF16, R and C multiples of 64.
 __global__ void __launch_bounds__(256) k_transpose_bf16(int R, int C, const uint16_t *__restrict__ in,
@@ -450,14 +579,21 @@ static void forward(const SurNet &net, int64_t n, const float *X, const SurWs &w
                        inv_n, logits, w.loss_terms, w.dz);
 }
 
+static void infer_fused(const SurNet &net, int64_t n, const float *X, float *logits, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + kFR - 1) / kFR)), dim3(256), 0, s, net.d, n, X, net.fourier,
+                       net.p16, net.p32, sur_layout(), logits);
+}
+
 hipError_t launch_sur_infer(const SurNet &net, int64_t n, const float *X, float *logits, void *ws, size_t ws_bytes,
                             hipStream_t s) {
-    const int64_t cap = sur_rows_for(ws_bytes);
-    if (cap <= 0) return hipErrorInvalidValue;
-    const SurWs w = carve_infer(cap, ws);
-    for (int64_t r = 0; r < n; r += cap) {
-        const int64_t c = n - r < cap ? n - r : cap;
-        forward(net, c, X + r * net.d, w, logits + r, nullptr, 0.f, s);
+    (void)ws;
+    (void)ws_bytes;
+    // the fused kernel needs no workspace; chunks bound the grid size
+    constexpr int64_t kChunk = (int64_t)1 << 30;
+    for (int64_t r = 0; r < n; r += kChunk) {
+        const int64_t c = n - r < kChunk ? n - r : kChunk;
+        infer_fused(net, c, X + r * net.d, logits + r, s);
     }
     return hipGetLastError();
 }
@@ -554,7 +690,7 @@ hipError_t launch_sur_prune(const gtmp_problem &p, const SurNet &net, const floa
         const int64_t c = E - e0 < cap ? E - e0 : cap;
         hipLaunchKernelGGL(k_edge_midpoints, dim3(blocks_for(c)), dim3(256), 0, s, p.d, p.M, p.N, p.G, e0, c, q0, goals,
                            Q, w.Xf);
-        forward(net, c, w.Xf, w, w.logit_tmp, nullptr, 0.f, s);
+        infer_fused(net, c, w.Xf, w.logit_tmp, s);
         hipLaunchKernelGGL(k_threshold, dim3(blocks_for(c)), dim3(256), 0, s, c, w.logit_tmp, tau, prune + e0,
                            logits ? logits + e0 : nullptr);
     }
