@@ -136,7 +136,7 @@ typedef struct gtmp_edge_opts {
     int32_t block;            /* ignored: the interior kernels run 256-thread blocks */
     int32_t blocks_per_cu;    /* resident blocks per CU for the persistent interior kernel (0 = auto) */
     int32_t sphere_chunks;    /* arms: the collision spheres of a state are tested in this many
-                                 chunks (1, 2 or 4; 0 = auto = 4) */
+                                 chunks (1, 2 or 4; 0 = auto = 2) */
     int32_t reserved[3];
     unsigned long long *stats; /* optional device [4]: states evaluated, edges checked in the
                                   interior pass, reserved, reserved.  Added to. */
@@ -324,7 +324,7 @@ typedef struct gtmp_batch_opts {
                                  whose sample expansion sorts with a library routine that clears memory
                                  with memset nodes, which are kept out of graphs */
     int32_t states_per_iter;  /* interior states per lane and iteration for point robots (0 = auto) */
-    int32_t sphere_chunks;    /* arms: spheres tested in 1 or 2 chunks (0 = auto) */
+    int32_t sphere_chunks;    /* arms: spheres tested in 1, 2 or 4 chunks (0 = auto = 2) */
     int32_t blocks_per_cu;    /* resident blocks per CU of the persistent kernels (0 = auto) */
     unsigned long long *stats; /* optional device [4], as gtmp_edge_opts.stats */
 } gtmp_batch_opts;

@@ -375,7 +375,8 @@ static gtmp_status check_batch(const gtmp_plan_desc *plans, int32_t n, const gtm
                                std::vector<gtmp::ArmParams> *arms) {
     if (!plans || n < 1) return fail(GTMP_EINVAL, "need at least one plan");
     if (!opts) return fail(GTMP_EINVAL, "opts is NULL");
-    if (opts->sphere_chunks < 0 || opts->sphere_chunks > 2 || opts->states_per_iter < 0 || opts->states_per_iter > 8 ||
+    if ((opts->sphere_chunks != 0 && opts->sphere_chunks != 1 && opts->sphere_chunks != 2 && opts->sphere_chunks != 4) ||
+        opts->states_per_iter < 0 || opts->states_per_iter > 8 ||
         opts->blocks_per_cu < 0 || opts->blocks_per_cu > 32)
         return fail(GTMP_EINVAL, "bad batch options");
     arms->assign(n, gtmp::ArmParams{});

@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(kTile) k_batch_prepass(const BPlan *plans, int
 // table are read with wave-uniform addresses.  A wave that draws a tile of
 // another plan finishes its edges before it switches.
 template <class Model, bool UNIFORM_R, int NCH>
-__global__ void __launch_bounds__(256, NCH == 1 ? 3 : 4)
+__global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
     k_batch_interior(const BPlan *plans, int p0, int p1, uint32_t n_gtiles, uint32_t *gcounter,
                      unsigned long long *stats) {
     constexpr int D = Model::D;
@@ -319,21 +319,7 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : 4)
             const auto &R = *Rp;
             const float r0 = R.r0;
             const v32f o = arm_fk<D>(R, q);
-            float pr[KC];
-            {
-                Probes<3, KC> P;
-                arm_spheres<KC, 0>(R, o, P);
-#pragma unroll
-                for (int k = 0; k < KC; ++k) pr[k] = UNIFORM_R ? 0.f : (k < R.n_spheres ? R.r[k] : 0.f);
-                gap = probes_min_gap<3, KC, UNIFORM_R>(P, pr, r0, S);
-            }
-            if constexpr (NCH > 1) {
-                Probes<3, KC> P;
-                arm_spheres<KC, KC>(R, o, P);
-#pragma unroll
-                for (int k = 0; k < KC; ++k) pr[k] = UNIFORM_R ? 0.f : (KC + k < R.n_spheres ? R.r[KC + k] : 0.f);
-                gap = __builtin_fminf(gap, probes_min_gap<3, KC, UNIFORM_R>(P, pr, r0, S));
-            }
+            gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
         } else {
             Probes<W, KP> P;
 #pragma unroll
@@ -516,6 +502,28 @@ __global__ void k_batch_init(const BPlan *plans, int n_plans) {
     P.best_meta[2] = 0;
     P.best_meta[3] = 0;
     *P.counter = 0;
+}
+
+// Rounding bound of the expanded sphere test per arm plan (see
+// k_store_params_tol): one wave per plan of the group range [p0, p1).
+__global__ void __launch_bounds__(64) k_batch_arm_tol(const BPlan *plans, int p0) {
+    const BPlan &P = plans[p0 + blockIdx.x];
+    float cmax = 0.f, rmax = 0.f;
+    for (int o = threadIdx.x; o < P.S.n_sph; o += blockDim.x) {
+        const float *c = P.S.sph + 4 * o;
+        cmax = __builtin_fmaxf(cmax, __builtin_sqrtf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]));
+        rmax = __builtin_fmaxf(rmax, __builtin_fabsf(c[3]));
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cmax = __builtin_fmaxf(cmax, __shfl_xor(cmax, off));
+        rmax = __builtin_fmaxf(rmax, __shfl_xor(rmax, off));
+    }
+    if (threadIdx.x == 0) {
+        ArmParams *R = const_cast<ArmParams *>(P.arm);
+        const float pc = (R->reach + cmax) * 1.001f, rr = (rmax + R->r0) * 1.001f;
+        R->sph_tol = 0x1p-19f * (pc * pc + rr * rr);
+    }
 }
 
 __global__ void k_batch_zero(uint32_t *p, int n) {
@@ -753,12 +761,14 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
     if (err != hipSuccess) return err;
 
     const int spi = o.states_per_iter == 1 || o.states_per_iter == 2 || o.states_per_iter == 8 ? o.states_per_iter : 4;
-    const int nch = o.sphere_chunks == 1 ? 1 : 2;
+    const int nch = o.sphere_chunks == 1 ? 1 : o.sphere_chunks == 4 ? 4 : 2;
 
     auto enqueue = [&](hipStream_t st_) -> hipError_t {
         if (info.empty()) return hipSuccess;
         // archive init over the plans of stage 0 (every plan has a stage 0)
         hipLaunchKernelGGL(k_batch_init, dim3((info[0].count + 255) / 256), dim3(256), 0, st_, tables, info[0].count);
+        if (info[0].g3 > info[0].g2)
+            hipLaunchKernelGGL(k_batch_arm_tol, dim3(info[0].g3 - info[0].g2), dim3(64), 0, st_, tables, info[0].g2);
         for (int st = 0; st < L.max_stages; ++st) {
             const StageInfo &I = info[st];
             const BPlan *T = tables + (size_t)st * n;
@@ -819,11 +829,12 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
             }
             if (I.gtiles[2] > 0) {
                 const void *k = nullptr;
+#define GTMP_BK1(K, C) (uniform_r ? (const void *)k_batch_interior<ArmModel<K>, true, C> : (const void *)k_batch_interior<ArmModel<K>, false, C>)
 #define GTMP_BK(K) \
-    if (kp == K) k = nch == 1 ? (uniform_r ? (const void *)k_batch_interior<ArmModel<K>, true, 1> : (const void *)k_batch_interior<ArmModel<K>, false, 1>) \
-                              : (uniform_r ? (const void *)k_batch_interior<ArmModel<K>, true, 2> : (const void *)k_batch_interior<ArmModel<K>, false, 2>);
+    if (kp == K) k = nch == 1 ? GTMP_BK1(K, 1) : nch == 4 ? GTMP_BK1(K, 4) : GTMP_BK1(K, 2);
                 GTMP_BK(8) GTMP_BK(16) GTMP_BK(24) GTMP_BK(32) GTMP_BK(40) GTMP_BK(48) GTMP_BK(56) GTMP_BK(64)
 #undef GTMP_BK
+#undef GTMP_BK1
                 if (!k) return hipErrorInvalidValue;
                 const int grid = persistent_blocks(k, o.blocks_per_cu);
                 uint32_t *c2 = ctr + 2;

@@ -287,45 +287,7 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interi
             asm volatile("" : "+s"(Rp));
             const auto &R = *Rp;
             const v32f o = arm_fk<D>(R, q);
-            float pr[KC];
-            if constexpr (UNIFORM_R) {
-                // sphere obstacles in the expanded form, re-evaluated in the
-                // difference form for the lanes whose result is within the
-                // rounding bound of zero; boxes in the difference form
-                const float tol = R.sph_tol;
-#pragma unroll
-                for (int k = 0; k < KC; ++k) pr[k] = 0.f;
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    Probes<3, KC> P;
-                    if (ch == 0) arm_spheres<KC, 0>(R, o, P);
-                    else if (ch == 1) arm_spheres<KC, (NCH > 1 ? KC : 0)>(R, o, P);
-                    else if (ch == 2) arm_spheres<KC, (NCH > 2 ? 2 * KC : 0)>(R, o, P);
-                    else arm_spheres<KC, (NCH > 3 ? 3 * KC : 0)>(R, o, P);
-                    float gs = sph_min_gap_expanded<KC>(P, r0, S);
-                    const bool near = __builtin_fabsf(gs) <= tol;
-                    if (ballot(near) != 0) {
-                        const float ex = probes_min_gap<3, KC, true, true, false>(P, pr, r0, S);
-                        if (near) gs = ex;
-                    }
-                    const float gb = probes_min_gap<3, KC, true, false, true>(P, pr, r0, S);
-                    const float g = __builtin_fminf(gs, gb);
-                    gap = ch == 0 ? g : __builtin_fminf(gap, g);
-                }
-            } else {
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    Probes<3, KC> P;
-                    if (ch == 0) arm_spheres<KC, 0>(R, o, P);
-                    else if (ch == 1) arm_spheres<KC, (NCH > 1 ? KC : 0)>(R, o, P);
-                    else if (ch == 2) arm_spheres<KC, (NCH > 2 ? 2 * KC : 0)>(R, o, P);
-                    else arm_spheres<KC, (NCH > 3 ? 3 * KC : 0)>(R, o, P);
-#pragma unroll
-                    for (int k = 0; k < KC; ++k) pr[k] = ch * KC + k < R.n_spheres ? R.r[ch * KC + k] : 0.f;
-                    const float g = probes_min_gap<3, KC, false>(P, pr, r0, S);
-                    gap = ch == 0 ? g : __builtin_fminf(gap, g);
-                }
-            }
+            gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
         } else {
             Probes<W, KP> P;
 #pragma unroll

@@ -25,6 +25,48 @@ struct EdgeArgs {
     float tord[GTMP_MAX_H];  // t = h / (H-1) of the interior states, in check order
 };
 
+// ------------------------------------------------------------------ arm state test
+// Collision gap of one arm state (<= 0 iff some robot sphere touches an
+// obstacle), its spheres evaluated in NCH chunks of KP / NCH.  Uniform robot
+// radius: sphere obstacles in the expanded form with the difference form
+// re-evaluated for the lanes within the rounding bound R.sph_tol of zero
+// (wave-uniform branch), boxes in the difference form.  Otherwise every
+// obstacle in the difference form with per-sphere radii.  Every lane of the
+// wave must call this (it contains a ballot).
+template <int KP, int NCH, bool UNIFORM_R, class AP>
+__device__ __forceinline__ float arm_state_gap(const AP &R, const v32f &o, float r0, const SceneParams &S) {
+    constexpr int KC = KP / NCH;
+    float gap = __builtin_inff();
+    float pr[KC];
+    const float tol = UNIFORM_R ? R.sph_tol : 0.f;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) pr[k] = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        Probes<3, KC> P;
+        if (ch == 0) arm_spheres<KC, 0>(R, o, P);
+        else if (ch == 1) arm_spheres<KC, (NCH > 1 ? KC : 0)>(R, o, P);
+        else if (ch == 2) arm_spheres<KC, (NCH > 2 ? 2 * KC : 0)>(R, o, P);
+        else arm_spheres<KC, (NCH > 3 ? 3 * KC : 0)>(R, o, P);
+        float g;
+        if constexpr (UNIFORM_R) {
+            float gs = sph_min_gap_expanded<KC>(P, r0, S);
+            const bool near = __builtin_fabsf(gs) <= tol;
+            if (ballot(near) != 0) {
+                const float ex = probes_min_gap<3, KC, true, true, false>(P, pr, r0, S);
+                if (near) gs = ex;
+            }
+            g = __builtin_fminf(gs, probes_min_gap<3, KC, true, false, true>(P, pr, r0, S));
+        } else {
+#pragma unroll
+            for (int k = 0; k < KC; ++k) pr[k] = ch * KC + k < R.n_spheres ? R.r[ch * KC + k] : 0.f;
+            g = probes_min_gap<3, KC, false>(P, pr, r0, S);
+        }
+        gap = ch == 0 ? g : __builtin_fminf(gap, g);
+    }
+    return gap;
+}
+
 // Row / tile decoding.  Rows enumerate the edges by their shared endpoint:
 //   row 0                 : q0 -> layer 0 vertex n            (C_s[n])
 //   row 1 + m N + u       : layer m vertex u -> layer m+1 vertex n  (C_h[m][u][n])
