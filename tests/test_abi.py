@@ -101,3 +101,99 @@ def test_bad_models_rejected(g):
     scene.wdim = 2
     assert g._lib.gtmp_edge_check_cost(C.byref(p), C.byref(robot), C.byref(scene), *([C.c_void_p(256)] * 9), ws,
                                        C.c_size_t(16), None, None) == g.GTMP_EWORKSPACE
+
+
+# ------------------------------------------------------------ anytime / batch / surrogate validation
+def _net(g, d=7, params=256, p16=256, fourier=256):
+    return g.gtmp_surrogate(d, C.c_void_p(fourier) if fourier else None, C.c_void_p(params) if params else None,
+                            C.c_void_p(p16) if p16 else None)
+
+
+def test_surrogate_layout_and_workspace(g):
+    off = g.gtmp_surrogate_layout()
+    assert off[0] == 0 and off[10] == 64 * 256 + 256 + 3 * (256 * 256 + 256) + 256 + 1
+    assert all(o % 64 == 0 for o in off[:9])  # every weight block 16-byte aligned in both precisions
+    n = C.c_size_t()
+    assert g._lib.gtmp_surrogate_workspace_size(0, C.byref(n)) == g.GTMP_EINVAL
+    assert g.gtmp_surrogate_workspace_size(256) < g.gtmp_surrogate_workspace_size(8192)
+
+
+@pytest.mark.parametrize("bad", [dict(d=0), dict(d=9), dict(params=0), dict(p16=0), dict(fourier=0),
+                                 dict(p16=258), dict(params=260)])
+def test_surrogate_bad_net_rejected(g, bad):
+    net = _net(g, **bad)
+    ws = C.c_void_p(1 << 20)
+    assert g._lib.gtmp_surrogate_infer(C.byref(net), 10, C.c_void_p(256), C.c_void_p(256), ws, 1 << 30,
+                                       None) == g.GTMP_EINVAL
+    assert g._lib.gtmp_surrogate_refresh_bf16(C.byref(net), None) == g.GTMP_EINVAL
+
+
+def test_surrogate_calls_validate_sizes(g):
+    net = _net(g)
+    ws = C.c_void_p(1 << 20)
+    big = C.c_size_t(1 << 40)
+    # training batches are positive multiples of 256
+    for n in (0, 100, 300):
+        assert g._lib.gtmp_surrogate_grad(C.byref(net), n, *([C.c_void_p(256)] * 5), ws, big, None) == g.GTMP_EINVAL
+    # workspace too small / misaligned
+    assert g._lib.gtmp_surrogate_grad(C.byref(net), 256, *([C.c_void_p(256)] * 5), ws, C.c_size_t(1024),
+                                      None) == g.GTMP_EWORKSPACE
+    assert g._lib.gtmp_surrogate_infer(C.byref(net), 10, C.c_void_p(256), C.c_void_p(256), C.c_void_p(1 << 20 | 8),
+                                       big, None) == g.GTMP_EINVAL
+    # Adam hyper-parameters
+    for t, lr, b1, b2, eps in ((0, 1e-3, .9, .999, 1e-8), (1, -1.0, .9, .999, 1e-8), (1, 1e-3, 1.0, .999, 1e-8),
+                               (1, 1e-3, .9, .999, 0.0)):
+        assert g._lib.gtmp_surrogate_adam(C.byref(net), *([C.c_void_p(256)] * 3), t, lr, b1, b2, eps,
+                                          None) == g.GTMP_EINVAL
+    # label states need interior states; prune needs matching d
+    p = _prob(g, H=2)
+    assert g._lib.gtmp_surrogate_label_states(C.byref(p), 1, 0, 10, C.c_void_p(256), None) == g.GTMP_EINVAL
+    p = _prob(g)
+    assert g._lib.gtmp_surrogate_prune(C.byref(p), C.byref(net), *([C.c_void_p(256)] * 3), 0.0, C.c_void_p(256),
+                                       None, ws, big, None) == g.GTMP_EINVAL  # net d = 7, problem d = 2
+
+
+def test_biased_expansion_validates(g):
+    p = _prob(g)
+    net = _net(g, d=2)
+    need = g.gtmp_expand_biased_workspace_size(p)
+    assert need > g.gtmp_expand_workspace_size(p)
+    args = lambda n_old, ws_bytes, netp: (C.byref(p), C.c_void_p(256), C.c_void_p(256), C.c_void_p(1 << 20), n_old,
+                                          C.c_void_p(2 << 20), C.c_void_p(256), 1, 0, netp, 0.0, C.c_void_p(1 << 24),
+                                          C.c_size_t(ws_bytes), None)
+    assert g._lib.gtmp_expand_samples_biased(*args(-1, need, C.byref(net))) == g.GTMP_EINVAL
+    assert g._lib.gtmp_expand_samples_biased(*args(9, need, C.byref(net))) == g.GTMP_EINVAL
+    assert g._lib.gtmp_expand_samples_biased(*args(4, need - 1, C.byref(net))) == g.GTMP_EWORKSPACE
+    bad = _net(g, d=3)
+    assert g._lib.gtmp_expand_samples_biased(*args(4, need, C.byref(bad))) == g.GTMP_EINVAL
+
+
+def test_anytime_and_batch_options_validate(g):
+    p = _prob(g)
+    o = g.gtmp_anytime_opts()
+    o.mode, o.max_stages = g.GTMP_ANYTIME_GROWING, 4
+    o.M_min, o.M_max, o.N_min, o.N_max = 2, 1, 4, 8  # M_min > M_max
+    n = C.c_size_t()
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_EINVAL
+    o.M_min, o.M_max = 1, 3
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_OK
+    o.max_stages = 0
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_EINVAL
+    o.max_stages, o.mode = 4, 7
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_EINVAL
+    # batch: empty, bad options, bad plan
+    descs = (g.gtmp_plan_desc * 1)()
+    D = descs[0]
+    D.problem = p
+    D.robot = g.make_point_robot()
+    D.scene.wdim, D.scene.n_spheres, D.scene.spheres = 2, 1, 256
+    D.q0, D.goals, D.seed, D.mode, D.stages, D.M_min, D.N_min = 256, 256, 1, g.GTMP_ANYTIME_RESTART, 2, 3, 8
+    bo = g.gtmp_batch_opts()
+    assert g._lib.gtmp_batch_workspace_size(descs, 0, C.byref(bo), C.byref(n)) == g.GTMP_EINVAL
+    assert g._lib.gtmp_batch_workspace_size(descs, 1, C.byref(bo), C.byref(n)) == g.GTMP_OK and n.value > 0
+    for field, val in (("sphere_chunks", 3), ("states_per_iter", 9), ("blocks_per_cu", 40)):
+        bo2 = g.gtmp_batch_opts()
+        setattr(bo2, field, val)
+        assert g._lib.gtmp_batch_workspace_size(descs, 1, C.byref(bo2), C.byref(n)) == g.GTMP_EINVAL, field
+    D.stages = 0
+    assert g._lib.gtmp_batch_workspace_size(descs, 1, C.byref(bo), C.byref(n)) == g.GTMP_EINVAL

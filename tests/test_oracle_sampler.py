@@ -72,3 +72,21 @@ def test_samples_deterministic_and_stage_dependent(orc):
     assert np.array_equal(a, b)
     assert not np.array_equal(a, c)
     assert not np.array_equal(a, d)
+
+
+def test_layer_coverage_of_a_corridor():
+    """Sec. III (Layered Sampling Model): a layer of N independent draws misses
+    a set A with probability (1 - pi(A))^N for the uniform sampler, within the
+    paper's bound (1 - pi(A)/2)^N for the fair-coin mixture.  A = the corridor
+    |x| <= 0.5 of the 2D box [-10, 10]^2, pi(A) = 0.05, N = 40."""
+    import oracle
+    from scipy import stats
+    lo, hi = np.array([-10.0, -10.0]), np.array([10.0, 10.0])
+    N, trials = 40, 3000
+    miss = 0
+    for t in range(trials):
+        Q = oracle.sample_layers(1, N, 2, lo, hi, 1000 + t, 7)[0]
+        miss += int(not np.any(np.abs(Q[:, 0]) <= 0.5))
+    p_exact = (1 - 0.05) ** N
+    assert stats.binomtest(miss, trials, p_exact).pvalue > 1e-3
+    assert miss / trials <= (1 - 0.05 / 2) ** N
