@@ -84,3 +84,18 @@ def check_path_indices(or_cost3, V, idx_or, idx_gpu, cost, rel=REL):
         assert idx_gpu[step] == idx_or[step], f"index mismatch at step {step}: {idx_gpu[step]} vs {idx_or[step]}"
         compared += 1
     return compared
+
+
+# Surrogate logits (BF16 network, FP32 accumulation) against the FP64 oracle
+# with the same BF16 rounding points: see tests/test_gpu_surrogate.py for how
+# these bounds follow from the arithmetic.
+Z_TOL = 1e-4
+Z_LOOSE = 1e-2
+
+
+def check_logits(z, z_or):
+    scale = np.maximum(1.0, np.abs(z_or))
+    err = np.abs(np.asarray(z, np.float64) - z_or) / scale
+    assert np.all(err <= Z_LOOSE), err.max()
+    assert np.mean(err <= Z_TOL) >= 0.97, np.mean(err <= Z_TOL)
+    return err

@@ -26,17 +26,9 @@ import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-Z_TOL = 1e-4
-Z_LOOSE = 1e-2
+from tests.parity import Z_LOOSE, Z_TOL, check_logits as _check_logits  # noqa: E402
+
 G_TOL = 1e-3
-
-
-def _check_logits(z, z_or):
-    scale = np.maximum(1.0, np.abs(z_or))
-    err = np.abs(np.asarray(z, np.float64) - z_or) / scale
-    assert np.all(err <= Z_LOOSE), err.max()
-    assert np.mean(err <= Z_TOL) >= 0.97, np.mean(err <= Z_TOL)
-    return err
 
 
 def _say(*a):
