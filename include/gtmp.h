@@ -132,9 +132,10 @@ gtmp_status gtmp_sample_layers(const gtmp_problem *prob, uint64_t seed, uint64_t
 /* Tuning knobs; zero-initialise for the defaults. */
 typedef struct gtmp_edge_opts {
     int32_t mode;             /* GTMP_CHECK_FAST (default) or GTMP_CHECK_FULL */
-    int32_t states_per_iter;  /* point robots: interior states per lane and iteration (1,2,4,8; 0 = auto) */
+    int32_t states_per_iter;  /* point robots: interior states per lane and iteration (1,2,4,8; 0 = auto = 8) */
     int32_t block;            /* ignored: the interior kernels run 256-thread blocks */
-    int32_t blocks_per_cu;    /* resident blocks per CU for the persistent interior kernel (0 = auto) */
+    int32_t blocks_per_cu;    /* resident blocks per CU for the persistent interior kernel (0 = auto:
+                                 the occupancy limit, at most 3 for point robots) */
     int32_t sphere_chunks;    /* arms: the collision spheres of a state are tested in this many
                                  chunks (1, 2 or 4; 0 = auto = 2) */
     int32_t reserved[3];
@@ -323,7 +324,7 @@ typedef struct gtmp_batch_opts {
                                  ignored (stages enqueued directly) when a plan uses the growing policy,
                                  whose sample expansion sorts with a library routine that clears memory
                                  with memset nodes, which are kept out of graphs */
-    int32_t states_per_iter;  /* interior states per lane and iteration for point robots (0 = auto) */
+    int32_t states_per_iter;  /* interior states per lane and iteration for point robots (0 = auto = 8) */
     int32_t sphere_chunks;    /* arms: spheres tested in 1, 2 or 4 chunks (0 = auto = 2) */
     int32_t blocks_per_cu;    /* resident blocks per CU of the persistent kernels (0 = auto) */
     unsigned long long *stats; /* optional device [4], as gtmp_edge_opts.stats */

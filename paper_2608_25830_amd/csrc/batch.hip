@@ -541,7 +541,7 @@ __global__ void k_store_params_n(const ArmParams *src, ArmParams *dst, int n) {
 }
 
 // ------------------------------------------------------------------ host side
-static int persistent_blocks(const void *kernel, int per_cu_req) {
+static int persistent_blocks(const void *kernel, int per_cu_req, int auto_cap = 1 << 20) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
@@ -551,7 +551,7 @@ static int persistent_blocks(const void *kernel, int per_cu_req) {
     if (per_cu <= 0) {
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, 0) != hipSuccess || occ <= 0) occ = 2;
-        per_cu = occ;
+        per_cu = occ < auto_cap ? occ : auto_cap;
     }
     return cus * per_cu;
 }
@@ -760,7 +760,9 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
     err = hipMemcpy(bases, host_bases.data(), sizeof(uint64_t) * host_bases.size(), hipMemcpyHostToDevice);
     if (err != hipSuccess) return err;
 
-    const int spi = o.states_per_iter == 1 || o.states_per_iter == 2 || o.states_per_iter == 8 ? o.states_per_iter : 4;
+    // point robots: 8 states per lane and at most 3 resident blocks per CU
+    // unless asked otherwise (as the single-plan launcher)
+    const int spi = o.states_per_iter == 1 || o.states_per_iter == 2 || o.states_per_iter == 4 ? o.states_per_iter : 8;
     const int nch = o.sphere_chunks == 1 ? 1 : o.sphere_chunks == 4 ? 4 : 2;
 
     auto enqueue = [&](hipStream_t st_) -> hipError_t {
@@ -812,15 +814,15 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                               : spi == 2 ? (const void *)k_batch_interior<PointModel<2, 2>, true, 1>
                               : spi == 8 ? (const void *)k_batch_interior<PointModel<2, 8>, true, 1>
                                          : (const void *)k_batch_interior<PointModel<2, 4>, true, 1>;
-                const int grid = persistent_blocks(k, o.blocks_per_cu);
+                const int grid = persistent_blocks(k, o.blocks_per_cu, 3);
                 void *args[] = {(void *)&T, (void *)&I.g0, (void *)&I.g1, (void *)&I.gtiles[0], (void *)&ctr,
                                 (void *)&out.stats};
                 hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, st_);
                 if (e != hipSuccess) return e;
             }
             if (I.gtiles[1] > 0) {
-                const void *k = (const void *)k_batch_interior<PointModel<3, 4>, true, 1>;
-                const int grid = persistent_blocks(k, o.blocks_per_cu);
+                const void *k = (const void *)k_batch_interior<PointModel<3, 8>, true, 1>;
+                const int grid = persistent_blocks(k, o.blocks_per_cu, 3);
                 uint32_t *c1 = ctr + 1;
                 void *args[] = {(void *)&T, (void *)&I.g1, (void *)&I.g2, (void *)&I.gtiles[1], (void *)&c1,
                                 (void *)&out.stats};

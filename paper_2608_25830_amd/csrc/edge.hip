@@ -531,7 +531,10 @@ static hipError_t launch_point(const EdgeArgs &A, const ArmParams &R, const Scen
     }
 }
 
-static int persistent_grid(const void *kernel, int block, int blocks_per_cu_req) {
+// Resident blocks of a persistent launch: the request, else the occupancy
+// limit capped at auto_cap (cheap states make the tile cursor a point of
+// contention when every resident wave claims tiles from it).
+static int persistent_grid(const void *kernel, int block, int blocks_per_cu_req, int auto_cap = 1 << 20) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
@@ -541,10 +544,15 @@ static int persistent_grid(const void *kernel, int block, int blocks_per_cu_req)
     if (per_cu <= 0) {
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0) != hipSuccess || occ <= 0) occ = 2;
-        per_cu = occ;
+        per_cu = occ < auto_cap ? occ : auto_cap;
     }
     return cus * per_cu;
 }
+
+// automatic launch shape of the point-robot interior kernel (measured on the
+// 2D workload with 50 circles and 20 boxes: 8 states per lane, 3 blocks per CU)
+constexpr int kPointSpiAuto = 8;
+constexpr int kPointBlocksPerCuAuto = 3;
 
 hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s) {
@@ -632,21 +640,21 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
         }
     }
     int spi = o.states_per_iter;
-    if (spi <= 0) spi = 4;
+    if (spi <= 0) spi = kPointSpiAuto;
     if (spi != 1 && spi != 2 && spi != 4) spi = 8;
     if (wdim == 2) {
         const void *kern = spi == 1 ? (const void *)k_interior<PointModel<2, 1>, true, 1>
                          : spi == 2 ? (const void *)k_interior<PointModel<2, 2>, true, 1>
                          : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true, 1>
                                     : (const void *)k_interior<PointModel<2, 8>, true, 1>;
-        const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
+        const int grid = persistent_grid(kern, 256, o.blocks_per_cu, kPointBlocksPerCuAuto);
         return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag);
     }
     const void *kern = spi == 1 ? (const void *)k_interior<PointModel<3, 1>, true, 1>
                      : spi == 2 ? (const void *)k_interior<PointModel<3, 2>, true, 1>
                      : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true, 1>
                                 : (const void *)k_interior<PointModel<3, 8>, true, 1>;
-    const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
+    const int grid = persistent_grid(kern, 256, o.blocks_per_cu, kPointBlocksPerCuAuto);
     return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag);
 }
 
