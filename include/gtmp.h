@@ -356,6 +356,48 @@ gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_b
                             int32_t stage_stride, void *workspace, size_t ws_bytes, void *stream);
 
 
+/* ------------------------------------- class-augmented sweep (2D robots) */
+/* Class-augmented value iteration (Sec. IV-B; Prop. 2) and the class-indexed
+ * archive of Anytime-GTMP (Sec. IV-D) for point robots in the plane (d = 2).
+ *
+ * Class label: for each of k <= 16 representative points z_i (one inside
+ * each obstacle that separates classes) the signed number of crossings of the
+ * path with the upward ray {(z_x, y): y > z_y}, +1 moving in +x.  Labels add
+ * along concatenation, and two start-to-goal paths avoiding the obstacles
+ * have equal labels iff they wind equally around every z_i (the discrete form
+ * of the h-signature).  Packed: field i = bits 4i..4i+3 of a uint64, value
+ * (count + 8) for chains of at most 7 edges (M <= 6), fields past k at 8.
+ * The crossing decision is FP32 with a fixed order: u, v straddle z_x
+ * ((u_x < z_x) != (v_x < z_x)) and the crossing lies above z, i.e.
+ * cr = fl(fl(dx * ey) - fl(dy * ex)) < 0 when dx > 0, > 0 when dx < 0, with
+ * dx = v_x - u_x, dy = v_y - u_y, ex = z_x - u_x, ey = z_y - u_y.
+ *
+ * Sweep: for every vertex the least cost of a chain to a goal per label,
+ * keeping at most L <= 64 labels per vertex (a full list keeps the L
+ * cheapest; *overflow counts dropped labels: the result is exact when it is
+ * 0).  Edges with cost >= penalty are absent.  Outputs for the start vertex:
+ * labels [L], costs [L], chains [L][M+1] (layer indices, then the goal),
+ * count [1] (classes found); device pointers; reps device float [k][2]. */
+gtmp_status gtmp_class_sweep_workspace_size(int32_t M, int32_t N, int32_t L, size_t *bytes);
+gtmp_status gtmp_class_sweep(int32_t M, int32_t N, int32_t G, int32_t L, const float *Q, const float *q0,
+                             const float *goals, const float *C_s, const float *C_h, const float *C_l, float penalty,
+                             const float *reps, int32_t k, uint64_t *labels, float *costs, int32_t *chains,
+                             int32_t *count, uint32_t *overflow, void *workspace, size_t ws_bytes, void *stream);
+
+/* Anytime-GTMP with the class archive: `stages` restart stages (samples of
+ * key (seed, stage), edge check, class sweep), each class's best path kept
+ * (a later stage replaces an entry only with a strictly lower cost).  Archive
+ * (device, capacity cap): a_labels [cap], a_costs [cap], a_stage [cap],
+ * a_wp [cap][M+2][2] waypoints, a_count [1]; overflow [1] counts labels
+ * dropped by full vertex lists or a full archive.  prob->d must be 2 and
+ * scene->wdim 2 (point robot). */
+gtmp_status gtmp_class_anytime_workspace_size(const gtmp_problem *prob, int32_t L, size_t *bytes);
+gtmp_status gtmp_plan_classes(const gtmp_problem *prob, const gtmp_scene *scene, const float *q0, const float *goals,
+                              uint64_t seed, int32_t stages, const float *reps, int32_t k, int32_t L, int32_t cap,
+                              uint64_t *a_labels, float *a_costs, int32_t *a_stage, float *a_wp, int32_t *a_count,
+                              uint32_t *overflow, void *workspace, size_t ws_bytes, const gtmp_edge_opts *edge_opts,
+                              void *stream);
+
 /* ------------------------------------------------- a9 learned surrogate */
 /* A small ReLU MLP that predicts whether a configuration collides, used only
  * to prune edges before the exact check and to bias the heuristic half of

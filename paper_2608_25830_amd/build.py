@@ -30,10 +30,12 @@ FLAGS = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
-SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip", "batch.hip", "surrogate.hip"]
-# the growing-budget sampler is defined as an FP32 computation with a fixed
-# operation order: no contraction into fused multiply-adds in that file
-EXTRA = {"anytime.hip": ["-ffp-contract=off"]}
+SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip", "batch.hip", "surrogate.hip",
+           "classes.hip"]
+# the growing-budget sampler and the class labels are defined as FP32
+# computations with a fixed operation order: no contraction into fused
+# multiply-adds in those files
+EXTRA = {"anytime.hip": ["-ffp-contract=off"], "classes.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

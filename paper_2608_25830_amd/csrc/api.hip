@@ -579,4 +579,87 @@ gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate 
                       "gtmp_surrogate_prune");
 }
 
+// ------------------------------------------------------------------ class-augmented sweep
+static gtmp_status check_class_sizes(int M, int N, int G, int L, int k) {
+    if (M < 1 || M > 6) return fail(GTMP_EINVAL, "class sweep needs 1 <= M <= 6 (labels of at most 7 edges)");
+    if (N < 1 || N >= (1 << 24) || G < 1 || G >= (1 << 24)) return fail(GTMP_EINVAL, "N=%d G=%d out of range", N, G);
+    if (L < 1 || L > 64) return fail(GTMP_EINVAL, "L=%d outside 1..64", L);
+    if (k < 0 || k > 16) return fail(GTMP_EINVAL, "k=%d outside 0..16 representative points", k);
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_class_sweep_workspace_size(int32_t M, int32_t N, int32_t L, size_t *bytes) {
+    g_err[0] = 0;
+    gtmp_status st = check_class_sizes(M, N, 1, L, 0);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::make_class_plan(M, N, L).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_class_sweep(int32_t M, int32_t N, int32_t G, int32_t L, const float *Q, const float *q0,
+                             const float *goals, const float *C_s, const float *C_h, const float *C_l, float penalty,
+                             const float *reps, int32_t k, uint64_t *labels, float *costs, int32_t *chains,
+                             int32_t *count, uint32_t *overflow, void *workspace, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_class_sizes(M, N, G, L, k);
+    if (st != GTMP_OK) return st;
+    if (!Q || !q0 || !goals || !C_s || !C_l || !labels || !costs || !chains || !count || !overflow || !workspace ||
+        (k > 0 && !reps) || (M > 1 && !C_h))
+        return fail(GTMP_EINVAL, "NULL buffer");
+    if (!(penalty > 0.f)) return fail(GTMP_EINVAL, "penalty must be > 0");
+    const size_t need = gtmp::make_class_plan(M, N, L).total;
+    if (ws_bytes < need) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    return hip_status(gtmp::launch_class_sweep(M, N, G, L, Q, q0, goals, C_s, C_h, C_l, penalty, reps, k, labels, costs,
+                                               chains, count, overflow, true, workspace, (hipStream_t)stream),
+                      "gtmp_class_sweep");
+}
+
+gtmp_status gtmp_class_anytime_workspace_size(const gtmp_problem *prob, int32_t L, size_t *bytes) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (prob->d != 2) return fail(GTMP_EINVAL, "class archive needs d = 2");
+    st = check_class_sizes(prob->M, prob->N, prob->G, L, 0);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::make_class_anytime_plan(*prob, L).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_plan_classes(const gtmp_problem *prob, const gtmp_scene *scene, const float *q0, const float *goals,
+                              uint64_t seed, int32_t stages, const float *reps, int32_t k, int32_t L, int32_t cap,
+                              uint64_t *a_labels, float *a_costs, int32_t *a_stage, float *a_wp, int32_t *a_count,
+                              uint32_t *overflow, void *workspace, size_t ws_bytes, const gtmp_edge_opts *edge_opts,
+                              void *stream) {
+    g_err[0] = 0;
+    size_t need = 0;
+    gtmp_status st = gtmp_class_anytime_workspace_size(prob, L, &need);
+    if (st != GTMP_OK) return st;
+    st = check_class_sizes(prob->M, prob->N, prob->G, L, k);
+    if (st != GTMP_OK) return st;
+    gtmp::ArmParams arm{};
+    gtmp::SceneParams sp{};
+    bool is_arm = false;
+    gtmp_robot point{};
+    point.kind = GTMP_ROBOT_POINT;
+    st = check_model(&point, scene, prob->d, &arm, &is_arm, &sp);
+    if (st != GTMP_OK) return st;
+    if (scene->wdim != 2) return fail(GTMP_EINVAL, "class archive needs a 2D scene");
+    if (stages < 1) return fail(GTMP_EINVAL, "stages=%d < 1", stages);
+    if (cap < 1) return fail(GTMP_EINVAL, "cap=%d < 1", cap);
+    if (!q0 || !goals || !a_labels || !a_costs || !a_stage || !a_wp || !a_count || !overflow || !workspace ||
+        (k > 0 && !reps))
+        return fail(GTMP_EINVAL, "NULL buffer");
+    if (ws_bytes < need) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    gtmp_edge_opts eo{};
+    if (edge_opts) eo = *edge_opts;
+    eo.mode = GTMP_CHECK_FAST;
+    return hip_status(gtmp::launch_plan_classes(*prob, sp, q0, goals, seed, stages, reps, k, L, cap, a_labels, a_costs,
+                                                a_stage, a_wp, a_count, overflow, eo, workspace, (hipStream_t)stream),
+                      "gtmp_plan_classes");
+}
+
 }  // extern "C"

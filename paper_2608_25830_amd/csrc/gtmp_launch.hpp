@@ -99,6 +99,28 @@ hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const Sce
                           const gtmp_edge_opts &eo, const AnytimeOut &out, void *workspace, hipStream_t s,
                           const SurNet *bias = nullptr);
 
+// ---- class-augmented sweep and class archive (classes.hip)
+struct ClassPlan {
+    size_t off_lab, off_cost, off_nxt, off_cnt, off_s, total;
+};
+ClassPlan make_class_plan(int M, int N, int L);
+hipError_t launch_class_sweep(int M, int N, int G, int L, const float *Q, const float *q0, const float *goals,
+                              const float *C_s, const float *C_h, const float *C_l, float penalty, const float *reps,
+                              int k, uint64_t *labels, float *costs, int32_t *chains, int32_t *count,
+                              uint32_t *overflow, bool reset_overflow, void *ws, hipStream_t s);
+hipError_t launch_class_archive(int M, int N, int stage, const float *Q, const float *q0, const float *goals,
+                                const uint64_t *labels, const float *costs, const int32_t *chains,
+                                const int32_t *count, int cap, uint64_t *a_lab, float *a_cost, int32_t *a_stage,
+                                float *a_wp, int32_t *a_count, uint32_t *overflow, hipStream_t s);
+struct ClassAnytimePlan {
+    size_t off_Q, off_Cs, off_Ch, off_Cl, off_out, off_edge, off_class, total;
+};
+ClassAnytimePlan make_class_anytime_plan(const gtmp_problem &p, int L);
+hipError_t launch_plan_classes(const gtmp_problem &p, const SceneParams &scene, const float *q0, const float *goals,
+                               uint64_t seed, int stages, const float *reps, int k, int L, int cap, uint64_t *a_lab,
+                               float *a_cost, int32_t *a_stage, float *a_wp, int32_t *a_count, uint32_t *overflow,
+                               const gtmp_edge_opts &eo, void *workspace, hipStream_t s);
+
 // ---- batched plans (batch.hip)
 struct StageShape {
     int M, N, n_old;

@@ -135,13 +135,22 @@ _lib.gtmp_surrogate_label_states.argtypes = [C.POINTER(gtmp_problem), C.c_uint64
 _lib.gtmp_surrogate_prune.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_surrogate), _vp, _vp, _vp, C.c_float,
                                       _vp, _vp, _vp, C.c_size_t, _vp]
 
+_lib.gtmp_class_sweep_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+_lib.gtmp_class_sweep.argtypes = [C.c_int32] * 4 + [_vp] * 6 + [C.c_float, _vp, C.c_int32] + [_vp] * 5 + \
+    [_vp, C.c_size_t, _vp]
+_lib.gtmp_class_anytime_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.c_int32, C.POINTER(C.c_size_t)]
+_lib.gtmp_plan_classes.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_scene), _vp, _vp, C.c_uint64, C.c_int32,
+                                   _vp, C.c_int32, C.c_int32, C.c_int32] + [_vp] * 7 + [C.c_size_t, _vp, _vp]
+
 EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample_layers",
            "gtmp_edge_check_workspace_size", "gtmp_edge_check_cost", "gtmp_state_check", "gtmp_minplus_sweep",
            "gtmp_extract_path", "gtmp_expand_workspace_size", "gtmp_expand_samples", "gtmp_sample_informed",
            "gtmp_anytime_workspace_size", "gtmp_plan_anytime", "gtmp_batch_workspace_size", "gtmp_plan_batch",
            "gtmp_surrogate_layout", "gtmp_surrogate_refresh_bf16", "gtmp_surrogate_workspace_size",
            "gtmp_surrogate_infer", "gtmp_surrogate_grad", "gtmp_surrogate_adam", "gtmp_surrogate_label_states",
-           "gtmp_surrogate_prune", "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased"]
+           "gtmp_surrogate_prune", "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased",
+           "gtmp_class_sweep_workspace_size", "gtmp_class_sweep", "gtmp_class_anytime_workspace_size",
+           "gtmp_plan_classes"]
 
 
 def _check(st):
@@ -687,3 +696,82 @@ def free_recall_threshold(logits, flags, recall=0.999):
         return math.inf
     k = max(0, min(zf.numel() - 1, math.ceil(recall * zf.numel()) - 1))
     return float(zf[k].item())
+
+
+# --------------------------------------------------------------------------- #
+# class-augmented sweep and class archive (2D point robots)
+# --------------------------------------------------------------------------- #
+def unpack_label(lab, k):
+    """Packed class label -> tuple of k signed crossing counts."""
+    lab = int(lab) & 0xFFFFFFFFFFFFFFFF
+    return tuple(((lab >> (4 * i)) & 15) - 8 for i in range(k))
+
+
+def gtmp_class_sweep_workspace_size(M, N, L) -> int:
+    n = C.c_size_t()
+    _check(_lib.gtmp_class_sweep_workspace_size(M, N, L, C.byref(n)))
+    return n.value
+
+
+def class_sweep(pl: "Planner", reps, L=64, stream=None):
+    """Class-augmented sweep on a planner's current samples and costs.
+    Returns (dict label -> (cost, chain), overflow)."""
+    reps_t = torch.from_numpy(np.ascontiguousarray(reps, np.float32).reshape(-1, 2)).to(pl.Q.device)
+    k = reps_t.shape[0]
+    dev = pl.Q.device
+    labels = torch.empty(L, device=dev, dtype=torch.int64)
+    costs = torch.empty(L, device=dev)
+    chains = torch.empty((L, pl.M + 1), device=dev, dtype=torch.int32)
+    count = torch.zeros(1, device=dev, dtype=torch.int32)
+    overflow = torch.zeros(1, device=dev, dtype=torch.int32)
+    ws = _aligned_workspace(gtmp_class_sweep_workspace_size(pl.M, pl.N, L), dev)
+    _check(_lib.gtmp_class_sweep(pl.M, pl.N, pl.G, L, _p(pl.Q), _p(pl.q0), _p(pl.goals), _p(pl.C_s),
+                                 _p(pl.C_h) if pl.M > 1 else None, _p(pl.C_l), float(pl.w["penalty"]), _p(reps_t), k,
+                                 _p(labels), _p(costs), _p(chains), _p(count), _p(overflow), _p(ws), _nbytes(ws),
+                                 _stream(stream)))
+    n = int(count.item())
+    lab = labels.cpu().numpy()[:n]
+    cst = costs.cpu().numpy()[:n]
+    ch = chains.cpu().numpy()[:n]
+    out = {unpack_label(lab[i], k): (float(cst[i]), [int(x) for x in ch[i]]) for i in range(n)}
+    return out, int(overflow.item())
+
+
+class ClassPlanner:
+    """Anytime-GTMP with the class-indexed archive for a 2D point-robot
+    workload: ``stages`` restart stages, at most ``L`` labels per vertex and
+    ``cap`` archived classes."""
+
+    def __init__(self, w, reps, stages, L=64, cap=1024, device="cuda"):
+        assert w["kind"] == "point2d"
+        self.w = w
+        d, M, N, G, H = (int(w[k]) for k in ("d", "M", "N", "G", "H"))
+        self.M, self.k, self.L, self.cap, self.stages = M, len(reps), L, cap, stages
+        self.prob = make_problem(d, M, N, G, H, w["lo"], w["hi"], w["penalty"])
+        self.scene = Scene(2, w["circles"], w["boxes"], device)
+        self.q0 = torch.from_numpy(np.asarray(w["q0"], np.float32)).to(device)
+        self.goals = torch.from_numpy(np.asarray(w["goals"], np.float32).reshape(G, d)).to(device)
+        self.reps = torch.from_numpy(np.ascontiguousarray(reps, np.float32).reshape(-1, 2)).to(device)
+        self.a_lab = torch.zeros(cap, device=device, dtype=torch.int64)
+        self.a_cost = torch.zeros(cap, device=device)
+        self.a_stage = torch.zeros(cap, device=device, dtype=torch.int32)
+        self.a_wp = torch.zeros((cap, M + 2, 2), device=device)
+        self.a_count = torch.zeros(1, device=device, dtype=torch.int32)
+        self.overflow = torch.zeros(1, device=device, dtype=torch.int32)
+        n = C.c_size_t()
+        _check(_lib.gtmp_class_anytime_workspace_size(C.byref(self.prob), L, C.byref(n)))
+        self.workspace = _aligned_workspace(n.value, device)
+        self.edge_opts = gtmp_edge_opts()
+
+    def run(self, seed, stream=None):
+        _check(_lib.gtmp_plan_classes(C.byref(self.prob), C.byref(self.scene.c), _p(self.q0), _p(self.goals), seed,
+                                      self.stages, _p(self.reps), self.k, self.L, self.cap, _p(self.a_lab),
+                                      _p(self.a_cost), _p(self.a_stage), _p(self.a_wp), _p(self.a_count),
+                                      _p(self.overflow), _p(self.workspace), _nbytes(self.workspace),
+                                      C.byref(self.edge_opts), _stream(stream)))
+
+    def archive(self):
+        n = int(self.a_count.item())
+        lab = self.a_lab.cpu().numpy()[:n]
+        return {unpack_label(lab[i], self.k): (float(self.a_cost[i].item()), int(self.a_stage[i].item()),
+                                               self.a_wp[i].cpu().numpy()) for i in range(n)}

@@ -197,3 +197,20 @@ def test_anytime_and_batch_options_validate(g):
         assert g._lib.gtmp_batch_workspace_size(descs, 1, C.byref(bo2), C.byref(n)) == g.GTMP_EINVAL, field
     D.stages = 0
     assert g._lib.gtmp_batch_workspace_size(descs, 1, C.byref(bo), C.byref(n)) == g.GTMP_EINVAL
+
+
+def test_class_entry_points_validate(g):
+    n = C.c_size_t()
+    assert g._lib.gtmp_class_sweep_workspace_size(7, 16, 8, C.byref(n)) == g.GTMP_EINVAL  # M > 6
+    assert g._lib.gtmp_class_sweep_workspace_size(3, 16, 65, C.byref(n)) == g.GTMP_EINVAL  # L > 64
+    assert g._lib.gtmp_class_sweep_workspace_size(3, 16, 8, C.byref(n)) == g.GTMP_OK and n.value > 0
+    bufs = [C.c_void_p(256)] * 6
+    outs = [C.c_void_p(256)] * 5
+    assert g._lib.gtmp_class_sweep(3, 16, 1, 8, *bufs, 1e3, C.c_void_p(256), 17, *outs, C.c_void_p(1 << 20),
+                                   1 << 30, None) == g.GTMP_EINVAL  # k > 16
+    assert g._lib.gtmp_class_sweep(3, 16, 1, 8, *bufs, 1e3, C.c_void_p(256), 4, *outs, C.c_void_p(1 << 20),
+                                   16, None) == g.GTMP_EWORKSPACE
+    p3 = g.make_problem(3, 3, 8, 1, 6, [-1] * 3, [1] * 3, 1e3)
+    assert g._lib.gtmp_class_anytime_workspace_size(C.byref(p3), 8, C.byref(n)) == g.GTMP_EINVAL  # d != 2
+    p2 = _prob(g)
+    assert g._lib.gtmp_class_anytime_workspace_size(C.byref(p2), 8, C.byref(n)) == g.GTMP_OK
