@@ -98,6 +98,57 @@ def cpu_baseline(w, min_seconds=10.0, max_seconds=30.0):
                        f"all {H} states each, {el:.1f} s wall", plans_per_s=rate / (E * H))
 
 
+def bench_classes(args, torch, wl, gtmp):
+    """Anytime-GTMP with the class-indexed archive on the small 2D scene:
+    one step = one restart stage (sample, edge check, class-augmented sweep,
+    archive update); reports the classes archived after all stages next to
+    the plain restart policy on the same stages."""
+    w = wl.make_workload("2d-small", args.scene, N=args.classes_n)
+    reps = w["circles"][:, :2]
+    S = args.steps
+    cp = gtmp.ClassPlanner(w, reps, S, L=64, cap=4096)
+    cp.run(w["seed"])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    cp.run(w["seed"])
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / S
+    arch = cp.archive()
+    rp = gtmp.AnytimePlanner(w, gtmp.GTMP_ANYTIME_RESTART, S)
+    rp.run(w["seed"])
+    torch.cuda.synchronize()
+    a.record()
+    rp.run(w["seed"])
+    b.record()
+    b.synchronize()
+    ms_plain = a.elapsed_time(b) / S
+    costs = sorted(c for c, _, _ in arch.values())
+    out = {
+        "metric": "restart stages/s with the class-augmented sweep and class archive (2D)",
+        "value": 1e3 / ms,
+        "unit": "stages/s",
+        "n_gpus": 1,
+        "steps": S,
+        "warmup": 1,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2d-small scene seed {w['seed']}: M={w['M']}, N={w['N']}, H={w['H']}, "
+                               f"{len(reps)} class-defining circles, L=64 labels per vertex"},
+        "classes_archived": len(arch),
+        "overflow": int(cp.overflow.item()),
+        "best_cost": costs[0] if costs else None,
+        "median_class_cost": costs[len(costs) // 2] if costs else None,
+        "plain_restart_ms_per_stage": ms_plain,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_restart(args, torch, wl, gtmp):
     """Random-restart policy: one step = one stage = one whole plan on fresh
     samples (sample, edge check, sweep, extract, archive), the stage captured
@@ -316,7 +367,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="arm7")
-    ap.add_argument("--form", default="plain", choices=["plain", "batch", "surrogate", "restart"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batch", "surrogate", "restart", "classes"])
+    ap.add_argument("--classes-n", type=int, default=64, help="classes form: samples per layer")
     ap.add_argument("--no-graph", action="store_true", help="restart form: enqueue stages instead of replaying a graph")
     ap.add_argument("--labels", type=int, default=1 << 20, help="surrogate: label pairs (2x states)")
     ap.add_argument("--epochs", type=int, default=5, help="surrogate: training epochs")
@@ -356,6 +408,8 @@ def main():
         return bench_surrogate(args, torch, wl, gtmp)
     if args.form == "restart":
         return bench_restart(args, torch, wl, gtmp)
+    if args.form == "classes":
+        return bench_classes(args, torch, wl, gtmp)
     w = wl.make_workload(args.workload, args.scene)
     pl = gtmp.Planner(w)
     for kv in args.opt:
