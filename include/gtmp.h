@@ -181,6 +181,30 @@ gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *rob
 gtmp_status gtmp_state_check(const gtmp_robot *robot, const gtmp_scene *scene, int32_t d, int64_t n,
                              const float *X, float *sd, uint8_t *coll, void *stream);
 
+/* ------------------------------------------------- path shortcutting */
+/* Shortcutting of planned paths, simp() of Alg. 1 ao-gtmp (Sec. IV-E); the
+ * paper uses it without a definition.  Reading implemented: for each of B
+ * paths of K waypoints w_0 .. w_{K-1}, the shortcut w_i -> w_j (i < j) passes
+ * iff none of its H_ij = (j - i)(H - 1) + 1 states w_i + (h/(H_ij - 1))
+ * (w_j - w_i), h = 0 .. H_ij - 1 (endpoints exact), collides, with the state
+ * test of gtmp_state_check; a consecutive pair is thus tested at the plan's
+ * own H states.  The simplified path is the shortest chain w_0 -> w_{K-1}
+ * over passing shortcuts, lengths |w_j - w_i| in FP32 as the edge check
+ * computes them, summed from the goal backwards; among equal costs the
+ * lowest next index.  A waypoint with a non-finite coordinate fails every
+ * shortcut that starts or ends at it.
+ *   wp      device float32 [B][K][d], the paths (e.g. gtmp_extract_path's wp)
+ *   valid   device uint8 [B][K][K], written: 1 iff i < j and w_i -> w_j passes
+ *   idx     device int32 [B][K]: waypoint indices of the simplified path, then -1
+ *   count   device int32 [B]: waypoints kept (0 when no chain passes)
+ *   cost    device float32 [B]: its length (+inf when count is 0)
+ *   out_wp  device float32 [B][K][d] or NULL: the kept waypoints, then NaN
+ * Sizes: 2 <= K <= 64, 2 <= H <= GTMP_MAX_H, B K^2 <= 2^31; robot and scene
+ * as for gtmp_edge_check_cost with d the configuration dimension. */
+gtmp_status gtmp_simplify_paths(const gtmp_robot *robot, const gtmp_scene *scene, int32_t d, int32_t B, int32_t K,
+                                int32_t H, const float *wp, uint8_t *valid, int32_t *idx, int32_t *count, float *cost,
+                                float *out_wp, void *stream);
+
 /* --------------------------------------------------- a5 min-plus sweep */
 /* Backward value iteration on the layered DAG (Sec. IV-B; Alg. 1):
  *   V[M-1][u] = min_g C_l[u][g] + V_g[g]

@@ -31,7 +31,7 @@ FLAGS = [
 ]
 
 SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip", "batch.hip", "surrogate.hip",
-           "classes.hip"]
+           "classes.hip", "simplify.hip"]
 # the growing-budget sampler and the class labels are defined as FP32
 # computations with a fixed operation order: no contraction into fused
 # multiply-adds in those files

@@ -200,6 +200,26 @@ gtmp_status gtmp_state_check(const gtmp_robot *robot, const gtmp_scene *scene, i
                       "gtmp_state_check");
 }
 
+gtmp_status gtmp_simplify_paths(const gtmp_robot *robot, const gtmp_scene *scene, int32_t d, int32_t B, int32_t K,
+                                int32_t H, const float *wp, uint8_t *valid, int32_t *idx, int32_t *count, float *cost,
+                                float *out_wp, void *stream) {
+    g_err[0] = 0;
+    if (d < 1 || d > GTMP_MAX_DOF) return fail(GTMP_EINVAL, "d=%d", d);
+    if (B < 0) return fail(GTMP_EINVAL, "B=%d < 0", B);
+    if (K < 2 || K > 64) return fail(GTMP_EINVAL, "K=%d outside 2..64", K);
+    if (H < 2 || H > GTMP_MAX_H) return fail(GTMP_EINVAL, "H=%d outside 2..%d", H, GTMP_MAX_H);
+    if ((long long)B * K * K > (1ll << 31)) return fail(GTMP_EINVAL, "B K^2 = %lld too large", (long long)B * K * K);
+    gtmp::ArmParams arm{};
+    gtmp::SceneParams sp{};
+    bool is_arm = false;
+    gtmp_status st = check_model(robot, scene, d, &arm, &is_arm, &sp);
+    if (st != GTMP_OK) return st;
+    if (B > 0 && (!wp || !valid || !idx || !count || !cost)) return fail(GTMP_EINVAL, "NULL buffer");
+    return hip_status(gtmp::launch_simplify(is_arm ? &arm : nullptr, sp, scene->wdim, d, B, K, H, wp, valid, idx, count,
+                                            cost, out_wp, (hipStream_t)stream),
+                      "gtmp_simplify_paths");
+}
+
 gtmp_status gtmp_minplus_sweep(int32_t M, int32_t N, int32_t G, const float *C_s, const float *C_h, const float *C_l,
                                const float *Vg, float *V, int32_t *A, float *V_s, int32_t *a_s, void *stream) {
     g_err[0] = 0;

@@ -121,6 +121,11 @@ hipError_t launch_plan_classes(const gtmp_problem &p, const SceneParams &scene, 
                                float *a_cost, int32_t *a_stage, float *a_wp, int32_t *a_count, uint32_t *overflow,
                                const gtmp_edge_opts &eo, void *workspace, hipStream_t s);
 
+// ---- path shortcutting (simplify.hip)
+hipError_t launch_simplify(const ArmParams *arm, const SceneParams &scene, int wdim, int d, int B, int K, int H,
+                           const float *wp, uint8_t *valid, int32_t *idx, int32_t *count, float *cost, float *out_wp,
+                           hipStream_t s);
+
 // ---- batched plans (batch.hip)
 struct StageShape {
     int M, N, n_old;

@@ -76,6 +76,8 @@ _lib.gtmp_edge_check_cost.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_ro
                                       C.POINTER(gtmp_edge_opts), _vp]
 _lib.gtmp_state_check.argtypes = [C.POINTER(gtmp_robot), C.POINTER(gtmp_scene), C.c_int32, C.c_int64, _vp, _vp,
                                   _vp, _vp]
+_lib.gtmp_simplify_paths.argtypes = [C.POINTER(gtmp_robot), C.POINTER(gtmp_scene), C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_int32] + [_vp] * 7
 _lib.gtmp_minplus_sweep.argtypes = [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.gtmp_extract_path.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    _vp, _vp, _vp]
@@ -150,7 +152,7 @@ EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample
            "gtmp_surrogate_infer", "gtmp_surrogate_grad", "gtmp_surrogate_adam", "gtmp_surrogate_label_states",
            "gtmp_surrogate_prune", "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased",
            "gtmp_class_sweep_workspace_size", "gtmp_class_sweep", "gtmp_class_anytime_workspace_size",
-           "gtmp_plan_classes"]
+           "gtmp_plan_classes", "gtmp_simplify_paths"]
 
 
 def _check(st):
@@ -259,6 +261,27 @@ def gtmp_state_check(robot, scene: Scene, d, X, sd=None, coll=None, stream=None)
     n = X.shape[0] if X is not None else 0
     return _check(_lib.gtmp_state_check(C.byref(robot), C.byref(scene.c), int(d), int(n), _p(X), _p(sd), _p(coll),
                                         _stream(stream)))
+
+
+def gtmp_simplify_paths(robot, scene: Scene, d, H, wp, valid, idx, count, cost, out_wp=None, stream=None):
+    B, K = (int(wp.shape[0]), int(wp.shape[1])) if wp is not None else (0, 2)
+    return _check(_lib.gtmp_simplify_paths(C.byref(robot), C.byref(scene.c), int(d), B, K, int(H), _p(wp), _p(valid),
+                                           _p(idx), _p(count), _p(cost), _p(out_wp), _stream(stream)))
+
+
+def simplify_paths(robot, scene: Scene, d, H, wp, stream=None):
+    """Shortcut B paths (wp [B][K][d] on the device).  Returns a dict of
+    device tensors: valid [B][K][K], idx [B][K], count [B], cost [B], wp [B][K][d]."""
+    wp = wp.contiguous()
+    B, K = wp.shape[0], wp.shape[1]
+    dev = wp.device
+    out = dict(valid=torch.empty((B, K, K), device=dev, dtype=torch.uint8),
+               idx=torch.empty((B, K), device=dev, dtype=torch.int32),
+               count=torch.empty((B,), device=dev, dtype=torch.int32),
+               cost=torch.empty((B,), device=dev, dtype=torch.float32),
+               wp=torch.empty((B, K, d), device=dev, dtype=torch.float32))
+    gtmp_simplify_paths(robot, scene, d, H, wp, out["valid"], out["idx"], out["count"], out["cost"], out["wp"], stream)
+    return out
 
 
 def gtmp_minplus_sweep(M, N, G, C_s, C_h, C_l, V, A, V_s, a_s, Vg=None, stream=None):
@@ -400,6 +423,11 @@ class Planner:
         self.sweep(stream)
         self.extract(stream)
         return self.result()
+
+    def simplify(self, wp=None, stream=None):
+        """Shortcut the extracted path (or the paths wp [B][M+2][d])."""
+        wp = self.wp.unsqueeze(0) if wp is None else wp
+        return simplify_paths(self.robot, self.scene, self.d, self.H, wp, stream)
 
     def result(self) -> PlanResult:
         return PlanResult(self.Q, self.C_s, self.C_h, self.C_l, self.V, self.A, self.V_s, self.a_s, self.idx, self.wp,

@@ -214,3 +214,22 @@ def test_class_entry_points_validate(g):
     assert g._lib.gtmp_class_anytime_workspace_size(C.byref(p3), 8, C.byref(n)) == g.GTMP_EINVAL  # d != 2
     p2 = _prob(g)
     assert g._lib.gtmp_class_anytime_workspace_size(C.byref(p2), 8, C.byref(n)) == g.GTMP_OK
+
+
+def test_simplify_validates(g):
+    scene = g.gtmp_scene()
+    scene.wdim = 2
+    robot = g.make_point_robot()
+    bufs = [C.c_void_p(256)] * 4  # valid, idx, count, cost
+    call = lambda d, B, K, H, wp=C.c_void_p(256), b=bufs: g._lib.gtmp_simplify_paths(
+        C.byref(robot), C.byref(scene), d, B, K, H, wp, *b, None, None)
+    assert call(2, 4, 1, 8) == g.GTMP_EINVAL  # K < 2
+    assert call(2, 4, 65, 8) == g.GTMP_EINVAL  # K > 64
+    assert call(2, 4, 8, 1) == g.GTMP_EINVAL  # H < 2
+    assert call(2, 4, 8, 257) == g.GTMP_EINVAL  # H > max
+    assert call(2, -1, 8, 8) == g.GTMP_EINVAL
+    assert call(2, 1 << 30, 8, 8) == g.GTMP_EINVAL  # B K^2 too large
+    assert call(3, 4, 8, 8) == g.GTMP_EINVAL  # point robot needs d == wdim
+    assert call(2, 4, 8, 8, wp=None) == g.GTMP_EINVAL
+    assert call(2, 4, 8, 8, b=[C.c_void_p(256)] * 3 + [None]) == g.GTMP_EINVAL  # cost NULL
+    assert call(2, 0, 8, 8, wp=None, b=[None] * 4) == g.GTMP_OK  # nothing to do

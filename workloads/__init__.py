@@ -250,6 +250,28 @@ def batch_specs(n: int = BATCH["n"], seed: int = 0, N_choices=BATCH["N"], M_rang
 
 
 # --------------------------------------------------------------------------- #
+# paths to shortcut
+# --------------------------------------------------------------------------- #
+def random_paths(w, B: int, K: int, seed: int = 0, spread: float = 1.0):
+    """B seeded paths of K waypoints from the workload's start to its first
+    goal: waypoint k is the point k/(K-1) of the way along the straight line
+    plus a perturbation uniform in +-spread/2 of the box width per axis,
+    clipped to the box (spread 1 gives waypoints anywhere in the box).
+    float32 [B][K][d]."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x5137, seed]))
+    d = int(w["d"])
+    lo, hi = np.asarray(w["lo"], np.float64)[:d], np.asarray(w["hi"], np.float64)[:d]
+    q0 = np.asarray(w["q0"], np.float64).reshape(d)
+    qg = np.asarray(w["goals"], np.float64).reshape(-1, d)[0]
+    t = np.linspace(0.0, 1.0, K)[None, :, None]
+    base = q0 + t * (qg - q0)
+    noise = rng.uniform(-0.5, 0.5, (B, K, d)) * spread * (hi - lo)
+    P = np.clip(base + noise, lo, hi)
+    P[:, 0], P[:, -1] = q0, qg
+    return P.astype(np.float32)
+
+
+# --------------------------------------------------------------------------- #
 # learned collision surrogate: initial parameters and Fourier frequencies
 # --------------------------------------------------------------------------- #
 SURROGATE = dict(width=256, depth=4, n_freq=16, in_pad=64, batch=8192, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
