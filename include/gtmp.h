@@ -297,6 +297,8 @@ typedef struct gtmp_anytime_opts {
     float bias_tau;             /* growing: logit threshold of the surrogate bias */
     const struct gtmp_surrogate *bias_net; /* growing: surrogate biasing the heuristic half
                                               (gtmp_expand_samples_biased), NULL = off */
+    int32_t simplify;           /* nonzero: shortcut each stage's path (simp() of Alg. 1, by
+                                   gtmp_simplify_paths); needs M + 2 <= 64 (M_max + 2 growing) */
 } gtmp_anytime_opts;
 
 /* Bytes of device workspace gtmp_plan_anytime needs (sizes of prob for a
@@ -317,7 +319,17 @@ gtmp_status gtmp_anytime_workspace_size(const gtmp_problem *prob, const gtmp_any
  * [(M_max + 2) d] for the best stage's (M); best_meta [4] = (best stage, its
  * M, its N, stages run); stage_costs [max_stages].  prob->M, N give the
  * restart sizes; prob->G, H, d, box and penalty apply to both.  The whole
- * loop is enqueued on `stream` with no host synchronisation. */
+ * loop is enqueued on `stream` with no host synchronisation.
+ * With opts->simplify the archive holds shortcut paths (Alg. 1): restart
+ * compares the stage path's cost with the archived cost and, when lower,
+ * stores the shortcut of the stage path; growing shortcuts every stage path
+ * first and compares shortcut lengths, so the informed sampler is bounded by
+ * the best shortcut length.  A stage path that no shortcut chain realises
+ * (one through failed edges) is never stored.  best_cost is then the stored
+ * shortcut's length, best_wp its waypoints followed by NaN rows, best_idx
+ * the layer indices of the stage path it was cut from, and stage_costs[s]
+ * the cost compared at stage s (restart: the stage path's; growing: its
+ * shortcut's, +inf when none). */
 gtmp_status gtmp_plan_anytime(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
                               const float *q0, const float *goals, uint64_t seed, const gtmp_anytime_opts *opts,
                               float *best_cost, int32_t *best_idx, float *best_wp, int32_t *best_meta,

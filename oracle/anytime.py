@@ -10,6 +10,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle as O
+import oracle.simplify as OSI
 
 MAX_ATTEMPTS = 4096
 # biased heuristic half: the closest pairs scored by the surrogate per new
@@ -126,10 +127,21 @@ def _plan_on(w, Qarr):
     return O.plan(ww, Q=Qarr)
 
 
-def plan_restart(w, stages, seed):
+def _shortcut(w, r):
+    """simp() of the stage path r (oracle/simplify.py): (kept waypoints or
+    None, shortcut length, +inf when no chain passes)."""
+    wp = np.asarray(r["wp"], np.float32)
+    kept, c, _, _ = OSI.simplify(O.Model(w), wp, int(w["H"]))
+    return (None, np.inf) if kept is None else (wp[kept], c)
+
+
+def plan_restart(w, stages, seed, simplify=False):
     """Anytime-GTMP (Alg. 1; Sec. IV-D) with |K| = 1: stage s plans on the
     samples of key (seed, s); the archive keeps the lowest cost (strictly
-    lower replaces, so ties keep the earlier stage)."""
+    lower replaces, so ties keep the earlier stage).  With ``simplify`` a
+    stage path whose cost is below the archived cost is stored shortcut
+    (Alg. 1: the archive entry becomes simp() of the path), and only when a
+    shortcut chain exists."""
     best = dict(cost=np.inf, stage=-1, idx=None)
     per_stage = []
     for s in range(stages):
@@ -137,7 +149,12 @@ def plan_restart(w, stages, seed):
         r = _plan_on(w, Q)
         per_stage.append(r["path_cost"])
         if r["path_cost"] < best["cost"]:
-            best = dict(cost=r["path_cost"], stage=s, idx=r["idx"].copy(), M=w["M"], N=w["N"])
+            if not simplify:
+                best = dict(cost=r["path_cost"], stage=s, idx=r["idx"].copy(), M=w["M"], N=w["N"])
+                continue
+            wp, c = _shortcut(w, r)
+            if wp is not None:
+                best = dict(cost=c, stage=s, idx=r["idx"].copy(), M=w["M"], N=w["N"], wp=wp)
     return best, per_stage
 
 
@@ -158,10 +175,12 @@ def growing_schedule(M_min, M_max, N_min, N_max, max_stages):
     return out
 
 
-def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None, trace=None):
+def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None, trace=None, simplify=False):
     """AO-GTMP (Alg. 1; Sec. IV-E): expand the samples under the current
     cost bound, plan, keep the best, grow the budget (``bias`` as in
-    expand_samples)."""
+    expand_samples).  With ``simplify`` every stage path is shortcut first
+    (Alg. 1: P_i = simp(gtmp(...))) and the shortcut lengths are compared,
+    so the best shortcut length bounds the informed sampler."""
     d = w["d"]
     best = dict(cost=np.inf, stage=-1, idx=None)
     per_stage, stages = [], []
@@ -172,8 +191,13 @@ def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None, tra
         Q = expand_samples(w, Q, M, N, best["cost"], seed, s, bias, trace)
         Qarr = np.stack(Q).astype(np.float32)
         r = _plan_on(w, Qarr)
-        per_stage.append(r["path_cost"])
-        stages.append(dict(M=M, N=N, Q=Qarr, cost=r["path_cost"], bound=best["cost"]))
-        if r["path_cost"] < best["cost"]:
-            best = dict(cost=r["path_cost"], stage=s, idx=r["idx"].copy(), M=M, N=N)
+        c, wp = r["path_cost"], None
+        if simplify:
+            ww = dict(w)
+            ww["M"], ww["N"] = M, N
+            wp, c = _shortcut(ww, r)
+        per_stage.append(c)
+        stages.append(dict(M=M, N=N, Q=Qarr, cost=c, bound=best["cost"]))
+        if c < best["cost"]:
+            best = dict(cost=c, stage=s, idx=r["idx"].copy(), M=M, N=N, wp=wp)
     return best, per_stage, stages

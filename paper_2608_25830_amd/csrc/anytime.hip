@@ -446,17 +446,24 @@ __global__ void __launch_bounds__(256) k_sample_dev_stage(int M, int N, int d, u
 // Archive update of the anytime policies with |K| = 1 (Alg. 1; Sec. IV-D):
 // the best path so far; strictly better costs replace it, so ties keep the
 // earlier stage.  Also records the stage's cost and advances the counter.
+// Archive update of the single-class anytime loops.  Without shortcutting
+// (s_cost == NULL) the stage path replaces the archived one iff its cost is
+// strictly lower.  With shortcutting the compared cost is the stage path's
+// (cmp_short == 0, the restart loop) or its shortcut's (cmp_short == 1, the
+// growing loop), and what is stored is the shortcut, if one exists.
 __global__ void k_archive(int M, int N, int d, const float *cost, const int32_t *idx, const float *wp,
-                          float *best_cost, int32_t *best_idx, float *best_wp, int32_t *best_meta, float *stage_costs,
-                          uint32_t *counter, int max_stages) {
+                          const float *s_cost, const float *s_wp, int cmp_short, float *best_cost, int32_t *best_idx,
+                          float *best_wp, int32_t *best_meta, float *stage_costs, uint32_t *counter, int max_stages) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const uint32_t stage = *counter;
-    const float c = *cost;
+    const float c = s_cost && cmp_short ? *s_cost : *cost;
     if ((int)stage < max_stages) stage_costs[stage] = c;
-    if (c < *best_cost) {
-        *best_cost = c;
+    const bool store = c < *best_cost && (!s_cost || *s_cost < __builtin_inff());
+    if (store) {
+        *best_cost = s_cost ? *s_cost : c;
+        const float *src = s_cost ? s_wp : wp;
         for (int m = 0; m <= M; ++m) best_idx[m] = idx[m];
-        for (int k = 0; k < (M + 2) * d; ++k) best_wp[k] = wp[k];
+        for (int k = 0; k < (M + 2) * d; ++k) best_wp[k] = src[k];
         best_meta[0] = (int32_t)stage;
         best_meta[1] = M;
         best_meta[2] = N;
@@ -476,6 +483,24 @@ __global__ void k_anytime_init(float *best_cost, int32_t *best_meta, uint32_t *c
 }
 
 // ------------------------------------------------------------------ drivers
+// Buffers of one path's shortcutting (at most K waypoints): the shortcut
+// table, then its length and kept count, the kept indices and waypoints.
+namespace {
+struct SimpCarve {
+    uint8_t *valid;
+    float *cost;
+    int32_t *count, *idx;
+    float *wp;
+};
+size_t simp_bytes(int K, int d) { return up256((size_t)K * K) + 256 + sizeof(int32_t) * K + sizeof(float) * K * d; }
+SimpCarve simp_carve(char *base, int K, int d) {
+    const size_t o = up256((size_t)K * K);
+    return SimpCarve{reinterpret_cast<uint8_t *>(base), reinterpret_cast<float *>(base + o),
+                     reinterpret_cast<int32_t *>(base + o + 4), reinterpret_cast<int32_t *>(base + o + 256),
+                     reinterpret_cast<float *>(base + o + 256 + sizeof(int32_t) * K)};
+}
+}  // namespace
+
 AnytimePlan make_anytime_plan(const gtmp_problem &p, const gtmp_anytime_opts &o) {
     AnytimePlan a{};
     gtmp_problem big = p;
@@ -495,6 +520,9 @@ AnytimePlan make_anytime_plan(const gtmp_problem &p, const gtmp_anytime_opts &o)
     a.off_A = off; off = up256(off + sizeof(int32_t) * M * N);
     a.off_small = off; off = up256(off + 256 + sizeof(int32_t) * (M + 1) + sizeof(float) * (M + 2) * d);
     a.off_counter = off; off = up256(off + 64);
+    if (o.simplify) {
+        a.off_simp = off; off = up256(off + simp_bytes((int)M + 2, (int)d));
+    }
     const EdgePlan ep = make_edge_plan(big);
     a.off_edge = off; off = up256(off + ep.total);
     if (o.mode == GTMP_ANYTIME_GROWING) {
@@ -553,8 +581,17 @@ hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const Sce
         if (e != hipSuccess) return e;
         e = launch_extract(pp.M, pp.N, pp.G, d, as, A, Vs, Qp, q0, goals, idx, wp, cost, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_archive, dim3(1), dim3(64), 0, st, pp.M, pp.N, d, cost, idx, wp, out.best_cost,
-                           out.best_idx, out.best_wp, out.best_meta, out.stage_costs, counter, o.max_stages);
+        const float *sc = nullptr, *swp = nullptr;
+        if (o.simplify) {
+            const SimpCarve c = simp_carve(ws + a.off_simp, a.big.M + 2, d);
+            e = launch_simplify(arm, scene, wdim, d, 1, pp.M + 2, pp.H, wp, c.valid, c.idx, c.count, c.cost, c.wp, st);
+            if (e != hipSuccess) return e;
+            sc = c.cost;
+            swp = c.wp;
+        }
+        hipLaunchKernelGGL(k_archive, dim3(1), dim3(64), 0, st, pp.M, pp.N, d, cost, idx, wp, sc, swp,
+                           o.mode == GTMP_ANYTIME_GROWING ? 1 : 0, out.best_cost, out.best_idx, out.best_wp,
+                           out.best_meta, out.stage_costs, counter, o.max_stages);
         return hipGetLastError();
     };
 
@@ -578,7 +615,7 @@ hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const Sce
         // (buffers, sizes, stream) and replayed max_stages times on `s`
         GraphKey key{std::make_tuple((const void *)workspace, (const void *)q0, (const void *)goals,
                                      (const void *)out.best_cost, seed, p.M, p.N, p.H, (int)eo.mode,
-                                     eo.sphere_chunks * 16 + eo.states_per_iter, s)};
+                                     eo.sphere_chunks * 16 + eo.states_per_iter + (o.simplify ? 1 << 16 : 0), s)};
         hipGraphExec_t exec = nullptr;
         {
             std::lock_guard<std::mutex> lk(g_graph_mu);

@@ -327,6 +327,10 @@ gtmp_status gtmp_expand_samples_biased(const gtmp_problem *prob, const float *q0
 static gtmp_status check_anytime(const gtmp_problem *prob, const gtmp_anytime_opts *o) {
     if (!o) return fail(GTMP_EINVAL, "opts is NULL");
     if (o->max_stages < 1) return fail(GTMP_EINVAL, "max_stages=%d < 1", o->max_stages);
+    if (o->simplify) {
+        const int Mx = o->mode == GTMP_ANYTIME_GROWING ? o->M_max : prob->M;
+        if (Mx + 2 > 64) return fail(GTMP_EINVAL, "simplify needs at most 64 waypoints (M=%d)", Mx);
+    }
     if (o->mode == GTMP_ANYTIME_RESTART) return check_problem(prob);
     if (o->mode != GTMP_ANYTIME_GROWING) return fail(GTMP_EINVAL, "unknown anytime mode %d", o->mode);
     if (o->M_min < 1 || o->M_min > o->M_max) return fail(GTMP_EINVAL, "need 1 <= M_min <= M_max");

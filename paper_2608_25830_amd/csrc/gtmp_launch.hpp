@@ -83,7 +83,8 @@ hipError_t launch_informed_batch(const gtmp_problem &p, const float *q0, const f
 
 struct AnytimePlan {
     gtmp_problem big;  // sizes the buffers are carved for
-    size_t off_Q, off_Q2, off_Cs, off_Ch, off_Cl, off_V, off_A, off_small, off_counter, off_edge, off_expand, total;
+    size_t off_Q, off_Q2, off_Cs, off_Ch, off_Cl, off_V, off_A, off_small, off_counter, off_simp, off_edge, off_expand,
+        total;
 };
 AnytimePlan make_anytime_plan(const gtmp_problem &p, const gtmp_anytime_opts &o);
 

@@ -181,6 +181,16 @@ def test_anytime_and_batch_options_validate(g):
     assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_EINVAL
     o.max_stages, o.mode = 4, 7
     assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_EINVAL
+    # shortcutting: at most 64 waypoints, and it costs workspace
+    o.mode, o.M_max = g.GTMP_ANYTIME_GROWING, 62
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_OK
+    n0 = n.value
+    o.simplify = 1
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_OK and n.value > n0
+    o.M_max = 63
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_EINVAL
+    o.mode, o.simplify, o.M_max = g.GTMP_ANYTIME_RESTART, 1, 3
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(_prob(g, M=63)), C.byref(o), C.byref(n)) == g.GTMP_EINVAL
     # batch: empty, bad options, bad plan
     descs = (g.gtmp_plan_desc * 1)()
     D = descs[0]

@@ -128,3 +128,49 @@ def test_growing_matches_oracle(gt, name, sched, kw):
     assert meta[3] == len(costs)
     assert float(ap.best_cost.item()) == pytest.approx(best["cost"], rel=P.REL)
     assert (meta[1], meta[2]) == (best["M"], best["N"]) or abs(sorted(costs)[1] - sorted(costs)[0]) <= P.REL * best["cost"]
+
+
+def _best_wp_rows(ap):
+    wp = ap.best_wp.cpu().numpy()
+    keep = ~np.isnan(wp).any(1)
+    n = int(keep.sum())
+    assert keep[:n].all() and not keep[n:].any()  # kept waypoints, then NaN rows
+    return wp[:n]
+
+
+@pytest.mark.parametrize("name,kw,graph", [("2d-small", {}, False), ("2d-small", {}, True),
+                                           ("arm7", dict(N=96, M=3), False), ("2d-large", dict(N=128, M=4), True)])
+def test_restart_with_shortcuts_matches_oracle(gt, name, kw, graph):
+    w = wl.make_workload(name, 1, **kw)
+    _say("restart + simp", name, kw, "graph", graph)
+    S = 5
+    ap = _anytime(gt, w, gt.GTMP_ANYTIME_RESTART, S, use_graph=graph, simplify=True)
+    best, costs = OA.plan_restart(w, S, w["seed"], simplify=True)
+    got = ap.stage_costs.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, costs, rtol=P.REL)  # stage paths themselves
+    meta = ap.best_meta.cpu().numpy()
+    _say("oracle best", best["cost"], "stage", best["stage"], "gpu", float(ap.best_cost.item()), "stage", meta[0])
+    assert float(ap.best_cost.item()) == pytest.approx(best["cost"], rel=P.REL)
+    srt = np.sort(costs)
+    if srt[1] - srt[0] > P.REL * srt[0] and meta[0] == best["stage"]:
+        np.testing.assert_array_equal(_best_wp_rows(ap), best["wp"])
+
+
+@pytest.mark.parametrize("name,sched", [("2d-small", (3, 5, 16, 64, 8)), ("arm7", (3, 4, 32, 64, 5))])
+def test_growing_with_shortcuts_matches_oracle(gt, name, sched):
+    w = wl.make_workload(name, 1)
+    M_min, M_max, N_min, N_max, S = sched
+    _say("growing + simp", name, sched)
+    ap = gt.AnytimePlanner(w, gt.GTMP_ANYTIME_GROWING, S, M_min=M_min, M_max=M_max, N_min=N_min, N_max=N_max,
+                           simplify=True)
+    ap.run(w["seed"])
+    torch.cuda.synchronize()
+    best, costs, _ = OA.plan_growing(w, M_min, M_max, N_min, N_max, S, w["seed"], simplify=True)
+    got = ap.stage_costs.cpu().numpy().astype(np.float64)[:len(costs)]
+    _say("stage shortcut lengths gpu", got, "oracle", costs)
+    np.testing.assert_allclose(got, costs, rtol=P.REL)
+    assert float(ap.best_cost.item()) == pytest.approx(best["cost"], rel=P.REL)
+    wp = _best_wp_rows(ap)
+    assert np.array_equal(wp[0], w["q0"]) and np.array_equal(wp[-1], w["goals"][0])
+    L = sum(np.linalg.norm(b.astype(np.float64) - a) for a, b in zip(wp[:-1], wp[1:]))
+    assert L == pytest.approx(float(ap.best_cost.item()), rel=P.REL)

@@ -195,3 +195,56 @@ def test_biased_heuristic_half_takes_closest_predicted_free_pairs():
     for h, n in enumerate(heur):
         np.testing.assert_array_equal(Q[1][n], free[h])
     assert all(float(Q[1][n][0]) <= np.pi / 3 for n in heur)
+
+
+def _polyline_ok(w, wp):
+    """Every segment of wp passes the straight-line check at the plan's
+    state spacing (H states per segment), first and last waypoints are the
+    start and the goal; returns the FP64 length."""
+    model = oracle.Model(w)
+    assert np.array_equal(wp[0], np.asarray(w["q0"], np.float32))
+    assert np.array_equal(wp[-1], np.asarray(w["goals"], np.float32)[0])
+    L = 0.0
+    for a, b in zip(wp[:-1], wp[1:]):
+        c, sd, f = oracle.edge(model, int(w["H"]), a, b)
+        assert f == 0
+        L += np.linalg.norm(b.astype(np.float64) - a)
+    return L
+
+
+def test_restart_with_shortcuts_stores_shorter_free_paths():
+    """Alg. 1 anytime-gtmp with simp(): the stored path is a shortcut of the
+    winning stage's path, no longer than it, and the archive never exceeds
+    the archive of the loop without shortcuts."""
+    w = wl.make_workload("2d-small", 1)
+    plain, costs = OA.plan_restart(w, 6, w["seed"])
+    best, costs2 = OA.plan_restart(w, 6, w["seed"], simplify=True)
+    assert costs2 == costs  # stage paths do not depend on the archive
+    assert best["cost"] <= plain["cost"]
+    r = oracle.plan(w, stage=best["stage"])
+    assert best["cost"] <= r["path_cost"]
+    assert best["cost"] == pytest.approx(_polyline_ok(w, best["wp"]), rel=1e-12)
+    # waypoints are a subsequence of the stage path
+    wp = np.asarray(r["wp"], np.float32)
+    pos = [int(np.flatnonzero((wp == x).all(1))[0]) for x in best["wp"]]
+    assert pos == sorted(pos) and pos[0] == 0 and pos[-1] == len(wp) - 1
+
+
+def test_growing_with_shortcuts_bounds_by_the_shortcut_length():
+    w = wl.make_workload("2d-small", 2)
+    best, costs, stages = OA.plan_growing(w, 3, 5, 16, 64, 8, 77, simplify=True)
+    plain, costs0, _ = OA.plan_growing(w, 3, 5, 16, 64, 8, 77)
+    # the first stage runs unbounded on both: its shortcut is no longer, and
+    # a path through a failed edge has none
+    if costs0[0] < w["penalty"]:
+        assert costs[0] <= costs0[0]
+    else:
+        assert costs[0] == np.inf
+    assert np.isfinite(best["cost"])
+    bounds = [st["bound"] for st in stages]
+    run = np.minimum.accumulate(costs)
+    assert bounds[1:] == list(run[:-1])  # c_min is the best shortcut length so far
+    assert best["cost"] == run[-1]
+    ww = dict(w)
+    ww["M"], ww["N"] = best["M"], best["N"]
+    assert best["cost"] == pytest.approx(_polyline_ok(ww, best["wp"]), rel=1e-12)
