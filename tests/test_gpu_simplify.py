@@ -113,7 +113,7 @@ def test_oracle_planned_paths_match(gt, orc, name, scene, N, M):
 
 
 @pytest.mark.parametrize("name,scene,N", [("2d-small", 1, 64), ("2d-large", 0, 256), ("arm7", 1, 256),
-                                          ("arm7", 3, 512)])
+                                          ("arm7", 3, 512), ("arm7", 0, 2048), ("2d-large", 1, 1024)])
 def test_gpu_plan_never_lengthens(gt, name, scene, N):
     """Invariant without the oracle: the plan's own chain is a candidate of
     the shortcut recursion (same FP32 edge lengths, same summation order as
