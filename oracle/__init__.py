@@ -90,6 +90,16 @@ def _declare(L):
     L.or_coin_heuristic.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]
     L.or_coin_heuristic.restype = C.c_int
     L.or_pair_d2_all.argtypes = [C.c_int, C.c_int, _fp, C.c_int, _fp, _fp]
+    L.or_rrtc_sample.argtypes = [C.c_int, _fp, _fp, _fp, _fp, C.c_float, C.c_float, C.c_uint64, C.c_uint64,
+                                 C.c_uint32, C.c_uint32, _fp]
+    L.or_rrtc_sample.restype = C.c_int
+    L.or_rrtc.argtypes = [C.POINTER(OrModel), _fp, _fp, _fp, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
+                          C.c_float, C.c_uint64, C.c_uint64, C.c_uint32, C.c_double, _fp, _ip, _dp, _ip, _ip, _ip,
+                          _fp, _ip]
+    L.or_rrtc.restype = C.c_int
+    L.or_rrtc_batch.argtypes = [C.POINTER(OrModel), C.c_int, _fp, _fp, _up, _fp, _fp, C.c_int, C.c_int, C.c_float,
+                                C.c_float, C.c_float, C.c_uint64, C.c_uint64, C.c_double, _ip, _dp, _ip, _ip, _ip,
+                                _ip]
 
 
 def threads() -> int:

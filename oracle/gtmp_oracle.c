@@ -506,3 +506,234 @@ void or_pair_d2_all(int d, int nu, const float *U, int nv, const float *V, float
     for (int a = 0; a < nu; ++a)
         for (int b = 0; b < nv; ++b) out[(size_t)a * nv + b] = or_pair_d2(d, U + (size_t)a * d, V + (size_t)b * d);
 }
+
+/* ------------------------------------------------------------------------ */
+/* RRT-Connect local planner LP(x, y; s, ell) (Sec. III, generalized GTMP   */
+/* graph; construction in the proof of the local-planner reach proposition  */
+/* of the appendix): confined to the query ellipsoid E(x, y; ell) = {z :    */
+/* |z - x| + |z - y| <= ell}, ell = ell_factor |y - x|, the straight line   */
+/* already having failed (short-range exactness is the caller's straight-   */
+/* line check).  Two trees rooted at x and y; iteration i (i < s) draws one */
+/* uniform sample of the ellipsoid intersected with the box, extends tree A */
+/* towards it by at most eta, and on success connects tree B greedily to    */
+/* the new node; then the trees swap roles.                                 */
+/*                                                                          */
+/* Decisions are FP32 computations with a fixed operation order (this file  */
+/* is compiled without contraction):                                        */
+/*   sample   attempt a of iteration i: y_j = (w_j >> 8) 2^-23 - 1, words   */
+/*            from Philox at counter (e, i, stage, (3 << 16) | (2a + j/4));  */
+/*            accepted iff sum y_j^2 < 1 and x = c + H (r1 y_1, r2 y_2, ...) */
+/*            lies in the box (the hyperspheroid map of the informed set    */
+/*            with foci x, y and major axis ell); at most 4096 attempts,    */
+/*            none accepted = no extension this iteration                   */
+/*   nearest  least FP32 squared distance summed in coordinate order,       */
+/*            lowest node index on ties                                     */
+/*   steer    dist = sqrt(d2); dist <= eta: the target itself (Reached);    */
+/*            else p + (eta / dist) (q - p), each operation rounded         */
+/*   check    the segment p -> q_new at H_s = max(2, ceil(len / res) + 1)   */
+/*            states (len its FP32 length), signed distance <= 0 collides   */
+/*   full     a tree holding `cap` nodes extends no further (Trapped)       */
+/* A path is x -> ... -> q_new -> ... -> y along the two trees; its cost is */
+/* its length.  Collision decisions are FP64 signed distances here; a       */
+/* segment whose minimum lies within `band` of zero sets *near_band, so a   */
+/* test can excuse calls whose result hinges on such a state.               */
+/* ------------------------------------------------------------------------ */
+#define OR_RRTC_TRAPPED 0
+#define OR_RRTC_ADVANCED 1
+#define OR_RRTC_REACHED 2
+#define OR_RRTC_ATTEMPTS 4096
+
+typedef struct {
+    float *pos; /* [cap][d] */
+    int *par;   /* [cap] */
+    int n;
+} or_tree;
+
+static int or_segment_free(const or_model *mdl, const float *a, const float *b, float res, double band,
+                           int *near_band)
+{
+    int d = mdl->d;
+    float len = sqrtf(or_pair_d2(d, a, b));
+    int Hs = (int)ceilf(len / res) + 1;
+    if (Hs < 2) Hs = 2;
+    double c, sd;
+    int f;
+    or_edge(mdl, Hs, INFINITY, INFINITY, a, b, &c, &sd, &f);
+    if (fabs(sd) <= band) *near_band = 1;
+    return f == 0;
+}
+
+static int or_extend(const or_model *mdl, or_tree *T, int cap, const float *q, float eta, float res, double band,
+                     int *near_band, int *new_idx)
+{
+    int d = mdl->d;
+    if (T->n >= cap) return OR_RRTC_TRAPPED;
+    int near = 0;
+    float best = or_pair_d2(d, T->pos, q);
+    for (int j = 1; j < T->n; ++j) {
+        float v = or_pair_d2(d, T->pos + (size_t)j * d, q);
+        if (v < best) {
+            best = v;
+            near = j;
+        }
+    }
+    const float *p = T->pos + (size_t)near * d;
+    float dist = sqrtf(best);
+    float qn[16];
+    int reached = dist <= eta;
+    if (reached) {
+        for (int i = 0; i < d; ++i) qn[i] = q[i];
+    } else {
+        float f = eta / dist;
+        for (int i = 0; i < d; ++i) qn[i] = p[i] + f * (q[i] - p[i]);
+    }
+    if (!or_segment_free(mdl, p, qn, res, band, near_band)) return OR_RRTC_TRAPPED;
+    memcpy(T->pos + (size_t)T->n * d, qn, sizeof(float) * d);
+    T->par[T->n] = near;
+    *new_idx = T->n;
+    T->n += 1;
+    return reached ? OR_RRTC_REACHED : OR_RRTC_ADVANCED;
+}
+
+/* Sample of iteration i: 1 and the point in q, or 0 when no attempt passed. */
+int or_rrtc_sample(int d, const float *lo, const float *hi, const float *centre, const float *H, float r1, float r2,
+                   uint64_t seed, uint64_t stage, uint32_t e, uint32_t i, float *q)
+{
+    for (int a = 0; a < OR_RRTC_ATTEMPTS; ++a) {
+        float y[16], z[16];
+        float s2 = 0.0f;
+        for (int j = 0; j < d; ++j) {
+            uint32_t w[4];
+            or_words(seed, stage, 3u, e, i, (uint32_t)(2 * a + j / 4), w);
+            y[j] = (float)(w[j % 4] >> 8) * (1.0f / 8388608.0f) - 1.0f;
+            s2 = s2 + y[j] * y[j];
+        }
+        if (!(s2 < 1.0f)) continue;
+        for (int j = 0; j < d; ++j) z[j] = (j == 0 ? r1 : r2) * y[j];
+        int inside = 1;
+        for (int r = 0; r < d; ++r) {
+            float acc = 0.0f;
+            for (int c = 0; c < d; ++c) acc = acc + H[r * d + c] * z[c];
+            q[r] = centre[r] + acc;
+            if (!(q[r] >= lo[r] && q[r] <= hi[r])) inside = 0;
+        }
+        if (inside) return 1;
+    }
+    return 0;
+}
+
+/* One call.  Returns 1 on success.  path [2 cap][d] (may be NULL) receives
+ * the waypoints from x to y, *n_path their count; *cost the path length
+ * (FP64 sum of segment lengths); *iters the iterations run; sizes[2] the
+ * node counts of the x and y trees; trees (may be NULL) [2][cap][d] and
+ * parents (may be NULL) [2][cap] the trees themselves. */
+int or_rrtc(const or_model *mdl, const float *x, const float *y, const float *lo, const float *hi, int budget,
+            int cap, float eta, float res, float ell_factor, uint64_t seed, uint64_t stage, uint32_t e, double band,
+            float *path, int *n_path, double *cost, int *iters, int *sizes, int *near_band, float *trees,
+            int *parents)
+{
+    int d = mdl->d;
+    or_tree TX, TY;
+    TX.pos = (float *)malloc(sizeof(float) * (size_t)cap * d);
+    TY.pos = (float *)malloc(sizeof(float) * (size_t)cap * d);
+    TX.par = (int *)malloc(sizeof(int) * (size_t)cap);
+    TY.par = (int *)malloc(sizeof(int) * (size_t)cap);
+    memcpy(TX.pos, x, sizeof(float) * d);
+    memcpy(TY.pos, y, sizeof(float) * d);
+    TX.par[0] = TY.par[0] = -1;
+    TX.n = TY.n = 1;
+    *near_band = 0;
+    float cmin = sqrtf(or_pair_d2(d, x, y));
+    float ell = ell_factor * cmin;
+    float centre[16], H[256], r1, r2, cm2;
+    or_informed_params(d, x, y, ell, centre, H, &r1, &r2, &cm2);
+    or_tree *Ta = &TX, *Tb = &TY;
+    int ok = 0, ax = -1, ay = -1, it = 0;
+    for (it = 0; it < budget && !ok; ++it) {
+        float q[16];
+        if (or_rrtc_sample(d, lo, hi, centre, H, r1, r2, seed, stage, e, (uint32_t)it, q)) {
+            int ia = -1;
+            if (or_extend(mdl, Ta, cap, q, eta, res, band, near_band, &ia) != OR_RRTC_TRAPPED) {
+                float qn[16];
+                memcpy(qn, Ta->pos + (size_t)ia * d, sizeof(float) * d);
+                int ib = -1, st;
+                do {
+                    st = or_extend(mdl, Tb, cap, qn, eta, res, band, near_band, &ib);
+                } while (st == OR_RRTC_ADVANCED);
+                if (st == OR_RRTC_REACHED) {
+                    ok = 1;
+                    ax = Ta == &TX ? ia : ib;
+                    ay = Ta == &TX ? ib : ia;
+                }
+            }
+        }
+        or_tree *t = Ta;
+        Ta = Tb;
+        Tb = t;
+    }
+    *iters = it;
+    sizes[0] = TX.n;
+    sizes[1] = TY.n;
+    *cost = INFINITY;
+    *n_path = 0;
+    if (ok) {
+        /* x-tree chain root -> ax, then the y-tree chain from the parent of ay
+         * (ay duplicates the junction) to its root */
+        int chain[2 * 4096 + 2];
+        int nx = 0;
+        for (int j = ax; j >= 0; j = TX.par[j]) chain[nx++] = j;
+        int np = 0;
+        double L = 0.0;
+        const float *prev = NULL;
+        for (int k = nx - 1; k >= 0; --k) {
+            const float *p = TX.pos + (size_t)chain[k] * d;
+            if (path) memcpy(path + (size_t)np * d, p, sizeof(float) * d);
+            if (prev) {
+                double s2 = 0.0;
+                for (int i = 0; i < d; ++i) s2 += ((double)p[i] - prev[i]) * ((double)p[i] - prev[i]);
+                L += sqrt(s2);
+            }
+            prev = p;
+            ++np;
+        }
+        for (int j = TY.par[ay]; j >= 0; j = TY.par[j]) {
+            const float *p = TY.pos + (size_t)j * d;
+            if (path) memcpy(path + (size_t)np * d, p, sizeof(float) * d);
+            double s2 = 0.0;
+            for (int i = 0; i < d; ++i) s2 += ((double)p[i] - prev[i]) * ((double)p[i] - prev[i]);
+            L += sqrt(s2);
+            prev = p;
+            ++np;
+        }
+        *n_path = np;
+        *cost = L;
+    }
+    if (trees) {
+        memcpy(trees, TX.pos, sizeof(float) * (size_t)TX.n * d);
+        memcpy(trees + (size_t)cap * d, TY.pos, sizeof(float) * (size_t)TY.n * d);
+    }
+    if (parents) {
+        memcpy(parents, TX.par, sizeof(int) * (size_t)TX.n);
+        memcpy(parents + cap, TY.par, sizeof(int) * (size_t)TY.n);
+    }
+    free(TX.pos);
+    free(TY.pos);
+    free(TX.par);
+    free(TY.par);
+    return ok;
+}
+
+/* Many calls (OpenMP over calls): X, Y [n][d], ids [n] the edge ids that key
+ * the random streams; outputs per call. */
+void or_rrtc_batch(const or_model *mdl, int n, const float *X, const float *Y, const uint32_t *ids,
+                   const float *lo, const float *hi, int budget, int cap, float eta, float res, float ell_factor,
+                   uint64_t seed, uint64_t stage, double band, int *ok, double *cost, int *iters, int *sizes,
+                   int *near_band, int *n_path)
+{
+    int d = mdl->d;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < n; ++k)
+        ok[k] = or_rrtc(mdl, X + (size_t)k * d, Y + (size_t)k * d, lo, hi, budget, cap, eta, res, ell_factor, seed,
+                        stage, ids[k], band, NULL, &n_path[k], &cost[k], &iters[k], sizes + 2 * k, &near_band[k],
+                        NULL, NULL);
+}
