@@ -205,6 +205,72 @@ gtmp_status gtmp_simplify_paths(const gtmp_robot *robot, const gtmp_scene *scene
                                 int32_t H, const float *wp, uint8_t *valid, int32_t *idx, int32_t *count, float *cost,
                                 float *out_wp, void *stream);
 
+/* ------------------------------------- RRT-Connect local planner (LP) */
+/* The second local planner of Sec. III / Sec. V: LP(x, y; s, ell) returns a
+ * collision-free path from x to y inside the query ellipsoid
+ * E(x, y; ell) = {z : |z - x| + |z - y| <= ell}, or fails.  RRT-Connect as
+ * constructed in the proof of the paper's local-planner reach proposition:
+ * the straight line first (that is the edge check above, so an edge it
+ * passes is kept as a straight segment), then two trees rooted at x and y,
+ * for iterations i = 0 .. budget-1: draw one sample, extend tree A towards
+ * it by at most `step`, on success connect tree B to the new node by
+ * repeated extensions, and swap the trees.  Decisions, all FP32 with a fixed
+ * operation order (no fused multiply-add):
+ *   ell      ell_factor * |y - x| (length summed in coordinate order)
+ *   sample   attempt a (a < 4096) of iteration i: y_j = (w_j >> 8) 2^-23 - 1
+ *            from Philox4x32-10 at key (seed) and counter
+ *            (e, i, stage, (3 << 16) | (2a + j div 4)), e the flat edge id;
+ *            accepted iff sum y_j^2 < 1 and z = c + H (r1 y_1, r2 y_2, ...) lies
+ *            in the box, with the hyperspheroid map of gtmp_sample_informed
+ *            for foci x, y and bound ell; the lowest accepted attempt is the
+ *            sample, none = no extension in this iteration
+ *   nearest  least squared distance summed in coordinate order, lowest node
+ *            index on ties
+ *   steer    d = sqrt(d2); d <= step: the target itself (reached); else
+ *            p + (step / d) (q - p)
+ *   check    states p + (h / (Hs - 1)) (q_new - p), h = 1 .. Hs - 1, with
+ *            Hs = max(2, ceil(|q_new - p| / resolution) + 1); the extension
+ *            fails if one collides (state test of gtmp_state_check)
+ *   full     a tree holding tree_cap nodes extends no further
+ * A path is the x tree's chain to the junction followed by the y tree's
+ * chain to y; its cost is its length in FP32, summed over the segments from
+ * x to y. */
+typedef struct gtmp_rrtc_opts {
+    int32_t budget;      /* s >= 1: iterations per call (one sample each) */
+    int32_t tree_cap;    /* nodes per tree, 2 .. 4096, with the LDS limit: 4 (2 d + 4) tree_cap + 256 <= 163840 */
+    float step;          /* eta > 0: extension step (configuration units) */
+    float resolution;    /* > 0, step / resolution <= 4096: spacing bound of checked states */
+    float ell_factor;    /* >= 1: major axis of the query ellipsoid over |y - x| */
+    int32_t reserved;
+    unsigned long long *stats; /* optional device [4]: calls, successes, iterations, tree nodes.  Added to. */
+} gtmp_rrtc_opts;
+
+/* Bytes of device workspace gtmp_rrtc_repair needs for this problem. */
+gtmp_status gtmp_rrtc_workspace_size(const gtmp_problem *prob, size_t *bytes);
+
+/* Run the RRT-Connect LP on every edge whose straight line failed (flags[e]
+ * == 1 as written by gtmp_edge_check_cost) with both endpoints
+ * collision-free and |y - x| <= max_edge_len.  A call that succeeds replaces
+ * the edge's cost by its path length and sets flags[e] = 2; a failed call
+ * leaves both.  Calls are keyed by (seed, stage, e), so a call is
+ * reproducible on its own (gtmp_rrtc_local_path).  Arguments as for
+ * gtmp_edge_check_cost; flags device uint8 [E], required (read and
+ * written); E < 2^32. */
+gtmp_status gtmp_rrtc_repair(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                             const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
+                             uint8_t *flags, uint64_t seed, uint64_t stage, const gtmp_rrtc_opts *opts,
+                             void *workspace, size_t ws_bytes, void *stream);
+
+/* The local path of edge `edge` (flat id, order C_s | C_h | C_l) by the same
+ * call gtmp_rrtc_repair makes: path device float32 [2 tree_cap][d] receives
+ * the waypoints from x to y, count device int32 [1] their number (0 when
+ * the call fails), cost device float32 [1] the length (+inf on failure),
+ * equal to the cost the repair wrote.  No workspace. */
+gtmp_status gtmp_rrtc_local_path(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                                 const float *q0, const float *goals, const float *Q, uint64_t edge, uint64_t seed,
+                                 uint64_t stage, const gtmp_rrtc_opts *opts, float *path, int32_t *count, float *cost,
+                                 void *stream);
+
 /* --------------------------------------------------- a5 min-plus sweep */
 /* Backward value iteration on the layered DAG (Sec. IV-B; Alg. 1):
  *   V[M-1][u] = min_g C_l[u][g] + V_g[g]

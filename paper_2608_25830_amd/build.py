@@ -31,11 +31,11 @@ FLAGS = [
 ]
 
 SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip", "batch.hip", "surrogate.hip",
-           "classes.hip", "simplify.hip"]
-# the growing-budget sampler and the class labels are defined as FP32
-# computations with a fixed operation order: no contraction into fused
-# multiply-adds in those files
-EXTRA = {"anytime.hip": ["-ffp-contract=off"], "classes.hip": ["-ffp-contract=off"]}
+           "classes.hip", "simplify.hip", "rrtc.hip"]
+# the growing-budget sampler, the class labels and the RRT-Connect decisions
+# are defined as FP32 computations with a fixed operation order: no
+# contraction into fused multiply-adds in those files
+EXTRA = {src: ["-ffp-contract=off"] for src in ("anytime.hip", "classes.hip", "rrtc.hip")}
 
 
 def _compile(src: str) -> str:

@@ -2,6 +2,7 @@
 // the public structs into kernel arguments, and dispatch to the launchers.
 // No C++ exception crosses the boundary; every failure returns a status and
 // records a thread-local message.
+#include <cmath>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -218,6 +219,75 @@ gtmp_status gtmp_simplify_paths(const gtmp_robot *robot, const gtmp_scene *scene
     return hip_status(gtmp::launch_simplify(is_arm ? &arm : nullptr, sp, scene->wdim, d, B, K, H, wp, valid, idx, count,
                                             cost, out_wp, (hipStream_t)stream),
                       "gtmp_simplify_paths");
+}
+
+static gtmp_status check_rrtc(const gtmp_problem *prob, const gtmp_rrtc_opts *o) {
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (!o) return fail(GTMP_EINVAL, "opts is NULL");
+    if (o->budget < 1) return fail(GTMP_EINVAL, "budget=%d < 1", o->budget);
+    if (o->tree_cap < 2 || o->tree_cap > 4096) return fail(GTMP_EINVAL, "tree_cap=%d outside 2..4096", o->tree_cap);
+    if (gtmp::rrtc_lds_bytes(prob->d, o->tree_cap) > 163840)
+        return fail(GTMP_EINVAL, "tree_cap=%d needs more than 160 KiB of LDS at d=%d", o->tree_cap, prob->d);
+    if (!(o->step > 0.f) || !std::isfinite(o->step)) return fail(GTMP_EINVAL, "step must be finite and > 0");
+    if (!(o->resolution > 0.f) || !std::isfinite(o->resolution))
+        return fail(GTMP_EINVAL, "resolution must be finite and > 0");
+    if (!(o->step / o->resolution <= 4096.f)) return fail(GTMP_EINVAL, "step / resolution > 4096");
+    if (!(o->ell_factor >= 1.f) || !std::isfinite(o->ell_factor)) return fail(GTMP_EINVAL, "ell_factor must be >= 1");
+    const uint64_t N = prob->N, M = prob->M, G = prob->G;
+    if (N + (M - 1) * N * N + N * G >= (1ull << 32)) return fail(GTMP_EINVAL, "more than 2^32 - 1 edges");
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_rrtc_workspace_size(const gtmp_problem *prob, size_t *bytes) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::make_rrtc_plan(*prob).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_rrtc_repair(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                             const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
+                             uint8_t *flags, uint64_t seed, uint64_t stage, const gtmp_rrtc_opts *opts,
+                             void *workspace, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_rrtc(prob, opts);
+    if (st != GTMP_OK) return st;
+    gtmp::ArmParams arm{};
+    gtmp::SceneParams sp{};
+    bool is_arm = false;
+    st = check_model(robot, scene, prob->d, &arm, &is_arm, &sp);
+    if (st != GTMP_OK) return st;
+    if (!q0 || !goals || !Q || !C_s || !C_l || !flags || !workspace) return fail(GTMP_EINVAL, "NULL buffer");
+    if (prob->M > 1 && !C_h) return fail(GTMP_EINVAL, "C_h is NULL with M > 1");
+    const size_t need = gtmp::make_rrtc_plan(*prob).total;
+    if (ws_bytes < need) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    return hip_status(gtmp::launch_rrtc_repair(*prob, is_arm ? &arm : nullptr, sp, scene->wdim, q0, goals, Q, C_s, C_h,
+                                               C_l, flags, seed, stage, *opts, workspace, (hipStream_t)stream),
+                      "gtmp_rrtc_repair");
+}
+
+gtmp_status gtmp_rrtc_local_path(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                                 const float *q0, const float *goals, const float *Q, uint64_t edge, uint64_t seed,
+                                 uint64_t stage, const gtmp_rrtc_opts *opts, float *path, int32_t *count, float *cost,
+                                 void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_rrtc(prob, opts);
+    if (st != GTMP_OK) return st;
+    gtmp::ArmParams arm{};
+    gtmp::SceneParams sp{};
+    bool is_arm = false;
+    st = check_model(robot, scene, prob->d, &arm, &is_arm, &sp);
+    if (st != GTMP_OK) return st;
+    const uint64_t N = prob->N, M = prob->M, G = prob->G;
+    if (edge >= N + (M - 1) * N * N + N * G) return fail(GTMP_EINVAL, "edge %llu out of range", (unsigned long long)edge);
+    if (!q0 || !goals || !Q || !path || !count || !cost) return fail(GTMP_EINVAL, "NULL buffer");
+    return hip_status(gtmp::launch_rrtc_path(*prob, is_arm ? &arm : nullptr, sp, scene->wdim, q0, goals, Q, edge, seed,
+                                             stage, *opts, path, count, cost, (hipStream_t)stream),
+                      "gtmp_rrtc_local_path");
 }
 
 gtmp_status gtmp_minplus_sweep(int32_t M, int32_t N, int32_t G, const float *C_s, const float *C_h, const float *C_l,

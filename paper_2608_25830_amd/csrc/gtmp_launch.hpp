@@ -127,6 +127,21 @@ hipError_t launch_simplify(const ArmParams *arm, const SceneParams &scene, int w
                            const float *wp, uint8_t *valid, int32_t *idx, int32_t *count, float *cost, float *out_wp,
                            hipStream_t s);
 
+// ---- RRT-Connect local planner (rrtc.hip)
+struct RrtcPlan {
+    size_t off_counters, off_vfree, off_cand, total;
+};
+RrtcPlan make_rrtc_plan(const gtmp_problem &p);
+size_t rrtc_lds_bytes(int d, int cap);
+hipError_t launch_rrtc_repair(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,
+                              const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
+                              uint8_t *flags, uint64_t seed, uint64_t stage, const gtmp_rrtc_opts &o, void *workspace,
+                              hipStream_t s);
+hipError_t launch_rrtc_path(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,
+                            const float *q0, const float *goals, const float *Q, uint64_t edge, uint64_t seed,
+                            uint64_t stage, const gtmp_rrtc_opts &o, float *path, int32_t *count, float *cost,
+                            hipStream_t s);
+
 // ---- batched plans (batch.hip)
 struct StageShape {
     int M, N, n_old;

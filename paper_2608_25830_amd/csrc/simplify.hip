@@ -17,6 +17,7 @@
 //                     waypoint j, the backward recursion takes K - 1 wave
 //                     arg-min reductions, then the chain is followed from w_0.
 #include "edge_common.hpp"
+#include "state_test.hpp"
 
 namespace gtmp {
 
@@ -62,22 +63,7 @@ __global__ void __launch_bounds__(256) k_shortcut_check(ArmParams R, SceneParams
         float q[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) q[k] = last ? v[k] : __builtin_fmaf(t, dv[k], u[k]);
-        float gap;
-        if constexpr (ARM) {
-            const v32f o = arm_fk<D>(R, q);
-            Probes<3, KP> P;
-            arm_spheres<KP>(R, o, P);
-            float pr[KP];
-#pragma unroll
-            for (int k = 0; k < KP; ++k) pr[k] = k < R.n_spheres ? R.r[k] : 0.f;
-            gap = R.uniform_r ? probes_min_gap<3, KP, true>(P, pr, R.r0, S) : probes_min_gap<3, KP, false>(P, pr, R.r0, S);
-        } else {
-            Probes<W, 1> P;
-#pragma unroll
-            for (int k = 0; k < W; ++k) P.p[k][0] = q[k];
-            const float pr[1] = {0.f};
-            gap = probes_min_gap<W, 1, true>(P, pr, 0.f, S);
-        }
+        const float gap = state_gap<ARM, W, KP>(R, S, q);
         if (ballot(act && !(gap > 0.f)) != 0) {
             free = false;
             break;
@@ -141,8 +127,6 @@ __global__ void __launch_bounds__(kWave) k_shortcut_dp(int d, int K, const float
         cost[b] = total;
     }
 }
-
-static int round8(int k) { return ((k + 7) / 8) * 8; }
 
 hipError_t launch_simplify(const ArmParams *arm, const SceneParams &scene, int wdim, int d, int B, int K, int H,
                            const float *wp, uint8_t *valid, int32_t *idx, int32_t *count, float *cost, float *out_wp,

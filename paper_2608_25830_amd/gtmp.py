@@ -76,6 +76,16 @@ _lib.gtmp_edge_check_cost.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_ro
                                       C.POINTER(gtmp_edge_opts), _vp]
 _lib.gtmp_state_check.argtypes = [C.POINTER(gtmp_robot), C.POINTER(gtmp_scene), C.c_int32, C.c_int64, _vp, _vp,
                                   _vp, _vp]
+class gtmp_rrtc_opts(C.Structure):
+    _fields_ = [("budget", C.c_int32), ("tree_cap", C.c_int32), ("step", C.c_float), ("resolution", C.c_float),
+                ("ell_factor", C.c_float), ("reserved", C.c_int32), ("stats", C.c_void_p)]
+
+
+_lib.gtmp_rrtc_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(C.c_size_t)]
+_lib.gtmp_rrtc_repair.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot), C.POINTER(gtmp_scene)] + \
+    [_vp] * 7 + [C.c_uint64, C.c_uint64, C.POINTER(gtmp_rrtc_opts), _vp, C.c_size_t, _vp]
+_lib.gtmp_rrtc_local_path.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot), C.POINTER(gtmp_scene)] + \
+    [_vp] * 3 + [C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(gtmp_rrtc_opts), _vp, _vp, _vp, _vp]
 _lib.gtmp_simplify_paths.argtypes = [C.POINTER(gtmp_robot), C.POINTER(gtmp_scene), C.c_int32, C.c_int32, C.c_int32,
                                      C.c_int32] + [_vp] * 7
 _lib.gtmp_minplus_sweep.argtypes = [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -152,7 +162,8 @@ EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample
            "gtmp_surrogate_infer", "gtmp_surrogate_grad", "gtmp_surrogate_adam", "gtmp_surrogate_label_states",
            "gtmp_surrogate_prune", "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased",
            "gtmp_class_sweep_workspace_size", "gtmp_class_sweep", "gtmp_class_anytime_workspace_size",
-           "gtmp_plan_classes", "gtmp_simplify_paths"]
+           "gtmp_plan_classes", "gtmp_simplify_paths", "gtmp_rrtc_workspace_size", "gtmp_rrtc_repair",
+           "gtmp_rrtc_local_path"]
 
 
 def _check(st):
@@ -261,6 +272,34 @@ def gtmp_state_check(robot, scene: Scene, d, X, sd=None, coll=None, stream=None)
     n = X.shape[0] if X is not None else 0
     return _check(_lib.gtmp_state_check(C.byref(robot), C.byref(scene.c), int(d), int(n), _p(X), _p(sd), _p(coll),
                                         _stream(stream)))
+
+
+def make_rrtc_opts(budget, tree_cap, step, resolution, ell_factor, stats=None) -> gtmp_rrtc_opts:
+    o = gtmp_rrtc_opts()
+    o.budget, o.tree_cap, o.step, o.resolution, o.ell_factor = int(budget), int(tree_cap), step, resolution, ell_factor
+    if stats is not None:
+        o.stats = stats.data_ptr()
+    return o
+
+
+def gtmp_rrtc_workspace_size(prob) -> int:
+    n = C.c_size_t()
+    _check(_lib.gtmp_rrtc_workspace_size(C.byref(prob), C.byref(n)))
+    return n.value
+
+
+def gtmp_rrtc_repair(prob, robot, scene: Scene, q0, goals, Q, C_s, C_h, C_l, flags, seed, stage, opts, workspace,
+                     stream=None):
+    return _check(_lib.gtmp_rrtc_repair(C.byref(prob), C.byref(robot), C.byref(scene.c), _p(q0), _p(goals), _p(Q),
+                                        _p(C_s), _p(C_h), _p(C_l), _p(flags), seed, stage, C.byref(opts),
+                                        _p(workspace), workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def gtmp_rrtc_local_path(prob, robot, scene: Scene, q0, goals, Q, edge, seed, stage, opts, path, count, cost,
+                         stream=None):
+    return _check(_lib.gtmp_rrtc_local_path(C.byref(prob), C.byref(robot), C.byref(scene.c), _p(q0), _p(goals),
+                                            _p(Q), int(edge), seed, stage, C.byref(opts), _p(path), _p(count),
+                                            _p(cost), _stream(stream)))
 
 
 def gtmp_simplify_paths(robot, scene: Scene, d, H, wp, valid, idx, count, cost, out_wp=None, stream=None):
@@ -423,6 +462,25 @@ class Planner:
         self.sweep(stream)
         self.extract(stream)
         return self.result()
+
+    def repair(self, opts, seed, stage=0, stream=None):
+        """RRT-Connect on the edges whose straight line failed (needs flags)."""
+        if self.flags is None:
+            raise ValueError("repair needs a Planner built with flags=True")
+        if getattr(self, "rrtc_ws", None) is None:
+            self.rrtc_ws = _aligned_workspace(gtmp_rrtc_workspace_size(self.prob), self.Q.device)
+        gtmp_rrtc_repair(self.prob, self.robot, self.scene, self.q0, self.goals, self.Q, self.C_s,
+                         self.C_h if self.M > 1 else None, self.C_l, self.flags, seed, stage, opts, self.rrtc_ws, stream)
+
+    def local_path(self, edge, opts, seed, stage=0, stream=None):
+        """The RRT-Connect path of one edge: (waypoints [n][d] device tensor, cost)."""
+        path = torch.empty((2 * opts.tree_cap, self.d), device=self.Q.device)
+        count = torch.empty((1,), device=self.Q.device, dtype=torch.int32)
+        cost = torch.empty((1,), device=self.Q.device)
+        gtmp_rrtc_local_path(self.prob, self.robot, self.scene, self.q0, self.goals, self.Q, edge, seed, stage, opts,
+                             path, count, cost, stream)
+        n = int(count.item())
+        return path[:n], float(cost.item())
 
     def simplify(self, wp=None, stream=None):
         """Shortcut the extracted path (or the paths wp [B][M+2][d])."""

@@ -243,3 +243,36 @@ def test_simplify_validates(g):
     assert call(2, 4, 8, 8, wp=None) == g.GTMP_EINVAL
     assert call(2, 4, 8, 8, b=[C.c_void_p(256)] * 3 + [None]) == g.GTMP_EINVAL  # cost NULL
     assert call(2, 0, 8, 8, wp=None, b=[None] * 4) == g.GTMP_OK  # nothing to do
+
+
+def test_rrtc_validates(g):
+    p = _prob(g)
+    scene = g.gtmp_scene()
+    scene.wdim = 2
+    robot = g.make_point_robot()
+    n = C.c_size_t()
+    assert g._lib.gtmp_rrtc_workspace_size(C.byref(p), C.byref(n)) == g.GTMP_OK and n.value > 0
+    ok = dict(budget=10, tree_cap=64, step=0.5, resolution=0.1, ell_factor=1.5)
+    bufs = [C.c_void_p(256)] * 7
+
+    def repair(o, ws=C.c_void_p(1 << 20), nbytes=1 << 30, b=bufs):
+        return g._lib.gtmp_rrtc_repair(C.byref(p), C.byref(robot), C.byref(scene), *b, 1, 0, C.byref(o), ws,
+                                       nbytes, None)
+    for k, v in (("budget", 0), ("tree_cap", 1), ("tree_cap", 5000), ("step", 0.0), ("step", float("inf")),
+                 ("resolution", -1.0), ("ell_factor", 0.9), ("ell_factor", float("nan"))):
+        kw = dict(ok)
+        kw[k] = v
+        assert repair(g.make_rrtc_opts(**kw)) == g.GTMP_EINVAL, (k, v)
+    kw = dict(ok, step=100.0, resolution=0.01)  # more than 4096 states per extension
+    assert repair(g.make_rrtc_opts(**kw)) == g.GTMP_EINVAL
+    p3 = _prob(g, d=8, lo=[-1] * 8, hi=[1] * 8)
+    assert g._lib.gtmp_rrtc_repair(C.byref(p3), C.byref(g.make_point_robot()), C.byref(scene), *bufs, 1, 0,
+                                   C.byref(g.make_rrtc_opts(**dict(ok, tree_cap=4096))), C.c_void_p(1 << 20),
+                                   1 << 30, None) == g.GTMP_EINVAL  # LDS limit at d = 8
+    o = g.make_rrtc_opts(**ok)
+    assert repair(o, b=bufs[:6] + [None]) == g.GTMP_EINVAL  # flags NULL
+    assert repair(o, nbytes=16) == g.GTMP_EWORKSPACE
+    assert repair(o, ws=C.c_void_p((1 << 20) + 8)) == g.GTMP_EINVAL  # alignment
+    E = 8 + 2 * 64 + 8
+    assert g._lib.gtmp_rrtc_local_path(C.byref(p), C.byref(robot), C.byref(scene), *bufs[:3], E, 1, 0, C.byref(o),
+                                       *bufs[:3], None) == g.GTMP_EINVAL  # edge out of range
