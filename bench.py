@@ -188,6 +188,141 @@ def bench_restart(args, torch, wl, gtmp):
     print(json.dumps(out), flush=True)
 
 
+RRTC_LP = dict(tree_cap=1024, step=0.4, resolution=0.1, ell_factor=1.5)
+
+
+def bench_rrtc(args, torch, wl, gtmp):
+    """RRT-Connect local planner (the paper's LP budget sweep setting: the
+    7-DoF arm at M = 6 layers of N = 100 samples).  One step = one whole plan:
+    sample, straight-line edge check, RRT-Connect on every edge whose straight
+    line failed between free endpoints, sweep, extract.  Each budget in the
+    sweep is timed over the same stages; budget 1 is the straight line alone
+    (no repair).  The main line reports the budget given by --rrtc-budget."""
+    budgets = [int(b) for b in args.rrtc_budgets.split(",")]
+    if args.rrtc_budget not in budgets:
+        budgets.append(args.rrtc_budget)
+    lp = dict(RRTC_LP, tree_cap=args.rrtc_cap)
+    w = wl.make_workload("arm7", args.scene, M=6, N=100)
+    pl = gtmp.Planner(w, flags=True)
+    d, M, N, H = pl.d, pl.M, pl.N, pl.H
+    f_state = arm_state_flops(d, len(w["sph_link"]), w["obs_spheres"].shape[0], w["obs_boxes"].shape[0], d)
+    stats = torch.zeros(6, device="cuda", dtype=torch.int64)
+    rows = []
+    for B in budgets:
+        opts = gtmp.make_rrtc_opts(B, stats=stats, **lp)
+
+        def one(stage):
+            pl.sample(w["seed"], stage)
+            pl.check()
+            if B > 1:
+                rb.record()
+                pl.repair(opts, w["seed"], stage)
+                re.record()
+            pl.sweep()
+            pl.extract()
+
+        rb, re = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for i in range(args.warmup):
+            one(1_000_000 + i)
+        torch.cuda.synchronize()
+        stats.zero_()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        costs, rep_ms = [], []
+        t0 = time.perf_counter()
+        a.record()
+        for i in range(args.steps):
+            one(i)
+            if B > 1:
+                re.synchronize()
+                rep_ms.append(rb.elapsed_time(re))
+            costs.append(pl.cost[0].clone())
+        b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = a.elapsed_time(b) / args.steps
+        st = stats.cpu().numpy().astype(np.float64) / args.steps
+        c = torch.stack(costs).cpu().numpy().astype(np.float64)
+        solved = c < w["penalty"]
+        rows.append({"budget": B, "ms_per_plan": ms, "plans_per_s": 1e3 / ms, "wall_s": wall,
+                     "rrtc_ms": float(np.mean(rep_ms)) if rep_ms else 0.0,
+                     "solved": int(solved.sum()), "mean_cost_solved": float(c[solved].mean()) if solved.any() else None,
+                     "calls": st[0], "repaired": st[1], "iterations": st[2], "tree_nodes": st[3],
+                     "states_checked": st[4], "nn_distances": st[5]})
+        print(f"[rrtc] budget {B}: {ms:.2f} ms/plan, solved {int(solved.sum())}/{args.steps}", file=sys.stderr,
+              flush=True)
+    main = next(r for r in rows if r["budget"] == args.rrtc_budget)
+    flop = main["states_checked"] * f_state + main["nn_distances"] * 3 * d
+    achieved = flop / (main["rrtc_ms"] / 1e3) / 1e12 if main["rrtc_ms"] > 0 else None
+    out = {
+        "metric": f"plans/s with the RRT-Connect local planner (7-DoF, M=6, N=100, budget {args.rrtc_budget})",
+        "value": main["plans_per_s"],
+        "unit": "plans/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main["ms_per_plan"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"arm7 (M=6, N=100, H={H}, scene seed {w['seed']}), RRT-Connect step "
+                               f"{lp['step']}, resolution {lp['resolution']}, ell "
+                               f"{lp['ell_factor']} |y - x|, tree cap {lp['tree_cap']}",
+                   "M": M, "N": N, "H": H, "d": d, "edges": pl.E},
+        "sweep": rows,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
+                     "kernel": "k_rrtc (one wave per RRT-Connect call; repair time incl. candidate collection)",
+                     "flop_per_state": f_state, "kernel_ms": main["rrtc_ms"]},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = rrtc_cpu_baseline(w, args.rrtc_budget, main["calls"], args.cpu_seconds, lp)
+    print(json.dumps(out), flush=True)
+
+
+def rrtc_cpu_baseline(w, budget, calls_per_plan, min_seconds, lp):
+    """The oracle on the same workload: its straight-line plan timed whole,
+    then RRT-Connect calls on the candidate edges of that plan, in chunks
+    until min_seconds have passed; plans/s = 1 / (plan time + calls per plan
+    / calls per second)."""
+    import oracle
+    import oracle.rrtc as R
+    t0 = time.perf_counter()
+    r = oracle.plan(w)
+    t_plan = time.perf_counter() - t0
+    flat = lambda t: np.concatenate([np.asarray(x).ravel() for x in t])
+    c0, f0 = flat(r["cost"]), flat(r["flag"])
+    o = R.LPOpts(budget, lp["tree_cap"], lp["step"], lp["resolution"], lp["ell_factor"])
+    model = oracle.Model(w)
+    ids = [e for e in np.flatnonzero(f0 == 1)]
+    rng = np.random.default_rng(0)
+    rng.shuffle(ids)
+    X, Y, I = [], [], []
+    for e in ids:
+        x, y = R.edge_endpoints(w, r["Q"], int(e))
+        if (oracle.state_sd(model, np.stack([x, y])) > 0).all():
+            X.append(x)
+            Y.append(y)
+            I.append(int(e))
+        if len(I) >= 20000:
+            break
+    done, t_calls, k = 0, 0.0, 0
+    while t_calls < min_seconds and k < len(I):
+        n = min(256, len(I) - k)
+        t0 = time.perf_counter()
+        R.batch(model, w, np.asarray(X[k:k + n]), np.asarray(Y[k:k + n]), np.asarray(I[k:k + n]), o, w["seed"], 0)
+        t_calls += time.perf_counter() - t0
+        done += n
+        k += n
+    cps = done / t_calls
+    t = t_plan + calls_per_plan / cps
+    return {"value": 1.0 / t, "unit": "plans/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"one straight-line plan ({t_plan:.2f} s) plus {done} RRT-Connect calls at budget {budget} "
+                      f"on uniformly drawn candidate edges of it ({t_calls:.1f} s, {cps:.0f} calls/s), scaled to "
+                      f"{calls_per_plan:.0f} calls per plan", "calls_per_s": cps}
+
+
 def bench_batch(args, torch, wl, gtmp):
     specs = wl.batch_specs(n=args.batch_plans)
     opts = {}
@@ -367,7 +502,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="arm7")
-    ap.add_argument("--form", default="plain", choices=["plain", "batch", "surrogate", "restart", "classes"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batch", "surrogate", "restart", "classes", "rrtc"])
+    ap.add_argument("--rrtc-budgets", default="1,100,400,1000", help="rrtc form: budgets of the sweep")
+    ap.add_argument("--rrtc-budget", type=int, default=400, help="rrtc form: budget of the main line")
+    ap.add_argument("--rrtc-cap", type=int, default=RRTC_LP["tree_cap"], help="rrtc form: nodes per tree")
     ap.add_argument("--classes-n", type=int, default=64, help="classes form: samples per layer")
     ap.add_argument("--no-graph", action="store_true", help="restart form: enqueue stages instead of replaying a graph")
     ap.add_argument("--labels", type=int, default=1 << 20, help="surrogate: label pairs (2x states)")
@@ -410,6 +548,8 @@ def main():
         return bench_restart(args, torch, wl, gtmp)
     if args.form == "classes":
         return bench_classes(args, torch, wl, gtmp)
+    if args.form == "rrtc":
+        return bench_rrtc(args, torch, wl, gtmp)
     w = wl.make_workload(args.workload, args.scene)
     pl = gtmp.Planner(w)
     for kv in args.opt:

@@ -242,7 +242,8 @@ typedef struct gtmp_rrtc_opts {
     float resolution;    /* > 0, step / resolution <= 4096: spacing bound of checked states */
     float ell_factor;    /* >= 1: major axis of the query ellipsoid over |y - x| */
     int32_t reserved;
-    unsigned long long *stats; /* optional device [4]: calls, successes, iterations, tree nodes.  Added to. */
+    unsigned long long *stats; /* optional device [6]: calls, successes, iterations, tree nodes, states
+                                  checked, nearest-node distances evaluated.  Added to. */
 } gtmp_rrtc_opts;
 
 /* Bytes of device workspace gtmp_rrtc_repair needs for this problem. */

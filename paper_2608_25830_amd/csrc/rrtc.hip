@@ -39,7 +39,7 @@ struct RrtcArgs {
     int budget, cap;
     float eta, res, ell_factor;
     uint32_t k0, k1, stage;
-    unsigned long long *stats;  // calls, successes, iterations, nodes
+    unsigned long long *stats;  // calls, successes, iterations, nodes, states checked, nearest-node distances
     // single-edge outputs (path mode)
     float *path;
     int32_t *path_count;
@@ -123,7 +123,7 @@ struct RrtcCall {
     RrtcLds L;
     int lane;
     int n0, n1;  // node counts of the x and y trees (scalars: no dynamically indexed array)
-    unsigned long long it_count;
+    unsigned long long it_count, states, dists;
 
     __device__ __forceinline__ int count(int t) const { return t ? n1 : n0; }
 
@@ -134,6 +134,7 @@ struct RrtcCall {
         const int d = A.d;
         const int nt = count(t);
         if (nt >= A.cap) return kTrapped;
+        dists += (unsigned long long)nt;
         float best = __builtin_inff();
         int bi = 0x7fffffff;
         for (int j = lane; j < nt; j += kWave) {
@@ -176,6 +177,7 @@ struct RrtcCall {
             for (int i = 0; i < D; ++i)
                 s[i] = i < d ? (h == Hs - 1 ? qn[i] : __builtin_fmaf(tt, qn[i] - p[i], p[i])) : 0.f;
             const float gap = state_gap<ARM, W, KP>(R, S, s);
+            states += (unsigned long long)(Hs - h0 < kWave ? Hs - h0 : kWave);
             if (ballot(act && !(gap > 0.f)) != 0) return kTrapped;
         }
         const int k = nt;
@@ -348,7 +350,7 @@ __global__ void __launch_bounds__(kWave) k_rrtc(RrtcArgs A, ArmParams R, ScenePa
     L.par = reinterpret_cast<int32_t *>(lds + (size_t)2 * d * A.cap);
     L.H = reinterpret_cast<float *>(L.par + 2 * A.cap);
     L.chain = reinterpret_cast<int32_t *>(L.H + GTMP_MAX_DOF * GTMP_MAX_DOF);
-    RrtcCall<ARM, W, KP> c{A, R, S, L, (int)threadIdx.x, 1, 1, 0ull};
+    RrtcCall<ARM, W, KP> c{A, R, S, L, (int)threadIdx.x, 1, 1, 0ull, 0ull, 0ull};
     unsigned long long calls = 0, wins = 0, nodes = 0;
     if (A.cand == nullptr) {  // one edge, path mode
         if (blockIdx.x != 0) return;
@@ -384,6 +386,8 @@ __global__ void __launch_bounds__(kWave) k_rrtc(RrtcArgs A, ArmParams R, ScenePa
         atomicAdd(&A.stats[1], wins);
         atomicAdd(&A.stats[2], c.it_count);
         atomicAdd(&A.stats[3], nodes);
+        atomicAdd(&A.stats[4], c.states);
+        atomicAdd(&A.stats[5], c.dists);
     }
 }
 

@@ -13,17 +13,29 @@ struct StateDim {
     static constexpr int D = ARM ? GTMP_MAX_JOINTS : W;
 };
 
+// Arm spheres BASE .. KP-1 in chunks of KC (fewer live registers than all
+// KP at once); the minimum over chunks is the minimum over all spheres.
+template <int KC, int BASE, int KP, bool UNIFORM>
+__device__ __forceinline__ float arm_gap_chunked(const ArmParams &R, const v32f &o, const SceneParams &S) {
+    Probes<3, KC> P;
+    arm_spheres<KC, BASE>(R, o, P);
+    float pr[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) pr[k] = BASE + k < R.n_spheres ? R.r[BASE + k] : 0.f;
+    const float g = probes_min_gap<3, KC, UNIFORM>(P, pr, R.r0, S);
+    if constexpr (BASE + KC < KP)
+        return __builtin_fminf(g, arm_gap_chunked<KC, BASE + KC, KP, UNIFORM>(R, o, S));
+    else
+        return g;
+}
+
 template <bool ARM, int W, int KP>
 __device__ __forceinline__ float state_gap(const ArmParams &R, const SceneParams &S,
                                            const float (&q)[StateDim<ARM, W>::D]) {
     if constexpr (ARM) {
+        constexpr int KC = KP >= 32 ? KP / 2 : KP;
         const v32f o = arm_fk<GTMP_MAX_JOINTS>(R, q);
-        Probes<3, KP> P;
-        arm_spheres<KP>(R, o, P);
-        float pr[KP];
-#pragma unroll
-        for (int k = 0; k < KP; ++k) pr[k] = k < R.n_spheres ? R.r[k] : 0.f;
-        return R.uniform_r ? probes_min_gap<3, KP, true>(P, pr, R.r0, S) : probes_min_gap<3, KP, false>(P, pr, R.r0, S);
+        return R.uniform_r ? arm_gap_chunked<KC, 0, KP, true>(R, o, S) : arm_gap_chunked<KC, 0, KP, false>(R, o, S);
     } else {
         Probes<W, 1> P;
 #pragma unroll

@@ -34,7 +34,7 @@ def _flat(t):
 def _run(gt, orc, name, scene, N, M, lp, seed=17, stage=0):
     w = wl.make_workload(name, scene, N=N, M=M)
     o = R.LPOpts(*lp)
-    stats = torch.zeros(4, device="cuda", dtype=torch.int64)
+    stats = torch.zeros(6, device="cuda", dtype=torch.int64)
     opts = gt.make_rrtc_opts(o.budget, o.cap, o.eta, o.res, o.ell_factor, stats)
     pl = gt.Planner(w, flags=True)
     pl.sample(w["seed"], 0)
@@ -131,7 +131,7 @@ def test_free_scene_has_no_candidates(gt):
     w = wl.make_workload("2d-small", 0, N=16, M=3)
     w["circles"] = np.zeros((0, 3), np.float32)
     w["boxes"] = np.zeros((0, 4), np.float32)
-    stats = torch.zeros(4, device="cuda", dtype=torch.int64)
+    stats = torch.zeros(6, device="cuda", dtype=torch.int64)
     pl = gt.Planner(w, flags=True)
     pl.sample(w["seed"], 0)
     pl.check()
