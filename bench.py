@@ -43,8 +43,7 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
 # still hash to the fingerprint it was measured on.
 MEASURED_TRAFFIC = {"arm7": (4.518e+08, "492e89ae80300518", "profiles/k_interior_arm7.md")}
 KERNEL_SOURCES = ["paper_2608_25830_amd/csrc/edge.hip", "paper_2608_25830_amd/csrc/edge_common.hpp",
-                  "paper_2608_25830_amd/csrc/gtmp_device.hpp",
-                  "paper_2608_25830_amd/csrc/gtmp_launch.hpp"]
+                  "paper_2608_25830_amd/csrc/gtmp_device.hpp"]
 
 
 def kernel_fingerprint():
@@ -188,7 +187,79 @@ def bench_restart(args, torch, wl, gtmp):
     print(json.dumps(out), flush=True)
 
 
-RRTC_LP = dict(tree_cap=1024, step=0.4, resolution=0.1, ell_factor=1.5)
+def bench_lazy(args, torch, wl, gtmp):
+    """Lazy edge realisation against the full check on the same plans: one
+    step = one whole plan (sample, then rounds of sweep / extract / check of
+    the selected edges), per band; the full plan beside it.  Every lazy cost
+    must equal the full plan's bit for bit."""
+    w = wl.make_workload(args.workload, args.scene)
+    bands = [float(b) for b in args.lazy_bands.split(",")]
+    full = gtmp.Planner(w, flags=True)
+    lazy = gtmp.Planner(w, flags=True)
+    stats = torch.zeros(2, device="cuda", dtype=torch.int64)
+
+    def timed(fn):
+        for i in range(args.warmup):
+            fn(1_000_000 + i)
+        torch.cuda.synchronize()
+        out, ms = [], []
+        for i in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            a.record()
+            extra = fn(i)
+            b.record()
+            b.synchronize()
+            ms.append((a.elapsed_time(b), (time.perf_counter() - t0) * 1e3))
+            out.append((float(full.cost.item()) if extra is None else float(lazy.cost.item()), extra))
+        return out, ms
+
+    def run_full(i):
+        full.plan(w["seed"], i)
+        return None
+
+    full_out, full_ms = timed(run_full)
+    rows = []
+    for band in bands:
+        def run(i):
+            stats.zero_()
+            st, r = lazy.plan_lazy(w["seed"], i, band=band, max_rounds=args.lazy_rounds, stats=stats)
+            known = int((lazy.flags != 0xFF).sum().item())
+            return (st, r, int(stats[1].item()), known)
+        out, ms = timed(run)
+        same = all(o[0] == f[0] for o, f in zip(out, full_out))
+        rows.append({"band": band, "ms_per_plan_host": float(np.mean([m[1] for m in ms])),
+                     "rounds": float(np.mean([o[1][1] for o in out])),
+                     "checked_frac": float(np.mean([o[1][2] for o in out])) / full.E,
+                     "known_frac": float(np.mean([o[1][3] for o in out])) / full.E,
+                     "complete": all(o[1][0] == gtmp.GTMP_OK for o in out), "cost_equals_full": same})
+        print(f"[lazy] band {band}: {rows[-1]['ms_per_plan_host']:.2f} ms, rounds {rows[-1]['rounds']:.1f}, "
+              f"checked {rows[-1]['checked_frac']:.4f}, same cost {same}", file=sys.stderr, flush=True)
+    best = min(rows, key=lambda r: r["ms_per_plan_host"])
+    full_host = float(np.mean([m[1] for m in full_ms]))
+    out = {
+        "metric": f"plans/s, lazy edge realisation ({args.workload}, best band {best['band']})",
+        "value": 1e3 / best["ms_per_plan_host"],
+        "unit": "plans/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": best["ms_per_plan_host"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {w['kind']} d={w['d']}, M={w['M']}, N={w['N']}, H={w['H']}, "
+                               f"scene seed {w['seed']}", "edges": full.E},
+        "full_check_ms_per_plan": full_host,
+        "full_check_ms_per_plan_gpu": float(np.mean([m[0] for m in full_ms])),
+        "bands": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+RRTC_LP = dict(tree_cap=512, step=0.4, resolution=0.1, ell_factor=1.5)
 
 
 def bench_rrtc(args, torch, wl, gtmp):
@@ -502,8 +573,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="arm7")
-    ap.add_argument("--form", default="plain", choices=["plain", "batch", "surrogate", "restart", "classes", "rrtc"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batch", "surrogate", "restart", "classes", "rrtc",
+                                                              "lazy"])
     ap.add_argument("--rrtc-budgets", default="1,100,400,1000", help="rrtc form: budgets of the sweep")
+    ap.add_argument("--lazy-bands", default="0.1,0.5,2", help="lazy form: selection bands")
+    ap.add_argument("--lazy-rounds", type=int, default=100000, help="lazy form: round limit")
     ap.add_argument("--rrtc-budget", type=int, default=400, help="rrtc form: budget of the main line")
     ap.add_argument("--rrtc-cap", type=int, default=RRTC_LP["tree_cap"], help="rrtc form: nodes per tree")
     ap.add_argument("--classes-n", type=int, default=64, help="classes form: samples per layer")
@@ -550,6 +624,8 @@ def main():
         return bench_classes(args, torch, wl, gtmp)
     if args.form == "rrtc":
         return bench_rrtc(args, torch, wl, gtmp)
+    if args.form == "lazy":
+        return bench_lazy(args, torch, wl, gtmp)
     w = wl.make_workload(args.workload, args.scene)
     pl = gtmp.Planner(w)
     for kv in args.opt:
@@ -569,6 +645,7 @@ def main():
 
     # per-step kernel events and counter snapshots stay on the device until the end
     kb, ke = make_events(args.steps), make_events(args.steps)
+    sb = make_events(args.steps + 1)  # step boundaries
     stats_hist = torch.zeros((args.steps + 1, 4), device="cuda", dtype=torch.int64)
     cost_hist = torch.zeros((args.steps,), device="cuda")
     start = torch.cuda.Event(enable_timing=True)
@@ -578,17 +655,20 @@ def main():
     start.record()
     stats_hist[0].copy_(pl.stats)
     for i in range(args.steps):
+        sb[i].record()
         pl.opts.ev_begin = kb[i].cuda_event
         pl.opts.ev_end = ke[i].cuda_event
         pl.plan(w["seed"], i)
         stats_hist[i + 1].copy_(pl.stats)
         cost_hist[i].copy_(pl.cost[0])
+    sb[args.steps].record()
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     total_ms = start.elapsed_time(stop)
     ms_per_step = total_ms / args.steps
     kernel_ms = [kb[i].elapsed_time(ke[i]) for i in range(args.steps)]
+    step_ms = np.array([sb[i].elapsed_time(sb[i + 1]) for i in range(args.steps)])
     states = torch.diff(stats_hist[:, 0]).cpu().numpy().astype(np.float64)
     costs = cost_hist.cpu().numpy()
 
@@ -631,6 +711,8 @@ def main():
         "edge_opts": {k: int(getattr(pl.opts, k)) for k in ("mode", "states_per_iter", "blocks_per_cu",
                                                                "sphere_chunks")},
         "mean_path_cost": float(np.mean(costs)),
+        "step_ms_median": float(np.median(step_ms)),
+        "step_ms_iqr": [float(np.percentile(step_ms, 25)), float(np.percentile(step_ms, 75))],
         "wall_s": wall,
     }
     out["simplify"] = simplify_report(args, torch, gtmp, w, pl)

@@ -40,6 +40,7 @@ extern "C" {
 typedef int gtmp_status;
 #define GTMP_OK 0
 #define GTMP_ENOPATH 1      /* informational: the graph holds no feasible chain */
+#define GTMP_INCOMPLETE 2   /* informational: a round limit stopped an iterative call early */
 #define GTMP_EINVAL (-1)    /* invalid argument; nothing was enqueued */
 #define GTMP_EHIP (-2)      /* a HIP call failed */
 #define GTMP_EWORKSPACE (-3) /* workspace too small */
@@ -237,7 +238,7 @@ gtmp_status gtmp_simplify_paths(const gtmp_robot *robot, const gtmp_scene *scene
  * x to y. */
 typedef struct gtmp_rrtc_opts {
     int32_t budget;      /* s >= 1: iterations per call (one sample each) */
-    int32_t tree_cap;    /* nodes per tree, 2 .. 4096, with the LDS limit: 4 (2 d + 4) tree_cap + 256 <= 163840 */
+    int32_t tree_cap;    /* nodes per tree, 2 .. 4096, with the LDS limit 4 (2 d + 4) tree_cap + 256 <= 155648 */
     float step;          /* eta > 0: extension step (configuration units) */
     float resolution;    /* > 0, step / resolution <= 4096: spacing bound of checked states */
     float ell_factor;    /* >= 1: major axis of the query ellipsoid over |y - x| */
@@ -271,6 +272,35 @@ gtmp_status gtmp_rrtc_local_path(const gtmp_problem *prob, const gtmp_robot *rob
                                  const float *q0, const float *goals, const float *Q, uint64_t edge, uint64_t seed,
                                  uint64_t stage, const gtmp_rrtc_opts *opts, float *path, int32_t *count, float *cost,
                                  void *stream);
+
+/* -------------------------------------------- lazy edge realisation */
+/* The lazy variant the paper names as future work (realise only a subset of
+ * the adjacent-layer pairs).  Every edge starts at its optimistic cost: its
+ * length, or length + penalty when an endpoint collides or it exceeds
+ * max_edge_len (known without a check).  Rounds of: backward sweep and
+ * extraction (as gtmp_minplus_sweep / gtmp_extract_path); stop when every
+ * edge of the extracted path has been checked; else the forward sweep
+ * F[m][v] = min_u F[m-1][u] + C(u, v) and a straight-line check (the fast
+ * mode of gtmp_edge_check_cost) of the unchecked edges of the extracted path
+ * and of every unchecked edge (u, v) whose best path through it,
+ * F(u) + C(u, v) + V(v), costs at most (1 + band) V_s.
+ * Checked costs are the true ones and unchecked ones are lower bounds, so
+ * the final path is optimal for the fully checked graph and its cost equals
+ * the full check's V_s (the same FP32 edge costs summed in the same order).
+ *   Q, q0, goals, C_*, V, A, V_s, a_s, idx, wp, cost  as for the plain calls
+ *   flags   device uint8 [E], written: 0 free, 1 failed, 0xFF not checked
+ *   band    >= 0; 0 checks only edges on currently optimal paths
+ *   max_rounds  >= 1: rounds before giving up (GTMP_INCOMPLETE is returned
+ *           and the path may hold unchecked edges)
+ *   stats   optional device [2]: rounds, edges checked.  Added to.
+ *   rounds  optional host int32 [1]: rounds run
+ * The call reads one flag back per round (it synchronises `stream`). */
+gtmp_status gtmp_lazy_workspace_size(const gtmp_problem *prob, size_t *bytes);
+gtmp_status gtmp_plan_lazy(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                           const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
+                           uint8_t *flags, float *V, int32_t *A, float *V_s, int32_t *a_s, int32_t *idx, float *wp,
+                           float *cost, float band, int32_t max_rounds, unsigned long long *stats, int32_t *rounds,
+                           void *workspace, size_t ws_bytes, const gtmp_edge_opts *edge_opts, void *stream);
 
 /* --------------------------------------------------- a5 min-plus sweep */
 /* Backward value iteration on the layered DAG (Sec. IV-B; Alg. 1):

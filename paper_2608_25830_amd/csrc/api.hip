@@ -125,6 +125,7 @@ const char *gtmp_status_string(gtmp_status s) {
     switch (s) {
         case GTMP_OK: return "GTMP_OK";
         case GTMP_ENOPATH: return "GTMP_ENOPATH";
+        case GTMP_INCOMPLETE: return "GTMP_INCOMPLETE";
         case GTMP_EINVAL: return "GTMP_EINVAL";
         case GTMP_EHIP: return "GTMP_EHIP";
         case GTMP_EWORKSPACE: return "GTMP_EWORKSPACE";
@@ -227,8 +228,8 @@ static gtmp_status check_rrtc(const gtmp_problem *prob, const gtmp_rrtc_opts *o)
     if (!o) return fail(GTMP_EINVAL, "opts is NULL");
     if (o->budget < 1) return fail(GTMP_EINVAL, "budget=%d < 1", o->budget);
     if (o->tree_cap < 2 || o->tree_cap > 4096) return fail(GTMP_EINVAL, "tree_cap=%d outside 2..4096", o->tree_cap);
-    if (gtmp::rrtc_lds_bytes(prob->d, o->tree_cap) > 163840)
-        return fail(GTMP_EINVAL, "tree_cap=%d needs more than 160 KiB of LDS at d=%d", o->tree_cap, prob->d);
+    if (gtmp::rrtc_lds_bytes(prob->d, o->tree_cap, 0) > 163840 - 8192)
+        return fail(GTMP_EINVAL, "tree_cap=%d needs more than 152 KiB of LDS at d=%d", o->tree_cap, prob->d);
     if (!(o->step > 0.f) || !std::isfinite(o->step)) return fail(GTMP_EINVAL, "step must be finite and > 0");
     if (!(o->resolution > 0.f) || !std::isfinite(o->resolution))
         return fail(GTMP_EINVAL, "resolution must be finite and > 0");
@@ -288,6 +289,50 @@ gtmp_status gtmp_rrtc_local_path(const gtmp_problem *prob, const gtmp_robot *rob
     return hip_status(gtmp::launch_rrtc_path(*prob, is_arm ? &arm : nullptr, sp, scene->wdim, q0, goals, Q, edge, seed,
                                              stage, *opts, path, count, cost, (hipStream_t)stream),
                       "gtmp_rrtc_local_path");
+}
+
+gtmp_status gtmp_lazy_workspace_size(const gtmp_problem *prob, size_t *bytes) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::make_lazy_plan(*prob).total;
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_plan_lazy(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                           const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
+                           uint8_t *flags, float *V, int32_t *A, float *V_s, int32_t *a_s, int32_t *idx, float *wp,
+                           float *cost, float band, int32_t max_rounds, unsigned long long *stats, int32_t *rounds,
+                           void *workspace, size_t ws_bytes, const gtmp_edge_opts *edge_opts, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    gtmp::ArmParams arm{};
+    gtmp::SceneParams sp{};
+    bool is_arm = false;
+    st = check_model(robot, scene, prob->d, &arm, &is_arm, &sp);
+    if (st != GTMP_OK) return st;
+    if (!(band >= 0.f) || !std::isfinite(band)) return fail(GTMP_EINVAL, "band must be finite and >= 0");
+    if (max_rounds < 1) return fail(GTMP_EINVAL, "max_rounds=%d < 1", max_rounds);
+    if (!q0 || !goals || !Q || !C_s || !C_l || !flags || !V || !A || !V_s || !a_s || !idx || !wp || !cost ||
+        !workspace)
+        return fail(GTMP_EINVAL, "NULL buffer");
+    if (prob->M > 1 && !C_h) return fail(GTMP_EINVAL, "C_h is NULL with M > 1");
+    const size_t need = gtmp::make_lazy_plan(*prob).total;
+    if (ws_bytes < need) return fail(GTMP_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(GTMP_EINVAL, "workspace must be 256-byte aligned");
+    gtmp_edge_opts eo{};
+    if (edge_opts) eo = *edge_opts;
+    int r = 0;
+    bool done = false;
+    st = hip_status(gtmp::launch_plan_lazy(*prob, is_arm ? &arm : nullptr, sp, scene->wdim, q0, goals, Q, C_s, C_h, C_l,
+                                           flags, V, A, V_s, a_s, idx, wp, cost, band, max_rounds, stats, eo,
+                                           workspace, &r, &done, (hipStream_t)stream),
+                    "gtmp_plan_lazy");
+    if (st != GTMP_OK) return st;
+    if (rounds) *rounds = r;
+    return done ? GTMP_OK : GTMP_INCOMPLETE;
 }
 
 gtmp_status gtmp_minplus_sweep(int32_t M, int32_t N, int32_t G, const float *C_s, const float *C_h, const float *C_l,

@@ -39,6 +39,7 @@ EdgePlan make_edge_plan(const gtmp_problem &p) {
     e.off_vflag = o; o = up(o + e.n_vertices);
     e.off_tile_off = o; o = up(o + (size_t)e.n_tiles * kTile);
     e.off_tile_cnt = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
+    e.off_tile_list = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
     e.off_counter = o; o = up(o + 256);
     e.off_params = o; o = up(o + sizeof(ArmParams));
     e.total = o;
@@ -165,13 +166,13 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
     const uint32_t n = seg * kTile + threadIdx.x;
     const bool valid = n < (uint32_t)A.N;
     bool cand = false;
-    if (valid) {
+    const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
+    if (valid && (!A.select || A.select[e] != 0)) {
         const uint32_t uid = ri.u_base + n * ri.u_step, vid = ri.v_base + n * ri.v_step;
         float u[D], v[D];
         load_vertex<D>(A, uid, u);
         load_vertex<D>(A, vid, v);
         const float len = edge_len<D>(u, v, A.d);
-        const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
         bool failed = (A.vflag[uid] | A.vflag[vid]) != 0 || len > A.max_len;
         if (A.prune) failed = failed || A.prune[e] != 0;
         ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
@@ -189,7 +190,10 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
         total += wave_cnt[k];
     }
     if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
-    if (threadIdx.x == 0) A.tile_cnt[tile] = total;
+    if (threadIdx.x == 0) {
+        A.tile_cnt[tile] = total;
+        if (A.tile_list && total) A.tile_list[atomicAdd(A.counter + 1, 1u)] = tile;
+    }
 }
 
 // ------------------------------------------------------------------ 3. interior
@@ -214,6 +218,7 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interi
     __syncthreads();
 
     const int lane = lane_id();
+    const uint32_t n_tiles = A.tile_list ? A.counter[1] : A.n_tiles;
 
     // wave-uniform tile state
     uint32_t tile = 0, cnt = 0, pos = 0;
@@ -240,13 +245,13 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interi
                 uint32_t t = 0;
                 if (lane == 0) t = atomicAdd(A.counter, 1u);
                 t = uniform(t);
-                if (t >= A.n_tiles) {
+                if (t >= n_tiles) {
                     exhausted = true;
                     break;
                 }
-                tile = t;
-                ri = decode_row(A, t / A.tiles_per_row);
-                cnt = uniform(A.tile_cnt[t]);
+                tile = A.tile_list ? uniform(A.tile_list[t]) : t;
+                ri = decode_row(A, tile / A.tiles_per_row);
+                cnt = uniform(A.tile_cnt[tile]);
                 pos = 0;
                 continue;
             }
@@ -484,12 +489,15 @@ static int round_kp(int k) { return ((k + 7) / 8) * 8; }
 template <int KP, int NCH>
 static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, const EdgeBuffers &b,
                                 const gtmp_edge_opts &o, int grid_persist, hipStream_t s, const float *q0,
-                                const float *goals, const float *Q, float *verts, uint8_t *vflag) {
+                                const float *goals, const float *Q, float *verts, uint8_t *vflag, int phases) {
     const unsigned vb = (A.n_vertices + 255) / 256;
-    hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
-    hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
     ArmParams *Rg = reinterpret_cast<ArmParams *>(static_cast<char *>(b.workspace) + A.off_params);
-    hipLaunchKernelGGL(k_store_params_tol, dim3(1), dim3(64), 0, s, R, Rg, S);
+    if (phases & kPhaseVertices) {
+        hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
+        hipLaunchKernelGGL(k_store_params_tol, dim3(1), dim3(64), 0, s, R, Rg, S);
+    }
+    if (!(phases & kPhaseEdges)) return hipGetLastError();
+    hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
@@ -519,9 +527,11 @@ static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const Sc
 template <int W>
 static hipError_t launch_point(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, int spi,
                                int grid_persist, const gtmp_edge_opts &o, hipStream_t s, const float *q0,
-                               const float *goals, const float *Q, float *verts, uint8_t *vflag) {
+                               const float *goals, const float *Q, float *verts, uint8_t *vflag, int phases) {
     const unsigned vb = (A.n_vertices + 255) / 256;
-    hipLaunchKernelGGL(k_vertices_point<W>, dim3(vb), dim3(256), 0, s, A, S, q0, goals, Q, verts, vflag);
+    if (phases & kPhaseVertices)
+        hipLaunchKernelGGL(k_vertices_point<W>, dim3(vb), dim3(256), 0, s, A, S, q0, goals, Q, verts, vflag);
+    if (!(phases & kPhaseEdges)) return hipGetLastError();
     hipLaunchKernelGGL(k_prepass<W>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
     switch (spi) {
         case 1: return launch_point_s<W, 1>(A, R, S, grid_persist, o, s);
@@ -556,6 +566,12 @@ constexpr int kPointBlocksPerCuAuto = 3;
 
 hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s) {
+    return launch_edge_phases(plan, arm, scene, wdim, b, o, s, nullptr, kPhaseVertices | kPhaseEdges);
+}
+
+hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
+                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s, const uint8_t *select,
+                              int phases) {
     EdgeArgs A{};
     A.d = plan.d; A.M = plan.M; A.N = plan.N; A.G = plan.G; A.H = plan.H; A.dp = vertex_stride(plan.d);
     A.penalty = plan.penalty; A.max_len = plan.max_len;
@@ -564,10 +580,11 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
     float *verts = reinterpret_cast<float *>(ws + plan.off_verts);
     uint8_t *vflag = reinterpret_cast<uint8_t *>(ws + plan.off_vflag);
     A.verts = verts; A.vflag = vflag;
-    A.C_s = b.C_s; A.C_h = b.C_h; A.C_l = b.C_l; A.flags = b.flags; A.prune = b.prune;
+    A.C_s = b.C_s; A.C_h = b.C_h; A.C_l = b.C_l; A.flags = b.flags; A.prune = b.prune; A.select = select;
     A.tile_off = reinterpret_cast<uint8_t *>(ws + plan.off_tile_off);
     A.tile_cnt = reinterpret_cast<uint32_t *>(ws + plan.off_tile_cnt);
     A.counter = reinterpret_cast<uint32_t *>(ws + plan.off_counter);
+    A.tile_list = select ? reinterpret_cast<uint32_t *>(ws + plan.off_tile_list) : nullptr;
     A.stats = o.stats;
     A.off_params = plan.off_params;
     uint8_t order[GTMP_MAX_H];
@@ -616,7 +633,7 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
 
     // fast mode: reset the tile cursor with a fill kernel (no memset node, so
     // the sequence can be captured into a graph and replayed)
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, A.counter, 1);
+    if (phases & kPhaseEdges) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, A.counter, 2);
     if (arm) {
         const int kp = round_kp(R.n_spheres);
         const int nch = o.sphere_chunks == 1 ? 1 : o.sphere_chunks == 4 ? 4 : 2;
@@ -631,7 +648,7 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
         }
         const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
         switch (kp * 8 + nch) {
-#define GTMP_LA(K, C) case K * 8 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag);
+#define GTMP_LA(K, C) case K * 8 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag, phases);
 #define GTMP_LA3(K) GTMP_LA(K, 1) GTMP_LA(K, 2) GTMP_LA(K, 4)
             GTMP_LA3(8) GTMP_LA3(16) GTMP_LA3(24) GTMP_LA3(32) GTMP_LA3(40) GTMP_LA3(48) GTMP_LA3(56) GTMP_LA3(64)
 #undef GTMP_LA3
@@ -648,14 +665,14 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const S
                          : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true, 1>
                                     : (const void *)k_interior<PointModel<2, 8>, true, 1>;
         const int grid = persistent_grid(kern, 256, o.blocks_per_cu, kPointBlocksPerCuAuto);
-        return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag);
+        return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases);
     }
     const void *kern = spi == 1 ? (const void *)k_interior<PointModel<3, 1>, true, 1>
                      : spi == 2 ? (const void *)k_interior<PointModel<3, 2>, true, 1>
                      : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true, 1>
                                 : (const void *)k_interior<PointModel<3, 8>, true, 1>;
     const int grid = persistent_grid(kern, 256, o.blocks_per_cu, kPointBlocksPerCuAuto);
-    return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag);
+    return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases);
 }
 
 hipError_t launch_state_check(const ArmParams *arm, const SceneParams &scene, int wdim, int d, int64_t n,

@@ -16,9 +16,11 @@ struct EdgeArgs {
     float *C_s, *C_h, *C_l;
     uint8_t *flags;
     const uint8_t *__restrict__ prune;
+    const uint8_t *__restrict__ select;  // lazy rounds: only edges with select[e] != 0 are touched
     uint8_t *tile_off;
     uint32_t *tile_cnt;
-    uint32_t *counter;  // [0] tile cursor of the interior kernel
+    uint32_t *counter;  // [0] tile cursor of the interior kernel, [1] length of tile_list
+    uint32_t *tile_list;  // lazy rounds: the tiles holding candidates (NULL: every tile in order)
     unsigned long long *stats;
     size_t off_params;  // workspace byte offset of the device copy of the robot table
     int n_int;

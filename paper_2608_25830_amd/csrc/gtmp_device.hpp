@@ -13,6 +13,12 @@ namespace gtmp {
 
 constexpr int kWave = 64;
 
+// Vertex stride (floats) of the packed vertex array used by the edge kernels:
+// every vertex takes GTMP_MAX_DOF floats (zero padded), 32-byte aligned.
+inline int vertex_stride(int) { return GTMP_MAX_DOF; }
+
+constexpr int kTile = 256;  // edges per pre-pass tile (one block, one edge per thread)
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64-bit products whose halves are mixed with the other counter words

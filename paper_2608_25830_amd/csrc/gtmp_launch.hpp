@@ -15,11 +15,6 @@
 
 namespace gtmp {
 
-// Vertex stride (floats) of the packed vertex array used by the edge kernels:
-// every vertex takes GTMP_MAX_DOF floats (zero padded), 32-byte aligned.
-inline int vertex_stride(int) { return GTMP_MAX_DOF; }
-
-constexpr int kTile = 256;  // edges per pre-pass tile (one block, one edge per thread)
 
 struct EdgePlan {
     // sizes
@@ -31,7 +26,7 @@ struct EdgePlan {
     uint32_t tiles_per_row;  // ceil(N / kTile)
     uint32_t n_tiles;
     // workspace carve-up (byte offsets)
-    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_counter, off_params, total;
+    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_tile_list, off_counter, off_params, total;
 };
 
 EdgePlan make_edge_plan(const gtmp_problem &p);
@@ -48,6 +43,14 @@ struct EdgeBuffers {
 hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm /* NULL = point robot */,
                              const SceneParams &scene, int wdim, const EdgeBuffers &b, const gtmp_edge_opts &o,
                              hipStream_t s);
+// The fast-mode check in phases: kPhaseVertices packs the vertices and their
+// collision flags into the workspace; kPhaseEdges runs the pre-pass and the
+// interior checks, on the edges with select[e] != 0 only when select is given
+// (the others are left as they are).
+constexpr int kPhaseVertices = 1, kPhaseEdges = 2;
+hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
+                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s, const uint8_t *select,
+                              int phases);
 
 hipError_t launch_state_check(const ArmParams *arm, const SceneParams &scene, int wdim, int d, int64_t n,
                               const float *X, float *sd, uint8_t *coll, hipStream_t s);
@@ -132,7 +135,7 @@ struct RrtcPlan {
     size_t off_counters, off_vfree, off_cand, total;
 };
 RrtcPlan make_rrtc_plan(const gtmp_problem &p);
-size_t rrtc_lds_bytes(int d, int cap);
+size_t rrtc_lds_bytes(int d, int cap, int obstacle_floats);
 hipError_t launch_rrtc_repair(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,
                               const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
                               uint8_t *flags, uint64_t seed, uint64_t stage, const gtmp_rrtc_opts &o, void *workspace,
@@ -140,6 +143,18 @@ hipError_t launch_rrtc_repair(const gtmp_problem &p, const ArmParams *arm, const
 hipError_t launch_rrtc_path(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,
                             const float *q0, const float *goals, const float *Q, uint64_t edge, uint64_t seed,
                             uint64_t stage, const gtmp_rrtc_opts &o, float *path, int32_t *count, float *cost,
+                            hipStream_t s);
+
+// ---- lazy edge realisation (lazy.hip)
+struct LazyPlan {
+    size_t off_edge, off_F, off_select, off_counters, total;
+};
+LazyPlan make_lazy_plan(const gtmp_problem &p);
+hipError_t launch_plan_lazy(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,
+                            const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
+                            uint8_t *flags, float *V, int32_t *Am, float *V_s, int32_t *a_s, int32_t *idx, float *wp,
+                            float *cost, float band, int max_rounds, unsigned long long *stats,
+                            const gtmp_edge_opts &eo, void *workspace, int *rounds_host, bool *done_host,
                             hipStream_t s);
 
 // ---- batched plans (batch.hip)

@@ -11,8 +11,9 @@
 //            (the sequential result);
 //   nearest  lanes stride over the tree, (squared distance, index) butterfly
 //            with the lowest index on ties;
-//   check    lanes take the states of the extension segment, a ballot ends
-//            it at the first colliding state.
+//   check    the states of the extension segment, each shared by 64 / s
+//            lanes that split the obstacles between them (s states at a
+//            time, a power of two), a ballot ends it at a colliding state.
 // This file is compiled without floating-point contraction: sampling, nearest
 // node and steering are FP32 computations with a fixed operation order (see
 // include/gtmp.h), so the trees are reproducible bit for bit.
@@ -22,6 +23,7 @@
 namespace gtmp {
 
 constexpr int kRrtcAttempts = 4096;
+constexpr int kRrtcLdsObstacles = 2048;  // obstacle floats held in LDS (more: read from global memory)
 enum { kTrapped = 0, kAdvanced = 1, kReached = 2 };
 
 struct RrtcArgs {
@@ -163,21 +165,28 @@ struct RrtcCall {
         const bool reached = dist <= A.eta;
         const float f = A.eta / dist;
         for (int i = 0; i < GTMP_MAX_DOF; ++i) qn[i] = i < d ? (reached ? q[i] : p[i] + f * (q[i] - p[i])) : 0.f;
-        // the segment p -> qn at H_s states; p itself is a tree node (free)
+        // the segment p -> qn at H_s states; p itself is a tree node (free).
+        // spr states per round (a power of two), lps = 64 / spr lanes sharing
+        // each state's obstacles
         const float len = __builtin_sqrtf(f32_d2(d, p, qn));
         int Hs = (int)__builtin_ceilf(len / A.res) + 1;
         Hs = Hs < 2 ? 2 : Hs;
         const float den = (float)(Hs - 1);
-        for (int h0 = 1; h0 < Hs; h0 += kWave) {
-            const int h = h0 + lane;
+        int lg = 0;
+        while ((1 << lg) < Hs - 1 && lg < 6) ++lg;
+        const int spr = 1 << lg, lgl = 6 - lg, lps = 1 << lgl;
+        const int sl = lane >> lgl, part = lane & (lps - 1);
+        for (int h0 = 1; h0 < Hs; h0 += spr) {
+            const int h = h0 + sl;
             const bool act = h < Hs;
             const float tt = (float)(act ? h : 1) / den;
             float s[D];
 #pragma unroll
             for (int i = 0; i < D; ++i)
                 s[i] = i < d ? (h == Hs - 1 ? qn[i] : __builtin_fmaf(tt, qn[i] - p[i], p[i])) : 0.f;
-            const float gap = state_gap<ARM, W, KP>(R, S, s);
-            states += (unsigned long long)(Hs - h0 < kWave ? Hs - h0 : kWave);
+            float gap = state_gap_part<ARM, W, KP>(R, S, s, part, lps);
+            for (int off = lps >> 1; off > 0; off >>= 1) gap = __builtin_fminf(gap, __shfl_xor(gap, off));
+            states += (unsigned long long)(Hs - h0 < spr ? Hs - h0 : spr);
             if (ballot(act && !(gap > 0.f)) != 0) return kTrapped;
         }
         const int k = nt;
@@ -341,8 +350,10 @@ struct RrtcCall {
     }
 };
 
-template <bool ARM, int W, int KP>
-__global__ void __launch_bounds__(kWave) k_rrtc(RrtcArgs A, ArmParams R, SceneParams S) {
+// OCC: waves per SIMD the register allocation is made for (2 when the trees
+// are small enough for 8 blocks per CU, else 1: more registers, no spills)
+template <bool ARM, int W, int KP, int OCC>
+__global__ void __launch_bounds__(kWave, OCC) k_rrtc(RrtcArgs A, ArmParams R, SceneParams Sg) {
     extern __shared__ float lds[];
     const int d = A.d;
     RrtcLds L;
@@ -350,6 +361,21 @@ __global__ void __launch_bounds__(kWave) k_rrtc(RrtcArgs A, ArmParams R, ScenePa
     L.par = reinterpret_cast<int32_t *>(lds + (size_t)2 * d * A.cap);
     L.H = reinterpret_cast<float *>(L.par + 2 * A.cap);
     L.chain = reinterpret_cast<int32_t *>(L.H + GTMP_MAX_DOF * GTMP_MAX_DOF);
+    // obstacles copied into LDS when they fit (the extension checks read them
+    // with per-lane indices)
+    SceneParams S = Sg;
+    {
+        constexpr int PW = ARM ? 3 : W;
+        const int ns = Sg.n_sph * (PW + 1), nb = Sg.n_box * 2 * PW;
+        if (ns + nb <= kRrtcLdsObstacles) {
+            float *obs = reinterpret_cast<float *>(L.chain + 2 * A.cap);
+            for (int i = threadIdx.x; i < ns; i += kWave) obs[i] = Sg.sph[i];
+            for (int i = threadIdx.x; i < nb; i += kWave) obs[ns + i] = Sg.box[i];
+            S.sph = obs;
+            S.box = obs + ns;
+            __syncthreads();
+        }
+    }
     RrtcCall<ARM, W, KP> c{A, R, S, L, (int)threadIdx.x, 1, 1, 0ull, 0ull, 0ull};
     unsigned long long calls = 0, wins = 0, nodes = 0;
     if (A.cand == nullptr) {  // one edge, path mode
@@ -445,8 +471,9 @@ RrtcPlan make_rrtc_plan(const gtmp_problem &p) {
     return r;
 }
 
-size_t rrtc_lds_bytes(int d, int cap) {
-    return sizeof(float) * ((size_t)2 * d * cap + (size_t)2 * cap + GTMP_MAX_DOF * GTMP_MAX_DOF + (size_t)2 * cap);
+size_t rrtc_lds_bytes(int d, int cap, int obstacle_floats) {
+    const size_t obs = obstacle_floats <= kRrtcLdsObstacles ? (size_t)obstacle_floats : 0;
+    return sizeof(float) * ((size_t)2 * d * cap + (size_t)2 * cap + GTMP_MAX_DOF * GTMP_MAX_DOF + (size_t)2 * cap + obs);
 }
 
 static RrtcArgs rrtc_args(const gtmp_problem &p, const float *q0, const float *goals, const float *Q, float *C_s,
@@ -472,12 +499,18 @@ template <bool ARM, int W, int KP>
 static hipError_t launch_rrtc_kernels(const RrtcArgs &A, const ArmParams &R, const SceneParams &S, uint64_t E,
                                       float max_len, uint8_t *vfree, uint32_t *cand, uint32_t *counters, bool single,
                                       hipStream_t s) {
-    const size_t lds = rrtc_lds_bytes(A.d, A.cap);
-    const void *kern = (const void *)k_rrtc<ARM, W, KP>;
+    constexpr int PW = ARM ? 3 : W;
+    const size_t lds = rrtc_lds_bytes(A.d, A.cap, S.n_sph * (PW + 1) + S.n_box * 2 * PW);
+    // 8 blocks (two waves per SIMD) fit in the 160 KiB of LDS of a CU?
+    const bool two = lds * 8 <= 163840;
+    const void *kern = two ? (const void *)k_rrtc<ARM, W, KP, 2> : (const void *)k_rrtc<ARM, W, KP, 1>;
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (single) {
-        hipLaunchKernelGGL((k_rrtc<ARM, W, KP>), dim3(1), dim3(kWave), lds, s, A, R, S);
+        if (two)
+            hipLaunchKernelGGL((k_rrtc<ARM, W, KP, 2>), dim3(1), dim3(kWave), lds, s, A, R, S);
+        else
+            hipLaunchKernelGGL((k_rrtc<ARM, W, KP, 1>), dim3(1), dim3(kWave), lds, s, A, R, S);
         return hipGetLastError();
     }
     const uint32_t nv = 1 + (uint32_t)A.M * A.N + A.G;
@@ -496,7 +529,10 @@ static hipError_t launch_rrtc_kernels(const RrtcArgs &A, const ArmParams &R, con
     }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kWave, lds) != hipSuccess || occ <= 0) occ = 1;
     occ = occ < 16 ? occ : 16;
-    hipLaunchKernelGGL((k_rrtc<ARM, W, KP>), dim3(cus * occ), dim3(kWave), lds, s, B, R, S);
+    if (two)
+        hipLaunchKernelGGL((k_rrtc<ARM, W, KP, 2>), dim3(cus * occ), dim3(kWave), lds, s, B, R, S);
+    else
+        hipLaunchKernelGGL((k_rrtc<ARM, W, KP, 1>), dim3(cus * occ), dim3(kWave), lds, s, B, R, S);
     return hipGetLastError();
 }
 

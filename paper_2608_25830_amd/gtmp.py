@@ -27,7 +27,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-GTMP_OK, GTMP_ENOPATH, GTMP_EINVAL, GTMP_EHIP, GTMP_EWORKSPACE = 0, 1, -1, -2, -3
+GTMP_OK, GTMP_ENOPATH, GTMP_INCOMPLETE, GTMP_EINVAL, GTMP_EHIP, GTMP_EWORKSPACE = 0, 1, 2, -1, -2, -3
 GTMP_MAX_DOF, GTMP_MAX_JOINTS, GTMP_MAX_ROBOT_SPHERES, GTMP_MAX_H = 8, 8, 64, 256
 GTMP_ROBOT_POINT, GTMP_ROBOT_DH_ARM = 0, 1
 GTMP_CHECK_FAST, GTMP_CHECK_FULL = 0, 1
@@ -86,6 +86,9 @@ _lib.gtmp_rrtc_repair.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot)
     [_vp] * 7 + [C.c_uint64, C.c_uint64, C.POINTER(gtmp_rrtc_opts), _vp, C.c_size_t, _vp]
 _lib.gtmp_rrtc_local_path.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot), C.POINTER(gtmp_scene)] + \
     [_vp] * 3 + [C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(gtmp_rrtc_opts), _vp, _vp, _vp, _vp]
+_lib.gtmp_lazy_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(C.c_size_t)]
+_lib.gtmp_plan_lazy.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot), C.POINTER(gtmp_scene)] + \
+    [_vp] * 14 + [C.c_float, C.c_int32, _vp, C.POINTER(C.c_int32), _vp, C.c_size_t, C.POINTER(gtmp_edge_opts), _vp]
 _lib.gtmp_simplify_paths.argtypes = [C.POINTER(gtmp_robot), C.POINTER(gtmp_scene), C.c_int32, C.c_int32, C.c_int32,
                                      C.c_int32] + [_vp] * 7
 _lib.gtmp_minplus_sweep.argtypes = [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -163,7 +166,7 @@ EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample
            "gtmp_surrogate_prune", "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased",
            "gtmp_class_sweep_workspace_size", "gtmp_class_sweep", "gtmp_class_anytime_workspace_size",
            "gtmp_plan_classes", "gtmp_simplify_paths", "gtmp_rrtc_workspace_size", "gtmp_rrtc_repair",
-           "gtmp_rrtc_local_path"]
+           "gtmp_rrtc_local_path", "gtmp_lazy_workspace_size", "gtmp_plan_lazy"]
 
 
 def _check(st):
@@ -300,6 +303,24 @@ def gtmp_rrtc_local_path(prob, robot, scene: Scene, q0, goals, Q, edge, seed, st
     return _check(_lib.gtmp_rrtc_local_path(C.byref(prob), C.byref(robot), C.byref(scene.c), _p(q0), _p(goals),
                                             _p(Q), int(edge), seed, stage, C.byref(opts), _p(path), _p(count),
                                             _p(cost), _stream(stream)))
+
+
+def gtmp_lazy_workspace_size(prob) -> int:
+    n = C.c_size_t()
+    _check(_lib.gtmp_lazy_workspace_size(C.byref(prob), C.byref(n)))
+    return n.value
+
+
+def gtmp_plan_lazy(prob, robot, scene: Scene, q0, goals, Q, C_s, C_h, C_l, flags, V, A, V_s, a_s, idx, wp, cost,
+                   band, max_rounds, workspace, stats=None, edge_opts=None, stream=None):
+    """Returns (status, rounds): status GTMP_OK, or GTMP_INCOMPLETE at the round limit."""
+    r = C.c_int32(0)
+    st = _check(_lib.gtmp_plan_lazy(C.byref(prob), C.byref(robot), C.byref(scene.c), _p(q0), _p(goals), _p(Q),
+                                    _p(C_s), _p(C_h), _p(C_l), _p(flags), _p(V), _p(A), _p(V_s), _p(a_s), _p(idx),
+                                    _p(wp), _p(cost), float(band), int(max_rounds), _p(stats), C.byref(r),
+                                    _p(workspace), workspace.numel() * workspace.element_size(),
+                                    C.byref(edge_opts) if edge_opts is not None else None, _stream(stream)))
+    return st, r.value
 
 
 def gtmp_simplify_paths(robot, scene: Scene, d, H, wp, valid, idx, count, cost, out_wp=None, stream=None):
@@ -481,6 +502,18 @@ class Planner:
                              path, count, cost, stream)
         n = int(count.item())
         return path[:n], float(cost.item())
+
+    def plan_lazy(self, seed, stage=0, band=0.0, max_rounds=1000, stats=None, stream=None):
+        """Sample, then the lazy plan (needs flags): (status, rounds)."""
+        if self.flags is None:
+            raise ValueError("plan_lazy needs a Planner built with flags=True")
+        if getattr(self, "lazy_ws", None) is None:
+            self.lazy_ws = _aligned_workspace(gtmp_lazy_workspace_size(self.prob), self.Q.device)
+        self.sample(seed, stage, stream)
+        return gtmp_plan_lazy(self.prob, self.robot, self.scene, self.q0, self.goals, self.Q, self.C_s,
+                              self.C_h if self.M > 1 else None, self.C_l, self.flags, self.V, self.A, self.V_s,
+                              self.a_s, self.idx, self.wp, self.cost, band, max_rounds, self.lazy_ws, stats,
+                              self.opts, stream)
 
     def simplify(self, wp=None, stream=None):
         """Shortcut the extracted path (or the paths wp [B][M+2][d])."""

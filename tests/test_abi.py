@@ -276,3 +276,25 @@ def test_rrtc_validates(g):
     E = 8 + 2 * 64 + 8
     assert g._lib.gtmp_rrtc_local_path(C.byref(p), C.byref(robot), C.byref(scene), *bufs[:3], E, 1, 0, C.byref(o),
                                        *bufs[:3], None) == g.GTMP_EINVAL  # edge out of range
+
+
+def test_lazy_validates(g):
+    p = _prob(g)
+    scene = g.gtmp_scene()
+    scene.wdim = 2
+    robot = g.make_point_robot()
+    n = C.c_size_t()
+    assert g._lib.gtmp_lazy_workspace_size(C.byref(p), C.byref(n)) == g.GTMP_OK and n.value > 0
+    bufs = [C.c_void_p(256)] * 14
+    r = C.c_int32(0)
+
+    def call(band=0.1, rounds=10, b=bufs, ws=C.c_void_p(1 << 20), nbytes=1 << 30):
+        return g._lib.gtmp_plan_lazy(C.byref(p), C.byref(robot), C.byref(scene), *b, band, rounds, None,
+                                     C.byref(r), ws, nbytes, None, None)
+    assert call(band=-0.1) == g.GTMP_EINVAL
+    assert call(band=float("inf")) == g.GTMP_EINVAL
+    assert call(rounds=0) == g.GTMP_EINVAL
+    assert call(b=bufs[:6] + [None] + bufs[7:]) == g.GTMP_EINVAL  # flags NULL
+    assert call(nbytes=16) == g.GTMP_EWORKSPACE
+    assert call(ws=C.c_void_p((1 << 20) + 4)) == g.GTMP_EINVAL
+    assert g._lib.gtmp_status_string(g.GTMP_INCOMPLETE) == b"GTMP_INCOMPLETE"
