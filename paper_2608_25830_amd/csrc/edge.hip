@@ -203,7 +203,9 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
 // fewer live probe registers buy a higher occupancy for a few per-obstacle
 // set-up instructions more.
 
-template <class Model, bool UNIFORM_R, int NCH>
+// LIST: tiles come from the compacted list of a lazy round (a separate
+// instantiation, so the full check's kernel carries no extra live state).
+template <class Model, bool UNIFORM_R, int NCH, bool LIST = false>
 __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interior(EdgeArgs A, const ArmParams *Rg,
                                                                                SceneParams S) {
     constexpr int D = Model::D;
@@ -218,7 +220,8 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interi
     __syncthreads();
 
     const int lane = lane_id();
-    const uint32_t n_tiles = A.tile_list ? A.counter[1] : A.n_tiles;
+    uint32_t n_tiles = A.n_tiles;
+    if constexpr (LIST) n_tiles = A.counter[1];
 
     // wave-uniform tile state
     uint32_t tile = 0, cnt = 0, pos = 0;
@@ -249,7 +252,8 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interi
                     exhausted = true;
                     break;
                 }
-                tile = A.tile_list ? uniform(A.tile_list[t]) : t;
+                tile = t;
+                if constexpr (LIST) tile = uniform(A.tile_list[t]);
                 ri = decode_row(A, tile / A.tiles_per_row);
                 cnt = uniform(A.tile_cnt[tile]);
                 pos = 0;
@@ -501,6 +505,11 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    } else if (A.tile_list) {  // lazy round: two sphere chunks, compacted tiles
+        if (R.uniform_r)
+            hipLaunchKernelGGL((k_interior<ArmModel<KP>, true, 2, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
+        else
+            hipLaunchKernelGGL((k_interior<ArmModel<KP>, false, 2, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     } else if (R.uniform_r) {
         hipLaunchKernelGGL((k_interior<ArmModel<KP>, true, NCH>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     } else {
@@ -517,6 +526,9 @@ static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const Sc
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.n_int == 0)
         hipLaunchKernelGGL(k_finalize_no_interior<W>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    else if (A.tile_list)  // lazy round: 8 states per lane, compacted tiles
+        hipLaunchKernelGGL((k_interior<PointModel<W, 8>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A,
+                           (const ArmParams *)nullptr, S);
     else
         hipLaunchKernelGGL((k_interior<PointModel<W, SPI>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A,
                            (const ArmParams *)nullptr, S);
