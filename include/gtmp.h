@@ -396,6 +396,9 @@ typedef struct gtmp_anytime_opts {
                                               (gtmp_expand_samples_biased), NULL = off */
     int32_t simplify;           /* nonzero: shortcut each stage's path (simp() of Alg. 1, by
                                    gtmp_simplify_paths); needs M + 2 <= 64 (M_max + 2 growing) */
+    const struct gtmp_rrtc_opts *lp; /* non-NULL: after each stage's straight-line check, the
+                                        RRT-Connect repair (gtmp_rrtc_repair, keyed by seed and
+                                        the stage index); use_graph is then ignored */
 } gtmp_anytime_opts;
 
 /* Bytes of device workspace gtmp_plan_anytime needs (sizes of prob for a

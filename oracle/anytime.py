@@ -121,10 +121,27 @@ def expand_samples(w, Q, M, N, c_best, seed, stage, bias=None, trace=None):
     return Q
 
 
-def _plan_on(w, Qarr):
+def _plan_on(w, Qarr, lp=None, seed=0, stage=0):
+    """The plain plan on samples Qarr; with ``lp`` (oracle.rrtc.LPOpts) the
+    RRT-Connect repair (keyed by seed and stage) runs on the straight-line
+    costs before the sweep."""
     ww = dict(w)
     ww["M"], ww["N"] = Qarr.shape[0], Qarr.shape[1]
-    return O.plan(ww, Q=Qarr)
+    r = O.plan(ww, Q=Qarr)
+    if lp is None:
+        return r
+    import oracle.rrtc as RR
+    M, N = Qarr.shape[0], Qarr.shape[1]
+    G = np.asarray(ww["goals"]).reshape(-1, ww["d"]).shape[0]
+    flat = np.concatenate([np.asarray(x).ravel() for x in r["cost"]])
+    fflag = np.concatenate([np.asarray(x).ravel() for x in r["flag"]])
+    cost, flag, info = RR.repair(ww, Qarr, flat, fflag, lp, seed, stage)
+    cost3 = O.split_edges(cost, M, N, G)
+    V, A, Vs, a_s = O.minplus(*cost3)
+    idx, wp, c, rc = O.extract(A, a_s, Vs, Qarr, ww["q0"], ww["goals"])
+    r.update(cost=cost3, flag=O.split_edges(flag, M, N, G), V=V, A=A, Vs=Vs, a_s=a_s, idx=idx, wp=wp,
+             path_cost=c, no_path=rc, lp_info=info)
+    return r
 
 
 def _shortcut(w, r):
@@ -135,7 +152,7 @@ def _shortcut(w, r):
     return (None, np.inf) if kept is None else (wp[kept], c)
 
 
-def plan_restart(w, stages, seed, simplify=False):
+def plan_restart(w, stages, seed, simplify=False, lp=None):
     """Anytime-GTMP (Alg. 1; Sec. IV-D) with |K| = 1: stage s plans on the
     samples of key (seed, s); the archive keeps the lowest cost (strictly
     lower replaces, so ties keep the earlier stage).  With ``simplify`` a
@@ -146,7 +163,7 @@ def plan_restart(w, stages, seed, simplify=False):
     per_stage = []
     for s in range(stages):
         Q = O.sample_layers(w["M"], w["N"], w["d"], w["lo"], w["hi"], seed, s)
-        r = _plan_on(w, Q)
+        r = _plan_on(w, Q, lp, seed, s)
         per_stage.append(r["path_cost"])
         if r["path_cost"] < best["cost"]:
             if not simplify:
@@ -175,12 +192,13 @@ def growing_schedule(M_min, M_max, N_min, N_max, max_stages):
     return out
 
 
-def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None, trace=None, simplify=False):
+def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None, trace=None, simplify=False, lp=None):
     """AO-GTMP (Alg. 1; Sec. IV-E): expand the samples under the current
     cost bound, plan, keep the best, grow the budget (``bias`` as in
     expand_samples).  With ``simplify`` every stage path is shortcut first
     (Alg. 1: P_i = simp(gtmp(...))) and the shortcut lengths are compared,
-    so the best shortcut length bounds the informed sampler."""
+    so the best shortcut length bounds the informed sampler.  ``lp`` runs the
+    RRT-Connect repair in every stage (see _plan_on)."""
     d = w["d"]
     best = dict(cost=np.inf, stage=-1, idx=None)
     per_stage, stages = [], []
@@ -190,7 +208,7 @@ def plan_growing(w, M_min, M_max, N_min, N_max, max_stages, seed, bias=None, tra
             Q = [np.zeros((0, d), np.float32) for _ in range(M)]
         Q = expand_samples(w, Q, M, N, best["cost"], seed, s, bias, trace)
         Qarr = np.stack(Q).astype(np.float32)
-        r = _plan_on(w, Qarr)
+        r = _plan_on(w, Qarr, lp, seed, s)
         c, wp = r["path_cost"], None
         if simplify:
             ww = dict(w)

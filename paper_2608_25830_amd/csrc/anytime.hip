@@ -523,6 +523,10 @@ AnytimePlan make_anytime_plan(const gtmp_problem &p, const gtmp_anytime_opts &o)
     if (o.simplify) {
         a.off_simp = off; off = up256(off + simp_bytes((int)M + 2, (int)d));
     }
+    if (o.lp) {  // edge flags and the RRT-Connect repair's buffers
+        a.off_flags = off; off = up256(off + N + (M > 1 ? M - 1 : 0) * N * N + N * G);
+        a.off_rrtc = off; off = up256(off + make_rrtc_plan(big).total);
+    }
     const EdgePlan ep = make_edge_plan(big);
     a.off_edge = off; off = up256(off + ep.total);
     if (o.mode == GTMP_ANYTIME_GROWING) {
@@ -574,9 +578,15 @@ hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const Sce
 
     auto one_plan = [&](const gtmp_problem &pp, const float *Qp, hipStream_t st) -> hipError_t {
         const EdgePlan ep = make_edge_plan(pp);
-        EdgeBuffers b{q0, goals, Qp, Cs, Ch, Cl, nullptr, nullptr, nullptr, edge_ws};
+        uint8_t *flags = o.lp ? reinterpret_cast<uint8_t *>(ws + a.off_flags) : nullptr;
+        EdgeBuffers b{q0, goals, Qp, Cs, Ch, Cl, nullptr, flags, nullptr, edge_ws};
         hipError_t e = launch_edge_check(ep, arm, scene, wdim, b, eo, st);
         if (e != hipSuccess) return e;
+        if (o.lp) {  // the stage index is the device counter's value during the stage
+            e = launch_rrtc_repair(pp, arm, scene, wdim, q0, goals, Qp, Cs, Ch, Cl, flags, seed, 0, *o.lp,
+                                   ws + a.off_rrtc, st, counter);
+            if (e != hipSuccess) return e;
+        }
         e = launch_minplus(pp.M, pp.N, pp.G, Cs, Ch, Cl, nullptr, V, A, Vs, as, st);
         if (e != hipSuccess) return e;
         e = launch_extract(pp.M, pp.N, pp.G, d, as, A, Vs, Qp, q0, goals, idx, wp, cost, st);
@@ -604,7 +614,7 @@ hipError_t launch_anytime(const gtmp_problem &p, const ArmParams *arm, const Sce
                                Q);
             return one_plan(p, Q, st);
         };
-        if (!o.use_graph) {
+        if (!o.use_graph || o.lp) {
             for (int r = 0; r < o.max_stages; ++r) {
                 hipError_t e = stage_ops(s);
                 if (e != hipSuccess) return e;

@@ -446,6 +446,15 @@ static gtmp_status check_anytime(const gtmp_problem *prob, const gtmp_anytime_op
         const int Mx = o->mode == GTMP_ANYTIME_GROWING ? o->M_max : prob->M;
         if (Mx + 2 > 64) return fail(GTMP_EINVAL, "simplify needs at most 64 waypoints (M=%d)", Mx);
     }
+    if (o->lp) {
+        gtmp_problem big = *prob;
+        if (o->mode == GTMP_ANYTIME_GROWING) {
+            big.M = o->M_max > 0 ? o->M_max : prob->M;
+            big.N = o->N_max > 0 ? o->N_max : prob->N;
+        }
+        gtmp_status st = check_rrtc(&big, o->lp);
+        if (st != GTMP_OK) return st;
+    }
     if (o->mode == GTMP_ANYTIME_RESTART) return check_problem(prob);
     if (o->mode != GTMP_ANYTIME_GROWING) return fail(GTMP_EINVAL, "unknown anytime mode %d", o->mode);
     if (o->M_min < 1 || o->M_min > o->M_max) return fail(GTMP_EINVAL, "need 1 <= M_min <= M_max");

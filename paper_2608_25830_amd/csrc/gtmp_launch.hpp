@@ -86,8 +86,8 @@ hipError_t launch_informed_batch(const gtmp_problem &p, const float *q0, const f
 
 struct AnytimePlan {
     gtmp_problem big;  // sizes the buffers are carved for
-    size_t off_Q, off_Q2, off_Cs, off_Ch, off_Cl, off_V, off_A, off_small, off_counter, off_simp, off_edge, off_expand,
-        total;
+    size_t off_Q, off_Q2, off_Cs, off_Ch, off_Cl, off_V, off_A, off_small, off_counter, off_simp, off_flags, off_rrtc,
+        off_edge, off_expand, total;
 };
 AnytimePlan make_anytime_plan(const gtmp_problem &p, const gtmp_anytime_opts &o);
 
@@ -139,7 +139,7 @@ size_t rrtc_lds_bytes(int d, int cap, int obstacle_floats);
 hipError_t launch_rrtc_repair(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,
                               const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
                               uint8_t *flags, uint64_t seed, uint64_t stage, const gtmp_rrtc_opts &o, void *workspace,
-                              hipStream_t s);
+                              hipStream_t s, const uint32_t *stage_dev = nullptr);
 hipError_t launch_rrtc_path(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,
                             const float *q0, const float *goals, const float *Q, uint64_t edge, uint64_t seed,
                             uint64_t stage, const gtmp_rrtc_opts &o, float *path, int32_t *count, float *cost,

@@ -41,6 +41,7 @@ struct RrtcArgs {
     int budget, cap;
     float eta, res, ell_factor;
     uint32_t k0, k1, stage;
+    const uint32_t *stage_dev;  // when set, the stage is read here at kernel start (replayed graphs)
     unsigned long long *stats;  // calls, successes, iterations, nodes, states checked, nearest-node distances
     // single-edge outputs (path mode)
     float *path;
@@ -124,6 +125,7 @@ struct RrtcCall {
     const SceneParams &S;
     RrtcLds L;
     int lane;
+    uint32_t stage;
     int n0, n1;  // node counts of the x and y trees (scalars: no dynamically indexed array)
     unsigned long long it_count, states, dists;
 
@@ -206,8 +208,8 @@ struct RrtcCall {
         const int d = A.d;
         for (int base = 0; base < kRrtcAttempts; base += kWave) {
             const uint32_t a = (uint32_t)(base + lane);
-            const uint4 w0 = philox4x32_10(make_uint4(e, it, A.stage, (3u << 16) | (2u * a)), A.k0, A.k1);
-            const uint4 w1 = philox4x32_10(make_uint4(e, it, A.stage, (3u << 16) | (2u * a + 1u)), A.k0, A.k1);
+            const uint4 w0 = philox4x32_10(make_uint4(e, it, stage, (3u << 16) | (2u * a)), A.k0, A.k1);
+            const uint4 w1 = philox4x32_10(make_uint4(e, it, stage, (3u << 16) | (2u * a + 1u)), A.k0, A.k1);
             float y[GTMP_MAX_DOF], x[GTMP_MAX_DOF];
             float s2 = 0.0f;
             for (int i = 0; i < GTMP_MAX_DOF; ++i) {
@@ -376,7 +378,8 @@ __global__ void __launch_bounds__(kWave, OCC) k_rrtc(RrtcArgs A, ArmParams R, Sc
             __syncthreads();
         }
     }
-    RrtcCall<ARM, W, KP> c{A, R, S, L, (int)threadIdx.x, 1, 1, 0ull, 0ull, 0ull};
+    const uint32_t stage = A.stage_dev ? *A.stage_dev : A.stage;
+    RrtcCall<ARM, W, KP> c{A, R, S, L, (int)threadIdx.x, stage, 1, 1, 0ull, 0ull, 0ull};
     unsigned long long calls = 0, wins = 0, nodes = 0;
     if (A.cand == nullptr) {  // one edge, path mode
         if (blockIdx.x != 0) return;
@@ -556,12 +559,13 @@ static hipError_t dispatch_rrtc(const ArmParams *arm, int wdim, const RrtcArgs &
 hipError_t launch_rrtc_repair(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,
                               const float *q0, const float *goals, const float *Q, float *C_s, float *C_h, float *C_l,
                               uint8_t *flags, uint64_t seed, uint64_t stage, const gtmp_rrtc_opts &o, void *workspace,
-                              hipStream_t s) {
+                              hipStream_t s, const uint32_t *stage_dev) {
     const RrtcPlan plan = make_rrtc_plan(p);
     char *ws = static_cast<char *>(workspace);
     const uint64_t N = p.N, M = p.M, G = p.G;
     const uint64_t E = N + (M - 1) * N * N + N * G;
     RrtcArgs A = rrtc_args(p, q0, goals, Q, C_s, C_h, C_l, flags, seed, stage, o);
+    A.stage_dev = stage_dev;
     return dispatch_rrtc(arm, wdim, A, S, E, p.max_edge_len, reinterpret_cast<uint8_t *>(ws + plan.off_vfree),
                          reinterpret_cast<uint32_t *>(ws + plan.off_cand),
                          reinterpret_cast<uint32_t *>(ws + plan.off_counters), false, s);

@@ -98,7 +98,7 @@ _lib.gtmp_extract_path.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _
 class gtmp_anytime_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_stages", C.c_int32), ("M_min", C.c_int32), ("M_max", C.c_int32),
                 ("N_min", C.c_int32), ("N_max", C.c_int32), ("use_graph", C.c_int32), ("bias_tau", C.c_float),
-                ("bias_net", C.c_void_p), ("simplify", C.c_int32)]
+                ("bias_net", C.c_void_p), ("simplify", C.c_int32), ("lp", C.c_void_p)]
 
 
 GTMP_ANYTIME_RESTART, GTMP_ANYTIME_GROWING = 0, 1
@@ -530,7 +530,7 @@ class AnytimePlanner:
     the workload's M, N; growing: the schedule's maxima)."""
 
     def __init__(self, w, mode, max_stages, M_min=None, M_max=None, N_min=None, N_max=None, use_graph=False,
-                 device="cuda", bias=None, bias_tau=0.0, simplify=False):
+                 device="cuda", bias=None, bias_tau=0.0, simplify=False, lp=None):
         self.w = w
         d, M, N, G, H = (int(w[k]) for k in ("d", "M", "N", "G", "H"))
         self.d = d
@@ -541,6 +541,9 @@ class AnytimePlanner:
         self.opts.N_min, self.opts.N_max = N_min or N, N_max or N
         self.opts.use_graph = int(use_graph)
         self.opts.simplify = int(simplify)
+        self.lp = lp  # a gtmp_rrtc_opts (kept alive for the struct's pointer)
+        if lp is not None:
+            self.opts.lp = C.cast(C.pointer(lp), C.c_void_p).value
         self.bias = bias  # a Surrogate (kept alive for the struct's pointer)
         if bias is not None:
             self.opts.bias_net = C.cast(C.pointer(bias.c), C.c_void_p).value

@@ -298,3 +298,18 @@ def test_lazy_validates(g):
     assert call(nbytes=16) == g.GTMP_EWORKSPACE
     assert call(ws=C.c_void_p((1 << 20) + 4)) == g.GTMP_EINVAL
     assert g._lib.gtmp_status_string(g.GTMP_INCOMPLETE) == b"GTMP_INCOMPLETE"
+
+
+def test_anytime_lp_option_validates(g):
+    p = _prob(g)
+    o = g.gtmp_anytime_opts()
+    o.mode, o.max_stages = g.GTMP_ANYTIME_RESTART, 3
+    n = C.c_size_t()
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_OK
+    n0 = n.value
+    lp = g.make_rrtc_opts(20, 64, 0.5, 0.1, 1.5)
+    o.lp = C.cast(C.pointer(lp), C.c_void_p).value
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_OK and n.value > n0
+    bad = g.make_rrtc_opts(0, 64, 0.5, 0.1, 1.5)  # budget 0
+    o.lp = C.cast(C.pointer(bad), C.c_void_p).value
+    assert g._lib.gtmp_anytime_workspace_size(C.byref(p), C.byref(o), C.byref(n)) == g.GTMP_EINVAL

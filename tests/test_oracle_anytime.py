@@ -248,3 +248,18 @@ def test_growing_with_shortcuts_bounds_by_the_shortcut_length():
     ww = dict(w)
     ww["M"], ww["N"] = best["M"], best["N"]
     assert best["cost"] == pytest.approx(_polyline_ok(ww, best["wp"]), rel=1e-12)
+
+
+def test_restart_with_rrt_connect_lowers_every_stage():
+    """The RRT-Connect repair only replaces failed costs by local path
+    lengths, so each stage's optimum can only drop; a stage whose straight-
+    line plan needs a failed edge is solved when the repair connects one."""
+    import oracle.rrtc as R
+    w = wl.make_workload("2d-small", 1, N=24, M=3)
+    lp = R.LPOpts(budget=40, cap=128, eta=1.0, res=0.1, ell_factor=1.5)
+    plain, c0 = OA.plan_restart(w, 4, w["seed"])
+    best, c1 = OA.plan_restart(w, 4, w["seed"], lp=lp)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(c0, c1))
+    assert best["cost"] <= plain["cost"]
+    assert any(b < a for a, b in zip(c0, c1))
+    assert all(c < w["penalty"] for c in c1)
