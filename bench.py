@@ -716,9 +716,29 @@ def main():
         "wall_s": wall,
     }
     out["simplify"] = simplify_report(args, torch, gtmp, w, pl)
+    out["lazy"] = lazy_report(args, torch, gtmp, w, costs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, min_seconds=args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def lazy_report(args, torch, gtmp, w, costs, band=0.2):
+    """Outside the timed region: the same stages planned lazily (checks
+    only near the optimum, reading back one flag per round), timed on the
+    host clock; every cost must equal the timed plans' bit for bit."""
+    lz = gtmp.Planner(w, flags=True)
+    lz.plan_lazy(w["seed"], 1_000_000, band=band)  # warm-up
+    torch.cuda.synchronize()
+    ms, same, rounds = [], True, []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        st, r = lz.plan_lazy(w["seed"], i, band=band)
+        c = float(lz.cost.item())
+        ms.append((time.perf_counter() - t0) * 1e3)
+        same = same and st == gtmp.GTMP_OK and c == float(costs[i])
+        rounds.append(r)
+    return {"band": band, "ms_per_plan": float(np.mean(ms)), "plans_per_s": 1e3 / float(np.mean(ms)),
+            "rounds_mean": float(np.mean(rounds)), "costs_equal_full_check": bool(same)}
 
 
 def simplify_report(args, torch, gtmp, w, pl):
