@@ -68,7 +68,8 @@ def arm_state_flops(n_joints, n_spheres, n_obs_sph, n_obs_box, d):
 
 
 def point_state_flops(n_circ, n_box, d):
-    """Point robot: lerp 2d, circle 2 sub + 2 fma + min = 7 (2D), box 2 med3 + 2 sub + 2 fma + min = 9."""
+    """Point robot in R^d: lerp 2d; per circle/sphere d sub + d fma (2 FLOP) + min; per box d med3 + d sub +
+    d fma + min (7 and 9 FLOP in 2D)."""
     return 2 * d + n_circ * (d + 2 * d + 1) + n_box * (2 * d + 2 * d + 1) + 0
 
 
@@ -676,7 +677,8 @@ def main():
     if w["kind"] == "arm":
         f_state = arm_state_flops(d, len(w["sph_link"]), w["obs_spheres"].shape[0], w["obs_boxes"].shape[0], d)
     else:
-        f_state = point_state_flops(w["circles"].shape[0], w["boxes"].shape[0], d)
+        sph, box = (w["circles"], w["boxes"]) if w["kind"] == "point2d" else (w["obs_spheres"], w["obs_boxes"])
+        f_state = point_state_flops(sph.shape[0], box.shape[0], d)
     k_ms = float(np.mean(kernel_ms))
     st = float(np.mean(states))
     achieved = st * f_state / (k_ms / 1e3) / 1e12
@@ -686,7 +688,8 @@ def main():
         if fp == kernel_fingerprint():
             traffic, traffic_src = tb, src
     out = {
-        "metric": "edge-states checked/sec (7-DoF, N=2048)",
+        "metric": "edge-states checked/sec (7-DoF, N=2048)" if args.workload == "arm7" else
+                  f"edge-states checked/sec ({args.workload})",
         "value": value,
         "unit": "edge-states/s",
         "n_gpus": 1,

@@ -6,7 +6,8 @@ some clearance, which needs the collision model; the generators in
 only and written to ``workloads/valid_scenes.json``.
 
 Rules (readings, the paper leaves the synthetic scenes open):
-* 2D workloads: signed distance of start and goal to the obstacles > 0.1.
+* Point-robot workloads (2D and 3D): signed distance of start and goal to
+  the obstacles > 0.1.
 * Arm: no obstacle within 0.2 m of the base (signed distance of the base
   point > 0.2); for the k-th candidate (start, goal) pair the first k whose
   configurations both have signed distance > 0.01 m and whose joint-space
@@ -62,7 +63,8 @@ def _valid_arm(n_want=N_SCENES, max_seed=1000, max_k=200):
 
 
 def main():
-    res = {"2d-small": _valid_2d("2d-small"), "2d-large": _valid_2d("2d-large"), "arm7": _valid_arm()}
+    res = {"2d-small": _valid_2d("2d-small"), "2d-large": _valid_2d("2d-large"), "arm7": _valid_arm(),
+           "3d-point": _valid_2d("3d-point")}
     with open(wl.VALID_SCENES_PATH, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res))

@@ -40,9 +40,10 @@ def _pow2_bucket(n: int) -> int:
 def problem_key(w) -> str:
     """Robot group, DoF, robot spheres, obstacles, H and the power-of-two
     bucket of N: the quantities that decide which launch shape wins."""
-    if w["kind"] == "point2d":
+    if w["kind"] in ("point2d", "point"):
         grp = f"point{int(w['d'])}"
-        nob = f"{len(w['circles'])}+{len(w['boxes'])}"
+        sph, box = (w["circles"], w["boxes"]) if w["kind"] == "point2d" else (w["obs_spheres"], w["obs_boxes"])
+        nob = f"{len(sph)}+{len(box)}"
         ks = 1
     else:
         grp = f"arm{int(w['d'])}"
@@ -52,7 +53,7 @@ def problem_key(w) -> str:
 
 
 def candidates(w) -> list[dict]:
-    if w["kind"] == "point2d":
+    if w["kind"] in ("point2d", "point"):
         return [dict(states_per_iter=s, sphere_chunks=0, blocks_per_cu=b) for s in (1, 2, 4, 8)
                 for b in (0, 1, 2, 4, 8)]
     return [dict(states_per_iter=0, sphere_chunks=c, blocks_per_cu=b) for c in (1, 2, 4) for b in (0, 1, 2, 3, 4)]
@@ -135,7 +136,7 @@ def tune_batch(specs, cache_path: str | None = None, reps: int = 2) -> dict:
     groups: dict[str, dict] = {}
     for sp in specs:
         w = sp["w"]
-        g = "arm" if w["kind"] != "point2d" else "point"
+        g = "arm" if w["kind"] == "arm" else "point"
         size = int(w["M"]) * int(w["N"]) ** 2
         if g not in groups or size > groups[g][0]:
             groups[g] = (size, w)

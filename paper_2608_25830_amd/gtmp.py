@@ -192,6 +192,17 @@ def _stream(stream):
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
 
 
+def model_of(w, device="cuda"):
+    """(robot, scene) of a workload dict: a point robot in the plane
+    (kind point2d), a point robot in space (kind point) or a DH arm."""
+    if w["kind"] == "point2d":
+        return make_point_robot(), Scene(2, w["circles"], w["boxes"], device)
+    if w["kind"] == "point":
+        return make_point_robot(), Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+    return make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"]), \
+        Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+
+
 def version() -> str:
     return _lib.gtmp_version().decode()
 
@@ -427,12 +438,7 @@ class Planner:
         d, M, N, G, H = (int(w[k]) for k in ("d", "M", "N", "G", "H"))
         self.d, self.M, self.N, self.G, self.H = d, M, N, G, H
         self.prob = make_problem(d, M, N, G, H, w["lo"], w["hi"], w["penalty"], max_edge_len)
-        if w["kind"] == "point2d":
-            self.robot = make_point_robot()
-            self.scene = Scene(2, w["circles"], w["boxes"], device)
-        else:
-            self.robot = make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"])
-            self.scene = Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+        self.robot, self.scene = model_of(w, device)
         f32 = dict(device=device, dtype=torch.float32)
         self.q0 = torch.from_numpy(np.asarray(w["q0"], np.float32)).to(device)
         self.goals = torch.from_numpy(np.asarray(w["goals"], np.float32).reshape(G, d)).to(device)
@@ -549,12 +555,7 @@ class AnytimePlanner:
             self.opts.bias_net = C.cast(C.pointer(bias.c), C.c_void_p).value
             self.opts.bias_tau = float(bias_tau)
         self.prob = make_problem(d, M, N, G, H, w["lo"], w["hi"], w["penalty"])
-        if w["kind"] == "point2d":
-            self.robot = make_point_robot()
-            self.scene = Scene(2, w["circles"], w["boxes"], device)
-        else:
-            self.robot = make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"])
-            self.scene = Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+        self.robot, self.scene = model_of(w, device)
         self.q0 = torch.from_numpy(np.asarray(w["q0"], np.float32)).to(device)
         self.goals = torch.from_numpy(np.asarray(w["goals"], np.float32).reshape(G, d)).to(device)
         Mx = self.opts.M_max if mode == GTMP_ANYTIME_GROWING else M
@@ -621,12 +622,7 @@ class BatchPlanner:
             d, M, N, G, H = (int(w[k]) for k in ("d", "M", "N", "G", "H"))
             D = self.descs[i]
             D.problem = make_problem(d, M, N, G, H, w["lo"], w["hi"], w["penalty"])
-            if w["kind"] == "point2d":
-                D.robot = make_point_robot()
-                scene = Scene(2, w["circles"], w["boxes"], device)
-            else:
-                D.robot = make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"])
-                scene = Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+            D.robot, scene = model_of(w, device)
             q0 = torch.from_numpy(np.asarray(w["q0"], np.float32)).to(device)
             goals = torch.from_numpy(np.asarray(w["goals"], np.float32).reshape(G, d)).to(device)
             self.keep += [scene, q0, goals]
@@ -786,11 +782,7 @@ def make_labels(w, n, seed, stage, device="cuda"):
     prob = make_problem(d, 3, max(int(n), 1), 1, int(w["H"]), w["lo"], w["hi"], w["penalty"])
     X = torch.empty((2 * n, d), device=device)
     gtmp_surrogate_label_states(prob, seed, stage, n, X)
-    if w["kind"] == "point2d":
-        robot, scene = make_point_robot(), Scene(2, w["circles"], w["boxes"], device)
-    else:
-        robot = make_arm_robot(w["dh"], w["sph_link"], w["sph_t"], w["sph_r"])
-        scene = Scene(3, w["obs_spheres"], w["obs_boxes"], device)
+    robot, scene = model_of(w, device)
     y = torch.empty(2 * n, device=device, dtype=torch.uint8)
     gtmp_state_check(robot, scene, d, X, None, y)
     return X, y

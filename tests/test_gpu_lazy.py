@@ -25,7 +25,7 @@ def _flat(pl, M):
 
 
 CASES = [("2d-small", 0, None, None), ("2d-small", 3, None, None), ("2d-large", 1, 256, None),
-         ("arm7", 1, 128, None), ("arm7", 2, 256, 5)]
+         ("arm7", 1, 128, None), ("arm7", 2, 256, 5), ("3d-point", 2, 128, None)]
 
 
 @pytest.mark.parametrize("name,scene,N,M", CASES)

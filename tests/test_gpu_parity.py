@@ -111,7 +111,7 @@ def test_minplus_exact_ties_lowest_index(gt, orc):
 # ----------------------------------------------------------------- a2-a4 edges
 EDGE_CASES = [("2d-small", 0, {}), ("2d-small", 3, {}), ("2d-large", 0, dict(N=300, M=3)),
               ("2d-large", 1, dict(N=128, M=4)), ("arm7", 0, dict(N=96, M=3)), ("arm7", 1, dict(N=300, M=2)),
-              ("arm7", 2, dict(N=40, M=4, H=9))]
+              ("arm7", 2, dict(N=40, M=4, H=9)), ("3d-point", 0, dict(N=96, M=4)), ("3d-point", 2, dict(N=64, M=3, H=7))]
 
 
 @pytest.mark.parametrize("name,scene,kw", EDGE_CASES)
@@ -157,7 +157,8 @@ def test_fast_equals_full_flags_arm(gt, orc):
 # ----------------------------------------------------------------- end to end
 PLAN_CASES = [("2d-small", s, {}) for s in range(5)] + [
     ("2d-large", 0, dict(N=256, M=6)), ("2d-large", 3, dict(N=160, M=8, H=20)),
-    ("arm7", 0, dict(N=128, M=4)), ("arm7", 1, dict(N=64, M=6)), ("arm7", 4, dict(N=200, M=3))]
+    ("arm7", 0, dict(N=128, M=4)), ("arm7", 1, dict(N=64, M=6)), ("arm7", 4, dict(N=200, M=3)),
+    ("3d-point", 1, dict(N=128, M=5)), ("3d-point", 3, {})]
 
 
 @pytest.mark.parametrize("name,scene,kw", PLAN_CASES)

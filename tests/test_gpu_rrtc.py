@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 CASES = [("2d-small", 1, 32, 4, (50, 256, 1.0, 0.1, 1.5)),
          ("2d-large", 2, 64, 5, (100, 512, 0.8, 0.05, 1.4)),
          ("arm7", 1, 32, 3, (30, 256, 0.5, 0.1, 1.3)),
-         ("arm7", 2, 48, 4, (100, 512, 0.4, 0.1, 1.5))]
+         ("arm7", 2, 48, 4, (100, 512, 0.4, 0.1, 1.5)),
+         ("3d-point", 1, 40, 4, (60, 256, 1.5, 0.2, 1.5))]
 
 
 def _say(*a):

@@ -96,7 +96,7 @@ def test_arm_random_paths_match_oracle(gt, orc, scene, spread):
     _say("excused pairs", _check(orc.Model(w), wp, H, out), "kept", out["count"].cpu().numpy())
 
 
-@pytest.mark.parametrize("name,scene,N,M", [("2d-small", 1, 64, None), ("2d-large", 0, 256, None),
+@pytest.mark.parametrize("name,scene,N,M", [("2d-small", 1, 64, None), ("2d-large", 0, 256, None), ("3d-point", 0, 96, None),
                                             ("2d-large", 2, 64, 62), ("arm7", 1, 64, None), ("arm7", 3, 64, None)])
 def test_oracle_planned_paths_match(gt, orc, name, scene, N, M):
     """The oracle's own plan (M + 2 waypoints, up to the 64-waypoint limit)

@@ -22,6 +22,10 @@ shapes given by the five workloads:
   U(0.05,0.2) m and centres uniform in [-1,1]^3, joint box [-pi,pi]^7,
   M=8, N=2048, H=16.
 * ``arm7-n4096``: the arm7 scene at N=4096 (surrogate workload).
+* ``3d-point``  : 3D point robot in [-10,10]^3, 40 spheres (radius U(1,2))
+  + 10 axis-aligned boxes (half-extents U(0.5,1.5)), start (-9,-9,-9), goal
+  (9,9,9), M=6, N=256, H=16 (the three-dimensional point case of the
+  collision kernels).
 
 Every array is float32 (int32 for indices), the precision the planner stores.
 A scene is identified by an integer seed; which seeds give a collision-free
@@ -58,6 +62,8 @@ WORKLOADS = {
                      n_boxes=0, h_box=(0.3, 1.5)),
     "2d-large": dict(kind="point2d", d=2, M=16, N=1024, H=32, n_circles=50, r_circ=(0.5, 1.0),
                      n_boxes=20, h_box=(0.3, 1.5)),
+    "3d-point": dict(kind="point", d=3, M=6, N=256, H=16, n_spheres=40, r_sph=(1.0, 2.0), n_boxes=10,
+                     h_box=(0.5, 1.5)),
     "arm7": dict(kind="arm", d=7, M=8, N=2048, H=16, n_obs_spheres=15, n_obs_boxes=15),
     "arm7-n4096": dict(kind="arm", d=7, M=8, N=4096, H=16, n_obs_spheres=15, n_obs_boxes=15),
 }
@@ -65,7 +71,7 @@ WORKLOADS = {
 
 def box_limits(kind: str, d: int):
     """Sampling box (lo, hi) as float32 arrays."""
-    if kind == "point2d":
+    if kind in ("point2d", "point"):
         lo = np.full(d, -10.0, np.float32)
         hi = np.full(d, 10.0, np.float32)
     else:
@@ -93,6 +99,24 @@ def scene_2d(seed: int, n_circles: int, r_circ=(1.0, 2.0), n_boxes: int = 0,
 
 START_2D = np.array([-9.0, -9.0], np.float32)
 GOAL_2D = np.array([9.0, 9.0], np.float32)
+
+
+def scene_3d(seed: int, n_spheres: int, r_sph=(1.0, 2.0), n_boxes: int = 0, h_box=(0.5, 1.5),
+             extent: float = 10.0):
+    """Spheres [n,4] = (c, r) and boxes [n,6] = (c, h), centres uniform in
+    [-extent, extent]^3."""
+    g = _rng(seed, 3)
+    sc = g.uniform(-extent, extent, size=(n_spheres, 3))
+    sr = g.uniform(r_sph[0], r_sph[1], size=(n_spheres, 1))
+    spheres = np.concatenate([sc, sr], axis=1).astype(np.float32)
+    bc = g.uniform(-extent, extent, size=(n_boxes, 3))
+    bh = g.uniform(h_box[0], h_box[1], size=(n_boxes, 3))
+    boxes = np.concatenate([bc, bh], axis=1).astype(np.float32).reshape(n_boxes, 6)
+    return spheres, boxes
+
+
+START_3D = np.array([-9.0, -9.0, -9.0], np.float32)
+GOAL_3D = np.array([9.0, 9.0, 9.0], np.float32)
 
 
 # --------------------------------------------------------------------------- #
@@ -203,6 +227,9 @@ def make_workload(name: str, scene: int = 0, *, seed: int | None = None, sg: int
     if spec["kind"] == "point2d":
         circles, boxes = scene_2d(seed, spec["n_circles"], spec["r_circ"], spec["n_boxes"], spec["h_box"])
         w.update(circles=circles, boxes=boxes, q0=START_2D.copy(), goals=GOAL_2D.reshape(1, 2).copy())
+    elif spec["kind"] == "point":
+        spheres, boxes = scene_3d(seed, spec["n_spheres"], spec["r_sph"], spec["n_boxes"], spec["h_box"])
+        w.update(obs_spheres=spheres, obs_boxes=boxes, q0=START_3D.copy(), goals=GOAL_3D.reshape(1, 3).copy())
     else:
         dh, sl, st, sr = arm_robot(seed)
         spheres, boxes = arm_obstacles(seed, spec["n_obs_spheres"], spec["n_obs_boxes"])
