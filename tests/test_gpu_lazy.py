@@ -87,3 +87,20 @@ def test_round_limit_reports_incomplete(gt):
         full.plan(w["seed"], 0)
         torch.cuda.synchronize()
         assert float(lazy.cost.item()) <= float(full.cost.item())
+
+
+def test_lazy_full_size_arm7_equals_full_plan(gt):
+    """arm7 at its full size (M 8, N 2048): the bench configuration."""
+    w = wl.make_workload("arm7", 0)
+    full = gt.Planner(w, flags=True)
+    lazy = gt.Planner(w, flags=True)
+    for stage in (0, 5):
+        full.plan(w["seed"], stage)
+        st, rounds = lazy.plan_lazy(w["seed"], stage, band=0.2)
+        torch.cuda.synchronize()
+        _say("full size stage", stage, "rounds", rounds, "lazy", float(lazy.cost.item()), "full",
+             float(full.cost.item()))
+        assert st == gt.GTMP_OK
+        assert float(lazy.V_s.item()) == float(full.V_s.item())
+        known = lazy.flags != 0xFF
+        assert torch.equal(lazy.flags[known], full.flags[known])

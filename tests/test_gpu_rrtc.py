@@ -140,3 +140,35 @@ def test_free_scene_has_no_candidates(gt):
     pl.repair(gt.make_rrtc_opts(20, 64, 1.0, 0.1, 1.5, stats), 1, 0)
     torch.cuda.synchronize()
     assert int(stats[0].item()) == 0 and torch.equal(before, pl.C_h) and int(pl.flags.max().item()) == 0
+
+
+def test_large_trees_match_oracle(gt, orc):
+    """Trees of up to 2048 nodes (the LDS holds both): a wall of circles
+    across x = 0 whose only gap lies far outside the query ellipsoids, so the
+    calls on crossing edges run their whole budget and fill their trees."""
+    import oracle.rrtc as R
+    ys = np.arange(-12.0, 12.01, 0.4)
+    ys = ys[(ys < 7.7) | (ys > 9.8)]
+    wall = np.stack([np.zeros_like(ys), ys, np.full_like(ys, 0.3)], 1).astype(np.float32)
+    w = wl.make_workload("2d-small", 0, N=12, M=2)
+    w["circles"], w["boxes"] = wall, np.zeros((0, 4), np.float32)
+    o = R.LPOpts(2500, 2048, 0.4, 0.05, 1.3)
+    opts = gt.make_rrtc_opts(o.budget, o.cap, o.eta, o.res, o.ell_factor)
+    pl = gt.Planner(w, flags=True)
+    pl.sample(w["seed"], 0)
+    pl.check()
+    pl.repair(opts, 17, 0)
+    torch.cuda.synchronize()
+    g_cost = _flat((pl.C_s.cpu().numpy(), pl.C_h.cpu().numpy()[:1], pl.C_l.cpu().numpy())).astype(np.float64)
+    g_flag = pl.flags.cpu().numpy().astype(np.int32)
+    r = orc.plan(w)
+    c0, f0, sd0 = _flat(r["cost"]), _flat(r["flag"]), _flat(r["minsd"])
+    cost, flag, info = R.repair(w, r["Q"], c0, f0, o, 17, 0)
+    ex = np.abs(sd0) <= P.BAND
+    ex[info["vertex_band"]] = True
+    ex[info["ids"][info["near_band"]]] = True
+    _say("large trees: calls", len(info["ids"]), "repaired", int((flag == 2).sum()), "largest tree",
+         int(info["sizes"].max()), "excused", int(ex.sum()))
+    assert not ((g_flag != flag) & ~ex).any()
+    np.testing.assert_allclose(g_cost[~ex], cost[~ex], rtol=P.REL)
+    assert info["sizes"].max() > 512
