@@ -718,11 +718,32 @@ def main():
         "step_ms_iqr": [float(np.percentile(step_ms, 25)), float(np.percentile(step_ms, 75))],
         "wall_s": wall,
     }
+    out["sweep_roofline"] = sweep_report(torch, pl)
     out["simplify"] = simplify_report(args, torch, gtmp, w, pl)
     out["lazy"] = lazy_report(args, torch, gtmp, w, costs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, min_seconds=args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def sweep_report(torch, pl, reps=20):
+    """Outside the timed region: the min-plus sweep of the last plan's costs
+    alone, HIP events around each call; algorithmic bytes = every cost read
+    once plus V and A written: 4 ((M-1) N^2 + N + N G) + 8 M N."""
+    M, N, G = pl.M, pl.N, pl.G
+    nbytes = 4 * ((M - 1) * N * N + N + N * G) + 8 * M * N
+    pl.sweep()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        pl.sweep()
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    gbs = nbytes / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+            "bytes_per_sweep": nbytes, "ms_per_sweep": ms, "layers": M - 1}
 
 
 def lazy_report(args, torch, gtmp, w, costs, band=0.2):

@@ -6,9 +6,9 @@
 // V_s       = min_u C_s[u] + V[0][u]
 // Minimisers keep the lowest index among equal values; a row whose minimum is
 // +inf stores -1.  Large layers are HBM bound (one read of C_h[m]): one wave
-// per row streams the row with 16-byte loads while V[m+1] sits in LDS; the
-// (value, index) pair is reduced across the wave with a butterfly.  Small
-// graphs run the whole recursion in one block.
+// per row streams the row with 16-byte loads beside the cache-resident
+// V[m+1]; the (value, index) pair is reduced across the wave with a
+// butterfly.  Small graphs run the whole recursion in one block.
 #include "gtmp_launch.hpp"
 
 namespace gtmp {
@@ -84,19 +84,12 @@ __global__ void __launch_bounds__(256) k_goal_layer(int M, int N, int G, const f
 }
 
 // ---------------------------------------------------------------- inner layer
-// V[m][u] for all u; V[m+1] staged in LDS when it fits.
-constexpr int kLdsMaxN = 16384;
-
+// V[m][u] for all u.  V[m+1] (N floats, read by every wave) is read straight
+// from global memory, where it stays cache-resident: no staging barrier holds
+// back the first loads of the streamed rows.
 __global__ void __launch_bounds__(256) k_inner_layer(int m, int N, int rows_per_wave, const float *__restrict__ C_h,
                                                      float *V, int32_t *A) {
-    extern __shared__ float vn_lds[];
-    const float *vnext = V + (size_t)(m + 1) * N;
-    const bool staged = N <= kLdsMaxN;
-    if (staged) {
-        for (int i = threadIdx.x; i < N; i += blockDim.x) vn_lds[i] = vnext[i];
-        __syncthreads();
-    }
-    const float *vn = staged ? vn_lds : vnext;
+    const float *vn = V + (size_t)(m + 1) * N;
     const int lane = lane_id();
     const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const int u0 = wave * rows_per_wave;
@@ -191,9 +184,8 @@ hipError_t launch_minplus(int M, int N, int G, const float *C_s, const float *C_
     const int rows_per_wave = N >= 4096 ? 2 : 1;
     const int waves = (N + rows_per_wave - 1) / rows_per_wave;
     const int blocks = (waves + 3) / 4;
-    const size_t lds = N <= kLdsMaxN ? sizeof(float) * (size_t)N : 0;
     for (int m = M - 2; m >= 0; --m)
-        hipLaunchKernelGGL(k_inner_layer, dim3(blocks), dim3(256), lds, s, m, N, rows_per_wave, C_h, V, A);
+        hipLaunchKernelGGL(k_inner_layer, dim3(blocks), dim3(256), 0, s, m, N, rows_per_wave, C_h, V, A);
     hipLaunchKernelGGL(k_start, dim3(1), dim3(1024), 0, s, N, C_s, V, V_s, a_s);
     return hipGetLastError();
 }
