@@ -128,18 +128,49 @@ __global__ void __launch_bounds__(1024) k_start(int N, const float *__restrict__
 }
 
 // ---------------------------------------------------------------- small graphs
-// Whole recursion in one block of 256 threads (N <= 1024).
+// Whole recursion in one block of 256 threads (N <= 1024).  When C_h fits
+// (kSmallStage floats) the block first loads all of it into LDS in one
+// parallel burst, so the rows of a layer are not each a dependent global
+// load away.
+constexpr int kSmallStage = 12288;
+
 __global__ void __launch_bounds__(256) k_sweep_small(int M, int N, int G, const float *__restrict__ C_s,
                                                      const float *__restrict__ C_h, const float *__restrict__ C_l,
                                                      const float *__restrict__ Vg, float *V, int32_t *A, float *V_s,
-                                                     int32_t *a_s) {
+                                                     int32_t *a_s, int staged) {
     __shared__ __align__(16) float buf[2][1024];
     __shared__ float sv[4];
     __shared__ int si[4];
+    extern __shared__ float ch_lds[];
     const int lane = lane_id();
     const int w = threadIdx.x / kWave;
     float *cur = buf[0];
     float *nxt = buf[1];
+    if (staged) {
+        // eight independent 16-byte loads per thread in flight before their
+        // LDS stores (a load-store loop would wait on every load in turn)
+        const int n = (M - 1) * N * N;
+        const int n4 = n >> 2;
+        const f4v *src = reinterpret_cast<const f4v *>(C_h);
+        f4v *dst = reinterpret_cast<f4v *>(ch_lds);
+        const bool vec = (reinterpret_cast<uintptr_t>(C_h) & 15) == 0;
+        if (vec) {
+            for (int base = 0; base < n4; base += 8 * 256) {
+                f4v t[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int i = base + k * 256 + threadIdx.x;
+                    if (i < n4) t[k] = src[i];
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int i = base + k * 256 + threadIdx.x;
+                    if (i < n4) dst[i] = t[k];
+                }
+            }
+        }
+        for (int i = vec ? 4 * n4 + threadIdx.x : threadIdx.x; i < n; i += blockDim.x) ch_lds[i] = C_h[i];
+    }
     for (int u = threadIdx.x; u < N; u += blockDim.x) {
         Best b{__builtin_inff(), -1};
         for (int g = 0; g < G; ++g) take(b, C_l[(size_t)u * G + g] + (Vg ? Vg[g] : 0.f), g);
@@ -148,13 +179,40 @@ __global__ void __launch_bounds__(256) k_sweep_small(int M, int N, int G, const 
         nxt[u] = b.v;
     }
     __syncthreads();
+    // staged: tpr threads per row (consecutive lanes, a power of two), each
+    // scanning its columns in increasing order, then a tpr-lane butterfly;
+    // otherwise one wave per row streaming from global memory
+    int lg = 0;
+    while ((N << (lg + 1)) <= 256 && lg < 6) ++lg;
+    const int tpr = 1 << lg, sub = threadIdx.x & (tpr - 1), rows_per_pass = 256 >> lg;
     for (int m = M - 2; m >= 0; --m) {
-        for (int u = w; u < N; u += 4) {
-            const Best b = row_argmin(C_h + ((size_t)m * N + u) * N, nxt, N, lane);
-            if (lane == 0) {
-                V[(size_t)m * N + u] = b.v;
-                A[(size_t)m * N + u] = b.i;
-                cur[u] = b.v;
+        if (staged) {
+            for (int u0 = 0; u0 < N; u0 += rows_per_pass) {
+                const int u = u0 + (threadIdx.x >> lg);
+                Best b{__builtin_inff(), -1};
+                if (u < N) {
+                    const float *row = ch_lds + ((size_t)m * N + u) * N;
+                    for (int v = sub; v < N; v += tpr) take(b, row[v] + nxt[v], v);
+                }
+                for (int off = tpr >> 1; off > 0; off >>= 1) {
+                    const float ov = __shfl_xor(b.v, off);
+                    const int oi = __shfl_xor(b.i, off);
+                    if (ov < b.v || (ov == b.v && (unsigned)oi < (unsigned)b.i)) { b.v = ov; b.i = oi; }
+                }
+                if (u < N && sub == 0) {
+                    V[(size_t)m * N + u] = b.v;
+                    A[(size_t)m * N + u] = b.i;
+                    cur[u] = b.v;
+                }
+            }
+        } else {
+            for (int u = w; u < N; u += 4) {
+                const Best b = row_argmin(C_h + ((size_t)m * N + u) * N, nxt, N, lane);
+                if (lane == 0) {
+                    V[(size_t)m * N + u] = b.v;
+                    A[(size_t)m * N + u] = b.i;
+                    cur[u] = b.v;
+                }
             }
         }
         __syncthreads();
@@ -177,7 +235,10 @@ __global__ void __launch_bounds__(256) k_sweep_small(int M, int N, int G, const 
 hipError_t launch_minplus(int M, int N, int G, const float *C_s, const float *C_h, const float *C_l,
                           const float *Vg, float *V, int32_t *A, float *V_s, int32_t *a_s, hipStream_t s) {
     if (N <= 1024 && (long long)(M - 1) * N * N <= (1ll << 20)) {
-        hipLaunchKernelGGL(k_sweep_small, dim3(1), dim3(256), 0, s, M, N, G, C_s, C_h, C_l, Vg, V, A, V_s, a_s);
+        const int staged = (long long)(M - 1) * N * N <= kSmallStage ? 1 : 0;
+        const size_t lds = staged ? sizeof(float) * (size_t)(M - 1) * N * N : 0;
+        hipLaunchKernelGGL(k_sweep_small, dim3(1), dim3(256), lds, s, M, N, G, C_s, C_h, C_l, Vg, V, A, V_s, a_s,
+                           staged);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_goal_layer, dim3((N + 255) / 256), dim3(256), 0, s, M, N, G, C_l, Vg, V, A);

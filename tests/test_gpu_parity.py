@@ -87,10 +87,13 @@ def test_minplus_matches_oracle(gt, orc, M, N, G, p_inf, p_tie):
         assert math.isinf(Vs.item()) and int(a_s.item()) == -1
 
 
-def test_minplus_exact_ties_lowest_index(gt, orc):
+@pytest.mark.parametrize("M,N", [(3, 96), (3, 48), (4, 33), (2, 300), (5, 7)])
+def test_minplus_exact_ties_lowest_index(gt, orc, M, N):
     # integer costs and a zero goal layer: every sum is exact on both sides,
     # so equal values are genuine ties and both sides keep the lowest index
-    M, N, G = 3, 96, 1
+    # (sizes cover the LDS-staged small sweep, with one or several threads
+    # per row, and the streamed one)
+    G = 1
     g = np.random.default_rng(3)
     Cs = g.integers(0, 3, N).astype(np.float32)
     Ch = g.integers(0, 3, (M - 1, N, N)).astype(np.float32)
