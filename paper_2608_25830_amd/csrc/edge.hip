@@ -556,7 +556,8 @@ static hipError_t launch_point(const EdgeArgs &A, const ArmParams &R, const Scen
 // Resident blocks of a persistent launch: the request, else the occupancy
 // limit capped at auto_cap (cheap states make the tile cursor a point of
 // contention when every resident wave claims tiles from it).
-static int persistent_grid(const void *kernel, int block, int blocks_per_cu_req, int auto_cap = 1 << 20) {
+static int persistent_grid(const void *kernel, int block, int blocks_per_cu_req, uint32_t n_tiles,
+                           int auto_cap = 1 << 20) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
@@ -568,7 +569,11 @@ static int persistent_grid(const void *kernel, int block, int blocks_per_cu_req,
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0) != hipSuccess || occ <= 0) occ = 2;
         per_cu = occ < auto_cap ? occ : auto_cap;
     }
-    return cus * per_cu;
+    // a small graph gets one wave per tile at most: thousands of idle waves
+    // would only queue on the tile cursor's atomic
+    const uint64_t cap = ((uint64_t)n_tiles + (block / kWave) - 1) / (block / kWave);
+    const uint64_t g = (uint64_t)cus * per_cu;
+    return (int)(g < cap ? g : (cap > 0 ? cap : 1));
 }
 
 // automatic launch shape of the point-robot interior kernel (measured on the
@@ -658,7 +663,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
 #undef GTMP_KK
             default: return hipErrorInvalidValue;
         }
-        const int grid = persistent_grid(kern, 256, o.blocks_per_cu);
+        const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles);
         switch (kp * 8 + nch) {
 #define GTMP_LA(K, C) case K * 8 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag, phases);
 #define GTMP_LA3(K) GTMP_LA(K, 1) GTMP_LA(K, 2) GTMP_LA(K, 4)
@@ -676,14 +681,14 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
                          : spi == 2 ? (const void *)k_interior<PointModel<2, 2>, true, 1>
                          : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true, 1>
                                     : (const void *)k_interior<PointModel<2, 8>, true, 1>;
-        const int grid = persistent_grid(kern, 256, o.blocks_per_cu, kPointBlocksPerCuAuto);
+        const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, kPointBlocksPerCuAuto);
         return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases);
     }
     const void *kern = spi == 1 ? (const void *)k_interior<PointModel<3, 1>, true, 1>
                      : spi == 2 ? (const void *)k_interior<PointModel<3, 2>, true, 1>
                      : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true, 1>
                                 : (const void *)k_interior<PointModel<3, 8>, true, 1>;
-    const int grid = persistent_grid(kern, 256, o.blocks_per_cu, kPointBlocksPerCuAuto);
+    const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, kPointBlocksPerCuAuto);
     return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases);
 }
 
