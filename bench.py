@@ -41,7 +41,7 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
 # FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/ (scaled by the
 # plain-copy calibration).  A value is only reported while the kernel sources
 # still hash to the fingerprint it was measured on.
-MEASURED_TRAFFIC = {"arm7": (4.548e+08, "884a525de81ac954", "profiles/k_interior_arm7.md")}
+MEASURED_TRAFFIC = {"arm7": (5.211e+07, "0f1a6a45a815573d", "profiles/k_interior_arm7.md")}
 KERNEL_SOURCES = ["paper_2608_25830_amd/csrc/edge.hip", "paper_2608_25830_amd/csrc/edge_common.hpp",
                   "paper_2608_25830_amd/csrc/gtmp_device.hpp"]
 
@@ -65,6 +65,21 @@ def arm_state_flops(n_joints, n_spheres, n_obs_sph, n_obs_box, d):
       box obstacles        per obstacle 6 + per (sphere) 3 med3 + 3 sub + 3 fma + 1 min = 13"""
     K = n_spheres
     return (2 * d + 51 * n_joints + 9 * K + n_obs_sph * (2 + 10 * K) + n_obs_box * (6 + 13 * K))
+
+
+def arm_grid_state_flops(n_joints, n_spheres, d):
+    """Algorithmic FP32 operations of one arm state behind the obstacle bins,
+    apart from the exact tests (FMA = 2, any other arithmetic op = 1):
+      lerp                 2 d
+      DH FK per joint      48 + 1 + 2 as above, and the link vector 3 sub
+      per sphere           centre 3 fma + bin coordinates 3 fma + 3 clamps = 15
+    Each exact sphere-obstacle test (counted by the kernel) adds
+      GRID_TEST_FLOPS      R add + R^2 mul + 3 (med3 + sub + fma) + compare = 15"""
+    return 2 * d + 54 * n_joints + 15 * n_spheres
+
+
+GRID_TEST_FLOPS = 15
+GRID_MAX_OBS = 64  # obstacles the bin masks hold (the filter's automatic range)
 
 
 def point_state_flops(n_circ, n_box, d):
@@ -671,17 +686,33 @@ def main():
     kernel_ms = [kb[i].elapsed_time(ke[i]) for i in range(args.steps)]
     step_ms = np.array([sb[i].elapsed_time(sb[i + 1]) for i in range(args.steps)])
     states = torch.diff(stats_hist[:, 0]).cpu().numpy().astype(np.float64)
+    tests = torch.diff(stats_hist[:, 2]).cpu().numpy().astype(np.float64)
     costs = cost_hist.cpu().numpy()
 
     value = E * H / (ms_per_step / 1e3)
+    k_ms = float(np.mean(kernel_ms))
+    st = float(np.mean(states))
+    grid = None
     if w["kind"] == "arm":
-        f_state = arm_state_flops(d, len(w["sph_link"]), w["obs_spheres"].shape[0], w["obs_boxes"].shape[0], d)
+        n_obs = w["obs_spheres"].shape[0] + w["obs_boxes"].shape[0]
+        f_dense = arm_state_flops(d, len(w["sph_link"]), w["obs_spheres"].shape[0], w["obs_boxes"].shape[0], d)
+        if int(pl.opts.sphere_chunks) == 0 and n_obs <= GRID_MAX_OBS:
+            # the bin filter: per-state work plus the exact tests it made
+            f_state = arm_grid_state_flops(d, len(w["sph_link"]), d)
+            t_mean = float(np.mean(tests))
+            flop = st * f_state + t_mean * GRID_TEST_FLOPS
+            grid = {"exact_tests_per_launch": t_mean, "exact_tests_per_state": t_mean / st,
+                    "test_flops": GRID_TEST_FLOPS,
+                    "full_test_flop_per_state": f_dense,
+                    "full_test_equivalent_tflops": st * f_dense / (k_ms / 1e3) / 1e12}
+        else:
+            f_state = f_dense
+            flop = st * f_state
     else:
         sph, box = (w["circles"], w["boxes"]) if w["kind"] == "point2d" else (w["obs_spheres"], w["obs_boxes"])
         f_state = point_state_flops(sph.shape[0], box.shape[0], d)
-    k_ms = float(np.mean(kernel_ms))
-    st = float(np.mean(states))
-    achieved = st * f_state / (k_ms / 1e3) / 1e12
+        flop = st * f_state
+    achieved = flop / (k_ms / 1e3) / 1e12
     traffic, traffic_src = None, None
     if args.workload in MEASURED_TRAFFIC and not args.opt:
         tb, fp, src = MEASURED_TRAFFIC[args.workload]
@@ -708,9 +739,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic, "traffic_unit": "bytes/launch",
                      "traffic_source": traffic_src,
-                     "kernel": "k_interior (early-exit interior edge checker)",
+                     "kernel": "k_interior (early-exit interior edge checker)" + (", obstacle-bin filter" if grid else ""),
                      "kernel_ms": k_ms, "states_evaluated_per_launch": st, "flop_per_state": f_state,
-                     "states_evaluated_frac": st / (E * H)},
+                     "states_evaluated_frac": st / (E * H), "obstacle_bins": grid},
         "edge_opts": {k: int(getattr(pl.opts, k)) for k in ("mode", "states_per_iter", "blocks_per_cu",
                                                                "sphere_chunks")},
         "mean_path_cost": float(np.mean(costs)),

@@ -105,7 +105,8 @@ typedef struct gtmp_robot {
  *   spheres [n_spheres][wdim + 1]  (centre, radius)      -- circles in 2D
  *   boxes   [n_boxes][2 * wdim]    (centre, half extents), axis-aligned
  * A configuration is in collision iff its signed distance to the union of
- * obstacles is <= 0 (Sec. III: the free space is open).                  */
+ * obstacles is <= 0 (Sec. III: the free space is open).  Obstacle data must
+ * be finite; the results for non-finite obstacles are unspecified.        */
 typedef struct gtmp_scene {
     int32_t wdim;
     int32_t n_spheres;
@@ -137,11 +138,15 @@ typedef struct gtmp_edge_opts {
     int32_t block;            /* ignored: the interior kernels run 256-thread blocks */
     int32_t blocks_per_cu;    /* resident blocks per CU for the persistent interior kernel (0 = auto:
                                  the occupancy limit, at most 3 for point robots) */
-    int32_t sphere_chunks;    /* arms: the collision spheres of a state are tested in this many
-                                 chunks (1, 2 or 4; 0 = auto = 2) */
+    int32_t sphere_chunks;    /* arms: 0 (auto) = each robot sphere is tested exactly against the
+                                 obstacles that its per-axis obstacle bins list (a conservative
+                                 filter: the same decisions as testing every obstacle) when the
+                                 scene has at most 64 obstacles, else as for 2; 1, 2 or 4 = every
+                                 sphere against every obstacle, the spheres in this many chunks */
     int32_t reserved[3];
     unsigned long long *stats; /* optional device [4]: states evaluated, edges checked in the
-                                  interior pass, reserved, reserved.  Added to. */
+                                  interior pass, exact sphere-obstacle tests made behind the
+                                  obstacle bins (arms, sphere_chunks 0), reserved.  Added to. */
     void *ev_begin;            /* optional hipEvent_t recorded on `stream` just before the
                                   interior (fast mode) or every-state (full mode) kernel */
     void *ev_end;              /* optional hipEvent_t recorded just after it */
@@ -461,7 +466,8 @@ typedef struct gtmp_batch_opts {
                                  whose sample expansion sorts with a library routine that clears memory
                                  with memset nodes, which are kept out of graphs */
     int32_t states_per_iter;  /* interior states per lane and iteration for point robots (0 = auto = 8) */
-    int32_t sphere_chunks;    /* arms: spheres tested in 1, 2 or 4 chunks (0 = auto = 2) */
+    int32_t sphere_chunks;    /* arms: as gtmp_edge_opts.sphere_chunks; 0 (auto) uses the obstacle bins
+                                 when every arm plan's scene has at most 64 obstacles */
     int32_t blocks_per_cu;    /* resident blocks per CU of the persistent kernels (0 = auto) */
     unsigned long long *stats; /* optional device [4], as gtmp_edge_opts.stats */
 } gtmp_batch_opts;

@@ -11,9 +11,11 @@ file keyed by robot group and problem-size bucket.
 Knobs:
   point robots: states_per_iter in {1, 2, 4, 8}  (interior states per lane
                 and iteration), blocks_per_cu in {0 (occupancy), 1, 2, 4, 8}
-  arms:         sphere_chunks in {1, 2, 4}  (robot spheres tested in one pass at
-                128+ VGPRs, or two passes at fewer registers and higher
-                occupancy), blocks_per_cu in {0, 1, 2, 3, 4}
+  arms:         sphere_chunks 0 (the obstacle-bin filter, when the scene has
+                at most 64 obstacles) with blocks_per_cu in {0, 2, 4, 6}, or
+                {1, 2, 4} (every robot sphere against every obstacle in one
+                pass at 128+ VGPRs, or in chunks at fewer registers and higher
+                occupancy) with blocks_per_cu in {0, 1, 2, 3, 4}
 """
 from __future__ import annotations
 
@@ -56,7 +58,9 @@ def candidates(w) -> list[dict]:
     if w["kind"] in ("point2d", "point"):
         return [dict(states_per_iter=s, sphere_chunks=0, blocks_per_cu=b) for s in (1, 2, 4, 8)
                 for b in (0, 1, 2, 4, 8)]
-    return [dict(states_per_iter=0, sphere_chunks=c, blocks_per_cu=b) for c in (1, 2, 4) for b in (0, 1, 2, 3, 4)]
+    bins = [dict(states_per_iter=0, sphere_chunks=0, blocks_per_cu=b) for b in (0, 2, 4, 6)]
+    return bins + [dict(states_per_iter=0, sphere_chunks=c, blocks_per_cu=b) for c in (1, 2, 4)
+                   for b in (0, 1, 2, 3, 4)]
 
 
 def apply(opts, cand: dict):

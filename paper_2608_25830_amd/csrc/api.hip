@@ -79,7 +79,10 @@ gtmp_status to_arm(const gtmp_robot *r, int d, gtmp::ArmParams *out) {
         a.t[k] = r->sph_t[k];
         a.r[k] = r->sph_r[k];
         if (r->sph_r[k] != a.r0) a.uniform_r = 0;
+        a.lk_end[L - 1] = k + 1;
     }
+    for (int j = 1; j < r->n_joints; ++j)  // links without spheres: empty ranges
+        if (a.lk_end[j] < a.lk_end[j - 1]) a.lk_end[j] = a.lk_end[j - 1];
     // |sphere centre| <= max(1, max |t|) * sum of link lengths: frame origins
     // are at most the summed lengths sqrt(a^2 + d^2) from the base
     double len = 0.0, tmax = 1.0;

@@ -14,6 +14,7 @@ struct BPlan {
     EdgeArgs A;          // edge check of this plan's stage (workspace, costs, tiles, t order)
     SceneParams S;
     const ArmParams *arm;  // device copy of the robot table (arms), null for points
+    float grid_r_max;      // arms: largest robot sphere radius (the obstacle bins are built for it)
     int group;           // 0: 2D point, 1: 3D point, 2: arm
     uint32_t vert_base;  // first vertex of this plan in its group's vertex space
     uint32_t tile_base;  // first tile of this plan in the batch's tile space
@@ -216,16 +217,22 @@ __global__ void __launch_bounds__(kTile) k_batch_prepass(const BPlan *plans, int
 // table are read with wave-uniform addresses.  A wave that draws a tile of
 // another plan finishes its edges before it switches.
 template <class Model, bool UNIFORM_R, int NCH>
-__global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
+__global__ void __launch_bounds__(256, Model::kGrid ? 3 : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
     k_batch_interior(const BPlan *plans, int p0, int p1, uint32_t n_gtiles, uint32_t *gcounter,
                      unsigned long long *stats) {
     constexpr int D = Model::D;
     constexpr int KP = Model::KP;
     constexpr bool ARM = Model::kArm;
+    constexpr bool GRID = Model::kGrid;
     constexpr int W = ARM ? 3 : D;
     constexpr int SP = ARM ? 1 : KP;
-    constexpr int KC = ARM ? KP / NCH : KP;
     __shared__ float tord[4][GTMP_MAX_H];
+    // obstacle bins (arms): each wave holds the bins of its current plan
+    constexpr int WG = Model::kWords > 1 ? 2 : 1;
+    __shared__ typename std::conditional<GRID, GridLds<WG>[4], char>::type glds_raw;
+    __shared__ typename std::conditional<GRID, GridQueue<WG>[4], char>::type gque;
+    float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
+    uint32_t n_tests = 0;
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
 
@@ -266,9 +273,23 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
                     n_int = plans[cur].A.n_int;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     for (int i = lane; i < n_int; i += kWave) tord[wv][i] = plans[cur].A.tord[i];
+                    if constexpr (GRID) {
+                        const uint4 *src = reinterpret_cast<const uint4 *>(plans[cur].A.grid);
+                        uint4 *dst = reinterpret_cast<uint4 *>(&glds_raw[wv]);
+                        constexpr int n16 = (int)(grid_lds_bytes<WG>() / 16);
+                        for (int i = lane; i < n16; i += kWave) dst[i] = src[i];
+                    }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if constexpr (GRID) {
+                        const ObsGrid &G = *reinterpret_cast<const ObsGrid *>(&glds_raw[wv]);
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            ginv[i] = G.inv[i];
+                            goff[i] = G.off[i];
+                        }
+                    }
                 }
                 const EdgeArgs &A = plans[cur].A;
                 tile = pending - plans[cur].gtile_base;
@@ -317,9 +338,16 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
             carm Rp = (carm)Pp->arm;
             asm volatile("" : "+s"(Rp));
             const auto &R = *Rp;
-            const float r0 = R.r0;
-            const v32f o = arm_fk<D>(R, q);
-            gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
+            if constexpr (GRID) {
+                const ObsGrid &G = *reinterpret_cast<const ObsGrid *>(&glds_raw[wv]);
+                uint32_t tests = 0;
+                gap = arm_hit_grid<Model::kWords>(R, q, G, ginv, goff, gque[wv], tests, has) ? -1.f : 1.f;
+                n_tests += tests;
+            } else {
+                const float r0 = R.r0;
+                const v32f o = arm_fk<D>(R, q);
+                gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
+            }
         } else {
             Probes<W, KP> P;
 #pragma unroll
@@ -351,6 +379,14 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
                     has = false;
                 }
             }
+        }
+    }
+    if constexpr (GRID) {
+        if (stats) {
+            unsigned long long t = n_tests;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+            if (lane == 0) atomicAdd(&stats[2], t);
         }
     }
     if (stats && lane == 0) {
@@ -526,6 +562,13 @@ __global__ void __launch_bounds__(64) k_batch_arm_tol(const BPlan *plans, int p0
     }
 }
 
+// Obstacle bins of every arm plan of the group range [p0, p0 + gridDim.x)
+// (one block per plan; the bins depend on the scene and the robot radii only).
+__global__ void __launch_bounds__(kGridBuildThreads) k_batch_build_grid(const BPlan *plans, int p0) {
+    const BPlan &P = plans[p0 + blockIdx.x];
+    build_grid_block(P.S, P.grid_r_max, const_cast<ObsGrid *>(P.A.grid));
+}
+
 __global__ void k_batch_zero(uint32_t *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -607,6 +650,7 @@ BatchLayout make_batch_layout(const gtmp_plan_desc *plans, int n, const gtmp_bat
     }
     L.max_stages = max_stages;
     L.off_arm = off; off = up(off + sizeof(ArmParams) * (size_t)n);
+    L.off_grids = off; off = up(off + sizeof(ObsGrid) * (size_t)n);
     L.off_tables = off; off = up(off + sizeof(BPlan) * (size_t)n * (size_t)max_stages);
     L.off_bases = off; off = up(off + sizeof(uint64_t) * (size_t)n * (size_t)max_stages);
     L.off_counters = off; off = up(off + sizeof(uint32_t) * 8 * (size_t)max_stages + 256);
@@ -639,6 +683,16 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
     bool uniform_r = true;
     for (int p = 0; p < n; ++p)
         if (group[p] == 2 && !arms[p].uniform_r) uniform_r = false;
+    // the obstacle-bin filter for the arm group (automatic choice) when every
+    // arm plan's scene fits the masks; mask words: the most any plan needs
+    int grid_words = o.sphere_chunks == 0 ? 1 : 0;
+    for (int p = 0; p < n && grid_words; ++p) {
+        if (group[p] != 2) continue;
+        const int n_obs = plans[p].scene.n_spheres + plans[p].scene.n_boxes;
+        if (n_obs > kGridMaxObs) grid_words = 0;
+        else if (n_obs > 32) grid_words = 2;
+    }
+    ObsGrid *grids = reinterpret_cast<ObsGrid *>(ws + L.off_grids);
 
     struct StageInfo {
         int count;
@@ -693,6 +747,12 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                 for (int i = 0; i < A.n_int; ++i) A.tord[i] = (float)ordr[i] / (float)(pp.H - 1);
                 B.S = SceneParams{D.scene.spheres, D.scene.boxes, D.scene.n_spheres, D.scene.n_boxes};
                 B.arm = gi == 2 ? arm_dev + p : nullptr;
+                if (gi == 2) {
+                    A.grid = grids + p;
+                    float r_max = 0.f;
+                    for (int k = 0; k < arms[p].n_spheres; ++k) r_max = std::max(r_max, arms[p].r[k]);
+                    B.grid_r_max = r_max;
+                }
                 B.group = gi;
                 B.vert_base = vb[gi]; vb[gi] += ep.n_vertices;
                 B.gtile_base = gb[gi]; gb[gi] += ep.n_tiles;
@@ -769,8 +829,12 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         if (info.empty()) return hipSuccess;
         // archive init over the plans of stage 0 (every plan has a stage 0)
         hipLaunchKernelGGL(k_batch_init, dim3((info[0].count + 255) / 256), dim3(256), 0, st_, tables, info[0].count);
-        if (info[0].g3 > info[0].g2)
+        if (info[0].g3 > info[0].g2) {
             hipLaunchKernelGGL(k_batch_arm_tol, dim3(info[0].g3 - info[0].g2), dim3(64), 0, st_, tables, info[0].g2);
+            if (grid_words)
+                hipLaunchKernelGGL(k_batch_build_grid, dim3(info[0].g3 - info[0].g2), dim3(kGridBuildThreads), 0, st_,
+                                   tables, info[0].g2);
+        }
         for (int st = 0; st < L.max_stages; ++st) {
             const StageInfo &I = info[st];
             const BPlan *T = tables + (size_t)st * n;
@@ -837,6 +901,8 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                 GTMP_BK(8) GTMP_BK(16) GTMP_BK(24) GTMP_BK(32) GTMP_BK(40) GTMP_BK(48) GTMP_BK(56) GTMP_BK(64)
 #undef GTMP_BK
 #undef GTMP_BK1
+                if (grid_words == 1) k = (const void *)k_batch_interior<ArmGridModel<1>, true, 1>;
+                if (grid_words == 2) k = (const void *)k_batch_interior<ArmGridModel<2>, true, 1>;
                 if (!k) return hipErrorInvalidValue;
                 const int grid = persistent_blocks(k, o.blocks_per_cu);
                 uint32_t *c2 = ctr + 2;

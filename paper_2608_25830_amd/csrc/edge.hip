@@ -20,7 +20,7 @@
 //                     again (cost |v-u|, flag 0).
 // Full mode evaluates the exact signed distance of every state of every edge
 // (lanes = states, wave-level segmented min per edge) and writes minsd.
-#include "gtmp_launch.hpp"
+#include "edge_common.hpp"
 
 namespace gtmp {
 
@@ -42,6 +42,7 @@ EdgePlan make_edge_plan(const gtmp_problem &p) {
     e.off_tile_list = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
     e.off_counter = o; o = up(o + 256);
     e.off_params = o; o = up(o + sizeof(ArmParams));
+    e.off_grid = o; o = up(o + sizeof(ObsGrid));
     e.total = o;
     return e;
 }
@@ -64,11 +65,6 @@ int interior_order(int H, uint8_t *order) {
     return n;
 }
 
-}  // namespace gtmp
-
-#include "edge_common.hpp"
-
-namespace gtmp {
 
 // Copy of the robot table (a kernel argument) into device memory.
 __global__ void k_store_params(ArmParams R, ArmParams *dst) {
@@ -105,6 +101,10 @@ __global__ void k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
 __global__ void k_zero_u32(uint32_t *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+
+__global__ void __launch_bounds__(kGridBuildThreads) k_build_grid(SceneParams S, float r_max, ObsGrid *G) {
+    build_grid_block(S, r_max, G);
 }
 
 // ------------------------------------------------------------------ 1. vertices
@@ -206,18 +206,37 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
 // LIST: tiles come from the compacted list of a lazy round (a separate
 // instantiation, so the full check's kernel carries no extra live state).
 template <class Model, bool UNIFORM_R, int NCH, bool LIST = false>
-__global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interior(EdgeArgs A, const ArmParams *Rg,
-                                                                               SceneParams S) {
+__global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
+    k_interior(EdgeArgs A, const ArmParams *Rg, SceneParams S) {
     constexpr int D = Model::D;
     constexpr int KP = Model::KP;
     constexpr bool ARM = Model::kArm;
+    constexpr bool GRID = Model::kGrid;
     constexpr int W = ARM ? 3 : D;
     constexpr int SP = ARM ? 1 : KP;  // interior states per evaluation
     constexpr int KC = ARM ? KP / NCH : KP;
     static_assert(!ARM || KP % NCH == 0, "chunking must divide the sphere slots");
     __shared__ float tord[GTMP_MAX_H];
+    constexpr int WG = Model::kWords > 1 ? 2 : 1;
+    __shared__ typename std::conditional<GRID, GridLds<WG>, char>::type glds_raw;
+    __shared__ typename std::conditional<GRID, GridQueue<WG>[256 / kWave], char>::type gque;
+    const ObsGrid &glds = *reinterpret_cast<const ObsGrid *>(&glds_raw);  // the first grid_lds_bytes<WG>()
     for (int i = threadIdx.x; i < A.n_int; i += blockDim.x) tord[i] = A.tord[i];
+    if constexpr (GRID) {  // the maps, the obstacles and the mask words this kernel reads
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.grid);
+        uint4 *dst = reinterpret_cast<uint4 *>(&glds_raw);
+        constexpr int n16 = (int)(grid_lds_bytes<WG>() / 16);
+        for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+    }
     __syncthreads();
+    float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
+    if constexpr (GRID) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ginv[i] = glds.inv[i];
+            goff[i] = glds.off[i];
+        }
+    }
 
     const int lane = lane_id();
     uint32_t n_tiles = A.n_tiles;
@@ -228,6 +247,7 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interi
     RowInfo ri{};
     bool exhausted = false;
     unsigned long long n_states = 0, n_edges = 0;
+    uint32_t n_tests = 0;  // exact sphere-obstacle tests behind the bin filter (this lane)
 
     // lane state: the edge (flat id), its start and direction, next state
     bool has = false;
@@ -295,8 +315,15 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interi
             carm Rp = (carm)Rg;
             asm volatile("" : "+s"(Rp));
             const auto &R = *Rp;
-            const v32f o = arm_fk<D>(R, q);
-            gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
+            if constexpr (GRID) {
+                uint32_t tests = 0;
+                gap = arm_hit_grid<Model::kWords>(R, q, glds, ginv, goff, gque[threadIdx.x / kWave], tests, has)
+                          ? -1.f : 1.f;
+                n_tests += tests;
+            } else {
+                const v32f o = arm_fk<D>(R, q);
+                gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
+            }
         } else {
             Probes<W, KP> P;
 #pragma unroll
@@ -328,6 +355,14 @@ __global__ void __launch_bounds__(256, NCH == 1 ? 3 : NCH == 2 ? 4 : 5) k_interi
                     has = false;
                 }
             }
+        }
+    }
+    if constexpr (GRID) {
+        if (A.stats) {
+            unsigned long long t = n_tests;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+            if (lane == 0) atomicAdd(&A.stats[2], t);
         }
     }
     if (A.stats && lane == 0) {
@@ -490,10 +525,13 @@ __global__ void __launch_bounds__(256) k_state_check(ArmParams R, SceneParams S,
 // ------------------------------------------------------------------ launchers
 static int round_kp(int k) { return ((k + 7) / 8) * 8; }
 
+// gw: mask words of the obstacle-bin filter (1 or 2), 0 for the chunked test
+// of every sphere against every obstacle.
 template <int KP, int NCH>
 static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, const EdgeBuffers &b,
                                 const gtmp_edge_opts &o, int grid_persist, hipStream_t s, const float *q0,
-                                const float *goals, const float *Q, float *verts, uint8_t *vflag, int phases) {
+                                const float *goals, const float *Q, float *verts, uint8_t *vflag, int phases,
+                                int gw) {
     const unsigned vb = (A.n_vertices + 255) / 256;
     ArmParams *Rg = reinterpret_cast<ArmParams *>(static_cast<char *>(b.workspace) + A.off_params);
     if (phases & kPhaseVertices) {
@@ -502,9 +540,24 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
     }
     if (!(phases & kPhaseEdges)) return hipGetLastError();
     hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    if (gw && A.n_int > 0) {
+        float r_max = 0.f;
+        for (int k = 0; k < R.n_spheres; ++k) r_max = r_max > R.r[k] ? r_max : R.r[k];
+        hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max,
+                           const_cast<ObsGrid *>(A.grid));
+    }
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    } else if (gw) {
+        if (A.tile_list && gw == 1)  // lazy round: compacted tiles
+            hipLaunchKernelGGL((k_interior<ArmGridModel<1>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
+        else if (A.tile_list)
+            hipLaunchKernelGGL((k_interior<ArmGridModel<2>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
+        else if (gw == 1)
+            hipLaunchKernelGGL((k_interior<ArmGridModel<1>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
+        else
+            hipLaunchKernelGGL((k_interior<ArmGridModel<2>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     } else if (A.tile_list) {  // lazy round: two sphere chunks, compacted tiles
         if (R.uniform_r)
             hipLaunchKernelGGL((k_interior<ArmModel<KP>, true, 2, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
@@ -653,9 +706,16 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
     if (phases & kPhaseEdges) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, A.counter, 2);
     if (arm) {
         const int kp = round_kp(R.n_spheres);
+        const int n_obs = scene.n_sph + scene.n_box;
+        // automatic choice: the obstacle-bin filter whenever the masks hold
+        // every obstacle, else (and on request) the chunked full test
+        const int gw = o.sphere_chunks == 0 && n_obs <= kGridMaxObs ? (n_obs <= 32 ? 1 : 2) : 0;
         const int nch = o.sphere_chunks == 1 ? 1 : o.sphere_chunks == 4 ? 4 : 2;
+        A.grid = reinterpret_cast<const ObsGrid *>(ws + plan.off_grid);
         const void *kern = nullptr;
-        switch (kp * 8 + nch) {
+        switch (gw ? -gw : kp * 8 + nch) {
+            case -1: kern = (const void *)k_interior<ArmGridModel<1>, true, 1>; break;
+            case -2: kern = (const void *)k_interior<ArmGridModel<2>, true, 1>; break;
 #define GTMP_KK(K, C) case K * 8 + C: kern = R.uniform_r ? (const void *)k_interior<ArmModel<K>, true, C> : (const void *)k_interior<ArmModel<K>, false, C>; break;
 #define GTMP_KK3(K) GTMP_KK(K, 1) GTMP_KK(K, 2) GTMP_KK(K, 4)
             GTMP_KK3(8) GTMP_KK3(16) GTMP_KK3(24) GTMP_KK3(32) GTMP_KK3(40) GTMP_KK3(48) GTMP_KK3(56) GTMP_KK3(64)
@@ -665,7 +725,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
         }
         const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles);
         switch (kp * 8 + nch) {
-#define GTMP_LA(K, C) case K * 8 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag, phases);
+#define GTMP_LA(K, C) case K * 8 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag, phases, gw);
 #define GTMP_LA3(K) GTMP_LA(K, 1) GTMP_LA(K, 2) GTMP_LA(K, 4)
             GTMP_LA3(8) GTMP_LA3(16) GTMP_LA3(24) GTMP_LA3(32) GTMP_LA3(40) GTMP_LA3(48) GTMP_LA3(56) GTMP_LA3(64)
 #undef GTMP_LA3

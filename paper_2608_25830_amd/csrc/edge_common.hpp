@@ -2,9 +2,50 @@
 // single-plan edge kernels (edge.hip) and the batched ones (batch.hip).
 #pragma once
 
+#include <stddef.h>
+
+#include <type_traits>
+
 #include "gtmp_launch.hpp"
 
 namespace gtmp {
+
+// ------------------------------------------------------------------ obstacle bins
+// A conservative filter in front of the exact sphere test of an arm state.
+// Each obstacle o is a rounded box: the points within rho_o of the box
+// [lo_o, hi_o] (a sphere obstacle has lo = hi = centre and rho = its radius,
+// a box has rho = 0).  A robot sphere of radius r at p can only touch it if,
+// on every axis i, p_i lies in [lo_oi - E_o, hi_oi + E_o] with
+// E_o = (rho_o + r_max)(1 + 2^-12).  Each axis is cut into bins by the bin
+// coordinate f = x inv_i + off_i (one FP32 fused multiply-add) and the bin
+// index rne(f) saturated to 0..255 (one v_cvt_pk_u8_f32, which also sends NaN
+// to 0).  The obstacles span f in about [5, 250], so bins 0 and 255 catch
+// everything outside and hold no obstacle.  mask[w][i][b] has bit o - 32 w
+// set when obstacle o's interval on axis i reaches bin b, widened by one bin
+// on each side.  The AND of the three masks of p's bins therefore holds every
+// obstacle the exact test could find in contact with p: the kernel evaluates
+// the exact test on those obstacles only, and its decision is the one of the
+// full test.
+constexpr int kGridCells = 256;
+constexpr int kGridMaxObs = 64;
+
+struct ObsGrid {
+    float inv[4], off[4];                  // axes x, y, z (the fourth entry unused)
+    float4 rec[kGridMaxObs][2];            // (lo.xyz, rho), (hi.xyz, 0)
+    uint32_t mask[2][3][kGridCells];       // mask word, axis, bin
+};
+// The part of the grid a kernel with WORDS mask words copies to LDS.
+template <int WORDS>
+constexpr size_t grid_lds_bytes() { return offsetof(ObsGrid, mask) + sizeof(uint32_t) * 3 * kGridCells * WORDS; }
+
+template <int WORDS>
+struct alignas(16) GridLds {
+    unsigned char bytes[grid_lds_bytes<WORDS>()];
+};
+
+__device__ __forceinline__ uint32_t grid_bin(float f) { return __builtin_amdgcn_cvt_pk_u8_f32(f, 0u, 0u); }
+
+static_assert(sizeof(ObsGrid) % 16 == 0 && grid_lds_bytes<1>() % 16 == 0, "the grid is copied in 16-byte words");
 
 // ------------------------------------------------------------------ kernel args
 struct EdgeArgs {
@@ -22,6 +63,7 @@ struct EdgeArgs {
     uint32_t *counter;  // [0] tile cursor of the interior kernel, [1] length of tile_list
     uint32_t *tile_list;  // lazy rounds: the tiles holding candidates (NULL: every tile in order)
     unsigned long long *stats;
+    const ObsGrid *grid;  // arms with the bin filter: the obstacle bins of this scene
     size_t off_params;  // workspace byte offset of the device copy of the robot table
     int n_int;
     float tord[GTMP_MAX_H];  // t = h / (H-1) of the interior states, in check order
@@ -67,6 +109,223 @@ __device__ __forceinline__ float arm_state_gap(const AP &R, const v32f &o, float
         gap = ch == 0 ? g : __builtin_fminf(gap, g);
     }
     return gap;
+}
+
+// The obstacle bins of a scene for robot spheres of radius <= r_max, built
+// by one block of kGridBuildThreads threads (a thread per obstacle, then a
+// wave per axis, then a thread per (axis, bin) cell).  The bin maps and the obstacle intervals are computed in
+// FP32 with the same fused multiply-add and bin rounding the interior kernel
+// applies to a sphere centre (both monotone), and every interval is widened by
+// one bin on each side, so rounding in either place cannot move a sphere out
+// of a bin that lists the obstacle.  An obstacle with non-finite data is
+// listed in every bin, the outer two included, and takes no part in the bin
+// maps; should a map still come out non-finite, every obstacle is listed
+// everywhere.  Either way the exact test then sees that obstacle for every
+// sphere, as without the filter.
+constexpr int kGridBuildThreads = 3 * kGridCells;  // one (axis, bin) cell per thread
+
+__device__ __forceinline__ void build_grid_block(const SceneParams &S, float r_max, ObsGrid *G) {
+    __shared__ float lo_s[kGridMaxObs][3], hi_s[kGridMaxObs][3];
+    __shared__ int wild_s[kGridMaxObs];
+    __shared__ int2 span_s[3][kGridMaxObs];  // bins listed for obstacle o on each axis
+    __shared__ float map_s[3][2];
+    __shared__ int bad_s;
+    const int n = S.n_sph + S.n_box;  // <= kGridMaxObs (checked by the launcher)
+    const int tid = threadIdx.x;
+    if (tid == 0) bad_s = 0;
+    if (tid < n) {
+        float lo[3], hi[3], rho;
+        if (tid < S.n_sph) {
+            const float *c = S.sph + 4 * tid;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) lo[i] = hi[i] = c[i];
+            rho = c[3];
+        } else {
+            const float *b = S.box + 6 * (tid - S.n_sph);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                lo[i] = b[i] - b[3 + i];
+                hi[i] = b[i] + b[3 + i];
+            }
+            rho = 0.f;
+        }
+        G->rec[tid][0] = make_float4(lo[0], lo[1], lo[2], rho);
+        G->rec[tid][1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+        const float ext = (__builtin_fabsf(rho) + r_max) * (1.f + 0x1p-12f);
+        bool wild = !__builtin_isfinite(ext);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lo_s[tid][i] = lo[i] - ext;
+            hi_s[tid][i] = hi[i] + ext;
+            wild = wild || !__builtin_isfinite(lo[i] - ext) || !__builtin_isfinite(hi[i] + ext);
+        }
+        wild_s[tid] = wild ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid < 3 * kWave) {  // one wave per axis: the extent of the finite obstacles
+        const int ax = tid / kWave, l = tid % kWave;
+        float a = __builtin_inff(), b = -__builtin_inff();
+        if (l < n && !wild_s[l]) {
+            a = lo_s[l][ax];
+            b = hi_s[l][ax];
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            a = __builtin_fminf(a, __shfl_xor(a, off));
+            b = __builtin_fmaxf(b, __shfl_xor(b, off));
+        }
+        if (!(a <= b)) {  // no finite obstacle
+            a = 0.f;
+            b = 1.f;
+        }
+        // [a, b] -> f in [1, 254], the obstacles (four bins in) in about [5, 250]
+        constexpr float kSpan = (float)(kGridCells - 3);
+        const float scale = __builtin_fmaxf(1.f, __builtin_fmaxf(__builtin_fabsf(a), __builtin_fabsf(b)));
+        const float span = __builtin_fmaxf(b - a, 1e-6f * scale);
+        const float pad = span * (4.f / kSpan);
+        a -= pad;
+        b += pad;
+        const float inv = kSpan / (b - a);
+        const float off = __builtin_fmaf(-a, inv, 1.f);
+        if (l == 0) {
+            if (!__builtin_isfinite(inv) || !__builtin_isfinite(off) || !(inv > 0.f)) bad_s = 1;
+            map_s[ax][0] = inv;
+            map_s[ax][1] = off;
+            G->inv[ax] = inv;
+            G->off[ax] = off;
+        }
+        if (l < n) {  // the obstacle's bins on this axis, one bin wider on each side
+            int2 sp = make_int2(0, kGridCells - 1);  // non-finite obstacle: every bin
+            if (!wild_s[l]) {
+                sp.x = (int)grid_bin(__builtin_fmaf(lo_s[l][ax], inv, off)) - 1;
+                sp.y = (int)grid_bin(__builtin_fmaf(hi_s[l][ax], inv, off)) + 1;
+                sp.x = sp.x < 1 ? 1 : sp.x;
+                sp.y = sp.y > kGridCells - 2 ? kGridCells - 2 : sp.y;
+            }
+            span_s[ax][l] = sp;
+        }
+    }
+    if (tid == 3 * kWave) {
+        G->inv[3] = 0.f;
+        G->off[3] = 0.f;
+    }
+    __syncthreads();
+    const int ax = tid / kGridCells, bin = tid - ax * kGridCells;
+    uint32_t w[2] = {0u, 0u};
+    const bool all = bad_s != 0;
+    for (int o = 0; o < n; ++o) {
+        const int2 sp = span_s[ax][o];
+        if (all || (bin >= sp.x && bin <= sp.y)) w[o >> 5] |= 1u << (o & 31);
+    }
+    G->mask[0][ax][bin] = w[0];
+    G->mask[1][ax][bin] = w[1];
+}
+
+// Collision of one arm state through the obstacle bins (G in LDS; inv / off
+// the bin maps of G held in registers).  For every robot sphere k (centre c,
+// radius r_k) the obstacles of its bin masks are tested exactly as the full
+// test does, R = rho_o + r_k, gap = -R^2 + sum_i (c_i - med3(c_i, lo_i, hi_i))^2
+// in that order, and the state collides iff some gap is <= 0.
+//
+// Few spheres of a wave have a non-empty mask (about one in seven on the arm
+// workloads), so the exact tests are not made where the masks are found:
+// each such sphere is appended to the wave's queue Qw in LDS (centre, radius,
+// mask, owning lane), and whenever 64 entries are waiting the wave takes them
+// one per lane, which keeps every lane busy in the tests.  A lane appends
+// nothing more once a drained test has found its state in contact, and a lane
+// that is not `live` appends nothing at all (its result is then meaningless).
+// `tests` counts the exact tests this lane made (for other lanes' entries too).
+// Every lane of the wave must call this (it drains on ballots).
+constexpr int kQueue = 128;  // entries per wave: up to 63 waiting plus one sphere of every lane
+
+template <int WORDS>
+struct GridQueue {
+    typedef typename std::conditional<WORDS == 2, uint64_t, uint32_t>::type Mask;
+    struct Entry {
+        float4 c;  // centre, radius
+        uint4 m;   // mask words 0 and 1, owning lane, unused
+    } e[kQueue];
+    uint8_t hit[kWave];
+};
+
+template <int WORDS, class AP>
+__device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_MAX_JOINTS], const ObsGrid &G,
+                                             const float (&inv)[3], const float (&off)[3],
+                                             GridQueue<WORDS> &Qw, uint32_t &tests, bool live) {
+    typedef typename GridQueue<WORDS>::Mask Mask;
+    const int lane = lane_id();
+    uint32_t head = 0, tail = 0;  // wave-uniform queue positions (mod kQueue in LDS)
+    bool hit = !live;             // an idle lane appends nothing
+    Qw.hit[lane] = 0;
+    auto drain = [&](uint32_t n) {  // the n <= 64 oldest entries, one per lane
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t slot = (head + (uint32_t)lane) & (kQueue - 1);
+        Mask m = 0;
+        float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+        int own = 0;
+        if ((uint32_t)lane < n) {
+            e = Qw.e[slot].c;
+            const uint4 w = Qw.e[slot].m;
+            m = WORDS == 1 ? (Mask)w.x : (Mask)(((uint64_t)w.y << 32) | w.x);
+            own = (int)w.z;
+        }
+        while (ballot(m != 0) != 0) {
+            if (m != 0) {
+                const int o = WORDS == 1 ? __builtin_ctz((uint32_t)m) : __builtin_ctzll((uint64_t)m);
+                m &= m - 1;
+                ++tests;
+                const float4 a = G.rec[o][0], h = G.rec[o][1];
+                const float Rr = a.w + e.w;
+                float g = -Rr * Rr;
+                const float c[3] = {e.x, e.y, e.z}, lo[3] = {a.x, a.y, a.z}, hi[3] = {h.x, h.y, h.z};
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const float dlt = c[i] - __builtin_amdgcn_fmed3f(c[i], lo[i], hi[i]);
+                    g = __builtin_fmaf(dlt, dlt, g);
+                }
+                if (g <= 0.f) {
+                    Qw.hit[own] = 1;
+                    m = 0;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        head += n;
+        hit = hit || Qw.hit[lane] != 0;
+    };
+    arm_fk_visit<GTMP_MAX_JOINTS>(R, q, [&](int L, const float (&b)[3], const float (&p)[3]) {
+        float dd[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dd[i] = p[i] - b[i];
+        const int k0 = L == 1 ? 0 : R.lk_end[L - 2];
+        const int k1 = R.lk_end[L - 1];
+        for (int k = k0; k < k1; ++k) {
+            const float t = R.t[k], rk = R.r[k];
+            float c[3];
+            uint32_t bin[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                c[i] = __builtin_fmaf(t, dd[i], b[i]);
+                bin[i] = grid_bin(__builtin_fmaf(c[i], inv[i], off[i]));
+            }
+            Mask m = G.mask[0][0][bin[0]] & G.mask[0][1][bin[1]] & G.mask[0][2][bin[2]];
+            if constexpr (WORDS == 2)
+                m |= (Mask)(G.mask[1][0][bin[0]] & G.mask[1][1][bin[1]] & G.mask[1][2][bin[2]]) << 32;
+            const bool want = m != 0 && !hit;
+            const uint64_t wmask = ballot(want);
+            if (wmask != 0) {
+                if (want) {
+                    const uint32_t slot = (tail + (uint32_t)rank_in(wmask)) & (kQueue - 1);
+                    Qw.e[slot].c = make_float4(c[0], c[1], c[2], rk);
+                    Qw.e[slot].m = make_uint4((uint32_t)m, (uint32_t)((uint64_t)m >> 32), (uint32_t)lane, 0u);
+                }
+                tail += (uint32_t)__popcll(wmask);
+                if (tail - head >= (uint32_t)kWave) drain(kWave);
+            }
+        }
+    });
+    if (tail != head) drain(tail - head);
+    return hit;
 }
 
 // Row / tile decoding.  Rows enumerate the edges by their shared endpoint:
@@ -145,6 +404,8 @@ __device__ __forceinline__ float failed_cost(float len, float penalty) { return 
 template <int W, int S>
 struct PointModel {
     static constexpr bool kArm = false;
+    static constexpr bool kGrid = false;
+    static constexpr int kWords = 0;
     static constexpr int D = W;
     static constexpr int KP = S;  // probes per evaluation = S states
 };
@@ -152,8 +413,21 @@ struct PointModel {
 template <int KPm>
 struct ArmModel {
     static constexpr bool kArm = true;
+    static constexpr bool kGrid = false;
+    static constexpr int kWords = 0;
     static constexpr int D = GTMP_MAX_JOINTS;
     static constexpr int KP = KPm;
+};
+
+// Arm states tested through the obstacle bins (WORDS 32-bit mask words: up to
+// 32 WORDS obstacles).
+template <int WORDS>
+struct ArmGridModel {
+    static constexpr bool kArm = true;
+    static constexpr bool kGrid = true;
+    static constexpr int kWords = WORDS;
+    static constexpr int D = GTMP_MAX_JOINTS;
+    static constexpr int KP = 1;
 };
 
 

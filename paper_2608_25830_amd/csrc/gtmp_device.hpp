@@ -53,6 +53,7 @@ struct ArmParams {
     int link[GTMP_MAX_ROBOT_SPHERES];
     float t[GTMP_MAX_ROBOT_SPHERES];
     float r[GTMP_MAX_ROBOT_SPHERES];
+    int lk_end[GTMP_MAX_JOINTS];  // spheres of link L (1-based) are lk_end[L-2] .. lk_end[L-1]-1 (from 0 for L = 1)
     float reach;    // bound on |sphere centre|: sum of the link lengths sqrt(a^2 + d^2), rounded up
     float sph_tol;  // rounding bound of the expanded sphere test (set on the device per launch)
 };
@@ -293,12 +294,10 @@ __device__ __forceinline__ float point_sd(const float (&p)[W], const SceneParams
 // ---------------------------------------------------------------------------
 typedef float v32f __attribute__((ext_vector_type(32)));
 
-template <int D, class AP>
-__device__ __forceinline__ v32f arm_fk(const AP &A, const float (&q)[D]) {
-    v32f o;  // only o_0 .. o_J are written and read
-    o[0] = 0.f;
-    o[1] = 0.f;
-    o[2] = 0.f;
+// Frame origins visited link by link: after joint j the visitor gets the link
+// index L = j + 1 and the origins o_{L-1} (b) and o_L (p) of that link.
+template <int D, class AP, class F>
+__device__ __forceinline__ void arm_fk_visit(const AP &A, const float (&q)[D], F &&link) {
     float x0 = 1.f, x1 = 0.f, x2 = 0.f;
     float y0 = 0.f, y1 = 1.f, y2 = 0.f;
     float z0 = 0.f, z1 = 0.f, z2 = 1.f;
@@ -306,6 +305,7 @@ __device__ __forceinline__ v32f arm_fk(const AP &A, const float (&q)[D]) {
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         if (j >= A.n_joints) break;
+        const float b[3] = {p0, p1, p2};
         float st, ct;
         sincosf(q[j] + A.off[j], &st, &ct);
         const float xn0 = ct * x0 + st * y0, xn1 = ct * x1 + st * y1, xn2 = ct * x2 + st * y2;
@@ -319,10 +319,22 @@ __device__ __forceinline__ v32f arm_fk(const AP &A, const float (&q)[D]) {
         x0 = xn0; x1 = xn1; x2 = xn2;
         y0 = yn0; y1 = yn1; y2 = yn2;
         z0 = zn0; z1 = zn1; z2 = zn2;
-        o[3 * (j + 1) + 0] = p0;
-        o[3 * (j + 1) + 1] = p1;
-        o[3 * (j + 1) + 2] = p2;
+        const float p[3] = {p0, p1, p2};
+        link(j + 1, b, p);
     }
+}
+
+template <int D, class AP>
+__device__ __forceinline__ v32f arm_fk(const AP &A, const float (&q)[D]) {
+    v32f o;  // only o_0 .. o_J are written and read
+    o[0] = 0.f;
+    o[1] = 0.f;
+    o[2] = 0.f;
+    arm_fk_visit<D>(A, q, [&](int L, const float (&)[3], const float (&p)[3]) {
+        o[3 * L + 0] = p[0];
+        o[3 * L + 1] = p[1];
+        o[3 * L + 2] = p[2];
+    });
     return o;
 }
 
@@ -355,7 +367,7 @@ __device__ __forceinline__ void arm_spheres(const AP &A, const v32f &o, Probes<3
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ int rank_in(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

@@ -26,7 +26,7 @@ struct EdgePlan {
     uint32_t tiles_per_row;  // ceil(N / kTile)
     uint32_t n_tiles;
     // workspace carve-up (byte offsets)
-    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_tile_list, off_counter, off_params, total;
+    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_tile_list, off_counter, off_params, off_grid, total;
 };
 
 EdgePlan make_edge_plan(const gtmp_problem &p);
@@ -168,7 +168,7 @@ struct BatchLayout {
     int n, max_stages;
     std::vector<PlanOffsets> plan_off;
     std::vector<std::vector<StageShape>> schedules;
-    size_t off_arm, off_tables, off_bases, off_counters, total;
+    size_t off_arm, off_grids, off_tables, off_bases, off_counters, total;
 };
 BatchLayout make_batch_layout(const gtmp_plan_desc *plans, int n, const gtmp_batch_opts &o);
 struct BatchOut {

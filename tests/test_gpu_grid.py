@@ -1,0 +1,140 @@
+"""The obstacle-bin filter of the arm edge check (the automatic choice for
+scenes of at most 64 obstacles) against the chunked test of every robot
+sphere against every obstacle (sphere_chunks = 2): both decide each state by
+the same FP32 difference-form gaps, so every edge cost and flag must agree
+bit for bit.  Cases: the arm7 scenes, per-sphere radii, one and two mask
+words (32 / 33 / 60 obstacles), the fallback above 64, no obstacles,
+degenerate obstacles and robot spheres of radius 0, a scene scaled by 50, and
+the lazy rounds' compacted-tile kernel.  Agreement with the oracle is checked
+by the parity tests, which run the automatic choice."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _flat(pl):
+    M = pl.M
+    parts = [pl.C_s.cpu().numpy().ravel()]
+    if M > 1:
+        parts.append(pl.C_h.cpu().numpy()[: M - 1].ravel())
+    parts.append(pl.C_l.cpu().numpy().ravel())
+    return np.concatenate(parts)
+
+
+def _both(gt, w, seed=None):
+    """Edge costs and flags of one sample set under both arm tests."""
+    out = []
+    for chunks in (0, 2):
+        pl = gt.Planner(w, flags=True)
+        pl.opts.sphere_chunks = chunks
+        pl.sample(w["seed"] if seed is None else seed, 0)
+        pl.check()
+        torch.cuda.synchronize()
+        out.append((_flat(pl), pl.flags.cpu().numpy().copy(), int(pl.stats[0].item())))
+    return out
+
+
+def _assert_same(res, label):
+    (cg, fg, sg), (cd, fd, sd) = res
+    n_free = int((fg == 0).sum())
+    _say(label, "edges", fg.size, "free", n_free, "states grid", sg, "dense", sd)
+    assert np.array_equal(fg, fd), f"{label}: flags differ at {np.flatnonzero(fg != fd)[:10]}"
+    assert np.array_equal(cg.view(np.uint32), cd.view(np.uint32)), label
+    assert sg == sd  # the same states are evaluated (same early exits)
+    return n_free
+
+
+def _obstacles(seed, n_sph, n_box, extent=1.0):
+    g = np.random.default_rng(seed)
+    sp = np.concatenate([g.uniform(-extent, extent, (n_sph, 3)), g.uniform(0.05, 0.2, (n_sph, 1))], 1)
+    bx = np.concatenate([g.uniform(-extent, extent, (n_box, 3)), g.uniform(0.05, 0.2, (n_box, 3))], 1)
+    return sp.astype(np.float32).reshape(n_sph, 4), bx.astype(np.float32).reshape(n_box, 6)
+
+
+@pytest.mark.parametrize("scene", [0, 1, 2])
+def test_grid_matches_full_test_arm7(gt, scene):
+    w = wl.make_workload("arm7", scene, M=4, N=256)
+    n_free = _assert_same(_both(gt, w), f"arm7 scene {scene}")
+    assert 0 < n_free < w["N"] * (w["N"] * 3 + 2)
+
+
+def test_grid_per_sphere_radii(gt):
+    w = wl.make_workload("arm7", 0, M=3, N=256)
+    g = np.random.default_rng(7)
+    w["sph_r"] = g.uniform(0.02, 0.09, w["sph_r"].shape).astype(np.float32)
+    _assert_same(_both(gt, w), "per-sphere radii")
+
+
+@pytest.mark.parametrize("n_sph,n_box", [(16, 16), (17, 16), (30, 30), (0, 40), (40, 0), (40, 30)])
+def test_grid_obstacle_counts(gt, n_sph, n_box):
+    """32 obstacles fill one mask word, 33 and 60 take two, 70 fall back to the
+    full test for both settings."""
+    w = wl.make_workload("arm7", 1, M=3, N=192)
+    w["obs_spheres"], w["obs_boxes"] = _obstacles(n_sph * 100 + n_box, n_sph, n_box)
+    _assert_same(_both(gt, w), f"{n_sph} spheres + {n_box} boxes")
+
+
+def test_grid_no_obstacles(gt):
+    w = wl.make_workload("arm7", 0, M=3, N=128)
+    w["obs_spheres"] = np.zeros((0, 4), np.float32)
+    w["obs_boxes"] = np.zeros((0, 6), np.float32)
+    res = _both(gt, w)
+    _assert_same(res, "no obstacles")
+    assert (res[0][1] == 0).all()
+
+
+def test_grid_degenerate_obstacles_and_radius(gt):
+    """Flat boxes (one half-extent 0), point boxes, sphere obstacles of radius
+    0 and robot spheres of radius 0: the bins still list every contact."""
+    w = wl.make_workload("arm7", 2, M=3, N=192)
+    sp, bx = _obstacles(5, 12, 14)
+    sp[:4, 3] = 0.0
+    bx[np.arange(5), 3 + np.arange(5) % 3] = 0.0
+    bx[5:8, 3:] = 0.0
+    w["obs_spheres"], w["obs_boxes"] = sp, bx
+    _assert_same(_both(gt, w), "degenerate obstacles")
+    w["sph_r"] = np.zeros_like(w["sph_r"])
+    _assert_same(_both(gt, w), "robot radius 0")
+
+
+def test_grid_scaled_scene(gt):
+    """Arm and obstacles scaled by 50: the bin maps follow the scene's extent."""
+    w = wl.make_workload("arm7", 0, M=3, N=192)
+    w["dh"] = w["dh"].copy()
+    w["dh"][:, 0] *= 50.0
+    w["dh"][:, 2] *= 50.0
+    w["sph_r"] = w["sph_r"] * 50.0
+    w["obs_spheres"] = w["obs_spheres"] * 50.0
+    w["obs_boxes"] = w["obs_boxes"] * 50.0
+    _assert_same(_both(gt, w), "scaled by 50")
+
+
+@pytest.mark.parametrize("band", [0.0, 0.5])
+def test_grid_lazy_rounds(gt, band):
+    """Lazy rounds run the compacted-tile kernel: the filtered and the full
+    test give the same rounds, checked edges and plan."""
+    w = wl.make_workload("arm7", 1, M=4, N=256)
+    res = []
+    for chunks in (0, 2):
+        pl = gt.Planner(w, flags=True)
+        pl.opts.sphere_chunks = chunks
+        stats = torch.zeros(2, device="cuda", dtype=torch.int64)
+        st, rounds = pl.plan_lazy(w["seed"], 0, band=band, max_rounds=20000, stats=stats)
+        torch.cuda.synchronize()
+        res.append((st, rounds, stats.cpu().numpy().copy(), pl.flags.cpu().numpy().copy(), _flat(pl),
+                    float(pl.V_s.item())))
+    _say("lazy band", band, "rounds", res[0][1], res[1][1], "V_s", res[0][5], res[1][5])
+    assert res[0][0] == res[1][0] == gt.GTMP_OK
+    assert res[0][1] == res[1][1]
+    assert np.array_equal(res[0][2], res[1][2])
+    assert np.array_equal(res[0][3], res[1][3])
+    assert np.array_equal(res[0][4].view(np.uint32), res[1][4].view(np.uint32))
+    assert res[0][5] == res[1][5]
