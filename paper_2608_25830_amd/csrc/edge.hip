@@ -137,6 +137,46 @@ __global__ void __launch_bounds__(256) k_vertices_arm(EdgeArgs A, ArmParams R, S
     if (valid) vflag[i] = gap <= 0.f ? 1 : 0;
 }
 
+// Vertex flags of an arm through the obstacle bins (the same decisions as
+// k_vertices_arm).
+template <int WG>
+__global__ void __launch_bounds__(256) k_vertices_arm_grid(EdgeArgs A, ArmParams R, const float *q0,
+                                                           const float *goals, const float *Q, float *verts,
+                                                           uint8_t *vflag) {
+    __shared__ GridLds<WG> glds_raw;
+    __shared__ GridQueue<WG> gque[256 / kWave];
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.grid);
+        uint4 *dst = reinterpret_cast<uint4 *>(&glds_raw);
+        for (int k = threadIdx.x; k < (int)(grid_lds_bytes<WG>() / 16); k += blockDim.x) dst[k] = src[k];
+    }
+    __syncthreads();
+    const ObsGrid &G = *reinterpret_cast<const ObsGrid *>(&glds_raw);
+    float inv[3], off[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        inv[k] = G.inv[k];
+        off[k] = G.off[k];
+    }
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < A.n_vertices;
+    const uint32_t MN = (uint32_t)A.M * (uint32_t)A.N;
+    float q[GTMP_MAX_JOINTS];
+#pragma unroll
+    for (int j = 0; j < GTMP_MAX_JOINTS; ++j) q[j] = 0.f;
+    if (valid) {
+        const float *src = i == 0 ? q0 : (i <= MN ? Q + (size_t)(i - 1) * A.d : goals + (size_t)(i - 1 - MN) * A.d);
+#pragma unroll
+        for (int j = 0; j < GTMP_MAX_JOINTS; ++j)
+            if (j < A.d) q[j] = src[j];
+#pragma unroll
+        for (int j = 0; j < GTMP_MAX_JOINTS; ++j) verts[(size_t)i * A.dp + j] = q[j];
+    }
+    uint32_t tests = 0;
+    const bool hit = arm_hit_grid<WG>(R, q, G, inv, off, gque[threadIdx.x / kWave], tests, valid);
+    if (valid) vflag[i] = hit ? 1 : 0;
+}
+
 template <int W>
 __global__ void __launch_bounds__(256) k_vertices_point(EdgeArgs A, SceneParams S, const float *q0,
                                                         const float *goals, const float *Q, float *verts,
@@ -534,18 +574,26 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
                                 int gw) {
     const unsigned vb = (A.n_vertices + 255) / 256;
     ArmParams *Rg = reinterpret_cast<ArmParams *>(static_cast<char *>(b.workspace) + A.off_params);
+    float r_max = 0.f;
+    for (int k = 0; k < R.n_spheres; ++k) r_max = r_max > R.r[k] ? r_max : R.r[k];
+    ObsGrid *grid = const_cast<ObsGrid *>(A.grid);
     if (phases & kPhaseVertices) {
-        hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
+        if (gw) {
+            // the bins serve the vertex flags and, later, the interior kernel
+            hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max, grid);
+            if (gw == 1)
+                hipLaunchKernelGGL(k_vertices_arm_grid<1>, dim3(vb), dim3(256), 0, s, A, R, q0, goals, Q, verts, vflag);
+            else
+                hipLaunchKernelGGL(k_vertices_arm_grid<2>, dim3(vb), dim3(256), 0, s, A, R, q0, goals, Q, verts, vflag);
+        } else {
+            hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
+        }
         hipLaunchKernelGGL(k_store_params_tol, dim3(1), dim3(64), 0, s, R, Rg, S);
     }
     if (!(phases & kPhaseEdges)) return hipGetLastError();
     hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
-    if (gw && A.n_int > 0) {
-        float r_max = 0.f;
-        for (int k = 0; k < R.n_spheres; ++k) r_max = r_max > R.r[k] ? r_max : R.r[k];
-        hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max,
-                           const_cast<ObsGrid *>(A.grid));
-    }
+    if (gw && A.n_int > 0 && !(phases & kPhaseVertices))  // an edge pass on its own: bins built afresh
+        hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max, grid);
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
