@@ -196,44 +196,85 @@ __global__ void __launch_bounds__(256) k_vertices_point(EdgeArgs A, SceneParams 
 }
 
 // ------------------------------------------------------------------ 2. pre-pass
+// One block per (kPrepassRows consecutive rows, row segment): thread i takes
+// column seg * kTile + i of every row.  Consecutive rows of a layer share
+// their target vertices, so a thread loads its target once and reuses it
+// while the rows' targets stay the same; the per-tile compaction of all the
+// rows shares one barrier.
+constexpr int kPrepassRows = 8;
+
 template <int D>
 __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
-    __shared__ uint32_t wave_cnt[kTile / kWave];
-    const uint32_t tile = blockIdx.x;
-    const uint32_t row = tile / A.tiles_per_row;
-    const uint32_t seg = tile - row * A.tiles_per_row;
-    const RowInfo ri = decode_row(A, row);
-    const uint32_t n = seg * kTile + threadIdx.x;
-    const bool valid = n < (uint32_t)A.N;
-    bool cand = false;
-    const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
-    if (valid && (!A.select || A.select[e] != 0)) {
-        const uint32_t uid = ri.u_base + n * ri.u_step, vid = ri.v_base + n * ri.v_step;
-        float u[D], v[D];
-        load_vertex<D>(A, uid, u);
-        load_vertex<D>(A, vid, v);
-        const float len = edge_len<D>(u, v, A.d);
-        bool failed = (A.vflag[uid] | A.vflag[vid]) != 0 || len > A.max_len;
-        if (A.prune) failed = failed || A.prune[e] != 0;
-        ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
-        if (A.flags) A.flags[e] = 1;
-        cand = !failed;
-    }
-    const uint64_t mask = ballot(cand);
+    __shared__ uint32_t wave_cnt[kPrepassRows][kTile / kWave];
     const int w = threadIdx.x / kWave;
-    if (lane_id() == 0) wave_cnt[w] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    uint32_t base = 0, total = 0;
+    const uint32_t seg = blockIdx.x % A.tiles_per_row;
+    const uint32_t row0 = (blockIdx.x / A.tiles_per_row) * kPrepassRows;
+    const uint32_t rows = A.n_tiles / A.tiles_per_row;
+    const uint32_t n = seg * kTile + threadIdx.x;
+    const bool col = n < (uint32_t)A.N;
+    uint32_t candbits = 0;
+    uint32_t vb = 0xffffffffu, vs = 0xffffffffu;  // target pattern of the loaded v
+    float v[D];
 #pragma unroll
-    for (int k = 0; k < kTile / kWave; ++k) {
-        if (k < w) base += wave_cnt[k];
-        total += wave_cnt[k];
+    for (int i = 0; i < D; ++i) v[i] = 0.f;
+    uint8_t vfl = 0;
+#pragma unroll
+    for (int r = 0; r < kPrepassRows; ++r) {
+        const uint32_t row = row0 + r;
+        if (row >= rows) break;
+        const RowInfo ri = decode_row(A, row);
+        bool cand = false;
+        if (ri.v_base != vb || ri.v_step != vs) {
+            vb = ri.v_base;
+            vs = ri.v_step;
+            if (col) {
+                const uint32_t vid = vb + n * vs;
+                load_vertex<D>(A, vid, v);
+                vfl = A.vflag[vid];
+            }
+        }
+        const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
+        if (col && (!A.select || A.select[e] != 0)) {
+            const uint32_t uid = ri.u_base + n * ri.u_step;
+            float u[D];
+            load_vertex<D>(A, uid, u);
+            const float len = edge_len<D>(u, v, A.d);
+            bool failed = (A.vflag[uid] | vfl) != 0 || len > A.max_len;
+            if (A.prune) failed = failed || A.prune[e] != 0;
+            ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
+            if (A.flags) A.flags[e] = 1;
+            cand = !failed;
+        }
+        candbits |= (cand ? 1u : 0u) << r;
+        const uint64_t mask = ballot(cand);
+        if (lane_id() == 0) wave_cnt[r][w] = (uint32_t)__popcll(mask);
     }
-    if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
-    if (threadIdx.x == 0) {
-        A.tile_cnt[tile] = total;
-        if (A.tile_list && total) A.tile_list[atomicAdd(A.counter + 1, 1u)] = tile;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPrepassRows; ++r) {
+        const uint32_t row = row0 + r;
+        if (row >= rows) break;
+        const uint32_t tile = row * A.tiles_per_row + seg;
+        uint32_t base = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < kTile / kWave; ++k) {
+            if (k < w) base += wave_cnt[r][k];
+            total += wave_cnt[r][k];
+        }
+        const bool cand = (candbits >> r) & 1u;
+        const uint64_t mask = ballot(cand);
+        if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
+        if (threadIdx.x == 0) {
+            A.tile_cnt[tile] = total;
+            if (A.tile_list && total) A.tile_list[atomicAdd(A.counter + 1, 1u)] = tile;
+        }
     }
+}
+
+// Blocks of the pre-pass for a plan's tiles.
+static inline unsigned prepass_blocks(const EdgeArgs &A) {
+    const uint32_t rows = A.n_tiles / A.tiles_per_row;
+    return (unsigned)(((rows + kPrepassRows - 1) / kPrepassRows) * A.tiles_per_row);
 }
 
 // ------------------------------------------------------------------ 3. interior
@@ -591,7 +632,7 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
         hipLaunchKernelGGL(k_store_params_tol, dim3(1), dim3(64), 0, s, R, Rg, S);
     }
     if (!(phases & kPhaseEdges)) return hipGetLastError();
-    hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
     if (gw && A.n_int > 0 && !(phases & kPhaseVertices))  // an edge pass on its own: bins built afresh
         hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max, grid);
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
@@ -645,7 +686,7 @@ static hipError_t launch_point(const EdgeArgs &A, const ArmParams &R, const Scen
     if (phases & kPhaseVertices)
         hipLaunchKernelGGL(k_vertices_point<W>, dim3(vb), dim3(256), 0, s, A, S, q0, goals, Q, verts, vflag);
     if (!(phases & kPhaseEdges)) return hipGetLastError();
-    hipLaunchKernelGGL(k_prepass<W>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
+    hipLaunchKernelGGL(k_prepass<W>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
     switch (spi) {
         case 1: return launch_point_s<W, 1>(A, R, S, grid_persist, o, s);
         case 2: return launch_point_s<W, 2>(A, R, S, grid_persist, o, s);
