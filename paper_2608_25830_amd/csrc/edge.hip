@@ -39,7 +39,6 @@ EdgePlan make_edge_plan(const gtmp_problem &p) {
     e.off_vflag = o; o = up(o + e.n_vertices);
     e.off_tile_off = o; o = up(o + (size_t)e.n_tiles * kTile);
     e.off_tile_cnt = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
-    e.off_tile_list = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
     e.off_counter = o; o = up(o + 256);
     e.off_params = o; o = up(o + sizeof(ArmParams));
     e.off_grid = o; o = up(o + sizeof(ObsGrid));
@@ -234,7 +233,7 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
             }
         }
         const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
-        if (col && (!A.select || A.select[e] != 0)) {
+        if (col) {
             const uint32_t uid = ri.u_base + n * ri.u_step;
             float u[D];
             load_vertex<D>(A, uid, u);
@@ -264,10 +263,7 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
         const bool cand = (candbits >> r) & 1u;
         const uint64_t mask = ballot(cand);
         if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
-        if (threadIdx.x == 0) {
-            A.tile_cnt[tile] = total;
-            if (A.tile_list && total) A.tile_list[atomicAdd(A.counter + 1, 1u)] = tile;
-        }
+        if (threadIdx.x == 0) A.tile_cnt[tile] = total;
     }
 }
 
@@ -284,8 +280,21 @@ static inline unsigned prepass_blocks(const EdgeArgs &A) {
 // fewer live probe registers buy a higher occupancy for a few per-obstacle
 // set-up instructions more.
 
-// LIST: tiles come from the compacted list of a lazy round (a separate
-// instantiation, so the full check's kernel carries no extra live state).
+// Lazy lists of at most this many (edge, state) pairs are checked by
+// k_list_states, all states side by side; longer ones by the early-exit
+// interior kernel in list mode (both are launched; each returns at once when
+// the list is the other's).
+__device__ __forceinline__ uint64_t list_states_limit() { return 1ull << 19; }
+
+// LIST: the edges of a lazy round's list (A.edge_list, *A.n_list of them)
+// when the list is too long for k_list_states to take all their states at
+// once, in chunks instead of the pre-pass tiles: chunks sized to spread the
+// list over every resident wave (at least kListChunk edges, at most 64), a
+// lane walking its edge's states with early exit; a collision marks the edge
+// for k_list_finish (no pre-pass wrote a provisional cost).  A separate
+// instantiation, so the full check's kernel carries no extra live state.
+constexpr int kListChunk = 4;
+
 template <class Model, bool UNIFORM_R, int NCH, bool LIST = false>
 __global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
     k_interior(EdgeArgs A, const ArmParams *Rg, SceneParams S) {
@@ -321,7 +330,15 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 
 
     const int lane = lane_id();
     uint32_t n_tiles = A.n_tiles;
-    if constexpr (LIST) n_tiles = A.counter[1];
+    uint32_t chunk = kWave;
+    if constexpr (LIST) {
+        const uint32_t n_list = uniform(*A.n_list);
+        if ((uint64_t)n_list * (uint32_t)A.n_int <= list_states_limit()) return;  // k_list_states took it
+        const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+        chunk = (n_list + waves - 1) / waves;
+        chunk = chunk < (uint32_t)kListChunk ? (uint32_t)kListChunk : chunk > (uint32_t)kWave ? (uint32_t)kWave : chunk;
+        n_tiles = (n_list + chunk - 1) / chunk;
+    }
 
     // wave-uniform tile state
     uint32_t tile = 0, cnt = 0, pos = 0;
@@ -341,7 +358,9 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 
 
     while (true) {
         // ---- refill idle lanes from the current tile, taking new tiles as needed
-        uint64_t need = ballot(!has);
+        // (a list chunk fills the first `chunk` lanes of the wave)
+        const bool taker = !LIST || (uint32_t)lane < chunk;
+        uint64_t need = ballot(!has && taker);
         int n_need = __popcll(need);
         while (n_need > 0 && !exhausted) {
             const uint32_t avail = cnt - pos;
@@ -354,29 +373,41 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 
                     break;
                 }
                 tile = t;
-                if constexpr (LIST) tile = uniform(A.tile_list[t]);
-                ri = decode_row(A, tile / A.tiles_per_row);
-                cnt = uniform(A.tile_cnt[tile]);
+                if constexpr (LIST) {
+                    const uint32_t left = uniform(*A.n_list) - t * chunk;
+                    cnt = left < chunk ? left : chunk;
+                } else {
+                    ri = decode_row(A, tile / A.tiles_per_row);
+                    cnt = uniform(A.tile_cnt[tile]);
+                }
                 pos = 0;
                 continue;
             }
             const uint32_t take = avail < (uint32_t)n_need ? avail : (uint32_t)n_need;
             const int r = rank_in(need);
             if (!has && (uint32_t)r < take) {
-                const uint32_t seg = tile - (tile / A.tiles_per_row) * A.tiles_per_row;
-                const uint32_t n = seg * kTile + A.tile_off[(size_t)tile * kTile + pos + r];
+                uint32_t uid, vid;
+                if constexpr (LIST) {
+                    e = A.edge_list[(size_t)tile * chunk + pos + r];
+                    edge_vertex_ids(A, e, uid, vid);
+                } else {
+                    const uint32_t seg = tile - (tile / A.tiles_per_row) * A.tiles_per_row;
+                    const uint32_t n = seg * kTile + A.tile_off[(size_t)tile * kTile + pos + r];
+                    uid = ri.u_base + n * ri.u_step;
+                    vid = ri.v_base + n * ri.v_step;
+                    e = (uint32_t)(ri.e_base + (uint64_t)n * ri.e_step);
+                }
                 float v[D];
-                load_vertex<D>(A, ri.u_base + n * ri.u_step, u);
-                load_vertex<D>(A, ri.v_base + n * ri.v_step, v);
+                load_vertex<D>(A, uid, u);
+                load_vertex<D>(A, vid, v);
 #pragma unroll
                 for (int i = 0; i < D; ++i) dv[i] = v[i] - u[i];
-                e = (uint32_t)(ri.e_base + (uint64_t)n * ri.e_step);
                 j = 0;
                 has = true;
             }
             pos += take;
-            n_edges += take;
-            need = ballot(!has);
+            if constexpr (!LIST) n_edges += take;  // lists: counted by k_list_finish
+            need = ballot(!has && taker);
             n_need = __popcll(need);
         }
         const uint64_t busy = ballot(has);
@@ -422,10 +453,13 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 
         }
         if (has) {
             if (gap <= 0.f) {
-                has = false;  // failed: provisional cost and flag stand
+                if constexpr (LIST) A.list_mark[e] = 2;
+                has = false;  // failed: provisional cost and flag stand (lists: marked for k_list_finish)
             } else {
                 j += SP;
-                if (j >= A.n_int) {
+                if (j >= A.n_int && LIST) {
+                    has = false;  // free: k_list_finish writes the length
+                } else if (j >= A.n_int) {
                     // free edge: its cost is the length, computed as in the pre-pass
                     float acc = 0.f;
 #pragma unroll
@@ -468,6 +502,134 @@ __global__ void __launch_bounds__(kTile) k_finalize_no_interior(EdgeArgs A) {
     load_vertex<D>(A, ri.v_base + n * ri.v_step, v);
     ri.c_base[(size_t)n * ri.c_step] = edge_len<D>(u, v, A.d);
     if (A.flags) A.flags[ri.e_base + (uint64_t)n * ri.e_step] = 0;
+}
+
+// ------------------------------------------------------------------ lazy lists
+// The listed edges of a lazy round (flat ids of edges with free endpoints
+// within the length limit), every interior state of each at once: lane =
+// (listed edge, state).  A round lists few edges, mostly free, and walking an
+// edge's states one after another would chain their latencies; side by side
+// (without early exit: the flag is the OR over the states either way) they
+// overlap.  A colliding state marks its edge (list_mark[e] = 2), and
+// k_list_finish then writes every listed edge's cost and flag as the full
+// check does.
+constexpr int kListBlocksPerCu = 4;
+
+template <class Model, bool UNIFORM_R, int NCH>
+__global__ void __launch_bounds__(256, 3) k_list_states(EdgeArgs A, const ArmParams *Rg, SceneParams S) {
+    constexpr int D = Model::D;
+    constexpr int KP = Model::KP;
+    constexpr bool ARM = Model::kArm;
+    constexpr bool GRID = Model::kGrid;
+    constexpr int W = ARM ? 3 : D;
+    constexpr int WG = Model::kWords > 1 ? 2 : 1;
+    __shared__ float tord[GTMP_MAX_H];
+    __shared__ typename std::conditional<GRID, GridLds<WG>, char>::type glds_raw;
+    __shared__ typename std::conditional<GRID, GridQueue<WG>[256 / kWave], char>::type gque;
+    const ObsGrid &G = *reinterpret_cast<const ObsGrid *>(&glds_raw);
+    for (int i = threadIdx.x; i < A.n_int; i += blockDim.x) tord[i] = A.tord[i];
+    if constexpr (GRID) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.grid);
+        uint4 *dst = reinterpret_cast<uint4 *>(&glds_raw);
+        for (int i = threadIdx.x; i < (int)(grid_lds_bytes<WG>() / 16); i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
+    if constexpr (GRID) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ginv[i] = G.inv[i];
+            goff[i] = G.off[i];
+        }
+    }
+    const int lane = lane_id();
+    const uint32_t n_int = (uint32_t)A.n_int;
+    const uint64_t n_items = (uint64_t)uniform(*A.n_list) * n_int;
+    if (n_items > list_states_limit()) return;  // long lists: the early-exit kernel takes them
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    unsigned long long n_states = 0;
+    uint32_t n_tests = 0;
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave; base < n_items;
+         base += waves * kWave) {
+        const uint64_t item = base + (uint64_t)lane;
+        const bool live = item < n_items;
+        const uint32_t k = live ? (uint32_t)(item / n_int) : 0u, jj = live ? (uint32_t)(item - (uint64_t)k * n_int) : 0u;
+        const uint32_t e = A.edge_list[k];
+        uint32_t uid, vid;
+        edge_vertex_ids(A, e, uid, vid);
+        float u[D], v[D], q[D];
+        load_vertex<D>(A, uid, u);
+        load_vertex<D>(A, vid, v);
+        const float t = tord[jj];
+#pragma unroll
+        for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, v[i] - u[i], u[i]);
+        bool hit;
+        if constexpr (ARM) {
+            carm Rp = (carm)Rg;
+            asm volatile("" : "+s"(Rp));
+            const auto &R = *Rp;
+            if constexpr (GRID) {
+                hit = arm_hit_grid<Model::kWords>(R, q, G, ginv, goff, gque[threadIdx.x / kWave], n_tests, live);
+            } else {
+                const v32f o = arm_fk<D>(R, q);
+                hit = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, R.r0, S) <= 0.f;
+            }
+        } else {
+            Probes<W, 1> P;
+#pragma unroll
+            for (int i = 0; i < W; ++i) P.p[i][0] = q[i];
+            const float pr[1] = {0.f};
+            hit = probes_min_gap<W, 1, true>(P, pr, 0.f, S) <= 0.f;
+        }
+        if (live && hit) A.list_mark[e] = 2;
+        n_states += (unsigned long long)__popcll(ballot(live));
+    }
+    if (A.stats && lane == 0) atomicAdd(&A.stats[0], n_states);
+    if constexpr (GRID) {
+        if (A.stats) {
+            unsigned long long tt = n_tests;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) tt += __shfl_xor(tt, off);
+            if (lane == 0) atomicAdd(&A.stats[2], tt);
+        }
+    }
+}
+
+// Costs and flags of the listed edges: length if no state collided, else
+// length + penalty (the same FP32 values as the full check's).
+template <int D>
+__global__ void __launch_bounds__(256) k_list_finish(EdgeArgs A) {
+    const uint32_t n = *A.n_list;
+    if (A.stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&A.stats[1], (unsigned long long)n);
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const uint32_t e = A.edge_list[k];
+        uint32_t uid, vid;
+        edge_vertex_ids(A, e, uid, vid);
+        float u[D], v[D];
+        load_vertex<D>(A, uid, u);
+        load_vertex<D>(A, vid, v);
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            if (i < A.d) {
+                const float dv = v[i] - u[i];
+                acc = __builtin_fmaf(dv, dv, acc);
+            }
+        const float len = __builtin_sqrtf(acc);
+        const bool hit = A.list_mark[e] == 2;
+        *cost_slot(A, e) = hit ? failed_cost(len, A.penalty) : len;
+        if (A.flags) A.flags[e] = hit ? 1 : 0;
+    }
+}
+
+// Blocks of a lazy-list launch (the kernels stride over the list).
+static unsigned list_blocks() {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    return (unsigned)(cus * kListBlocksPerCu);
 }
 
 // ------------------------------------------------------------------ full mode
@@ -632,26 +794,39 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
         hipLaunchKernelGGL(k_store_params_tol, dim3(1), dim3(64), 0, s, R, Rg, S);
     }
     if (!(phases & kPhaseEdges)) return hipGetLastError();
-    hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
+    if (!A.edge_list) hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
     if (gw && A.n_int > 0 && !(phases & kPhaseVertices))  // an edge pass on its own: bins built afresh
         hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max, grid);
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
-    if (A.n_int == 0) {
+    if (A.edge_list) {  // lazy round: the listed edges, states side by side
+        const unsigned lb = list_blocks();
+        if (A.n_int > 0) {
+            if (gw == 1) {
+                hipLaunchKernelGGL((k_list_states<ArmGridModel<1>, true, 1>), dim3(lb), dim3(256), 0, s, A, Rg, S);
+                hipLaunchKernelGGL((k_interior<ArmGridModel<1>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A,
+                                   Rg, S);
+            } else if (gw == 2) {
+                hipLaunchKernelGGL((k_list_states<ArmGridModel<2>, true, 1>), dim3(lb), dim3(256), 0, s, A, Rg, S);
+                hipLaunchKernelGGL((k_interior<ArmGridModel<2>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A,
+                                   Rg, S);
+            } else if (R.uniform_r) {
+                hipLaunchKernelGGL((k_list_states<ArmModel<KP>, true, 2>), dim3(lb), dim3(256), 0, s, A, Rg, S);
+                hipLaunchKernelGGL((k_interior<ArmModel<KP>, true, 2, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg,
+                                   S);
+            } else {
+                hipLaunchKernelGGL((k_list_states<ArmModel<KP>, false, 2>), dim3(lb), dim3(256), 0, s, A, Rg, S);
+                hipLaunchKernelGGL((k_interior<ArmModel<KP>, false, 2, true>), dim3(grid_persist), dim3(256), 0, s, A,
+                                   Rg, S);
+            }
+        }
+        hipLaunchKernelGGL(k_list_finish<GTMP_MAX_JOINTS>, dim3(lb), dim3(256), 0, s, A);
+    } else if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
     } else if (gw) {
-        if (A.tile_list && gw == 1)  // lazy round: compacted tiles
-            hipLaunchKernelGGL((k_interior<ArmGridModel<1>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
-        else if (A.tile_list)
-            hipLaunchKernelGGL((k_interior<ArmGridModel<2>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
-        else if (gw == 1)
+        if (gw == 1)
             hipLaunchKernelGGL((k_interior<ArmGridModel<1>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
         else
             hipLaunchKernelGGL((k_interior<ArmGridModel<2>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
-    } else if (A.tile_list) {  // lazy round: two sphere chunks, compacted tiles
-        if (R.uniform_r)
-            hipLaunchKernelGGL((k_interior<ArmModel<KP>, true, 2, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
-        else
-            hipLaunchKernelGGL((k_interior<ArmModel<KP>, false, 2, true>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     } else if (R.uniform_r) {
         hipLaunchKernelGGL((k_interior<ArmModel<KP>, true, NCH>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     } else {
@@ -666,11 +841,17 @@ template <int W, int SPI>
 static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, int grid_persist,
                                  const gtmp_edge_opts &o, hipStream_t s) {
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
-    if (A.n_int == 0)
+    if (A.edge_list) {  // lazy round: the listed edges, states side by side
+        const unsigned lb = list_blocks();
+        if (A.n_int > 0) {
+            hipLaunchKernelGGL((k_list_states<PointModel<W, 1>, true, 1>), dim3(lb), dim3(256), 0, s, A,
+                               (const ArmParams *)nullptr, S);
+            hipLaunchKernelGGL((k_interior<PointModel<W, 8>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A,
+                               (const ArmParams *)nullptr, S);
+        }
+        hipLaunchKernelGGL(k_list_finish<W>, dim3(lb), dim3(256), 0, s, A);
+    } else if (A.n_int == 0)
         hipLaunchKernelGGL(k_finalize_no_interior<W>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
-    else if (A.tile_list)  // lazy round: 8 states per lane, compacted tiles
-        hipLaunchKernelGGL((k_interior<PointModel<W, 8>, true, 1, true>), dim3(grid_persist), dim3(256), 0, s, A,
-                           (const ArmParams *)nullptr, S);
     else
         hipLaunchKernelGGL((k_interior<PointModel<W, SPI>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A,
                            (const ArmParams *)nullptr, S);
@@ -686,7 +867,7 @@ static hipError_t launch_point(const EdgeArgs &A, const ArmParams &R, const Scen
     if (phases & kPhaseVertices)
         hipLaunchKernelGGL(k_vertices_point<W>, dim3(vb), dim3(256), 0, s, A, S, q0, goals, Q, verts, vflag);
     if (!(phases & kPhaseEdges)) return hipGetLastError();
-    hipLaunchKernelGGL(k_prepass<W>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
+    if (!A.edge_list) hipLaunchKernelGGL(k_prepass<W>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
     switch (spi) {
         case 1: return launch_point_s<W, 1>(A, R, S, grid_persist, o, s);
         case 2: return launch_point_s<W, 2>(A, R, S, grid_persist, o, s);
@@ -725,11 +906,13 @@ constexpr int kPointBlocksPerCuAuto = 3;
 
 hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s) {
-    return launch_edge_phases(plan, arm, scene, wdim, b, o, s, nullptr, kPhaseVertices | kPhaseEdges);
+    return launch_edge_phases(plan, arm, scene, wdim, b, o, s, nullptr, nullptr, nullptr,
+                              kPhaseVertices | kPhaseEdges);
 }
 
 hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
-                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s, const uint8_t *select,
+                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s,
+                              const uint32_t *edge_list, const uint32_t *n_list, uint8_t *list_mark,
                               int phases) {
     EdgeArgs A{};
     A.d = plan.d; A.M = plan.M; A.N = plan.N; A.G = plan.G; A.H = plan.H; A.dp = vertex_stride(plan.d);
@@ -739,11 +922,13 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
     float *verts = reinterpret_cast<float *>(ws + plan.off_verts);
     uint8_t *vflag = reinterpret_cast<uint8_t *>(ws + plan.off_vflag);
     A.verts = verts; A.vflag = vflag;
-    A.C_s = b.C_s; A.C_h = b.C_h; A.C_l = b.C_l; A.flags = b.flags; A.prune = b.prune; A.select = select;
+    A.C_s = b.C_s; A.C_h = b.C_h; A.C_l = b.C_l; A.flags = b.flags; A.prune = b.prune;
     A.tile_off = reinterpret_cast<uint8_t *>(ws + plan.off_tile_off);
     A.tile_cnt = reinterpret_cast<uint32_t *>(ws + plan.off_tile_cnt);
     A.counter = reinterpret_cast<uint32_t *>(ws + plan.off_counter);
-    A.tile_list = select ? reinterpret_cast<uint32_t *>(ws + plan.off_tile_list) : nullptr;
+    A.edge_list = edge_list;
+    A.n_list = n_list;
+    A.list_mark = list_mark;
     A.stats = o.stats;
     A.off_params = plan.off_params;
     uint8_t order[GTMP_MAX_H];

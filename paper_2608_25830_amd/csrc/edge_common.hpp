@@ -57,11 +57,12 @@ struct EdgeArgs {
     float *C_s, *C_h, *C_l;
     uint8_t *flags;
     const uint8_t *__restrict__ prune;
-    const uint8_t *__restrict__ select;  // lazy rounds: only edges with select[e] != 0 are touched
     uint8_t *tile_off;
     uint32_t *tile_cnt;
-    uint32_t *counter;  // [0] tile cursor of the interior kernel, [1] length of tile_list
-    uint32_t *tile_list;  // lazy rounds: the tiles holding candidates (NULL: every tile in order)
+    uint32_t *counter;  // [0] tile (or list chunk) cursor of the interior kernel
+    const uint32_t *edge_list;  // lazy rounds: the edges to check (flat ids), *n_list of them
+    const uint32_t *n_list;
+    uint8_t *list_mark;         // lazy rounds: per flat edge id, set to 2 when a listed edge collides
     unsigned long long *stats;
     const ObsGrid *grid;  // arms with the bin filter: the obstacle bins of this scene
     size_t off_params;  // workspace byte offset of the device copy of the robot table
@@ -363,6 +364,25 @@ __device__ __forceinline__ RowInfo decode_row(const EdgeArgs &A, uint32_t row) {
         r.c_base = A.C_l + g; r.c_step = (uint32_t)A.G;
     }
     return r;
+}
+
+// Vertex ids (u, v) of flat edge e (C_s | C_h | C_l order, rows as above);
+// 32-bit arithmetic: every edge id and N^2 are below 2^32.
+__device__ __forceinline__ void edge_vertex_ids(const EdgeArgs &A, uint32_t e, uint32_t &u, uint32_t &v) {
+    const uint32_t N = (uint32_t)A.N, NN = N * N;
+    const uint32_t inner = (uint32_t)(A.M - 1) * NN;
+    if (e < N) {
+        u = 0;
+        v = 1 + e;
+    } else if (e - N < inner) {
+        const uint32_t r = e - N, m = r / NN, uv = r - m * NN, a = uv / N;
+        u = 1 + m * N + a;
+        v = 1 + (m + 1) * N + (uv - a * N);
+    } else {
+        const uint32_t r = e - N - inner, n = r / (uint32_t)A.G, g = r - n * (uint32_t)A.G;
+        u = 1 + (uint32_t)(A.M - 1) * N + n;
+        v = 1 + (uint32_t)A.M * N + g;
+    }
 }
 
 template <int D>

@@ -26,7 +26,7 @@ struct EdgePlan {
     uint32_t tiles_per_row;  // ceil(N / kTile)
     uint32_t n_tiles;
     // workspace carve-up (byte offsets)
-    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_tile_list, off_counter, off_params, off_grid, total;
+    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_counter, off_params, off_grid, total;
 };
 
 EdgePlan make_edge_plan(const gtmp_problem &p);
@@ -45,12 +45,16 @@ hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm /* NULL 
                              hipStream_t s);
 // The fast-mode check in phases: kPhaseVertices packs the vertices and their
 // collision flags into the workspace; kPhaseEdges runs the pre-pass and the
-// interior checks, on the edges with select[e] != 0 only when select is given
-// (the others are left as they are).
+// interior checks.  With edge_list given (device, *n_list flat edge ids of
+// edges with free endpoints within the length limit) kPhaseEdges checks those
+// edges only, without a pre-pass, and writes each one's cost and flag (the
+// others are left as they are); list_mark (device, per flat edge id) holds a
+// value other than 2 for each listed edge and is set to 2 for those that
+// collide.
 constexpr int kPhaseVertices = 1, kPhaseEdges = 2;
 hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
-                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s, const uint8_t *select,
-                              int phases);
+                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s,
+                              const uint32_t *edge_list, const uint32_t *n_list, uint8_t *list_mark, int phases);
 
 hipError_t launch_state_check(const ArmParams *arm, const SceneParams &scene, int wdim, int d, int64_t n,
                               const float *X, float *sd, uint8_t *coll, hipStream_t s);
@@ -147,7 +151,7 @@ hipError_t launch_rrtc_path(const gtmp_problem &p, const ArmParams *arm, const S
 
 // ---- lazy edge realisation (lazy.hip)
 struct LazyPlan {
-    size_t off_edge, off_F, off_select, off_counters, total;
+    size_t off_edge, off_F, off_select, off_list, off_counters, total;
 };
 LazyPlan make_lazy_plan(const gtmp_problem &p);
 hipError_t launch_plan_lazy(const gtmp_problem &p, const ArmParams *arm, const SceneParams &S, int wdim,

@@ -28,6 +28,7 @@ struct LazyArgs {
     const float *V, *F;  // cost-to-go [M][N], cost-from-start [M][N]
     const float *V_s;
     uint8_t *select;
+    uint32_t *list;      // the round's selected edges (flat ids), counters[1] of them
     uint32_t *counters;  // [0] done, [1] edges selected this round, [2] unknown edges on the path
     unsigned long long *stats;  // optional: rounds, edges selected for checking
 };
@@ -117,15 +118,20 @@ __global__ void k_lazy_done(LazyArgs A, const int32_t *idx) {
 }
 
 // Selection of the round: unknown edges whose best path through them (cost
-// from the start + edge + cost to go) is at most thr = (1 + band) V_s.
-// Grid-stride; the count of selected edges is reduced per block first (one
-// atomic per block instead of one per wave).
+// from the start + edge + cost to go) is at most thr = (1 + band) V_s, marked
+// in select and appended to the round's list.  Each block walks its
+// grid-stride range twice: first selecting and counting (one atomic per block
+// reserves its part of the list), then writing its selected edges into that
+// part in order (the list order is immaterial to the check).
 __global__ void __launch_bounds__(256) k_lazy_select(LazyArgs A, uint64_t E, float band) {
     __shared__ uint32_t part[256 / kWave];
+    __shared__ uint32_t base_s;
     const uint64_t N = A.N, inner = (uint64_t)(A.M - 1) * N * N;
     const float thr = (1.0f + band) * *A.V_s;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const int w = threadIdx.x / kWave;
     uint32_t cnt = 0;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += stride) {
         bool sel = false;
         if (A.flags[e] == kUnknown) {
             float t;
@@ -144,12 +150,32 @@ __global__ void __launch_bounds__(256) k_lazy_select(LazyArgs A, uint64_t E, flo
         cnt += sel ? 1u : 0u;
     }
     for (int off = kWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-    if (lane_id() == 0) part[threadIdx.x / kWave] = cnt;
+    if (lane_id() == 0) part[w] = cnt;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int w = 0; w < 256 / kWave; ++w) tot += part[w];
-        if (tot) atomicAdd(&A.counters[1], tot);
+    uint32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < 256 / kWave; ++k) tot += part[k];
+    if (tot == 0) return;  // uniform over the block
+    if (threadIdx.x == 0) base_s = atomicAdd(&A.counters[1], tot);
+    __syncthreads();
+    // second walk: the block's selected edges in grid-stride order, each wave
+    // placing its ballot after the earlier waves' of the same step
+    uint32_t next = base_s;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x; e0 < E && next < base_s + tot; e0 += stride) {
+        const uint64_t e = e0 + threadIdx.x;
+        const bool sel = e < E && A.select[e] != 0;
+        const uint64_t mask = ballot(sel);
+        __syncthreads();  // part[] of the previous step has been read by every wave
+        if (lane_id() == 0) part[w] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        uint32_t before = 0, step = 0;
+#pragma unroll
+        for (int k = 0; k < 256 / kWave; ++k) {
+            if (k < w) before += part[k];
+            step += part[k];
+        }
+        if (sel) A.list[next + before + rank_in(mask)] = (uint32_t)e;
+        next += step;
     }
 }
 
@@ -162,7 +188,7 @@ __global__ void k_lazy_mark_path(LazyArgs A, const int32_t *idx) {
     auto mark = [&](uint64_t e) {
         if (A.flags[e] == kUnknown && A.select[e] == 0) {
             A.select[e] = 1;
-            A.counters[1] += 1;
+            A.list[A.counters[1]++] = (uint32_t)e;
         }
     };
     mark((uint64_t)idx[0]);
@@ -188,6 +214,7 @@ LazyPlan make_lazy_plan(const gtmp_problem &p) {
     L.off_edge = off; off = up256_l(off + ep.total);
     L.off_F = off; off = up256_l(off + sizeof(float) * M * N);
     L.off_select = off; off = up256_l(off + E);
+    L.off_list = off; off = up256_l(off + sizeof(uint32_t) * E);
     L.off_counters = off; off = up256_l(off + 256);
     L.total = off;
     return L;
@@ -215,12 +242,13 @@ hipError_t launch_plan_lazy(const gtmp_problem &p, const ArmParams *arm, const S
     A.F = F;
     A.V_s = V_s;
     A.select = reinterpret_cast<uint8_t *>(ws + plan.off_select);
+    A.list = reinterpret_cast<uint32_t *>(ws + plan.off_list);
     A.counters = reinterpret_cast<uint32_t *>(ws + plan.off_counters);
     A.stats = stats;
     gtmp_edge_opts o = eo;
     o.mode = GTMP_CHECK_FAST;
     o.ev_begin = o.ev_end = nullptr;
-    hipError_t e = launch_edge_phases(ep, arm, S, wdim, b, o, s, nullptr, kPhaseVertices);
+    hipError_t e = launch_edge_phases(ep, arm, S, wdim, b, o, s, nullptr, nullptr, nullptr, kPhaseVertices);
     if (e != hipSuccess) return e;
     const unsigned eb = (unsigned)((E + 255) / 256);
     hipLaunchKernelGGL(k_lazy_init, dim3(eb), dim3(256), 0, s, A, E);
@@ -244,7 +272,7 @@ hipError_t launch_plan_lazy(const gtmp_problem &p, const ArmParams *arm, const S
         const unsigned sb = eb < 8192u ? eb : 8192u;
         hipLaunchKernelGGL(k_lazy_select, dim3(sb), dim3(256), 0, s, A, E, band);
         hipLaunchKernelGGL(k_lazy_mark_path, dim3(1), dim3(64), 0, s, A, idx);
-        e = launch_edge_phases(ep, arm, S, wdim, b, o, s, A.select, kPhaseEdges);
+        e = launch_edge_phases(ep, arm, S, wdim, b, o, s, A.list, A.counters + 1, A.select, kPhaseEdges);
         if (e != hipSuccess) return e;
         if (stats) hipLaunchKernelGGL(k_lazy_count, dim3(1), dim3(64), 0, s, A);
         ++r;
