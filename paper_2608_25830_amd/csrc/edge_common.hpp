@@ -312,15 +312,20 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
             Mask m = G.mask[0][0][bin[0]] & G.mask[0][1][bin[1]] & G.mask[0][2][bin[2]];
             if constexpr (WORDS == 2)
                 m |= (Mask)(G.mask[1][0][bin[0]] & G.mask[1][1][bin[1]] & G.mask[1][2][bin[2]]) << 32;
-            const bool want = m != 0 && !hit;
+            if (hit) m = 0;  // (a select: the ballot below is then one compare)
+            const bool want = m != 0;
             const uint64_t wmask = ballot(want);
-            if (wmask != 0) {
+            // a scalar count, laundered so that the test below stays a scalar
+            // compare (the compiler would otherwise rebuild the lane mask in VGPRs)
+            uint32_t nw = (uint32_t)__popcll(wmask);
+            asm volatile("" : "+s"(nw));
+            if (nw != 0) {
                 if (want) {
                     const uint32_t slot = (tail + (uint32_t)rank_in(wmask)) & (kQueue - 1);
                     Qw.e[slot].c = make_float4(c[0], c[1], c[2], rk);
                     Qw.e[slot].m = make_uint4((uint32_t)m, (uint32_t)((uint64_t)m >> 32), (uint32_t)lane, 0u);
                 }
-                tail += (uint32_t)__popcll(wmask);
+                tail += nw;
                 if (tail - head >= (uint32_t)kWave) drain(kWave);
             }
         }
