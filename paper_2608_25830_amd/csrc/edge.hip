@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256) k_vertices_arm(EdgeArgs A, ArmParams R, S
 }
 
 // Vertex flags of an arm through the obstacle bins (the same decisions as
-// k_vertices_arm).
+// k_vertices_arm); blocks of up to 256 threads.
 template <int WG>
 __global__ void __launch_bounds__(256) k_vertices_arm_grid(EdgeArgs A, ArmParams R, const float *q0,
                                                            const float *goals, const float *Q, float *verts,
@@ -784,10 +784,14 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
         if (gw) {
             // the bins serve the vertex flags and, later, the interior kernel
             hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max, grid);
+            // one wave per block: a plan has few vertices, so small blocks spread them over more CUs
+            const unsigned vb64 = (A.n_vertices + kWave - 1) / kWave;
             if (gw == 1)
-                hipLaunchKernelGGL(k_vertices_arm_grid<1>, dim3(vb), dim3(256), 0, s, A, R, q0, goals, Q, verts, vflag);
+                hipLaunchKernelGGL(k_vertices_arm_grid<1>, dim3(vb64), dim3(kWave), 0, s, A, R, q0, goals, Q, verts,
+                                   vflag);
             else
-                hipLaunchKernelGGL(k_vertices_arm_grid<2>, dim3(vb), dim3(256), 0, s, A, R, q0, goals, Q, verts, vflag);
+                hipLaunchKernelGGL(k_vertices_arm_grid<2>, dim3(vb64), dim3(kWave), 0, s, A, R, q0, goals, Q, verts,
+                                   vflag);
         } else {
             hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
         }
