@@ -138,3 +138,31 @@ def test_grid_lazy_rounds(gt, band):
     assert np.array_equal(res[0][3], res[1][3])
     assert np.array_equal(res[0][4].view(np.uint32), res[1][4].view(np.uint32))
     assert res[0][5] == res[1][5]
+
+
+# ---------------------------------------------------------------- against the oracle
+@pytest.mark.parametrize("variant", ["radii", "two_words", "radii_two_words"])
+@pytest.mark.parametrize("chunks", [0, 2])
+def test_arm_variants_match_oracle(gt, orc, variant, chunks):
+    """Per-sphere radii and scenes needing two mask words, through the bins
+    and through the chunked test, against the FP64 oracle (flags exact
+    outside the 1e-5 signed-distance band, costs within 1e-5 relative)."""
+    from tests import parity as P
+    w = wl.make_workload("arm7", 3, M=3, N=96)
+    g = np.random.default_rng(11)
+    if "radii" in variant:
+        w["sph_r"] = g.uniform(0.02, 0.09, w["sph_r"].shape).astype(np.float32)
+    if "two_words" in variant:
+        w["obs_spheres"], w["obs_boxes"] = _obstacles(23, 26, 22)
+    pl = gt.Planner(w, flags=True)
+    pl.opts.sphere_chunks = chunks
+    pl.plan(w["seed"], 0)
+    torch.cuda.synchronize()
+    Q = orc.sample_layers(w["M"], w["N"], w["d"], w["lo"], w["hi"], w["seed"], 0)
+    assert np.array_equal(pl.Q.cpu().numpy(), Q)
+    cost, minsd, flag = orc.edge_costs(orc.Model(w), w["M"], w["N"], w["G"], w["H"], w["q0"], w["goals"], Q,
+                                       w["penalty"])
+    got = P.flat(pl.C_s.cpu().numpy(), pl.C_h.cpu().numpy()[: w["M"] - 1], pl.C_l.cpu().numpy())
+    rep = P.compare_edges(got, pl.flags.cpu().numpy(), P.flat(*cost), P.flat(*minsd), P.flat(*flag))
+    _say("arm variant", variant, "chunks", chunks, rep)
+    assert 0 < rep["failed"] < rep["edges"]
