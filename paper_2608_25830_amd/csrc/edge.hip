@@ -195,19 +195,21 @@ __global__ void __launch_bounds__(256) k_vertices_point(EdgeArgs A, SceneParams 
 }
 
 // ------------------------------------------------------------------ 2. pre-pass
-// One block per (kPrepassRows consecutive rows, row segment): thread i takes
-// column seg * kTile + i of every row.  Consecutive rows of a layer share
-// their target vertices, so a thread loads its target once and reuses it
-// while the rows' targets stay the same; the per-tile compaction of all the
-// rows shares one barrier.
+// One block per (A.prepass_rows <= kPrepassRows consecutive rows, row
+// segment): thread i takes column seg * kTile + i of every row.  Consecutive
+// rows of a layer share their target vertices, so a thread loads its target
+// once and reuses it while the rows' targets stay the same; the per-tile
+// compaction of all the rows shares one barrier.  Small graphs take one row
+// per block (more blocks in flight).
 constexpr int kPrepassRows = 8;
+constexpr uint32_t kPrepassRowsMinTiles = 4096;  // graphs from this size take kPrepassRows rows per block
 
 template <int D>
 __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
     __shared__ uint32_t wave_cnt[kPrepassRows][kTile / kWave];
     const int w = threadIdx.x / kWave;
     const uint32_t seg = blockIdx.x % A.tiles_per_row;
-    const uint32_t row0 = (blockIdx.x / A.tiles_per_row) * kPrepassRows;
+    const uint32_t row0 = (blockIdx.x / A.tiles_per_row) * A.prepass_rows;
     const uint32_t rows = A.n_tiles / A.tiles_per_row;
     const uint32_t n = seg * kTile + threadIdx.x;
     const bool col = n < (uint32_t)A.N;
@@ -220,7 +222,7 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
 #pragma unroll
     for (int r = 0; r < kPrepassRows; ++r) {
         const uint32_t row = row0 + r;
-        if (row >= rows) break;
+        if (r >= A.prepass_rows || row >= rows) break;
         const RowInfo ri = decode_row(A, row);
         bool cand = false;
         if (ri.v_base != vb || ri.v_step != vs) {
@@ -252,7 +254,7 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
 #pragma unroll
     for (int r = 0; r < kPrepassRows; ++r) {
         const uint32_t row = row0 + r;
-        if (row >= rows) break;
+        if (r >= A.prepass_rows || row >= rows) break;
         const uint32_t tile = row * A.tiles_per_row + seg;
         uint32_t base = 0, total = 0;
 #pragma unroll
@@ -270,7 +272,7 @@ __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
 // Blocks of the pre-pass for a plan's tiles.
 static inline unsigned prepass_blocks(const EdgeArgs &A) {
     const uint32_t rows = A.n_tiles / A.tiles_per_row;
-    return (unsigned)(((rows + kPrepassRows - 1) / kPrepassRows) * A.tiles_per_row);
+    return (unsigned)(((rows + A.prepass_rows - 1) / A.prepass_rows) * A.tiles_per_row);
 }
 
 // ------------------------------------------------------------------ 3. interior
@@ -922,6 +924,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
     A.d = plan.d; A.M = plan.M; A.N = plan.N; A.G = plan.G; A.H = plan.H; A.dp = vertex_stride(plan.d);
     A.penalty = plan.penalty; A.max_len = plan.max_len;
     A.tiles_per_row = plan.tiles_per_row; A.n_tiles = plan.n_tiles; A.n_vertices = plan.n_vertices;
+    A.prepass_rows = plan.n_tiles >= kPrepassRowsMinTiles ? (uint32_t)kPrepassRows : 1u;
     char *ws = static_cast<char *>(b.workspace);
     float *verts = reinterpret_cast<float *>(ws + plan.off_verts);
     uint8_t *vflag = reinterpret_cast<uint8_t *>(ws + plan.off_vflag);

@@ -52,6 +52,7 @@ struct EdgeArgs {
     int d, M, N, G, H, dp;
     float penalty, max_len;
     uint32_t tiles_per_row, n_tiles, n_vertices;
+    uint32_t prepass_rows;  // rows per pre-pass block (1..8)
     const float *__restrict__ verts;
     const uint8_t *__restrict__ vflag;
     float *C_s, *C_h, *C_l;
