@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(kTile) k_batch_prepass(const BPlan *plans, int
 // table are read with wave-uniform addresses.  A wave that draws a tile of
 // another plan finishes its edges before it switches.
 template <class Model, bool UNIFORM_R, int NCH>
-__global__ void __launch_bounds__(256, Model::kGrid ? 3 : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
+__global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4) : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
     k_batch_interior(const BPlan *plans, int p0, int p1, uint32_t n_gtiles, uint32_t *gcounter,
                      unsigned long long *stats) {
     constexpr int D = Model::D;
@@ -227,10 +227,13 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 3 : NCH == 1 ? 3 : NCH == 
     constexpr int W = ARM ? 3 : D;
     constexpr int SP = ARM ? 1 : KP;
     __shared__ float tord[4][GTMP_MAX_H];
-    // obstacle bins (arms): each wave holds the bins of its current plan
+    // obstacle bins (arms): each wave holds the mask words of its current
+    // plan in LDS; the obstacle records (read by the exact tests only) stay in
+    // device memory
     constexpr int WG = Model::kWords > 1 ? 2 : 1;
-    __shared__ typename std::conditional<GRID, GridLds<WG>[4], char>::type glds_raw;
+    __shared__ typename std::conditional<GRID, GridMaskTable[4][WG], char>::type gmask;
     __shared__ typename std::conditional<GRID, GridQueue<WG>[4], char>::type gque;
+    const float4(*grec)[2] = nullptr;
     float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
     uint32_t n_tests = 0;
     const int lane = lane_id();
@@ -274,20 +277,21 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 3 : NCH == 1 ? 3 : NCH == 
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     for (int i = lane; i < n_int; i += kWave) tord[wv][i] = plans[cur].A.tord[i];
                     if constexpr (GRID) {
-                        const uint4 *src = reinterpret_cast<const uint4 *>(plans[cur].A.grid);
-                        uint4 *dst = reinterpret_cast<uint4 *>(&glds_raw[wv]);
-                        constexpr int n16 = (int)(grid_lds_bytes<WG>() / 16);
+                        const uint4 *src = reinterpret_cast<const uint4 *>(plans[cur].A.grid->mask);
+                        uint4 *dst = reinterpret_cast<uint4 *>(&gmask[wv][0]);
+                        constexpr int n16 = (int)(sizeof(GridMaskTable) * WG / 16);
                         for (int i = lane; i < n16; i += kWave) dst[i] = src[i];
                     }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     if constexpr (GRID) {
-                        const ObsGrid &G = *reinterpret_cast<const ObsGrid *>(&glds_raw[wv]);
+                        const ObsGrid *G = plans[cur].A.grid;
+                        grec = G->rec;
 #pragma unroll
                         for (int i = 0; i < 3; ++i) {
-                            ginv[i] = G.inv[i];
-                            goff[i] = G.off[i];
+                            ginv[i] = G->inv[i];
+                            goff[i] = G->off[i];
                         }
                     }
                 }
@@ -339,9 +343,8 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 3 : NCH == 1 ? 3 : NCH == 
             asm volatile("" : "+s"(Rp));
             const auto &R = *Rp;
             if constexpr (GRID) {
-                const ObsGrid &G = *reinterpret_cast<const ObsGrid *>(&glds_raw[wv]);
                 uint32_t tests = 0;
-                gap = arm_hit_grid<Model::kWords>(R, q, G, ginv, goff, gque[wv], tests, has) ? -1.f : 1.f;
+                gap = arm_hit_grid<Model::kWords>(R, q, gmask[wv], grec, ginv, goff, gque[wv], tests, has) ? -1.f : 1.f;
                 n_tests += tests;
             } else {
                 const float r0 = R.r0;

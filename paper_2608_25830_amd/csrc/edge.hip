@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256) k_vertices_arm_grid(EdgeArgs A, ArmParams
         for (int j = 0; j < GTMP_MAX_JOINTS; ++j) verts[(size_t)i * A.dp + j] = q[j];
     }
     uint32_t tests = 0;
-    const bool hit = arm_hit_grid<WG>(R, q, G, inv, off, gque[threadIdx.x / kWave], tests, valid);
+    const bool hit = arm_hit_grid<WG>(R, q, G.mask, G.rec, inv, off, gque[threadIdx.x / kWave], tests, valid);
     if (valid) vflag[i] = hit ? 1 : 0;
 }
 
@@ -431,7 +431,8 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 
             const auto &R = *Rp;
             if constexpr (GRID) {
                 uint32_t tests = 0;
-                gap = arm_hit_grid<Model::kWords>(R, q, glds, ginv, goff, gque[threadIdx.x / kWave], tests, has)
+                gap = arm_hit_grid<Model::kWords>(R, q, glds.mask, glds.rec, ginv, goff, gque[threadIdx.x / kWave], tests,
+                                                  has)
                           ? -1.f : 1.f;
                 n_tests += tests;
             } else {
@@ -571,7 +572,8 @@ __global__ void __launch_bounds__(256, 3) k_list_states(EdgeArgs A, const ArmPar
             asm volatile("" : "+s"(Rp));
             const auto &R = *Rp;
             if constexpr (GRID) {
-                hit = arm_hit_grid<Model::kWords>(R, q, G, ginv, goff, gque[threadIdx.x / kWave], n_tests, live);
+                hit = arm_hit_grid<Model::kWords>(R, q, G.mask, G.rec, ginv, goff, gque[threadIdx.x / kWave], n_tests,
+                                                   live);
             } else {
                 const v32f o = arm_fk<D>(R, q);
                 hit = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, R.r0, S) <= 0.f;

@@ -250,8 +250,13 @@ struct GridQueue {
     uint8_t hit[kWave];
 };
 
+typedef uint32_t GridMaskTable[3][kGridCells];  // one mask word: axis, bin
+
+// mk: the mask tables (mk[w] = word w), rec: the obstacle records; both may
+// live in LDS or in device memory.
 template <int WORDS, class AP>
-__device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_MAX_JOINTS], const ObsGrid &G,
+__device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_MAX_JOINTS],
+                                             const GridMaskTable *mk, const float4 (*rec)[2],
                                              const float (&inv)[3], const float (&off)[3],
                                              GridQueue<WORDS> &Qw, uint32_t &tests, bool live) {
     typedef typename GridQueue<WORDS>::Mask Mask;
@@ -276,7 +281,7 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
                 const int o = WORDS == 1 ? __builtin_ctz((uint32_t)m) : __builtin_ctzll((uint64_t)m);
                 m &= m - 1;
                 ++tests;
-                const float4 a = G.rec[o][0], h = G.rec[o][1];
+                const float4 a = rec[o][0], h = rec[o][1];
                 const float Rr = a.w + e.w;
                 float g = -Rr * Rr;
                 const float c[3] = {e.x, e.y, e.z}, lo[3] = {a.x, a.y, a.z}, hi[3] = {h.x, h.y, h.z};
@@ -310,9 +315,8 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
                 c[i] = __builtin_fmaf(t, dd[i], b[i]);
                 bin[i] = grid_bin(__builtin_fmaf(c[i], inv[i], off[i]));
             }
-            Mask m = G.mask[0][0][bin[0]] & G.mask[0][1][bin[1]] & G.mask[0][2][bin[2]];
-            if constexpr (WORDS == 2)
-                m |= (Mask)(G.mask[1][0][bin[0]] & G.mask[1][1][bin[1]] & G.mask[1][2][bin[2]]) << 32;
+            Mask m = mk[0][0][bin[0]] & mk[0][1][bin[1]] & mk[0][2][bin[2]];
+            if constexpr (WORDS == 2) m |= (Mask)(mk[1][0][bin[0]] & mk[1][1][bin[1]] & mk[1][2][bin[2]]) << 32;
             if (hit) m = 0;  // (a select: the ballot below is then one compare)
             const bool want = m != 0;
             const uint64_t wmask = ballot(want);
