@@ -196,26 +196,33 @@ __global__ void k_pair_keys(int d, int nu, const float *U, int nv, const float *
     vals[t] = (uint32_t)t;
 }
 
-// Fill the new slots of layer m, one wave per slot: a heuristic slot of
-// rank h takes the midpoint of the h-th closest pair (a uniform draw when
-// fewer pairs exist), every other slot a draw of the uniform half.  The
-// draw's attempts are tested 64 at a time, one per lane, and the lowest
-// accepted attempt index wins, so the result is the sequential first accepted
-// attempt.  With the surrogate bias the pair list is the compacted list of
-// candidates predicted free and its length is read from n_avail.
-__global__ void __launch_bounds__(256) k_expand_layer(int m, int n_old, int N, int d, BoxArgs B, uint32_t k0,
-                                                      uint32_t k1, uint32_t stage, const Informed *Ip,
-                                                      const int32_t *rank, const uint32_t *sorted_pairs,
-                                                      uint64_t n_pairs, const uint32_t *n_avail, int nv,
-                                                      const float *U, const float *Vv, float *Qm) {
-    const int n = n_old + (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-    if (n >= N) return;  // whole wave
-    const int lane = lane_id();
+// Fill the new slots of layer m, one block of kExpandThreads per slot: a
+// heuristic slot of rank h takes the midpoint of the h-th closest pair (a
+// uniform draw when fewer pairs exist), every other slot a draw of the
+// uniform half.  The draw's attempts are tested kExpandThreads at a time, one
+// per thread, and the lowest accepted attempt index wins (a minimum over the
+// block's waves), so the result is the sequential first accepted attempt.
+// A draw from a large informed set accepts rarely and can take many rounds:
+// several waves per slot shorten that chain of rounds.  With the surrogate
+// bias the pair list is the compacted list of candidates predicted free and
+// its length is read from n_avail.
+constexpr int kExpandThreads = 256;
+static_assert(kMaxAttempts % kExpandThreads == 0, "whole rounds of attempts");
+
+__global__ void __launch_bounds__(kExpandThreads) k_expand_layer(int m, int n_old, int N, int d, BoxArgs B, uint32_t k0,
+                                                                 uint32_t k1, uint32_t stage, const Informed *Ip,
+                                                                 const int32_t *rank, const uint32_t *sorted_pairs,
+                                                                 uint64_t n_pairs, const uint32_t *n_avail, int nv,
+                                                                 const float *U, const float *Vv, float *Qm) {
+    __shared__ uint32_t first[kExpandThreads / kWave];
+    const int n = n_old + (int)blockIdx.x;  // block-uniform
+    if (n >= N) return;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
     const Informed I = *Ip;
     const int h = rank[n];
     const uint64_t avail = n_avail ? (uint64_t)*n_avail : n_pairs;
     if (h >= 0 && (uint64_t)h < avail) {
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             const uint32_t p = sorted_pairs[h];
             const uint32_t a = p / (uint32_t)nv, b = p % (uint32_t)nv;
             for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = (U[(size_t)a * d + i] + Vv[(size_t)b * d + i]) * 0.5f;
@@ -223,18 +230,25 @@ __global__ void __launch_bounds__(256) k_expand_layer(int m, int n_old, int N, i
         return;
     }
     if (I.bounded) {
-        for (int base = 0; base < kMaxAttempts; base += kWave) {
+        for (int base = 0; base < kMaxAttempts; base += kExpandThreads) {
+            const int att = base + (int)threadIdx.x;
             float x[GTMP_MAX_DOF];
-            const bool ok = informed_attempt(d, B.lo, B.hi, I, k0, k1, stage, (uint32_t)m, (uint32_t)n, base + lane, x);
+            const bool ok = informed_attempt(d, B.lo, B.hi, I, k0, k1, stage, (uint32_t)m, (uint32_t)n, att, x);
             const uint64_t acc = ballot(ok);
-            if (acc != 0) {
-                if (lane == __builtin_ctzll(acc))
+            if (lane == 0) first[w] = acc != 0 ? (uint32_t)(base + kWave * w + __builtin_ctzll(acc)) : 0xffffffffu;
+            __syncthreads();
+            uint32_t best = 0xffffffffu;
+#pragma unroll
+            for (int k = 0; k < kExpandThreads / kWave; ++k) best = first[k] < best ? first[k] : best;
+            __syncthreads();  // first[] is read by every wave before the next round writes it
+            if (best != 0xffffffffu) {  // block-uniform
+                if ((uint32_t)att == best)
                     for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
                 return;
             }
         }
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         float x[GTMP_MAX_DOF];
         box_draw(d, B.lo, B.wd, k0, k1, stage, (uint32_t)m, (uint32_t)n, x);
         for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
@@ -403,8 +417,8 @@ hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *go
             sorted = bfree;
             n_avail = bcount;
         }
-        const unsigned slots = (unsigned)(N - n_old);  // one wave per new slot, four per block
-        hipLaunchKernelGGL(k_expand_layer, dim3((slots + 3) / 4), dim3(256), 0, s, m, n_old, N, d, B, k0, k1, st, I,
+        const unsigned slots = (unsigned)(N - n_old);  // one block per new slot
+        hipLaunchKernelGGL(k_expand_layer, dim3(slots), dim3(kExpandThreads), 0, s, m, n_old, N, d, B, k0, k1, st, I,
                            rank, sorted, heuristic_ok ? npairs : 0, n_avail, nv, U, Vv, Q_new + (size_t)m * N * d);
     }
     return hipGetLastError();
