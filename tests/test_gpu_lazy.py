@@ -62,6 +62,33 @@ def test_lazy_equals_full_plan(gt, name, scene, N, M, band):
     assert all(lf[i] != 0xFF for i in ids)
 
 
+@pytest.mark.parametrize("name,scene,N,M,band", [("arm7", 1, 512, 4, 5.0), ("arm7", 2, 64, 3, 0.0),
+                                                 ("2d-large", 0, 512, 5, 3.0), ("2d-large", 2, 32, 3, 0.0)])
+def test_lazy_long_and_short_lists(gt, name, scene, N, M, band):
+    """Lists too long to check all their states at once (the early-exit list
+    kernel: large bands on large graphs) and short ones (all states side by
+    side): the same costs and flags as the full check."""
+    w = wl.make_workload(name, scene, N=N, M=M)
+    full = gt.Planner(w, flags=True)
+    full.plan(w["seed"], 0)
+    lazy = gt.Planner(w, flags=True)
+    stats = torch.zeros(2, device="cuda", dtype=torch.int64)
+    st, rounds = lazy.plan_lazy(w["seed"], 0, band=band, max_rounds=20000, stats=stats)
+    torch.cuda.synchronize()
+    n_int = int(w["H"]) - 2
+    _say(name, "band", band, "rounds", rounds, "checked", int(stats[1].item()), "pairs/round",
+         int(stats[1].item()) * n_int / max(rounds, 1))
+    assert st == gt.GTMP_OK
+    assert float(lazy.V_s.item()) == float(full.V_s.item())
+    fc, lc = _flat(full, int(w["M"])), _flat(lazy, int(w["M"]))
+    ff, lf = full.flags.cpu().numpy(), lazy.flags.cpu().numpy()
+    known = lf != 0xFF
+    assert np.array_equal(lf[known], ff[known])
+    assert np.array_equal(lc[known].view(np.uint32), fc[known].view(np.uint32))
+    if band >= 3.0:
+        assert int(stats[1].item()) * n_int > (1 << 19)  # the early-exit list kernel ran
+
+
 @pytest.mark.parametrize("name,scene,N", [("2d-small", 2, None), ("arm7", 3, 96)])
 def test_lazy_matches_oracle(gt, orc, name, scene, N):
     w = wl.make_workload(name, scene, N=N)
