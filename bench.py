@@ -41,7 +41,7 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
 # FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/ (scaled by the
 # plain-copy calibration).  A value is only reported while the kernel sources
 # still hash to the fingerprint it was measured on.
-MEASURED_TRAFFIC = {"arm7": (5.247e+07, "24eda5eabf1e4697", "profiles/k_interior_arm7.md")}
+MEASURED_TRAFFIC = {"arm7": (5.254e+07, "fff4edd9da1e086f", "profiles/k_interior_arm7.md")}
 KERNEL_SOURCES = ["paper_2608_25830_amd/csrc/edge.hip", "paper_2608_25830_amd/csrc/edge_common.hpp",
                   "paper_2608_25830_amd/csrc/gtmp_device.hpp"]
 
@@ -80,6 +80,24 @@ def arm_grid_state_flops(n_joints, n_spheres, d):
 
 GRID_TEST_FLOPS = 15
 GRID_MAX_OBS = 64  # obstacles the bin masks hold (the filter's automatic range)
+
+
+POINT_GRID_MAX_OBS = 96     # obstacles the point kernels' bin masks hold
+POINT_GRID_MIN_TILES = 1024  # 256-edge tiles from which the point kernels take the bins
+
+
+def point_grid_state_flops(d):
+    """Point state in R^d behind the obstacle bins, apart from the exact tests
+    (GRID_TEST_FLOPS each): lerp 2d, bin coordinates d fma, d saturating
+    conversions = 5d."""
+    return 5 * d
+
+
+def point_uses_bins(w, opts):
+    n_obs = sum(len(w[k]) for k in (("circles", "boxes") if w["kind"] == "point2d" else ("obs_spheres", "obs_boxes")))
+    rows = 1 + (w["M"] - 1) * w["N"] + w["G"]
+    tiles = rows * ((w["N"] + 255) // 256)
+    return int(opts.sphere_chunks) == 0 and 0 < n_obs <= POINT_GRID_MAX_OBS and tiles >= POINT_GRID_MIN_TILES
 
 
 def point_state_flops(n_circ, n_box, d):
@@ -710,8 +728,18 @@ def main():
             flop = st * f_state
     else:
         sph, box = (w["circles"], w["boxes"]) if w["kind"] == "point2d" else (w["obs_spheres"], w["obs_boxes"])
-        f_state = point_state_flops(sph.shape[0], box.shape[0], d)
-        flop = st * f_state
+        f_dense = point_state_flops(sph.shape[0], box.shape[0], d)
+        if point_uses_bins(w, pl.opts):
+            f_state = point_grid_state_flops(d)
+            t_mean = float(np.mean(tests))
+            flop = st * f_state + t_mean * GRID_TEST_FLOPS
+            grid = {"exact_tests_per_launch": t_mean, "exact_tests_per_state": t_mean / st,
+                    "test_flops": GRID_TEST_FLOPS,
+                    "full_test_flop_per_state": f_dense,
+                    "full_test_equivalent_tflops": st * f_dense / (k_ms / 1e3) / 1e12}
+        else:
+            f_state = f_dense
+            flop = st * f_state
     achieved = flop / (k_ms / 1e3) / 1e12
     traffic, traffic_src = None, None
     if args.workload in MEASURED_TRAFFIC and not args.opt:

@@ -142,11 +142,15 @@ typedef struct gtmp_edge_opts {
                                  obstacles that its per-axis obstacle bins list (a conservative
                                  filter: the same decisions as testing every obstacle) when the
                                  scene has at most 64 obstacles, else as for 2; 1, 2 or 4 = every
-                                 sphere against every obstacle, the spheres in this many chunks */
+                                 sphere against every obstacle, the spheres in this many chunks.
+                                 Point robots, full check: 0 (auto) = the same bins, four states
+                                 per lane (states_per_iter ignored), when the graph has at least
+                                 1024 tiles of 256 edges and the scene 1 to 96 obstacles; other
+                                 values (and lazy rounds) = every state against every obstacle */
     int32_t reserved[3];
     unsigned long long *stats; /* optional device [4]: states evaluated, edges checked in the
                                   interior pass, exact sphere-obstacle tests made behind the
-                                  obstacle bins (arms, sphere_chunks 0), reserved.  Added to. */
+                                  obstacle bins (sphere_chunks 0), reserved.  Added to. */
     void *ev_begin;            /* optional hipEvent_t recorded on `stream` just before the
                                   interior (fast mode) or every-state (full mode) kernel */
     void *ev_end;              /* optional hipEvent_t recorded just after it */

@@ -9,8 +9,11 @@ fastest; results are cached in memory and, when a path is given, in a JSON
 file keyed by robot group and problem-size bucket.
 
 Knobs:
-  point robots: states_per_iter in {1, 2, 4, 8}  (interior states per lane
-                and iteration), blocks_per_cu in {0 (occupancy), 1, 2, 4, 8}
+  point robots: sphere_chunks 0 (the obstacle bins, on graphs of at least
+                1024 tiles whose scene has at most 96 obstacles) with
+                blocks_per_cu in {0, 1, 2, 4}, or 2 (every state against every
+                obstacle) with states_per_iter in {1, 2, 4, 8} (interior states
+                per lane and iteration) and blocks_per_cu in {0 (auto), 1, 2, 4, 8}
   arms:         sphere_chunks 0 (the obstacle-bin filter, when the scene has
                 at most 64 obstacles) with blocks_per_cu in {0, 2, 4, 6}, or
                 {1, 2, 4} (every robot sphere against every obstacle in one
@@ -56,8 +59,9 @@ def problem_key(w) -> str:
 
 def candidates(w) -> list[dict]:
     if w["kind"] in ("point2d", "point"):
-        return [dict(states_per_iter=s, sphere_chunks=0, blocks_per_cu=b) for s in (1, 2, 4, 8)
-                for b in (0, 1, 2, 4, 8)]
+        bins = [dict(states_per_iter=0, sphere_chunks=0, blocks_per_cu=b) for b in (0, 1, 2, 4)]
+        return bins + [dict(states_per_iter=s, sphere_chunks=2, blocks_per_cu=b) for s in (1, 2, 4, 8)
+                       for b in (0, 1, 2, 4, 8)]
     bins = [dict(states_per_iter=0, sphere_chunks=0, blocks_per_cu=b) for b in (0, 2, 4, 6)]
     return bins + [dict(states_per_iter=0, sphere_chunks=c, blocks_per_cu=b) for c in (1, 2, 4)
                    for b in (0, 1, 2, 3, 4)]

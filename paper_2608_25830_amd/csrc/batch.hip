@@ -569,7 +569,7 @@ __global__ void __launch_bounds__(64) k_batch_arm_tol(const BPlan *plans, int p0
 // (one block per plan; the bins depend on the scene and the robot radii only).
 __global__ void __launch_bounds__(kGridBuildThreads) k_batch_build_grid(const BPlan *plans, int p0) {
     const BPlan &P = plans[p0 + blockIdx.x];
-    build_grid_block(P.S, P.grid_r_max, const_cast<ObsGrid *>(P.A.grid));
+    build_grid_block(P.S, 3, P.grid_r_max, const_cast<ObsGrid *>(P.A.grid));
 }
 
 __global__ void k_batch_zero(uint32_t *p, int n) {
@@ -692,7 +692,7 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
     for (int p = 0; p < n && grid_words; ++p) {
         if (group[p] != 2) continue;
         const int n_obs = plans[p].scene.n_spheres + plans[p].scene.n_boxes;
-        if (n_obs > kGridMaxObs) grid_words = 0;
+        if (n_obs > 64) grid_words = 0;  // the arm kernels take at most two mask words
         else if (n_obs > 32) grid_words = 2;
     }
     ObsGrid *grids = reinterpret_cast<ObsGrid *>(ws + L.off_grids);

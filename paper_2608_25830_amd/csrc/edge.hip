@@ -102,8 +102,9 @@ __global__ void k_zero_u32(uint32_t *p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-__global__ void __launch_bounds__(kGridBuildThreads) k_build_grid(SceneParams S, float r_max, ObsGrid *G) {
-    build_grid_block(S, r_max, G);
+__global__ void __launch_bounds__(kGridBuildThreads) k_build_grid(SceneParams S, int wdim, float r_max,
+                                                                        ObsGrid *G) {
+    build_grid_block(S, wdim, r_max, G);
 }
 
 // ------------------------------------------------------------------ 1. vertices
@@ -298,7 +299,7 @@ __device__ __forceinline__ uint64_t list_states_limit() { return 1ull << 19; }
 constexpr int kListChunk = 4;
 
 template <class Model, bool UNIFORM_R, int NCH, bool LIST = false>
-__global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
+__global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
     k_interior(EdgeArgs A, const ArmParams *Rg, SceneParams S) {
     constexpr int D = Model::D;
     constexpr int KP = Model::KP;
@@ -306,10 +307,9 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 
     constexpr bool GRID = Model::kGrid;
     constexpr int W = ARM ? 3 : D;
     constexpr int SP = ARM ? 1 : KP;  // interior states per evaluation
-    constexpr int KC = ARM ? KP / NCH : KP;
     static_assert(!ARM || KP % NCH == 0, "chunking must divide the sphere slots");
     __shared__ float tord[GTMP_MAX_H];
-    constexpr int WG = Model::kWords > 1 ? 2 : 1;
+    constexpr int WG = Model::kWords > 0 ? Model::kWords : 1;
     __shared__ typename std::conditional<GRID, GridLds<WG>, char>::type glds_raw;
     __shared__ typename std::conditional<GRID, GridQueue<WG>[256 / kWave], char>::type gque;
     const ObsGrid &glds = *reinterpret_cast<const ObsGrid *>(&glds_raw);  // the first grid_lds_bytes<WG>()
@@ -439,6 +439,21 @@ __global__ void __launch_bounds__(256, Model::kGrid ? 6 : NCH == 1 ? 3 : NCH == 
                 const v32f o = arm_fk<D>(R, q);
                 gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
             }
+        } else if constexpr (GRID) {
+            float p[W][SP];
+#pragma unroll
+            for (int s = 0; s < SP; ++s) {
+                int jj = j + s;
+                jj = jj < A.n_int ? jj : A.n_int - 1;
+                const float t = tord[has ? jj : 0];
+#pragma unroll
+                for (int i = 0; i < W; ++i) p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
+            }
+            uint32_t tests = 0;
+            gap = point_hit_grid<W, SP, Model::kWords>(p, glds.mask, glds.rec, ginv, goff, gque[threadIdx.x / kWave],
+                                                       tests, has)
+                      ? -1.f : 1.f;
+            n_tests += tests;
         } else {
             Probes<W, KP> P;
 #pragma unroll
@@ -525,7 +540,7 @@ __global__ void __launch_bounds__(256, 3) k_list_states(EdgeArgs A, const ArmPar
     constexpr bool ARM = Model::kArm;
     constexpr bool GRID = Model::kGrid;
     constexpr int W = ARM ? 3 : D;
-    constexpr int WG = Model::kWords > 1 ? 2 : 1;
+    constexpr int WG = Model::kWords > 0 ? Model::kWords : 1;
     __shared__ float tord[GTMP_MAX_H];
     __shared__ typename std::conditional<GRID, GridLds<WG>, char>::type glds_raw;
     __shared__ typename std::conditional<GRID, GridQueue<WG>[256 / kWave], char>::type gque;
@@ -787,7 +802,7 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
     if (phases & kPhaseVertices) {
         if (gw) {
             // the bins serve the vertex flags and, later, the interior kernel
-            hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max, grid);
+            hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, 3, r_max, grid);
             // one wave per block: a plan has few vertices, so small blocks spread them over more CUs
             const unsigned vb64 = (A.n_vertices + kWave - 1) / kWave;
             if (gw == 1)
@@ -804,7 +819,7 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
     if (!(phases & kPhaseEdges)) return hipGetLastError();
     if (!A.edge_list) hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
     if (gw && A.n_int > 0 && !(phases & kPhaseVertices))  // an edge pass on its own: bins built afresh
-        hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, r_max, grid);
+        hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, 3, r_max, grid);
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.edge_list) {  // lazy round: the listed edges, states side by side
         const unsigned lb = list_blocks();
@@ -845,9 +860,22 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
     return hipGetLastError();
 }
 
+// States per lane and evaluation of the point kernels behind the obstacle bins.
+constexpr int kPointGridSp = 4;
+// Fewest tiles for which the point kernels take the bins (a small graph does
+// not repay building them).
+constexpr int kPointGridMinTiles = 1024;
+// Resident blocks per CU of the point kernels behind the bins (automatic),
+// 2D and 3D: their states are cheap, and fewer waves contend for the tile
+// cursor (measured best on 2d-large, M 16, N 1024: 0.76 ms at one block
+// against 0.79 at two and 0.92 at the occupancy limit).
+constexpr int kPointGridBlocksPerCuAuto[2] = {1, 2};
+// The arm kernels take at most two mask words.
+constexpr int kGridArmMaxObs = 64;
+
 template <int W, int SPI>
 static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, int grid_persist,
-                                 const gtmp_edge_opts &o, hipStream_t s) {
+                                 const gtmp_edge_opts &o, hipStream_t s, int gw) {
     if (o.ev_begin) (void)hipEventRecord((hipEvent_t)o.ev_begin, s);
     if (A.edge_list) {  // lazy round: the listed edges, states side by side
         const unsigned lb = list_blocks();
@@ -858,11 +886,17 @@ static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const Sc
                                (const ArmParams *)nullptr, S);
         }
         hipLaunchKernelGGL(k_list_finish<W>, dim3(lb), dim3(256), 0, s, A);
-    } else if (A.n_int == 0)
+    } else if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<W>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
-    else
+    } else if (gw) {
+        const auto kern = gw == 1 ? k_interior<PointGridModel<W, kPointGridSp, 1>, true, 1>
+                        : gw == 2 ? k_interior<PointGridModel<W, kPointGridSp, 2>, true, 1>
+                                  : k_interior<PointGridModel<W, kPointGridSp, 3>, true, 1>;
+        hipLaunchKernelGGL(kern, dim3(grid_persist), dim3(256), 0, s, A, (const ArmParams *)nullptr, S);
+    } else {
         hipLaunchKernelGGL((k_interior<PointModel<W, SPI>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A,
                            (const ArmParams *)nullptr, S);
+    }
     if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
     return hipGetLastError();
 }
@@ -870,17 +904,21 @@ static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const Sc
 template <int W>
 static hipError_t launch_point(const EdgeArgs &A, const ArmParams &R, const SceneParams &S, int spi,
                                int grid_persist, const gtmp_edge_opts &o, hipStream_t s, const float *q0,
-                               const float *goals, const float *Q, float *verts, uint8_t *vflag, int phases) {
+                               const float *goals, const float *Q, float *verts, uint8_t *vflag, int phases,
+                               int gw) {
     const unsigned vb = (A.n_vertices + 255) / 256;
     if (phases & kPhaseVertices)
         hipLaunchKernelGGL(k_vertices_point<W>, dim3(vb), dim3(256), 0, s, A, S, q0, goals, Q, verts, vflag);
     if (!(phases & kPhaseEdges)) return hipGetLastError();
     if (!A.edge_list) hipLaunchKernelGGL(k_prepass<W>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
+    if (gw)  // the bins of the full check (lazy rounds keep the full test)
+        hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, W, 0.f,
+                           const_cast<ObsGrid *>(A.grid));
     switch (spi) {
-        case 1: return launch_point_s<W, 1>(A, R, S, grid_persist, o, s);
-        case 2: return launch_point_s<W, 2>(A, R, S, grid_persist, o, s);
-        case 4: return launch_point_s<W, 4>(A, R, S, grid_persist, o, s);
-        default: return launch_point_s<W, 8>(A, R, S, grid_persist, o, s);
+        case 1: return launch_point_s<W, 1>(A, R, S, grid_persist, o, s, gw);
+        case 2: return launch_point_s<W, 2>(A, R, S, grid_persist, o, s, gw);
+        case 4: return launch_point_s<W, 4>(A, R, S, grid_persist, o, s, gw);
+        default: return launch_point_s<W, 8>(A, R, S, grid_persist, o, s, gw);
     }
 }
 
@@ -992,7 +1030,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
         const int n_obs = scene.n_sph + scene.n_box;
         // automatic choice: the obstacle-bin filter whenever the masks hold
         // every obstacle, else (and on request) the chunked full test
-        const int gw = o.sphere_chunks == 0 && n_obs <= kGridMaxObs ? (n_obs <= 32 ? 1 : 2) : 0;
+        const int gw = o.sphere_chunks == 0 && n_obs <= kGridArmMaxObs ? grid_words(n_obs) : 0;
         const int nch = o.sphere_chunks == 1 ? 1 : o.sphere_chunks == 4 ? 4 : 2;
         A.grid = reinterpret_cast<const ObsGrid *>(ws + plan.off_grid);
         const void *kern = nullptr;
@@ -1019,20 +1057,32 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
     int spi = o.states_per_iter;
     if (spi <= 0) spi = kPointSpiAuto;
     if (spi != 1 && spi != 2 && spi != 4) spi = 8;
+    // automatic choice: the obstacle bins for a full check of a graph with
+    // many tiles whose scene the masks hold, else (and on request) the full test
+    const int n_obs = scene.n_sph + scene.n_box;
+    const int gw = o.sphere_chunks == 0 && !A.edge_list && n_obs > 0 && plan.n_tiles >= kPointGridMinTiles
+                       ? grid_words(n_obs) : 0;
+    A.grid = reinterpret_cast<const ObsGrid *>(ws + plan.off_grid);
     if (wdim == 2) {
-        const void *kern = spi == 1 ? (const void *)k_interior<PointModel<2, 1>, true, 1>
+        const void *kern = gw == 1 ? (const void *)k_interior<PointGridModel<2, kPointGridSp, 1>, true, 1>
+                         : gw == 2 ? (const void *)k_interior<PointGridModel<2, kPointGridSp, 2>, true, 1>
+                         : gw == 3 ? (const void *)k_interior<PointGridModel<2, kPointGridSp, 3>, true, 1>
+                         : spi == 1 ? (const void *)k_interior<PointModel<2, 1>, true, 1>
                          : spi == 2 ? (const void *)k_interior<PointModel<2, 2>, true, 1>
                          : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true, 1>
                                     : (const void *)k_interior<PointModel<2, 8>, true, 1>;
-        const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, kPointBlocksPerCuAuto);
-        return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases);
+        const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, gw ? kPointGridBlocksPerCuAuto[0] : kPointBlocksPerCuAuto);
+        return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases, gw);
     }
-    const void *kern = spi == 1 ? (const void *)k_interior<PointModel<3, 1>, true, 1>
+    const void *kern = gw == 1 ? (const void *)k_interior<PointGridModel<3, kPointGridSp, 1>, true, 1>
+                     : gw == 2 ? (const void *)k_interior<PointGridModel<3, kPointGridSp, 2>, true, 1>
+                     : gw == 3 ? (const void *)k_interior<PointGridModel<3, kPointGridSp, 3>, true, 1>
+                     : spi == 1 ? (const void *)k_interior<PointModel<3, 1>, true, 1>
                      : spi == 2 ? (const void *)k_interior<PointModel<3, 2>, true, 1>
                      : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true, 1>
                                 : (const void *)k_interior<PointModel<3, 8>, true, 1>;
-    const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, kPointBlocksPerCuAuto);
-    return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases);
+    const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, gw ? kPointGridBlocksPerCuAuto[1] : kPointBlocksPerCuAuto);
+    return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases, gw);
 }
 
 hipError_t launch_state_check(const ArmParams *arm, const SceneParams &scene, int wdim, int d, int64_t n,

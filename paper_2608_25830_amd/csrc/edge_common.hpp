@@ -27,13 +27,16 @@ namespace gtmp {
 // the exact test on those obstacles only, and its decision is the one of the
 // full test.
 constexpr int kGridCells = 256;
-constexpr int kGridMaxObs = 64;
+constexpr int kGridMaxObs = 96;  // three mask words
 
 struct ObsGrid {
     float inv[4], off[4];                  // axes x, y, z (the fourth entry unused)
-    float4 rec[kGridMaxObs][2];            // (lo.xyz, rho), (hi.xyz, 0)
-    uint32_t mask[2][3][kGridCells];       // mask word, axis, bin
+    float4 rec[kGridMaxObs][2];            // (lo.xyz, rho), (hi.xyz, 0); 2D scenes: z = 0
+    uint32_t mask[3][3][kGridCells];       // mask word, axis, bin (axes past the workspace list every obstacle)
 };
+
+// Mask words for a scene of n obstacles (0: too many for the bins).
+inline int grid_words(int n) { return n <= 32 ? 1 : n <= 64 ? 2 : n <= kGridMaxObs ? 3 : 0; }
 // The part of the grid a kernel with WORDS mask words copies to LDS.
 template <int WORDS>
 constexpr size_t grid_lds_bytes() { return offsetof(ObsGrid, mask) + sizeof(uint32_t) * 3 * kGridCells * WORDS; }
@@ -113,41 +116,40 @@ __device__ __forceinline__ float arm_state_gap(const AP &R, const v32f &o, float
     return gap;
 }
 
-// The obstacle bins of a scene for robot spheres of radius <= r_max, built
-// by one block of kGridBuildThreads threads (a thread per obstacle, then a
-// wave per axis, then a thread per (axis, bin) cell).  The bin maps and the obstacle intervals are computed in
-// FP32 with the same fused multiply-add and bin rounding the interior kernel
-// applies to a sphere centre (both monotone), and every interval is widened by
-// one bin on each side, so rounding in either place cannot move a sphere out
-// of a bin that lists the obstacle.  An obstacle with non-finite data is
-// listed in every bin, the outer two included, and takes no part in the bin
-// maps; should a map still come out non-finite, every obstacle is listed
-// everywhere.  Either way the exact test then sees that obstacle for every
-// sphere, as without the filter.
+// The obstacle bins of a scene of dimension wdim (2 or 3) for robot spheres
+// of radius <= r_max (a point robot: 0), built by one block of
+// kGridBuildThreads threads (a thread per obstacle, then a wave per axis, then
+// a thread per (axis, bin) cell).  The bin maps and the obstacle intervals are
+// computed in FP32 with the same fused multiply-add and bin rounding the
+// kernels apply to a probe centre (both monotone), and every interval is
+// widened by one bin on each side, so rounding in either place cannot move a
+// probe out of a bin that lists the obstacle.  An obstacle with non-finite
+// data is listed in every bin, the outer two included, and takes no part in
+// the bin maps; should a map still come out non-finite, every obstacle is
+// listed everywhere.  Either way the exact test then sees that obstacle for
+// every probe, as without the filter.  Axes past the workspace list every
+// obstacle in every bin.
 constexpr int kGridBuildThreads = 3 * kGridCells;  // one (axis, bin) cell per thread
 
-__device__ __forceinline__ void build_grid_block(const SceneParams &S, float r_max, ObsGrid *G) {
+__device__ __forceinline__ void build_grid_block(const SceneParams &S, int wdim, float r_max, ObsGrid *G) {
     __shared__ float lo_s[kGridMaxObs][3], hi_s[kGridMaxObs][3];
     __shared__ int wild_s[kGridMaxObs];
     __shared__ int2 span_s[3][kGridMaxObs];  // bins listed for obstacle o on each axis
-    __shared__ float map_s[3][2];
     __shared__ int bad_s;
     const int n = S.n_sph + S.n_box;  // <= kGridMaxObs (checked by the launcher)
     const int tid = threadIdx.x;
     if (tid == 0) bad_s = 0;
     if (tid < n) {
-        float lo[3], hi[3], rho;
+        float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f}, rho;
         if (tid < S.n_sph) {
-            const float *c = S.sph + 4 * tid;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) lo[i] = hi[i] = c[i];
-            rho = c[3];
+            const float *c = S.sph + (wdim + 1) * tid;
+            for (int i = 0; i < wdim; ++i) lo[i] = hi[i] = c[i];
+            rho = c[wdim];
         } else {
-            const float *b = S.box + 6 * (tid - S.n_sph);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                lo[i] = b[i] - b[3 + i];
-                hi[i] = b[i] + b[3 + i];
+            const float *bx = S.box + 2 * wdim * (tid - S.n_sph);
+            for (int i = 0; i < wdim; ++i) {
+                lo[i] = bx[i] - bx[wdim + i];
+                hi[i] = bx[i] + bx[wdim + i];
             }
             rho = 0.f;
         }
@@ -167,10 +169,11 @@ __device__ __forceinline__ void build_grid_block(const SceneParams &S, float r_m
     if (tid < 3 * kWave) {  // one wave per axis: the extent of the finite obstacles
         const int ax = tid / kWave, l = tid % kWave;
         float a = __builtin_inff(), b = -__builtin_inff();
-        if (l < n && !wild_s[l]) {
-            a = lo_s[l][ax];
-            b = hi_s[l][ax];
-        }
+        for (int o = l; o < n; o += kWave)
+            if (!wild_s[o]) {
+                a = __builtin_fminf(a, lo_s[o][ax]);
+                b = __builtin_fmaxf(b, hi_s[o][ax]);
+            }
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) {
             a = __builtin_fminf(a, __shfl_xor(a, off));
@@ -191,20 +194,18 @@ __device__ __forceinline__ void build_grid_block(const SceneParams &S, float r_m
         const float off = __builtin_fmaf(-a, inv, 1.f);
         if (l == 0) {
             if (!__builtin_isfinite(inv) || !__builtin_isfinite(off) || !(inv > 0.f)) bad_s = 1;
-            map_s[ax][0] = inv;
-            map_s[ax][1] = off;
             G->inv[ax] = inv;
             G->off[ax] = off;
         }
-        if (l < n) {  // the obstacle's bins on this axis, one bin wider on each side
-            int2 sp = make_int2(0, kGridCells - 1);  // non-finite obstacle: every bin
-            if (!wild_s[l]) {
-                sp.x = (int)grid_bin(__builtin_fmaf(lo_s[l][ax], inv, off)) - 1;
-                sp.y = (int)grid_bin(__builtin_fmaf(hi_s[l][ax], inv, off)) + 1;
+        for (int o = l; o < n; o += kWave) {  // the obstacle's bins on this axis, one bin wider on each side
+            int2 sp = make_int2(0, kGridCells - 1);  // non-finite obstacle or axis past the workspace: every bin
+            if (!wild_s[o] && ax < wdim) {
+                sp.x = (int)grid_bin(__builtin_fmaf(lo_s[o][ax], inv, off)) - 1;
+                sp.y = (int)grid_bin(__builtin_fmaf(hi_s[o][ax], inv, off)) + 1;
                 sp.x = sp.x < 1 ? 1 : sp.x;
                 sp.y = sp.y > kGridCells - 2 ? kGridCells - 2 : sp.y;
             }
-            span_s[ax][l] = sp;
+            span_s[ax][o] = sp;
         }
     }
     if (tid == 3 * kWave) {
@@ -213,14 +214,14 @@ __device__ __forceinline__ void build_grid_block(const SceneParams &S, float r_m
     }
     __syncthreads();
     const int ax = tid / kGridCells, bin = tid - ax * kGridCells;
-    uint32_t w[2] = {0u, 0u};
+    uint32_t w[3] = {0u, 0u, 0u};
     const bool all = bad_s != 0;
     for (int o = 0; o < n; ++o) {
         const int2 sp = span_s[ax][o];
         if (all || (bin >= sp.x && bin <= sp.y)) w[o >> 5] |= 1u << (o & 31);
     }
-    G->mask[0][ax][bin] = w[0];
-    G->mask[1][ax][bin] = w[1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) G->mask[k][ax][bin] = w[k];
 }
 
 // Collision of one arm state through the obstacle bins (G in LDS; inv / off
@@ -238,48 +239,62 @@ __device__ __forceinline__ void build_grid_block(const SceneParams &S, float r_m
 // that is not `live` appends nothing at all (its result is then meaningless).
 // `tests` counts the exact tests this lane made (for other lanes' entries too).
 // Every lane of the wave must call this (it drains on ballots).
-constexpr int kQueue = 128;  // entries per wave: up to 63 waiting plus one sphere of every lane
+constexpr int kQueue = 128;  // entries per wave: up to 63 waiting plus one probe of every lane
 
 template <int WORDS>
 struct GridQueue {
-    typedef typename std::conditional<WORDS == 2, uint64_t, uint32_t>::type Mask;
     struct Entry {
-        float4 c;  // centre, radius
-        uint4 m;   // mask words 0 and 1, owning lane, unused
+        float4 c;  // probe centre, radius
+        uint4 m;   // mask words 0, 1, 2 (unused words 0), owning lane
     } e[kQueue];
     uint8_t hit[kWave];
 };
 
 typedef uint32_t GridMaskTable[3][kGridCells];  // one mask word: axis, bin
 
-// mk: the mask tables (mk[w] = word w), rec: the obstacle records; both may
-// live in LDS or in device memory.
-template <int WORDS, class AP>
-__device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_MAX_JOINTS],
-                                             const GridMaskTable *mk, const float4 (*rec)[2],
-                                             const float (&inv)[3], const float (&off)[3],
-                                             GridQueue<WORDS> &Qw, uint32_t &tests, bool live) {
-    typedef typename GridQueue<WORDS>::Mask Mask;
-    const int lane = lane_id();
-    uint32_t head = 0, tail = 0;  // wave-uniform queue positions (mod kQueue in LDS)
-    bool hit = !live;             // an idle lane appends nothing
-    Qw.hit[lane] = 0;
-    auto drain = [&](uint32_t n) {  // the n <= 64 oldest entries, one per lane
+// The wave's side of the queue: probes are offered one per lane at a time
+// (every lane of the wave takes part in each offer and drain).
+template <int WORDS>
+struct GridProber {
+    GridQueue<WORDS> &Q;
+    const float4 (*rec)[2];
+    uint32_t &tests;
+    uint32_t head, tail;  // wave-uniform queue positions (mod kQueue in LDS)
+    bool hit;             // this lane's state is in contact (known from a drain)
+
+    __device__ __forceinline__ GridProber(GridQueue<WORDS> &q, const float4 (*r)[2], uint32_t &t, bool live)
+        : Q(q), rec(r), tests(t), head(0), tail(0), hit(!live) {
+        Q.hit[lane_id()] = 0;
+    }
+
+    // The n <= 64 oldest entries, one per lane.
+    __device__ __forceinline__ void drain(uint32_t n) {
+        const int lane = lane_id();
         __builtin_amdgcn_wave_barrier();
         const uint32_t slot = (head + (uint32_t)lane) & (kQueue - 1);
+        // words 0-1 as one 32- or 64-bit mask, word 2 beside it
+        typedef typename std::conditional<WORDS == 1, uint32_t, uint64_t>::type Mask;
         Mask m = 0;
+        uint32_t m2 = 0;
         float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
         int own = 0;
         if ((uint32_t)lane < n) {
-            e = Qw.e[slot].c;
-            const uint4 w = Qw.e[slot].m;
+            e = Q.e[slot].c;
+            const uint4 w = Q.e[slot].m;
             m = WORDS == 1 ? (Mask)w.x : (Mask)(((uint64_t)w.y << 32) | w.x);
-            own = (int)w.z;
+            if constexpr (WORDS > 2) m2 = w.z;
+            own = (int)w.w;
         }
-        while (ballot(m != 0) != 0) {
-            if (m != 0) {
-                const int o = WORDS == 1 ? __builtin_ctz((uint32_t)m) : __builtin_ctzll((uint64_t)m);
-                m &= m - 1;
+        while (ballot(m != 0 || m2 != 0) != 0) {
+            if (m != 0 || m2 != 0) {
+                int o;
+                if (m != 0) {
+                    o = WORDS == 1 ? __builtin_ctz((uint32_t)m) : __builtin_ctzll((uint64_t)m);
+                    m &= m - 1;
+                } else {
+                    o = 64 + __builtin_ctz(m2);
+                    m2 &= m2 - 1;
+                }
                 ++tests;
                 const float4 a = rec[o][0], h = rec[o][1];
                 const float Rr = a.w + e.w;
@@ -291,15 +306,56 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
                     g = __builtin_fmaf(dlt, dlt, g);
                 }
                 if (g <= 0.f) {
-                    Qw.hit[own] = 1;
+                    Q.hit[own] = 1;
                     m = 0;
+                    m2 = 0;
                 }
             }
         }
         __builtin_amdgcn_wave_barrier();
         head += n;
-        hit = hit || Qw.hit[lane] != 0;
-    };
+        hit = hit || Q.hit[lane] != 0;
+    }
+
+    // This lane's probe (centre c, radius r, bin mask words mw): queued when
+    // some obstacle is listed and the lane's state is not known to collide.
+    __device__ __forceinline__ void offer(const float (&c)[3], float r, const uint32_t (&mw)[WORDS]) {
+        uint32_t any = mw[0];
+#pragma unroll
+        for (int wd = 1; wd < WORDS; ++wd) any |= mw[wd];
+        if (hit) any = 0;  // (a select: the ballot below is then one compare)
+        const bool want = any != 0;
+        const uint64_t wmask = ballot(want);
+        // a scalar count, laundered so that the test below stays a scalar
+        // compare (the compiler would otherwise rebuild the lane mask in VGPRs)
+        uint32_t nw = (uint32_t)__popcll(wmask);
+        asm volatile("" : "+s"(nw));
+        if (nw != 0) {
+            if (want) {
+                const uint32_t slot = (tail + (uint32_t)rank_in(wmask)) & (kQueue - 1);
+                Q.e[slot].c = make_float4(c[0], c[1], c[2], r);
+                Q.e[slot].m = make_uint4(mw[0], WORDS > 1 ? mw[WORDS > 1 ? 1 : 0] : 0u,
+                                         WORDS > 2 ? mw[WORDS > 2 ? 2 : 0] : 0u, (uint32_t)lane_id());
+            }
+            tail += nw;
+            if (tail - head >= (uint32_t)kWave) drain(kWave);
+        }
+    }
+
+    __device__ __forceinline__ bool finish() {
+        if (tail != head) drain(tail - head);
+        return hit;
+    }
+};
+
+// mk: the mask tables (mk[w] = word w), rec: the obstacle records; both may
+// live in LDS or in device memory.
+template <int WORDS, class AP>
+__device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_MAX_JOINTS],
+                                             const GridMaskTable *mk, const float4 (*rec)[2],
+                                             const float (&inv)[3], const float (&off)[3],
+                                             GridQueue<WORDS> &Qw, uint32_t &tests, bool live) {
+    GridProber<WORDS> P(Qw, rec, tests, live);
     arm_fk_visit<GTMP_MAX_JOINTS>(R, q, [&](int L, const float (&b)[3], const float (&p)[3]) {
         float dd[3];
 #pragma unroll
@@ -315,28 +371,45 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
                 c[i] = __builtin_fmaf(t, dd[i], b[i]);
                 bin[i] = grid_bin(__builtin_fmaf(c[i], inv[i], off[i]));
             }
-            Mask m = mk[0][0][bin[0]] & mk[0][1][bin[1]] & mk[0][2][bin[2]];
-            if constexpr (WORDS == 2) m |= (Mask)(mk[1][0][bin[0]] & mk[1][1][bin[1]] & mk[1][2][bin[2]]) << 32;
-            if (hit) m = 0;  // (a select: the ballot below is then one compare)
-            const bool want = m != 0;
-            const uint64_t wmask = ballot(want);
-            // a scalar count, laundered so that the test below stays a scalar
-            // compare (the compiler would otherwise rebuild the lane mask in VGPRs)
-            uint32_t nw = (uint32_t)__popcll(wmask);
-            asm volatile("" : "+s"(nw));
-            if (nw != 0) {
-                if (want) {
-                    const uint32_t slot = (tail + (uint32_t)rank_in(wmask)) & (kQueue - 1);
-                    Qw.e[slot].c = make_float4(c[0], c[1], c[2], rk);
-                    Qw.e[slot].m = make_uint4((uint32_t)m, (uint32_t)((uint64_t)m >> 32), (uint32_t)lane, 0u);
-                }
-                tail += nw;
-                if (tail - head >= (uint32_t)kWave) drain(kWave);
-            }
+            uint32_t mw[WORDS];
+#pragma unroll
+            for (int wd = 0; wd < WORDS; ++wd) mw[wd] = mk[wd][0][bin[0]] & mk[wd][1][bin[1]] & mk[wd][2][bin[2]];
+            P.offer(c, rk, mw);
         }
     });
-    if (tail != head) drain(tail - head);
-    return hit;
+    return P.finish();
+}
+
+// Collision of SP point states of dimension W (radius 0) through the obstacle
+// bins: the obstacles their W bin masks list, tested exactly as the full test
+// does (R = rho_o, gap = -R^2 + sum_i (p_i - med3(p_i, lo_i, hi_i))^2, the
+// third axis of a 2D state at 0 on both sides, which adds nothing); true when
+// some state is in contact.  Every lane of the wave must call this.
+template <int W, int SP, int WORDS>
+__device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP], const GridMaskTable *mk,
+                                               const float4 (*rec)[2], const float (&inv)[3],
+                                               const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
+                                               bool live) {
+    GridProber<WORDS> P(Qw, rec, tests, live);
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+        float c[3] = {0.f, 0.f, 0.f};
+        uint32_t bin[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            c[i] = p[i][s];
+            bin[i] = grid_bin(__builtin_fmaf(c[i], inv[i], off[i]));
+        }
+        uint32_t mw[WORDS];
+#pragma unroll
+        for (int wd = 0; wd < WORDS; ++wd) {
+            mw[wd] = mk[wd][0][bin[0]];
+#pragma unroll
+            for (int i = 1; i < W; ++i) mw[wd] &= mk[wd][i][bin[i]];
+        }
+        P.offer(c, 0.f, mw);
+    }
+    return P.finish();
 }
 
 // Row / tile decoding.  Rows enumerate the edges by their shared endpoint:
@@ -458,6 +531,17 @@ struct ArmGridModel {
     static constexpr int kWords = WORDS;
     static constexpr int D = GTMP_MAX_JOINTS;
     static constexpr int KP = 1;
+};
+
+// Point states in R^W tested through the obstacle bins, S states per
+// evaluation (WORDS mask words).
+template <int W, int S, int WORDS>
+struct PointGridModel {
+    static constexpr bool kArm = false;
+    static constexpr bool kGrid = true;
+    static constexpr int kWords = WORDS;
+    static constexpr int D = W;
+    static constexpr int KP = S;
 };
 
 

@@ -18,7 +18,9 @@ def test_candidates_cover_each_knob():
     arm = AT.candidates(wl.make_workload("arm7", 0))
     pt = AT.candidates(wl.make_workload("2d-small", 0))
     assert {c["sphere_chunks"] for c in arm} == {0, 1, 2, 4}
-    assert {c["states_per_iter"] for c in pt} == {1, 2, 4, 8}
+    assert {c["states_per_iter"] for c in pt} == {0, 1, 2, 4, 8}
+    assert {c["sphere_chunks"] for c in pt} == {0, 2}
+    assert len({tuple(sorted(c.items())) for c in pt}) == len(pt)
     assert len({tuple(sorted(c.items())) for c in arm}) == len(arm)
 
 

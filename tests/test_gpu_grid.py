@@ -1,8 +1,9 @@
-"""The obstacle-bin filter of the arm edge check (the automatic choice for
-scenes of at most 64 obstacles) against the chunked test of every robot
-sphere against every obstacle (sphere_chunks = 2): both decide each state by
-the same FP32 difference-form gaps, so every edge cost and flag must agree
-bit for bit.  Cases: the arm7 scenes, per-sphere radii, one and two mask
+"""The obstacle-bin filter of the edge check (the automatic choice for arm
+scenes of at most 64 obstacles and for point-robot graphs of at least 1024
+tiles whose scene has at most 96) against the test of every robot sphere or
+point state against every obstacle (sphere_chunks = 2): both decide each
+state by the same FP32 difference-form gaps, so every edge cost and flag must
+agree bit for bit.  Cases: the arm7 scenes, per-sphere radii, one and two mask
 words (32 / 33 / 60 obstacles), the fallback above 64, no obstacles,
 degenerate obstacles and robot spheres of radius 0, a scene scaled by 50, and
 the lazy rounds' compacted-tile kernel.  Agreement with the oracle is checked
@@ -30,11 +31,14 @@ def _flat(pl):
 
 
 def _both(gt, w, seed=None):
-    """Edge costs and flags of one sample set under both arm tests."""
+    """Edge costs and flags of one sample set under both tests (point robots:
+    four states per lane and evaluation on both sides, as the bin kernel
+    takes them, so that the same states are evaluated)."""
     out = []
     for chunks in (0, 2):
         pl = gt.Planner(w, flags=True)
         pl.opts.sphere_chunks = chunks
+        pl.opts.states_per_iter = 4
         pl.sample(w["seed"] if seed is None else seed, 0)
         pl.check()
         torch.cuda.synchronize()
@@ -165,4 +169,61 @@ def test_arm_variants_match_oracle(gt, orc, variant, chunks):
     got = P.flat(pl.C_s.cpu().numpy(), pl.C_h.cpu().numpy()[: w["M"] - 1], pl.C_l.cpu().numpy())
     rep = P.compare_edges(got, pl.flags.cpu().numpy(), P.flat(*cost), P.flat(*minsd), P.flat(*flag))
     _say("arm variant", variant, "chunks", chunks, rep)
+    assert 0 < rep["failed"] < rep["edges"]
+
+
+# ---------------------------------------------------------------- point robots
+def _scene_2d(seed, n_circ, n_box):
+    g = np.random.default_rng(seed)
+    circ = np.concatenate([g.uniform(-10, 10, (n_circ, 2)), g.uniform(0.5, 1.0, (n_circ, 1))], 1)
+    box = np.concatenate([g.uniform(-10, 10, (n_box, 2)), g.uniform(0.3, 1.5, (n_box, 2))], 1)
+    return circ.astype(np.float32).reshape(n_circ, 3), box.astype(np.float32).reshape(n_box, 4)
+
+
+@pytest.mark.parametrize("name", ["2d-large", "3d-point"])
+@pytest.mark.parametrize("scene", [0, 1])
+def test_point_grid_matches_full_test(gt, name, scene):
+    """Point robots: the bins (automatic for a graph of at least 1024 tiles)
+    against every state tested against every obstacle."""
+    w = wl.make_workload(name, scene, M=5, N=256)  # 1026 tiles of 256 edges
+    n_free = _assert_same(_both(gt, w), f"{name} scene {scene}")
+    assert 0 < n_free < w["N"] * (w["N"] * 3 + 2)
+
+
+@pytest.mark.parametrize("n_circ,n_box", [(20, 10), (40, 20), (60, 30), (70, 30), (0, 1)])
+def test_point_grid_obstacle_counts(gt, n_circ, n_box):
+    """One, two and three mask words (30 / 60 / 90 obstacles), the full test
+    above 96 for both settings, and a single box."""
+    w = wl.make_workload("2d-large", 0, M=3, N=320)
+    w["circles"], w["boxes"] = _scene_2d(n_circ * 100 + n_box, n_circ, n_box)
+    _assert_same(_both(gt, w), f"2d {n_circ} circles + {n_box} boxes")
+
+
+def test_point_grid_degenerate(gt):
+    """Circles of radius 0, flat and point boxes, every state in one bin
+    column (a scene of obstacles stacked at one x)."""
+    w = wl.make_workload("2d-large", 1, M=3, N=320)
+    circ, box = _scene_2d(9, 30, 20)
+    circ[:6, 2] = 0.0
+    box[:5, 2] = 0.0
+    box[5:9, 2:] = 0.0
+    circ[10:20, 0] = 3.0
+    w["circles"], w["boxes"] = circ, box
+    _assert_same(_both(gt, w), "2d degenerate")
+
+
+def test_point_grid_matches_oracle(gt, orc):
+    """The automatic (bin) path of the 3D point robot against the FP64 oracle."""
+    from tests import parity as P
+    w = wl.make_workload("3d-point", 2, M=3, N=320)  # 1284 tiles
+    pl = gt.Planner(w, flags=True)
+    pl.plan(w["seed"], 0)
+    torch.cuda.synchronize()
+    Q = orc.sample_layers(w["M"], w["N"], w["d"], w["lo"], w["hi"], w["seed"], 0)
+    assert np.array_equal(pl.Q.cpu().numpy(), Q)
+    cost, minsd, flag = orc.edge_costs(orc.Model(w), w["M"], w["N"], w["G"], w["H"], w["q0"], w["goals"], Q,
+                                       w["penalty"])
+    got = P.flat(pl.C_s.cpu().numpy(), pl.C_h.cpu().numpy()[: w["M"] - 1], pl.C_l.cpu().numpy())
+    rep = P.compare_edges(got, pl.flags.cpu().numpy(), P.flat(*cost), P.flat(*minsd), P.flat(*flag))
+    _say("3d point oracle", rep)
     assert 0 < rep["failed"] < rep["edges"]
