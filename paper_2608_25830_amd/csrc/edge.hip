@@ -24,6 +24,16 @@
 
 namespace gtmp {
 
+// Tile cursors of the interior kernel: the tiles fall into kCursors
+// contiguous ranges, one per XCD of the chip (blocks are dealt to the XCDs in
+// turn), each counted by its own cursor 256 bytes from the next, so that the
+// waves' atomics spread over several addresses instead of queueing on one.
+constexpr int kCursors = 8;
+constexpr int kCursorStride = 64;  // 32-bit words between two cursors
+__host__ __device__ __forceinline__ uint32_t cursor_begin(uint32_t n_tiles, uint32_t c) {
+    return (uint32_t)((uint64_t)n_tiles * c / kCursors);
+}
+
 // ------------------------------------------------------------------ plan
 EdgePlan make_edge_plan(const gtmp_problem &p) {
     EdgePlan e{};
@@ -39,7 +49,7 @@ EdgePlan make_edge_plan(const gtmp_problem &p) {
     e.off_vflag = o; o = up(o + e.n_vertices);
     e.off_tile_off = o; o = up(o + (size_t)e.n_tiles * kTile);
     e.off_tile_cnt = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
-    e.off_counter = o; o = up(o + 256);
+    e.off_counter = o; o = up(o + sizeof(uint32_t) * kCursorStride * kCursors);
     e.off_params = o; o = up(o + sizeof(ArmParams));
     e.off_grid = o; o = up(o + sizeof(ObsGrid));
     e.total = o;
@@ -310,15 +320,26 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     static_assert(!ARM || KP % NCH == 0, "chunking must divide the sphere slots");
     __shared__ float tord[GTMP_MAX_H];
     constexpr int WG = Model::kWords > 0 ? Model::kWords : 1;
-    __shared__ typename std::conditional<GRID, GridLds<WG>, char>::type glds_raw;
+    constexpr int WS = point_mask_stride<WG>();
+    // arms: the grid's own mask layout; points: the maps and obstacles here,
+    // the mask words in pmask, one cell's words side by side
+    __shared__ typename std::conditional<GRID, GridLds<ARM ? WG : 0>, char>::type glds_raw;
+    __shared__ typename std::conditional<GRID && !ARM, PointMaskLds<WG>, char>::type pmask;
     __shared__ typename std::conditional<GRID, GridQueue<WG>[256 / kWave], char>::type gque;
-    const ObsGrid &glds = *reinterpret_cast<const ObsGrid *>(&glds_raw);  // the first grid_lds_bytes<WG>()
+    const ObsGrid &glds = *reinterpret_cast<const ObsGrid *>(&glds_raw);  // the first grid_lds_bytes()
     for (int i = threadIdx.x; i < A.n_int; i += blockDim.x) tord[i] = A.tord[i];
     if constexpr (GRID) {  // the maps, the obstacles and the mask words this kernel reads
         const uint4 *src = reinterpret_cast<const uint4 *>(A.grid);
         uint4 *dst = reinterpret_cast<uint4 *>(&glds_raw);
-        constexpr int n16 = (int)(grid_lds_bytes<WG>() / 16);
+        constexpr int n16 = (int)(grid_lds_bytes<ARM ? WG : 0>() / 16);
         for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+        if constexpr (!ARM) {
+            for (int i = threadIdx.x; i < W * kGridCells; i += blockDim.x) {
+                const int ax = i / kGridCells, bin = i - ax * kGridCells;
+#pragma unroll
+                for (int wd = 0; wd < WS; ++wd) pmask.m[ax][bin][wd] = wd < WG ? A.grid->mask[wd][ax][bin] : 0u;
+            }
+        }
     }
     __syncthreads();
     float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
@@ -344,6 +365,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
 
     // wave-uniform tile state
     uint32_t tile = 0, cnt = 0, pos = 0;
+    uint32_t cursor = blockIdx.x % kCursors, cursors_left = kCursors;
     RowInfo ri{};
     bool exhausted = false;
     unsigned long long n_states = 0, n_edges = 0;
@@ -368,11 +390,32 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             const uint32_t avail = cnt - pos;
             if (avail == 0) {
                 uint32_t t = 0;
-                if (lane == 0) t = atomicAdd(A.counter, 1u);
-                t = uniform(t);
-                if (t >= n_tiles) {
-                    exhausted = true;
-                    break;
+                if constexpr (LIST) {
+                    if (lane == 0) t = atomicAdd(A.counter, 1u);
+                    t = uniform(t);
+                    if (t >= n_tiles) {
+                        exhausted = true;
+                        break;
+                    }
+                } else {
+                    // the tiles fall into kCursors ranges, each with its own
+                    // cursor; a wave starts on its block's range and moves on
+                    // to the next ones as they run dry
+                    bool got = false;
+                    while (cursors_left > 0) {
+                        if (lane == 0) t = atomicAdd(A.counter + kCursorStride * cursor, 1u);
+                        t = uniform(t) + cursor_begin(n_tiles, cursor);
+                        if (t < cursor_begin(n_tiles, cursor + 1)) {
+                            got = true;
+                            break;
+                        }
+                        cursor = cursor + 1 < (uint32_t)kCursors ? cursor + 1 : 0u;
+                        --cursors_left;
+                    }
+                    if (!got) {
+                        exhausted = true;
+                        break;
+                    }
                 }
                 tile = t;
                 if constexpr (LIST) {
@@ -450,7 +493,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                 for (int i = 0; i < W; ++i) p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
             }
             uint32_t tests = 0;
-            gap = point_hit_grid<W, SP, Model::kWords>(p, glds.mask, glds.rec, ginv, goff, gque[threadIdx.x / kWave],
+            gap = point_hit_grid<W, SP, Model::kWords>(p, pmask.m, glds.rec, ginv, goff, gque[threadIdx.x / kWave],
                                                        tests, has)
                       ? -1.f : 1.f;
             n_tests += tests;
@@ -865,11 +908,10 @@ constexpr int kPointGridSp = 4;
 // Fewest tiles for which the point kernels take the bins (a small graph does
 // not repay building them).
 constexpr int kPointGridMinTiles = 1024;
-// Resident blocks per CU of the point kernels behind the bins (automatic),
-// 2D and 3D: their states are cheap, and fewer waves contend for the tile
-// cursor (measured best on 2d-large, M 16, N 1024: 0.76 ms at one block
-// against 0.79 at two and 0.92 at the occupancy limit).
-constexpr int kPointGridBlocksPerCuAuto[2] = {1, 2};
+// Resident blocks per CU of the point kernels behind the bins (automatic;
+// 2d-large, M 16, N 1024: 0.35 ms at four blocks against 0.38 at two and 0.60
+// at one).
+constexpr int kPointGridBlocksPerCuAuto = 4;
 // The arm kernels take at most two mask words.
 constexpr int kGridArmMaxObs = 64;
 
@@ -945,10 +987,11 @@ static int persistent_grid(const void *kernel, int block, int blocks_per_cu_req,
     return (int)(g < cap ? g : (cap > 0 ? cap : 1));
 }
 
-// automatic launch shape of the point-robot interior kernel (measured on the
-// 2D workload with 50 circles and 20 boxes: 8 states per lane, 3 blocks per CU)
+// automatic launch shape of the point-robot interior kernel with the full test
+// (measured on the 2D workload with 50 circles and 20 boxes: 8 states per
+// lane, 6 blocks per CU: 0.70 ms against 0.73 at 3)
 constexpr int kPointSpiAuto = 8;
-constexpr int kPointBlocksPerCuAuto = 3;
+constexpr int kPointBlocksPerCuAuto = 6;
 
 hipError_t launch_edge_check(const EdgePlan &plan, const ArmParams *arm, const SceneParams &scene, int wdim,
                              const EdgeBuffers &b, const gtmp_edge_opts &o, hipStream_t s) {
@@ -1024,7 +1067,9 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
 
     // fast mode: reset the tile cursor with a fill kernel (no memset node, so
     // the sequence can be captured into a graph and replayed)
-    if (phases & kPhaseEdges) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, A.counter, 2);
+    if (phases & kPhaseEdges)
+        hipLaunchKernelGGL(k_zero_u32, dim3(kCursors * kCursorStride / 256), dim3(256), 0, s, A.counter,
+                           kCursors * kCursorStride);
     if (arm) {
         const int kp = round_kp(R.n_spheres);
         const int n_obs = scene.n_sph + scene.n_box;
@@ -1071,7 +1116,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
                          : spi == 2 ? (const void *)k_interior<PointModel<2, 2>, true, 1>
                          : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true, 1>
                                     : (const void *)k_interior<PointModel<2, 8>, true, 1>;
-        const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, gw ? kPointGridBlocksPerCuAuto[0] : kPointBlocksPerCuAuto);
+        const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, gw ? kPointGridBlocksPerCuAuto : kPointBlocksPerCuAuto);
         return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases, gw);
     }
     const void *kern = gw == 1 ? (const void *)k_interior<PointGridModel<3, kPointGridSp, 1>, true, 1>
@@ -1081,7 +1126,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
                      : spi == 2 ? (const void *)k_interior<PointModel<3, 2>, true, 1>
                      : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true, 1>
                                 : (const void *)k_interior<PointModel<3, 8>, true, 1>;
-    const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, gw ? kPointGridBlocksPerCuAuto[1] : kPointBlocksPerCuAuto);
+    const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, gw ? kPointGridBlocksPerCuAuto : kPointBlocksPerCuAuto);
     return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases, gw);
 }
 

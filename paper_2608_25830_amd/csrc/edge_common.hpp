@@ -46,6 +46,17 @@ struct alignas(16) GridLds {
     unsigned char bytes[grid_lds_bytes<WORDS>()];
 };
 
+// Point kernels keep the mask words of one (axis, bin) cell side by side in
+// LDS, padded to 1, 2 or 4 words, so that a probe reads each axis with one
+// vector load.
+template <int WORDS>
+constexpr int point_mask_stride() { return WORDS == 3 ? 4 : WORDS; }
+
+template <int WORDS>
+struct alignas(16) PointMaskLds {
+    uint32_t m[3][kGridCells][point_mask_stride<WORDS>()];  // axis, bin, word
+};
+
 __device__ __forceinline__ uint32_t grid_bin(float f) { return __builtin_amdgcn_cvt_pk_u8_f32(f, 0u, 0u); }
 
 static_assert(sizeof(ObsGrid) % 16 == 0 && grid_lds_bytes<1>() % 16 == 0, "the grid is copied in 16-byte words");
@@ -386,7 +397,8 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
 // third axis of a 2D state at 0 on both sides, which adds nothing); true when
 // some state is in contact.  Every lane of the wave must call this.
 template <int W, int SP, int WORDS>
-__device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP], const GridMaskTable *mk,
+__device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP],
+                                               const uint32_t (&pm)[3][kGridCells][point_mask_stride<WORDS>()],
                                                const float4 (*rec)[2], const float (&inv)[3],
                                                const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
                                                bool live) {
@@ -402,10 +414,22 @@ __device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP], const Gr
         }
         uint32_t mw[WORDS];
 #pragma unroll
-        for (int wd = 0; wd < WORDS; ++wd) {
-            mw[wd] = mk[wd][0][bin[0]];
+        for (int wd = 0; wd < WORDS; ++wd) mw[wd] = ~0u;
 #pragma unroll
-            for (int i = 1; i < W; ++i) mw[wd] &= mk[wd][i][bin[i]];
+        for (int i = 0; i < W; ++i) {
+            const uint32_t *cell = pm[i][bin[i]];
+            if constexpr (WORDS == 3) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(cell);
+                mw[0] &= v.x;
+                mw[1 % WORDS] &= v.y;
+                mw[2 % WORDS] &= v.z;
+            } else if constexpr (WORDS == 2) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(cell);
+                mw[0] &= v.x;
+                mw[1 % WORDS] &= v.y;
+            } else {
+                mw[0] &= cell[0];
+            }
         }
         P.offer(c, 0.f, mw);
     }
