@@ -9,6 +9,19 @@
 
 namespace gtmp {
 
+// Tile cursors of the batched interior kernels: a group's tiles fall into
+// kBatchCursors contiguous ranges, one per XCD (blocks are dealt to the XCDs
+// in turn), each counted by its own cursor 256 bytes from the next, so that
+// the waves' atomics spread over several addresses.
+constexpr int kBatchCursors = 8;
+constexpr int kBatchCursorStride = 64;                                      // 32-bit words
+constexpr int kBatchGroupCounters = kBatchCursors * kBatchCursorStride;    // one robot group
+constexpr int kBatchStageCounters = 3 * kBatchGroupCounters;               // the three groups of a stage
+static_assert(kBatchStageCounters % 256 == 0, "cleared by whole 256-thread blocks");
+__device__ __forceinline__ uint32_t batch_cursor_begin(uint32_t n, uint32_t c) {
+    return (uint32_t)((uint64_t)n * c / kBatchCursors);
+}
+
 // Per-plan, per-stage descriptor (device table, read-only during a stage).
 struct BPlan {
     EdgeArgs A;          // edge check of this plan's stage (workspace, costs, tiles, t order)
@@ -241,6 +254,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4
 
     int cur = -1;               // plan of the lanes' edges (wave uniform)
     uint32_t tile = 0, cnt = 0, pos = 0, pending = 0xffffffffu;
+    uint32_t cursor = blockIdx.x % kBatchCursors, cursors_left = kBatchCursors;
     int pend_plan = -1;
     RowInfo ri{};
     bool exhausted = false;
@@ -259,10 +273,22 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4
         while (n_need > 0 && !exhausted) {
             const uint32_t avail = cnt - pos;
             if (avail == 0 && pending == 0xffffffffu) {
+                // the group's tiles fall into kBatchCursors ranges, each with
+                // its own cursor; a wave starts on its block's range and moves
+                // on to the next ones as they run dry
                 uint32_t t = 0;
-                if (lane == 0) t = atomicAdd(gcounter, 1u);
-                t = uniform(t);
-                if (t >= n_gtiles) {
+                bool got = false;
+                while (cursors_left > 0) {
+                    if (lane == 0) t = atomicAdd(gcounter + kBatchCursorStride * cursor, 1u);
+                    t = uniform(t) + batch_cursor_begin(n_gtiles, cursor);
+                    if (t < batch_cursor_begin(n_gtiles, cursor + 1)) {
+                        got = true;
+                        break;
+                    }
+                    cursor = cursor + 1 < (uint32_t)kBatchCursors ? cursor + 1 : 0u;
+                    --cursors_left;
+                }
+                if (!got) {
                     exhausted = true;
                     break;
                 }
@@ -656,7 +682,7 @@ BatchLayout make_batch_layout(const gtmp_plan_desc *plans, int n, const gtmp_bat
     L.off_grids = off; off = up(off + sizeof(ObsGrid) * (size_t)n);
     L.off_tables = off; off = up(off + sizeof(BPlan) * (size_t)n * (size_t)max_stages);
     L.off_bases = off; off = up(off + sizeof(uint64_t) * (size_t)n * (size_t)max_stages);
-    L.off_counters = off; off = up(off + sizeof(uint32_t) * 8 * (size_t)max_stages + 256);
+    L.off_counters = off; off = up(off + sizeof(uint32_t) * kBatchStageCounters * (size_t)max_stages + 256);
     L.total = off;
     (void)o;
     return L;
@@ -842,8 +868,9 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
             const StageInfo &I = info[st];
             const BPlan *T = tables + (size_t)st * n;
             const uint64_t *Bs = bases + (size_t)st * n;
-            uint32_t *ctr = counters + 8 * st;
-            hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(64), 0, st_, ctr, 8);
+            uint32_t *ctr = counters + kBatchStageCounters * st;  // the three groups' cursors
+            hipLaunchKernelGGL(k_batch_zero, dim3(kBatchStageCounters / 256), dim3(256), 0, st_, ctr,
+                               kBatchStageCounters);
             // samples
             if (I.samples > 0)
                 hipLaunchKernelGGL(k_batch_sample, dim3((unsigned)((I.samples + 255) / 256)), dim3(256), 0, st_, T,
@@ -890,7 +917,7 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
             if (I.gtiles[1] > 0) {
                 const void *k = (const void *)k_batch_interior<PointModel<3, 8>, true, 1>;
                 const int grid = persistent_blocks(k, o.blocks_per_cu, 3);
-                uint32_t *c1 = ctr + 1;
+                uint32_t *c1 = ctr + kBatchGroupCounters;
                 void *args[] = {(void *)&T, (void *)&I.g1, (void *)&I.g2, (void *)&I.gtiles[1], (void *)&c1,
                                 (void *)&out.stats};
                 hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, st_);
@@ -908,7 +935,7 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                 if (grid_words == 2) k = (const void *)k_batch_interior<ArmGridModel<2>, true, 1>;
                 if (!k) return hipErrorInvalidValue;
                 const int grid = persistent_blocks(k, o.blocks_per_cu);
-                uint32_t *c2 = ctr + 2;
+                uint32_t *c2 = ctr + 2 * kBatchGroupCounters;
                 void *args[] = {(void *)&T, (void *)&I.g2, (void *)&I.g3, (void *)&I.gtiles[2], (void *)&c2,
                                 (void *)&out.stats};
                 hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, st_);
