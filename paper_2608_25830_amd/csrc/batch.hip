@@ -27,7 +27,7 @@ struct BPlan {
     EdgeArgs A;          // edge check of this plan's stage (workspace, costs, tiles, t order)
     SceneParams S;
     const ArmParams *arm;  // device copy of the robot table (arms), null for points
-    float grid_r_max;      // arms: largest robot sphere radius (the obstacle bins are built for it)
+    float grid_r_max;      // arms: largest robot sphere radius (the obstacle bins are built for it); points: 0
     int group;           // 0: 2D point, 1: 3D point, 2: arm
     uint32_t vert_base;  // first vertex of this plan in its group's vertex space
     uint32_t tile_base;  // first tile of this plan in the batch's tile space
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4
     // obstacle bins (arms): each wave holds the mask words of its current
     // plan in LDS; the obstacle records (read by the exact tests only) stay in
     // device memory
-    constexpr int WG = Model::kWords > 1 ? 2 : 1;
+    constexpr int WG = Model::kWords > 0 ? Model::kWords : 1;
     __shared__ typename std::conditional<GRID, GridMaskTable[4][WG], char>::type gmask;
     __shared__ typename std::conditional<GRID, GridQueue<WG>[4], char>::type gque;
     const float4(*grec)[2] = nullptr;
@@ -377,6 +377,20 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4
                 const v32f o = arm_fk<D>(R, q);
                 gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
             }
+        } else if constexpr (GRID) {
+            float p[W][SP];
+#pragma unroll
+            for (int s = 0; s < SP; ++s) {
+                int jj = j + s;
+                jj = jj < n_int ? jj : n_int - 1;
+                const float t = tord[wv][has ? jj : 0];
+#pragma unroll
+                for (int i = 0; i < W; ++i) p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
+            }
+            uint32_t tests = 0;
+            gap = point_hit_grid<W, SP, Model::kWords>(p, gmask[wv], grec, ginv, goff, gque[wv], tests, has) ? -1.f
+                                                                                                              : 1.f;
+            n_tests += tests;
         } else {
             Probes<W, KP> P;
 #pragma unroll
@@ -593,9 +607,9 @@ __global__ void __launch_bounds__(64) k_batch_arm_tol(const BPlan *plans, int p0
 
 // Obstacle bins of every arm plan of the group range [p0, p0 + gridDim.x)
 // (one block per plan; the bins depend on the scene and the robot radii only).
-__global__ void __launch_bounds__(kGridBuildThreads) k_batch_build_grid(const BPlan *plans, int p0) {
+__global__ void __launch_bounds__(kGridBuildThreads) k_batch_build_grid(const BPlan *plans, int p0, int wdim) {
     const BPlan &P = plans[p0 + blockIdx.x];
-    build_grid_block(P.S, 3, P.grid_r_max, const_cast<ObsGrid *>(P.A.grid));
+    build_grid_block(P.S, wdim, P.grid_r_max, const_cast<ObsGrid *>(P.A.grid));
 }
 
 __global__ void k_batch_zero(uint32_t *p, int n) {
@@ -721,6 +735,15 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         if (n_obs > 64) grid_words = 0;  // the arm kernels take at most two mask words
         else if (n_obs > 32) grid_words = 2;
     }
+    // the same bins for the 2D point group when every plan's scene fits them
+    // (four states per lane; states_per_iter then applies to the full test only)
+    int pgrid_words = 0;
+    if (o.sphere_chunks == 0) {
+        int most = 1;
+        for (int p = 0; p < n; ++p)
+            if (group[p] == 0) most = std::max(most, plans[p].scene.n_spheres + plans[p].scene.n_boxes);
+        pgrid_words = most <= kGridMaxObs ? grid_words_for(most) : 0;
+    }
     ObsGrid *grids = reinterpret_cast<ObsGrid *>(ws + L.off_grids);
 
     struct StageInfo {
@@ -776,6 +799,10 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                 for (int i = 0; i < A.n_int; ++i) A.tord[i] = (float)ordr[i] / (float)(pp.H - 1);
                 B.S = SceneParams{D.scene.spheres, D.scene.boxes, D.scene.n_spheres, D.scene.n_boxes};
                 B.arm = gi == 2 ? arm_dev + p : nullptr;
+                if (gi == 0) {
+                    A.grid = grids + p;  // point robot: bins for radius 0
+                    B.grid_r_max = 0.f;
+                }
                 if (gi == 2) {
                     A.grid = grids + p;
                     float r_max = 0.f;
@@ -858,11 +885,14 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         if (info.empty()) return hipSuccess;
         // archive init over the plans of stage 0 (every plan has a stage 0)
         hipLaunchKernelGGL(k_batch_init, dim3((info[0].count + 255) / 256), dim3(256), 0, st_, tables, info[0].count);
+        if (pgrid_words && info[0].g1 > info[0].g0)
+            hipLaunchKernelGGL(k_batch_build_grid, dim3(info[0].g1 - info[0].g0), dim3(kGridBuildThreads), 0, st_,
+                               tables, info[0].g0, 2);
         if (info[0].g3 > info[0].g2) {
             hipLaunchKernelGGL(k_batch_arm_tol, dim3(info[0].g3 - info[0].g2), dim3(64), 0, st_, tables, info[0].g2);
             if (grid_words)
                 hipLaunchKernelGGL(k_batch_build_grid, dim3(info[0].g3 - info[0].g2), dim3(kGridBuildThreads), 0, st_,
-                                   tables, info[0].g2);
+                                   tables, info[0].g2, 3);
         }
         for (int st = 0; st < L.max_stages; ++st) {
             const StageInfo &I = info[st];
@@ -904,7 +934,10 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
             hipLaunchKernelGGL(k_batch_no_interior, dim3(I.tiles), dim3(kTile), 0, st_, T, I.count);
             // persistent interior per group
             if (I.gtiles[0] > 0) {
-                const void *k = spi == 1 ? (const void *)k_batch_interior<PointModel<2, 1>, true, 1>
+                const void *k = pgrid_words == 1 ? (const void *)k_batch_interior<PointGridModel<2, 4, 1>, true, 1>
+                              : pgrid_words == 2 ? (const void *)k_batch_interior<PointGridModel<2, 4, 2>, true, 1>
+                              : pgrid_words == 3 ? (const void *)k_batch_interior<PointGridModel<2, 4, 3>, true, 1>
+                              : spi == 1 ? (const void *)k_batch_interior<PointModel<2, 1>, true, 1>
                               : spi == 2 ? (const void *)k_batch_interior<PointModel<2, 2>, true, 1>
                               : spi == 8 ? (const void *)k_batch_interior<PointModel<2, 8>, true, 1>
                                          : (const void *)k_batch_interior<PointModel<2, 4>, true, 1>;

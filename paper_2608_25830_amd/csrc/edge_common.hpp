@@ -37,6 +37,7 @@ struct ObsGrid {
 
 // Mask words for a scene of n obstacles (0: too many for the bins).
 inline int grid_words(int n) { return n <= 32 ? 1 : n <= 64 ? 2 : n <= kGridMaxObs ? 3 : 0; }
+inline int grid_words_for(int n) { return grid_words(n); }  // (where a local variable hides grid_words)
 // The part of the grid a kernel with WORDS mask words copies to LDS.
 template <int WORDS>
 constexpr size_t grid_lds_bytes() { return offsetof(ObsGrid, mask) + sizeof(uint32_t) * 3 * kGridCells * WORDS; }
@@ -395,13 +396,13 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
 // bins: the obstacles their W bin masks list, tested exactly as the full test
 // does (R = rho_o, gap = -R^2 + sum_i (p_i - med3(p_i, lo_i, hi_i))^2, the
 // third axis of a 2D state at 0 on both sides, which adds nothing); true when
-// some state is in contact.  Every lane of the wave must call this.
-template <int W, int SP, int WORDS>
-__device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP],
-                                               const uint32_t (&pm)[3][kGridCells][point_mask_stride<WORDS>()],
-                                               const float4 (*rec)[2], const float (&inv)[3],
-                                               const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
-                                               bool live) {
+// some state is in contact.  and_mask(i, bin, mw) ANDs the mask words of
+// bin `bin` on axis i into mw.  Every lane of the wave must call this.
+template <int W, int SP, int WORDS, class AndMask>
+__device__ __forceinline__ bool point_hit_grid_by(const float (&p)[W][SP], const AndMask &and_mask,
+                                                  const float4 (*rec)[2], const float (&inv)[3],
+                                                  const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
+                                                  bool live) {
     GridProber<WORDS> P(Qw, rec, tests, live);
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
@@ -416,24 +417,48 @@ __device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP],
 #pragma unroll
         for (int wd = 0; wd < WORDS; ++wd) mw[wd] = ~0u;
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            const uint32_t *cell = pm[i][bin[i]];
-            if constexpr (WORDS == 3) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(cell);
-                mw[0] &= v.x;
-                mw[1 % WORDS] &= v.y;
-                mw[2 % WORDS] &= v.z;
-            } else if constexpr (WORDS == 2) {
-                const uint2 v = *reinterpret_cast<const uint2 *>(cell);
-                mw[0] &= v.x;
-                mw[1 % WORDS] &= v.y;
-            } else {
-                mw[0] &= cell[0];
-            }
-        }
+        for (int i = 0; i < W; ++i) and_mask(i, bin[i], mw);
         P.offer(c, 0.f, mw);
     }
     return P.finish();
+}
+
+// The masks with one cell's words side by side (one vector read per axis).
+template <int W, int SP, int WORDS>
+__device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP],
+                                               const uint32_t (&pm)[3][kGridCells][point_mask_stride<WORDS>()],
+                                               const float4 (*rec)[2], const float (&inv)[3],
+                                               const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
+                                               bool live) {
+    auto and_mask = [&](int i, uint32_t bin, uint32_t (&mw)[WORDS]) {
+        const uint32_t *cell = pm[i][bin];
+        if constexpr (WORDS == 3) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(cell);
+            mw[0] &= v.x;
+            mw[1 % WORDS] &= v.y;
+            mw[2 % WORDS] &= v.z;
+        } else if constexpr (WORDS == 2) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(cell);
+            mw[0] &= v.x;
+            mw[1 % WORDS] &= v.y;
+        } else {
+            mw[0] &= cell[0];
+        }
+    };
+    return point_hit_grid_by<W, SP, WORDS>(p, and_mask, rec, inv, off, Qw, tests, live);
+}
+
+// The masks in the grid's own layout (mk[w] = word w).
+template <int W, int SP, int WORDS>
+__device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP], const GridMaskTable *mk,
+                                               const float4 (*rec)[2], const float (&inv)[3],
+                                               const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
+                                               bool live) {
+    auto and_mask = [&](int i, uint32_t bin, uint32_t (&mw)[WORDS]) {
+#pragma unroll
+        for (int wd = 0; wd < WORDS; ++wd) mw[wd] &= mk[wd][i][bin];
+    };
+    return point_hit_grid_by<W, SP, WORDS>(p, and_mask, rec, inv, off, Qw, tests, live);
 }
 
 // Row / tile decoding.  Rows enumerate the edges by their shared endpoint:
