@@ -389,33 +389,24 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
         while (n_need > 0 && !exhausted) {
             const uint32_t avail = cnt - pos;
             if (avail == 0) {
+                // the tiles (lists: chunks) fall into kCursors ranges, each with
+                // its own cursor; a wave starts on its block's range and moves
+                // on to the next ones as they run dry
                 uint32_t t = 0;
-                if constexpr (LIST) {
-                    if (lane == 0) t = atomicAdd(A.counter, 1u);
-                    t = uniform(t);
-                    if (t >= n_tiles) {
-                        exhausted = true;
+                bool got = false;
+                while (cursors_left > 0) {
+                    if (lane == 0) t = atomicAdd(A.counter + kCursorStride * cursor, 1u);
+                    t = uniform(t) + cursor_begin(n_tiles, cursor);
+                    if (t < cursor_begin(n_tiles, cursor + 1)) {
+                        got = true;
                         break;
                     }
-                } else {
-                    // the tiles fall into kCursors ranges, each with its own
-                    // cursor; a wave starts on its block's range and moves on
-                    // to the next ones as they run dry
-                    bool got = false;
-                    while (cursors_left > 0) {
-                        if (lane == 0) t = atomicAdd(A.counter + kCursorStride * cursor, 1u);
-                        t = uniform(t) + cursor_begin(n_tiles, cursor);
-                        if (t < cursor_begin(n_tiles, cursor + 1)) {
-                            got = true;
-                            break;
-                        }
-                        cursor = cursor + 1 < (uint32_t)kCursors ? cursor + 1 : 0u;
-                        --cursors_left;
-                    }
-                    if (!got) {
-                        exhausted = true;
-                        break;
-                    }
+                    cursor = cursor + 1 < (uint32_t)kCursors ? cursor + 1 : 0u;
+                    --cursors_left;
+                }
+                if (!got) {
+                    exhausted = true;
+                    break;
                 }
                 tile = t;
                 if constexpr (LIST) {
