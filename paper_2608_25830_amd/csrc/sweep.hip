@@ -128,7 +128,8 @@ __global__ void __launch_bounds__(1024) k_start(int N, const float *__restrict__
 }
 
 // ---------------------------------------------------------------- small graphs
-// Whole recursion in one block of 256 threads (N <= 1024).  When C_h fits
+// Whole recursion in one block of 256 threads; only for N <= 1024 (the
+// value buffers below hold one layer of at most 1024 entries each).  When C_h fits
 // (kSmallStage floats) the block first loads all of it into LDS in one
 // parallel burst, so the rows of a layer are not each a dependent global
 // load away.
@@ -237,7 +238,9 @@ hipError_t launch_minplus(int M, int N, int G, const float *C_s, const float *C_
     // one block only while C_h fits its LDS: streamed from memory by a single
     // block the recursion is slower than a launch per layer (measured: M 4,
     // N 128 78 us against about 20; M 16, N 256 1.0 ms)
-    if ((long long)(M - 1) * N * N <= kSmallStage) {
+    // (N <= 1024: the block's two value buffers hold one layer each; at M = 1
+    // the staging bound alone would admit any N)
+    if (N <= 1024 && (long long)(M - 1) * N * N <= kSmallStage) {
         const int staged = 1;
         const size_t lds = staged ? sizeof(float) * (size_t)(M - 1) * N * N : 0;
         hipLaunchKernelGGL(k_sweep_small, dim3(1), dim3(256), lds, s, M, N, G, C_s, C_h, C_l, Vg, V, A, V_s, a_s,

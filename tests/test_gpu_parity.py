@@ -51,7 +51,8 @@ def test_sampler_bit_exact(gt, orc, name):
 @pytest.mark.parametrize("M,N,G,p_inf,p_tie", [(4, 64, 1, 0, 0), (4, 64, 1, 0.3, 0.5), (16, 1024, 1, 0, 0.3),
                                                (8, 2048, 1, 0, 0), (8, 2048, 1, 0.1, 0.2), (5, 1000, 3, 0.2, 0.3),
                                                (3, 333, 2, 0.5, 0), (1, 50, 4, 0, 0), (6, 1, 1, 0, 0),
-                                               (3, 4096, 1, 0, 0.1), (2, 7, 1, 1.0, 0)])
+                                               (3, 4096, 1, 0, 0.1), (2, 7, 1, 1.0, 0),
+                                               (1, 2048, 1, 0, 0), (1, 4096, 3, 0.1, 0.2), (1, 1025, 2, 0, 0.3)])
 def test_minplus_matches_oracle(gt, orc, M, N, G, p_inf, p_tie):
     _say("minplus", M, N, G, p_inf, p_tie)
     Cs, Ch, Cl = wl.random_costs(M * 1000 + N, M, N, G, p_inf=p_inf, p_tie=p_tie)
@@ -260,6 +261,21 @@ def test_multi_goal_single_layer_and_length_limit(gt, orc):
     L = np.linalg.norm(Q[1][None, :, :] - Q[0][:, None, :], axis=-1)
     E0 = pl3.flags.cpu().numpy()[64: 64 + 64 * 64].reshape(64, 64)
     assert np.all(E0[L > 6.0 + 1e-4] == 1)
+
+
+def test_single_layer_many_samples(gt, orc):
+    # M = 1 with N beyond the one-block sweep's value buffers (1024): the
+    # goal layer and the start reduction must take the per-layer launches
+    w = wl.make_workload("2d-small", 4, M=1, N=2048, H=8)
+    _say("M=1 N=2048")
+    pl = gpu_plan(gt, w)
+    ref = orc.plan(w)
+    got = P.flat(pl.C_s.cpu().numpy(), np.zeros(0), pl.C_l.cpu().numpy())
+    rep = P.compare_edges(got, pl.flags.cpu().numpy(), P.flat(*ref["cost"]), P.flat(*ref["minsd"]),
+                          P.flat(*ref["flag"]))
+    assert rep["excused"] == 0
+    assert float(pl.cost.item()) == pytest.approx(ref["path_cost"], rel=P.REL)
+    P.check_path_indices(ref["cost"], ref["V"], ref["idx"], pl.idx.cpu().numpy(), ref["path_cost"])
 
 
 def test_single_sample_layers(gt, orc):
