@@ -84,6 +84,8 @@ def _declare(L):
                              _ip, _dp, _dp]
     L.or_extract.restype = C.c_int
     L.or_informed_params.argtypes = [C.c_int, _fp, _fp, C.c_float, _fp, _fp, _fp, _fp, _fp]
+    L.or_informed_proposal.argtypes = [C.c_int, _fp, _fp, _fp, _fp, C.c_float, C.c_float, _fp, _fp]
+    L.or_informed_proposal.restype = C.c_int
     L.or_sample_informed.argtypes = [C.c_int, _fp, _fp, _fp, _fp, C.c_float, C.c_float, C.c_uint64, C.c_uint64,
                                      C.c_uint32, C.c_uint32, C.c_int, _fp]
     L.or_sample_informed.restype = C.c_int

@@ -12,7 +12,7 @@ import numpy as np
 import oracle as O
 import oracle.simplify as OSI
 
-MAX_ATTEMPTS = 4096
+MAX_ATTEMPTS = 16384
 # biased heuristic half: the closest pairs scored by the surrogate per new
 # slot of a layer
 BIAS_CANDIDATES = 4
@@ -31,7 +31,8 @@ def _bound(c, penalty):
 def informed_draw(w, c, seed, stage, m, n):
     """One draw of the uniform half for slot (m, n): the informed set
     X_f(c) (Sec. IV-E) intersected with the box; uniform in the box without a
-    bound.  Returns (x float32[d], attempts)."""
+    bound.  Returns (x float32[d], attempts); attempts is 0 for an unbounded
+    draw and -1 when the attempt cap was reached (x is then the centre)."""
     d = w["d"]
     out = np.zeros(d, np.float32)
     lo, hi = O._f32(w["lo"]), O._f32(w["hi"])
@@ -50,6 +51,20 @@ def informed_params(d, q0, qg, c):
     O.lib().or_informed_params(d, O._ptr(q0, O._fp), O._ptr(qg, O._fp), float(c), O._ptr(centre, O._fp),
                                O._ptr(H, O._fp), O._ptr(r1, O._fp), O._ptr(r2, O._fp), O._ptr(cmin, O._fp))
     return centre, H.reshape(d, d), float(r1[0]), float(r2[0]), float(cmin[0])
+
+
+def informed_proposal(w, c):
+    """Proposal region of the uniform half for the bound c: (clipped, c_lo,
+    c_hi) with clipped = True for the hyperspheroid's bounding box clipped to
+    the sampling box (bounds c_lo, c_hi), False for its own frame box."""
+    d = w["d"]
+    centre, H, r1, r2, _ = informed_params(d, w["q0"], np.asarray(w["goals"])[0], c)
+    lo, hi = O._f32(w["lo"]), O._f32(w["hi"])
+    c_lo, c_hi = np.zeros(d, np.float32), np.zeros(d, np.float32)
+    H = np.ascontiguousarray(H.ravel(), np.float32)
+    k = O.lib().or_informed_proposal(d, O._ptr(lo, O._fp), O._ptr(hi, O._fp), O._ptr(centre, O._fp),
+                                     O._ptr(H, O._fp), r1, r2, O._ptr(c_lo, O._fp), O._ptr(c_hi, O._fp))
+    return bool(k), c_lo, c_hi
 
 
 def coin_heuristic(seed, stage, m, n):

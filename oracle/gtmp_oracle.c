@@ -380,28 +380,49 @@ int or_extract(int M, int N, int G, int d, int as, const int *A, double Vs, cons
 /*                                                                          */
 /* Uniform half: a uniform draw from the informed set                       */
 /*   X_f(c) = {x : |x - q0| + |x - q_g| <= c}   (Sec. IV-E)                  */
-/* intersected with the sampling box, by the direct method of Gammell et    */
-/* al. (2018): a uniform point y of the unit d-ball, scaled per axis to the */
-/* hyperspheroid radii (c/2, sqrt(c^2 - c_min^2)/2, ...), rotated so that   */
-/* the first axis points from q0 to q_g, and moved to the centre            */
-/* (q0 + q_g)/2.  The ball point is drawn by rejection from the cube        */
-/* [-1, 1]^d; a transformed point outside the box is rejected as well.      */
+/* intersected with the sampling box B, by rejection from one of two        */
+/* proposal regions that both contain X_f(c) n B:                           */
+/*   R: the hyperspheroid's own frame box.  A point y of the cube [-1, 1]^d */
+/*      is kept iff |y| < 1 (a uniform point of the unit ball), scaled per  */
+/*      axis to the radii (c/2, sqrt(c^2 - c_min^2)/2, ...), rotated so     */
+/*      that the first axis points from q0 to q_g and moved to the centre   */
+/*      (q0 + q_g)/2 (the direct map of Gammell et al. 2018); the mapped    */
+/*      point is kept iff it lies in B.                                     */
+/*   C: the axis-aligned bounding box of the hyperspheroid clipped to B.    */
+/*      A uniform point of C is kept iff |x - q0| + |x - q_g| <= c.         */
+/* Both accept exactly the points of X_f(c) n B, so either gives a uniform  */
+/* draw of it; the one with the smaller volume (|R| = prod 2 r_i against    */
+/* |C| = prod of C's side lengths) accepts more often and is used.  R wins  */
+/* for thin hyperspheroids inside the box, C as soon as the hyperspheroid   */
+/* reaches beyond the box, where R alone accepts rarely.                    */
 /* Without a bound (c = +inf or c >= the edge penalty) the draw is uniform  */
 /* in the box.                                                              */
 /*                                                                          */
 /* The sample is defined as an FP32 computation with a fixed operation     */
 /* order (no fused multiply-add), which this file reproduces with float     */
 /* arithmetic (compiled with -ffp-contract=off):                            */
-/*   y_i = (w_i >> 8) * 2^-23 - 1, accept iff sum_i y_i^2 < 1 (summed in i) */
-/*   z = (r1 y_1, r2 y_2, ..., r2 y_d)                                      */
-/*   x_i = centre_i + sum_j H_ij z_j (summed in j)                          */
+/*   y_i = (w_i >> 8) * 2^-23 - 1                                           */
+/*   R: accept iff sum_i y_i^2 < 1 (summed in i); z = (r1 y_1, r2 y_2, ...);*/
+/*      x_i = centre_i + sum_j H_ij z_j (summed in j); accept iff x in B    */
+/*   C: x_i = mid_i + half_i y_i; accept iff x in B and                     */
+/*      sqrt(sum_i (x_i - q0_i)^2) + sqrt(sum_i (x_i - qg_i)^2) <= c        */
 /* with the Householder reflection H = I - s w w^T, w = e_1 - a_1,          */
-/* s = 2 / (w^T w), a_1 = (q_g - q0)/c_min, H = I when w = 0.                */
+/* s = 2 / (w^T w), a_1 = (q_g - q0)/c_min, H = I when w = 0; the bounding  */
+/* half-extents e_i = sqrt(sum_j (H_ij r_j)^2) * (1 + 2^-10) (the factor    */
+/* keeps FP32 rounding from shaving the hyperspheroid's extreme points off),*/
+/* C = [max(lo, centre - e), min(hi, centre + e)], mid = (C_lo + C_hi)/2,   */
+/* half = (C_hi - C_lo)/2, |R| = prod_i (2 r_i) and |C| = prod_i (C_hi_i -  */
+/* C_lo_i) multiplied in i; C is used iff |C| < |R|.                        */
 /* Random words: key (seed lo, seed hi), counter                            */
 /*   (n, m, stage, (1 << 16) | (2 * attempt + block)), block = j div 4.     */
-/* After max_attempts rejections the draw falls back to a uniform box       */
-/* sample from attempt 0's words.                                           */
+/* Attempts are unbounded in the definition; the implementation stops after */
+/* OR_INFORMED_ATTEMPTS (at least 3 % of the proposals are accepted on      */
+/* every workload and bound measured, so the cap is reached with            */
+/* probability below 0.97^16384 < e^-499) and then returns the centre, a    */
+/* point of X_f(c) n B, with the count -1.                                  */
 /* ------------------------------------------------------------------------ */
+#define OR_INFORMED_ATTEMPTS 16384
+
 void or_informed_params(int d, const float *q0, const float *qg, float c, float *centre, float *H,
                         float *r1, float *r2, float *cmin_out)
 {
@@ -435,38 +456,81 @@ void or_informed_params(int d, const float *q0, const float *qg, float c, float 
         }
 }
 
-/* Returns the number of attempts used, or -1 for the box fallback. */
+/* Proposal choice of the uniform half: writes C's bounds and returns 1 when
+ * the clipped bounding box C is used, 0 for the frame box R. */
+int or_informed_proposal(int d, const float *lo, const float *hi, const float *centre, const float *H, float r1,
+                         float r2, float *c_lo, float *c_hi)
+{
+    float vol_r = 1.0f, vol_c = 1.0f;
+    for (int i = 0; i < d; ++i) {
+        float acc = 0.0f;
+        for (int j = 0; j < d; ++j) {
+            float t = H[i * d + j] * (j == 0 ? r1 : r2);
+            acc = acc + t * t;
+        }
+        float e = sqrtf(acc) * 1.0009765625f;
+        float a = centre[i] - e, b = centre[i] + e;
+        c_lo[i] = a > lo[i] ? a : lo[i];
+        c_hi[i] = b < hi[i] ? b : hi[i];
+        vol_r = vol_r * ((i == 0 ? r1 : r2) * 2.0f);
+        vol_c = vol_c * (c_hi[i] - c_lo[i]);
+    }
+    return vol_c < vol_r ? 1 : 0;
+}
+
+/* Returns the number of attempts used (0 for an unbounded draw), or -1 when
+ * the attempt cap was reached. */
 int or_sample_informed(int d, const float *lo, const float *hi, const float *q0, const float *qg, float c,
                        float penalty, uint64_t seed, uint64_t stage, uint32_t m, uint32_t n, int max_attempts,
                        float *out)
 {
     int bounded = !(isinf(c) || c >= penalty);
     if (bounded) {
-        float centre[16], H[256], r1, r2, cmin;
+        float centre[16], H[256], r1, r2, cmin, c_lo[16], c_hi[16], mid[16], half[16];
         or_informed_params(d, q0, qg, c, centre, H, &r1, &r2, &cmin);
+        int clipped = or_informed_proposal(d, lo, hi, centre, H, r1, r2, c_lo, c_hi);
+        for (int i = 0; i < d; ++i) {
+            mid[i] = (c_lo[i] + c_hi[i]) * 0.5f;
+            half[i] = (c_hi[i] - c_lo[i]) * 0.5f;
+        }
+        if (max_attempts > OR_INFORMED_ATTEMPTS) max_attempts = OR_INFORMED_ATTEMPTS;
         for (int a = 0; a < max_attempts; ++a) {
-            float y[16];
-            float s2 = 0.0f;
+            float y[16], x[16];
             for (int i = 0; i < d; ++i) {
                 uint32_t w[4];
                 or_words(seed, stage, 1u, n, m, (uint32_t)(2 * a + i / 4), w);
                 y[i] = (float)(w[i % 4] >> 8) * (1.0f / 8388608.0f) - 1.0f;
-                s2 = s2 + y[i] * y[i];
             }
-            if (!(s2 < 1.0f)) continue;
-            float z[16], x[16];
-            for (int i = 0; i < d; ++i) z[i] = (i == 0 ? r1 : r2) * y[i];
             int inside = 1;
-            for (int i = 0; i < d; ++i) {
-                float acc = 0.0f;
-                for (int j = 0; j < d; ++j) acc = acc + H[i * d + j] * z[j];
-                x[i] = centre[i] + acc;
-                if (!(x[i] >= lo[i] && x[i] <= hi[i])) inside = 0;
+            if (clipped) {
+                float s0 = 0.0f, s1 = 0.0f;
+                for (int i = 0; i < d; ++i) {
+                    x[i] = mid[i] + half[i] * y[i];
+                    if (!(x[i] >= lo[i] && x[i] <= hi[i])) inside = 0;
+                    float t0 = x[i] - q0[i], t1 = x[i] - qg[i];
+                    s0 = s0 + t0 * t0;
+                    s1 = s1 + t1 * t1;
+                }
+                if (!(sqrtf(s0) + sqrtf(s1) <= c)) inside = 0;
+            } else {
+                float s2 = 0.0f;
+                for (int i = 0; i < d; ++i) s2 = s2 + y[i] * y[i];
+                if (!(s2 < 1.0f)) continue;
+                float z[16];
+                for (int i = 0; i < d; ++i) z[i] = (i == 0 ? r1 : r2) * y[i];
+                for (int i = 0; i < d; ++i) {
+                    float acc = 0.0f;
+                    for (int j = 0; j < d; ++j) acc = acc + H[i * d + j] * z[j];
+                    x[i] = centre[i] + acc;
+                    if (!(x[i] >= lo[i] && x[i] <= hi[i])) inside = 0;
+                }
             }
             if (!inside) continue;
             for (int i = 0; i < d; ++i) out[i] = x[i];
             return a + 1;
         }
+        for (int i = 0; i < d; ++i) out[i] = centre[i];
+        return -1;
     }
     for (int i = 0; i < d; ++i) {
         uint32_t w[4];
@@ -475,7 +539,7 @@ int or_sample_informed(int d, const float *lo, const float *hi, const float *q0,
         double width = (double)(float)((double)hi[i] - (double)lo[i]);
         out[i] = (float)((double)lo[i] + u * width);
     }
-    return bounded ? -1 : 0;
+    return 0;
 }
 
 /* Coin of the sample mixture (Sec. III-A): heuristic half iff the top bit of

@@ -74,6 +74,136 @@ def test_informed_draws_arm_in_set_box_and_acceptance():
     assert rate <= p_ball * 1.3  # box rejections can only lower it
 
 
+def _ref_informed(w, c, n, seed):
+    """Uniform points of X_f(c) n box drawn by two constructions that share
+    nothing with the oracle's sampler: a uniform point of the hyperspheroid
+    (Gaussian direction, radius u^(1/d), an orthonormal frame from a QR
+    factorisation) kept when inside the box, or a uniform point of the box
+    kept when inside X_f(c); whichever accepts more often."""
+    g = np.random.default_rng(seed)
+    q0 = w["q0"].astype(np.float64)
+    qg = np.asarray(w["goals"], np.float64)[0]
+    lo, hi = w["lo"].astype(np.float64), w["hi"].astype(np.float64)
+    d = q0.size
+    cmin = np.linalg.norm(qg - q0)
+    a1 = (qg - q0) / cmin
+    F, _ = np.linalg.qr(np.column_stack([a1, g.normal(size=(d, d - 1))]))
+    F[:, 0] = a1
+    r = np.array([c / 2] + [math.sqrt(max(c * c - cmin * cmin, 0.0)) / 2] * (d - 1))
+
+    def ell(k):
+        z = g.normal(size=(k, d))
+        z /= np.linalg.norm(z, axis=1, keepdims=True)
+        z *= g.uniform(size=(k, 1)) ** (1.0 / d)
+        x = (q0 + qg) / 2 + (z * r) @ F.T
+        return x[np.all((x >= lo) & (x <= hi), axis=1)]
+
+    def box(k):
+        x = g.uniform(lo, hi, size=(k, d))
+        return x[np.linalg.norm(x - q0, axis=1) + np.linalg.norm(x - qg, axis=1) <= c]
+
+    gen = max((ell, box), key=lambda f: f(4000).shape[0])
+    out, have = [], 0
+    while have < n:
+        x = gen(200000)
+        out.append(x)
+        have += x.shape[0]
+    return np.concatenate(out)[:n]
+
+
+@pytest.mark.parametrize("name,scene", [("arm7", 0), ("arm7", 1), ("2d-small", 0)])
+@pytest.mark.parametrize("factor", [1.05, 2.0, 3.0, 4.0])
+def test_informed_draws_exact_uniform_in_both_regimes(name, scene, factor):
+    """The uniform half is exactly uniform on X_f(c) n box at every bound:
+    thin hyperspheroids inside the box (frame-box proposal) and ones reaching
+    far beyond it (clipped bounding box): every draw inside the set and the
+    box, no draw reaching the attempt cap, and the same law as an
+    independent construction (two-sample KS on each coordinate, on
+    |x - q0| + |x - q_g| and on the radius in the hyperspheroid's frame)."""
+    w = wl.make_workload(name, scene)
+    q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)
+    cmin = np.linalg.norm(qg - q0)
+    c = np.float32(cmin * factor)
+    n = 2500
+    draws = [OA.informed_draw(w, c, 13, 2, 3, k) for k in range(n)]
+    X = np.stack([x for x, _ in draws]).astype(np.float64)
+    att = np.array([a for _, a in draws])
+    assert np.all(att >= 1), "a draw reached the attempt cap"
+    assert att.mean() < 40  # at least ~3 % of the proposals accepted
+    s = np.linalg.norm(X - q0, axis=1) + np.linalg.norm(X - qg, axis=1)
+    assert np.all(s <= float(c) * (1 + 1e-6))
+    assert np.all(X >= w["lo"]) and np.all(X <= w["hi"])
+    clipped, _, _ = OA.informed_proposal(w, c)
+    assert clipped == (factor > 1.5)  # the regimes the workloads reach
+    R = _ref_informed(w, float(c), 20000, 1000 + scene)
+    Y = ellipsoid_coords(w, float(c), X)
+    Yr = ellipsoid_coords(w, float(c), R)
+    sr = np.linalg.norm(R - q0, axis=1) + np.linalg.norm(R - qg, axis=1)
+    pv = [stats.ks_2samp(X[:, i], R[:, i]).pvalue for i in range(X.shape[1])]
+    pv.append(stats.ks_2samp(s, sr).pvalue)
+    pv.append(stats.ks_2samp(np.linalg.norm(Y, axis=1), np.linalg.norm(Yr, axis=1)).pvalue)
+    assert min(pv) > 1e-4, pv
+
+
+def test_informed_radius_law_inside_the_box():
+    """A hyperspheroid inside the box: the draws are uniform in it, so the
+    radius in its frame follows |y|^d ~ U(0, 1) (one-sample KS)."""
+    w = wl.make_workload("2d-small", 1)
+    c = np.float32(26.0)  # c_min = 25.456; the ellipse stays inside the box
+    clipped, c_lo, c_hi = OA.informed_proposal(w, c)
+    assert not clipped
+    X = np.stack([OA.informed_draw(w, c, 21, 0, 0, k)[0] for k in range(3000)])
+    rad = np.linalg.norm(ellipsoid_coords(w, float(c), X), axis=1)
+    assert rad.max() <= 1 + 1e-5
+    assert stats.kstest(rad ** 2, "uniform").pvalue > 1e-3
+
+
+def test_informed_clipped_box_covers_the_set():
+    """The clipped bounding box holds every point of X_f(c) n box: the
+    extreme points of the hyperspheroid along each axis (closed form:
+    centre_i +- sqrt(sum_j F_ij^2 r_j^2)) clipped to the box lie inside it."""
+    for name, scene, f in (("arm7", 0, 1.5), ("arm7", 2, 1.2), ("2d-small", 0, 1.3), ("3d-point", 1, 1.1)):
+        w = wl.make_workload(name, scene)
+        q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)
+        cmin = np.linalg.norm(qg - q0)
+        c = float(np.float32(cmin * f))
+        _, c_lo, c_hi = OA.informed_proposal(w, np.float32(c))
+        d = q0.size
+        r = np.array([c / 2] + [math.sqrt(c * c - cmin * cmin) / 2] * (d - 1))
+        a1 = (qg - q0) / cmin
+        F, _ = np.linalg.qr(np.column_stack([a1, np.eye(d)[:, :d - 1] + 1e-3]))
+        F[:, 0] = a1
+        e = np.sqrt(((F * r) ** 2).sum(axis=1))
+        lo = np.maximum(w["lo"], (q0 + qg) / 2 - e)
+        hi = np.minimum(w["hi"], (q0 + qg) / 2 + e)
+        assert np.all(c_lo <= lo) and np.all(c_hi >= hi)
+        assert np.all(c_lo >= w["lo"]) and np.all(c_hi <= w["hi"])
+
+
+def test_informed_attempt_cap_returns_the_centre():
+    """Past the attempt cap the draw is the hyperspheroid's centre (a point
+    of the set) with the count -1; with one allowed attempt at a thin bound
+    in 7 dimensions the first ball test fails for most slots."""
+    w = wl.make_workload("arm7", 0)
+    d = 7
+    q0, qg = oracle._f32(w["q0"]), oracle._f32(w["goals"][0])
+    lo, hi = oracle._f32(w["lo"]), oracle._f32(w["hi"])
+    cmin = float(np.linalg.norm(qg.astype(np.float64) - q0))
+    c = float(np.float32(cmin * 1.05))
+    capped = 0
+    for n in range(40):
+        out = np.zeros(d, np.float32)
+        a = oracle.lib().or_sample_informed(d, oracle._ptr(lo, oracle._fp), oracle._ptr(hi, oracle._fp),
+                                            oracle._ptr(q0, oracle._fp), oracle._ptr(qg, oracle._fp), c, 1e3, 3, 0,
+                                            0, n, 1, oracle._ptr(out, oracle._fp))
+        if a == -1:
+            capped += 1
+            np.testing.assert_array_equal(out, (q0 + qg) * np.float32(0.5))
+        else:
+            assert a == 1
+    assert capped > 20
+
+
 def test_unbounded_draw_is_box_sample():
     w = wl.make_workload("2d-small", 0)
     x, a = OA.informed_draw(w, None, 5, 2, 1, 9)
