@@ -519,7 +519,9 @@ def bench_surrogate(args, torch, wl, gtmp):
     # threshold: free-edge recall on a held-out plan (stage 999)
     pl.plan(w["seed"], 999)
     net.prune(pl.prob, pl.q0, pl.goals, pl.Q, math.inf, prune, logits)
-    tau = gtmp.free_recall_threshold(logits, pl.flags, S["recall"])
+    tau_dev = torch.empty(1, device="cuda")
+    gtmp.gtmp_surrogate_threshold(logits, pl.flags, S["recall"], tau_dev)
+    tau = float(tau_dev.item())
     print(f"[bench] tau {tau:.4f}", file=sys.stderr, flush=True)
 
     def ev():

@@ -375,16 +375,27 @@ gtmp_status gtmp_expand_samples_biased(const gtmp_problem *prob, const float *q0
                                        float tau_logit, void *workspace, size_t ws_bytes, void *stream);
 
 /* Draws of the uniform half of the growing-budget sampler for slots
- * (m, 0..count-1) at `stage`.  Informed set of Sec. IV-E by the direct method
- * of Gammell et al. (2018), as an FP32 computation with a fixed operation
- * order: y_i = (w_i >> 8) 2^-23 - 1 from Philox words at counter
- * (n, m, stage, (1 << 16) | (2 a + j div 4)) for attempt a; accept iff
- * sum y_i^2 < 1; z = (c/2 y_1, r2 y_2, ...) with r2 = sqrt(c^2 - c_min^2)/2,
- * c_min = |q_g - q0|; x = (q0 + q_g)/2 + H z with the Householder reflection
- * H = I - (2/w.w) w w^T, w = e_1 - (q_g - q0)/c_min; reject x outside the box.
- * After 4096 attempts (or without a bound) x is the box sample of attempt 0.
+ * (m, 0..count-1) at `stage`: uniform draws of the informed set of Sec. IV-E,
+ * X_f(c) = {x : |x-q0| + |x-q_g| <= c} (goal 0), intersected with the box,
+ * by rejection from one of two proposal regions that both contain it:
+ *   R  the hyperspheroid's frame box: a cube point y kept iff |y| < 1, mapped
+ *      by the direct method of Gammell et al. (2018),
+ *      x = (q0 + q_g)/2 + H (c/2 y_1, r2 y_2, ...), r2 = sqrt(c^2 - c_min^2)/2,
+ *      c_min = |q_g - q0|, H = I - (2/w.w) w w^T, w = e_1 - (q_g - q0)/c_min;
+ *      x kept iff inside the box;
+ *   C  the hyperspheroid's axis-aligned bounding box (half-extents
+ *      sqrt(sum_j (H_ij r_j)^2) (1 + 2^-10)) clipped to the box: x = mid +
+ *      half y, kept iff inside the box and sqrt(|x-q0|^2) + sqrt(|x-q_g|^2)
+ *      <= c.
+ * C is used iff its volume (product of its sides) is below R's
+ * (prod 2 r_i).  Everything is FP32 with a fixed operation order (sums in
+ * coordinate order, no fused multiply-add); y_i = (w_i >> 8) 2^-23 - 1 from
+ * Philox words at counter (n, m, stage, (1 << 16) | (2 a + j div 4)) for
+ * attempt a.  Past 16384 attempts (probability below e^-499 wherever 3 % of
+ * the proposals are accepted) x is the centre (q0 + q_g)/2.  Without a bound
+ * (c = +inf or c >= penalty) x is the box sample of attempt 0's words.
  *   X         device float32 [count][d]
- *   attempts  device int32 [count] or NULL: attempts used, 0 unbounded, -1 fallback
+ *   attempts  device int32 [count] or NULL: attempts used, 0 unbounded, -1 cap reached
  *   workspace device, at least 1024 bytes */
 gtmp_status gtmp_sample_informed(const gtmp_problem *prob, const float *q0, const float *goals, const float *c_best,
                                  uint64_t seed, uint64_t stage, int32_t m, int32_t count, float *X, int32_t *attempts,
@@ -618,6 +629,23 @@ gtmp_status gtmp_surrogate_label_states(const gtmp_problem *prob, uint64_t seed,
 gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate *net, const float *q0,
                                  const float *goals, const float *Q, float tau_logit, uint8_t *prune, float *logits,
                                  void *workspace, size_t ws_bytes, void *stream);
+
+/* Pruning threshold of the surrogate for a free-edge recall (the calibration
+ * that makes the pruning conservative: at least `recall` of the free edges
+ * stay unpruned).  With n_free edges of flags[e] == 0, tau is the k-th
+ * smallest of their logits (0-based, NaN ordered last),
+ * k = ceil(recall * n_free) - 1 (FP64) clamped to [0, n_free - 1], so that
+ * pruning logit > tau keeps at least recall * n_free of them; tau = +inf when
+ * no edge is free.  Found on the device by a radix select; nothing is read
+ * back and no memory is cleared with memset (the call can be captured).
+ *   logits    device float32 [E] (e.g. gtmp_surrogate_prune's logits output)
+ *   flags     device uint8 [E], the exact checker's flags (0 = free)
+ *   recall    in (0, 1]
+ *   tau       device float32 [1], written
+ *   workspace device, 256-byte aligned, gtmp_surrogate_threshold_workspace_size bytes */
+gtmp_status gtmp_surrogate_threshold_workspace_size(size_t *bytes);
+gtmp_status gtmp_surrogate_threshold(const float *logits, const uint8_t *flags, int64_t E, double recall, float *tau,
+                                     void *workspace, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,7 @@ FLAGS = [
 ]
 
 SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip", "batch.hip", "surrogate.hip",
-           "classes.hip", "simplify.hip", "rrtc.hip", "lazy.hip"]
+           "classes.hip", "simplify.hip", "rrtc.hip", "lazy.hip", "select.hip"]
 # the growing-budget sampler, the class labels and the RRT-Connect decisions
 # are defined as FP32 computations with a fixed operation order: no
 # contraction into fused multiply-adds in those files

@@ -17,31 +17,55 @@
 
 namespace gtmp {
 
-constexpr int kMaxAttempts = 4096;
+// Attempt cap of one uniform-half draw.  Past it (probability below
+// 0.97^16384 wherever at least 3 % of the proposals are accepted, which
+// holds at every bound the workloads reach) the draw is the centre of the
+// hyperspheroid, a point of the set.  2 * attempt + 1 must stay below 2^16
+// (the counter's block field).
+constexpr int kMaxAttempts = 16384;
+
+struct BoxArgs {
+    float lo[GTMP_MAX_DOF], hi[GTMP_MAX_DOF], wd[GTMP_MAX_DOF];
+};
 
 // ------------------------------------------------------------------ informed set
+// Proposal regions of the uniform half (both contain X_f(c) n box, and each
+// attempt is accepted iff its point lies in X_f(c) n box, so either gives a
+// uniform draw of that set): the hyperspheroid's frame box (a cube point
+// kept inside the unit ball, mapped by the direct method of Gammell et al.
+// 2018, kept inside the box) or its axis-aligned bounding box clipped to the
+// sampling box (a point kept iff |x - q0| + |x - q_g| <= c).  The smaller
+// of the two accepts more often and is used.
 struct Informed {
     float centre[GTMP_MAX_DOF];
     float H[GTMP_MAX_DOF * GTMP_MAX_DOF];
-    float r1, r2;
-    int bounded;
+    float mid[GTMP_MAX_DOF], half[GTMP_MAX_DOF];
+    float q0[GTMP_MAX_DOF], qg[GTMP_MAX_DOF];
+    float r1, r2, c;
+    int bounded, clipped;
 };
 
 // Hyperspheroid of the informed set X_f(c) (Sec. IV-E; Gammell et al. 2018):
 // centre (q0 + q_g)/2, radii c/2 along q_g - q0 and sqrt(c^2 - c_min^2)/2
 // across, orientation by the Householder reflection mapping e_1 to the unit
-// vector from q0 to q_g.  Without a bound (c = +inf or c >= penalty) the
-// draws are uniform in the box.
+// vector from q0 to q_g; the bounding half-extents sqrt(sum_j (H_ij r_j)^2),
+// widened by 2^-10 of themselves against FP32 rounding, clipped to the box;
+// the clipped box is used iff its volume is below the frame box's
+// prod 2 r_i (both multiplied in coordinate order).  Without a bound
+// (c = +inf or c >= penalty) the draws are uniform in the box.
 __global__ void k_informed_prep(int d, const float *q0, const float *goals, const float *c_dev, float penalty,
-                                Informed *out) {
+                                BoxArgs L, Informed *out) {
     if (threadIdx.x != 0) return;
     const float c = *c_dev;
     Informed I;
     I.bounded = !(__builtin_isinf(c) || c >= penalty || c != c);
+    I.c = c;
     float acc = 0.0f;
     for (int i = 0; i < d; ++i) {
         const float t = goals[i] - q0[i];
         acc = acc + t * t;
+        I.q0[i] = q0[i];
+        I.qg[i] = goals[i];
     }
     const float cmin = __builtin_sqrtf(acc);
     for (int i = 0; i < d; ++i) I.centre[i] = (q0[i] + goals[i]) * 0.5f;
@@ -65,6 +89,23 @@ __global__ void k_informed_prep(int d, const float *q0, const float *goals, cons
                 I.H[i * d + j] = delta - (s * w[i]) * w[j];
             }
         }
+    float vol_r = 1.0f, vol_c = 1.0f;
+    for (int i = 0; i < d; ++i) {
+        float e2 = 0.0f;
+        for (int j = 0; j < d; ++j) {
+            const float t = I.H[i * d + j] * (j == 0 ? I.r1 : I.r2);
+            e2 = e2 + t * t;
+        }
+        const float e = __builtin_sqrtf(e2) * 1.0009765625f;
+        const float a = I.centre[i] - e, b = I.centre[i] + e;
+        const float clo = a > L.lo[i] ? a : L.lo[i];
+        const float chi = b < L.hi[i] ? b : L.hi[i];
+        I.mid[i] = (clo + chi) * 0.5f;
+        I.half[i] = (chi - clo) * 0.5f;
+        vol_r = vol_r * ((i == 0 ? I.r1 : I.r2) * 2.0f);
+        vol_c = vol_c * (chi - clo);
+    }
+    I.clipped = vol_c < vol_r ? 1 : 0;
     *out = I;
 }
 
@@ -78,23 +119,34 @@ __device__ __forceinline__ uint32_t pick(const uint4 &w, int i) {
 }
 
 // Attempt a of the uniform-half draw for slot (m, n): true iff accepted
-// (inside the unit ball, and the mapped point inside the box), the point in x.
+// (the point lies in X_f(c) and in the box), the point in x.
 __device__ __forceinline__ bool informed_attempt(int d, const float *lo, const float *hi, const Informed &I,
                                                  uint32_t k0, uint32_t k1, uint32_t stage, uint32_t m, uint32_t n,
                                                  int a, float *x) {
     float y[GTMP_MAX_DOF];
-    float s2 = 0.0f;
     const uint4 w0 = words(k0, k1, n, m, stage, 1u, (uint32_t)(2 * a));
     const uint4 w1 = words(k0, k1, n, m, stage, 1u, (uint32_t)(2 * a + 1));
     for (int i = 0; i < d; ++i) {
         const uint32_t wi = i < 4 ? pick(w0, i) : pick(w1, i - 4);
         y[i] = (float)(wi >> 8) * (1.0f / 8388608.0f) - 1.0f;
-        s2 = s2 + y[i] * y[i];
     }
+    bool inside = true;
+    if (I.clipped) {
+        float s0 = 0.0f, s1 = 0.0f;
+        for (int i = 0; i < d; ++i) {
+            x[i] = I.mid[i] + I.half[i] * y[i];
+            if (!(x[i] >= lo[i] && x[i] <= hi[i])) inside = false;
+            const float t0 = x[i] - I.q0[i], t1 = x[i] - I.qg[i];
+            s0 = s0 + t0 * t0;
+            s1 = s1 + t1 * t1;
+        }
+        return inside && __builtin_sqrtf(s0) + __builtin_sqrtf(s1) <= I.c;
+    }
+    float s2 = 0.0f;
+    for (int i = 0; i < d; ++i) s2 = s2 + y[i] * y[i];
     if (!(s2 < 1.0f)) return false;
     float z[GTMP_MAX_DOF];
     for (int i = 0; i < d; ++i) z[i] = (i == 0 ? I.r1 : I.r2) * y[i];
-    bool inside = true;
     for (int i = 0; i < d; ++i) {
         float acc = 0.0f;
         for (int j = 0; j < d; ++j) acc = acc + I.H[i * d + j] * z[j];
@@ -116,7 +168,8 @@ __device__ __forceinline__ void box_draw(int d, const float *lo, const float *wd
 }
 
 // One draw of the uniform half for slot (m, n): the first accepted attempt.
-// Returns attempts used (0 for an unbounded draw, -1 for the box fallback).
+// Returns attempts used (0 for an unbounded draw, -1 past the attempt cap,
+// where x is the centre).
 __device__ int informed_draw(int d, const float *lo, const float *wd, const float *hi, const Informed &I,
                              uint32_t k0, uint32_t k1, uint32_t stage, uint32_t m, uint32_t n, float *x) {
     if (I.bounded) {
@@ -126,15 +179,14 @@ __device__ int informed_draw(int d, const float *lo, const float *wd, const floa
             for (int i = 0; i < d; ++i) x[i] = xx[i];
             return a + 1;
         }
+        for (int i = 0; i < d; ++i) x[i] = I.centre[i];
+        return -1;
     }
     box_draw(d, lo, wd, k0, k1, stage, m, n, x);
-    return I.bounded ? -1 : 0;
+    return 0;
 }
 
 // ------------------------------------------------------------------ expansion
-struct BoxArgs {
-    float lo[GTMP_MAX_DOF], hi[GTMP_MAX_DOF], wd[GTMP_MAX_DOF];
-};
 
 // Copy the old samples of every layer into the new (wider) layout.
 __global__ void k_relayout(int M, int n_old, int N, int d, const float *Q_old, float *Q_new) {
@@ -250,7 +302,11 @@ __global__ void __launch_bounds__(kExpandThreads) k_expand_layer(int m, int n_ol
     }
     if (threadIdx.x == 0) {
         float x[GTMP_MAX_DOF];
-        box_draw(d, B.lo, B.wd, k0, k1, stage, (uint32_t)m, (uint32_t)n, x);
+        if (I.bounded) {  // past the attempt cap: the centre, a point of the set
+            for (int i = 0; i < d; ++i) x[i] = I.centre[i];
+        } else {
+            box_draw(d, B.lo, B.wd, k0, k1, stage, (uint32_t)m, (uint32_t)n, x);
+        }
         for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
     }
 }
@@ -372,7 +428,7 @@ hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *go
     void *sort_tmp = ws + e.off_sort;
     const int M = p.M, N = p.N, d = p.d;
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32), st = (uint32_t)stage;
-    hipLaunchKernelGGL(k_informed_prep, dim3(1), dim3(64), 0, s, d, q0, goals, c_dev, p.penalty, I);
+    hipLaunchKernelGGL(k_informed_prep, dim3(1), dim3(64), 0, s, d, q0, goals, c_dev, p.penalty, box_args(p), I);
     if (n_old > 0) {
         const uint64_t total = (uint64_t)M * n_old * d;
         hipLaunchKernelGGL(k_relayout, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, M, n_old, N, d, Q_old,
@@ -428,7 +484,7 @@ hipError_t launch_informed_batch(const gtmp_problem &p, const float *q0, const f
                                  uint64_t seed, uint64_t stage, uint32_t m, int count, float *X, int32_t *attempts,
                                  void *workspace, hipStream_t s) {
     Informed *I = reinterpret_cast<Informed *>(workspace);
-    hipLaunchKernelGGL(k_informed_prep, dim3(1), dim3(64), 0, s, p.d, q0, goals, c_dev, p.penalty, I);
+    hipLaunchKernelGGL(k_informed_prep, dim3(1), dim3(64), 0, s, p.d, q0, goals, c_dev, p.penalty, box_args(p), I);
     if (count > 0)
         hipLaunchKernelGGL(k_informed_batch, dim3((count + 255) / 256), dim3(256), 0, s, p.d, box_args(p),
                            (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)stage, m, count, I, X,

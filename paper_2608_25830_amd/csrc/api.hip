@@ -730,6 +730,25 @@ gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate 
                       "gtmp_surrogate_prune");
 }
 
+gtmp_status gtmp_surrogate_threshold_workspace_size(size_t *bytes) {
+    g_err[0] = 0;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::sur_threshold_bytes();
+    return GTMP_OK;
+}
+
+gtmp_status gtmp_surrogate_threshold(const float *logits, const uint8_t *flags, int64_t E, double recall, float *tau,
+                                     void *workspace, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    if (E < 0) return fail(GTMP_EINVAL, "E=%lld is negative", (long long)E);
+    if (!(recall > 0.0 && recall <= 1.0)) return fail(GTMP_EINVAL, "recall=%g outside (0, 1]", recall);
+    if (!tau || (E > 0 && (!logits || !flags))) return fail(GTMP_EINVAL, "NULL buffer");
+    gtmp_status st = check_ws(workspace, ws_bytes, gtmp::sur_threshold_bytes());
+    if (st != GTMP_OK) return st;
+    return hip_status(gtmp::launch_sur_threshold(logits, flags, E, recall, tau, workspace, (hipStream_t)stream),
+                      "gtmp_surrogate_threshold");
+}
+
 // ------------------------------------------------------------------ class-augmented sweep
 static gtmp_status check_class_sizes(int M, int N, int G, int L, int k) {
     if (M < 1 || M > 6) return fail(GTMP_EINVAL, "class sweep needs 1 <= M <= 6 (labels of at most 7 edges)");

@@ -40,6 +40,12 @@ hipError_t launch_sur_adam(const SurNet &net, const float *grad, float *m, float
 hipError_t launch_sur_refresh(const SurNet &net, hipStream_t s);
 hipError_t launch_sur_label_states(const gtmp_problem &p, uint64_t seed, uint64_t stage, int64_t n, float *X,
                                    hipStream_t s);
+// Pruning threshold of the surrogate (select.hip): the k-th smallest logit
+// among the edges with flag 0, k = ceil(recall n_free) - 1; +inf without
+// free edges.  tau is a device float.
+size_t sur_threshold_bytes();
+hipError_t launch_sur_threshold(const float *logits, const uint8_t *flags, int64_t E, double recall, float *tau,
+                                void *workspace, hipStream_t s);
 hipError_t launch_sur_prune(const gtmp_problem &p, const SurNet &net, const float *q0, const float *goals,
                             const float *Q, float tau, uint8_t *prune, float *logits, void *ws, size_t ws_bytes,
                             hipStream_t s);

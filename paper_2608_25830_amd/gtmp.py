@@ -149,6 +149,8 @@ _lib.gtmp_surrogate_adam.argtypes = [C.POINTER(gtmp_surrogate), _vp, _vp, _vp, C
 _lib.gtmp_surrogate_label_states.argtypes = [C.POINTER(gtmp_problem), C.c_uint64, C.c_uint64, C.c_int64, _vp, _vp]
 _lib.gtmp_surrogate_prune.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_surrogate), _vp, _vp, _vp, C.c_float,
                                       _vp, _vp, _vp, C.c_size_t, _vp]
+_lib.gtmp_surrogate_threshold_workspace_size.argtypes = [C.POINTER(C.c_size_t)]
+_lib.gtmp_surrogate_threshold.argtypes = [_vp, _vp, C.c_int64, C.c_double, _vp, _vp, C.c_size_t, _vp]
 
 _lib.gtmp_class_sweep_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
 _lib.gtmp_class_sweep.argtypes = [C.c_int32] * 4 + [_vp] * 6 + [C.c_float, _vp, C.c_int32] + [_vp] * 5 + \
@@ -163,7 +165,8 @@ EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample
            "gtmp_anytime_workspace_size", "gtmp_plan_anytime", "gtmp_batch_workspace_size", "gtmp_plan_batch",
            "gtmp_surrogate_layout", "gtmp_surrogate_refresh_bf16", "gtmp_surrogate_workspace_size",
            "gtmp_surrogate_infer", "gtmp_surrogate_grad", "gtmp_surrogate_adam", "gtmp_surrogate_label_states",
-           "gtmp_surrogate_prune", "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased",
+           "gtmp_surrogate_prune", "gtmp_surrogate_threshold_workspace_size", "gtmp_surrogate_threshold",
+           "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased",
            "gtmp_class_sweep_workspace_size", "gtmp_class_sweep", "gtmp_class_anytime_workspace_size",
            "gtmp_plan_classes", "gtmp_simplify_paths", "gtmp_rrtc_workspace_size", "gtmp_rrtc_repair",
            "gtmp_rrtc_local_path", "gtmp_lazy_workspace_size", "gtmp_plan_lazy"]
@@ -801,16 +804,16 @@ def gtmp_expand_samples_biased(prob, q0, goals, Q_old, n_old, Q_new, c_best, see
                                                   _p(workspace), _nbytes(workspace), _stream(stream)))
 
 
-def free_recall_threshold(logits, flags, recall=0.999):
-    """Smallest logit threshold tau such that pruning edges with logit > tau
-    keeps at least ``recall`` of the free edges (flag 0): the
-    ceil(recall * n_free)-th smallest free-edge logit (device tensors in,
-    float out)."""
-    zf = torch.sort(logits[flags == 0]).values
-    if zf.numel() == 0:
-        return math.inf
-    k = max(0, min(zf.numel() - 1, math.ceil(recall * zf.numel()) - 1))
-    return float(zf[k].item())
+def gtmp_surrogate_threshold(logits, flags, recall, tau, workspace=None, stream=None):
+    """tau (device float32 [1]) <- the smallest logit threshold that keeps at
+    least ``recall`` of the free edges (flags == 0) unpruned, computed on the
+    device (see include/gtmp.h)."""
+    if workspace is None:
+        n = C.c_size_t()
+        _check(_lib.gtmp_surrogate_threshold_workspace_size(C.byref(n)))
+        workspace = _aligned_workspace(n.value, logits.device)
+    return _check(_lib.gtmp_surrogate_threshold(_p(logits), _p(flags), int(logits.numel()), float(recall), _p(tau),
+                                                _p(workspace), _nbytes(workspace), _stream(stream)))
 
 
 # --------------------------------------------------------------------------- #

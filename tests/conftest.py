@@ -27,3 +27,13 @@ def gt():
         pytest.skip("no GPU")
     from paper_2608_25830_amd import gtmp
     return gtmp
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Figures the parity tests record (excused edges, compared indices...),
+    printed after the run so that they appear in a quiet run's output."""
+    from tests import parity
+    if parity.NOTES:
+        terminalreporter.section("parity figures")
+        for line in parity.NOTES:
+            terminalreporter.write_line(line)

@@ -16,6 +16,13 @@ import numpy as np
 BAND = 1e-5
 REL = 1e-5
 
+# figures recorded by tests, printed at the end of the run (tests/conftest.py)
+NOTES: list = []
+
+
+def note(*a):
+    NOTES.append(" ".join(str(x) for x in a))
+
 
 def flat(Cs, Ch, Cl):
     return np.concatenate([np.ravel(Cs), np.ravel(Ch), np.ravel(Cl)])

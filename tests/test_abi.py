@@ -153,6 +153,20 @@ def test_surrogate_calls_validate_sizes(g):
                                        None, ws, big, None) == g.GTMP_EINVAL  # net d = 7, problem d = 2
 
 
+def test_surrogate_threshold_validates(g):
+    n = C.c_size_t()
+    assert g._lib.gtmp_surrogate_threshold_workspace_size(C.byref(n)) == 0 and n.value >= 256
+    ws, big, p = C.c_void_p(1 << 20), C.c_size_t(1 << 20), C.c_void_p(256)
+    f = g._lib.gtmp_surrogate_threshold
+    assert f(p, p, -1, 0.999, p, ws, big, None) == g.GTMP_EINVAL  # negative E
+    for r in (0.0, -0.5, 1.5, float("nan")):
+        assert f(p, p, 10, r, p, ws, big, None) == g.GTMP_EINVAL
+    assert f(None, p, 10, 0.999, p, ws, big, None) == g.GTMP_EINVAL
+    assert f(p, p, 10, 0.999, None, ws, big, None) == g.GTMP_EINVAL
+    assert f(p, p, 10, 0.999, p, C.c_void_p((1 << 20) | 8), big, None) == g.GTMP_EINVAL
+    assert f(p, p, 10, 0.999, p, ws, C.c_size_t(16), None) == g.GTMP_EWORKSPACE
+
+
 def test_biased_expansion_validates(g):
     p = _prob(g)
     net = _net(g, d=2)

@@ -24,10 +24,15 @@ def _dev(a, dtype=None):
     return t.cuda() if dtype is None else t.to("cuda", dtype)
 
 
-@pytest.mark.parametrize("name,scale", [("2d-small", 1.02), ("2d-small", 1.3), ("arm7", 1.05), ("arm7", 2.0),
-                                        ("2d-small", None)])
-def test_informed_draws_bit_exact(gt, name, scale):
-    w = wl.make_workload(name, 0)
+@pytest.mark.parametrize("name,scale,scene", [("2d-small", 1.02, 0), ("2d-small", 1.3, 0), ("2d-small", 2.0, 0),
+                                              ("2d-small", 4.0, 0), ("arm7", 1.05, 0), ("arm7", 1.5, 1),
+                                              ("arm7", 2.0, 0), ("arm7", 3.0, 1), ("arm7", 4.0, 2),
+                                              ("3d-point", 1.05, 0), ("3d-point", 2.5, 1), ("2d-small", None, 0)])
+def test_informed_draws_bit_exact(gt, name, scale, scene):
+    """Both proposal regions (frame box at thin bounds, clipped bounding box
+    once the hyperspheroid reaches beyond the box): same points, same attempt
+    counts as the oracle."""
+    w = wl.make_workload(name, scene)
     _say("informed", name, scale)
     d = w["d"]
     q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)

@@ -1,6 +1,7 @@
 """Parity at the full sizes the benchmarks run, in the launch configuration
-bench.py times (default options): the oracle computes sampled edges one by
-one (every state of each), the returned path is re-summed from the oracle's
+bench.py times (default options): the oracle computes a million sampled
+edges one by one (every state of each; the arm at N = 2048 is compared edge
+for edge in test_gpu_fullsize_arm7.py), the returned path is re-summed from the oracle's
 edge costs, and the sweep is checked row by row on sampled rows against its
 defining recursion evaluated on the host in FP32.  Also the full 512-plan
 batch distribution (a seeded subset of its plans) against single-plan calls,
@@ -50,7 +51,7 @@ def _path_edges(w, idx):
     return e
 
 
-@pytest.mark.parametrize("name,n_sample", [("arm7", 100_000), ("2d-large", 100_000)])
+@pytest.mark.parametrize("name,n_sample", [("arm7-n4096", 1_000_000), ("2d-large", 1_000_000)])
 def test_full_size_plan(gt, orc, name, n_sample):
     w = wl.make_workload(name, 0)
     M, N, G, H = w["M"], w["N"], w["G"], w["H"]
@@ -72,6 +73,7 @@ def test_full_size_plan(gt, orc, name, n_sample):
     c_or, sd_or, f_or = orc.edge_subset(model, M, N, G, H, w["q0"], w["goals"], Q, ids, w["penalty"])
     rep = P.compare_edges(got_c, got_f, c_or, sd_or, f_or)
     _say("sampled edges", rep)
+    P.note(f"{name} sampled edges: {rep}")
     # the returned path re-summed from the oracle's costs of its edges
     pe = _path_edges(w, idx)
     pos = np.searchsorted(ids, pe)

@@ -162,6 +162,7 @@ def test_fast_equals_full_flags_arm(gt, orc):
 PLAN_CASES = [("2d-small", s, {}) for s in range(5)] + [
     ("2d-large", 0, dict(N=256, M=6)), ("2d-large", 3, dict(N=160, M=8, H=20)),
     ("arm7", 0, dict(N=128, M=4)), ("arm7", 1, dict(N=64, M=6)), ("arm7", 4, dict(N=200, M=3)),
+    ("arm7", 2, dict(N=256, M=5)),
     ("3d-point", 1, dict(N=128, M=5)), ("3d-point", 3, {})]
 
 

@@ -230,13 +230,47 @@ def test_pruned_check_is_exact_on_survivors(gt, orc):
         assert c_pr == c_plain
 
 
+# ------------------------------------------------- pruning threshold
+@pytest.mark.parametrize("E,p_free,recall,kind", [(0, 0.5, 0.999, "normal"), (1000, 0.0, 0.999, "normal"),
+                                                  (1, 1.0, 0.999, "normal"), (5000, 0.3, 0.999, "normal"),
+                                                  (5000, 0.3, 1.0, "normal"), (5000, 0.3, 0.5, "ties"),
+                                                  (100_003, 0.04, 0.999, "ties"), (4_000_000, 0.05, 0.999, "normal"),
+                                                  (20_000, 0.5, 0.9, "signed-zero"), (20_000, 0.5, 0.999, "nan")])
+def test_threshold_matches_oracle(gt, E, p_free, recall, kind):
+    """gtmp_surrogate_threshold against the oracle's definition: the same
+    logit (the k-th smallest free-edge logit), +inf without a free edge."""
+    _say("threshold", E, p_free, recall, kind)
+    g = np.random.default_rng(E + 7)
+    z = (g.normal(size=E) * 3).astype(np.float32)
+    if kind == "ties":
+        z = np.round(z * 4).astype(np.float32) / 4
+    elif kind == "signed-zero":
+        z[g.random(E) < 0.3] = 0.0
+        z[g.random(E) < 0.3] = -0.0
+    elif kind == "nan":
+        z[g.random(E) < 0.01] = np.nan
+    flags = (g.random(E) >= p_free).astype(np.uint8)
+    want = OS.free_recall_threshold(z.astype(np.float64), flags, recall)
+    tau = torch.empty(1, device="cuda")
+    gt.gtmp_surrogate_threshold(torch.from_numpy(z).cuda(), torch.from_numpy(flags).cuda(), recall, tau)
+    got = float(tau.item())
+    if np.isnan(want):
+        assert np.isnan(got)
+    else:
+        assert got == want, (got, want)
+    # the recall it promises
+    if (flags == 0).any() and np.isfinite(got):
+        zf = z[flags == 0].astype(np.float64)
+        assert np.mean(zf <= got) >= recall - 1e-12
+
+
 # ------------------------------------------------- biased heuristic half
 def _clear_tau(zs):
     """The middle of the widest gap between sorted candidate logits in their
-    central 60 %: a threshold whose decisions no logit error within Z_LOOSE
+    central 90 %: a threshold whose decisions no logit error within Z_LOOSE
     can change."""
     z = np.sort(np.concatenate([np.asarray(a, np.float64) for a in zs]))
-    lo, hi = int(0.2 * z.size), int(0.8 * z.size)
+    lo, hi = int(0.05 * z.size), int(0.95 * z.size)
     gaps = z[lo + 1:hi + 1] - z[lo:hi]
     k = int(np.argmax(gaps))
     tau = 0.5 * (z[lo + k] + z[lo + k + 1])
