@@ -184,6 +184,25 @@ gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *rob
                                  void *workspace, size_t ws_bytes, const gtmp_edge_opts *opts,
                                  void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * edge check as gtmp_edge_check_cost, same kernels and results, with its
+ * scratch taken from a static device array of GTMP_NOALLOC_SCRATCH_BYTES
+ * (32 MiB) that the library holds on every GPU it runs on until the process
+ * ends.  The call allocates and frees nothing; the caller still owns the
+ * inputs and outputs.  Problems whose gtmp_edge_check_workspace_size exceeds
+ * GTMP_NOALLOC_SCRATCH_BYTES are rejected with GTMP_EINVAL (the arm with
+ * M = 8, N = 2048 needs 30.4 MB and fits).  `stream` must belong to the
+ * current device.  Every call on one GPU shares that GPU's array and leaves
+ * its contents behind: calls that overlap on one GPU (concurrent streams,
+ * threads) race and must be serialised by the caller. */
+#define GTMP_NOALLOC_SCRATCH_BYTES (32u << 20)
+gtmp_status gtmp_edge_check_cost_noalloc(const gtmp_problem *prob, const gtmp_robot *robot,
+                                         const gtmp_scene *scene, const float *q0, const float *goals,
+                                         const float *Q, float *C_s, float *C_h, float *C_l, float *minsd,
+                                         uint8_t *flags, const uint8_t *prune, const gtmp_edge_opts *opts,
+                                         void *stream);
+
 /* Signed distance / collision flag of a batch of configurations (the state
  * test of Sec. III used by the edge check).  X device float32 [n][d];
  * sd device float32 [n] or NULL (exact signed distance); coll device

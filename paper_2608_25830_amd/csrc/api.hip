@@ -8,6 +8,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "gtmp_launch.hpp"
 #include "surrogate.hpp"
 
@@ -157,17 +159,17 @@ gtmp_status gtmp_edge_check_workspace_size(const gtmp_problem *prob, size_t *byt
     return GTMP_OK;
 }
 
-gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
-                                 const float *q0, const float *goals, const float *Q, float *C_s, float *C_h,
-                                 float *C_l, float *minsd, uint8_t *flags, const uint8_t *prune, void *workspace,
-                                 size_t ws_bytes, const gtmp_edge_opts *opts, void *stream) {
-    g_err[0] = 0;
-    gtmp_status st = check_problem(prob);
-    if (st != GTMP_OK) return st;
+namespace {
+
+// Validation and dispatch shared by the two edge-check entry points.
+gtmp_status edge_check(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene, const float *q0,
+                       const float *goals, const float *Q, float *C_s, float *C_h, float *C_l, float *minsd,
+                       uint8_t *flags, const uint8_t *prune, void *workspace, size_t ws_bytes,
+                       const gtmp_edge_opts *opts, void *stream, const char *who) {
     gtmp::ArmParams arm{};
     gtmp::SceneParams sp{};
     bool is_arm = false;
-    st = check_model(robot, scene, prob->d, &arm, &is_arm, &sp);
+    gtmp_status st = check_model(robot, scene, prob->d, &arm, &is_arm, &sp);
     if (st != GTMP_OK) return st;
     if (!q0 || !goals || !Q || !C_s || !C_l) return fail(GTMP_EINVAL, "q0, goals, Q, C_s and C_l must be non-NULL");
     if (prob->M > 1 && !C_h) return fail(GTMP_EINVAL, "C_h is NULL with M > 1");
@@ -185,7 +187,71 @@ gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *rob
         return fail(GTMP_EINVAL, "sphere_chunks=%d (0, 1, 2 or 4)", o.sphere_chunks);
     gtmp::EdgeBuffers b{q0, goals, Q, C_s, C_h, C_l, minsd, flags, prune, workspace};
     return hip_status(gtmp::launch_edge_check(plan, is_arm ? &arm : nullptr, sp, scene->wdim, b, o, (hipStream_t)stream),
-                      "gtmp_edge_check_cost");
+                      who);
+}
+
+}  // namespace
+
+gtmp_status gtmp_edge_check_cost(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                                 const float *q0, const float *goals, const float *Q, float *C_s, float *C_h,
+                                 float *C_l, float *minsd, uint8_t *flags, const uint8_t *prune, void *workspace,
+                                 size_t ws_bytes, const gtmp_edge_opts *opts, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    return edge_check(prob, robot, scene, q0, goals, Q, C_s, C_h, C_l, minsd, flags, prune, workspace, ws_bytes, opts,
+                      stream, "gtmp_edge_check_cost");
+}
+
+// ------------------------------------------------------------------ edge check without allocation
+// The scratch of gtmp_edge_check_cost_noalloc: a file-scope device array,
+// one copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): the
+// device address of each GPU's copy is looked up once per device with that
+// device current and kept in scratch_addr.
+static __device__ __align__(256) unsigned char scratch[GTMP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+gtmp_status scratch_addr(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(GTMP_EINVAL, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255) != 0) return fail(GTMP_EHIP, "scratch address not aligned");
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return GTMP_OK;
+}
+
+}  // namespace
+
+gtmp_status gtmp_edge_check_cost_noalloc(const gtmp_problem *prob, const gtmp_robot *robot, const gtmp_scene *scene,
+                                         const float *q0, const float *goals, const float *Q, float *C_s, float *C_h,
+                                         float *C_l, float *minsd, uint8_t *flags, const uint8_t *prune,
+                                         const gtmp_edge_opts *opts, void *stream) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    const size_t need = gtmp::make_edge_plan(*prob).total;
+    if (need > (size_t)GTMP_NOALLOC_SCRATCH_BYTES)
+        return fail(GTMP_EINVAL, "problem needs %zu bytes of scratch; the static scratch holds %zu", need,
+                    (size_t)GTMP_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    st = scratch_addr(&ws);
+    if (st != GTMP_OK) return st;
+    return edge_check(prob, robot, scene, q0, goals, Q, C_s, C_h, C_l, minsd, flags, prune, ws,
+                      (size_t)GTMP_NOALLOC_SCRATCH_BYTES, opts, stream, "gtmp_edge_check_cost_noalloc");
 }
 
 gtmp_status gtmp_state_check(const gtmp_robot *robot, const gtmp_scene *scene, int32_t d, int64_t n, const float *X,

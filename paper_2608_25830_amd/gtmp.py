@@ -74,6 +74,9 @@ _lib.gtmp_edge_check_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINT
 _lib.gtmp_edge_check_cost.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot), C.POINTER(gtmp_scene),
                                       _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
                                       C.POINTER(gtmp_edge_opts), _vp]
+_lib.gtmp_edge_check_cost_noalloc.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_robot),
+                                              C.POINTER(gtmp_scene)] + [_vp] * 9 + [C.POINTER(gtmp_edge_opts), _vp]
+NOALLOC_SCRATCH_BYTES = 32 << 20
 _lib.gtmp_state_check.argtypes = [C.POINTER(gtmp_robot), C.POINTER(gtmp_scene), C.c_int32, C.c_int64, _vp, _vp,
                                   _vp, _vp]
 class gtmp_rrtc_opts(C.Structure):
@@ -160,7 +163,8 @@ _lib.gtmp_plan_classes.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_scene
                                    _vp, C.c_int32, C.c_int32, C.c_int32] + [_vp] * 7 + [C.c_size_t, _vp, _vp]
 
 EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample_layers",
-           "gtmp_edge_check_workspace_size", "gtmp_edge_check_cost", "gtmp_state_check", "gtmp_minplus_sweep",
+           "gtmp_edge_check_workspace_size", "gtmp_edge_check_cost", "gtmp_edge_check_cost_noalloc",
+           "gtmp_state_check", "gtmp_minplus_sweep",
            "gtmp_extract_path", "gtmp_expand_workspace_size", "gtmp_expand_samples", "gtmp_sample_informed",
            "gtmp_anytime_workspace_size", "gtmp_plan_anytime", "gtmp_batch_workspace_size", "gtmp_plan_batch",
            "gtmp_surrogate_layout", "gtmp_surrogate_refresh_bf16", "gtmp_surrogate_workspace_size",
@@ -283,6 +287,13 @@ def gtmp_edge_check_cost(prob, robot, scene: Scene, q0, goals, Q, C_s, C_h, C_l,
         C.byref(prob), C.byref(robot), C.byref(scene.c), _p(q0), _p(goals), _p(Q), _p(C_s), _p(C_h), _p(C_l),
         _p(minsd), _p(flags), _p(prune), _p(workspace), workspace.numel() * workspace.element_size(),
         C.byref(opts) if opts is not None else None, _stream(stream)))
+
+
+def gtmp_edge_check_cost_noalloc(prob, robot, scene: Scene, q0, goals, Q, C_s, C_h, C_l, minsd=None, flags=None,
+                                 prune=None, opts: gtmp_edge_opts | None = None, stream=None):
+    return _check(_lib.gtmp_edge_check_cost_noalloc(
+        C.byref(prob), C.byref(robot), C.byref(scene.c), _p(q0), _p(goals), _p(Q), _p(C_s), _p(C_h), _p(C_l),
+        _p(minsd), _p(flags), _p(prune), C.byref(opts) if opts is not None else None, _stream(stream)))
 
 
 def gtmp_state_check(robot, scene: Scene, d, X, sd=None, coll=None, stream=None):

@@ -153,6 +153,19 @@ def test_surrogate_calls_validate_sizes(g):
                                        None, ws, big, None) == g.GTMP_EINVAL  # net d = 7, problem d = 2
 
 
+def test_noalloc_edge_check_validates(g):
+    """The static-scratch edge check rejects, on the host, invalid problems
+    and problems whose scratch exceeds the static array."""
+    p = C.c_void_p(256)
+    f = g._lib.gtmp_edge_check_cost_noalloc
+    bad = _prob(g, N=0)
+    assert f(C.byref(bad), None, None, *([p] * 9), None, None) == g.GTMP_EINVAL
+    big = _prob(g, d=7, M=8, N=4096, lo=[-3] * 7, hi=[3] * 7)
+    assert g.gtmp_edge_check_workspace_size(big) > g.NOALLOC_SCRATCH_BYTES
+    assert f(C.byref(big), None, None, *([p] * 9), None, None) == g.GTMP_EINVAL
+    assert "scratch" in g._lib.gtmp_last_error().decode()
+
+
 def test_surrogate_threshold_validates(g):
     n = C.c_size_t()
     assert g._lib.gtmp_surrogate_threshold_workspace_size(C.byref(n)) == 0 and n.value >= 256
