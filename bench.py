@@ -707,6 +707,7 @@ def main():
     step_ms = np.array([sb[i].elapsed_time(sb[i + 1]) for i in range(args.steps)])
     states = torch.diff(stats_hist[:, 0]).cpu().numpy().astype(np.float64)
     tests = torch.diff(stats_hist[:, 2]).cpu().numpy().astype(np.float64)
+    rounds = torch.diff(stats_hist[:, 3]).cpu().numpy().astype(np.float64)
     costs = cost_hist.cpu().numpy()
 
     value = E * H / (ms_per_step / 1e3)
@@ -771,7 +772,9 @@ def main():
                      "traffic_source": traffic_src,
                      "kernel": "k_interior (early-exit interior edge checker)" + (", obstacle-bin filter" if grid else ""),
                      "kernel_ms": k_ms, "states_evaluated_per_launch": st, "flop_per_state": f_state,
-                     "states_evaluated_frac": st / (E * H), "obstacle_bins": grid},
+                     "states_evaluated_frac": st / (E * H),
+                     "lane_busy_frac": st / (64.0 * float(np.mean(rounds))) if np.mean(rounds) > 0 else None,
+                     "obstacle_bins": grid},
         "edge_opts": {k: int(getattr(pl.opts, k)) for k in ("mode", "states_per_iter", "blocks_per_cu",
                                                                "sphere_chunks")},
         "mean_path_cost": float(np.mean(costs)),

@@ -93,6 +93,19 @@ gtmp_status to_arm(const gtmp_robot *r, int d, gtmp::ArmParams *out) {
     for (int k = 0; k < r->n_spheres; ++k) tmax = fmax(tmax, fabs((double)r->sph_t[k]));
     a.reach = (float)(len * tmax * (1.0 + 1e-6));
     a.sph_tol = 0.f;
+    // per link: the spheres of link L lie on the line through o_{L-1} and
+    // o_L at t, so |centre| <= |o_{L-1}| + |t| |o_L - o_{L-1}| <= (lengths of
+    // links before L) + max(1, max |t|) (length of L)
+    double before = 0.0;
+    for (int j = 0; j < r->n_joints; ++j) {
+        const double lj = sqrt((double)r->dh[j][0] * r->dh[j][0] + (double)r->dh[j][2] * r->dh[j][2]);
+        double tl = 1.0;
+        for (int k = 0; k < r->n_spheres; ++k)
+            if (r->sph_link[k] == j + 1) tl = fmax(tl, fabs((double)r->sph_t[k]));
+        a.link_reach[j] = (float)((before + tl * lj) * (1.0 + 1e-6));
+        before += lj;
+    }
+    a.k_first = 0;
     *out = a;
     return GTMP_OK;
 }

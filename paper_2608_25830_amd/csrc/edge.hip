@@ -101,6 +101,40 @@ __global__ void k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
     // rounding of the bound itself: inflate by 1e-3 relative
     const float pc = (R.reach + cmax) * 1.001f, rr = (rmax + R.r0) * 1.001f;
     R.sph_tol = 0x1p-19f * (pc * pc + rr * rr);
+    // Links near the base that no obstacle can reach: an obstacle (box of
+    // half-extents h around c, grown by rho) is at distance dist(0, box) - rho
+    // from the base, and a sphere of link L has |centre| <= link_reach[L-1];
+    // while every obstacle is farther than (link_reach + r_max) (1 + 1e-3) +
+    // 1e-6, no sphere of links 1..L can touch one (the exact test's rounding
+    // is far inside that margin), and the bin filter may skip them.
+    float dmin = __builtin_inff(), rk_max = 0.f;
+    for (int o = threadIdx.x; o < S.n_sph + S.n_box; o += blockDim.x) {
+        float dd;
+        if (o < S.n_sph) {
+            const float *c = S.sph + 4 * o;
+            dd = __builtin_sqrtf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) - __builtin_fabsf(c[3]);
+        } else {
+            const float *b = S.box + 6 * (o - S.n_sph);
+            float acc = 0.f;
+            for (int i = 0; i < 3; ++i) {
+                const float e = __builtin_fmaxf(__builtin_fabsf(b[i]) - __builtin_fabsf(b[3 + i]), 0.f);
+                acc += e * e;
+            }
+            dd = __builtin_sqrtf(acc);
+        }
+        dmin = __builtin_fminf(dmin, dd != dd ? -__builtin_inff() : dd);  // NaN data: nothing is skipped
+    }
+    for (int k = threadIdx.x; k < R.n_spheres; k += blockDim.x) rk_max = __builtin_fmaxf(rk_max, R.r[k]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        dmin = __builtin_fminf(dmin, __shfl_xor(dmin, off));
+        rk_max = __builtin_fmaxf(rk_max, __shfl_xor(rk_max, off));
+    }
+    R.k_first = 0;
+    for (int L = 1; L <= R.n_joints; ++L) {
+        if (!(dmin > (R.link_reach[L - 1] + rk_max) * 1.001f + 1e-6f)) break;
+        R.k_first = R.lk_end[L - 1];
+    }
     const uint32_t *src = reinterpret_cast<const uint32_t *>(&R);
     uint32_t *d = reinterpret_cast<uint32_t *>(dst);
     constexpr int n = sizeof(ArmParams) / 4;
@@ -343,11 +377,11 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     }
     __syncthreads();
     float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
-    if constexpr (GRID) {
+    if constexpr (GRID) {  // wave-uniform: held in scalar registers
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            ginv[i] = glds.inv[i];
-            goff[i] = glds.off[i];
+            ginv[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(glds.inv[i])));
+            goff[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(glds.off[i])));
         }
     }
 
@@ -370,6 +404,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     bool exhausted = false;
     unsigned long long n_states = 0, n_edges = 0;
     uint32_t n_tests = 0;  // exact sphere-obstacle tests behind the bin filter (this lane)
+    uint32_t n_iters = 0;  // evaluation rounds of this wave (64 lane slots each)
 
     // lane state: the edge (flat id), its start and direction, next state
     bool has = false;
@@ -449,6 +484,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
         const uint64_t busy = ballot(has);
         if (busy == 0) break;  // exhausted and every lane idle
         n_states += (unsigned long long)__popcll(busy) * SP;
+        ++n_iters;
 
         // ---- evaluate the next interior state(s) of every busy lane
         float gap;
@@ -535,6 +571,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     if (A.stats && lane == 0) {
         atomicAdd(&A.stats[0], n_states);
         atomicAdd(&A.stats[1], n_edges);
+        atomicAdd(&A.stats[3], (unsigned long long)n_iters);
     }
 }
 

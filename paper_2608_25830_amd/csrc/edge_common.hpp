@@ -272,10 +272,12 @@ struct GridProber {
     const float4 (*rec)[2];
     uint32_t &tests;
     uint32_t head, tail;  // wave-uniform queue positions (mod kQueue in LDS)
-    bool hit;             // this lane's state is in contact (known from a drain)
+    uint32_t hit;         // 1: this lane's state is in contact (known from a drain); an integer,
+                          // not a bool, so that it stays a plain register across the loops
+    uint64_t done;        // wave-uniform: the lanes that offer nothing more (hit, or not live)
 
     __device__ __forceinline__ GridProber(GridQueue<WORDS> &q, const float4 (*r)[2], uint32_t &t, bool live)
-        : Q(q), rec(r), tests(t), head(0), tail(0), hit(!live) {
+        : Q(q), rec(r), tests(t), head(0), tail(0), hit(live ? 0u : 1u), done(ballot(!live)) {
         Q.hit[lane_id()] = 0;
     }
 
@@ -326,42 +328,56 @@ struct GridProber {
         }
         __builtin_amdgcn_wave_barrier();
         head += n;
-        hit = hit || Q.hit[lane] != 0;
+        hit |= Q.hit[lane] != 0 ? 1u : 0u;
+        done = ballot(hit != 0);
     }
 
-    // This lane's probe (centre c, radius r, bin mask words mw): queued when
-    // some obstacle is listed and the lane's state is not known to collide.
-    __device__ __forceinline__ void offer(const float (&c)[3], float r, const uint32_t (&mw)[WORDS]) {
+    // This lane's probe (bin mask words mw; centre(c) writes its centre,
+    // radius(): its radius, both evaluated only for a queued probe): queued
+    // when some obstacle is listed and the lane's state is not known to
+    // collide.  The lanes to queue are found as one wave-wide mask (the
+    // compare's own lane mask less `done`), so the common case of no lane
+    // queueing costs one vector compare.
+    template <class C, class Rad>
+    __device__ __forceinline__ void offer(const uint32_t (&mw)[WORDS], C &&centre, Rad &&radius) {
         uint32_t any = mw[0];
 #pragma unroll
         for (int wd = 1; wd < WORDS; ++wd) any |= mw[wd];
-        if (hit) any = 0;  // (a select: the ballot below is then one compare)
-        const bool want = any != 0;
-        const uint64_t wmask = ballot(want);
-        // a scalar count, laundered so that the test below stays a scalar
-        // compare (the compiler would otherwise rebuild the lane mask in VGPRs)
-        uint32_t nw = (uint32_t)__popcll(wmask);
-        asm volatile("" : "+s"(nw));
-        if (nw != 0) {
-            if (want) {
+        const uint64_t wmask = ballot(any != 0) & ~done;
+        if (wmask != 0) {
+            if (any != 0 && hit == 0) {  // the lanes of wmask (`done` is the ballot of `hit`)
+                float c[3];
+                centre(c);
                 const uint32_t slot = (tail + (uint32_t)rank_in(wmask)) & (kQueue - 1);
-                Q.e[slot].c = make_float4(c[0], c[1], c[2], r);
+                Q.e[slot].c = make_float4(c[0], c[1], c[2], radius());
                 Q.e[slot].m = make_uint4(mw[0], WORDS > 1 ? mw[WORDS > 1 ? 1 : 0] : 0u,
                                          WORDS > 2 ? mw[WORDS > 2 ? 2 : 0] : 0u, (uint32_t)lane_id());
             }
-            tail += nw;
+            tail += (uint32_t)__popcll(wmask);
             if (tail - head >= (uint32_t)kWave) drain(kWave);
         }
     }
 
+    __device__ __forceinline__ void offer(const float (&c)[3], float r, const uint32_t (&mw)[WORDS]) {
+        offer(mw, [&](float (&o)[3]) { o[0] = c[0]; o[1] = c[1]; o[2] = c[2]; }, [&] { return r; });
+    }
+
     __device__ __forceinline__ bool finish() {
         if (tail != head) drain(tail - head);
-        return hit;
+        return hit != 0;
     }
 };
 
 // mk: the mask tables (mk[w] = word w), rec: the obstacle records; both may
-// live in LDS or in device memory.
+// live in LDS or in device memory.  The bin coordinate of a sphere centre
+// c = b + t (p - b) on axis i is taken as f = (b_i inv_i + off_i) +
+// t ((p_i - b_i) inv_i), two terms formed once per link; it differs from the
+// coordinate of the FP32 centre, c_i inv_i + off_i, by rounding only (below
+// 1e-4 of a bin for any centre within the bins' span), and every obstacle's
+// bin interval is widened by a bin on each side, so the bins still list
+// every obstacle the exact test can find in contact.  The centre itself,
+// fma(t, p - b, b) as the full test forms it, is formed only for the
+// spheres queued for an exact test.
 template <int WORDS, class AP>
 __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_MAX_JOINTS],
                                              const GridMaskTable *mk, const float4 (*rec)[2],
@@ -369,24 +385,34 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
                                              GridQueue<WORDS> &Qw, uint32_t &tests, bool live) {
     GridProber<WORDS> P(Qw, rec, tests, live);
     arm_fk_visit<GTMP_MAX_JOINTS>(R, q, [&](int L, const float (&b)[3], const float (&p)[3]) {
-        float dd[3];
+        float fb[3], fd[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) dd[i] = p[i] - b[i];
-        const int k0 = L == 1 ? 0 : R.lk_end[L - 2];
+        for (int i = 0; i < 3; ++i) {
+            fb[i] = __builtin_fmaf(b[i], inv[i], off[i]);
+            fd[i] = (p[i] - b[i]) * inv[i];
+            // formed once per link: kept in registers rather than re-formed
+            // in every iteration of the sphere loop below
+            asm volatile("" : "+v"(fb[i]), "+v"(fd[i]));
+        }
+        const int kl = L == 1 ? 0 : R.lk_end[L - 2];
+        const int k0 = kl > R.k_first ? kl : R.k_first;  // spheres below k_first reach no obstacle
         const int k1 = R.lk_end[L - 1];
-        for (int k = k0; k < k1; ++k) {
-            const float t = R.t[k], rk = R.r[k];
-            float c[3];
+        // unsigned index: the parameter address is a plain increment
+        for (uint32_t k = (uint32_t)k0; k < (uint32_t)k1; ++k) {
+            const float t = R.t[k];
             uint32_t bin[3];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                c[i] = __builtin_fmaf(t, dd[i], b[i]);
-                bin[i] = grid_bin(__builtin_fmaf(c[i], inv[i], off[i]));
-            }
+            for (int i = 0; i < 3; ++i) bin[i] = grid_bin(__builtin_fmaf(t, fd[i], fb[i]));
             uint32_t mw[WORDS];
 #pragma unroll
             for (int wd = 0; wd < WORDS; ++wd) mw[wd] = mk[wd][0][bin[0]] & mk[wd][1][bin[1]] & mk[wd][2][bin[2]];
-            P.offer(c, rk, mw);
+            P.offer(
+                mw,
+                [&](float (&c)[3]) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) c[i] = __builtin_fmaf(t, p[i] - b[i], b[i]);
+                },
+                [&] { return R.r[k]; });
         }
     });
     return P.finish();

@@ -56,6 +56,8 @@ struct ArmParams {
     int lk_end[GTMP_MAX_JOINTS];  // spheres of link L (1-based) are lk_end[L-2] .. lk_end[L-1]-1 (from 0 for L = 1)
     float reach;    // bound on |sphere centre|: sum of the link lengths sqrt(a^2 + d^2), rounded up
     float sph_tol;  // rounding bound of the expanded sphere test (set on the device per launch)
+    float link_reach[GTMP_MAX_JOINTS];  // bound on |centre| of the spheres of link L (index L-1), rounded up
+    int k_first;    // spheres below this index can touch no obstacle of the scene (set on the device; 0 = unknown)
 };
 
 // Obstacles: raw device arrays of the scene, spheres [n][wdim+1], boxes
@@ -285,6 +287,51 @@ __device__ __forceinline__ float point_sd(const float (&p)[W], const SceneParams
 }
 
 // ---------------------------------------------------------------------------
+// Sine and cosine of a joint angle.  For |x| <= 32: Cody-Waite reduction
+// r = x - k pi/2, k = rint(2x/pi), with pi/2 split into three FP32 parts
+// (every product k * part is exact inside its fused multiply-add), then the
+// Taylor series of sin r to r^9 and of cos r to r^10 on |r| <= pi/4 (the
+// first omitted terms are below 2e-9 there) and the quadrant of k.  The
+// result is within a few 1e-8 of the exact values, far inside what the
+// collision decisions can resolve.  Arguments beyond 32 (or not finite)
+// take the library sincosf in that lane only, so a state's result never
+// depends on the other lanes of its wave.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void joint_sincos(float x, float &s, float &c) {
+    constexpr float kTwoOverPi = 0.636619772367581f;
+    constexpr float kP1 = 1.5707963705062866f;       // fl(pi/2)
+    constexpr float kP2 = -4.371138828673793e-08f;   // fl(pi/2 - kP1)
+    constexpr float kP3 = -1.7151245100058819e-15f;  // fl(pi/2 - kP1 - kP2)
+    const float k = __builtin_rintf(x * kTwoOverPi);
+    float r = __builtin_fmaf(-k, kP1, x);
+    r = __builtin_fmaf(-k, kP2, r);
+    r = __builtin_fmaf(-k, kP3, r);
+    const float z = r * r;
+    // sin r = r (1 - z/3! + z^2/5! - z^3/7! + z^4/9!); the innermost
+    // coefficients enter through scalar registers, so that no vector
+    // register holds a constant for the whole kernel
+    const float s9 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(2.7557319223985893e-06f)));
+    const float c10 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(-2.7557319223985888e-07f)));
+    float ps = __builtin_fmaf(z, s9, -1.9841269841269841e-04f);
+    ps = __builtin_fmaf(z, ps, 8.3333333333333332e-03f);
+    ps = __builtin_fmaf(z, ps, -1.6666666666666666e-01f);
+    const float sr = __builtin_fmaf(r * z, ps, r);
+    // cos r = 1 - z/2! + z^2/4! - z^3/6! + z^4/8! - z^5/10!
+    float pc = __builtin_fmaf(z, c10, 2.4801587301587302e-05f);
+    pc = __builtin_fmaf(z, pc, -1.3888888888888889e-03f);
+    pc = __builtin_fmaf(z, pc, 4.1666666666666664e-02f);
+    pc = __builtin_fmaf(z, pc, -0.5f);
+    const float cr = __builtin_fmaf(z, pc, 1.0f);
+    // quadrant n = k mod 4: sin x = (s, c, -s, -c)[n], cos x = (c, -s, -c, s)[n]
+    const int n = (int)k;
+    const bool swap = (n & 1) != 0;
+    const float a = swap ? cr : sr, b = swap ? sr : cr;
+    s = __uint_as_float(__float_as_uint(a) ^ (((uint32_t)n << 30) & 0x80000000u));
+    c = __uint_as_float(__float_as_uint(b) ^ (((uint32_t)(n + 1) << 30) & 0x80000000u));
+    if (!(__builtin_fabsf(x) <= 32.0f)) sincosf(x, &s, &c);
+}
+
+// ---------------------------------------------------------------------------
 // Serial-arm forward kinematics, standard DH: frame i+1 = frame i *
 // Rz(q_i + off_i) Tz(dz_i) Tx(a_i) Rx(alpha_i).  The frame is updated in place
 // (columns x, y, z and origin p).  The origins o_0..o_J are returned packed in
@@ -295,7 +342,10 @@ __device__ __forceinline__ float point_sd(const float (&p)[W], const SceneParams
 typedef float v32f __attribute__((ext_vector_type(32)));
 
 // Frame origins visited link by link: after joint j the visitor gets the link
-// index L = j + 1 and the origins o_{L-1} (b) and o_L (p) of that link.
+// index L = j + 1 and the origins o_{L-1} (b) and o_L (p) of that link.  The
+// first joint starts from the identity frame, written out (the general
+// update would multiply by the frame's zeros and ones, which floating point
+// cannot drop; the values are the same).
 template <int D, class AP, class F>
 __device__ __forceinline__ void arm_fk_visit(const AP &A, const float (&q)[D], F &&link) {
     float x0 = 1.f, x1 = 0.f, x2 = 0.f;
@@ -307,18 +357,25 @@ __device__ __forceinline__ void arm_fk_visit(const AP &A, const float (&q)[D], F
         if (j >= A.n_joints) break;
         const float b[3] = {p0, p1, p2};
         float st, ct;
-        sincosf(q[j] + A.off[j], &st, &ct);
-        const float xn0 = ct * x0 + st * y0, xn1 = ct * x1 + st * y1, xn2 = ct * x2 + st * y2;
-        const float yp0 = ct * y0 - st * x0, yp1 = ct * y1 - st * x1, yp2 = ct * y2 - st * x2;
-        p0 += A.a[j] * xn0 + A.dz[j] * z0;
-        p1 += A.a[j] * xn1 + A.dz[j] * z1;
-        p2 += A.a[j] * xn2 + A.dz[j] * z2;
+        joint_sincos(q[j] + A.off[j], st, ct);
         const float ca = A.ca[j], sa = A.sa[j];
-        const float yn0 = ca * yp0 + sa * z0, yn1 = ca * yp1 + sa * z1, yn2 = ca * yp2 + sa * z2;
-        const float zn0 = ca * z0 - sa * yp0, zn1 = ca * z1 - sa * yp1, zn2 = ca * z2 - sa * yp2;
-        x0 = xn0; x1 = xn1; x2 = xn2;
-        y0 = yn0; y1 = yn1; y2 = yn2;
-        z0 = zn0; z1 = zn1; z2 = zn2;
+        if (j == 0) {
+            x0 = ct; x1 = st; x2 = 0.f;
+            p0 = A.a[0] * ct; p1 = A.a[0] * st; p2 = A.dz[0];
+            y0 = -(ca * st); y1 = ca * ct; y2 = sa;
+            z0 = sa * st; z1 = -(sa * ct); z2 = ca;
+        } else {
+            const float xn0 = ct * x0 + st * y0, xn1 = ct * x1 + st * y1, xn2 = ct * x2 + st * y2;
+            const float yp0 = ct * y0 - st * x0, yp1 = ct * y1 - st * x1, yp2 = ct * y2 - st * x2;
+            p0 += A.a[j] * xn0 + A.dz[j] * z0;
+            p1 += A.a[j] * xn1 + A.dz[j] * z1;
+            p2 += A.a[j] * xn2 + A.dz[j] * z2;
+            const float yn0 = ca * yp0 + sa * z0, yn1 = ca * yp1 + sa * z1, yn2 = ca * yp2 + sa * z2;
+            const float zn0 = ca * z0 - sa * yp0, zn1 = ca * z1 - sa * yp1, zn2 = ca * z2 - sa * yp2;
+            x0 = xn0; x1 = xn1; x2 = xn2;
+            y0 = yn0; y1 = yn1; y2 = yn2;
+            z0 = zn0; z1 = zn1; z2 = zn2;
+        }
         const float p[3] = {p0, p1, p2};
         link(j + 1, b, p);
     }
