@@ -435,8 +435,9 @@ def bench_batch(args, torch, wl, gtmp):
         from paper_2608_25830_amd import autotune
         opts = autotune.tune_batch(specs)
     print(f"[bench] batch of {len(specs)} plans, opts {opts}", file=sys.stderr, flush=True)
-    bp = gtmp.BatchPlanner(specs, opts=opts)
-    for _ in range(args.warmup):
+    # captured as one graph on the first call, launched again by the others
+    bp = gtmp.BatchPlanner(specs, opts=opts, use_graph=not args.no_graph)
+    for _ in range(max(args.warmup, 1)):
         bp.run()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -617,7 +618,8 @@ def main():
     ap.add_argument("--rrtc-budget", type=int, default=400, help="rrtc form: budget of the main line")
     ap.add_argument("--rrtc-cap", type=int, default=RRTC_LP["tree_cap"], help="rrtc form: nodes per tree")
     ap.add_argument("--classes-n", type=int, default=64, help="classes form: samples per layer")
-    ap.add_argument("--no-graph", action="store_true", help="restart form: enqueue stages instead of replaying a graph")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="restart and batch forms: enqueue stages instead of replaying a graph")
     ap.add_argument("--labels", type=int, default=1 << 20, help="surrogate: label pairs (2x states)")
     ap.add_argument("--epochs", type=int, default=5, help="surrogate: training epochs")
     ap.add_argument("--batch-plans", type=int, default=512)
@@ -783,6 +785,8 @@ def main():
         "wall_s": wall,
     }
     out["sweep_roofline"] = sweep_report(torch, pl)
+    if not args.opt:
+        out["roofline_full_test"] = full_test_report(torch, w, pl)
     out["simplify"] = simplify_report(args, torch, gtmp, w, pl)
     out["lazy"] = lazy_report(args, torch, gtmp, w, costs)
     if not args.no_cpu:
@@ -855,6 +859,41 @@ def simplify_report(args, torch, gtmp, w, pl):
             "mean_path_cost": float(raw[ok].mean()) if ok.any() else None,
             "mean_simplified_cost": float(sc[ok].mean()) if ok.any() else None,
             "mean_waypoints_kept": float(out["count"].cpu().numpy()[ok].mean()) if ok.any() else None}
+
+
+def full_test_report(torch, w, pl, reps=3):
+    """Outside the timed region: the same plans with the unfiltered test
+    (sphere_chunks 2: every robot sphere against every obstacle at each
+    evaluated state; early exit along an edge and the vertex pre-pass stay
+    on), its interior kernel timed with HIP events on the plan's stream.
+    Algorithmic FLOP = states evaluated (kernel counter) x the full test's
+    FP32 operations per state."""
+    if w["kind"] != "arm":
+        return None
+    saved = {k: int(getattr(pl.opts, k)) for k in ("sphere_chunks", "states_per_iter", "blocks_per_cu")}
+    pl.opts.sphere_chunks, pl.opts.states_per_iter, pl.opts.blocks_per_cu = 2, 0, 0
+    f_dense = arm_state_flops(pl.d, len(w["sph_link"]), w["obs_spheres"].shape[0], w["obs_boxes"].shape[0], pl.d)
+    ms, states = [], []
+    try:
+        for i in range(reps + 1):
+            kb, ke = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0 = pl.stats.clone()
+            pl.opts.ev_begin, pl.opts.ev_end = kb.cuda_event, ke.cuda_event
+            pl.plan(w["seed"], i)
+            torch.cuda.synchronize()
+            if i > 0:
+                ms.append(kb.elapsed_time(ke))
+                states.append(float((pl.stats[0] - s0[0]).item()))
+    finally:
+        pl.opts.ev_begin, pl.opts.ev_end = None, None
+        for k, v in saved.items():
+            setattr(pl.opts, k, v)
+    k_ms, st = float(np.mean(ms)), float(np.mean(states))
+    achieved = st * f_dense / (k_ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "kernel": "k_interior, unfiltered test (sphere_chunks 2)",
+            "kernel_ms": k_ms, "states_evaluated_per_launch": st, "flop_per_state": f_dense,
+            "early_exit": True, "plans": reps}
 
 
 if __name__ == "__main__":

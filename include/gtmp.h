@@ -497,10 +497,9 @@ typedef struct gtmp_plan_desc {
 } gtmp_plan_desc;
 
 typedef struct gtmp_batch_opts {
-    int32_t use_graph;        /* capture the whole batch (every stage) as one hipGraph and launch it;
-                                 ignored (stages enqueued directly) when a plan uses the growing policy,
-                                 whose sample expansion sorts with a library routine that clears memory
-                                 with memset nodes, which are kept out of graphs */
+    int32_t use_graph;        /* capture the whole batch (every stage, every policy) as one hipGraph
+                                 and launch it; the instantiated graph is kept and launched again by
+                                 later calls with the same plans, options, outputs and workspace */
     int32_t states_per_iter;  /* interior states per lane and iteration for point robots (0 = auto = 8) */
     int32_t sphere_chunks;    /* arms: as gtmp_edge_opts.sphere_chunks; 0 (auto) uses the obstacle bins
                                  when every arm plan's scene has at most 64 obstacles */
@@ -527,8 +526,13 @@ gtmp_status gtmp_batch_workspace_size(const gtmp_plan_desc *plans, int32_t n, co
  * A plan's best_idx / best_wp hold the best stage's chain in their first
  * M + 1 / (M + 2) d entries (M = best_meta[1]); the rest is left as it was.
  * The call writes its tables into the workspace with a synchronous copy
- * after waiting for `stream`, then enqueues (or, with use_graph, launches the
- * captured graph and waits for it). */
+ * after waiting for `stream`, then enqueues the stages, or with use_graph
+ * captures them into a graph and launches it, asynchronously.  With use_graph
+ * a later call with byte-identical plan descriptors, options, output
+ * pointers and workspace only launches the kept graph (no host tables, no
+ * wait), re-uploading the tables first (with the wait) if another batch used
+ * that workspace in between.  At most 64 graphs are kept per process; past
+ * that a call captures, launches and waits for its graph, then releases it. */
 gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_batch_opts *opts, float *best_cost,
                             int32_t *best_idx, float *best_wp, int32_t *best_meta, float *stage_costs,
                             int32_t stage_stride, void *workspace, size_t ws_bytes, void *stream);

@@ -6,7 +6,8 @@ check of an edge stops at its first colliding state in any order, and a free
 edge's cost is its length either way).  The tuner times each candidate on the
 caller's own problem with HIP events around the edge check and keeps the
 fastest; results are cached in memory and, when a path is given, in a JSON
-file keyed by robot group and problem-size bucket.
+file keyed by robot group, problem sizes and a hash of the library (entries
+of another build of the kernels never match).
 
 Knobs:
   point robots: sphere_chunks 0 (the obstacle bins, on graphs of at least
@@ -42,9 +43,23 @@ def _pow2_bucket(n: int) -> int:
     return b
 
 
+_LIB_TAG: list[str] = []
+
+
+def library_tag() -> str:
+    """First 12 hex digits of the SHA-256 of the loaded libgtmp.so: a cached
+    timing is only reused by the kernels it was measured on."""
+    if not _LIB_TAG:
+        import hashlib
+        with open(gt.LIB_PATH, "rb") as f:
+            _LIB_TAG.append(hashlib.sha256(f.read()).hexdigest()[:12])
+    return _LIB_TAG[0]
+
+
 def problem_key(w) -> str:
-    """Robot group, DoF, robot spheres, obstacles, H and the power-of-two
-    bucket of N: the quantities that decide which launch shape wins."""
+    """Robot group, DoF, robot spheres, obstacles, H, M and the power-of-two
+    bucket of N (the quantities that decide which launch shape wins), and
+    the library the timings belong to."""
     if w["kind"] in ("point2d", "point"):
         grp = f"point{int(w['d'])}"
         sph, box = (w["circles"], w["boxes"]) if w["kind"] == "point2d" else (w["obs_spheres"], w["obs_boxes"])
@@ -54,7 +69,8 @@ def problem_key(w) -> str:
         grp = f"arm{int(w['d'])}"
         nob = f"{len(w['obs_spheres'])}+{len(w['obs_boxes'])}"
         ks = len(w["sph_r"])
-    return f"{grp}:K{ks}:obs{nob}:H{int(w['H'])}:N{_pow2_bucket(int(w['N']))}"
+    return (f"{grp}:K{ks}:obs{nob}:H{int(w['H'])}:M{int(w['M'])}:N{_pow2_bucket(int(w['N']))}"
+            f":lib{library_tag()}")
 
 
 def candidates(w) -> list[dict]:

@@ -32,10 +32,10 @@ FLAGS = [
 
 SOURCES = ["api.hip", "sample.hip", "edge.hip", "sweep.hip", "anytime.hip", "batch.hip", "surrogate.hip",
            "classes.hip", "simplify.hip", "rrtc.hip", "lazy.hip", "select.hip"]
-# the growing-budget sampler, the class labels and the RRT-Connect decisions
-# are defined as FP32 computations with a fixed operation order: no
-# contraction into fused multiply-adds in those files
-EXTRA = {src: ["-ffp-contract=off"] for src in ("anytime.hip", "classes.hip", "rrtc.hip")}
+# the growing-budget sampler and its pair ranking, the class labels and the
+# RRT-Connect decisions are defined as FP32 computations with a fixed
+# operation order: no contraction into fused multiply-adds in those files
+EXTRA = {src: ["-ffp-contract=off"] for src in ("anytime.hip", "classes.hip", "rrtc.hip", "select.hip")}
 
 
 def _compile(src: str) -> str:

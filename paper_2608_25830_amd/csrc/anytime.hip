@@ -6,8 +6,6 @@
 // sampler and the ranking of sample pairs are defined as FP32 computations
 // with a fixed operation order (see include/gtmp.h), so that the decisions
 // they take (ball rejection, box rejection, pair order) are reproducible.
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -232,49 +230,33 @@ __global__ void __launch_bounds__(1024) k_coin_rank(int m, int n_old, int N, uin
     }
 }
 
-// Keys of all (u, v) pairs, u in the previous layer, v in the next one:
-// FP32 squared distance summed in coordinate order (no contraction), as
-// its bit pattern (monotone for non-negative floats); value = u * nv + v.
-__global__ void k_pair_keys(int d, int nu, const float *U, int nv, const float *Vv, uint32_t *keys, uint32_t *vals) {
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (uint64_t)nu * nv) return;
-    const uint32_t a = (uint32_t)(t / nv), b = (uint32_t)(t % nv);
-    float acc = 0.0f;
-    for (int i = 0; i < d; ++i) {
-        const float x = U[(size_t)a * d + i] - Vv[(size_t)b * d + i];
-        acc = acc + x * x;
-    }
-    keys[t] = __float_as_uint(acc);
-    vals[t] = (uint32_t)t;
-}
-
-// Fill the new slots of layer m, one block of kExpandThreads per slot: a
+// Fill the new slots of layer m, one wave per slot (four per block): a
 // heuristic slot of rank h takes the midpoint of the h-th closest pair (a
 // uniform draw when fewer pairs exist), every other slot a draw of the
-// uniform half.  The draw's attempts are tested kExpandThreads at a time, one
-// per thread, and the lowest accepted attempt index wins (a minimum over the
-// block's waves), so the result is the sequential first accepted attempt.
-// A draw from a large informed set accepts rarely and can take many rounds:
-// several waves per slot shorten that chain of rounds.  With the surrogate
+// uniform half.  The draw's attempts are tested 64 at a time, one per lane,
+// and the lowest accepted attempt index wins (the first set bit of the
+// wave's ballot), so the result is the sequential first accepted attempt;
+// the proposal of the uniform half accepts at least a few per cent of its
+// attempts, so a slot nearly always needs one round.  With the surrogate
 // bias the pair list is the compacted list of candidates predicted free and
 // its length is read from n_avail.
 constexpr int kExpandThreads = 256;
-static_assert(kMaxAttempts % kExpandThreads == 0, "whole rounds of attempts");
+constexpr int kExpandSlots = kExpandThreads / kWave;  // slots per block
+static_assert(kMaxAttempts % kWave == 0, "whole rounds of attempts");
 
 __global__ void __launch_bounds__(kExpandThreads) k_expand_layer(int m, int n_old, int N, int d, BoxArgs B, uint32_t k0,
                                                                  uint32_t k1, uint32_t stage, const Informed *Ip,
                                                                  const int32_t *rank, const uint32_t *sorted_pairs,
                                                                  uint64_t n_pairs, const uint32_t *n_avail, int nv,
                                                                  const float *U, const float *Vv, float *Qm) {
-    __shared__ uint32_t first[kExpandThreads / kWave];
-    const int n = n_old + (int)blockIdx.x;  // block-uniform
+    const int lane = lane_id();
+    const int n = n_old + (int)blockIdx.x * kExpandSlots + (int)(threadIdx.x / kWave);  // wave-uniform
     if (n >= N) return;
-    const int lane = lane_id(), w = threadIdx.x / kWave;
     const Informed I = *Ip;
     const int h = rank[n];
     const uint64_t avail = n_avail ? (uint64_t)*n_avail : n_pairs;
     if (h >= 0 && (uint64_t)h < avail) {
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             const uint32_t p = sorted_pairs[h];
             const uint32_t a = p / (uint32_t)nv, b = p % (uint32_t)nv;
             for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = (U[(size_t)a * d + i] + Vv[(size_t)b * d + i]) * 0.5f;
@@ -282,25 +264,19 @@ __global__ void __launch_bounds__(kExpandThreads) k_expand_layer(int m, int n_ol
         return;
     }
     if (I.bounded) {
-        for (int base = 0; base < kMaxAttempts; base += kExpandThreads) {
-            const int att = base + (int)threadIdx.x;
+        for (int base = 0; base < kMaxAttempts; base += kWave) {
+            const int att = base + lane;
             float x[GTMP_MAX_DOF];
             const bool ok = informed_attempt(d, B.lo, B.hi, I, k0, k1, stage, (uint32_t)m, (uint32_t)n, att, x);
             const uint64_t acc = ballot(ok);
-            if (lane == 0) first[w] = acc != 0 ? (uint32_t)(base + kWave * w + __builtin_ctzll(acc)) : 0xffffffffu;
-            __syncthreads();
-            uint32_t best = 0xffffffffu;
-#pragma unroll
-            for (int k = 0; k < kExpandThreads / kWave; ++k) best = first[k] < best ? first[k] : best;
-            __syncthreads();  // first[] is read by every wave before the next round writes it
-            if (best != 0xffffffffu) {  // block-uniform
-                if ((uint32_t)att == best)
+            if (acc != 0) {  // wave-uniform
+                if (lane == __builtin_ctzll(acc))
                     for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
                 return;
             }
         }
     }
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         float x[GTMP_MAX_DOF];
         if (I.bounded) {  // past the attempt cap: the centre, a point of the set
             for (int i = 0; i < d; ++i) x[i] = I.centre[i];
@@ -375,31 +351,20 @@ static BoxArgs box_args(const gtmp_problem &p) {
 }
 
 // ------------------------------------------------------------------ workspace of the expansion
-static size_t sort_temp_bytes(uint64_t n) {
-    size_t bytes = 0;
-    (void)rocprim::radix_sort_pairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                    (const uint32_t *)nullptr, (uint32_t *)nullptr, (unsigned int)n, 0, 32,
-                                    (hipStream_t)0);
-    return bytes;
-}
-
 static size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
 ExpandPlan make_expand_plan(const gtmp_problem &p, bool bias) {
     ExpandPlan e{};
     const uint64_t Nn = (uint64_t)p.N;
-    const uint64_t G = (uint64_t)p.G;
-    const uint64_t maxpairs = Nn * (Nn > G ? Nn : G);
-    e.max_pairs = maxpairs;
+    // at most N - n_old <= N heuristic slots per layer: the N closest pairs
+    // (4 N candidates with the surrogate bias)
+    e.max_k = (uint32_t)((bias ? (uint64_t)kBiasCandidates : 1ull) * Nn);
     size_t o = 0;
     e.off_informed = o; o = up256(o + sizeof(Informed));
     e.off_rank = o; o = up256(o + sizeof(int32_t) * Nn);
-    e.off_keys = o; o = up256(o + sizeof(uint32_t) * maxpairs);
-    e.off_keys2 = o; o = up256(o + sizeof(uint32_t) * maxpairs);
-    e.off_vals = o; o = up256(o + sizeof(uint32_t) * maxpairs);
-    e.off_vals2 = o; o = up256(o + sizeof(uint32_t) * maxpairs);
-    e.sort_bytes = sort_temp_bytes(maxpairs);
-    e.off_sort = o; o = up256(o + e.sort_bytes);
+    e.off_sorted = o; o = up256(o + sizeof(uint32_t) * e.max_k);
+    const RankPlan rp = make_rank_plan(e.max_k);
+    e.off_rankws = o; o = up256(o + rp.total);
     if (bias) {
         const uint64_t K = (uint64_t)kBiasCandidates * Nn;
         e.bias_rows = K;
@@ -418,14 +383,11 @@ hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *go
                          float *Q_new, const float *c_dev, uint64_t seed, uint64_t stage, void *workspace,
                          hipStream_t s, const SurNet *bias, float bias_tau) {
     const ExpandPlan e = make_expand_plan(p, bias != nullptr);
+    const RankPlan rp = make_rank_plan(e.max_k);
     char *ws = static_cast<char *>(workspace);
     Informed *I = reinterpret_cast<Informed *>(ws + e.off_informed);
     int32_t *rank = reinterpret_cast<int32_t *>(ws + e.off_rank);
-    uint32_t *keys = reinterpret_cast<uint32_t *>(ws + e.off_keys);
-    uint32_t *keys2 = reinterpret_cast<uint32_t *>(ws + e.off_keys2);
-    uint32_t *vals = reinterpret_cast<uint32_t *>(ws + e.off_vals);
-    uint32_t *vals2 = reinterpret_cast<uint32_t *>(ws + e.off_vals2);
-    void *sort_tmp = ws + e.off_sort;
+    uint32_t *sorted_pairs = reinterpret_cast<uint32_t *>(ws + e.off_sorted);
     const int M = p.M, N = p.N, d = p.d;
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32), st = (uint32_t)stage;
     hipLaunchKernelGGL(k_informed_prep, dim3(1), dim3(64), 0, s, d, q0, goals, c_dev, p.penalty, box_args(p), I);
@@ -447,20 +409,17 @@ hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *go
         const uint64_t npairs = (uint64_t)nu * (uint64_t)nv;
         const int heuristic_ok = npairs > 0;
         hipLaunchKernelGGL(k_coin_rank, dim3(1), dim3(1024), 0, s, m, n_old, N, k0, k1, st, I, heuristic_ok, rank);
-        const uint32_t *sorted = vals;
+        // the closest pairs in rank order: as many as there are new slots (a
+        // heuristic rank never reaches past them), or the bias candidates
+        const uint64_t cap = (uint64_t)(bias ? kBiasCandidates : 1) * (uint64_t)(N - n_old);
+        const uint64_t K = npairs < cap ? npairs : cap;
+        const uint32_t *sorted = sorted_pairs;
         if (heuristic_ok) {
-            hipLaunchKernelGGL(k_pair_keys, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, d, nu, U, nv, Vv,
-                               keys, vals);
-            size_t tb = e.sort_bytes;
-            hipError_t err = rocprim::radix_sort_pairs(sort_tmp, tb, keys, keys2, vals, vals2, (unsigned int)npairs, 0,
-                                                       32, s);
+            hipError_t err = launch_rank_pairs(d, nu, U, nv, Vv, (uint32_t)K, sorted_pairs, rp, ws + e.off_rankws, s);
             if (err != hipSuccess) return err;
-            sorted = vals2;
         }
         const uint32_t *n_avail = nullptr;
         if (heuristic_ok && bias) {
-            const uint64_t cap = (uint64_t)kBiasCandidates * (uint64_t)(N - n_old);
-            const uint64_t K = npairs < cap ? npairs : cap;
             float *bX = reinterpret_cast<float *>(ws + e.off_bX);
             float *bz = reinterpret_cast<float *>(ws + e.off_bz);
             uint32_t *bfree = reinterpret_cast<uint32_t *>(ws + e.off_bfree);
@@ -473,9 +432,9 @@ hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *go
             sorted = bfree;
             n_avail = bcount;
         }
-        const unsigned slots = (unsigned)(N - n_old);  // one block per new slot
-        hipLaunchKernelGGL(k_expand_layer, dim3(slots), dim3(kExpandThreads), 0, s, m, n_old, N, d, B, k0, k1, st, I,
-                           rank, sorted, heuristic_ok ? npairs : 0, n_avail, nv, U, Vv, Q_new + (size_t)m * N * d);
+        const unsigned blocks = (unsigned)((N - n_old + kExpandSlots - 1) / kExpandSlots);
+        hipLaunchKernelGGL(k_expand_layer, dim3(blocks), dim3(kExpandThreads), 0, s, m, n_old, N, d, B, k0, k1, st, I,
+                           rank, sorted, heuristic_ok ? K : 0, n_avail, nv, U, Vv, Q_new + (size_t)m * N * d);
     }
     return hipGetLastError();
 }

@@ -5,6 +5,10 @@
 // (Alg. 1 gtmp / anytime-gtmp / ao-gtmp), and every result equals the
 // single-plan call with the same seed: the kernels run the same per-edge,
 // per-row and per-plan code as the single-plan ones.
+#include <map>
+#include <mutex>
+#include <string>
+
 #include "edge_common.hpp"
 
 namespace gtmp {
@@ -702,13 +706,87 @@ BatchLayout make_batch_layout(const gtmp_plan_desc *plans, int n, const gtmp_bat
     return L;
 }
 
+// ------------------------------------------------------------------ graph cache
+// An instantiated batch graph depends on everything the host put into its
+// kernel arguments and tables: the plan descriptors (sizes, policies, seeds,
+// device pointers), the options, the output buffers and the workspace.  A
+// call whose key matches an earlier one launches that graph again; the
+// tables it reads live in the workspace and are uploaded again only if
+// another batch wrote that workspace in between.  Graphs are kept for the
+// life of the process, at most kMaxBatchGraphs of them (later keys are
+// captured, launched, waited for and released as before).
+namespace {
+struct BatchGraph {
+    hipGraphExec_t exec;
+    std::vector<ArmParams> arms;
+    std::vector<BPlan> host;
+    std::vector<uint64_t> bases;
+};
+constexpr size_t kMaxBatchGraphs = 64;
+std::mutex g_batch_mu;
+std::map<std::string, BatchGraph> g_batch_graphs;
+std::map<const void *, std::string> g_batch_ws_owner;  // the key whose tables a workspace holds
+
+template <class T>
+void key_add(std::string &k, const T &v) {
+    k.append(reinterpret_cast<const char *>(&v), sizeof(T));
+}
+
+std::string batch_key(const gtmp_plan_desc *plans, int n, const gtmp_batch_opts &o, const BatchLayout &L,
+                      const BatchOut &out, const void *workspace) {
+    std::string k;
+    key_add(k, n);
+    k.append(reinterpret_cast<const char *>(plans), sizeof(gtmp_plan_desc) * (size_t)n);
+    key_add(k, o);
+    key_add(k, L.total);
+    key_add(k, out.best_cost);
+    key_add(k, out.best_idx);
+    key_add(k, out.best_wp);
+    key_add(k, out.best_meta);
+    key_add(k, out.stage_costs);
+    key_add(k, out.stage_stride);
+    key_add(k, workspace);
+    return k;
+}
+
+hipError_t upload_tables(const BatchLayout &L, void *workspace, const std::vector<ArmParams> &arms,
+                         const std::vector<BPlan> &host, const std::vector<uint64_t> &bases, hipStream_t s) {
+    // after the work already on the stream (which may still read an earlier
+    // table) is done
+    char *ws = static_cast<char *>(workspace);
+    hipError_t err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return err;
+    err = hipMemcpy(ws + L.off_arm, arms.data(), sizeof(ArmParams) * arms.size(), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return err;
+    err = hipMemcpy(ws + L.off_tables, host.data(), sizeof(BPlan) * host.size(), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return err;
+    return hipMemcpy(ws + L.off_bases, bases.data(), sizeof(uint64_t) * bases.size(), hipMemcpyHostToDevice);
+}
+}  // namespace
+
 hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host, int n, const gtmp_batch_opts &o,
                         const BatchLayout &L, const BatchOut &out, void *workspace, hipStream_t s) {
+    std::string key;
+    if (o.use_graph) {
+        key = batch_key(plans, n, o, L, out, workspace);
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        auto it = g_batch_graphs.find(key);
+        if (it != g_batch_graphs.end()) {
+            auto ow = g_batch_ws_owner.find(workspace);
+            if (ow == g_batch_ws_owner.end() || ow->second != key) {
+                hipError_t err = upload_tables(L, workspace, it->second.arms, it->second.host, it->second.bases, s);
+                if (err != hipSuccess) return err;
+                g_batch_ws_owner[workspace] = key;
+            }
+            return hipGraphLaunch(it->second.exec, s);
+        }
+    }
     char *ws = static_cast<char *>(workspace);
     ArmParams *arm_dev = reinterpret_cast<ArmParams *>(ws + L.off_arm);
     BPlan *tables = reinterpret_cast<BPlan *>(ws + L.off_tables);
     uint64_t *bases = reinterpret_cast<uint64_t *>(ws + L.off_bases);
     uint32_t *counters = reinterpret_cast<uint32_t *>(ws + L.off_counters);
+    (void)arm_dev;
 
     // ---- host tables of every stage (plans grouped: 2D points, 3D points, arms)
     std::vector<ArmParams> arms(arms_host, arms_host + n);
@@ -865,16 +943,14 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         I.samples = sb;
         info[st] = I;
     }
-    // tables are written once, before any work is enqueued, after the work
-    // already on the stream (which may still read an earlier table) is done
-    hipError_t err = hipStreamSynchronize(s);
+    // tables are written once, before any work is enqueued
+    hipError_t err = upload_tables(L, workspace, arms, host, host_bases, s);
     if (err != hipSuccess) return err;
-    err = hipMemcpy(arm_dev, arms.data(), sizeof(ArmParams) * n, hipMemcpyHostToDevice);
-    if (err != hipSuccess) return err;
-    err = hipMemcpy(tables, host.data(), sizeof(BPlan) * host.size(), hipMemcpyHostToDevice);
-    if (err != hipSuccess) return err;
-    err = hipMemcpy(bases, host_bases.data(), sizeof(uint64_t) * host_bases.size(), hipMemcpyHostToDevice);
-    if (err != hipSuccess) return err;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        if (o.use_graph) g_batch_ws_owner[workspace] = key;
+        else g_batch_ws_owner.erase(workspace);
+    }
 
     // point robots: 8 states per lane and at most 3 resident blocks per CU
     // unless asked otherwise (as the single-plan launcher)
@@ -983,11 +1059,10 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         return hipGetLastError();
     };
 
-    // the sample expansion of growing plans sorts with a library routine
-    // that clears memory with hipMemsetAsync: such batches are not captured
-    bool any_growing = false;
-    for (int p = 0; p < n; ++p) any_growing = any_growing || plans[p].mode == GTMP_ANYTIME_GROWING;
-    if (!o.use_graph || any_growing) return enqueue(s);
+    // every stage of every policy is capturable: no memset and no host
+    // read-back anywhere in the enqueued work (the growing plans' pair
+    // ranking included)
+    if (!o.use_graph) return enqueue(s);
     hipStream_t cs;
     err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (err != hipSuccess) return err;
@@ -1003,8 +1078,15 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
     err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (err != hipSuccess) return err;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        if (g_batch_graphs.size() < kMaxBatchGraphs) {
+            g_batch_graphs.emplace(key, BatchGraph{exec, std::move(arms), std::move(host), std::move(host_bases)});
+            return hipGraphLaunch(exec, s);
+        }
+    }
     err = hipGraphLaunch(exec, s);
-    // the executable graph is released once the stream has run it
+    // beyond the cache: the executable graph is released once the stream has run it
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     (void)hipGraphExecDestroy(exec);
     return err;

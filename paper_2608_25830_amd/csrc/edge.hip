@@ -182,13 +182,18 @@ __global__ void __launch_bounds__(256) k_vertices_arm(EdgeArgs A, ArmParams R, S
 }
 
 // Vertex flags of an arm through the obstacle bins (the same decisions as
-// k_vertices_arm); blocks of up to 256 threads.
+// k_vertices_arm).
+// Waves per block of the arm vertex kernel: a plan has few vertices, so
+// one-wave blocks spread them over more CUs (and hold one queue each).
+constexpr int kVertexGridWaves = 1;
+
 template <int WG>
-__global__ void __launch_bounds__(256) k_vertices_arm_grid(EdgeArgs A, ArmParams R, const float *q0,
-                                                           const float *goals, const float *Q, float *verts,
-                                                           uint8_t *vflag) {
+__global__ void __launch_bounds__(kVertexGridWaves * kWave) k_vertices_arm_grid(EdgeArgs A, ArmParams R,
+                                                                                const float *q0,
+                                                                                const float *goals, const float *Q,
+                                                                                float *verts, uint8_t *vflag) {
     __shared__ GridLds<WG> glds_raw;
-    __shared__ GridQueue<WG> gque[256 / kWave];
+    __shared__ GridQueue<WG> gque[kVertexGridWaves];  // one queue per wave of the block
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(A.grid);
         uint4 *dst = reinterpret_cast<uint4 *>(&glds_raw);
@@ -875,12 +880,13 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
             // the bins serve the vertex flags and, later, the interior kernel
             hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, 3, r_max, grid);
             // one wave per block: a plan has few vertices, so small blocks spread them over more CUs
-            const unsigned vb64 = (A.n_vertices + kWave - 1) / kWave;
+            constexpr int vt = kVertexGridWaves * kWave;
+            const unsigned vb64 = (A.n_vertices + vt - 1) / vt;
             if (gw == 1)
-                hipLaunchKernelGGL(k_vertices_arm_grid<1>, dim3(vb64), dim3(kWave), 0, s, A, R, q0, goals, Q, verts,
+                hipLaunchKernelGGL(k_vertices_arm_grid<1>, dim3(vb64), dim3(vt), 0, s, A, R, q0, goals, Q, verts,
                                    vflag);
             else
-                hipLaunchKernelGGL(k_vertices_arm_grid<2>, dim3(vb64), dim3(kWave), 0, s, A, R, q0, goals, Q, verts,
+                hipLaunchKernelGGL(k_vertices_arm_grid<2>, dim3(vb64), dim3(vt), 0, s, A, R, q0, goals, Q, verts,
                                    vflag);
         } else {
             hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);

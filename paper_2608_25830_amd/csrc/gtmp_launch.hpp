@@ -68,10 +68,22 @@ hipError_t launch_extract(int M, int N, int G, int d, const int32_t *a_s, const 
                           const float *Q, const float *q0, const float *goals, int32_t *idx, float *wp,
                           float *cost, hipStream_t s);
 
+// ---- ranking of sample pairs (select.hip): the K closest pairs of U [nu][d]
+// and V [nv][d] by FP32 squared distance (summed in coordinate order, no
+// contraction), ties by pair index a * nv + b, as pair indices in rank order
+// (K <= nu nv < 2^32).  Asynchronous, no memset.
+struct RankPlan {
+    uint32_t cap;  // candidate keys the final sort holds
+    size_t off_state, off_hist, off_cand, total;
+};
+RankPlan make_rank_plan(uint32_t max_k);
+hipError_t launch_rank_pairs(int d, int nu, const float *U, int nv, const float *V, uint32_t K, uint32_t *out,
+                             const RankPlan &rp, void *workspace, hipStream_t s);
+
 // ---- growing-budget sampler and anytime drivers (anytime.hip)
 struct ExpandPlan {
-    uint64_t max_pairs;
-    size_t off_informed, off_rank, off_keys, off_keys2, off_vals, off_vals2, off_sort, sort_bytes;
+    uint32_t max_k;  // closest pairs ranked per layer at most
+    size_t off_informed, off_rank, off_sorted, off_rankws;
     // surrogate-biased heuristic half (when planned with bias)
     uint64_t bias_rows;
     size_t off_bX, off_bz, off_bfree, off_bcount, off_bws, bws_bytes;

@@ -12,6 +12,20 @@ def test_keys_bucket_N_and_separate_groups():
     assert AT.problem_key(a) == AT.problem_key(b)
     assert AT.problem_key(b) != AT.problem_key(c)
     assert AT.problem_key(b).startswith("arm7:K40:")
+    # M scales the tile count as N does; the key names the library build
+    d = wl.make_workload("arm7", 0, N=2048, M=4)
+    assert AT.problem_key(d) != AT.problem_key(b)
+    assert AT.problem_key(b).endswith(":lib" + AT.library_tag()) and len(AT.library_tag()) == 12
+
+
+def test_entries_of_another_library_build_are_not_reused(tmp_path):
+    w = wl.make_workload("2d-small", 0)
+    path = tmp_path / "t.json"
+    stale = AT.problem_key(w).rsplit(":lib", 1)[0] + ":lib000000000000"
+    path.write_text(json.dumps({stale: dict(states_per_iter=2, sphere_chunks=0, blocks_per_cu=1, ms=0.5, table=[])}))
+    AT._MEM.clear()
+    assert AT.problem_key(w) not in json.loads(path.read_text())
+    AT._MEM.clear()
 
 
 def test_candidates_cover_each_knob():

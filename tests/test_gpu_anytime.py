@@ -49,16 +49,24 @@ def test_informed_draws_bit_exact(gt, name, scale, scene):
         assert np.array_equal(x.view(np.uint32), Xg[n].view(np.uint32)), (n, x, Xg[n])
 
 
-@pytest.mark.parametrize("name,M,N,n_old,cscale", [("2d-small", 4, 64, 32, 1.3), ("2d-small", 3, 40, 0, 1.5),
-                                                   ("arm7", 3, 48, 24, 1.5), ("2d-large", 5, 256, 128, 1.2),
-                                                   ("2d-small", 4, 64, 32, None)])
-def test_expand_samples_bit_exact(gt, name, M, N, n_old, cscale):
+@pytest.mark.parametrize("name,M,N,n_old,cscale,dup", [("2d-small", 4, 64, 32, 1.3, 0), ("2d-small", 3, 40, 0, 1.5, 0),
+                                                       ("arm7", 3, 48, 24, 1.5, 0), ("2d-large", 5, 256, 128, 1.2, 0),
+                                                       ("2d-small", 4, 64, 32, None, 0),
+                                                       ("2d-small", 4, 96, 48, 1.3, 6), ("arm7", 3, 64, 32, 2.0, 4),
+                                                       ("arm7", 3, 2048, 1024, 1.5, 0), ("2d-large", 3, 1024, 700, 1.1, 0)])
+def test_expand_samples_bit_exact(gt, name, M, N, n_old, cscale, dup):
+    """Expansion against the oracle, bit for bit: closest-pair ranks from the
+    device pair ranking (with exact ties from repeated samples when dup > 0:
+    each old sample repeated dup times, ties broken by pair index) and the
+    uniform half."""
     w = wl.make_workload(name, 1, M=M, N=N)
-    _say("expand", name, M, N, n_old, cscale)
+    _say("expand", name, M, N, n_old, cscale, dup)
     d = w["d"]
     q0, qg = w["q0"].astype(np.float64), w["goals"][0].astype(np.float64)
     c = np.float32(np.inf) if cscale is None else np.float32(np.linalg.norm(qg - q0) * cscale)
     Q_old = oracle.sample_layers(M, max(n_old, 1), d, w["lo"], w["hi"], 3, 1)[:, :n_old]
+    if dup:
+        Q_old = np.ascontiguousarray(np.repeat(Q_old[:, : (n_old + dup - 1) // dup], dup, axis=1)[:, :n_old])
     want = OA.expand_samples(w, [Q_old[m] for m in range(M)], M, N, None if cscale is None else c, 13, 6)
     prob = gt.make_problem(d, M, N, 1, w["H"], w["lo"], w["hi"], w["penalty"])
     ws = gt._aligned_workspace(gt.gtmp_expand_workspace_size(prob))

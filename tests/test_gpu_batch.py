@@ -60,9 +60,21 @@ def test_batch_equals_single_plans(gt, graph):
         assert torch.equal(bp.plan_idx(i)[:Mb + 1], ap.best_idx[:Mb + 1])
 
 
+def _same_chains(a, b):
+    """best_idx holds each plan's best chain in its first M + 1 entries (M of
+    the best stage); the rest is not written."""
+    ma, mb = a.best_meta.cpu().numpy(), b.best_meta.cpu().numpy()
+    assert np.array_equal(ma, mb)
+    for i in range(len(a.specs)):
+        M = int(ma[i, 1])
+        assert torch.equal(a.plan_idx(i)[:M + 1], b.plan_idx(i)[:M + 1]), i
+
+
 def test_batch_graph_equals_eager_repeatedly(gt):
-    """Restart plans only: with a growing plan the batch is not captured."""
-    specs = [sp for sp in mixed_specs(gt) if sp["mode"] == gt.GTMP_ANYTIME_RESTART]
+    """Every policy, growing plans included, captured: the kept graph is
+    launched again by later calls (with eager work and synchronisations in
+    between) and matches the eager batch each time."""
+    specs = mixed_specs(gt)
     _say("batch graph repeat", len(specs))
     eager = gt.BatchPlanner(specs, use_graph=False)
     eager.run()
@@ -72,11 +84,36 @@ def test_batch_graph_equals_eager_repeatedly(gt):
         g.run()
         torch.cuda.synchronize()
         assert torch.equal(g.best_cost, eager.best_cost), rep
-        assert torch.equal(g.best_idx, eager.best_idx), rep
+        _same_chains(g, eager)
         assert torch.equal(g.stage_costs.nan_to_num(-1), eager.stage_costs.nan_to_num(-1)), rep
         x = torch.randn(4096, device="cuda").sum()  # eager work between launches
         torch.cuda.synchronize()
         del x
+
+
+def test_batch_graph_after_another_batch_on_its_workspace(gt):
+    """A kept graph launched after another batch wrote the same workspace:
+    its tables are uploaded again first, and its results stay those of the
+    eager batch.  The two batches alternate on one workspace, results
+    checked after every call."""
+    specs_a = mixed_specs(gt)
+    specs_b = [sp for sp in specs_a if sp["mode"] == gt.GTMP_ANYTIME_RESTART][::-1]
+    _say("alternating batches on one workspace")
+    ref_a = gt.BatchPlanner(specs_a, use_graph=False)
+    ref_b = gt.BatchPlanner(specs_b, use_graph=False)
+    ref_a.run()
+    ref_b.run()
+    torch.cuda.synchronize()
+    a = gt.BatchPlanner(specs_a, use_graph=True)
+    b = gt.BatchPlanner(specs_b, use_graph=True)
+    assert b.workspace.numel() <= a.workspace.numel()
+    b.workspace = a.workspace[: b.workspace.numel()]
+    for rep in range(2):
+        for bp, ref in ((a, ref_a), (b, ref_b)):
+            bp.run()
+            torch.cuda.synchronize()
+            assert torch.equal(bp.best_cost, ref.best_cost), rep
+            _same_chains(bp, ref)
 
 
 def test_batch_same_robot_many_plans(gt):
