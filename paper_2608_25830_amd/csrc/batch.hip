@@ -36,6 +36,7 @@ struct BPlan {
     uint32_t vert_base;  // first vertex of this plan in its group's vertex space
     uint32_t tile_base;  // first tile of this plan in the batch's tile space
     uint32_t gtile_base; // first tile of this plan in its group's tile space
+    uint32_t pblock_base; // first pre-pass block of this plan in its group's block space
     uint32_t row_base;   // first row (layer vertex) in the batch's row space
     const float *Q, *q0, *goals;
     float *V;
@@ -190,43 +191,14 @@ __global__ void __launch_bounds__(256) k_batch_vertices(const BPlan *plans, int 
 }
 
 // ------------------------------------------------------------------ pre-pass
-__global__ void __launch_bounds__(kTile) k_batch_prepass(const BPlan *plans, int n_plans) {
-    __shared__ uint32_t wave_cnt[kTile / kWave];
+// Pre-pass of the plans [p0, p1) of one robot group: the single-plan
+// pre-pass (rows per block, target vertices reused along a run of rows),
+// block b of the launch being block b - pblock_base of its plan.
+template <int D>
+__global__ void __launch_bounds__(kTile) k_batch_prepass(const BPlan *plans, int p0, int p1) {
     const uint32_t g = blockIdx.x;
-    const int p = find_plan(0, n_plans, g, [&](int i) { return plans[i].tile_base; });
-    const EdgeArgs &A = plans[p].A;
-    const uint32_t tile = g - plans[p].tile_base;
-    const uint32_t row = tile / A.tiles_per_row;
-    const uint32_t seg = tile - row * A.tiles_per_row;
-    const RowInfo ri = decode_row(A, row);
-    const uint32_t n = seg * kTile + threadIdx.x;
-    const bool valid = n < (uint32_t)A.N;
-    bool cand = false;
-    if (valid) {
-        const uint32_t uid = ri.u_base + n * ri.u_step, vid = ri.v_base + n * ri.v_step;
-        float u[GTMP_MAX_DOF], v[GTMP_MAX_DOF];
-        load_vertex<GTMP_MAX_DOF>(A, uid, u);
-        load_vertex<GTMP_MAX_DOF>(A, vid, v);
-        const float len = edge_len<GTMP_MAX_DOF>(u, v, A.d);
-        const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
-        bool failed = (A.vflag[uid] | A.vflag[vid]) != 0 || len > A.max_len;
-        if (A.prune) failed = failed || A.prune[e] != 0;
-        ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
-        if (A.flags) A.flags[e] = 1;
-        cand = !failed;
-    }
-    const uint64_t mask = ballot(cand);
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == 0) wave_cnt[w] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    uint32_t base = 0, total = 0;
-#pragma unroll
-    for (int k = 0; k < kTile / kWave; ++k) {
-        if (k < w) base += wave_cnt[k];
-        total += wave_cnt[k];
-    }
-    if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
-    if (threadIdx.x == 0) A.tile_cnt[tile] = total;
+    const int p = find_plan(p0, p1, g, [&](int i) { return plans[i].pblock_base; });
+    prepass_block<D>(plans[p].A, g - plans[p].pblock_base);
 }
 
 // ------------------------------------------------------------------ interior (persistent)
@@ -244,11 +216,14 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4
     constexpr int W = ARM ? 3 : D;
     constexpr int SP = ARM ? 1 : KP;
     __shared__ float tord[4][GTMP_MAX_H];
-    // obstacle bins (arms): each wave holds the mask words of its current
-    // plan in LDS; the obstacle records (read by the exact tests only) stay in
-    // device memory
+    // obstacle bins: each wave holds the mask words of its current plan in
+    // LDS (arms: the grid's layout; points: the W axes a point state uses,
+    // one cell's words side by side, one vector read per axis); the obstacle
+    // records (read by the exact tests only) stay in device memory
     constexpr int WG = Model::kWords > 0 ? Model::kWords : 1;
-    __shared__ typename std::conditional<GRID, GridMaskTable[4][WG], char>::type gmask;
+    constexpr int WS = point_mask_stride<WG>();
+    __shared__ typename std::conditional<GRID && ARM, GridMaskTable[4][WG], char>::type gmask;
+    __shared__ typename std::conditional<GRID && !ARM, uint32_t[4][W][kGridCells][WS], char>::type pmask;
     __shared__ typename std::conditional<GRID, GridQueue<WG>[4], char>::type gque;
     const float4(*grec)[2] = nullptr;
     float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
@@ -306,11 +281,18 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4
                     n_int = plans[cur].A.n_int;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     for (int i = lane; i < n_int; i += kWave) tord[wv][i] = plans[cur].A.tord[i];
-                    if constexpr (GRID) {
+                    if constexpr (GRID && ARM) {
                         const uint4 *src = reinterpret_cast<const uint4 *>(plans[cur].A.grid->mask);
                         uint4 *dst = reinterpret_cast<uint4 *>(&gmask[wv][0]);
                         constexpr int n16 = (int)(sizeof(GridMaskTable) * WG / 16);
                         for (int i = lane; i < n16; i += kWave) dst[i] = src[i];
+                    } else if constexpr (GRID) {
+                        const ObsGrid *G = plans[cur].A.grid;
+                        for (int i = lane; i < W * kGridCells; i += kWave) {
+                            const int ax = i / kGridCells, bin = i - ax * kGridCells;
+#pragma unroll
+                            for (int wd = 0; wd < WS; ++wd) pmask[wv][ax][bin][wd] = wd < WG ? G->mask[wd][ax][bin] : 0u;
+                        }
                     }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
@@ -392,7 +374,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4
                 for (int i = 0; i < W; ++i) p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
             }
             uint32_t tests = 0;
-            gap = point_hit_grid<W, SP, Model::kWords>(p, gmask[wv], grec, ginv, goff, gque[wv], tests, has) ? -1.f
+            gap = point_hit_grid<W, SP, Model::kWords>(p, pmask[wv], grec, ginv, goff, gque[wv], tests, has) ? -1.f
                                                                                                               : 1.f;
             n_tests += tests;
         } else {
@@ -833,14 +815,15 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         uint32_t rows;
         uint64_t samples;
         int maxM;
-        bool any_interior;
+        uint32_t pblocks[3];
+        bool any_interior, any_no_interior;
     };
     std::vector<StageInfo> info(L.max_stages);
     std::vector<BPlan> host(n * (size_t)L.max_stages);
     std::vector<uint64_t> host_bases(n * (size_t)L.max_stages);
     for (int st = 0; st < L.max_stages; ++st) {
         StageInfo I{};
-        uint32_t vb[3] = {0, 0, 0}, gb[3] = {0, 0, 0}, tb = 0, rb = 0;
+        uint32_t vb[3] = {0, 0, 0}, gb[3] = {0, 0, 0}, pbb[3] = {0, 0, 0}, tb = 0, rb = 0;
         uint64_t sb = 0;
         int cnt = 0;
         int gstart[4] = {0, 0, 0, 0};
@@ -861,6 +844,7 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                 A.d = pp.d; A.M = pp.M; A.N = pp.N; A.G = pp.G; A.H = pp.H; A.dp = vertex_stride(pp.d);
                 A.penalty = pp.penalty; A.max_len = pp.max_edge_len;
                 A.tiles_per_row = ep.tiles_per_row; A.n_tiles = ep.n_tiles; A.n_vertices = ep.n_vertices;
+                A.prepass_rows = prepass_rows_for(ep.n_tiles);
                 A.verts = reinterpret_cast<float *>(ews + ep.off_verts);
                 A.vflag = reinterpret_cast<uint8_t *>(ews + ep.off_vflag);
                 A.C_s = reinterpret_cast<float *>(ws + PO.Cs);
@@ -890,6 +874,7 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                 B.group = gi;
                 B.vert_base = vb[gi]; vb[gi] += ep.n_vertices;
                 B.gtile_base = gb[gi]; gb[gi] += ep.n_tiles;
+                B.pblock_base = pbb[gi]; pbb[gi] += prepass_block_count(A);
                 B.tile_base = tb; tb += ep.n_tiles;
                 B.row_base = rb; rb += (uint32_t)pp.N;
                 // samples: restart stages draw uniform samples into Q; growing
@@ -927,6 +912,7 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                 host_bases[(size_t)st * n + cnt] = sb;
                 sb += grow ? 0 : (uint64_t)pp.M * pp.N * ((pp.d + 3) / 4);
                 if (A.n_int > 0) I.any_interior = true;
+                else I.any_no_interior = true;
                 if (pp.M > I.maxM) I.maxM = pp.M;
                 ++cnt;
             }
@@ -937,6 +923,7 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         for (int gi = 0; gi < 3; ++gi) {
             I.verts[gi] = vb[gi];
             I.gtiles[gi] = gb[gi];
+            I.pblocks[gi] = pbb[gi];
         }
         I.tiles = tb;
         I.rows = rb;
@@ -1006,8 +993,15 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
             if (I.verts[2] > 0)
                 hipLaunchKernelGGL((k_batch_vertices<2, 8>), dim3((I.verts[2] + 255) / 256), dim3(256), 0, st_, T,
                                    I.g2, I.g3, I.verts[2]);
-            hipLaunchKernelGGL(k_batch_prepass, dim3(I.tiles), dim3(kTile), 0, st_, T, I.count);
-            hipLaunchKernelGGL(k_batch_no_interior, dim3(I.tiles), dim3(kTile), 0, st_, T, I.count);
+            if (I.pblocks[0] > 0)
+                hipLaunchKernelGGL(k_batch_prepass<2>, dim3(I.pblocks[0]), dim3(kTile), 0, st_, T, I.g0, I.g1);
+            if (I.pblocks[1] > 0)
+                hipLaunchKernelGGL(k_batch_prepass<3>, dim3(I.pblocks[1]), dim3(kTile), 0, st_, T, I.g1, I.g2);
+            if (I.pblocks[2] > 0)
+                hipLaunchKernelGGL(k_batch_prepass<GTMP_MAX_JOINTS>, dim3(I.pblocks[2]), dim3(kTile), 0, st_, T, I.g2,
+                                   I.g3);
+            if (I.any_no_interior)  // H = 2 plans: every candidate is free
+                hipLaunchKernelGGL(k_batch_no_interior, dim3(I.tiles), dim3(kTile), 0, st_, T, I.count);
             // persistent interior per group
             if (I.gtiles[0] > 0) {
                 const void *k = pgrid_words == 1 ? (const void *)k_batch_interior<PointGridModel<2, 4, 1>, true, 1>

@@ -245,85 +245,13 @@ __global__ void __launch_bounds__(256) k_vertices_point(EdgeArgs A, SceneParams 
 }
 
 // ------------------------------------------------------------------ 2. pre-pass
-// One block per (A.prepass_rows <= kPrepassRows consecutive rows, row
-// segment): thread i takes column seg * kTile + i of every row.  Consecutive
-// rows of a layer share their target vertices, so a thread loads its target
-// once and reuses it while the rows' targets stay the same; the per-tile
-// compaction of all the rows shares one barrier.  Small graphs take one row
-// per block (more blocks in flight).
-constexpr int kPrepassRows = 8;
-constexpr uint32_t kPrepassRowsMinTiles = 4096;  // graphs from this size take kPrepassRows rows per block
-
+// (prepass_block in edge_common.hpp; shared with the batched planner)
 template <int D>
 __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
-    __shared__ uint32_t wave_cnt[kPrepassRows][kTile / kWave];
-    const int w = threadIdx.x / kWave;
-    const uint32_t seg = blockIdx.x % A.tiles_per_row;
-    const uint32_t row0 = (blockIdx.x / A.tiles_per_row) * A.prepass_rows;
-    const uint32_t rows = A.n_tiles / A.tiles_per_row;
-    const uint32_t n = seg * kTile + threadIdx.x;
-    const bool col = n < (uint32_t)A.N;
-    uint32_t candbits = 0;
-    uint32_t vb = 0xffffffffu, vs = 0xffffffffu;  // target pattern of the loaded v
-    float v[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) v[i] = 0.f;
-    uint8_t vfl = 0;
-#pragma unroll
-    for (int r = 0; r < kPrepassRows; ++r) {
-        const uint32_t row = row0 + r;
-        if (r >= A.prepass_rows || row >= rows) break;
-        const RowInfo ri = decode_row(A, row);
-        bool cand = false;
-        if (ri.v_base != vb || ri.v_step != vs) {
-            vb = ri.v_base;
-            vs = ri.v_step;
-            if (col) {
-                const uint32_t vid = vb + n * vs;
-                load_vertex<D>(A, vid, v);
-                vfl = A.vflag[vid];
-            }
-        }
-        const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
-        if (col) {
-            const uint32_t uid = ri.u_base + n * ri.u_step;
-            float u[D];
-            load_vertex<D>(A, uid, u);
-            const float len = edge_len<D>(u, v, A.d);
-            bool failed = (A.vflag[uid] | vfl) != 0 || len > A.max_len;
-            if (A.prune) failed = failed || A.prune[e] != 0;
-            ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
-            if (A.flags) A.flags[e] = 1;
-            cand = !failed;
-        }
-        candbits |= (cand ? 1u : 0u) << r;
-        const uint64_t mask = ballot(cand);
-        if (lane_id() == 0) wave_cnt[r][w] = (uint32_t)__popcll(mask);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kPrepassRows; ++r) {
-        const uint32_t row = row0 + r;
-        if (r >= A.prepass_rows || row >= rows) break;
-        const uint32_t tile = row * A.tiles_per_row + seg;
-        uint32_t base = 0, total = 0;
-#pragma unroll
-        for (int k = 0; k < kTile / kWave; ++k) {
-            if (k < w) base += wave_cnt[r][k];
-            total += wave_cnt[r][k];
-        }
-        const bool cand = (candbits >> r) & 1u;
-        const uint64_t mask = ballot(cand);
-        if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
-        if (threadIdx.x == 0) A.tile_cnt[tile] = total;
-    }
+    prepass_block<D>(A, blockIdx.x);
 }
 
-// Blocks of the pre-pass for a plan's tiles.
-static inline unsigned prepass_blocks(const EdgeArgs &A) {
-    const uint32_t rows = A.n_tiles / A.tiles_per_row;
-    return (unsigned)(((rows + A.prepass_rows - 1) / A.prepass_rows) * A.tiles_per_row);
-}
+static inline unsigned prepass_blocks(const EdgeArgs &A) { return prepass_block_count(A); }
 
 // ------------------------------------------------------------------ 3. interior
 // Persistent: blocks loop until the tile cursor runs past n_tiles.  Every
@@ -1041,7 +969,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
     A.d = plan.d; A.M = plan.M; A.N = plan.N; A.G = plan.G; A.H = plan.H; A.dp = vertex_stride(plan.d);
     A.penalty = plan.penalty; A.max_len = plan.max_len;
     A.tiles_per_row = plan.tiles_per_row; A.n_tiles = plan.n_tiles; A.n_vertices = plan.n_vertices;
-    A.prepass_rows = plan.n_tiles >= kPrepassRowsMinTiles ? (uint32_t)kPrepassRows : 1u;
+    A.prepass_rows = prepass_rows_for(plan.n_tiles);
     char *ws = static_cast<char *>(b.workspace);
     float *verts = reinterpret_cast<float *>(ws + plan.off_verts);
     uint8_t *vflag = reinterpret_cast<uint8_t *>(ws + plan.off_vflag);

@@ -449,10 +449,11 @@ __device__ __forceinline__ bool point_hit_grid_by(const float (&p)[W][SP], const
     return P.finish();
 }
 
-// The masks with one cell's words side by side (one vector read per axis).
-template <int W, int SP, int WORDS>
+// The masks with one cell's words side by side (one vector read per axis),
+// for AX >= W axes.
+template <int W, int SP, int WORDS, int AX>
 __device__ __forceinline__ bool point_hit_grid(const float (&p)[W][SP],
-                                               const uint32_t (&pm)[3][kGridCells][point_mask_stride<WORDS>()],
+                                               const uint32_t (&pm)[AX][kGridCells][point_mask_stride<WORDS>()],
                                                const float4 (*rec)[2], const float (&inv)[3],
                                                const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
                                                bool live) {
@@ -575,6 +576,93 @@ __device__ __forceinline__ float edge_len(const float (&u)[D], const float (&v)[
 }
 
 __device__ __forceinline__ float failed_cost(float len, float penalty) { return len + penalty; }
+
+// ------------------------------------------------------------------ pre-pass
+// One block per (A.prepass_rows <= kPrepassRows consecutive rows, row
+// segment): thread i takes column seg * kTile + i of every row.  Consecutive
+// rows of a layer share their target vertices, so a thread loads its target
+// once and reuses it while the rows' targets stay the same; the per-tile
+// compaction of all the rows shares one barrier.  Small graphs take one row
+// per block (more blocks in flight).
+constexpr int kPrepassRows = 8;
+constexpr uint32_t kPrepassRowsMinTiles = 4096;  // graphs from this size take kPrepassRows rows per block
+
+// Rows per pre-pass block of a graph of n_tiles tiles, and the blocks of a
+// plan's pre-pass.
+__host__ __device__ inline uint32_t prepass_rows_for(uint32_t n_tiles) {
+    return n_tiles >= kPrepassRowsMinTiles ? (uint32_t)kPrepassRows : 1u;
+}
+__host__ __device__ inline uint32_t prepass_block_count(const EdgeArgs &A) {
+    const uint32_t rows = A.n_tiles / A.tiles_per_row;
+    return ((rows + A.prepass_rows - 1) / A.prepass_rows) * A.tiles_per_row;
+}
+
+// Pre-pass block b of a plan (blocks of kTile threads).
+template <int D>
+__device__ __forceinline__ void prepass_block(const EdgeArgs &A, uint32_t b) {
+    __shared__ uint32_t wave_cnt[kPrepassRows][kTile / kWave];
+    const int w = threadIdx.x / kWave;
+    const uint32_t seg = b % A.tiles_per_row;
+    const uint32_t row0 = (b / A.tiles_per_row) * A.prepass_rows;
+    const uint32_t rows = A.n_tiles / A.tiles_per_row;
+    const uint32_t n = seg * kTile + threadIdx.x;
+    const bool col = n < (uint32_t)A.N;
+    uint32_t candbits = 0;
+    uint32_t vb = 0xffffffffu, vs = 0xffffffffu;  // target pattern of the loaded v
+    float v[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = 0.f;
+    uint8_t vfl = 0;
+#pragma unroll
+    for (int r = 0; r < kPrepassRows; ++r) {
+        const uint32_t row = row0 + r;
+        if (r >= A.prepass_rows || row >= rows) break;
+        const RowInfo ri = decode_row(A, row);
+        bool cand = false;
+        if (ri.v_base != vb || ri.v_step != vs) {
+            vb = ri.v_base;
+            vs = ri.v_step;
+            if (col) {
+                const uint32_t vid = vb + n * vs;
+                load_vertex<D>(A, vid, v);
+                vfl = A.vflag[vid];
+            }
+        }
+        const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
+        if (col) {
+            const uint32_t uid = ri.u_base + n * ri.u_step;
+            float u[D];
+            load_vertex<D>(A, uid, u);
+            const float len = edge_len<D>(u, v, A.d);
+            bool failed = (A.vflag[uid] | vfl) != 0 || len > A.max_len;
+            if (A.prune) failed = failed || A.prune[e] != 0;
+            ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
+            if (A.flags) A.flags[e] = 1;
+            cand = !failed;
+        }
+        candbits |= (cand ? 1u : 0u) << r;
+        const uint64_t mask = ballot(cand);
+        if (lane_id() == 0) wave_cnt[r][w] = (uint32_t)__popcll(mask);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPrepassRows; ++r) {
+        const uint32_t row = row0 + r;
+        if (r >= A.prepass_rows || row >= rows) break;
+        const uint32_t tile = row * A.tiles_per_row + seg;
+        uint32_t base = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < kTile / kWave; ++k) {
+            if (k < w) base += wave_cnt[r][k];
+            total += wave_cnt[r][k];
+        }
+        const bool cand = (candbits >> r) & 1u;
+        const uint64_t mask = ballot(cand);
+        if (cand) A.tile_off[(size_t)tile * kTile + base + rank_in(mask)] = (uint8_t)threadIdx.x;
+        if (threadIdx.x == 0) A.tile_cnt[tile] = total;
+    }
+}
+
 
 // ------------------------------------------------------------------ robot adapters
 // Point robot in R^W: a state is one probe of radius 0.  Arm: a state is KP
