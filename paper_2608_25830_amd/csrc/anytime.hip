@@ -11,6 +11,7 @@
 #include <tuple>
 
 #include "gtmp_launch.hpp"
+#include "rank.hpp"
 #include "surrogate.hpp"
 
 namespace gtmp {
@@ -51,9 +52,8 @@ struct Informed {
 // the clipped box is used iff its volume is below the frame box's
 // prod 2 r_i (both multiplied in coordinate order).  Without a bound
 // (c = +inf or c >= penalty) the draws are uniform in the box.
-__global__ void k_informed_prep(int d, const float *q0, const float *goals, const float *c_dev, float penalty,
-                                BoxArgs L, Informed *out) {
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void informed_prep(int d, const float *q0, const float *goals, const float *c_dev,
+                                              float penalty, const BoxArgs &L, Informed *out) {
     const float c = *c_dev;
     Informed I;
     I.bounded = !(__builtin_isinf(c) || c >= penalty || c != c);
@@ -105,6 +105,11 @@ __global__ void k_informed_prep(int d, const float *q0, const float *goals, cons
     }
     I.clipped = vol_c < vol_r ? 1 : 0;
     *out = I;
+}
+
+__global__ void k_informed_prep(int d, const float *q0, const float *goals, const float *c_dev, float penalty,
+                                BoxArgs L, Informed *out) {
+    if (threadIdx.x == 0) informed_prep(d, q0, goals, c_dev, penalty, L, out);
 }
 
 __device__ __forceinline__ uint4 words(uint32_t k0, uint32_t k1, uint32_t n, uint32_t m, uint32_t stage,
@@ -187,22 +192,24 @@ __device__ int informed_draw(int d, const float *lo, const float *wd, const floa
 // ------------------------------------------------------------------ expansion
 
 // Copy the old samples of every layer into the new (wider) layout.
-__global__ void k_relayout(int M, int n_old, int N, int d, const float *Q_old, float *Q_new) {
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t total = (uint64_t)M * n_old * d;
-    if (t >= total) return;
+__device__ __forceinline__ void relayout_one(uint64_t t, int n_old, int N, int d, const float *Q_old, float *Q_new) {
     const uint64_t j = t % d, mn = t / d;
     const uint64_t n = mn % n_old, m = mn / n_old;
     Q_new[(m * N + n) * d + j] = Q_old[t];
 }
 
+__global__ void k_relayout(int M, int n_old, int N, int d, const float *Q_old, float *Q_new) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (uint64_t)M * n_old * d) relayout_one(t, n_old, N, d, Q_old, Q_new);
+}
+
 // Mixture coin and heuristic rank of the new slots of one layer (Sec. III-A
 // coin flip; Alg. 1 expand-samples): rank[n] = index among this layer's
 // heuristic draws, -1 for a uniform-half draw.  One block.
-__global__ void __launch_bounds__(1024) k_coin_rank(int m, int n_old, int N, uint32_t k0, uint32_t k1, uint32_t stage,
-                                                    const Informed *I, int heuristic_ok, int32_t *rank) {
-    __shared__ int wsum[1024 / kWave];
-    __shared__ int carry;
+// (wsum, carry: the block's LDS, blockDim.x / 64 words and one)
+__device__ __forceinline__ void coin_rank_block(int m, int n_old, int N, uint32_t k0, uint32_t k1, uint32_t stage,
+                                                const Informed *I, int heuristic_ok, int32_t *rank, int *wsum,
+                                                int &carry) {
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     const bool allow = heuristic_ok && I->bounded;
@@ -230,6 +237,13 @@ __global__ void __launch_bounds__(1024) k_coin_rank(int m, int n_old, int N, uin
     }
 }
 
+__global__ void __launch_bounds__(1024) k_coin_rank(int m, int n_old, int N, uint32_t k0, uint32_t k1, uint32_t stage,
+                                                    const Informed *I, int heuristic_ok, int32_t *rank) {
+    __shared__ int wsum[1024 / kWave];
+    __shared__ int carry;
+    coin_rank_block(m, n_old, N, k0, k1, stage, I, heuristic_ok, rank, wsum, carry);
+}
+
 // Fill the new slots of layer m, one wave per slot (four per block): a
 // heuristic slot of rank h takes the midpoint of the h-th closest pair (a
 // uniform draw when fewer pairs exist), every other slot a draw of the
@@ -244,14 +258,12 @@ constexpr int kExpandThreads = 256;
 constexpr int kExpandSlots = kExpandThreads / kWave;  // slots per block
 static_assert(kMaxAttempts % kWave == 0, "whole rounds of attempts");
 
-__global__ void __launch_bounds__(kExpandThreads) k_expand_layer(int m, int n_old, int N, int d, BoxArgs B, uint32_t k0,
-                                                                 uint32_t k1, uint32_t stage, const Informed *Ip,
-                                                                 const int32_t *rank, const uint32_t *sorted_pairs,
-                                                                 uint64_t n_pairs, const uint32_t *n_avail, int nv,
-                                                                 const float *U, const float *Vv, float *Qm) {
+// Slot n of layer m, by one wave.
+__device__ __forceinline__ void fill_slot(int m, int n, int d, const BoxArgs &B, uint32_t k0, uint32_t k1,
+                                          uint32_t stage, const Informed *Ip, const int32_t *rank,
+                                          const uint32_t *sorted_pairs, uint64_t n_pairs, const uint32_t *n_avail,
+                                          int nv, const float *U, const float *Vv, float *Qm) {
     const int lane = lane_id();
-    const int n = n_old + (int)blockIdx.x * kExpandSlots + (int)(threadIdx.x / kWave);  // wave-uniform
-    if (n >= N) return;
     const Informed I = *Ip;
     const int h = rank[n];
     const uint64_t avail = n_avail ? (uint64_t)*n_avail : n_pairs;
@@ -285,6 +297,15 @@ __global__ void __launch_bounds__(kExpandThreads) k_expand_layer(int m, int n_ol
         }
         for (int i = 0; i < d; ++i) Qm[(size_t)n * d + i] = x[i];
     }
+}
+
+__global__ void __launch_bounds__(kExpandThreads) k_expand_layer(int m, int n_old, int N, int d, BoxArgs B, uint32_t k0,
+                                                                 uint32_t k1, uint32_t stage, const Informed *Ip,
+                                                                 const int32_t *rank, const uint32_t *sorted_pairs,
+                                                                 uint64_t n_pairs, const uint32_t *n_avail, int nv,
+                                                                 const float *U, const float *Vv, float *Qm) {
+    const int n = n_old + (int)blockIdx.x * kExpandSlots + (int)(threadIdx.x / kWave);  // wave-uniform
+    if (n < N) fill_slot(m, n, d, B, k0, k1, stage, Ip, rank, sorted_pairs, n_pairs, n_avail, nv, U, Vv, Qm);
 }
 
 // Surrogate bias of the heuristic half: midpoints of the K closest pairs
@@ -435,6 +456,195 @@ hipError_t launch_expand(const gtmp_problem &p, const float *q0, const float *go
         const unsigned blocks = (unsigned)((N - n_old + kExpandSlots - 1) / kExpandSlots);
         hipLaunchKernelGGL(k_expand_layer, dim3(blocks), dim3(kExpandThreads), 0, s, m, n_old, N, d, B, k0, k1, st, I,
                            rank, sorted, heuristic_ok ? K : 0, n_avail, nv, U, Vv, Q_new + (size_t)m * N * d);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ expansions of several plans
+// Layer m's neighbour sets of a job, as launch_expand forms them.
+struct LayerPairs {
+    const float *U, *V;
+    int nu, nv;
+    uint64_t npairs, K;
+};
+
+__host__ __device__ inline LayerPairs layer_pairs(const ExpandJob &J, int m) {
+    LayerPairs L;
+    L.U = m == 0 ? J.q0 : J.Q_new + (size_t)(m - 1) * J.N * J.d;
+    L.nu = m == 0 ? 1 : J.N;
+    L.V = m == J.M - 1 ? J.goals : J.Q_new + (size_t)(m + 1) * J.N * J.d;
+    L.nv = m == J.M - 1 ? J.G : J.n_old;
+    L.npairs = (uint64_t)L.nu * (uint64_t)L.nv;
+    const uint64_t cap = (uint64_t)(J.N - J.n_old);
+    L.K = L.npairs < cap ? L.npairs : cap;
+    return L;
+}
+
+__device__ __forceinline__ BoxArgs job_box(const ExpandJob &J) {
+    BoxArgs B{};
+    for (int j = 0; j < J.d; ++j) {
+        B.lo[j] = J.lo[j];
+        B.hi[j] = J.hi[j];
+        B.wd[j] = J.hi[j] - J.lo[j];
+    }
+    return B;
+}
+
+__device__ __forceinline__ bool job_active(const ExpandJob &J, int m) { return m < J.M && J.n_old < J.N; }
+
+__global__ void k_bx_prep(const ExpandJob *jobs) {
+    const ExpandJob &J = jobs[blockIdx.x];
+    if (threadIdx.x == 0)
+        informed_prep(J.d, J.q0, J.goals, J.c_dev, J.penalty, job_box(J), static_cast<Informed *>(J.informed));
+}
+
+__global__ void __launch_bounds__(256) k_bx_relayout(const ExpandJob *jobs) {
+    const ExpandJob &J = jobs[blockIdx.y];
+    const uint64_t total = (uint64_t)J.M * J.n_old * J.d;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x)
+        relayout_one(t, J.n_old, J.N, J.d, J.Q_old, J.Q_new);
+}
+
+__global__ void __launch_bounds__(1024) k_bx_coin(const ExpandJob *jobs, int m) {
+    __shared__ int wsum[1024 / kWave];
+    __shared__ int carry;
+    const ExpandJob &J = jobs[blockIdx.x];
+    if (!job_active(J, m)) return;
+    const int heuristic_ok = layer_pairs(J, m).npairs > 0;
+    coin_rank_block(m, J.n_old, J.N, J.k0, J.k1, J.stage, static_cast<const Informed *>(J.informed), heuristic_ok,
+                    J.rank, wsum, carry);
+}
+
+__device__ __forceinline__ bool job_ranks_small(const ExpandJob &J, int m, LayerPairs &L) {
+    if (!job_active(J, m)) return false;
+    L = layer_pairs(J, m);
+    return L.npairs > 0 && L.npairs <= (uint64_t)rank::kRankSortCap;
+}
+
+__device__ __forceinline__ bool job_ranks_large(const ExpandJob &J, int m, LayerPairs &L) {
+    if (!job_active(J, m)) return false;
+    L = layer_pairs(J, m);
+    return L.npairs > (uint64_t)rank::kRankSortCap;
+}
+
+__global__ void __launch_bounds__(rank::kRankSortThreads) k_bx_rank_small(const ExpandJob *jobs, int m) {
+    __shared__ uint64_t lds[rank::kRankSortCap];
+    const ExpandJob &J = jobs[blockIdx.x];
+    LayerPairs L;
+    if (!job_ranks_small(J, m, L)) return;
+    rank::rank_small_block(J.d, L.U, L.nv, L.V, (uint32_t)L.npairs, (uint32_t)L.K, J.sorted, lds);
+}
+
+__global__ void __launch_bounds__(256) k_bx_rank_init(const ExpandJob *jobs, int m) {
+    const ExpandJob &J = jobs[blockIdx.x];
+    LayerPairs L;
+    if (!job_ranks_large(J, m, L)) return;
+    rank::rank_init_block((uint32_t)L.K, reinterpret_cast<uint32_t *>(J.rankws + J.rank_off_hist),
+                          reinterpret_cast<rank::RankState *>(J.rankws));
+}
+
+__global__ void __launch_bounds__(256) k_bx_rank_pass(const ExpandJob *jobs, int m, int pass) {
+    __shared__ uint32_t h[rank::kRankBins];
+    __shared__ uint32_t part[256];
+    __shared__ bool last;
+    const ExpandJob &J = jobs[blockIdx.y];
+    LayerPairs L;
+    if (!job_ranks_large(J, m, L)) return;  // every block of the job returns alike
+    rank::rank_pass_block(pass, J.d, L.U, L.nv, L.V, (uint32_t)L.npairs, (uint32_t)L.K,
+                          reinterpret_cast<uint32_t *>(J.rankws + J.rank_off_hist),
+                          reinterpret_cast<rank::RankState *>(J.rankws), blockIdx.x, gridDim.x, h, part, last);
+}
+
+__global__ void __launch_bounds__(256) k_bx_rank_compact(const ExpandJob *jobs, int m) {
+    const ExpandJob &J = jobs[blockIdx.y];
+    LayerPairs L;
+    if (!job_ranks_large(J, m, L)) return;
+    rank::rank_compact_block(J.d, L.U, L.nv, L.V, (uint32_t)L.npairs, reinterpret_cast<rank::RankState *>(J.rankws),
+                             reinterpret_cast<uint64_t *>(J.rankws + J.rank_off_cand), J.rank_cap, blockIdx.x,
+                             gridDim.x);
+}
+
+__global__ void __launch_bounds__(rank::kRankSortThreads) k_bx_rank_sort(const ExpandJob *jobs, int m) {
+    __shared__ uint64_t lds[rank::kRankSortCap];
+    const ExpandJob &J = jobs[blockIdx.x];
+    LayerPairs L;
+    if (!job_ranks_large(J, m, L)) return;
+    rank::rank_sort_block((uint32_t)L.K, reinterpret_cast<const rank::RankState *>(J.rankws),
+                          reinterpret_cast<uint64_t *>(J.rankws + J.rank_off_cand), J.rank_cap, J.sorted, lds);
+}
+
+__global__ void __launch_bounds__(kExpandThreads) k_bx_fill(const ExpandJob *jobs, int m) {
+    const ExpandJob &J = jobs[blockIdx.y];
+    if (!job_active(J, m)) return;
+    const int n = J.n_old + (int)blockIdx.x * kExpandSlots + (int)(threadIdx.x / kWave);  // wave-uniform
+    if (n >= J.N) return;
+    const LayerPairs L = layer_pairs(J, m);
+    fill_slot(m, n, J.d, job_box(J), J.k0, J.k1, J.stage, static_cast<const Informed *>(J.informed), J.rank, J.sorted,
+              L.npairs > 0 ? L.K : 0, nullptr, L.nv, L.U, L.V, J.Q_new + (size_t)m * J.N * J.d);
+}
+
+void fill_expand_job(ExpandJob &J, const gtmp_problem &p, const float *q0, const float *goals, const float *Q_old,
+                     int n_old, float *Q_new, const float *c_dev, uint64_t seed, uint64_t stage, void *workspace) {
+    const ExpandPlan e = make_expand_plan(p, false);
+    const RankPlan rp = make_rank_plan(e.max_k);
+    char *ws = static_cast<char *>(workspace);
+    J = ExpandJob{};
+    J.d = p.d; J.M = p.M; J.N = p.N; J.G = p.G; J.n_old = n_old;
+    J.penalty = p.penalty;
+    for (int j = 0; j < p.d; ++j) {
+        J.lo[j] = p.lo[j];
+        J.hi[j] = p.hi[j];
+    }
+    J.k0 = (uint32_t)(seed & 0xffffffffu);
+    J.k1 = (uint32_t)(seed >> 32);
+    J.stage = (uint32_t)stage;
+    J.q0 = q0; J.goals = goals; J.Q_old = Q_old; J.Q_new = Q_new; J.c_dev = c_dev;
+    J.informed = ws + e.off_informed;
+    J.rank = reinterpret_cast<int32_t *>(ws + e.off_rank);
+    J.sorted = reinterpret_cast<uint32_t *>(ws + e.off_sorted);
+    J.rankws = ws + e.off_rankws;
+    J.rank_cap = rp.cap;
+    J.rank_off_hist = (uint32_t)rp.off_hist;
+    J.rank_off_cand = (uint32_t)rp.off_cand;
+}
+
+hipError_t launch_expand_jobs(const ExpandJob *jobs_dev, const std::vector<ExpandJob> &jobs, hipStream_t s) {
+    const unsigned nj = (unsigned)jobs.size();
+    if (nj == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bx_prep, dim3(nj), dim3(64), 0, s, jobs_dev);
+    uint64_t most = 0;
+    int maxM = 0;
+    for (const ExpandJob &J : jobs) {
+        most = std::max(most, (uint64_t)J.M * J.n_old * J.d);
+        maxM = std::max(maxM, J.M);
+    }
+    if (most > 0)
+        hipLaunchKernelGGL(k_bx_relayout, dim3((unsigned)std::min<uint64_t>((most + 255) / 256, 4096), nj), dim3(256), 0,
+                           s, jobs_dev);
+    for (int m = 0; m < maxM; ++m) {
+        bool any_small = false;
+        uint64_t large = 0;
+        int slots = 0;
+        for (const ExpandJob &J : jobs) {
+            if (m >= J.M || J.n_old >= J.N) continue;
+            const LayerPairs L = layer_pairs(J, m);
+            if (L.npairs > 0 && L.npairs <= (uint64_t)rank::kRankSortCap) any_small = true;
+            if (L.npairs > (uint64_t)rank::kRankSortCap) large = std::max(large, L.npairs);
+            slots = std::max(slots, J.N - J.n_old);
+        }
+        if (slots == 0) continue;
+        hipLaunchKernelGGL(k_bx_coin, dim3(nj), dim3(1024), 0, s, jobs_dev, m);
+        if (any_small) hipLaunchKernelGGL(k_bx_rank_small, dim3(nj), dim3(rank::kRankSortThreads), 0, s, jobs_dev, m);
+        if (large > 0) {
+            const unsigned bx = (unsigned)std::min<uint64_t>((large + 1023) / 1024, 1024);
+            hipLaunchKernelGGL(k_bx_rank_init, dim3(nj), dim3(256), 0, s, jobs_dev, m);
+            for (int pass = 0; pass < rank::kRankPasses; ++pass)
+                hipLaunchKernelGGL(k_bx_rank_pass, dim3(bx, nj), dim3(256), 0, s, jobs_dev, m, pass);
+            hipLaunchKernelGGL(k_bx_rank_compact, dim3(bx, nj), dim3(256), 0, s, jobs_dev, m);
+            hipLaunchKernelGGL(k_bx_rank_sort, dim3(nj), dim3(rank::kRankSortThreads), 0, s, jobs_dev, m);
+        }
+        hipLaunchKernelGGL(k_bx_fill, dim3((unsigned)((slots + kExpandSlots - 1) / kExpandSlots), nj),
+                           dim3(kExpandThreads), 0, s, jobs_dev, m);
     }
     return hipGetLastError();
 }

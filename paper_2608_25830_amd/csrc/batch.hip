@@ -682,6 +682,7 @@ BatchLayout make_batch_layout(const gtmp_plan_desc *plans, int n, const gtmp_bat
     L.off_grids = off; off = up(off + sizeof(ObsGrid) * (size_t)n);
     L.off_tables = off; off = up(off + sizeof(BPlan) * (size_t)n * (size_t)max_stages);
     L.off_bases = off; off = up(off + sizeof(uint64_t) * (size_t)n * (size_t)max_stages);
+    L.off_jobs = off; off = up(off + sizeof(ExpandJob) * (size_t)n * (size_t)max_stages);
     L.off_counters = off; off = up(off + sizeof(uint32_t) * kBatchStageCounters * (size_t)max_stages + 256);
     L.total = off;
     (void)o;
@@ -703,6 +704,7 @@ struct BatchGraph {
     std::vector<ArmParams> arms;
     std::vector<BPlan> host;
     std::vector<uint64_t> bases;
+    std::vector<ExpandJob> jobs;
 };
 constexpr size_t kMaxBatchGraphs = 64;
 std::mutex g_batch_mu;
@@ -732,7 +734,8 @@ std::string batch_key(const gtmp_plan_desc *plans, int n, const gtmp_batch_opts 
 }
 
 hipError_t upload_tables(const BatchLayout &L, void *workspace, const std::vector<ArmParams> &arms,
-                         const std::vector<BPlan> &host, const std::vector<uint64_t> &bases, hipStream_t s) {
+                         const std::vector<BPlan> &host, const std::vector<uint64_t> &bases,
+                         const std::vector<ExpandJob> &jobs, hipStream_t s) {
     // after the work already on the stream (which may still read an earlier
     // table) is done
     char *ws = static_cast<char *>(workspace);
@@ -742,7 +745,9 @@ hipError_t upload_tables(const BatchLayout &L, void *workspace, const std::vecto
     if (err != hipSuccess) return err;
     err = hipMemcpy(ws + L.off_tables, host.data(), sizeof(BPlan) * host.size(), hipMemcpyHostToDevice);
     if (err != hipSuccess) return err;
-    return hipMemcpy(ws + L.off_bases, bases.data(), sizeof(uint64_t) * bases.size(), hipMemcpyHostToDevice);
+    err = hipMemcpy(ws + L.off_bases, bases.data(), sizeof(uint64_t) * bases.size(), hipMemcpyHostToDevice);
+    if (err != hipSuccess || jobs.empty()) return err;
+    return hipMemcpy(ws + L.off_jobs, jobs.data(), sizeof(ExpandJob) * jobs.size(), hipMemcpyHostToDevice);
 }
 }  // namespace
 
@@ -756,7 +761,8 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         if (it != g_batch_graphs.end()) {
             auto ow = g_batch_ws_owner.find(workspace);
             if (ow == g_batch_ws_owner.end() || ow->second != key) {
-                hipError_t err = upload_tables(L, workspace, it->second.arms, it->second.host, it->second.bases, s);
+                hipError_t err = upload_tables(L, workspace, it->second.arms, it->second.host, it->second.bases,
+                                               it->second.jobs, s);
                 if (err != hipSuccess) return err;
                 g_batch_ws_owner[workspace] = key;
             }
@@ -930,8 +936,32 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
         I.samples = sb;
         info[st] = I;
     }
+    // the growing plans' expansions of each stage, run together (one launch
+    // per kernel and layer step for all of them)
+    std::vector<ExpandJob> jobs;
+    std::vector<size_t> job_begin(L.max_stages + 1, 0);
+    for (int st = 0; st < L.max_stages; ++st) {
+        job_begin[st] = jobs.size();
+        for (int p = 0; p < n; ++p) {
+            if (plans[p].mode != GTMP_ANYTIME_GROWING || st >= (int)L.schedules[p].size()) continue;
+            const StageShape sh = L.schedules[p][st];
+            gtmp_problem pp = plans[p].problem;
+            pp.M = sh.M;
+            pp.N = sh.N;
+            const PlanOffsets &PO = L.plan_off[p];
+            float *Qa = reinterpret_cast<float *>(ws + PO.Q);
+            float *Qb = reinterpret_cast<float *>(ws + PO.Q2);
+            ExpandJob J;
+            fill_expand_job(J, pp, plans[p].q0, plans[p].goals, (st & 1) ? Qa : Qb, sh.n_old, (st & 1) ? Qb : Qa,
+                            out.best_cost + p, plans[p].seed, (uint64_t)st, ws + PO.expand);
+            jobs.push_back(J);
+        }
+    }
+    job_begin[L.max_stages] = jobs.size();
+    const ExpandJob *jobs_dev = reinterpret_cast<const ExpandJob *>(ws + L.off_jobs);
+
     // tables are written once, before any work is enqueued
-    hipError_t err = upload_tables(L, workspace, arms, host, host_bases, s);
+    hipError_t err = upload_tables(L, workspace, arms, host, host_bases, jobs, s);
     if (err != hipSuccess) return err;
     {
         std::lock_guard<std::mutex> lk(g_batch_mu);
@@ -968,19 +998,9 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
             if (I.samples > 0)
                 hipLaunchKernelGGL(k_batch_sample, dim3((unsigned)((I.samples + 255) / 256)), dim3(256), 0, st_, T,
                                    I.count, Bs, I.samples);
-            for (int p = 0; p < n; ++p) {
-                if (plans[p].mode != GTMP_ANYTIME_GROWING || st >= (int)L.schedules[p].size()) continue;
-                const StageShape sh = L.schedules[p][st];
-                gtmp_problem pp = plans[p].problem;
-                pp.M = sh.M;
-                pp.N = sh.N;
-                const PlanOffsets &PO = L.plan_off[p];
-                float *Qa = reinterpret_cast<float *>(ws + PO.Q);
-                float *Qb = reinterpret_cast<float *>(ws + PO.Q2);
-                float *dst = (st & 1) ? Qb : Qa;
-                float *src = (st & 1) ? Qa : Qb;
-                hipError_t e = launch_expand(pp, plans[p].q0, plans[p].goals, src, sh.n_old, dst, out.best_cost + p,
-                                             plans[p].seed, (uint64_t)st, ws + PO.expand, st_);
+            if (job_begin[st + 1] > job_begin[st]) {
+                const std::vector<ExpandJob> stage_jobs(jobs.begin() + job_begin[st], jobs.begin() + job_begin[st + 1]);
+                hipError_t e = launch_expand_jobs(jobs_dev + job_begin[st], stage_jobs, st_);
                 if (e != hipSuccess) return e;
             }
             // vertices per group
@@ -1075,7 +1095,8 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
     {
         std::lock_guard<std::mutex> lk(g_batch_mu);
         if (g_batch_graphs.size() < kMaxBatchGraphs) {
-            g_batch_graphs.emplace(key, BatchGraph{exec, std::move(arms), std::move(host), std::move(host_bases)});
+            g_batch_graphs.emplace(key, BatchGraph{exec, std::move(arms), std::move(host), std::move(host_bases),
+                                                   std::move(jobs)});
             return hipGraphLaunch(exec, s);
         }
     }

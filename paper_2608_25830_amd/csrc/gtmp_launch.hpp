@@ -89,6 +89,30 @@ struct ExpandPlan {
     size_t off_bX, off_bz, off_bfree, off_bcount, off_bws, bws_bytes;
     size_t total;
 };
+// One growing plan's expansion inside a batch: the arguments of
+// launch_expand (no surrogate bias) with the workspace carved as
+// make_expand_plan lays it out.  launch_expand_jobs runs the expansions of
+// several plans together, kernel by kernel (each launch covers every plan),
+// with the same kernels' device code and results as launch_expand.
+struct ExpandJob {
+    int d, M, N, G, n_old;
+    float penalty;
+    float lo[GTMP_MAX_DOF], hi[GTMP_MAX_DOF];
+    uint32_t k0, k1, stage;
+    const float *q0, *goals, *Q_old;
+    float *Q_new;
+    const float *c_dev;
+    void *informed;
+    int32_t *rank;
+    uint32_t *sorted;
+    char *rankws;
+    uint32_t rank_cap;
+    uint32_t rank_off_hist, rank_off_cand;
+};
+void fill_expand_job(ExpandJob &J, const gtmp_problem &p, const float *q0, const float *goals, const float *Q_old,
+                     int n_old, float *Q_new, const float *c_dev, uint64_t seed, uint64_t stage, void *workspace);
+hipError_t launch_expand_jobs(const ExpandJob *jobs_dev, const std::vector<ExpandJob> &jobs, hipStream_t s);
+
 // closest pairs scored by the surrogate per new slot of a layer
 constexpr int kBiasCandidates = 4;
 struct SurNet;
@@ -184,7 +208,7 @@ struct BatchLayout {
     int n, max_stages;
     std::vector<PlanOffsets> plan_off;
     std::vector<std::vector<StageShape>> schedules;
-    size_t off_arm, off_grids, off_tables, off_bases, off_counters, total;
+    size_t off_arm, off_grids, off_tables, off_bases, off_jobs, off_counters, total;
 };
 BatchLayout make_batch_layout(const gtmp_plan_desc *plans, int n, const gtmp_batch_opts &o);
 struct BatchOut {
