@@ -547,8 +547,9 @@ gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_b
  * path with the upward ray {(z_x, y): y > z_y}, +1 moving in +x.  Labels add
  * along concatenation, and two start-to-goal paths avoiding the obstacles
  * have equal labels iff they wind equally around every z_i (the discrete form
- * of the h-signature).  Packed: field i = bits 4i..4i+3 of a uint64, value
- * (count + 8) for chains of at most 7 edges (M <= 6), fields past k at 8.
+ * of the h-signature).  Packed as two uint64 words per label: field i is
+ * byte (i mod 8) of word (i / 8), value (count + 128), fields past k at 128;
+ * chains have at most 127 edges (M <= 126), so no count leaves -127..127.
  * The crossing decision is FP32 with a fixed order: u, v straddle z_x
  * ((u_x < z_x) != (v_x < z_x)) and the crossing lies above z, i.e.
  * cr = fl(fl(dx * ey) - fl(dy * ex)) < 0 when dx > 0, > 0 when dx < 0, with
@@ -558,7 +559,7 @@ gtmp_status gtmp_plan_batch(const gtmp_plan_desc *plans, int32_t n, const gtmp_b
  * keeping at most L <= 64 labels per vertex (a full list keeps the L
  * cheapest; *overflow counts dropped labels: the result is exact when it is
  * 0).  Edges with cost >= penalty are absent.  Outputs for the start vertex:
- * labels [L], costs [L], chains [L][M+1] (layer indices, then the goal),
+ * labels [L][2], costs [L], chains [L][M+1] (layer indices, then the goal),
  * count [1] (classes found); device pointers; reps device float [k][2]. */
 gtmp_status gtmp_class_sweep_workspace_size(int32_t M, int32_t N, int32_t L, size_t *bytes);
 gtmp_status gtmp_class_sweep(int32_t M, int32_t N, int32_t G, int32_t L, const float *Q, const float *q0,
@@ -569,7 +570,7 @@ gtmp_status gtmp_class_sweep(int32_t M, int32_t N, int32_t G, int32_t L, const f
 /* Anytime-GTMP with the class archive: `stages` restart stages (samples of
  * key (seed, stage), edge check, class sweep), each class's best path kept
  * (a later stage replaces an entry only with a strictly lower cost).  Archive
- * (device, capacity cap): a_labels [cap], a_costs [cap], a_stage [cap],
+ * (device, capacity cap): a_labels [cap][2], a_costs [cap], a_stage [cap],
  * a_wp [cap][M+2][2] waypoints, a_count [1]; overflow [1] counts labels
  * dropped by full vertex lists or a full archive.  prob->d must be 2 and
  * scene->wdim 2 (point robot). */

@@ -830,7 +830,7 @@ gtmp_status gtmp_surrogate_threshold(const float *logits, const uint8_t *flags, 
 
 // ------------------------------------------------------------------ class-augmented sweep
 static gtmp_status check_class_sizes(int M, int N, int G, int L, int k) {
-    if (M < 1 || M > 6) return fail(GTMP_EINVAL, "class sweep needs 1 <= M <= 6 (labels of at most 7 edges)");
+    if (M < 1 || M > 126) return fail(GTMP_EINVAL, "class sweep needs 1 <= M <= 126 (labels of at most 127 edges)");
     if (N < 1 || N >= (1 << 24) || G < 1 || G >= (1 << 24)) return fail(GTMP_EINVAL, "N=%d G=%d out of range", N, G);
     if (L < 1 || L > 64) return fail(GTMP_EINVAL, "L=%d outside 1..64", L);
     if (k < 0 || k > 16) return fail(GTMP_EINVAL, "k=%d outside 0..16 representative points", k);

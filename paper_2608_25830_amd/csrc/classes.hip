@@ -3,12 +3,14 @@
 // point robots.
 //
 // Class label of an edge: its signed crossings with upward rays from up to 16
-// representative obstacle points, one 4-bit two's-complement field per point
-// in a 64-bit word (labels of chains of at most 7 edges stay in -7..7; the
-// empty label has every field at 8 in offset-binary form, so chain labels are
-// sums of edge labels in offset binary).  Fields are added without carries
-// between them (SWAR addition).  The crossing decision is taken in FP32 with
-// a fixed operation order; this file is compiled without contraction.
+// representative obstacle points, one 8-bit field per point in a 128-bit
+// label held as two 64-bit words (fields 0..7 in the first, 8..15 in the
+// second).  A chain of at most 127 edges (M <= 126) crosses a ray at most 127
+// times, so every count fits a field: chain labels are kept in offset binary
+// (the empty label has every field at 128) and edge labels in two's
+// complement, and a sum is a field-wise addition modulo 256 with no carries
+// between fields (SWAR addition).  The crossing decision is taken in FP32
+// with a fixed operation order; this file is compiled without contraction.
 //
 // Sweep: one wave per vertex u.  Lane j holds entry j of u's list (label, least
 // cost of a chain from u to the goal with that label, successor).  For every
@@ -23,16 +25,29 @@
 namespace gtmp {
 
 constexpr int kClassMaxReps = 16;
-constexpr uint64_t kEmptyLabel = 0x8888888888888888ull;
-constexpr uint64_t kNibbleHigh = 0x8888888888888888ull;
+constexpr uint64_t kByteHigh = 0x8080808080808080ull;
+constexpr uint64_t kEmptyWord = 0x8080808080808080ull;  // eight fields at zero, offset binary
+
+struct Label {
+    uint64_t w[2];
+};
 
 __device__ __forceinline__ uint64_t swar_add(uint64_t x, uint64_t y) {
-    return ((x & ~kNibbleHigh) + (y & ~kNibbleHigh)) ^ ((x ^ y) & kNibbleHigh);
+    return ((x & ~kByteHigh) + (y & ~kByteHigh)) ^ ((x ^ y) & kByteHigh);
 }
 
-// Signed crossings of u -> v with the upward rays of reps[0..k), packed.
-__device__ __forceinline__ uint64_t edge_label(float ux, float uy, float vx, float vy, const float *reps, int k) {
-    uint64_t lab = 0;
+__device__ __forceinline__ Label label_add(const Label &a, const Label &b) {
+    return Label{{swar_add(a.w[0], b.w[0]), swar_add(a.w[1], b.w[1])}};
+}
+
+__device__ __forceinline__ bool label_eq(const Label &a, const Label &b) {
+    return a.w[0] == b.w[0] && a.w[1] == b.w[1];
+}
+
+// Signed crossings of u -> v with the upward rays of reps[0..k), packed in
+// two's complement.
+__device__ __forceinline__ Label edge_label(float ux, float uy, float vx, float vy, const float *reps, int k) {
+    Label lab{{0ull, 0ull}};
     for (int i = 0; i < k; ++i) {
         const float zx = reps[2 * i], zy = reps[2 * i + 1];
         if ((ux < zx) == (vx < zx)) continue;
@@ -40,8 +55,8 @@ __device__ __forceinline__ uint64_t edge_label(float ux, float uy, float vx, flo
         const float cross = dx * ey - dy * ex;
         const bool above = dx > 0.f ? cross < 0.f : cross > 0.f;
         if (!above) continue;
-        const uint64_t nib = dx > 0.f ? 1ull : 15ull;  // +1 or -1 mod 16
-        lab |= nib << (4 * i);
+        const uint64_t field = dx > 0.f ? 1ull : 255ull;  // +1 or -1 mod 256
+        lab.w[i >> 3] |= field << (8 * (i & 7));
     }
     return lab;
 }
@@ -52,12 +67,31 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ __forceinline__ Label readlane_label(const Label &x, int l) {
+    return Label{{readlane64(x.w[0], l), readlane64(x.w[1], l)}};
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int l) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ Label load_label(const uint64_t *p, size_t i) {
+    const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(p)[i];
+    return Label{{v.x, v.y}};
+}
+
+__device__ __forceinline__ void store_label(uint64_t *p, size_t i, const Label &l) {
+    reinterpret_cast<ulonglong2 *>(p)[i] = make_ulonglong2(l.w[0], l.w[1]);
+}
+
 struct ClassLists {
-    uint64_t *lab;   // [M][N][L]
+    uint64_t *lab;   // [M][N][L][2]
     float *cost;     // [M][N][L]
     uint32_t *nxt;   // [M][N][L]: successor << 8 | its entry
     int32_t *cnt;    // [M][N]
-    uint64_t *s_lab; // start list [L]
+    uint64_t *s_lab; // start list [L][2]
     float *s_cost;
     uint32_t *s_nxt;
     int32_t *s_cnt;  // [1]
@@ -79,7 +113,7 @@ __global__ void __launch_bounds__(256) k_class_layer(int m, int M, int N, int G,
     const float ux = pu[0], uy = pu[1];
     const int nv = m == M - 1 ? G : N;
 
-    uint64_t my_lab = 0;
+    Label my_lab{{0ull, 0ull}};
     float my_cost = __builtin_inff();
     uint32_t my_nxt = 0;
     int cnt = 0;
@@ -100,16 +134,16 @@ __global__ void __launch_bounds__(256) k_class_layer(int m, int M, int N, int G,
         }
         c = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(c)));  // one value for the wave
         if (!(c < penalty)) continue;  // absent or failed edge
-        const uint64_t kap = edge_label(ux, uy, pv[0], pv[1], reps, k);
+        const Label kap = edge_label(ux, uy, pv[0], pv[1], reps, k);
         // candidates: one per lane
         int n_src;
-        uint64_t cl = 0;
+        Label cl{{0ull, 0ull}};
         float cc = __builtin_inff();
         uint32_t cn = 0;
         if (m == M - 1) {
             n_src = 1;
             if (lane == 0) {
-                cl = swar_add(kap, kEmptyLabel);
+                cl = label_add(kap, Label{{kEmptyWord, kEmptyWord}});
                 cc = c;
                 cn = (uint32_t)v << 8;
             }
@@ -118,7 +152,7 @@ __global__ void __launch_bounds__(256) k_class_layer(int m, int M, int N, int G,
             n_src = __builtin_amdgcn_readfirstlane(CL.cnt[(size_t)mm * N + v]);
             if (lane < n_src) {
                 const size_t base = ((size_t)mm * N + v) * L + lane;
-                cl = swar_add(kap, CL.lab[base]);
+                cl = label_add(kap, load_label(CL.lab, base));
                 cc = c + CL.cost[base];
                 cn = ((uint32_t)v << 8) | (uint32_t)lane;
             }
@@ -129,8 +163,8 @@ __global__ void __launch_bounds__(256) k_class_layer(int m, int M, int N, int G,
         uint64_t matched = 0;
         int src = -1;
         for (int e = 0; e < n_src; ++e) {
-            const uint64_t le = readlane64(cl, e);
-            const bool hit = lane < cnt && my_lab == le;
+            const Label le = readlane_label(cl, e);
+            const bool hit = lane < cnt && label_eq(my_lab, le);
             if (hit) src = e;
             if (ballot(hit) != 0) matched |= 1ull << e;
         }
@@ -156,12 +190,11 @@ __global__ void __launch_bounds__(256) k_class_layer(int m, int M, int N, int G,
         }
         {
             const int from = asrc < 0 ? 0 : asrc;
-            const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)cl, from);
-            const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(cl >> 32), from);
+            const Label pl{{shfl64(cl.w[0], from), shfl64(cl.w[1], from)}};
             const float pc = __shfl(cc, from);
             const uint32_t pn = (uint32_t)__shfl((int)cn, from);
             if (asrc >= 0) {
-                my_lab = ((uint64_t)hi << 32) | lo;
+                my_lab = pl;
                 my_cost = pc;
                 my_nxt = pn;
             }
@@ -171,7 +204,7 @@ __global__ void __launch_bounds__(256) k_class_layer(int m, int M, int N, int G,
         while (pending != 0) {
             const int e = __builtin_ctzll(pending);
             pending &= pending - 1;
-            const uint64_t el = readlane64(cl, e);
+            const Label el = readlane_label(cl, e);
             const float ec = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(cc), e));
             const uint32_t en = __builtin_amdgcn_readlane(cn, e);
             float mx = lane < cnt ? my_cost : -__builtin_inff();
@@ -196,7 +229,7 @@ __global__ void __launch_bounds__(256) k_class_layer(int m, int M, int N, int G,
     // store u's list
     if (m < 0) {
         if (lane < cnt) {
-            CL.s_lab[lane] = my_lab;
+            store_label(CL.s_lab, lane, my_lab);
             CL.s_cost[lane] = my_cost;
             CL.s_nxt[lane] = my_nxt;
         }
@@ -204,7 +237,7 @@ __global__ void __launch_bounds__(256) k_class_layer(int m, int M, int N, int G,
     } else {
         const size_t base = ((size_t)m * N + u) * L;
         if (lane < cnt) {
-            CL.lab[base + lane] = my_lab;
+            store_label(CL.lab, base + lane, my_lab);
             CL.cost[base + lane] = my_cost;
             CL.nxt[base + lane] = my_nxt;
         }
@@ -220,7 +253,8 @@ __global__ void __launch_bounds__(64) k_class_extract(int M, int N, int L, Class
     const int n = *CL.s_cnt;
     if (e == 0) *count = n;
     if (e >= n) return;
-    labels[e] = CL.s_lab[e];
+    labels[2 * e] = CL.s_lab[2 * e];
+    labels[2 * e + 1] = CL.s_lab[2 * e + 1];
     costs[e] = CL.s_cost[e];
     uint32_t nx = CL.s_nxt[e];
     for (int m = 0; m < M; ++m) {
@@ -251,12 +285,12 @@ __global__ void __launch_bounds__(64) k_class_archive(int M, int N, int stage, c
     const int na0 = *a_count;
     int na = na0;
     for (int e = 0; e < n; ++e) {
-        const uint64_t lab = labels[e];
+        const uint64_t lab0 = labels[2 * e], lab1 = labels[2 * e + 1];
         const float c = costs[e];
         int found = -1;
         for (int base = 0; base < na0; base += kWave) {
             const int j = base + lane;
-            const uint64_t hit = ballot(j < na0 && a_lab[j] == lab);
+            const uint64_t hit = ballot(j < na0 && a_lab[2 * j] == lab0 && a_lab[2 * j + 1] == lab1);
             if (hit != 0) {
                 found = base + __builtin_ctzll(hit);
                 break;
@@ -272,7 +306,8 @@ __global__ void __launch_bounds__(64) k_class_archive(int M, int N, int stage, c
         }
         if (slot < 0) continue;
         if (lane == 0) {
-            a_lab[slot] = lab;
+            a_lab[2 * slot] = lab0;
+            a_lab[2 * slot + 1] = lab1;
             a_cost[slot] = c;
             a_stage[slot] = stage;
         }
@@ -295,11 +330,11 @@ ClassPlan make_class_plan(int M, int N, int L) {
     ClassPlan p{};
     size_t o = 0;
     const size_t e = (size_t)M * N * L;
-    p.off_lab = o; o = up256c(o + sizeof(uint64_t) * e);
+    p.off_lab = o; o = up256c(o + 2 * sizeof(uint64_t) * e);
     p.off_cost = o; o = up256c(o + sizeof(float) * e);
     p.off_nxt = o; o = up256c(o + sizeof(uint32_t) * e);
     p.off_cnt = o; o = up256c(o + sizeof(int32_t) * (size_t)M * N);
-    p.off_s = o; o = up256c(o + (sizeof(uint64_t) + sizeof(float) + sizeof(uint32_t)) * (size_t)L + 64);
+    p.off_s = o; o = up256c(o + (2 * sizeof(uint64_t) + sizeof(float) + sizeof(uint32_t)) * (size_t)L + 64);
     p.total = o;
     return p;
 }
@@ -313,9 +348,9 @@ static ClassLists carve_lists(const ClassPlan &p, int L, void *ws, uint32_t *ove
     CL.cnt = reinterpret_cast<int32_t *>(w + p.off_cnt);
     char *s = w + p.off_s;
     CL.s_lab = reinterpret_cast<uint64_t *>(s);
-    CL.s_cost = reinterpret_cast<float *>(s + sizeof(uint64_t) * L);
-    CL.s_nxt = reinterpret_cast<uint32_t *>(s + (sizeof(uint64_t) + sizeof(float)) * L);
-    CL.s_cnt = reinterpret_cast<int32_t *>(s + (sizeof(uint64_t) + sizeof(float) + sizeof(uint32_t)) * L);
+    CL.s_cost = reinterpret_cast<float *>(s + 2 * sizeof(uint64_t) * L);
+    CL.s_nxt = reinterpret_cast<uint32_t *>(s + (2 * sizeof(uint64_t) + sizeof(float)) * L);
+    CL.s_cnt = reinterpret_cast<int32_t *>(s + (2 * sizeof(uint64_t) + sizeof(float) + sizeof(uint32_t)) * L);
     CL.overflow = overflow;
     return CL;
 }
@@ -354,7 +389,7 @@ ClassAnytimePlan make_class_anytime_plan(const gtmp_problem &p, int L) {
     a.off_Cs = o; o = up256c(o + sizeof(float) * N);
     a.off_Ch = o; o = up256c(o + sizeof(float) * (M > 1 ? M - 1 : 1) * N * N);
     a.off_Cl = o; o = up256c(o + sizeof(float) * N * G);
-    a.off_out = o; o = up256c(o + (sizeof(uint64_t) + sizeof(float)) * (size_t)L + sizeof(int32_t) * (size_t)L * (M + 1) + 64);
+    a.off_out = o; o = up256c(o + (2 * sizeof(uint64_t) + sizeof(float)) * (size_t)L + sizeof(int32_t) * (size_t)L * (M + 1) + 64);
     const EdgePlan ep = make_edge_plan(p);
     a.off_edge = o; o = up256c(o + ep.total);
     const ClassPlan cp = make_class_plan(p.M, p.N, L);
@@ -382,9 +417,9 @@ hipError_t launch_plan_classes(const gtmp_problem &p, const SceneParams &scene, 
     float *Cl = reinterpret_cast<float *>(ws + a.off_Cl);
     char *out = ws + a.off_out;
     uint64_t *labels = reinterpret_cast<uint64_t *>(out);
-    float *costs = reinterpret_cast<float *>(out + sizeof(uint64_t) * L);
-    int32_t *chains = reinterpret_cast<int32_t *>(out + (sizeof(uint64_t) + sizeof(float)) * L);
-    int32_t *count = reinterpret_cast<int32_t *>(out + (sizeof(uint64_t) + sizeof(float)) * L +
+    float *costs = reinterpret_cast<float *>(out + 2 * sizeof(uint64_t) * L);
+    int32_t *chains = reinterpret_cast<int32_t *>(out + (2 * sizeof(uint64_t) + sizeof(float)) * L);
+    int32_t *count = reinterpret_cast<int32_t *>(out + (2 * sizeof(uint64_t) + sizeof(float)) * L +
                                                  sizeof(int32_t) * (size_t)L * (p.M + 1));
     hipLaunchKernelGGL(k_class_archive_init, dim3(1), dim3(64), 0, s, a_count, overflow);
     const EdgePlan ep = make_edge_plan(p);

@@ -830,10 +830,11 @@ def gtmp_surrogate_threshold(logits, flags, recall, tau, workspace=None, stream=
 # --------------------------------------------------------------------------- #
 # class-augmented sweep and class archive (2D point robots)
 # --------------------------------------------------------------------------- #
-def unpack_label(lab, k):
-    """Packed class label -> tuple of k signed crossing counts."""
-    lab = int(lab) & 0xFFFFFFFFFFFFFFFF
-    return tuple(((lab >> (4 * i)) & 15) - 8 for i in range(k))
+def unpack_label(words, k):
+    """Packed class label (two 64-bit words) -> tuple of k signed crossing
+    counts."""
+    lab = (int(words[0]) & 0xFFFFFFFFFFFFFFFF) | ((int(words[1]) & 0xFFFFFFFFFFFFFFFF) << 64)
+    return tuple(((lab >> (8 * i)) & 255) - 128 for i in range(k))
 
 
 def gtmp_class_sweep_workspace_size(M, N, L) -> int:
@@ -848,7 +849,7 @@ def class_sweep(pl: "Planner", reps, L=64, stream=None):
     reps_t = torch.from_numpy(np.ascontiguousarray(reps, np.float32).reshape(-1, 2)).to(pl.Q.device)
     k = reps_t.shape[0]
     dev = pl.Q.device
-    labels = torch.empty(L, device=dev, dtype=torch.int64)
+    labels = torch.empty((L, 2), device=dev, dtype=torch.int64)
     costs = torch.empty(L, device=dev)
     chains = torch.empty((L, pl.M + 1), device=dev, dtype=torch.int32)
     count = torch.zeros(1, device=dev, dtype=torch.int32)
@@ -881,7 +882,7 @@ class ClassPlanner:
         self.q0 = torch.from_numpy(np.asarray(w["q0"], np.float32)).to(device)
         self.goals = torch.from_numpy(np.asarray(w["goals"], np.float32).reshape(G, d)).to(device)
         self.reps = torch.from_numpy(np.ascontiguousarray(reps, np.float32).reshape(-1, 2)).to(device)
-        self.a_lab = torch.zeros(cap, device=device, dtype=torch.int64)
+        self.a_lab = torch.zeros((cap, 2), device=device, dtype=torch.int64)
         self.a_cost = torch.zeros(cap, device=device)
         self.a_stage = torch.zeros(cap, device=device, dtype=torch.int32)
         self.a_wp = torch.zeros((cap, M + 2, 2), device=device)

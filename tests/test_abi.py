@@ -238,7 +238,8 @@ def test_anytime_and_batch_options_validate(g):
 
 def test_class_entry_points_validate(g):
     n = C.c_size_t()
-    assert g._lib.gtmp_class_sweep_workspace_size(7, 16, 8, C.byref(n)) == g.GTMP_EINVAL  # M > 6
+    assert g._lib.gtmp_class_sweep_workspace_size(127, 16, 8, C.byref(n)) == g.GTMP_EINVAL  # M > 126
+    assert g._lib.gtmp_class_sweep_workspace_size(16, 16, 8, C.byref(n)) == g.GTMP_OK
     assert g._lib.gtmp_class_sweep_workspace_size(3, 16, 65, C.byref(n)) == g.GTMP_EINVAL  # L > 64
     assert g._lib.gtmp_class_sweep_workspace_size(3, 16, 8, C.byref(n)) == g.GTMP_OK and n.value > 0
     bufs = [C.c_void_p(256)] * 6

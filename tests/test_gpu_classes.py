@@ -76,10 +76,11 @@ def test_full_lists_count_dropped_labels(gt, orc):
     assert min(c for c, _ in got.values()) == pytest.approx(min(c for c, _ in want.values()), rel=P.REL)
 
 
-@pytest.mark.parametrize("scene,N,M,S", [(0, 32, 4, 6), (2, 24, 3, 8)])
-def test_class_archive_matches_oracle(gt, orc, scene, N, M, S):
-    w = wl.make_workload("2d-small", scene, N=N, M=M)
-    reps = w["circles"][:, :2]
+@pytest.mark.parametrize("kind,scene,N,M,S,k", [("2d-small", 0, 32, 4, 6, 16), ("2d-small", 2, 24, 3, 8, 16),
+                                                  ("2d-large", 2, 32, 16, 4, 16)])
+def test_class_archive_matches_oracle(gt, orc, kind, scene, N, M, S, k):
+    w = wl.make_workload(kind, scene, N=N, M=M)
+    reps = w["circles"][:k, :2]
     _say("class archive scene", scene, "stages", S)
     cp = gt.ClassPlanner(w, reps, S, L=64, cap=512)
     cp.run(w["seed"])
@@ -106,3 +107,87 @@ def test_class_archive_matches_oracle(gt, orc, scene, N, M, S):
                 np.testing.assert_array_equal(wp, np.array(pts, np.float32))
     # anytime: at least as many classes as one stage, the best no worse than stage 0
     assert len(arch) >= 1
+
+
+def _gpu_sweep_vs_oracle(gt, orc, w, k, L):
+    reps = w["circles"][:k, :2]
+    pl = gt.Planner(w, flags=True)
+    pl.plan(w["seed"], 0)
+    torch.cuda.synchronize()
+    got, ovf = gt.class_sweep(pl, reps, L=L)
+    r = _oracle_costs(orc, w)
+    Cs, Ch, Cl = r["cost"]
+    want, J = OC.class_sweep(Cs, Ch, Cl, r["Q"], w["q0"], w["goals"], reps, w["penalty"])
+    M = int(w["M"])
+    rep = P.compare_edges(P.flat(pl.C_s.cpu().numpy(), pl.C_h.cpu().numpy()[: M - 1], pl.C_l.cpu().numpy()),
+                          pl.flags.cpu().numpy(), P.flat(*r["cost"]), P.flat(*r["minsd"]), P.flat(*r["flag"]))
+    return pl, reps, got, ovf, r, want, J, rep
+
+
+@pytest.mark.parametrize("scene,N,k", [(2, 48, 16), (1, 48, 8), (2, 32, 16)])
+def test_class_sweep_m16_matches_oracle(gt, orc, scene, N, k):
+    """The 2d-large workload at its own chain length (M = 16: chains of 17
+    edges) with up to 16 representative points, so that labels use both
+    words; every vertex list fits L = 64, so the sets must agree."""
+    w = wl.make_workload("2d-large", scene, N=N, M=16)
+    _say("class sweep 2d-large M=16 scene", scene, "N", N, "k", k)
+    pl, reps, got, ovf, r, want, J, rep = _gpu_sweep_vs_oracle(gt, orc, w, k, 64)
+    Cs, Ch, Cl = r["cost"]
+    assert max(len(d) for layer in J for d in layer) <= 64
+    assert ovf == 0
+    P.note(f"class sweep 2d-large M=16 scene {scene} N={N} k={k}: {len(got)} classes (oracle {len(want)}), "
+           f"excused edges {rep['excused']}")
+    assert len(want) > 0
+    for lab, (cost, chain) in got.items():
+        lab2, cost2 = OC.chain_label_cost(Cs, Ch, Cl, r["Q"], w["q0"], w["goals"], reps, chain)
+        assert lab2 == lab
+        if rep["excused"] == 0:
+            assert cost2 == pytest.approx(cost, rel=P.REL)
+    if rep["excused"] == 0:
+        assert set(got) == set(want)
+        for lab, (cost, _) in want.items():
+            assert got[lab][0] == pytest.approx(cost, rel=P.REL)
+        assert min(c for c, _ in got.values()) == pytest.approx(float(pl.cost.item()), rel=P.REL)
+
+
+def test_class_sweep_m16_full_lists(gt, orc):
+    """M = 16 with more labels per vertex than L = 64: the kept labels are
+    real classes at no less than their optimum, and the global optimum
+    survives."""
+    w = wl.make_workload("2d-large", 2, N=64, M=16)
+    pl, reps, got, ovf, r, want, J, rep = _gpu_sweep_vs_oracle(gt, orc, w, 16, 64)
+    Cs, Ch, Cl = r["cost"]
+    _say("2d-large M=16 N=64 classes", len(got), "oracle", len(want), "dropped", ovf)
+    assert max(len(d) for layer in J for d in layer) > 64 and ovf > 0
+    assert rep["excused"] == 0
+    for lab, (cost, chain) in got.items():
+        lab2, cost2 = OC.chain_label_cost(Cs, Ch, Cl, r["Q"], w["q0"], w["goals"], reps, chain)
+        assert lab2 == lab and lab in want
+        assert cost2 == pytest.approx(cost, rel=P.REL)
+        assert cost >= want[lab][0] * (1 - P.REL)
+    assert min(c for c, _ in got.values()) == pytest.approx(min(c for c, _ in want.values()), rel=P.REL)
+
+
+def test_class_sweep_full_size_2d_large(gt):
+    """The full 2d-large workload (M = 16, N = 1024, 16 representative
+    points, L = 64): every returned chain carries its label (recomputed by the
+    oracle's crossing rule from the chain's own waypoints) and its cost (the
+    sum of the GPU's edge costs along it), labels are distinct, and the
+    cheapest class is the plain optimum of the same graph."""
+    w = wl.make_workload("2d-large", 2)
+    assert int(w["M"]) == 16 and int(w["N"]) == 1024
+    reps = w["circles"][:16, :2]
+    pl = gt.Planner(w)
+    pl.plan(w["seed"], 0)
+    torch.cuda.synchronize()
+    _say("class sweep 2d-large full size")
+    got, ovf = gt.class_sweep(pl, reps, L=64)
+    Cs, Ch, Cl = (x.cpu().numpy() for x in (pl.C_s, pl.C_h, pl.C_l))
+    Q = pl.Q.cpu().numpy()
+    P.note(f"class sweep 2d-large full size: {len(got)} classes kept, {ovf} labels dropped")
+    assert len(got) > 0
+    for lab, (cost, chain) in got.items():
+        lab2, cost2 = OC.chain_label_cost(Cs, Ch, Cl, Q, w["q0"], w["goals"], reps, chain)
+        assert lab2 == lab
+        assert cost2 == pytest.approx(cost, rel=P.REL)
+    assert min(c for c, _ in got.values()) == pytest.approx(float(pl.cost.item()), rel=P.REL)
