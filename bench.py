@@ -496,11 +496,7 @@ def bench_batch(args, torch, wl, gtmp):
     print(json.dumps(out), flush=True)
 
 
-def bench_surrogate(args, torch, wl, gtmp):
-    """7-DoF arm at N = 4096, M = 8: plain plans against surrogate-pruned
-    plans on the same samples, and the growing loop with and without the
-    surrogate bias of the heuristic half."""
-    w = wl.make_workload("arm7", args.scene, N=4096)
+def _train_surrogate(args, torch, wl, gtmp, w):
     P0, Bf = wl.surrogate_init(7, w["d"])
     S = wl.SURROGATE
     net = gtmp.Surrogate(P0, Bf, batch=S["batch"])
@@ -512,12 +508,47 @@ def bench_surrogate(args, torch, wl, gtmp):
     del X, y
     Xh, yh = gtmp.make_labels(w, 1 << 16, seed=101, stage=1)
     acc = float(((net.infer(Xh) > 0) == (yh == 1)).float().mean().item())
+    return net, losses, train_s, acc
+
+
+def _growing_series(torch, gtmp, w, seed, net, stages=6):
+    """Best cost after each stage of the growing loop (M 6 -> 8, N 256 ->
+    2048) and the time to finish stages 1..s, each prefix run on its own
+    (the loop is deterministic, so prefix s repeats the first s stages)."""
+    ap = gtmp.AnytimePlanner(w, gtmp.GTMP_ANYTIME_GROWING, stages, M_min=6, M_max=8, N_min=256, N_max=2048,
+                             bias=net, bias_tau=0.0)
+    ap.run(seed)  # warm-up
+    torch.cuda.synchronize()
+    sc = ap.stage_costs.cpu().numpy().astype(float)
+    best = np.minimum.accumulate(np.where(np.isnan(sc), np.inf, sc))
+    ms = []
+    for s in range(1, stages + 1):
+        ap.opts.max_stages = s
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ap.run(seed)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return [float(x) for x in best], ms
+
+
+def bench_surrogate(args, torch, wl, gtmp):
+    """7-DoF arm at N = 4096, M = 8: plain plans against surrogate-pruned
+    plans on the same samples (only edges with two free endpoints inferred),
+    and the growing loop with and without the surrogate bias of the heuristic
+    half over 16 (scene, seed) pairs as cost against time."""
+    w = wl.make_workload("arm7", args.scene, N=4096)
+    S = wl.SURROGATE
+    net, losses, train_s, acc = _train_surrogate(args, torch, wl, gtmp, w)
     print(f"[bench] trained in {train_s:.2f} s, held-out accuracy {acc:.4f}", file=sys.stderr, flush=True)
     pl = gtmp.Planner(w, flags=True)
-    net.workspace = gtmp._aligned_workspace(gtmp.gtmp_surrogate_workspace_size(1 << 21))
+    robot, scene = gtmp.model_of(w)
+    M, N, d = int(w["M"]), int(w["N"]), int(w["d"])
+    coll = torch.empty(M * N, device="cuda", dtype=torch.uint8)
     prune = torch.empty(pl.E, device="cuda", dtype=torch.uint8)
     logits = torch.empty(pl.E, device="cuda")
-    # threshold: free-edge recall on a held-out plan (stage 999)
+    # threshold: free-edge recall on a held-out plan (stage 999), every edge inferred
     pl.plan(w["seed"], 999)
     net.prune(pl.prob, pl.q0, pl.goals, pl.Q, math.inf, prune, logits)
     tau_dev = torch.empty(1, device="cuda")
@@ -528,7 +559,7 @@ def bench_surrogate(args, torch, wl, gtmp):
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
-    res = dict(plain=[], pruned=[], prune_ms=[], same=0, optimum_pruned=0, false_prune=[], pruned_frac=[])
+    res = dict(plain=[], pruned=[], prune_ms=[], same=0, false_prune=[], pruned_frac=[], cand=[])
     for i in range(args.warmup + args.steps):
         a, b, c, e = ev(), ev(), ev(), ev()
         a.record()
@@ -537,9 +568,9 @@ def bench_surrogate(args, torch, wl, gtmp):
         b.synchronize()
         c_plain = float(pl.cost.item())
         flags_plain = pl.flags.clone()
-        idx = pl.idx.cpu().numpy()
         c.record()
-        net.prune(pl.prob, pl.q0, pl.goals, pl.Q, tau, prune)
+        gtmp.gtmp_state_check(robot, scene, d, pl.Q.reshape(M * N, d), None, coll)
+        net.prune(pl.prob, pl.q0, pl.goals, pl.Q, tau, prune, vcoll=coll)
         e.record()
         pl.check(prune=prune)
         pl.sweep()
@@ -557,24 +588,46 @@ def bench_surrogate(args, torch, wl, gtmp):
         free = flags_plain == 0
         res["false_prune"].append(float((prune.bool() & free).sum().item()) / max(1, int(free.sum().item())))
         res["pruned_frac"].append(float(prune.float().mean().item()))
+        nf = (coll.reshape(M, N) == 0).sum(dim=1).cpu().numpy().astype(np.int64)
+        res["cand"].append(int(nf[0] + (nf[:-1] * nf[1:]).sum() + nf[-1] * int(w["G"])))
     ms_plain = float(np.mean(res["plain"]))
     ms_pruned = float(np.mean(res["pruned"]))
     ms_prune = float(np.mean(res["prune_ms"]))
+    cand = float(np.mean(res["cand"]))
     mlp_flop = 2 * (64 * 256 + 3 * 256 * 256 + 256)
-    achieved = pl.E * mlp_flop / (ms_prune / 1e3) / 1e12
-    # growing loop with and without the bias (same key): best cost per stage
-    grow = {}
-    for biased in (False, True):
-        ap = gtmp.AnytimePlanner(w, gtmp.GTMP_ANYTIME_GROWING, 8, M_min=6, M_max=8, N_min=256, N_max=2048,
-                                 bias=net if biased else None, bias_tau=0.0)
-        a, b = ev(), ev()
-        a.record()
-        ap.run(w["seed"])
-        b.record()
-        b.synchronize()
-        sc = ap.stage_costs.cpu().numpy()
-        grow["biased" if biased else "plain"] = dict(ms=a.elapsed_time(b), stage_costs=[float(x) for x in sc],
-                                                      best=float(np.nanmin(sc)))
+    achieved = cand * mlp_flop / (ms_prune / 1e3) / 1e12
+
+    # growing loop, plain against biased, 4 scenes x 4 seeds: cost against time
+    pairs = []
+    for sc_i in range(4):
+        ws = wl.make_workload("arm7", sc_i, N=4096)
+        net_s = net if sc_i == args.scene else _train_surrogate(args, torch, wl, gtmp, ws)[0]
+        for k in range(4):
+            seed = int(ws["seed"]) + 1000 * k
+            bp, tp = _growing_series(torch, gtmp, ws, seed, None)
+            bb, tb = _growing_series(torch, gtmp, ws, seed, net_s)
+            target = bp[-1]
+            s_p = next(i for i, c in enumerate(bp) if c <= target * (1 + 1e-5))
+            s_b = next((i for i, c in enumerate(bb) if c <= target * (1 + 1e-5)), None)
+            pairs.append(dict(scene=sc_i, seed=seed, plain_best=bp, plain_ms=tp, biased_best=bb, biased_ms=tb,
+                              plain_time_to_cost_ms=tp[s_p],
+                              biased_time_to_cost_ms=None if s_b is None else tb[s_b]))
+            print(f"[bench] growing scene {sc_i} seed {seed}: plain {bp[-1]:.3f} in {tp[-1]:.1f} ms, "
+                  f"biased {bb[-1]:.3f} in {tb[-1]:.1f} ms", file=sys.stderr, flush=True)
+    reached = [p for p in pairs if p["biased_time_to_cost_ms"] is not None]
+    ratio = [p["biased_time_to_cost_ms"] / p["plain_time_to_cost_ms"] for p in reached]
+    grow = {
+        "pairs": len(pairs),
+        "biased_reaches_plain_final_cost": len(reached),
+        "median_time_ratio_biased_over_plain": float(np.median(ratio)) if ratio else None,
+        "biased_better_final": sum(1 for p in pairs if p["biased_best"][-1] < p["plain_best"][-1] * (1 - 1e-5)),
+        "plain_better_final": sum(1 for p in pairs if p["plain_best"][-1] < p["biased_best"][-1] * (1 - 1e-5)),
+        "mean_final_cost": {"plain": float(np.mean([p["plain_best"][-1] for p in pairs])),
+                            "biased": float(np.mean([p["biased_best"][-1] for p in pairs]))},
+        "mean_loop_ms": {"plain": float(np.mean([p["plain_ms"][-1] for p in pairs])),
+                         "biased": float(np.mean([p["biased_ms"][-1] for p in pairs]))},
+        "series": pairs,
+    }
     out = {
         "metric": "plans/s (7-DoF, N=4096): surrogate-pruned vs plain at equal cost",
         "value": 1e3 / ms_pruned,
@@ -592,11 +645,14 @@ def bench_surrogate(args, torch, wl, gtmp):
                                f"BF16, {2 * args.labels} labels, {args.epochs} epochs", "edges": pl.E},
         "plain": {"plans_per_s": 1e3 / ms_plain, "ms": ms_plain},
         "pruned": {"plans_per_s": 1e3 / ms_pruned, "ms": ms_pruned, "prune_ms": ms_prune,
+                   "ratio_pruned_over_plain": ms_pruned / ms_plain,
+                   "candidate_edges": cand, "candidate_frac": cand / pl.E,
                    "pruned_frac": float(np.mean(res["pruned_frac"])),
                    "false_prune_frac": float(np.mean(res["false_prune"])),
                    "equal_cost_frac": res["same"] / args.steps, "tau_logit": tau},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": achieved / 2500.0, "traffic": None, "kernel": "surrogate inference (midpoint probes)"},
+                     "frac": achieved / 2500.0, "traffic": None,
+                     "kernel": "surrogate inference at candidate-edge midpoints (sample check, lists, k_mlp_prune)"},
         "training": {"seconds": train_s, "steps": int(losses.numel()), "final_loss": float(losses[-20:].mean()),
                      "heldout_accuracy": acc},
         "growing_bias": grow,

@@ -648,13 +648,28 @@ gtmp_status gtmp_surrogate_adam(const gtmp_surrogate *net, const float *grad, fl
 gtmp_status gtmp_surrogate_label_states(const gtmp_problem *prob, uint64_t seed, uint64_t stage, int64_t n, float *X,
                                         void *stream);
 
-/* Prune mask of every edge of a plan: prune[e] = 1 iff the logit at the
- * edge's midpoint (u + v) / 2 (FP32) exceeds tau_logit.  Edge order as
- * gtmp_edge_check_cost (C_s | C_h | C_l).  logits [E] or NULL.  Pass the
- * mask to gtmp_edge_check_cost, which checks every unpruned edge exactly. */
+/* Prune mask of a plan's edges: prune[e] = 1 iff the logit at the edge's
+ * midpoint (u + v) / 2 (FP32) exceeds tau_logit.  Edge order as
+ * gtmp_edge_check_cost (C_s | C_h | C_l).  Pass the mask to
+ * gtmp_edge_check_cost, which checks every unpruned edge exactly.
+ *   vcoll   device uint8 [M][N] or NULL: nonzero = the sample Q[m][n]
+ *           collides (e.g. gtmp_state_check's coll output on Q).  Only the
+ *           candidate edges, those whose sample endpoints are all free, are
+ *           inferred; every other edge gets prune 0 (its colliding endpoint
+ *           fails it in the exact check's vertex pass) and logit NaN.  NULL:
+ *           every edge is a candidate.  q0 and the goals count as free.
+ *   tau_logit  not NaN (+inf prunes nothing)
+ *   prune   device uint8 [E], every entry written
+ *   logits  device float32 [E] or NULL, every entry written
+ *   workspace  device, 256-byte aligned, of
+ *           gtmp_surrogate_prune_workspace_size bytes (M N int32 free lists
+ *           and a fragment-ordered copy of the BF16 weights).
+ * Candidates are processed by a persistent kernel in index order; nothing
+ * is read back to the host. */
+gtmp_status gtmp_surrogate_prune_workspace_size(const gtmp_problem *prob, size_t *bytes);
 gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate *net, const float *q0,
-                                 const float *goals, const float *Q, float tau_logit, uint8_t *prune, float *logits,
-                                 void *workspace, size_t ws_bytes, void *stream);
+                                 const float *goals, const float *Q, const uint8_t *vcoll, float tau_logit,
+                                 uint8_t *prune, float *logits, void *workspace, size_t ws_bytes, void *stream);
 
 /* Pruning threshold of the surrogate for a free-edge recall (the calibration
  * that makes the pruning conservative: at least `recall` of the free edges

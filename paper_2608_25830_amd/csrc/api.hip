@@ -791,9 +791,18 @@ gtmp_status gtmp_surrogate_label_states(const gtmp_problem *prob, uint64_t seed,
                       "gtmp_surrogate_label_states");
 }
 
+gtmp_status gtmp_surrogate_prune_workspace_size(const gtmp_problem *prob, size_t *bytes) {
+    g_err[0] = 0;
+    gtmp_status st = check_problem(prob);
+    if (st != GTMP_OK) return st;
+    if (!bytes) return fail(GTMP_EINVAL, "bytes is NULL");
+    *bytes = gtmp::sur_prune_bytes(*prob);
+    return GTMP_OK;
+}
+
 gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate *net, const float *q0,
-                                 const float *goals, const float *Q, float tau_logit, uint8_t *prune, float *logits,
-                                 void *workspace, size_t ws_bytes, void *stream) {
+                                 const float *goals, const float *Q, const uint8_t *vcoll, float tau_logit,
+                                 uint8_t *prune, float *logits, void *workspace, size_t ws_bytes, void *stream) {
     g_err[0] = 0;
     gtmp_status st = check_problem(prob);
     if (st != GTMP_OK) return st;
@@ -802,9 +811,10 @@ gtmp_status gtmp_surrogate_prune(const gtmp_problem *prob, const gtmp_surrogate 
     if (st != GTMP_OK) return st;
     if (net->d != prob->d) return fail(GTMP_EINVAL, "net d=%d differs from problem d=%d", net->d, prob->d);
     if (!q0 || !goals || !Q || !prune) return fail(GTMP_EINVAL, "NULL buffer");
-    st = check_ws(workspace, ws_bytes, gtmp::sur_infer_bytes(256));
+    if (isnan(tau_logit)) return fail(GTMP_EINVAL, "tau_logit is NaN");
+    st = check_ws(workspace, ws_bytes, gtmp::sur_prune_bytes(*prob));
     if (st != GTMP_OK) return st;
-    return hip_status(gtmp::launch_sur_prune(*prob, sn, q0, goals, Q, tau_logit, prune, logits, workspace, ws_bytes,
+    return hip_status(gtmp::launch_sur_prune(*prob, sn, q0, goals, Q, vcoll, tau_logit, prune, logits, workspace,
                                              (hipStream_t)stream),
                       "gtmp_surrogate_prune");
 }

@@ -7,6 +7,8 @@
 // Every reduction runs in a fixed order (split-K partials summed in split
 // order, column sums over fixed row chunks, wave reductions by butterfly), so
 // results are reproducible run to run.
+#include <algorithm>
+
 #include "surrogate.hpp"
 
 namespace gtmp {
@@ -183,17 +185,42 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K_split, cons
 }
 
 // ------------------------------------------------------------------ fused inference
-// Whole network for 128 rows per block (inference only): features computed in
-// FP64 straight into LDS, then four hidden layers whose BF16 activations stay
-// in LDS (one 128 x 256 tile, written back in place after a barrier), then the
-// FP32 head.  Wave w owns output columns [64 w, 64 w + 64) of every layer:
-// 4 x 2 tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16, 128 accumulators per
-// lane); activation fragments come from LDS, weight fragments from global
-// memory (L2-resident, each block reads every weight once per layer).  Two
-// blocks share a CU (2 x 68 KB of LDS), so one block's feature or epilogue
-// phase overlaps the other's MFMAs.  Sums run in K order as in k_gemm_nt.
-constexpr int kFR = 128;                              // rows per block
+// Whole network for 128 rows per block tile (inference only): features
+// computed in FP64 straight into LDS, then four hidden layers whose BF16
+// activations stay in LDS (one 128 x 256 tile, written back in place after a
+// barrier), then the FP32 head.  Wave w owns output columns [64 w, 64 w + 64)
+// of every layer: 4 x 2 tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16, 128
+// accumulators per lane); activation fragments come from LDS, weight
+// fragments from a copy of the weights stored in fragment order (for every
+// 32-column tile and 16-wide K slice, the 64 lanes' 16-byte operands side by
+// side), so each weight load of a wave is one contiguous 1 KB read from L2.
+// Two blocks share a CU (2 x 68 KB of LDS), so one block's feature or
+// epilogue phase overlaps the other's MFMAs.  Sums run in K order as in
+// k_gemm_nt.
+constexpr int kFR = 128;                              // rows per block tile
 constexpr int kFRow = GTMP_SUR_WIDTH + 8;             // LDS row stride (BF16), 528 bytes
+constexpr int kColTiles = GTMP_SUR_WIDTH / 32;        // 32-column output tiles per layer
+
+// Offsets (in 16-byte fragments) of the layers in the fragment-order copy.
+__host__ __device__ constexpr int frag_offset(int l) {
+    return l == 0 ? 0 : kColTiles * (GTMP_SUR_IN / 16) * 64 + (l - 1) * kColTiles * (GTMP_SUR_WIDTH / 16) * 64;
+}
+constexpr int kFragTotal = frag_offset(4);  // 16-byte fragments of the four hidden layers
+
+// Fragment f of layer l: lane = f % 64, K slice ks and column tile c from
+// f / 64 = c * S + ks; it holds W_l[32 c + lane % 32][16 ks + 8 (lane / 32) ..+8].
+__global__ void __launch_bounds__(256) k_weight_frag(const uint16_t *__restrict__ P16, SurLayout L,
+                                                     uint4 *__restrict__ Wf) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= kFragTotal) return;
+    const int l = f < frag_offset(1) ? 0 : 1 + (f - frag_offset(1)) / (frag_offset(2) - frag_offset(1));
+    const int K = l == 0 ? GTMP_SUR_IN : GTMP_SUR_WIDTH;
+    const int S = K / 16;
+    const int r = f - frag_offset(l);
+    const int lane = r & 63, ks = (r >> 6) % S, c = (r >> 6) / S;
+    const int row = 32 * c + (lane & 31), col = 16 * ks + 8 * (lane >> 5);
+    Wf[f] = *reinterpret_cast<const uint4 *>(P16 + L.W[l] + (size_t)row * K + col);
+}
 
 // One hidden layer on the block's LDS tile: K input columns -> 256 outputs,
 // bias + ReLU, BF16, written back in place.  The MFMA computes the transposed
@@ -205,7 +232,7 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
 template <int K>
-__device__ __forceinline__ void mlp_layer(const uint16_t *__restrict__ W, const float *__restrict__ bias,
+__device__ __forceinline__ void mlp_layer(const bf16x8 *__restrict__ Wf, const float *__restrict__ bias,
                                           uint16_t *act, int wave, int lane) {
     constexpr int S = K / 16;
     const int cl = lane & 31, kh = 8 * (lane >> 5);
@@ -217,16 +244,16 @@ __device__ __forceinline__ void mlp_layer(const uint16_t *__restrict__ W, const 
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
-    const uint16_t *wr0 = W + (size_t)(c0 + cl) * K + kh;
-    const uint16_t *wr1 = W + (size_t)(c0 + 32 + cl) * K + kh;
-    bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(wr0);
-    bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(wr1);
+    const bf16x8 *wr0 = Wf + (size_t)(2 * wave) * S * 64 + lane;
+    const bf16x8 *wr1 = Wf + (size_t)(2 * wave + 1) * S * 64 + lane;
+    bf16x8 w0 = wr0[0];
+    bf16x8 w1 = wr1[0];
 #pragma unroll
     for (int ks = 0; ks < S; ++ks) {
         bf16x8 nw0 = w0, nw1 = w1;
         if (ks + 1 < S) {
-            nw0 = *reinterpret_cast<const bf16x8 *>(wr0 + 16 * (ks + 1));
-            nw1 = *reinterpret_cast<const bf16x8 *>(wr1 + 16 * (ks + 1));
+            nw0 = wr0[64 * (ks + 1)];
+            nw1 = wr1[64 * (ks + 1)];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -264,50 +291,244 @@ __device__ __forceinline__ void mlp_layer(const uint16_t *__restrict__ W, const 
     __syncthreads();
 }
 
+// Features of one row into its LDS slot; two threads per row (half 0 and 1),
+// each taking half of the frequencies.  qh = q / pi in FP64.
+__device__ __forceinline__ void row_features(int d, const double (&qh)[GTMP_MAX_DOF], int half,
+                                             const float *__restrict__ Bf, uint16_t *dst) {
+    constexpr double kPi = 3.14159265358979323846;
+    if (half == 0) {
+        for (int j = 0; j < d; ++j) dst[j] = d2bf(qh[j]);
+        for (int k = d + 2 * GTMP_SUR_FREQ; k < GTMP_SUR_IN; ++k) dst[k] = 0;
+    }
+    for (int f = half * (GTMP_SUR_FREQ / 2); f < (half + 1) * (GTMP_SUR_FREQ / 2); ++f) {
+        double sarg = 0.0;
+        for (int j = 0; j < d; ++j) sarg += (double)Bf[f * d + j] * qh[j];
+        sarg *= 2.0 * kPi;
+        double sn, cs;
+        sincos(sarg, &sn, &cs);
+        dst[d + f] = d2bf(sn);
+        dst[d + GTMP_SUR_FREQ + f] = d2bf(cs);
+    }
+}
+
+// The four hidden layers and the FP32 head of the block's tile; thread
+// tid < kFR gets its row's logit.  Head: two threads per row, each summing
+// one half of the 256 products in K order (8 activations per LDS read);
+// z = first half + second half + b5.
+__device__ __forceinline__ float mlp_tile(const bf16x8 *__restrict__ Wf, const float *__restrict__ P32,
+                                          const SurLayout &L, uint16_t *act, const float *w5s, float *zpart,
+                                          int tid) {
+    const int lane = tid & 63, wave = tid >> 6;
+    mlp_layer<GTMP_SUR_IN>(Wf + frag_offset(0), P32 + L.b[0], act, wave, lane);
+    mlp_layer<GTMP_SUR_WIDTH>(Wf + frag_offset(1), P32 + L.b[1], act, wave, lane);
+    mlp_layer<GTMP_SUR_WIDTH>(Wf + frag_offset(2), P32 + L.b[2], act, wave, lane);
+    mlp_layer<GTMP_SUR_WIDTH>(Wf + frag_offset(3), P32 + L.b[3], act, wave, lane);
+    const int r = tid & (kFR - 1), half = tid >> 7;
+    constexpr int kHalf = GTMP_SUR_WIDTH / 2;
+    const uint4 *a = reinterpret_cast<const uint4 *>(act + r * kFRow + half * kHalf);
+    const float *w = w5s + half * kHalf;
+    float z = 0.f;
+#pragma unroll 4
+    for (int q = 0; q < kHalf / 8; ++q) {
+        const uint4 v = a[q];
+        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            z = __builtin_fmaf(w[8 * q + 2 * h], __uint_as_float(wd[h] << 16), z);
+            z = __builtin_fmaf(w[8 * q + 2 * h + 1], __uint_as_float(wd[h] & 0xffff0000u), z);
+        }
+    }
+    if (half == 1) zpart[r] = z;
+    __syncthreads();
+    return half == 0 ? z + zpart[r] + P32[L.b5] : 0.f;
+}
+
 __global__ void __launch_bounds__(256, 2) k_mlp_infer(int d, int64_t n, const float *__restrict__ X,
-                                                     const float *__restrict__ Bf, const uint16_t *__restrict__ P16,
+                                                     const float *__restrict__ Bf, const bf16x8 *__restrict__ Wf,
+                                                     const uint16_t *__restrict__ P16,
                                                      const float *__restrict__ P32, SurLayout L,
                                                      float *__restrict__ logits) {
     __shared__ __attribute__((aligned(16))) uint16_t act[kFR * kFRow];
     __shared__ float w5s[GTMP_SUR_WIDTH];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ float zpart[kFR];
+    const int tid = threadIdx.x;
     const int64_t row0 = (int64_t)blockIdx.x * kFR;
-
-    // ---- features: two threads per row, each half of the frequencies
     {
         const int r = tid & (kFR - 1), half = tid >> 7;
         const int64_t gr = row0 + r;
-        uint16_t *dst = act + r * kFRow;
         constexpr double kPi = 3.14159265358979323846;
         double qh[GTMP_MAX_DOF];
         for (int j = 0; j < GTMP_MAX_DOF; ++j) qh[j] = (gr < n && j < d) ? (double)X[gr * d + j] / kPi : 0.0;
-        if (half == 0) {
-            for (int j = 0; j < d; ++j) dst[j] = d2bf(qh[j]);
-            for (int k = d + 2 * GTMP_SUR_FREQ; k < GTMP_SUR_IN; ++k) dst[k] = 0;
-        }
-        for (int f = half * (GTMP_SUR_FREQ / 2); f < (half + 1) * (GTMP_SUR_FREQ / 2); ++f) {
-            double sarg = 0.0;
-            for (int j = 0; j < d; ++j) sarg += (double)Bf[f * d + j] * qh[j];
-            sarg *= 2.0 * kPi;
-            double sn, cs;
-            sincos(sarg, &sn, &cs);
-            dst[d + f] = d2bf(sn);
-            dst[d + GTMP_SUR_FREQ + f] = d2bf(cs);
-        }
+        row_features(d, qh, half, Bf, act + r * kFRow);
         if (tid < GTMP_SUR_WIDTH) w5s[tid] = bf2f(P16[L.w5 + tid]);
     }
     __syncthreads();
+    const float z = mlp_tile(Wf, P32, L, act, w5s, zpart, tid);
+    if (tid < kFR && row0 + tid < n) logits[row0 + tid] = z;
+}
 
-    mlp_layer<GTMP_SUR_IN>(P16 + L.W[0], P32 + L.b[0], act, wave, lane);
-    mlp_layer<GTMP_SUR_WIDTH>(P16 + L.W[1], P32 + L.b[1], act, wave, lane);
-    mlp_layer<GTMP_SUR_WIDTH>(P16 + L.W[2], P32 + L.b[2], act, wave, lane);
-    mlp_layer<GTMP_SUR_WIDTH>(P16 + L.W[3], P32 + L.b[3], act, wave, lane);
-    // ---- head: one thread per row, FP32 in K order
-    if (tid < kFR && row0 + tid < n) {
-        const uint16_t *a = act + tid * kFRow;
-        float z = 0.f;
-        for (int k = 0; k < GTMP_SUR_WIDTH; ++k) z = __builtin_fmaf(w5s[k], bf2f(a[k]), z);
-        logits[row0 + tid] = z + P32[L.b5];
+// ------------------------------------------------------------------ pruning
+// Candidate edges: those whose two endpoints are free samples (an edge with
+// a colliding endpoint fails the exact check at its vertex, so it is never
+// inferred).  Per layer m the free samples in index order fl[m][0 .. nf[m]);
+// candidate t lies in segment s with seg[s] <= t < seg[s + 1]: s = 0 start
+// edges (q0 -> free layer-0 samples), s = 1 .. M-1 the free pairs of layers
+// s-1 and s (row-major over the two free lists), s = M the edges from free
+// layer M-1 samples to every goal.
+__global__ void __launch_bounds__(256) k_free_lists(int N, int d, const float *__restrict__ Q,
+                                                    const uint8_t *__restrict__ vcoll, int32_t *__restrict__ fl,
+                                                    float *__restrict__ Qf, int32_t *__restrict__ nf) {
+    __shared__ int wsum[256 / kWave];
+    const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int count = 0;
+    for (int base = 0; base < N; base += 256) {
+        const int i = base + tid;
+        const bool fr = i < N && (vcoll == nullptr || vcoll[(size_t)m * N + i] == 0);
+        const uint64_t bal = __ballot(fr);
+        if (lane == 0) wsum[wv] = __popcll(bal);
+        __syncthreads();
+        int before = count;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        if (fr) {
+            const size_t slot = (size_t)m * N + before + __popcll(bal & ((1ull << lane) - 1ull));
+            fl[slot] = i;
+            for (int j = 0; j < d; ++j) Qf[slot * d + j] = Q[((size_t)m * N + i) * d + j];
+        }
+        for (int w = 0; w < 256 / kWave; ++w) count += wsum[w];
+        __syncthreads();
+    }
+    if (tid == 0) nf[m] = count;
+}
+
+__global__ void k_cand_segments(int M, int G, const int32_t *__restrict__ nf, int64_t *__restrict__ seg) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t o = 0;
+    seg[0] = 0;
+    o += nf[0];
+    seg[1] = o;
+    for (int s = 1; s < M; ++s) {
+        o += (int64_t)nf[s - 1] * nf[s];
+        seg[s + 1] = o;
+    }
+    o += (int64_t)nf[M - 1] * G;
+    seg[M + 1] = o;
+}
+
+__global__ void k_prune_fill(int64_t E, uint8_t *__restrict__ prune, float *__restrict__ logits) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += stride) {
+        prune[i] = 0;
+        if (logits) logits[i] = __builtin_nanf("");
+    }
+}
+
+// Endpoints of candidate t (t < total): the two configurations and the
+// edge's flat id.  Segment bounds and list lengths come from LDS; the
+// configurations from the compacted free rows Qf (one memory round trip,
+// with the original indices read beside them).
+struct CandRow {
+    float u[GTMP_MAX_DOF], v[GTMP_MAX_DOF];
+    int64_t e;
+};
+
+template <typename IDX>
+__device__ __forceinline__ void cand_fetch(int64_t t, int d, int M, int N, int G, const int64_t *seg,
+                                           const int32_t *nf, const float *__restrict__ q0,
+                                           const float *__restrict__ goals, const float *__restrict__ Qf,
+                                           const int32_t *__restrict__ fl, CandRow &c) {
+    int lo = 0, hi = M;  // largest s in [0, M] with seg[s] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const IDX loc = (IDX)(t - seg[lo]);
+    const float *pu, *pv;
+    if (lo == 0) {
+        pu = q0;
+        pv = Qf + (size_t)loc * d;
+        c.e = fl[loc];
+    } else if (lo < M) {
+        const int m = lo - 1;
+        const IDX n1 = (IDX)nf[m + 1];
+        const IDX i = loc / n1, j = loc - i * n1;
+        const size_t su = (size_t)m * N + i, sv = (size_t)(m + 1) * N + j;
+        pu = Qf + su * d;
+        pv = Qf + sv * d;
+        c.e = N + (int64_t)m * N * N + (int64_t)fl[su] * N + fl[sv];
+    } else {
+        const IDX i = loc / (IDX)G, g = loc - i * (IDX)G;
+        const size_t su = (size_t)(M - 1) * N + i;
+        pu = Qf + su * d;
+        pv = goals + (size_t)g * d;
+        c.e = N + (int64_t)(M - 1) * N * N + (int64_t)fl[su] * G + g;
+    }
+#pragma unroll
+    for (int j = 0; j < GTMP_MAX_DOF; ++j) {
+        c.u[j] = j < d ? pu[j] : 0.f;
+        c.v[j] = j < d ? pv[j] : 0.f;
+    }
+}
+
+constexpr int kSegLds = 130;  // segment bounds kept in LDS (M <= 128)
+
+// One block per tile of 128 candidates, launched over the upper bound E / 128
+// (the candidate count is known only on the device: blocks past it return
+// at once).  Blocks of one CU start at different times, so one block's
+// feature or head phase overlaps the other's MFMAs.  The candidate's
+// endpoints give the midpoint (u + v) * 0.5 (FP32), its features and logit
+// z; prune[e] = z > tau and logits[e] = z at the edge's flat id e
+// (C_s | C_h | C_l order).
+template <typename IDX>
+__global__ void __launch_bounds__(256, 2) k_mlp_prune(int d, int M, int N, int G, const float *__restrict__ q0,
+                                                     const float *__restrict__ goals, const float *__restrict__ Qf,
+                                                     const int32_t *__restrict__ fl, const int32_t *__restrict__ nf,
+                                                     const int64_t *__restrict__ seg, const float *__restrict__ Bf,
+                                                     const bf16x8 *__restrict__ Wf, const uint16_t *__restrict__ P16,
+                                                     const float *__restrict__ P32, SurLayout L, float tau,
+                                                     uint8_t *__restrict__ prune, float *__restrict__ logits) {
+    __shared__ __attribute__((aligned(16))) uint16_t act[kFR * kFRow];
+    __shared__ float w5s[GTMP_SUR_WIDTH];
+    __shared__ float zpart[kFR];
+    __shared__ int64_t eid[kFR];
+    __shared__ int64_t seg_s[kSegLds];
+    __shared__ int32_t nf_s[kSegLds];
+    const int tid = threadIdx.x;
+    const int64_t total = seg[M + 1];
+    const int64_t tile = blockIdx.x;
+    if (tile * kFR >= total) return;  // block-uniform
+    const bool in_lds = M + 2 <= kSegLds;
+    if (in_lds) {
+        for (int i = tid; i < M + 2; i += blockDim.x) seg_s[i] = seg[i];
+        for (int i = tid; i < M; i += blockDim.x) nf_s[i] = nf[i];
+    }
+    if (tid < GTMP_SUR_WIDTH) w5s[tid] = bf2f(P16[L.w5 + tid]);
+    __syncthreads();
+    const int64_t *sg = in_lds ? seg_s : seg;
+    const int32_t *nl = in_lds ? nf_s : nf;
+    {
+        const int r = tid & (kFR - 1), half = tid >> 7;
+        const int64_t t = tile * kFR + r;
+        constexpr double kPi = 3.14159265358979323846;
+        double qh[GTMP_MAX_DOF];
+        const bool live = t < total;
+        CandRow c;
+        c.e = -1;
+        if (live) cand_fetch<IDX>(t, d, M, N, G, sg, nl, q0, goals, Qf, fl, c);
+#pragma unroll
+        for (int j = 0; j < GTMP_MAX_DOF; ++j)
+            qh[j] = live && j < d ? (double)((c.u[j] + c.v[j]) * 0.5f) / kPi : 0.0;
+        if (half == 0) eid[r] = c.e;
+        row_features(d, qh, half, Bf, act + r * kFRow);
+    }
+    __syncthreads();
+    const float z = mlp_tile(Wf, P32, L, act, w5s, zpart, tid);
+    if (tid < kFR) {
+        const int64_t e = eid[tid];
+        if (e >= 0) {
+            prune[e] = z > tau ? 1 : 0;
+            if (logits) logits[e] = z;
+        }
     }
 }
 
@@ -453,40 +674,6 @@ __global__ void __launch_bounds__(256) k_label_states(int d, int64_t n, int H, u
     for (int q = 0; q < d; ++q) X[i * d + q] = x[q];
 }
 
-// Midpoints (u + v) * 0.5 of edges [e0, e0 + count) in edge order C_s | C_h | C_l.
-__global__ void __launch_bounds__(256) k_edge_midpoints(int d, int M, int N, int G, int64_t e0, int64_t count,
-                                                        const float *__restrict__ q0, const float *__restrict__ goals,
-                                                        const float *__restrict__ Q, float *__restrict__ X) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    const int64_t e = e0 + t;
-    const int64_t NN = (int64_t)N * N;
-    const int64_t n_h = (int64_t)(M - 1) * NN;
-    const float *u, *v;
-    if (e < N) {
-        u = q0;
-        v = Q + e * d;
-    } else if (e < N + n_h) {
-        const int64_t r = e - N;
-        const int64_t m = r / NN, uv = r % NN;
-        u = Q + (m * N + uv / N) * d;
-        v = Q + ((m + 1) * N + uv % N) * d;
-    } else {
-        const int64_t r = e - N - n_h;
-        u = Q + ((int64_t)(M - 1) * N + r / G) * d;
-        v = goals + (r % G) * d;
-    }
-    for (int q = 0; q < d; ++q) X[t * d + q] = (u[q] + v[q]) * 0.5f;
-}
-
-__global__ void __launch_bounds__(256) k_threshold(int64_t count, const float *__restrict__ z, float tau,
-                                                   uint8_t *__restrict__ out, float *__restrict__ z_out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    out[i] = z[i] > tau ? 1 : 0;
-    if (z_out) z_out[i] = z[i];
-}
-
 // ------------------------------------------------------------------ host side
 static unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
 
@@ -500,6 +687,7 @@ static void gemm(int M, int N, int K, int splits, const uint16_t *A, int lda, co
 
 // Workspace carve-up for n rows.
 struct SurWs {
+    uint4 *Wf;  // fragment-order weights (inference)
     uint16_t *X0, *A[4], *dZa, *dZb, *T1, *T2, *WT;
     float *part, *loss_terms, *dz, *logit_tmp, *Xf;
     size_t total;
@@ -531,13 +719,15 @@ static SurWs carve(int64_t n, void *base) {
     return w;
 }
 
-// Inference needs only the features, two activation buffers (layers
-// alternate between them), the logits and the FP32 probe states.
+// Inference needs the fragment-order weights, and for chunked use the
+// features, two activation buffers (layers alternate between them), the
+// logits and the FP32 probe states.
 static SurWs carve_infer(int64_t n, void *base) {
     SurWs w{};
     char *p = static_cast<char *>(base);
     size_t o = 0;
     auto take = [&](size_t bytes) { char *q = p ? p + o : nullptr; o = up256(o + bytes); return q; };
+    w.Wf = reinterpret_cast<uint4 *>(take(sizeof(uint4) * kFragTotal));
     w.X0 = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * GTMP_SUR_IN));
     w.A[0] = w.A[2] = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * GTMP_SUR_WIDTH));
     w.A[1] = w.A[3] = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * n * GTMP_SUR_WIDTH));
@@ -579,21 +769,23 @@ static void forward(const SurNet &net, int64_t n, const float *X, const SurWs &w
                        inv_n, logits, w.loss_terms, w.dz);
 }
 
-static void infer_fused(const SurNet &net, int64_t n, const float *X, float *logits, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + kFR - 1) / kFR)), dim3(256), 0, s, net.d, n, X, net.fourier,
-                       net.p16, net.p32, sur_layout(), logits);
+static void weight_frag(const SurNet &net, uint4 *Wf, hipStream_t s) {
+    hipLaunchKernelGGL(k_weight_frag, dim3((kFragTotal + 255) / 256), dim3(256), 0, s, net.p16, sur_layout(), Wf);
 }
 
 hipError_t launch_sur_infer(const SurNet &net, int64_t n, const float *X, float *logits, void *ws, size_t ws_bytes,
                             hipStream_t s) {
-    (void)ws;
     (void)ws_bytes;
-    // the fused kernel needs no workspace; chunks bound the grid size
+    if (n <= 0) return hipSuccess;
+    const SurWs w = carve_infer(0, ws);
+    weight_frag(net, w.Wf, s);
+    // chunks bound the grid size
     constexpr int64_t kChunk = (int64_t)1 << 30;
     for (int64_t r = 0; r < n; r += kChunk) {
         const int64_t c = n - r < kChunk ? n - r : kChunk;
-        infer_fused(net, c, X + r * net.d, logits + r, s);
+        hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((c + kFR - 1) / kFR)), dim3(256), 0, s, net.d, c,
+                           X + r * net.d, net.fourier, reinterpret_cast<const bf16x8 *>(w.Wf), net.p16, net.p32,
+                           sur_layout(), logits + r);
     }
     return hipGetLastError();
 }
@@ -679,21 +871,50 @@ hipError_t launch_sur_label_states(const gtmp_problem &p, uint64_t seed, uint64_
     return hipGetLastError();
 }
 
+// Workspace of the pruning call: fragment-order weights, the free lists
+// [M][N], their lengths [M] and the M + 2 segment bounds.
+struct PruneWs {
+    uint4 *Wf;
+    int32_t *fl, *nf;
+    float *Qf;
+    int64_t *seg;
+    size_t total;
+};
+
+static PruneWs carve_prune(const gtmp_problem &p, void *base) {
+    PruneWs w{};
+    char *q = static_cast<char *>(base);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char *r = q ? q + o : nullptr; o = up256(o + bytes); return r; };
+    w.Wf = reinterpret_cast<uint4 *>(take(sizeof(uint4) * kFragTotal));
+    w.fl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)p.M * p.N));
+    w.Qf = reinterpret_cast<float *>(take(sizeof(float) * (size_t)p.M * p.N * p.d));
+    w.nf = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)p.M));
+    w.seg = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * ((size_t)p.M + 2)));
+    w.total = o;
+    return w;
+}
+
+size_t sur_prune_bytes(const gtmp_problem &p) { return carve_prune(p, nullptr).total; }
+
 hipError_t launch_sur_prune(const gtmp_problem &p, const SurNet &net, const float *q0, const float *goals,
-                            const float *Q, float tau, uint8_t *prune, float *logits, void *ws, size_t ws_bytes,
+                            const float *Q, const uint8_t *vcoll, float tau, uint8_t *prune, float *logits, void *ws,
                             hipStream_t s) {
     const int64_t E = (int64_t)p.N + (int64_t)(p.M - 1) * p.N * p.N + (int64_t)p.N * p.G;
-    const int64_t cap = sur_rows_for(ws_bytes);
-    if (cap <= 0) return hipErrorInvalidValue;
-    const SurWs w = carve_infer(cap, ws);
-    for (int64_t e0 = 0; e0 < E; e0 += cap) {
-        const int64_t c = E - e0 < cap ? E - e0 : cap;
-        hipLaunchKernelGGL(k_edge_midpoints, dim3(blocks_for(c)), dim3(256), 0, s, p.d, p.M, p.N, p.G, e0, c, q0, goals,
-                           Q, w.Xf);
-        infer_fused(net, c, w.Xf, w.logit_tmp, s);
-        hipLaunchKernelGGL(k_threshold, dim3(blocks_for(c)), dim3(256), 0, s, c, w.logit_tmp, tau, prune + e0,
-                           logits ? logits + e0 : nullptr);
-    }
+    const PruneWs w = carve_prune(p, ws);
+    weight_frag(net, w.Wf, s);
+    const int64_t fill_blocks = std::min<int64_t>((E + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_prune_fill, dim3((unsigned)fill_blocks), dim3(256), 0, s, E, prune, logits);
+    hipLaunchKernelGGL(k_free_lists, dim3(p.M), dim3(256), 0, s, p.N, p.d, Q, vcoll, w.fl, w.Qf, w.nf);
+    hipLaunchKernelGGL(k_cand_segments, dim3(1), dim3(64), 0, s, p.M, p.G, w.nf, w.seg);
+    const int64_t grid = (E + kFR - 1) / kFR;  // candidates <= E
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    // 32-bit index arithmetic when every segment's local index fits
+    const bool narrow = (uint64_t)p.N * p.N < (1ull << 32) && (uint64_t)p.N * p.G < (1ull << 32);
+    const auto kern = narrow ? k_mlp_prune<uint32_t> : k_mlp_prune<uint64_t>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, s, net.d, p.M, p.N, p.G, q0, goals, w.Qf, w.fl,
+                       w.nf, w.seg, net.fourier, reinterpret_cast<const bf16x8 *>(w.Wf), net.p16, net.p32,
+                       sur_layout(), tau, prune, logits);
     return hipGetLastError();
 }
 

@@ -46,8 +46,9 @@ hipError_t launch_sur_label_states(const gtmp_problem &p, uint64_t seed, uint64_
 size_t sur_threshold_bytes();
 hipError_t launch_sur_threshold(const float *logits, const uint8_t *flags, int64_t E, double recall, float *tau,
                                 void *workspace, hipStream_t s);
+size_t sur_prune_bytes(const gtmp_problem &p);  // workspace of launch_sur_prune
 hipError_t launch_sur_prune(const gtmp_problem &p, const SurNet &net, const float *q0, const float *goals,
-                            const float *Q, float tau, uint8_t *prune, float *logits, void *ws, size_t ws_bytes,
+                            const float *Q, const uint8_t *vcoll, float tau, uint8_t *prune, float *logits, void *ws,
                             hipStream_t s);
 
 }  // namespace gtmp

@@ -150,8 +150,9 @@ _lib.gtmp_surrogate_grad.argtypes = [C.POINTER(gtmp_surrogate), C.c_int32, _vp, 
 _lib.gtmp_surrogate_adam.argtypes = [C.POINTER(gtmp_surrogate), _vp, _vp, _vp, C.c_int32, C.c_float, C.c_float,
                                      C.c_float, C.c_float, _vp]
 _lib.gtmp_surrogate_label_states.argtypes = [C.POINTER(gtmp_problem), C.c_uint64, C.c_uint64, C.c_int64, _vp, _vp]
-_lib.gtmp_surrogate_prune.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_surrogate), _vp, _vp, _vp, C.c_float,
-                                      _vp, _vp, _vp, C.c_size_t, _vp]
+_lib.gtmp_surrogate_prune_workspace_size.argtypes = [C.POINTER(gtmp_problem), C.POINTER(C.c_size_t)]
+_lib.gtmp_surrogate_prune.argtypes = [C.POINTER(gtmp_problem), C.POINTER(gtmp_surrogate), _vp, _vp, _vp, _vp,
+                                      C.c_float, _vp, _vp, _vp, C.c_size_t, _vp]
 _lib.gtmp_surrogate_threshold_workspace_size.argtypes = [C.POINTER(C.c_size_t)]
 _lib.gtmp_surrogate_threshold.argtypes = [_vp, _vp, C.c_int64, C.c_double, _vp, _vp, C.c_size_t, _vp]
 
@@ -169,7 +170,7 @@ EXPORTS = ["gtmp_status_string", "gtmp_last_error", "gtmp_version", "gtmp_sample
            "gtmp_anytime_workspace_size", "gtmp_plan_anytime", "gtmp_batch_workspace_size", "gtmp_plan_batch",
            "gtmp_surrogate_layout", "gtmp_surrogate_refresh_bf16", "gtmp_surrogate_workspace_size",
            "gtmp_surrogate_infer", "gtmp_surrogate_grad", "gtmp_surrogate_adam", "gtmp_surrogate_label_states",
-           "gtmp_surrogate_prune", "gtmp_surrogate_threshold_workspace_size", "gtmp_surrogate_threshold",
+           "gtmp_surrogate_prune_workspace_size", "gtmp_surrogate_prune", "gtmp_surrogate_threshold_workspace_size", "gtmp_surrogate_threshold",
            "gtmp_expand_biased_workspace_size", "gtmp_expand_samples_biased",
            "gtmp_class_sweep_workspace_size", "gtmp_class_sweep", "gtmp_class_anytime_workspace_size",
            "gtmp_plan_classes", "gtmp_simplify_paths", "gtmp_rrtc_workspace_size", "gtmp_rrtc_repair",
@@ -779,9 +780,17 @@ class Surrogate:
                 losses[ep * steps + s].copy_(self.loss_buf[0])
         return losses
 
-    def prune(self, prob, q0, goals, Q, tau_logit, prune, logits=None, stream=None):
-        _check(_lib.gtmp_surrogate_prune(C.byref(prob), C.byref(self.c), _p(q0), _p(goals), _p(Q), float(tau_logit),
-                                         _p(prune), _p(logits), _p(self.workspace), _nbytes(self.workspace),
+    def prune(self, prob, q0, goals, Q, tau_logit, prune, logits=None, vcoll=None, stream=None):
+        """Prune mask of every edge (and the logits, when given).  ``vcoll``
+        (uint8 [M][N], nonzero = colliding sample) restricts inference to the
+        edges whose endpoints are free."""
+        n = C.c_size_t()
+        _check(_lib.gtmp_surrogate_prune_workspace_size(C.byref(prob), C.byref(n)))
+        ws = getattr(self, "_prune_ws", None)
+        if ws is None or _nbytes(ws) < n.value:
+            ws = self._prune_ws = _aligned_workspace(n.value, Q.device)
+        _check(_lib.gtmp_surrogate_prune(C.byref(prob), C.byref(self.c), _p(q0), _p(goals), _p(Q), _p(vcoll),
+                                         float(tau_logit), _p(prune), _p(logits), _p(ws), _nbytes(ws),
                                          _stream(stream)))
 
 

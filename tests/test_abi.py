@@ -149,8 +149,15 @@ def test_surrogate_calls_validate_sizes(g):
     p = _prob(g, H=2)
     assert g._lib.gtmp_surrogate_label_states(C.byref(p), 1, 0, 10, C.c_void_p(256), None) == g.GTMP_EINVAL
     p = _prob(g)
-    assert g._lib.gtmp_surrogate_prune(C.byref(p), C.byref(net), *([C.c_void_p(256)] * 3), 0.0, C.c_void_p(256),
-                                       None, ws, big, None) == g.GTMP_EINVAL  # net d = 7, problem d = 2
+    assert g._lib.gtmp_surrogate_prune(C.byref(p), C.byref(net), *([C.c_void_p(256)] * 3), None, 0.0,
+                                       C.c_void_p(256), None, ws, big, None) == g.GTMP_EINVAL  # net d = 7, problem d = 2
+    p7 = g.make_problem(7, 3, 16, 1, 8, [-3] * 7, [3] * 7, 1e3)
+    n = C.c_size_t()
+    assert g._lib.gtmp_surrogate_prune_workspace_size(C.byref(p7), C.byref(n)) == g.GTMP_OK and n.value > 0
+    assert g._lib.gtmp_surrogate_prune(C.byref(p7), C.byref(net), *([C.c_void_p(256)] * 3), None, float("nan"),
+                                       C.c_void_p(256), None, ws, big, None) == g.GTMP_EINVAL  # NaN threshold
+    assert g._lib.gtmp_surrogate_prune(C.byref(p7), C.byref(net), *([C.c_void_p(256)] * 3), None, 0.0,
+                                       C.c_void_p(256), None, ws, n.value - 1, None) == g.GTMP_EWORKSPACE
 
 
 def test_noalloc_edge_check_validates(g):

@@ -230,6 +230,83 @@ def test_pruned_check_is_exact_on_survivors(gt, orc):
         assert c_pr == c_plain
 
 
+def _vertex_coll(gt, w, pl):
+    robot, scene = gt.model_of(w)
+    coll = torch.empty(w["M"] * w["N"], device="cuda", dtype=torch.uint8)
+    gt.gtmp_state_check(robot, scene, w["d"], pl.Q.reshape(-1, w["d"]).contiguous(), None, coll)
+    return coll
+
+
+def _candidates(free, N, G):
+    """Edges whose sample endpoints are free (q0 and goals count as free),
+    in edge order C_s | C_h | C_l, from the vertex flags."""
+    M = free.shape[0]
+    parts = [free[0]]
+    for m in range(M - 1):
+        parts.append((free[m][:, None] & free[m + 1][None, :]).reshape(-1))
+    parts.append(np.repeat(free[M - 1], G))
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("scene,N,M", [(1, 64, 3), (0, 100, 4), (2, 37, 1)])
+def test_prune_infers_only_candidate_edges(gt, scene, N, M):
+    """With the sample flags, only edges whose endpoints are free are
+    inferred: their logits and decisions are bit-identical to those of the
+    all-edge call, every other edge is unpruned with a NaN logit; the exact
+    check of the mask leaves the plain optimum's cost when no edge of it is
+    pruned."""
+    w = wl.make_workload("arm7", scene, N=N, M=M)
+    net, _, _ = _net(gt, seed=2)
+    pl = _small_plan(gt, w)
+    pl.check()
+    pl.sweep()
+    pl.extract()
+    c_plain = float(pl.cost.item())
+    flags_plain = pl.flags.clone()
+    coll = _vertex_coll(gt, w, pl)
+    E = pl.E
+    pa, za = torch.empty(E, device="cuda", dtype=torch.uint8), torch.empty(E, device="cuda")
+    pc, zc = torch.full((E,), 7, device="cuda", dtype=torch.uint8), torch.zeros(E, device="cuda")
+    net.prune(pl.prob, pl.q0, pl.goals, pl.Q, 0.0, pa, za)
+    net.prune(pl.prob, pl.q0, pl.goals, pl.Q, 0.0, pc, zc, vcoll=coll)
+    free = coll.cpu().numpy().reshape(M, N) == 0
+    cand = _candidates(free, N, w["G"])
+    assert cand.shape[0] == E
+    pa_, za_, pc_, zc_ = (t.cpu().numpy() for t in (pa, za, pc, zc))
+    _say("candidates", cand.mean(), "pruned among them", pc_[cand].mean() if cand.any() else 0)
+    assert np.array_equal(zc_[cand].view(np.uint32), za_[cand].view(np.uint32))
+    assert np.array_equal(pc_[cand], pa_[cand])
+    assert np.all(np.isnan(zc_[~cand])) and np.all(pc_[~cand] == 0)
+    # non-candidate edges fail the exact check
+    assert np.all(flags_plain.cpu().numpy()[~cand] == 1)
+    pl.check(prune=pc)
+    pl.sweep()
+    pl.extract()
+    m = pc_.astype(bool)
+    f1 = pl.flags.cpu().numpy()
+    assert np.array_equal(f1[~m], flags_plain.cpu().numpy()[~m])
+    assert float(pl.cost.item()) >= c_plain * (1 - 1e-6)
+
+
+def test_prune_with_every_sample_colliding_or_free(gt):
+    """Edge cases of the candidate lists: every sample colliding (no edge is
+    inferred) and every sample free (the all-edge result)."""
+    w = wl.make_workload("arm7", 1, N=40, M=3)
+    net, _, _ = _net(gt, seed=2)
+    pl = _small_plan(gt, w)
+    E = pl.E
+    pa, za = torch.empty(E, device="cuda", dtype=torch.uint8), torch.empty(E, device="cuda")
+    net.prune(pl.prob, pl.q0, pl.goals, pl.Q, 0.0, pa, za)
+    p1, z1 = torch.full((E,), 3, device="cuda", dtype=torch.uint8), torch.zeros(E, device="cuda")
+    net.prune(pl.prob, pl.q0, pl.goals, pl.Q, 0.0, p1, z1,
+              vcoll=torch.ones(w["M"] * w["N"], device="cuda", dtype=torch.uint8))
+    assert int(p1.sum().item()) == 0 and bool(torch.isnan(z1).all().item())
+    p0, z0 = torch.empty(E, device="cuda", dtype=torch.uint8), torch.empty(E, device="cuda")
+    net.prune(pl.prob, pl.q0, pl.goals, pl.Q, 0.0, p0, z0,
+              vcoll=torch.zeros(w["M"] * w["N"], device="cuda", dtype=torch.uint8))
+    assert torch.equal(p0, pa) and torch.equal(z0.view(torch.int32), za.view(torch.int32))
+
+
 # ------------------------------------------------- pruning threshold
 @pytest.mark.parametrize("E,p_free,recall,kind", [(0, 0.5, 0.999, "normal"), (1000, 0.0, 0.999, "normal"),
                                                   (1, 1.0, 0.999, "normal"), (5000, 0.3, 0.999, "normal"),
