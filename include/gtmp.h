@@ -649,7 +649,10 @@ gtmp_status gtmp_surrogate_label_states(const gtmp_problem *prob, uint64_t seed,
                                         void *stream);
 
 /* Prune mask of a plan's edges: prune[e] = 1 iff the logit at the edge's
- * midpoint (u + v) / 2 (FP32) exceeds tau_logit.  Edge order as
+ * midpoint (u + v) / 2 exceeds tau_logit.  The midpoint is exact (FP64 of
+ * the FP32 endpoints); its features are formed from per-sample phase tables
+ * (sin and cos of pi B x / pi for each sample x) by angle addition in FP64,
+ * then rounded to BF16 as in gtmp_surrogate_infer.  Edge order as
  * gtmp_edge_check_cost (C_s | C_h | C_l).  Pass the mask to
  * gtmp_edge_check_cost, which checks every unpruned edge exactly.
  *   vcoll   device uint8 [M][N] or NULL: nonzero = the sample Q[m][n]

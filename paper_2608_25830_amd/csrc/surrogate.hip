@@ -207,9 +207,48 @@ __host__ __device__ constexpr int frag_offset(int l) {
 }
 constexpr int kFragTotal = frag_offset(4);  // 16-byte fragments of the four hidden layers
 
+// Feature order of the fused kernels' LDS rows: each of a row's two
+// threads writes one half with four 16-byte stores, thread 0 [sin f0..7 |
+// cos f0..7 | q/pi (8, zero past d) | 0 x 8], thread 1 [sin f8..15 |
+// cos f8..15 | 0 x 16].  feature_at maps an LDS position to the input of the
+// standard order [q/pi (d) | sin (16) | cos (16) | 0...], -1 for a zero; the
+// first layer's weight fragments are stored in the LDS order, so the sums
+// are over the same products.
+__host__ __device__ inline int feature_at(int p, int d) {
+    if (p < 8) return d + p;
+    if (p < 16) return d + GTMP_SUR_FREQ + (p - 8);
+    if (p < 24) return p - 16 < d ? p - 16 : -1;
+    if (p < 32) return -1;
+    if (p < 40) return d + 8 + (p - 32);
+    if (p < 48) return d + GTMP_SUR_FREQ + 8 + (p - 40);
+    return -1;
+}
+
+__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+// Thread `half` of a row: sn, cs = its 8 frequencies' sines and cosines, qh
+// (half 0) the d linear features; BF16-rounded and stored in the LDS order.
+__device__ __forceinline__ void store_features(int d, int half, const double (&sn)[8], const double (&cs)[8],
+                                               const double (&qh)[GTMP_MAX_DOF], uint16_t *row) {
+    uint16_t v[32];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        v[q] = d2bf(sn[q]);
+        v[8 + q] = d2bf(cs[q]);
+        v[16 + q] = (half == 0 && q < d) ? d2bf(qh[q]) : (uint16_t)0;
+        v[24 + q] = 0;
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(row + 32 * half);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        dst[c] = make_uint4(pack2(v[8 * c], v[8 * c + 1]), pack2(v[8 * c + 2], v[8 * c + 3]),
+                            pack2(v[8 * c + 4], v[8 * c + 5]), pack2(v[8 * c + 6], v[8 * c + 7]));
+}
+
 // Fragment f of layer l: lane = f % 64, K slice ks and column tile c from
 // f / 64 = c * S + ks; it holds W_l[32 c + lane % 32][16 ks + 8 (lane / 32) ..+8].
-__global__ void __launch_bounds__(256) k_weight_frag(const uint16_t *__restrict__ P16, SurLayout L,
+// (Layer 1's columns in the LDS feature order of feature_at.)
+__global__ void __launch_bounds__(256) k_weight_frag(int d, const uint16_t *__restrict__ P16, SurLayout L,
                                                      uint4 *__restrict__ Wf) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= kFragTotal) return;
@@ -219,7 +258,18 @@ __global__ void __launch_bounds__(256) k_weight_frag(const uint16_t *__restrict_
     const int r = f - frag_offset(l);
     const int lane = r & 63, ks = (r >> 6) % S, c = (r >> 6) / S;
     const int row = 32 * c + (lane & 31), col = 16 * ks + 8 * (lane >> 5);
-    Wf[f] = *reinterpret_cast<const uint4 *>(P16 + L.W[l] + (size_t)row * K + col);
+    const uint16_t *src = P16 + L.W[l] + (size_t)row * K;
+    if (l > 0) {
+        Wf[f] = *reinterpret_cast<const uint4 *>(src + col);
+        return;
+    }
+    uint16_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int j = feature_at(col + k, d);
+        w[k] = j < 0 ? (uint16_t)0 : src[j];
+    }
+    Wf[f] = make_uint4(pack2(w[0], w[1]), pack2(w[2], w[3]), pack2(w[4], w[5]), pack2(w[6], w[7]));
 }
 
 // One hidden layer on the block's LDS tile: K input columns -> 256 outputs,
@@ -246,23 +296,42 @@ __device__ __forceinline__ void mlp_layer(const bf16x8 *__restrict__ Wf, const f
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
     const bf16x8 *wr0 = Wf + (size_t)(2 * wave) * S * 64 + lane;
     const bf16x8 *wr1 = Wf + (size_t)(2 * wave + 1) * S * 64 + lane;
-    bf16x8 w0 = wr0[0];
-    bf16x8 w1 = wr1[0];
+    // weight fragments requested kWPre K slices ahead (an L2 round trip is
+    // longer than one slice of MFMAs); the next slice's four activation
+    // fragments are read from LDS while the current slice's MFMAs run
+    constexpr int kWPre = 3;
+    bf16x8 w0[S], w1[S];
+#pragma unroll
+    for (int k = 0; k < kWPre && k < S; ++k) {
+        w0[k] = wr0[64 * k];
+        w1[k] = wr1[64 * k];
+    }
+    auto act_frag = [&](int i, int ks) {
+        return *reinterpret_cast<const bf16x8 *>(&act[(32 * i + cl) * kFRow + 16 * ks + kh]);
+    };
+    bf16x8 a_cur[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a_cur[i] = act_frag(i, 0);
 #pragma unroll
     for (int ks = 0; ks < S; ++ks) {
-        bf16x8 nw0 = w0, nw1 = w1;
+        if (ks + kWPre < S) {
+            w0[ks + kWPre] = wr0[64 * (ks + kWPre)];
+            w1[ks + kWPre] = wr1[64 * (ks + kWPre)];
+        }
+        bf16x8 a_nxt[4];
         if (ks + 1 < S) {
-            nw0 = wr0[64 * (ks + 1)];
-            nw1 = wr1[64 * (ks + 1)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a_nxt[i] = act_frag(i, ks + 1);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[(32 * i + cl) * kFRow + 16 * ks + kh]);
-            acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, a, acc[i][0], 0, 0, 0);
-            acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, a, acc[i][1], 0, 0, 0);
+            acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0[ks], a_cur[i], acc[i][0], 0, 0, 0);
+            acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[ks], a_cur[i], acc[i][1], 0, 0, 0);
         }
-        w0 = nw0;
-        w1 = nw1;
+        if (ks + 1 < S) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a_cur[i] = a_nxt[i];
+        }
     }
     // element v of tile (i, j): output column c0 + 32 j + 8 (v/4) + 4 (lane/32) + v%4, row 32 i + lane%32
     f32x4v bq[2][4];
@@ -296,19 +365,16 @@ __device__ __forceinline__ void mlp_layer(const bf16x8 *__restrict__ Wf, const f
 __device__ __forceinline__ void row_features(int d, const double (&qh)[GTMP_MAX_DOF], int half,
                                              const float *__restrict__ Bf, uint16_t *dst) {
     constexpr double kPi = 3.14159265358979323846;
-    if (half == 0) {
-        for (int j = 0; j < d; ++j) dst[j] = d2bf(qh[j]);
-        for (int k = d + 2 * GTMP_SUR_FREQ; k < GTMP_SUR_IN; ++k) dst[k] = 0;
-    }
-    for (int f = half * (GTMP_SUR_FREQ / 2); f < (half + 1) * (GTMP_SUR_FREQ / 2); ++f) {
+    double sn[8], cs[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int f = half * (GTMP_SUR_FREQ / 2) + q;
         double sarg = 0.0;
         for (int j = 0; j < d; ++j) sarg += (double)Bf[f * d + j] * qh[j];
         sarg *= 2.0 * kPi;
-        double sn, cs;
-        sincos(sarg, &sn, &cs);
-        dst[d + f] = d2bf(sn);
-        dst[d + GTMP_SUR_FREQ + f] = d2bf(cs);
+        sincos(sarg, &sn[q], &cs[q]);
     }
+    store_features(d, half, sn, cs, qh, dst);
 }
 
 // The four hidden layers and the FP32 head of the block's tile; thread
@@ -375,9 +441,8 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(int d, int64_t n, const fl
 // edges (q0 -> free layer-0 samples), s = 1 .. M-1 the free pairs of layers
 // s-1 and s (row-major over the two free lists), s = M the edges from free
 // layer M-1 samples to every goal.
-__global__ void __launch_bounds__(256) k_free_lists(int N, int d, const float *__restrict__ Q,
-                                                    const uint8_t *__restrict__ vcoll, int32_t *__restrict__ fl,
-                                                    float *__restrict__ Qf, int32_t *__restrict__ nf) {
+__global__ void __launch_bounds__(256) k_free_lists(int N, const uint8_t *__restrict__ vcoll,
+                                                    int32_t *__restrict__ fl, int32_t *__restrict__ nf) {
     __shared__ int wsum[256 / kWave];
     const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int count = 0;
@@ -389,15 +454,53 @@ __global__ void __launch_bounds__(256) k_free_lists(int N, int d, const float *_
         __syncthreads();
         int before = count;
         for (int w = 0; w < wv; ++w) before += wsum[w];
-        if (fr) {
-            const size_t slot = (size_t)m * N + before + __popcll(bal & ((1ull << lane) - 1ull));
-            fl[slot] = i;
-            for (int j = 0; j < d; ++j) Qf[slot * d + j] = Q[((size_t)m * N + i) * d + j];
-        }
+        if (fr) fl[(size_t)m * N + before + __popcll(bal & ((1ull << lane) - 1ull))] = i;
         for (int w = 0; w < 256 / kWave; ++w) count += wsum[w];
         __syncthreads();
     }
     if (tid == 0) nf[m] = count;
+}
+
+// Phase table of the probe features.  The midpoint of u and v is
+// (u + v) / 2 exactly (FP64), so its phases are 2 pi B (u + v) / (2 pi) =
+// a(u) + a(v) with a(x) = pi sum_j B_fj (x_j / pi), and its sines and
+// cosines follow from the endpoints' by angle addition.  Row of a sample
+// (kPhaseRow doubles): sin a_f (16), cos a_f (16), x_j / pi (8, zero past d).
+// Rows: the free samples in free-list order ([M][N] slots), then q0, then
+// the goals.
+constexpr int kPhaseRow = 2 * GTMP_SUR_FREQ + GTMP_MAX_DOF;
+
+__global__ void __launch_bounds__(256) k_sample_phases(int d, int M, int N, int G, const float *__restrict__ Q,
+                                                       const float *__restrict__ q0, const float *__restrict__ goals,
+                                                       const int32_t *__restrict__ fl, const int32_t *__restrict__ nf,
+                                                       const float *__restrict__ Bf, double *__restrict__ T) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t MN = (int64_t)M * N;
+    if (t >= MN + 1 + G) return;
+    const float *x;
+    if (t < MN) {
+        const int m = (int)(t / N), i = (int)(t - (int64_t)m * N);
+        if (i >= nf[m]) return;
+        x = Q + ((size_t)m * N + fl[t]) * d;
+    } else if (t == MN) {
+        x = q0;
+    } else {
+        x = goals + (size_t)(t - MN - 1) * d;
+    }
+    constexpr double kPi = 3.14159265358979323846;
+    double qh[GTMP_MAX_DOF];
+    for (int j = 0; j < GTMP_MAX_DOF; ++j) qh[j] = j < d ? (double)x[j] / kPi : 0.0;
+    double *row = T + (size_t)t * kPhaseRow;
+    for (int f = 0; f < GTMP_SUR_FREQ; ++f) {
+        double a = 0.0;
+        for (int j = 0; j < d; ++j) a += (double)Bf[f * d + j] * qh[j];
+        a *= kPi;
+        double sn, cs;
+        sincos(a, &sn, &cs);
+        row[f] = sn;
+        row[GTMP_SUR_FREQ + f] = cs;
+    }
+    for (int j = 0; j < GTMP_MAX_DOF; ++j) row[2 * GTMP_SUR_FREQ + j] = qh[j];
 }
 
 __global__ void k_cand_segments(int M, int G, const int32_t *__restrict__ nf, int64_t *__restrict__ seg) {
@@ -422,20 +525,11 @@ __global__ void k_prune_fill(int64_t E, uint8_t *__restrict__ prune, float *__re
     }
 }
 
-// Endpoints of candidate t (t < total): the two configurations and the
-// edge's flat id.  Segment bounds and list lengths come from LDS; the
-// configurations from the compacted free rows Qf (one memory round trip,
-// with the original indices read beside them).
-struct CandRow {
-    float u[GTMP_MAX_DOF], v[GTMP_MAX_DOF];
-    int64_t e;
-};
-
+// Endpoints of candidate t (t < total): their rows in the phase table and
+// the edge's flat id.  Segment bounds and list lengths come from LDS.
 template <typename IDX>
-__device__ __forceinline__ void cand_fetch(int64_t t, int d, int M, int N, int G, const int64_t *seg,
-                                           const int32_t *nf, const float *__restrict__ q0,
-                                           const float *__restrict__ goals, const float *__restrict__ Qf,
-                                           const int32_t *__restrict__ fl, CandRow &c) {
+__device__ __forceinline__ void cand_rows(int64_t t, int M, int N, int G, const int64_t *seg, const int32_t *nf,
+                                          const int32_t *__restrict__ fl, int64_t &ru, int64_t &rv, int64_t &e) {
     int lo = 0, hi = M;  // largest s in [0, M] with seg[s] <= t
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -443,31 +537,44 @@ __device__ __forceinline__ void cand_fetch(int64_t t, int d, int M, int N, int G
         else hi = mid - 1;
     }
     const IDX loc = (IDX)(t - seg[lo]);
-    const float *pu, *pv;
+    const int64_t MN = (int64_t)M * N;
     if (lo == 0) {
-        pu = q0;
-        pv = Qf + (size_t)loc * d;
-        c.e = fl[loc];
+        ru = MN;
+        rv = (int64_t)loc;
+        e = fl[loc];
     } else if (lo < M) {
         const int m = lo - 1;
         const IDX n1 = (IDX)nf[m + 1];
         const IDX i = loc / n1, j = loc - i * n1;
-        const size_t su = (size_t)m * N + i, sv = (size_t)(m + 1) * N + j;
-        pu = Qf + su * d;
-        pv = Qf + sv * d;
-        c.e = N + (int64_t)m * N * N + (int64_t)fl[su] * N + fl[sv];
+        ru = (int64_t)m * N + (int64_t)i;
+        rv = (int64_t)(m + 1) * N + (int64_t)j;
+        e = N + (int64_t)m * N * N + (int64_t)fl[ru] * N + fl[rv];
     } else {
         const IDX i = loc / (IDX)G, g = loc - i * (IDX)G;
-        const size_t su = (size_t)(M - 1) * N + i;
-        pu = Qf + su * d;
-        pv = goals + (size_t)g * d;
-        c.e = N + (int64_t)(M - 1) * N * N + (int64_t)fl[su] * G + g;
+        ru = (int64_t)(M - 1) * N + (int64_t)i;
+        rv = MN + 1 + (int64_t)g;
+        e = N + (int64_t)(M - 1) * N * N + (int64_t)fl[ru] * G + g;
     }
+}
+
+// Probe features of the midpoint of the samples with phase rows Tu and Tv:
+// x_j / pi = (Tu_j + Tv_j) / 2, sin(a_u + a_v) = sin a_u cos a_v + cos a_u
+// sin a_v, cos(a_u + a_v) = cos a_u cos a_v - sin a_u sin a_v (FP64), each
+// rounded once to BF16; two threads per row as in row_features.
+__device__ __forceinline__ void mid_features(int d, const double *__restrict__ Tu, const double *__restrict__ Tv,
+                                             int half, uint16_t *dst) {
+    double sn[8], cs[8], qh[GTMP_MAX_DOF];
 #pragma unroll
-    for (int j = 0; j < GTMP_MAX_DOF; ++j) {
-        c.u[j] = j < d ? pu[j] : 0.f;
-        c.v[j] = j < d ? pv[j] : 0.f;
+    for (int j = 0; j < GTMP_MAX_DOF; ++j)
+        qh[j] = half == 0 && j < d ? (Tu[2 * GTMP_SUR_FREQ + j] + Tv[2 * GTMP_SUR_FREQ + j]) * 0.5 : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int f = half * (GTMP_SUR_FREQ / 2) + q;
+        const double su = Tu[f], cu = Tu[GTMP_SUR_FREQ + f], sv = Tv[f], cv = Tv[GTMP_SUR_FREQ + f];
+        sn[q] = __builtin_fma(su, cv, cu * sv);
+        cs[q] = __builtin_fma(cu, cv, -(su * sv));
     }
+    store_features(d, half, sn, cs, qh, dst);
 }
 
 constexpr int kSegLds = 130;  // segment bounds kept in LDS (M <= 128)
@@ -476,16 +583,15 @@ constexpr int kSegLds = 130;  // segment bounds kept in LDS (M <= 128)
 // (the candidate count is known only on the device: blocks past it return
 // at once).  Blocks of one CU start at different times, so one block's
 // feature or head phase overlaps the other's MFMAs.  The candidate's
-// endpoints give the midpoint (u + v) * 0.5 (FP32), its features and logit
-// z; prune[e] = z > tau and logits[e] = z at the edge's flat id e
-// (C_s | C_h | C_l order).
+// endpoints give the features of the midpoint (u + v) / 2 (from their phase
+// rows) and its logit z; prune[e] = z > tau and logits[e] = z at the edge's
+// flat id e (C_s | C_h | C_l order).
 template <typename IDX>
-__global__ void __launch_bounds__(256, 2) k_mlp_prune(int d, int M, int N, int G, const float *__restrict__ q0,
-                                                     const float *__restrict__ goals, const float *__restrict__ Qf,
+__global__ void __launch_bounds__(256, 2) k_mlp_prune(int d, int M, int N, int G, const double *__restrict__ T,
                                                      const int32_t *__restrict__ fl, const int32_t *__restrict__ nf,
-                                                     const int64_t *__restrict__ seg, const float *__restrict__ Bf,
-                                                     const bf16x8 *__restrict__ Wf, const uint16_t *__restrict__ P16,
-                                                     const float *__restrict__ P32, SurLayout L, float tau,
+                                                     const int64_t *__restrict__ seg, const bf16x8 *__restrict__ Wf,
+                                                     const uint16_t *__restrict__ P16, const float *__restrict__ P32,
+                                                     SurLayout L, float tau,
                                                      uint8_t *__restrict__ prune, float *__restrict__ logits) {
     __shared__ __attribute__((aligned(16))) uint16_t act[kFR * kFRow];
     __shared__ float w5s[GTMP_SUR_WIDTH];
@@ -509,17 +615,15 @@ __global__ void __launch_bounds__(256, 2) k_mlp_prune(int d, int M, int N, int G
     {
         const int r = tid & (kFR - 1), half = tid >> 7;
         const int64_t t = tile * kFR + r;
-        constexpr double kPi = 3.14159265358979323846;
-        double qh[GTMP_MAX_DOF];
-        const bool live = t < total;
-        CandRow c;
-        c.e = -1;
-        if (live) cand_fetch<IDX>(t, d, M, N, G, sg, nl, q0, goals, Qf, fl, c);
-#pragma unroll
-        for (int j = 0; j < GTMP_MAX_DOF; ++j)
-            qh[j] = live && j < d ? (double)((c.u[j] + c.v[j]) * 0.5f) / kPi : 0.0;
-        if (half == 0) eid[r] = c.e;
-        row_features(d, qh, half, Bf, act + r * kFRow);
+        int64_t ru = 0, rv = 0, e = -1;
+        if (t < total) cand_rows<IDX>(t, M, N, G, sg, nl, fl, ru, rv, e);
+        if (half == 0) eid[r] = e;
+        if (e >= 0) {
+            mid_features(d, T + (size_t)ru * kPhaseRow, T + (size_t)rv * kPhaseRow, half, act + r * kFRow);
+        } else {
+            uint4 *z4 = reinterpret_cast<uint4 *>(act + r * kFRow + 32 * half);
+            for (int c = 0; c < 4; ++c) z4[c] = make_uint4(0u, 0u, 0u, 0u);
+        }
     }
     __syncthreads();
     const float z = mlp_tile(Wf, P32, L, act, w5s, zpart, tid);
@@ -770,7 +874,8 @@ static void forward(const SurNet &net, int64_t n, const float *X, const SurWs &w
 }
 
 static void weight_frag(const SurNet &net, uint4 *Wf, hipStream_t s) {
-    hipLaunchKernelGGL(k_weight_frag, dim3((kFragTotal + 255) / 256), dim3(256), 0, s, net.p16, sur_layout(), Wf);
+    hipLaunchKernelGGL(k_weight_frag, dim3((kFragTotal + 255) / 256), dim3(256), 0, s, net.d, net.p16, sur_layout(),
+                       Wf);
 }
 
 hipError_t launch_sur_infer(const SurNet &net, int64_t n, const float *X, float *logits, void *ws, size_t ws_bytes,
@@ -876,7 +981,7 @@ hipError_t launch_sur_label_states(const gtmp_problem &p, uint64_t seed, uint64_
 struct PruneWs {
     uint4 *Wf;
     int32_t *fl, *nf;
-    float *Qf;
+    double *T;
     int64_t *seg;
     size_t total;
 };
@@ -888,7 +993,7 @@ static PruneWs carve_prune(const gtmp_problem &p, void *base) {
     auto take = [&](size_t bytes) { char *r = q ? q + o : nullptr; o = up256(o + bytes); return r; };
     w.Wf = reinterpret_cast<uint4 *>(take(sizeof(uint4) * kFragTotal));
     w.fl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)p.M * p.N));
-    w.Qf = reinterpret_cast<float *>(take(sizeof(float) * (size_t)p.M * p.N * p.d));
+    w.T = reinterpret_cast<double *>(take(sizeof(double) * kPhaseRow * ((size_t)p.M * p.N + 1 + p.G)));
     w.nf = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)p.M));
     w.seg = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * ((size_t)p.M + 2)));
     w.total = o;
@@ -905,16 +1010,18 @@ hipError_t launch_sur_prune(const gtmp_problem &p, const SurNet &net, const floa
     weight_frag(net, w.Wf, s);
     const int64_t fill_blocks = std::min<int64_t>((E + 255) / 256, 4096);
     hipLaunchKernelGGL(k_prune_fill, dim3((unsigned)fill_blocks), dim3(256), 0, s, E, prune, logits);
-    hipLaunchKernelGGL(k_free_lists, dim3(p.M), dim3(256), 0, s, p.N, p.d, Q, vcoll, w.fl, w.Qf, w.nf);
+    hipLaunchKernelGGL(k_free_lists, dim3(p.M), dim3(256), 0, s, p.N, vcoll, w.fl, w.nf);
+    const int64_t rows = (int64_t)p.M * p.N + 1 + p.G;
+    hipLaunchKernelGGL(k_sample_phases, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, p.d, p.M, p.N, p.G, Q,
+                       q0, goals, w.fl, w.nf, net.fourier, w.T);
     hipLaunchKernelGGL(k_cand_segments, dim3(1), dim3(64), 0, s, p.M, p.G, w.nf, w.seg);
     const int64_t grid = (E + kFR - 1) / kFR;  // candidates <= E
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     // 32-bit index arithmetic when every segment's local index fits
     const bool narrow = (uint64_t)p.N * p.N < (1ull << 32) && (uint64_t)p.N * p.G < (1ull << 32);
     const auto kern = narrow ? k_mlp_prune<uint32_t> : k_mlp_prune<uint64_t>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, s, net.d, p.M, p.N, p.G, q0, goals, w.Qf, w.fl,
-                       w.nf, w.seg, net.fourier, reinterpret_cast<const bf16x8 *>(w.Wf), net.p16, net.p32,
-                       sur_layout(), tau, prune, logits);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, s, net.d, p.M, p.N, p.G, w.T, w.fl, w.nf, w.seg,
+                       reinterpret_cast<const bf16x8 *>(w.Wf), net.p16, net.p32, sur_layout(), tau, prune, logits);
     return hipGetLastError();
 }
 
