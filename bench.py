@@ -41,7 +41,7 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
 # FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/ (scaled by the
 # plain-copy calibration).  A value is only reported while the kernel sources
 # still hash to the fingerprint it was measured on.
-MEASURED_TRAFFIC = {"arm7": (6.043e+07, "6143bbbb93a86f49", "profiles/k_interior_arm7.md")}
+MEASURED_TRAFFIC = {"arm7": (5.201e+07, "71ff287695e334e2", "profiles/k_interior_arm7.md")}
 KERNEL_SOURCES = ["paper_2608_25830_amd/csrc/edge.hip", "paper_2608_25830_amd/csrc/edge_common.hpp",
                   "paper_2608_25830_amd/csrc/gtmp_device.hpp"]
 
@@ -765,7 +765,6 @@ def main():
     step_ms = np.array([sb[i].elapsed_time(sb[i + 1]) for i in range(args.steps)])
     states = torch.diff(stats_hist[:, 0]).cpu().numpy().astype(np.float64)
     tests = torch.diff(stats_hist[:, 2]).cpu().numpy().astype(np.float64)
-    rounds = torch.diff(stats_hist[:, 3]).cpu().numpy().astype(np.float64)
     costs = cost_hist.cpu().numpy()
 
     value = E * H / (ms_per_step / 1e3)
@@ -831,7 +830,6 @@ def main():
                      "kernel": "k_interior (early-exit interior edge checker)" + (", obstacle-bin filter" if grid else ""),
                      "kernel_ms": k_ms, "states_evaluated_per_launch": st, "flop_per_state": f_state,
                      "states_evaluated_frac": st / (E * H),
-                     "lane_busy_frac": st / (64.0 * float(np.mean(rounds))) if np.mean(rounds) > 0 else None,
                      "obstacle_bins": grid},
         "edge_opts": {k: int(getattr(pl.opts, k)) for k in ("mode", "states_per_iter", "blocks_per_cu",
                                                                "sphere_chunks")},

@@ -150,9 +150,7 @@ typedef struct gtmp_edge_opts {
     int32_t reserved[3];
     unsigned long long *stats; /* optional device [4]: states evaluated, edges checked in the
                                   interior pass, exact sphere-obstacle tests made behind the
-                                  obstacle bins (sphere_chunks 0), evaluation rounds of the
-                                  interior kernel's waves (64 lane slots each; single plans).
-                                  Added to. */
+                                  obstacle bins (sphere_chunks 0), [3] unused.  Added to. */
     void *ev_begin;            /* optional hipEvent_t recorded on `stream` just before the
                                   interior (fast mode) or every-state (full mode) kernel */
     void *ev_end;              /* optional hipEvent_t recorded just after it */

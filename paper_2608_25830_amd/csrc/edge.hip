@@ -310,11 +310,20 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     }
     __syncthreads();
     float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
-    if constexpr (GRID) {  // wave-uniform: held in scalar registers
+    if constexpr (GRID && Model::kArm) {
+        // wave-uniform and used once per link: held in scalar registers
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             ginv[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(glds.inv[i])));
             goff[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(glds.off[i])));
+        }
+    } else if constexpr (GRID) {
+        // point probes take both in one FMA per axis, which can read only one
+        // scalar operand: vector registers avoid a copy per probe
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ginv[i] = glds.inv[i];
+            goff[i] = glds.off[i];
         }
     }
 
@@ -337,7 +346,6 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     bool exhausted = false;
     unsigned long long n_states = 0, n_edges = 0;
     uint32_t n_tests = 0;  // exact sphere-obstacle tests behind the bin filter (this lane)
-    uint32_t n_iters = 0;  // evaluation rounds of this wave (64 lane slots each)
 
     // lane state: the edge (flat id), its start and direction, next state
     bool has = false;
@@ -417,7 +425,6 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
         const uint64_t busy = ballot(has);
         if (busy == 0) break;  // exhausted and every lane idle
         n_states += (unsigned long long)__popcll(busy) * SP;
-        ++n_iters;
 
         // ---- evaluate the next interior state(s) of every busy lane
         float gap;
@@ -504,7 +511,6 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     if (A.stats && lane == 0) {
         atomicAdd(&A.stats[0], n_states);
         atomicAdd(&A.stats[1], n_edges);
-        atomicAdd(&A.stats[3], (unsigned long long)n_iters);
     }
 }
 
