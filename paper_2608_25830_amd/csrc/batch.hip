@@ -410,17 +410,10 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4
             }
         }
     }
-    if constexpr (GRID) {
-        if (stats) {
-            unsigned long long t = n_tests;
-#pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
-            if (lane == 0) atomicAdd(&stats[2], t);
-        }
-    }
     if (stats && lane == 0) {
         atomicAdd(&stats[0], n_states);
         atomicAdd(&stats[1], n_edges);
+        if constexpr (GRID) atomicAdd(&stats[2], (unsigned long long)n_tests);  // wave total
     }
 }
 

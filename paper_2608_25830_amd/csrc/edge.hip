@@ -34,6 +34,56 @@ __host__ __device__ __forceinline__ uint32_t cursor_begin(uint32_t n_tiles, uint
     return (uint32_t)((uint64_t)n_tiles * c / kCursors);
 }
 
+// Statistics of the interior kernel.  Every wave writes its totals (states
+// evaluated, edges taken, exact tests) to its own slot with plain stores, and
+// k_wave_stats_sum adds the slots to the caller's counters after the kernel:
+// a persistent grid's waves all finish at about the same time, and one atomic
+// add per wave on the same three words then serialised into a tail of about
+// 0.1 ms.  Waves past kStatWaves add their totals directly.
+constexpr uint32_t kStatWaves = 16384;
+
+__global__ void __launch_bounds__(256) k_wave_stats_sum(const unsigned long long *__restrict__ w, uint32_t waves,
+                                                        unsigned long long *stats) {
+    __shared__ unsigned long long part[3][256 / kWave];
+    unsigned long long acc[3] = {0, 0, 0};
+    for (uint32_t i = threadIdx.x; i < waves; i += blockDim.x)
+        for (int c = 0; c < 3; ++c) acc[c] += w[4 * (size_t)i + c];
+    const int lane = lane_id(), wv = threadIdx.x / kWave;
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off);
+        if (lane == 0) part[c][wv] = acc[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long t = 0;
+        for (int k = 0; k < 256 / kWave; ++k) t += part[threadIdx.x][k];
+        atomicAdd(&stats[threadIdx.x], t);
+    }
+}
+
+static void finish_wave_stats(const EdgeArgs &A, unsigned grid_blocks, hipStream_t s) {
+    if (!A.stats) return;
+    const uint64_t waves = (uint64_t)grid_blocks * (256 / kWave);
+    hipLaunchKernelGGL(k_wave_stats_sum, dim3(1), dim3(256), 0, s, A.wstats,
+                       (uint32_t)(waves < kStatWaves ? waves : kStatWaves), A.stats);
+}
+
+// A wave's totals (lane 0 calls this).
+__device__ __forceinline__ void store_wave_stats(const EdgeArgs &A, unsigned long long states,
+                                                 unsigned long long edges, unsigned long long tests) {
+    const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (wid < kStatWaves) {
+        A.wstats[4 * (size_t)wid + 0] = states;
+        A.wstats[4 * (size_t)wid + 1] = edges;
+        A.wstats[4 * (size_t)wid + 2] = tests;
+    } else {
+        atomicAdd(&A.stats[0], states);
+        atomicAdd(&A.stats[1], edges);
+        atomicAdd(&A.stats[2], tests);
+    }
+}
+
 // ------------------------------------------------------------------ plan
 EdgePlan make_edge_plan(const gtmp_problem &p) {
     EdgePlan e{};
@@ -50,6 +100,7 @@ EdgePlan make_edge_plan(const gtmp_problem &p) {
     e.off_tile_off = o; o = up(o + (size_t)e.n_tiles * kTile);
     e.off_tile_cnt = o; o = up(o + sizeof(uint32_t) * (size_t)e.n_tiles);
     e.off_counter = o; o = up(o + sizeof(uint32_t) * kCursorStride * kCursors);
+    e.off_wstats = o; o = up(o + sizeof(unsigned long long) * 4 * kStatWaves);
     e.off_params = o; o = up(o + sizeof(ArmParams));
     e.off_grid = o; o = up(o + sizeof(ObsGrid));
     e.total = o;
@@ -332,7 +383,10 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     uint32_t chunk = kWave;
     if constexpr (LIST) {
         const uint32_t n_list = uniform(*A.n_list);
-        if ((uint64_t)n_list * (uint32_t)A.n_int <= list_states_limit()) return;  // k_list_states took it
+        if ((uint64_t)n_list * (uint32_t)A.n_int <= list_states_limit()) {  // k_list_states took it
+            if (A.stats && lane_id() == 0) store_wave_stats(A, 0, 0, 0);
+            return;
+        }
         const uint32_t waves = gridDim.x * (blockDim.x / kWave);
         chunk = (n_list + waves - 1) / waves;
         chunk = chunk < (uint32_t)kListChunk ? (uint32_t)kListChunk : chunk > (uint32_t)kWave ? (uint32_t)kWave : chunk;
@@ -344,8 +398,10 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     uint32_t cursor = blockIdx.x % kCursors, cursors_left = kCursors;
     RowInfo ri{};
     bool exhausted = false;
+    // wave totals (wave-uniform, scalar registers): states evaluated, edges
+    // taken, exact sphere-obstacle tests behind the bin filter
     unsigned long long n_states = 0, n_edges = 0;
-    uint32_t n_tests = 0;  // exact sphere-obstacle tests behind the bin filter (this lane)
+    uint32_t n_tests = 0;
 
     // lane state: the edge (flat id), its start and direction, next state
     bool has = false;
@@ -418,13 +474,17 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                 has = true;
             }
             pos += take;
-            if constexpr (!LIST) n_edges += take;  // lists: counted by k_list_finish
+            if constexpr (!LIST) {
+                n_edges += take;  // lists: counted by k_list_finish
+                asm volatile("" : "+s"(n_edges));
+            }
             need = ballot(!has && taker);
             n_need = __popcll(need);
         }
         const uint64_t busy = ballot(has);
         if (busy == 0) break;  // exhausted and every lane idle
         n_states += (unsigned long long)__popcll(busy) * SP;
+        asm volatile("" : "+s"(n_states));  // wave-uniform: a scalar register pair
 
         // ---- evaluate the next interior state(s) of every busy lane
         float gap;
@@ -500,18 +560,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             }
         }
     }
-    if constexpr (GRID) {
-        if (A.stats) {
-            unsigned long long t = n_tests;
-#pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
-            if (lane == 0) atomicAdd(&A.stats[2], t);
-        }
-    }
-    if (A.stats && lane == 0) {
-        atomicAdd(&A.stats[0], n_states);
-        atomicAdd(&A.stats[1], n_edges);
-    }
+    if (A.stats && lane == 0) store_wave_stats(A, n_states, n_edges, GRID ? n_tests : 0u);
 }
 
 // Edges with H == 2 have no interior state: the pre-pass result is final
@@ -613,14 +662,9 @@ __global__ void __launch_bounds__(256, 3) k_list_states(EdgeArgs A, const ArmPar
         if (live && hit) A.list_mark[e] = 2;
         n_states += (unsigned long long)__popcll(ballot(live));
     }
-    if (A.stats && lane == 0) atomicAdd(&A.stats[0], n_states);
-    if constexpr (GRID) {
-        if (A.stats) {
-            unsigned long long tt = n_tests;
-#pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1) tt += __shfl_xor(tt, off);
-            if (lane == 0) atomicAdd(&A.stats[2], tt);
-        }
+    if (A.stats && lane == 0) {
+        atomicAdd(&A.stats[0], n_states);
+        if constexpr (GRID) atomicAdd(&A.stats[2], (unsigned long long)n_tests);  // wave total
     }
 }
 
@@ -867,6 +911,7 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
         hipLaunchKernelGGL((k_interior<ArmModel<KP>, false, NCH>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     }
     if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
+    if (A.n_int > 0) finish_wave_stats(A, (unsigned)grid_persist, s);
     (void)b;
     return hipGetLastError();
 }
@@ -908,6 +953,7 @@ static hipError_t launch_point_s(const EdgeArgs &A, const ArmParams &R, const Sc
                            (const ArmParams *)nullptr, S);
     }
     if (o.ev_end) (void)hipEventRecord((hipEvent_t)o.ev_end, s);
+    if (A.n_int > 0) finish_wave_stats(A, (unsigned)grid_persist, s);
     return hipGetLastError();
 }
 
@@ -984,6 +1030,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
     A.tile_off = reinterpret_cast<uint8_t *>(ws + plan.off_tile_off);
     A.tile_cnt = reinterpret_cast<uint32_t *>(ws + plan.off_tile_cnt);
     A.counter = reinterpret_cast<uint32_t *>(ws + plan.off_counter);
+    A.wstats = reinterpret_cast<unsigned long long *>(ws + plan.off_wstats);
     A.edge_list = edge_list;
     A.n_list = n_list;
     A.list_mark = list_mark;

@@ -80,6 +80,7 @@ struct EdgeArgs {
     const uint32_t *n_list;
     uint8_t *list_mark;         // lazy rounds: per flat edge id, set to 2 when a listed edge collides
     unsigned long long *stats;
+    unsigned long long *wstats;  // [kStatWaves][4]: the interior kernel's per-wave totals (when stats is set)
     const ObsGrid *grid;  // arms with the bin filter: the obstacle bins of this scene
     size_t off_params;  // workspace byte offset of the device copy of the robot table
     int n_int;
@@ -249,7 +250,9 @@ __device__ __forceinline__ void build_grid_block(const SceneParams &S, int wdim,
 // one per lane, which keeps every lane busy in the tests.  A lane appends
 // nothing more once a drained test has found its state in contact, and a lane
 // that is not `live` appends nothing at all (its result is then meaningless).
-// `tests` counts the exact tests this lane made (for other lanes' entries too).
+// `tests` counts the exact tests of the whole wave, one popcount per round of
+// the test loop: a wave-uniform total held in a scalar register (a per-lane
+// count would take vector registers in the hot loop).
 // Every lane of the wave must call this (it drains on ballots).
 constexpr int kQueue = 128;  // entries per wave: up to 63 waiting plus one probe of every lane
 
@@ -299,7 +302,10 @@ struct GridProber {
             if constexpr (WORDS > 2) m2 = w.z;
             own = (int)w.w;
         }
-        while (ballot(m != 0 || m2 != 0) != 0) {
+        for (;;) {
+            const uint64_t act = ballot(m != 0 || m2 != 0);
+            if (act == 0) break;
+            tests += (uint32_t)__popcll(act);
             if (m != 0 || m2 != 0) {
                 int o;
                 if (m != 0) {
@@ -309,7 +315,6 @@ struct GridProber {
                     o = 64 + __builtin_ctz(m2);
                     m2 &= m2 - 1;
                 }
-                ++tests;
                 const float4 a = rec[o][0], h = rec[o][1];
                 const float Rr = a.w + e.w;
                 float g = -Rr * Rr;

@@ -26,7 +26,7 @@ struct EdgePlan {
     uint32_t tiles_per_row;  // ceil(N / kTile)
     uint32_t n_tiles;
     // workspace carve-up (byte offsets)
-    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_counter, off_params, off_grid, total;
+    size_t off_verts, off_vflag, off_tile_off, off_tile_cnt, off_counter, off_params, off_grid, off_wstats, total;
 };
 
 EdgePlan make_edge_plan(const gtmp_problem &p);
