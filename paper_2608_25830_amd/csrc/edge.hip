@@ -39,8 +39,11 @@ __host__ __device__ __forceinline__ uint32_t cursor_begin(uint32_t n_tiles, uint
 // k_wave_stats_sum adds the slots to the caller's counters after the kernel:
 // a persistent grid's waves all finish at about the same time, and one atomic
 // add per wave on the same three words then serialised into a tail of about
-// 0.1 ms.  Waves past kStatWaves add their totals directly.
+// 0.1 ms.  Waves past kStatWaves, and every wave of a grid under
+// kStatSlotsMinWaves (where the extra launch costs more than the atomics),
+// add their totals directly.
 constexpr uint32_t kStatWaves = 16384;
+constexpr uint32_t kStatSlotsMinWaves = 1024;
 
 __global__ void __launch_bounds__(256) k_wave_stats_sum(const unsigned long long *__restrict__ w, uint32_t waves,
                                                         unsigned long long *stats) {
@@ -62,8 +65,14 @@ __global__ void __launch_bounds__(256) k_wave_stats_sum(const unsigned long long
     }
 }
 
+// The per-wave slots of a grid of grid_blocks blocks of 256 threads (NULL:
+// its waves add to the counters directly).
+static unsigned long long *wave_stat_slots(const EdgeArgs &A, unsigned grid_blocks) {
+    return A.stats && (uint64_t)grid_blocks * (256 / kWave) >= kStatSlotsMinWaves ? A.wstats : nullptr;
+}
+
 static void finish_wave_stats(const EdgeArgs &A, unsigned grid_blocks, hipStream_t s) {
-    if (!A.stats) return;
+    if (!A.stats || !A.wstats) return;
     const uint64_t waves = (uint64_t)grid_blocks * (256 / kWave);
     hipLaunchKernelGGL(k_wave_stats_sum, dim3(1), dim3(256), 0, s, A.wstats,
                        (uint32_t)(waves < kStatWaves ? waves : kStatWaves), A.stats);
@@ -73,7 +82,7 @@ static void finish_wave_stats(const EdgeArgs &A, unsigned grid_blocks, hipStream
 __device__ __forceinline__ void store_wave_stats(const EdgeArgs &A, unsigned long long states,
                                                  unsigned long long edges, unsigned long long tests) {
     const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (wid < kStatWaves) {
+    if (A.wstats && wid < kStatWaves) {
         A.wstats[4 * (size_t)wid + 0] = states;
         A.wstats[4 * (size_t)wid + 1] = edges;
         A.wstats[4 * (size_t)wid + 2] = tests;
@@ -1105,6 +1114,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
             default: return hipErrorInvalidValue;
         }
         const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles);
+        A.wstats = wave_stat_slots(A, (unsigned)grid);
         switch (kp * 8 + nch) {
 #define GTMP_LA(K, C) case K * 8 + C: return launch_arm_kp<K, C>(A, R, scene, b, o, grid, s, b.q0, b.goals, b.Q, verts, vflag, phases, gw);
 #define GTMP_LA3(K) GTMP_LA(K, 1) GTMP_LA(K, 2) GTMP_LA(K, 4)
@@ -1132,6 +1142,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
                          : spi == 4 ? (const void *)k_interior<PointModel<2, 4>, true, 1>
                                     : (const void *)k_interior<PointModel<2, 8>, true, 1>;
         const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, gw ? kPointGridBlocksPerCuAuto : kPointBlocksPerCuAuto);
+        A.wstats = wave_stat_slots(A, (unsigned)grid);
         return launch_point<2>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases, gw);
     }
     const void *kern = gw == 1 ? (const void *)k_interior<PointGridModel<3, kPointGridSp, 1>, true, 1>
@@ -1142,6 +1153,7 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
                      : spi == 4 ? (const void *)k_interior<PointModel<3, 4>, true, 1>
                                 : (const void *)k_interior<PointModel<3, 8>, true, 1>;
     const int grid = persistent_grid(kern, 256, o.blocks_per_cu, plan.n_tiles, gw ? kPointGridBlocksPerCuAuto : kPointBlocksPerCuAuto);
+    A.wstats = wave_stat_slots(A, (unsigned)grid);
     return launch_point<3>(A, R, scene, spi, grid, o, s, b.q0, b.goals, b.Q, verts, vflag, phases, gw);
 }
 

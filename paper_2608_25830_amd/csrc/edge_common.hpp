@@ -80,7 +80,7 @@ struct EdgeArgs {
     const uint32_t *n_list;
     uint8_t *list_mark;         // lazy rounds: per flat edge id, set to 2 when a listed edge collides
     unsigned long long *stats;
-    unsigned long long *wstats;  // [kStatWaves][4]: the interior kernel's per-wave totals (when stats is set)
+    unsigned long long *wstats;  // [kStatWaves][4]: the interior kernel's per-wave totals, or NULL: atomics
     const ObsGrid *grid;  // arms with the bin filter: the obstacle bins of this scene
     size_t off_params;  // workspace byte offset of the device copy of the robot table
     int n_int;
