@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kTile) k_batch_prepass(const BPlan *plans, int
 // table are read with wave-uniform addresses.  A wave that draws a tile of
 // another plan finishes its edges before it switches.
 template <class Model, bool UNIFORM_R, int NCH>
-__global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : 4) : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
+__global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : (Model::kArm ? 5 : 4)) : NCH == 1 ? 3 : NCH == 2 ? 4 : 5)
     k_batch_interior(const BPlan *plans, int p0, int p1, uint32_t n_gtiles, uint32_t *gcounter,
                      unsigned long long *stats) {
     constexpr int D = Model::D;

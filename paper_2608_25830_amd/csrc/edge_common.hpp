@@ -258,10 +258,11 @@ constexpr int kQueue = 128;  // entries per wave: up to 63 waiting plus one prob
 
 template <int WORDS>
 struct GridQueue {
-    struct Entry {
-        float4 c;  // probe centre, radius
-        uint4 m;   // mask words 0, 1, 2 (unused words 0), owning lane
-    } e[kQueue];
+    // one array per field (2,752 bytes per wave with one mask word, against
+    // 4,160 for 32-byte entries; the batched kernels hold a queue per wave)
+    float4 c[kQueue];           // probe centre, radius
+    uint32_t m[WORDS][kQueue];  // mask words
+    uint8_t own[kQueue];        // owning lane
     uint8_t hit[kWave];
 };
 
@@ -296,11 +297,12 @@ struct GridProber {
         float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
         int own = 0;
         if ((uint32_t)lane < n) {
-            e = Q.e[slot].c;
-            const uint4 w = Q.e[slot].m;
-            m = WORDS == 1 ? (Mask)w.x : (Mask)(((uint64_t)w.y << 32) | w.x);
-            if constexpr (WORDS > 2) m2 = w.z;
-            own = (int)w.w;
+            e = Q.c[slot];
+            const uint32_t w0 = Q.m[0][slot];
+            if constexpr (WORDS == 1) m = (Mask)w0;
+            else m = (Mask)(((uint64_t)Q.m[WORDS > 1 ? 1 : 0][slot] << 32) | w0);
+            if constexpr (WORDS > 2) m2 = Q.m[WORDS > 2 ? 2 : 0][slot];
+            own = (int)Q.own[slot];
         }
         for (;;) {
             const uint64_t act = ballot(m != 0 || m2 != 0);
@@ -354,9 +356,10 @@ struct GridProber {
                 float c[3];
                 centre(c);
                 const uint32_t slot = (tail + (uint32_t)rank_in(wmask)) & (kQueue - 1);
-                Q.e[slot].c = make_float4(c[0], c[1], c[2], radius());
-                Q.e[slot].m = make_uint4(mw[0], WORDS > 1 ? mw[WORDS > 1 ? 1 : 0] : 0u,
-                                         WORDS > 2 ? mw[WORDS > 2 ? 2 : 0] : 0u, (uint32_t)lane_id());
+                Q.c[slot] = make_float4(c[0], c[1], c[2], radius());
+#pragma unroll
+                for (int wd = 0; wd < WORDS; ++wd) Q.m[wd][slot] = mw[wd];
+                Q.own[slot] = (uint8_t)lane_id();
             }
             tail += (uint32_t)__popcll(wmask);
             if (tail - head >= (uint32_t)kWave) drain(kWave);
