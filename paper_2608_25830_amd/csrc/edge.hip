@@ -47,10 +47,12 @@ constexpr uint32_t kStatSlotsMinWaves = 1024;
 
 __global__ void __launch_bounds__(256) k_wave_stats_sum(const unsigned long long *__restrict__ w, uint32_t waves,
                                                         unsigned long long *stats) {
+    // one slot per thread, a block's sums added with one atomic per counter
     __shared__ unsigned long long part[3][256 / kWave];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long acc[3] = {0, 0, 0};
-    for (uint32_t i = threadIdx.x; i < waves; i += blockDim.x)
-        for (int c = 0; c < 3; ++c) acc[c] += w[4 * (size_t)i + c];
+    if (i < waves)
+        for (int c = 0; c < 3; ++c) acc[c] = w[4 * (size_t)i + c];
     const int lane = lane_id(), wv = threadIdx.x / kWave;
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -73,9 +75,9 @@ static unsigned long long *wave_stat_slots(const EdgeArgs &A, unsigned grid_bloc
 
 static void finish_wave_stats(const EdgeArgs &A, unsigned grid_blocks, hipStream_t s) {
     if (!A.stats || !A.wstats) return;
-    const uint64_t waves = (uint64_t)grid_blocks * (256 / kWave);
-    hipLaunchKernelGGL(k_wave_stats_sum, dim3(1), dim3(256), 0, s, A.wstats,
-                       (uint32_t)(waves < kStatWaves ? waves : kStatWaves), A.stats);
+    const uint64_t all = (uint64_t)grid_blocks * (256 / kWave);
+    const uint32_t waves = (uint32_t)(all < kStatWaves ? all : kStatWaves);
+    hipLaunchKernelGGL(k_wave_stats_sum, dim3((waves + 255) / 256), dim3(256), 0, s, A.wstats, waves, A.stats);
 }
 
 // A wave's totals (lane 0 calls this).
