@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : (
                     float acc = 0.f;
 #pragma unroll
                     for (int i = 0; i < D; ++i)
-                        if (i < A.d) acc = __builtin_fmaf(dv[i], dv[i], acc);
+                        acc = __builtin_fmaf(dv[i], dv[i], acc);  // zero past d
                     *cost_slot(A, e) = __builtin_sqrtf(acc);
                     if (A.flags) A.flags[e] = 0;
                     has = false;

@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) k_vertices_point(EdgeArgs A, SceneParams 
     const float *src = i == 0 ? q0 : (i <= MN ? Q + (size_t)(i - 1) * W : goals + (size_t)(i - 1 - MN) * W);
     Probes<W, 1> P;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) verts[(size_t)i * A.dp + j] = j < W ? src[j] : 0.f;
+    for (int j = 0; j < GTMP_MAX_DOF; ++j) verts[(size_t)i * A.dp + j] = j < W ? src[j] : 0.f;  // zeros past W
 #pragma unroll
     for (int j = 0; j < W; ++j) P.p[j][0] = src[j];
     const float pr[1] = {0.f};
@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                     float acc = 0.f;
 #pragma unroll
                     for (int i = 0; i < D; ++i)
-                        if (i < A.d) acc = __builtin_fmaf(dv[i], dv[i], acc);
+                        acc = __builtin_fmaf(dv[i], dv[i], acc);  // zero past d
                     *cost_slot(A, e) = __builtin_sqrtf(acc);
                     if (A.flags) A.flags[e] = 0;
                     has = false;

@@ -570,16 +570,19 @@ __device__ __forceinline__ void load_vertex(const EdgeArgs &A, uint32_t vid, flo
 }
 
 // Euclidean length in configuration space (FP32, fixed summation order so
-// that the pre-pass and the interior kernel produce the same value).
+// that the pre-pass and the interior kernel produce the same value).  The
+// coordinates past d are zero in both endpoints (the packed vertex array and
+// every caller fill them with zeros), so all D are summed: a zero difference
+// leaves the sum exactly as it is.
 template <int D>
 __device__ __forceinline__ float edge_len(const float (&u)[D], const float (&v)[D], int d) {
+    (void)d;
     float acc = 0.f;
 #pragma unroll
-    for (int i = 0; i < D; ++i)
-        if (i < d) {
-            const float t = v[i] - u[i];
-            acc = __builtin_fmaf(t, t, acc);
-        }
+    for (int i = 0; i < D; ++i) {
+        const float t = v[i] - u[i];
+        acc = __builtin_fmaf(t, t, acc);
+    }
     return __builtin_sqrtf(acc);
 }
 
