@@ -64,8 +64,20 @@ gtmp_status to_arm(const gtmp_robot *r, int d, gtmp::ArmParams *out) {
         a.a[j] = r->dh[j][0];
         a.dz[j] = r->dh[j][2];
         a.off[j] = r->dh[j][3];
-        a.ca[j] = (float)cos((double)r->dh[j][1]);
-        a.sa[j] = (float)sin((double)r->dh[j][1]);
+        // a twist within 1e-6 rad of 0 or +-pi/2 is taken as exact: (cos, sin)
+        // = (1, 0) or (0, +-1), which the kinematics apply without products
+        const double al = (double)r->dh[j][1], qt = 1.5707963267948966;
+        if (fabs(al) <= 1e-6) {
+            a.ca[j] = 1.f; a.sa[j] = 0.f; a.twist[j] = gtmp::kTwistNone;
+        } else if (fabs(al - qt) <= 1e-6) {
+            a.ca[j] = 0.f; a.sa[j] = 1.f; a.twist[j] = gtmp::kTwistPlus;
+        } else if (fabs(al + qt) <= 1e-6) {
+            a.ca[j] = 0.f; a.sa[j] = -1.f; a.twist[j] = gtmp::kTwistMinus;
+        } else {
+            a.ca[j] = (float)cos(al);
+            a.sa[j] = (float)sin(al);
+            a.twist[j] = gtmp::kTwistGeneral;
+        }
     }
     int prev = 1;
     a.uniform_r = 1;

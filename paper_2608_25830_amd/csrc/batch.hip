@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : (
     float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
     uint32_t n_tests = 0;
     const int lane = lane_id();
-    const int wv = threadIdx.x / kWave;
+    const int wv = (int)wave_in_block();
 
     int cur = -1;               // plan of the lanes' edges (wave uniform)
     uint32_t tile = 0, cnt = 0, pos = 0, pending = 0xffffffffu;

@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(kVertexGridWaves * kWave) k_vertices_arm_grid(
         for (int j = 0; j < GTMP_MAX_JOINTS; ++j) verts[(size_t)i * A.dp + j] = q[j];
     }
     uint32_t tests = 0;
-    const bool hit = arm_hit_grid<WG>(R, q, G.mask, G.rec, inv, off, gque[threadIdx.x / kWave], tests, valid);
+    const bool hit = arm_hit_grid<WG>(R, q, G.mask, G.rec, inv, off, gque[wave_in_block()], tests, valid);
     if (valid) vflag[i] = hit ? 1 : 0;
 }
 
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             const auto &R = *Rp;
             if constexpr (GRID) {
                 uint32_t tests = 0;
-                gap = arm_hit_grid<Model::kWords>(R, q, glds.mask, glds.rec, ginv, goff, gque[threadIdx.x / kWave], tests,
+                gap = arm_hit_grid<Model::kWords>(R, q, glds.mask, glds.rec, ginv, goff, gque[wave_in_block()], tests,
                                                   has)
                           ? -1.f : 1.f;
                 n_tests += tests;
@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                 for (int i = 0; i < W; ++i) p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
             }
             uint32_t tests = 0;
-            gap = point_hit_grid<W, SP, Model::kWords>(p, pmask.m, glds.rec, ginv, goff, gque[threadIdx.x / kWave],
+            gap = point_hit_grid<W, SP, Model::kWords>(p, pmask.m, glds.rec, ginv, goff, gque[wave_in_block()],
                                                        tests, has)
                       ? -1.f : 1.f;
             n_tests += tests;
@@ -657,7 +657,7 @@ __global__ void __launch_bounds__(256, 3) k_list_states(EdgeArgs A, const ArmPar
             asm volatile("" : "+s"(Rp));
             const auto &R = *Rp;
             if constexpr (GRID) {
-                hit = arm_hit_grid<Model::kWords>(R, q, G.mask, G.rec, ginv, goff, gque[threadIdx.x / kWave], n_tests,
+                hit = arm_hit_grid<Model::kWords>(R, q, G.mask, G.rec, ginv, goff, gque[wave_in_block()], n_tests,
                                                    live);
             } else {
                 const v32f o = arm_fk<D>(R, q);

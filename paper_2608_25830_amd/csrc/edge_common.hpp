@@ -243,66 +243,76 @@ __device__ __forceinline__ void build_grid_block(const SceneParams &S, int wdim,
 // test does, R = rho_o + r_k, gap = -R^2 + sum_i (c_i - med3(c_i, lo_i, hi_i))^2
 // in that order, and the state collides iff some gap is <= 0.
 //
-// Few spheres of a wave have a non-empty mask (about one in seven on the arm
-// workloads), so the exact tests are not made where the masks are found:
-// each such sphere is appended to the wave's queue Qw in LDS (centre, radius,
-// mask, owning lane), and whenever 64 entries are waiting the wave takes them
-// one per lane, which keeps every lane busy in the tests.  A lane appends
-// nothing more once a drained test has found its state in contact, and a lane
-// that is not `live` appends nothing at all (its result is then meaningless).
-// `tests` counts the exact tests of the whole wave, one popcount per round of
-// the test loop: a wave-uniform total held in a scalar register (a per-lane
-// count would take vector registers in the hot loop).
-// Every lane of the wave must call this (it drains on ballots).
+// Few spheres of a wave have a non-empty mask, so the exact tests are not
+// made where the masks are found: each such sphere is appended to the wave's
+// queue Qw in LDS (centre, mask, owning lane and sphere index), and whenever
+// 64 entries are waiting the wave takes the 64 newest one per lane, which
+// keeps every lane busy in the tests.  A lane appends nothing more once a
+// drained test has found its state in contact, and a lane that is not `live`
+// appends nothing at all (its result is then meaningless).  `tests` counts
+// the exact tests of the whole wave, one popcount per round of the test loop:
+// a wave-uniform total held in a scalar register (a per-lane count would take
+// vector registers in the hot loop).
+// Every lane of the wave must call this (it drains on ballots), and Qw should
+// be addressed through a wave-uniform index, so that the queue's addresses
+// stay in scalar registers.
 constexpr int kQueue = 128;  // entries per wave: up to 63 waiting plus one probe of every lane
 
 template <int WORDS>
 struct GridQueue {
-    // one array per field (2,752 bytes per wave with one mask word, against
-    // 4,160 for 32-byte entries; the batched kernels hold a queue per wave)
-    float4 c[kQueue];           // probe centre, radius
-    uint32_t m[WORDS][kQueue];  // mask words
-    uint8_t own[kQueue];        // owning lane
+    // one array per field: the centre with the first mask word beside it in
+    // one 16-byte entry (one store per probe; 2,372 bytes per wave with one
+    // mask word)
+    float4 c[kQueue];                                                // centre x, y, z; mask word 0 (bits)
+    uint32_t m[WORDS > 1 ? WORDS - 1 : 1][WORDS > 1 ? kQueue : 1];  // mask words 1 ..
+    uint16_t own[kQueue];                                            // owning lane | probe index << 8
     uint8_t hit[kWave];
 };
 
 typedef uint32_t GridMaskTable[3][kGridCells];  // one mask word: axis, bin
 
 // The wave's side of the queue: probes are offered one per lane at a time
-// (every lane of the wave takes part in each offer and drain).
-template <int WORDS>
+// (every lane of the wave takes part in each offer and drain).  Entries
+// [0, tail) are waiting; a drain takes the newest 64 (the order of the tests
+// does not matter: a lane collides iff any of its tests finds contact), so
+// the queue needs no ring index.  rad(k) is the radius of probe k.
+template <int WORDS, class Rad>
 struct GridProber {
     GridQueue<WORDS> &Q;
     const float4 (*rec)[2];
     uint32_t &tests;
-    uint32_t head, tail;  // wave-uniform queue positions (mod kQueue in LDS)
+    const Rad &rad;
+    uint32_t tail;        // wave-uniform: entries waiting
     uint32_t hit;         // 1: this lane's state is in contact (known from a drain); an integer,
                           // not a bool, so that it stays a plain register across the loops
     uint64_t done;        // wave-uniform: the lanes that offer nothing more (hit, or not live)
 
-    __device__ __forceinline__ GridProber(GridQueue<WORDS> &q, const float4 (*r)[2], uint32_t &t, bool live)
-        : Q(q), rec(r), tests(t), head(0), tail(0), hit(live ? 0u : 1u), done(ballot(!live)) {
+    __device__ __forceinline__ GridProber(GridQueue<WORDS> &q, const float4 (*r)[2], uint32_t &t, const Rad &rd,
+                                          bool live)
+        : Q(q), rec(r), tests(t), rad(rd), tail(0), hit(live ? 0u : 1u), done(ballot(!live)) {
         Q.hit[lane_id()] = 0;
     }
 
-    // The n <= 64 oldest entries, one per lane.
-    __device__ __forceinline__ void drain(uint32_t n) {
+    // Entries [first, first + n), n <= 64, one per lane.
+    __device__ __forceinline__ void drain(uint32_t first, uint32_t n) {
         const int lane = lane_id();
         __builtin_amdgcn_wave_barrier();
-        const uint32_t slot = (head + (uint32_t)lane) & (kQueue - 1);
         // words 0-1 as one 32- or 64-bit mask, word 2 beside it
         typedef typename std::conditional<WORDS == 1, uint32_t, uint64_t>::type Mask;
         Mask m = 0;
         uint32_t m2 = 0;
         float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+        float pr = 0.f;
         int own = 0;
         if ((uint32_t)lane < n) {
-            e = Q.c[slot];
-            const uint32_t w0 = Q.m[0][slot];
+            e = (&Q.c[first])[lane];
+            const uint32_t w0 = __float_as_uint(e.w);
             if constexpr (WORDS == 1) m = (Mask)w0;
-            else m = (Mask)(((uint64_t)Q.m[WORDS > 1 ? 1 : 0][slot] << 32) | w0);
-            if constexpr (WORDS > 2) m2 = Q.m[WORDS > 2 ? 2 : 0][slot];
-            own = (int)Q.own[slot];
+            else m = (Mask)(((uint64_t)(&Q.m[0][first])[lane] << 32) | w0);
+            if constexpr (WORDS > 2) m2 = (&Q.m[WORDS > 2 ? 1 : 0][first])[lane];
+            const uint32_t o = (&Q.own[first])[lane];
+            own = (int)(o & 0xffu);
+            pr = rad(o >> 8);
         }
         for (;;) {
             const uint64_t act = ballot(m != 0 || m2 != 0);
@@ -318,7 +328,7 @@ struct GridProber {
                     m2 &= m2 - 1;
                 }
                 const float4 a = rec[o][0], h = rec[o][1];
-                const float Rr = a.w + e.w;
+                const float Rr = a.w + pr;
                 float g = -Rr * Rr;
                 const float c[3] = {e.x, e.y, e.z}, lo[3] = {a.x, a.y, a.z}, hi[3] = {h.x, h.y, h.z};
 #pragma unroll
@@ -334,44 +344,42 @@ struct GridProber {
             }
         }
         __builtin_amdgcn_wave_barrier();
-        head += n;
         hit |= Q.hit[lane] != 0 ? 1u : 0u;
         done = ballot(hit != 0);
     }
 
-    // This lane's probe (bin mask words mw; centre(c) writes its centre,
-    // radius(): its radius, both evaluated only for a queued probe): queued
-    // when some obstacle is listed and the lane's state is not known to
-    // collide.  The lanes to queue are found as one wave-wide mask (the
-    // compare's own lane mask less `done`), so the common case of no lane
+    // This lane's probe k (bin mask words mw; centre(c) writes its centre,
+    // evaluated only for a queued probe): queued when some obstacle is listed
+    // and the lane's state is not known to collide.  The lanes to queue are
+    // found as one wave-wide mask (the compare's own lane mask less `done`),
+    // which is also the branch condition, so the common case of no lane
     // queueing costs one vector compare.
-    template <class C, class Rad>
-    __device__ __forceinline__ void offer(const uint32_t (&mw)[WORDS], C &&centre, Rad &&radius) {
+    template <class C>
+    __device__ __forceinline__ void offer(const uint32_t (&mw)[WORDS], uint32_t k, C &&centre) {
         uint32_t any = mw[0];
 #pragma unroll
         for (int wd = 1; wd < WORDS; ++wd) any |= mw[wd];
         const uint64_t wmask = ballot(any != 0) & ~done;
         if (wmask != 0) {
-            if (any != 0 && hit == 0) {  // the lanes of wmask (`done` is the ballot of `hit`)
+            if (__builtin_amdgcn_inverse_ballot_w64(wmask)) {  // any != 0 && hit == 0 in this lane
                 float c[3];
                 centre(c);
-                const uint32_t slot = (tail + (uint32_t)rank_in(wmask)) & (kQueue - 1);
-                Q.c[slot] = make_float4(c[0], c[1], c[2], radius());
+                const int r = rank_in(wmask);
+                (&Q.c[tail])[r] = make_float4(c[0], c[1], c[2], __uint_as_float(mw[0]));
 #pragma unroll
-                for (int wd = 0; wd < WORDS; ++wd) Q.m[wd][slot] = mw[wd];
-                Q.own[slot] = (uint8_t)lane_id();
+                for (int wd = 1; wd < WORDS; ++wd) (&Q.m[wd - 1][tail])[r] = mw[wd];
+                (&Q.own[tail])[r] = (uint16_t)((uint32_t)lane_id() | k << 8);
             }
             tail += (uint32_t)__popcll(wmask);
-            if (tail - head >= (uint32_t)kWave) drain(kWave);
+            if (tail >= (uint32_t)kWave) {
+                tail -= (uint32_t)kWave;
+                drain(tail, kWave);
+            }
         }
     }
 
-    __device__ __forceinline__ void offer(const float (&c)[3], float r, const uint32_t (&mw)[WORDS]) {
-        offer(mw, [&](float (&o)[3]) { o[0] = c[0]; o[1] = c[1]; o[2] = c[2]; }, [&] { return r; });
-    }
-
     __device__ __forceinline__ bool finish() {
-        if (tail != head) drain(tail - head);
+        if (tail != 0) drain(0, tail);
         return hit != 0;
     }
 };
@@ -391,7 +399,9 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
                                              const GridMaskTable *mk, const float4 (*rec)[2],
                                              const float (&inv)[3], const float (&off)[3],
                                              GridQueue<WORDS> &Qw, uint32_t &tests, bool live) {
-    GridProber<WORDS> P(Qw, rec, tests, live);
+    // the radius of a queued sphere, read per lane when its tests are drained
+    const auto rad = [&](uint32_t k) { return R.r[k]; };
+    GridProber<WORDS, decltype(rad)> P(Qw, rec, tests, rad, live);
     arm_fk_visit<GTMP_MAX_JOINTS>(R, q, [&](int L, const float (&b)[3], const float (&p)[3]) {
         float fb[3], fd[3];
 #pragma unroll
@@ -414,13 +424,10 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
             uint32_t mw[WORDS];
 #pragma unroll
             for (int wd = 0; wd < WORDS; ++wd) mw[wd] = mk[wd][0][bin[0]] & mk[wd][1][bin[1]] & mk[wd][2][bin[2]];
-            P.offer(
-                mw,
-                [&](float (&c)[3]) {
+            P.offer(mw, k, [&](float (&c)[3]) {
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) c[i] = __builtin_fmaf(t, p[i] - b[i], b[i]);
-                },
-                [&] { return R.r[k]; });
+                for (int i = 0; i < 3; ++i) c[i] = __builtin_fmaf(t, p[i] - b[i], b[i]);
+            });
         }
     });
     return P.finish();
@@ -437,7 +444,8 @@ __device__ __forceinline__ bool point_hit_grid_by(const float (&p)[W][SP], const
                                                   const float4 (*rec)[2], const float (&inv)[3],
                                                   const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
                                                   bool live) {
-    GridProber<WORDS> P(Qw, rec, tests, live);
+    const auto rad = [](uint32_t) { return 0.f; };
+    GridProber<WORDS, decltype(rad)> P(Qw, rec, tests, rad, live);
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
         float c[3] = {0.f, 0.f, 0.f};
@@ -452,7 +460,10 @@ __device__ __forceinline__ bool point_hit_grid_by(const float (&p)[W][SP], const
         for (int wd = 0; wd < WORDS; ++wd) mw[wd] = ~0u;
 #pragma unroll
         for (int i = 0; i < W; ++i) and_mask(i, bin[i], mw);
-        P.offer(c, 0.f, mw);
+        P.offer(mw, 0u, [&](float (&o)[3]) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) o[i] = c[i];
+        });
     }
     return P.finish();
 }

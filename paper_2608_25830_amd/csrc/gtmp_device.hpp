@@ -43,6 +43,10 @@ __device__ __forceinline__ float unit_from_word(uint32_t w) { return (float)(w >
 // Robot model as passed by value in kernel arguments (uniform for the whole
 // grid, so every field is read through the scalar unit).
 // ---------------------------------------------------------------------------
+// Twist kinds of a joint: (cos, sin) of the twist exactly (1, 0), (0, 1),
+// (0, -1), or anything else.
+constexpr int kTwistGeneral = 0, kTwistNone = 1, kTwistPlus = 2, kTwistMinus = 3;
+
 struct ArmParams {
     int n_joints;
     int n_spheres;
@@ -50,6 +54,7 @@ struct ArmParams {
     float r0;
     float a[GTMP_MAX_JOINTS], dz[GTMP_MAX_JOINTS], off[GTMP_MAX_JOINTS];
     float ca[GTMP_MAX_JOINTS], sa[GTMP_MAX_JOINTS];  // cos / sin of the twist
+    int twist[GTMP_MAX_JOINTS];                       // kind of twist (kTwist*): exact quarter turns take no arithmetic
     int link[GTMP_MAX_ROBOT_SPHERES];
     float t[GTMP_MAX_ROBOT_SPHERES];
     float r[GTMP_MAX_ROBOT_SPHERES];
@@ -366,15 +371,30 @@ __device__ __forceinline__ void arm_fk_visit(const AP &A, const float (&q)[D], F
             z0 = sa * st; z1 = -(sa * ct); z2 = ca;
         } else {
             const float xn0 = ct * x0 + st * y0, xn1 = ct * x1 + st * y1, xn2 = ct * x2 + st * y2;
-            const float yp0 = ct * y0 - st * x0, yp1 = ct * y1 - st * x1, yp2 = ct * y2 - st * x2;
             p0 += A.a[j] * xn0 + A.dz[j] * z0;
             p1 += A.a[j] * xn1 + A.dz[j] * z1;
             p2 += A.a[j] * xn2 + A.dz[j] * z2;
-            const float yn0 = ca * yp0 + sa * z0, yn1 = ca * yp1 + sa * z1, yn2 = ca * yp2 + sa * z2;
-            const float zn0 = ca * z0 - sa * yp0, zn1 = ca * z1 - sa * yp1, zn2 = ca * z2 - sa * yp2;
+            if (j + 1 < A.n_joints) {  // the y and z axes feed the later joints only
+                const float yp0 = ct * y0 - st * x0, yp1 = ct * y1 - st * x1, yp2 = ct * y2 - st * x2;
+                // y' = ca yp + sa z, z' = ca z - sa yp; exact quarter turns and
+                // no twist give the same values without the products
+                const int tw = A.twist[j];
+                if (tw == kTwistNone) {
+                    y0 = yp0; y1 = yp1; y2 = yp2;
+                } else if (tw == kTwistPlus) {
+                    y0 = z0; y1 = z1; y2 = z2;
+                    z0 = -yp0; z1 = -yp1; z2 = -yp2;
+                } else if (tw == kTwistMinus) {
+                    y0 = -z0; y1 = -z1; y2 = -z2;
+                    z0 = yp0; z1 = yp1; z2 = yp2;
+                } else {
+                    const float yn0 = ca * yp0 + sa * z0, yn1 = ca * yp1 + sa * z1, yn2 = ca * yp2 + sa * z2;
+                    const float zn0 = ca * z0 - sa * yp0, zn1 = ca * z1 - sa * yp1, zn2 = ca * z2 - sa * yp2;
+                    y0 = yn0; y1 = yn1; y2 = yn2;
+                    z0 = zn0; z1 = zn1; z2 = zn2;
+                }
+            }
             x0 = xn0; x1 = xn1; x2 = xn2;
-            y0 = yn0; y1 = yn1; y2 = yn2;
-            z0 = zn0; z1 = zn1; z2 = zn2;
         }
         const float p[3] = {p0, p1, p2};
         link(j + 1, b, p);
@@ -431,5 +451,9 @@ __device__ __forceinline__ int rank_in(uint64_t mask) {
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Index of the calling wave in its block, as a scalar (so that per-wave LDS
+// arrays indexed by it keep their base addresses in scalar registers).
+__device__ __forceinline__ uint32_t wave_in_block() { return uniform(threadIdx.x / (uint32_t)kWave); }
 
 }  // namespace gtmp
