@@ -91,6 +91,7 @@ gtmp_status to_arm(const gtmp_robot *r, int d, gtmp::ArmParams *out) {
             return fail(GTMP_EINVAL, "sphere %d: bad t or radius", k);
         a.link[k] = L;
         a.t[k] = r->sph_t[k];
+        a.tm1[k] = r->sph_t[k] - 1.f;
         a.r[k] = r->sph_r[k];
         if (r->sph_r[k] != a.r0) a.uniform_r = 0;
         a.lk_end[L - 1] = k + 1;

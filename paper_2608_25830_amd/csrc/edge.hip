@@ -373,11 +373,13 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     __syncthreads();
     float ginv[3] = {0.f, 0.f, 0.f}, goff[3] = {0.f, 0.f, 0.f};
     if constexpr (GRID && Model::kArm) {
-        // wave-uniform and used once per link: held in scalar registers
+        // wave-uniform and used once per link: the scales in scalar
+        // registers, the offsets in vector registers (an FMA reads one
+        // scalar operand)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             ginv[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(glds.inv[i])));
-            goff[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(glds.off[i])));
+            goff[i] = glds.off[i];
         }
     } else if constexpr (GRID) {
         // point probes take both in one FMA per axis, which can read only one

@@ -386,8 +386,9 @@ struct GridProber {
 
 // mk: the mask tables (mk[w] = word w), rec: the obstacle records; both may
 // live in LDS or in device memory.  The bin coordinate of a sphere centre
-// c = b + t (p - b) on axis i is taken as f = (b_i inv_i + off_i) +
-// t ((p_i - b_i) inv_i), two terms formed once per link; it differs from the
+// c = b + t (p - b) on axis i is taken as f = fp_i + (t - 1) (fp_i - fb_i),
+// fb and fp the bin coordinates of the link's ends (o_{L-1} and o_L, each
+// formed once: o_L's serves as the next link's fb); it differs from the
 // coordinate of the FP32 centre, c_i inv_i + off_i, by rounding only (below
 // 1e-4 of a bin for any centre within the bins' span), and every obstacle's
 // bin interval is widened by a bin on each side, so the bins still list
@@ -402,33 +403,38 @@ __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_
     // the radius of a queued sphere, read per lane when its tests are drained
     const auto rad = [&](uint32_t k) { return R.r[k]; };
     GridProber<WORDS, decltype(rad)> P(Qw, rec, tests, rad, live);
+    float fb[3] = {off[0], off[1], off[2]};  // o_0 = 0
     arm_fk_visit<GTMP_MAX_JOINTS>(R, q, [&](int L, const float (&b)[3], const float (&p)[3]) {
-        float fb[3], fd[3];
+        float fp[3], fd[3], d[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            fb[i] = __builtin_fmaf(b[i], inv[i], off[i]);
-            fd[i] = (p[i] - b[i]) * inv[i];
+            fp[i] = __builtin_fmaf(p[i], inv[i], off[i]);
+            fd[i] = fp[i] - fb[i];
+            d[i] = p[i] - b[i];
             // formed once per link: kept in registers rather than re-formed
             // in every iteration of the sphere loop below
-            asm volatile("" : "+v"(fb[i]), "+v"(fd[i]));
+            asm volatile("" : "+v"(fp[i]), "+v"(fd[i]), "+v"(d[i]));
         }
         const int kl = L == 1 ? 0 : R.lk_end[L - 2];
         const int k0 = kl > R.k_first ? kl : R.k_first;  // spheres below k_first reach no obstacle
         const int k1 = R.lk_end[L - 1];
         // unsigned index: the parameter address is a plain increment
         for (uint32_t k = (uint32_t)k0; k < (uint32_t)k1; ++k) {
-            const float t = R.t[k];
+            const float tm = R.tm1[k];
             uint32_t bin[3];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) bin[i] = grid_bin(__builtin_fmaf(t, fd[i], fb[i]));
+            for (int i = 0; i < 3; ++i) bin[i] = grid_bin(__builtin_fmaf(tm, fd[i], fp[i]));
             uint32_t mw[WORDS];
 #pragma unroll
             for (int wd = 0; wd < WORDS; ++wd) mw[wd] = mk[wd][0][bin[0]] & mk[wd][1][bin[1]] & mk[wd][2][bin[2]];
             P.offer(mw, k, [&](float (&c)[3]) {
+                const float t = R.t[k];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) c[i] = __builtin_fmaf(t, p[i] - b[i], b[i]);
+                for (int i = 0; i < 3; ++i) c[i] = __builtin_fmaf(t, d[i], b[i]);
             });
         }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) fb[i] = fp[i];
     });
     return P.finish();
 }

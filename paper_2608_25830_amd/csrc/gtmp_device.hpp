@@ -57,6 +57,7 @@ struct ArmParams {
     int twist[GTMP_MAX_JOINTS];                       // kind of twist (kTwist*): exact quarter turns take no arithmetic
     int link[GTMP_MAX_ROBOT_SPHERES];
     float t[GTMP_MAX_ROBOT_SPHERES];
+    float tm1[GTMP_MAX_ROBOT_SPHERES];  // t - 1: the sphere's place measured from the link's end
     float r[GTMP_MAX_ROBOT_SPHERES];
     int lk_end[GTMP_MAX_JOINTS];  // spheres of link L (1-based) are lk_end[L-2] .. lk_end[L-1]-1 (from 0 for L = 1)
     float reach;    // bound on |sphere centre|: sum of the link lengths sqrt(a^2 + d^2), rounded up
@@ -293,39 +294,34 @@ __device__ __forceinline__ float point_sd(const float (&p)[W], const SceneParams
 
 // ---------------------------------------------------------------------------
 // Sine and cosine of a joint angle.  For |x| <= 32: Cody-Waite reduction
-// r = x - k pi/2, k = rint(2x/pi), with pi/2 split into three FP32 parts
-// (every product k * part is exact inside its fused multiply-add), then the
-// Taylor series of sin r to r^9 and of cos r to r^10 on |r| <= pi/4 (the
-// first omitted terms are below 2e-9 there) and the quadrant of k.  The
-// result is within a few 1e-8 of the exact values, far inside what the
-// collision decisions can resolve.  Arguments beyond 32 (or not finite)
-// take the library sincosf in that lane only, so a state's result never
-// depends on the other lanes of its wave.
+// r = x - k pi/2, k = rint(2x/pi), with pi/2 split into two FP32 parts
+// (every product k * part is exact inside its fused multiply-add; the third
+// part would move r by less than 4e-14 for |k| <= 21), then minimax
+// polynomials on |r| <= pi/4 (Remez exchange on the absolute error):
+// sin r = r + r^3 P(r^2), cos r = 1 + r^2 Q(r^2) with P and Q of degree 2
+// (approximation errors 1.8e-9 and 3.2e-8), and the quadrant of k.  In FP32
+// the results are within 1.2e-7 of the exact values over |x| <= 32, far
+// inside what the collision decisions can resolve.  Arguments beyond 32 (or
+// not finite) take the library sincosf in that lane only, so a state's
+// result never depends on the other lanes of its wave.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void joint_sincos(float x, float &s, float &c) {
     constexpr float kTwoOverPi = 0.636619772367581f;
-    constexpr float kP1 = 1.5707963705062866f;       // fl(pi/2)
-    constexpr float kP2 = -4.371138828673793e-08f;   // fl(pi/2 - kP1)
-    constexpr float kP3 = -1.7151245100058819e-15f;  // fl(pi/2 - kP1 - kP2)
+    constexpr float kP1 = 1.5707963705062866f;      // fl(pi/2)
+    constexpr float kP2 = -4.371138828673793e-08f;  // fl(pi/2 - kP1)
     const float k = __builtin_rintf(x * kTwoOverPi);
     float r = __builtin_fmaf(-k, kP1, x);
     r = __builtin_fmaf(-k, kP2, r);
-    r = __builtin_fmaf(-k, kP3, r);
     const float z = r * r;
-    // sin r = r (1 - z/3! + z^2/5! - z^3/7! + z^4/9!); the innermost
-    // coefficients enter through scalar registers, so that no vector
-    // register holds a constant for the whole kernel
-    const float s9 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(2.7557319223985893e-06f)));
-    const float c10 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(-2.7557319223985888e-07f)));
-    float ps = __builtin_fmaf(z, s9, -1.9841269841269841e-04f);
-    ps = __builtin_fmaf(z, ps, 8.3333333333333332e-03f);
-    ps = __builtin_fmaf(z, ps, -1.6666666666666666e-01f);
+    // the innermost coefficients enter through scalar registers, so that no
+    // vector register holds a constant for the whole kernel
+    const float p2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(-1.949563593e-04f)));
+    const float q2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(-1.359782298e-03f)));
+    float ps = __builtin_fmaf(z, p2, 8.331978694e-03f);
+    ps = __builtin_fmaf(z, ps, -1.666665077e-01f);
     const float sr = __builtin_fmaf(r * z, ps, r);
-    // cos r = 1 - z/2! + z^2/4! - z^3/6! + z^4/8! - z^5/10!
-    float pc = __builtin_fmaf(z, c10, 2.4801587301587302e-05f);
-    pc = __builtin_fmaf(z, pc, -1.3888888888888889e-03f);
-    pc = __builtin_fmaf(z, pc, 4.1666666666666664e-02f);
-    pc = __builtin_fmaf(z, pc, -0.5f);
+    float pc = __builtin_fmaf(z, q2, 4.165629297e-02f);
+    pc = __builtin_fmaf(z, pc, -4.999989569e-01f);
     const float cr = __builtin_fmaf(z, pc, 1.0f);
     // quadrant n = k mod 4: sin x = (s, c, -s, -c)[n], cos x = (c, -s, -c, s)[n]
     const int n = (int)k;
@@ -374,7 +370,7 @@ __device__ __forceinline__ void arm_fk_visit(const AP &A, const float (&q)[D], F
             p0 += A.a[j] * xn0 + A.dz[j] * z0;
             p1 += A.a[j] * xn1 + A.dz[j] * z1;
             p2 += A.a[j] * xn2 + A.dz[j] * z2;
-            if (j + 1 < A.n_joints) {  // the y and z axes feed the later joints only
+            {
                 const float yp0 = ct * y0 - st * x0, yp1 = ct * y1 - st * x1, yp2 = ct * y2 - st * x2;
                 // y' = ca yp + sa z, z' = ca z - sa yp; exact quarter turns and
                 // no twist give the same values without the products
