@@ -347,7 +347,11 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     constexpr int W = ARM ? 3 : D;
     constexpr int SP = ARM ? 1 : KP;  // interior states per evaluation
     static_assert(!ARM || KP % NCH == 0, "chunking must divide the sphere slots");
+    // arms outside lazy lists finish their last edges with the states spread
+    // over the lanes (below)
+    constexpr bool TAIL = ARM && !LIST;
     __shared__ float tord[GTMP_MAX_H];
+    __shared__ typename std::conditional<TAIL, uint8_t[256], char>::type tail_hit;  // per wave: 64 flags
     constexpr int WG = Model::kWords > 0 ? Model::kWords : 1;
     constexpr int WS = point_mask_stride<WG>();
     // arms: the grid's own mask layout; points: the maps and obstacles here,
@@ -392,6 +396,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     }
 
     const int lane = lane_id();
+    const uint32_t wv = wave_in_block();  // a scalar: the wave's LDS areas keep scalar base addresses
     uint32_t n_tiles = A.n_tiles;
     uint32_t chunk = kWave;
     if constexpr (LIST) {
@@ -424,6 +429,33 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
 #pragma unroll
     for (int i = 0; i < D; ++i) { u[i] = 0.f; dv[i] = 0.f; }
     const float r0 = ARM ? Rg->r0 : 0.f;
+    // gap sign of one arm state q (<= 0: in contact); `live` false: the lane
+    // takes part in the wave's queue but its result is meaningless
+    auto arm_gap = [&](const float (&q)[D], bool live) -> float {
+        if constexpr (ARM) {
+            // The robot table is re-read through a pointer the compiler cannot
+            // see through, so each value is a short-lived scalar load at its
+            // use instead of a register held (and spilled) across the loop.
+            carm Rp = (carm)Rg;
+            asm volatile("" : "+s"(Rp));
+            const auto &R = *Rp;
+            if constexpr (GRID) {
+                uint32_t tests = 0;
+                const bool hit =
+                    arm_hit_grid<WG>(R, q, glds.mask, glds.rec, ginv, goff, gque[wv], tests, live);
+                n_tests += tests;
+                return hit ? -1.f : 1.f;
+            } else {
+                (void)live;
+                const v32f o = arm_fk<D>(R, q);
+                return arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
+            }
+        } else {
+            (void)q;
+            (void)live;
+            return 1.f;
+        }
+    };
 
     while (true) {
         // ---- refill idle lanes from the current tile, taking new tiles as needed
@@ -496,6 +528,9 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
         }
         const uint64_t busy = ballot(has);
         if (busy == 0) break;  // exhausted and every lane idle
+        if constexpr (TAIL) {
+            if (exhausted) break;  // no tile left: the edges in progress are finished below
+        }
         n_states += (unsigned long long)__popcll(busy) * SP;
         asm volatile("" : "+s"(n_states));  // wave-uniform: a scalar register pair
 
@@ -506,22 +541,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             const float t = tord[has ? j : 0];
 #pragma unroll
             for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, dv[i], u[i]);
-            // The robot table is re-read through a pointer the compiler cannot
-            // see through, so each value is a short-lived scalar load at its
-            // use instead of a register held (and spilled) across the loop.
-            carm Rp = (carm)Rg;
-            asm volatile("" : "+s"(Rp));
-            const auto &R = *Rp;
-            if constexpr (GRID) {
-                uint32_t tests = 0;
-                gap = arm_hit_grid<Model::kWords>(R, q, glds.mask, glds.rec, ginv, goff, gque[wave_in_block()], tests,
-                                                  has)
-                          ? -1.f : 1.f;
-                n_tests += tests;
-            } else {
-                const v32f o = arm_fk<D>(R, q);
-                gap = arm_state_gap<KP, NCH, UNIFORM_R>(R, o, r0, S);
-            }
+            gap = arm_gap(q, has);
         } else if constexpr (GRID) {
             float p[W][SP];
 #pragma unroll
@@ -533,7 +553,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                 for (int i = 0; i < W; ++i) p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
             }
             uint32_t tests = 0;
-            gap = point_hit_grid<W, SP, Model::kWords>(p, pmask.m, glds.rec, ginv, goff, gque[wave_in_block()],
+            gap = point_hit_grid<W, SP, Model::kWords>(p, pmask.m, glds.rec, ginv, goff, gque[wv],
                                                        tests, has)
                       ? -1.f : 1.f;
             n_tests += tests;
@@ -571,6 +591,65 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                     has = false;
                 }
             }
+        }
+    }
+    if constexpr (TAIL) {
+        // No tile is left.  Instead of each lane walking the rest of its own
+        // edge while the lanes whose edges are done idle, the remaining
+        // (edge, state) pairs of the wave are spread over its lanes, 64 per
+        // round: an edge's pairs in its own state order, the edges in lane
+        // order.  An edge found in contact takes no further round; one whose
+        // states are all free is written as the main loop writes it.
+        uint8_t *th = tail_hit + wv * kWave;
+        uint32_t rem = has ? (uint32_t)(A.n_int - j) : 0u;
+        for (;;) {
+            uint32_t incl = rem;  // inclusive prefix sum of rem over the lanes
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t y = lane_read(lane - o, incl);
+                if (lane >= o) incl += y;
+            }
+            const uint32_t total = uniform(__builtin_amdgcn_readlane(incl, kWave - 1));
+            if (total == 0) break;
+            const uint32_t pre = incl - rem;
+            // pair `lane`: owner = the last lane whose prefix is <= lane (lanes
+            // after the last owner have prefix `total`, beyond every live pair)
+            const bool live = (uint32_t)lane < total;
+            int own = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                if (lane_read(own + step, pre) <= (uint32_t)lane) own += step;
+            const uint32_t st = (uint32_t)lane_read(own, (uint32_t)j) + ((uint32_t)lane - lane_read(own, pre));
+            const float t = tord[live ? st : 0];
+            float q[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                q[i] = __builtin_fmaf(t, __uint_as_float(lane_read(own, __float_as_uint(dv[i]))),
+                                      __uint_as_float(lane_read(own, __float_as_uint(u[i]))));
+            th[lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            const float gap = arm_gap(q, live);
+            n_states += (unsigned long long)__popcll(ballot(live));
+            asm volatile("" : "+s"(n_states));
+            if (live && gap <= 0.f) th[own] = 1;
+            __builtin_amdgcn_wave_barrier();
+            if (rem > 0) {
+                const uint32_t took = pre >= (uint32_t)kWave ? 0u : min(rem, (uint32_t)kWave - pre);
+                if (th[lane] != 0) {
+                    rem = 0;  // failed: provisional cost and flag stand
+                } else {
+                    rem -= took;
+                    j += (int)took;
+                    if (rem == 0) {  // free edge: its cost is the length, as in the main loop
+                        float acc = 0.f;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) acc = __builtin_fmaf(dv[i], dv[i], acc);  // zero past d
+                        *cost_slot(A, e) = __builtin_sqrtf(acc);
+                        if (A.flags) A.flags[e] = 0;
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
     if (A.stats && lane == 0) store_wave_stats(A, n_states, n_edges, GRID ? n_tests : 0u);

@@ -448,6 +448,11 @@ __device__ __forceinline__ int rank_in(uint64_t mask) {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// x of lane `src` (taken mod 64), for every lane.
+__device__ __forceinline__ uint32_t lane_read(int src, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)x);
+}
+
 // Index of the calling wave in its block, as a scalar (so that per-wave LDS
 // arrays indexed by it keep their base addresses in scalar registers).
 __device__ __forceinline__ uint32_t wave_in_block() { return uniform(threadIdx.x / (uint32_t)kWave); }
