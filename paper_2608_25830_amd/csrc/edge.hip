@@ -602,6 +602,12 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
         // states are all free is written as the main loop writes it.
         uint8_t *th = tail_hit + wv * kWave;
         uint32_t rem = has ? (uint32_t)(A.n_int - j) : 0u;
+        // A pair's edge comes from its owner lane: its start and direction
+        // read across lanes, or (the bin-filtered kernel, whose registers are
+        // tighter) its endpoints re-read from the vertex array by id.
+        uint32_t ue = 0, ve = 0;
+        if constexpr (GRID)
+            if (rem > 0) edge_vertex_ids(A, e, ue, ve);
         for (;;) {
             uint32_t incl = rem;  // inclusive prefix sum of rem over the lanes
 #pragma unroll
@@ -622,10 +628,18 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             const uint32_t st = (uint32_t)lane_read(own, (uint32_t)j) + ((uint32_t)lane - lane_read(own, pre));
             const float t = tord[live ? st : 0];
             float q[D];
+            if constexpr (GRID) {
+                float qu[D], qv[D];
+                load_vertex<D>(A, lane_read(own, ue), qu);
+                load_vertex<D>(A, lane_read(own, ve), qv);
 #pragma unroll
-            for (int i = 0; i < D; ++i)
-                q[i] = __builtin_fmaf(t, __uint_as_float(lane_read(own, __float_as_uint(dv[i]))),
-                                      __uint_as_float(lane_read(own, __float_as_uint(u[i]))));
+                for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, qv[i] - qu[i], qu[i]);  // as the refill forms it
+            } else {
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+                    q[i] = __builtin_fmaf(t, __uint_as_float(lane_read(own, __float_as_uint(dv[i]))),
+                                          __uint_as_float(lane_read(own, __float_as_uint(u[i]))));
+            }
             th[lane] = 0;
             __builtin_amdgcn_wave_barrier();
             const float gap = arm_gap(q, live);
@@ -641,9 +655,19 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                     rem -= took;
                     j += (int)took;
                     if (rem == 0) {  // free edge: its cost is the length, as in the main loop
-                        float acc = 0.f;
+                        float dd[D], acc = 0.f;
+                        if constexpr (GRID) {
+                            float a[D], b[D];
+                            load_vertex<D>(A, ue, a);
+                            load_vertex<D>(A, ve, b);
 #pragma unroll
-                        for (int i = 0; i < D; ++i) acc = __builtin_fmaf(dv[i], dv[i], acc);  // zero past d
+                            for (int i = 0; i < D; ++i) dd[i] = b[i] - a[i];
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < D; ++i) dd[i] = dv[i];
+                        }
+#pragma unroll
+                        for (int i = 0; i < D; ++i) acc = __builtin_fmaf(dd[i], dd[i], acc);  // zero past d
                         *cost_slot(A, e) = __builtin_sqrtf(acc);
                         if (A.flags) A.flags[e] = 0;
                     }
