@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : (
             const auto &R = *Rp;
             if constexpr (GRID) {
                 uint32_t tests = 0;
-                gap = arm_hit_grid<Model::kWords>(R, q, gmask[wv], grec, ginv, goff, gque[wv], tests, has) ? -1.f : 1.f;
+                gap = arm_hit_grid<Model::kWords, UNIFORM_R>(R, q, gmask[wv], grec, ginv, goff, gque[wv], tests, has) ? -1.f : 1.f;
                 n_tests += tests;
             } else {
                 const float r0 = R.r0;
@@ -1047,8 +1047,12 @@ hipError_t launch_batch(const gtmp_plan_desc *plans, const ArmParams *arms_host,
                 GTMP_BK(8) GTMP_BK(16) GTMP_BK(24) GTMP_BK(32) GTMP_BK(40) GTMP_BK(48) GTMP_BK(56) GTMP_BK(64)
 #undef GTMP_BK
 #undef GTMP_BK1
-                if (grid_words == 1) k = (const void *)k_batch_interior<ArmGridModel<1>, true, 1>;
-                if (grid_words == 2) k = (const void *)k_batch_interior<ArmGridModel<2>, true, 1>;
+                if (grid_words == 1)
+                    k = uniform_r ? (const void *)k_batch_interior<ArmGridModel<1>, true, 1>
+                                  : (const void *)k_batch_interior<ArmGridModel<1>, false, 1>;
+                if (grid_words == 2)
+                    k = uniform_r ? (const void *)k_batch_interior<ArmGridModel<2>, true, 1>
+                                  : (const void *)k_batch_interior<ArmGridModel<2>, false, 1>;
                 if (!k) return hipErrorInvalidValue;
                 const int grid = persistent_blocks(k, o.blocks_per_cu);
                 uint32_t *c2 = ctr + 2 * kBatchGroupCounters;

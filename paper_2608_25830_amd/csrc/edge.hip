@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             if constexpr (GRID) {
                 uint32_t tests = 0;
                 const bool hit =
-                    arm_hit_grid<WG>(R, q, glds.mask, glds.rec, ginv, goff, gque[wv], tests, live);
+                    arm_hit_grid<WG, UNIFORM_R && !LIST>(R, q, glds.mask, glds.rec, ginv, goff, gque[wv], tests, live);
                 n_tests += tests;
                 return hit ? -1.f : 1.f;
             } else {
@@ -1017,10 +1017,16 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
     } else if (A.n_int == 0) {
         hipLaunchKernelGGL(k_finalize_no_interior<GTMP_MAX_JOINTS>, dim3(A.n_tiles), dim3(kTile), 0, s, A);
     } else if (gw) {
-        if (gw == 1)
+        // robots whose spheres share one radius read the exact test's starting
+        // gap from the obstacle records
+        if (gw == 1 && R.uniform_r)
             hipLaunchKernelGGL((k_interior<ArmGridModel<1>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
-        else
+        else if (gw == 1)
+            hipLaunchKernelGGL((k_interior<ArmGridModel<1>, false, 1>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
+        else if (R.uniform_r)
             hipLaunchKernelGGL((k_interior<ArmGridModel<2>, true, 1>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
+        else
+            hipLaunchKernelGGL((k_interior<ArmGridModel<2>, false, 1>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     } else if (R.uniform_r) {
         hipLaunchKernelGGL((k_interior<ArmModel<KP>, true, NCH>), dim3(grid_persist), dim3(256), 0, s, A, Rg, S);
     } else {
@@ -1211,8 +1217,8 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
         A.grid = reinterpret_cast<const ObsGrid *>(ws + plan.off_grid);
         const void *kern = nullptr;
         switch (gw ? -gw : kp * 8 + nch) {
-            case -1: kern = (const void *)k_interior<ArmGridModel<1>, true, 1>; break;
-            case -2: kern = (const void *)k_interior<ArmGridModel<2>, true, 1>; break;
+            case -1: kern = R.uniform_r ? (const void *)k_interior<ArmGridModel<1>, true, 1> : (const void *)k_interior<ArmGridModel<1>, false, 1>; break;
+            case -2: kern = R.uniform_r ? (const void *)k_interior<ArmGridModel<2>, true, 1> : (const void *)k_interior<ArmGridModel<2>, false, 1>; break;
 #define GTMP_KK(K, C) case K * 8 + C: kern = R.uniform_r ? (const void *)k_interior<ArmModel<K>, true, C> : (const void *)k_interior<ArmModel<K>, false, C>; break;
 #define GTMP_KK3(K) GTMP_KK(K, 1) GTMP_KK(K, 2) GTMP_KK(K, 4)
             GTMP_KK3(8) GTMP_KK3(16) GTMP_KK3(24) GTMP_KK3(32) GTMP_KK3(40) GTMP_KK3(48) GTMP_KK3(56) GTMP_KK3(64)

@@ -31,7 +31,7 @@ constexpr int kGridMaxObs = 96;  // three mask words
 
 struct ObsGrid {
     float inv[4], off[4];                  // axes x, y, z (the fourth entry unused)
-    float4 rec[kGridMaxObs][2];            // (lo.xyz, rho), (hi.xyz, 0); 2D scenes: z = 0
+    float4 rec[kGridMaxObs][2];            // (lo.xyz, rho), (hi.xyz, -(rho + r_max)^2); 2D scenes: z = 0
     uint32_t mask[3][3][kGridCells];       // mask word, axis, bin (axes past the workspace list every obstacle)
 };
 
@@ -167,7 +167,10 @@ __device__ __forceinline__ void build_grid_block(const SceneParams &S, int wdim,
             rho = 0.f;
         }
         G->rec[tid][0] = make_float4(lo[0], lo[1], lo[2], rho);
-        G->rec[tid][1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+        // the exact test's starting gap -R^2 for probes of radius r_max,
+        // formed as the test forms it (R = rho + r, gap = -R R)
+        const float Rr = rho + r_max;
+        G->rec[tid][1] = make_float4(hi[0], hi[1], hi[2], -Rr * Rr);
         const float ext = (__builtin_fabsf(rho) + r_max) * (1.f + 0x1p-12f);
         bool wild = !__builtin_isfinite(ext);
 #pragma unroll
@@ -275,8 +278,10 @@ typedef uint32_t GridMaskTable[3][kGridCells];  // one mask word: axis, bin
 // (every lane of the wave takes part in each offer and drain).  Entries
 // [0, tail) are waiting; a drain takes the newest 64 (the order of the tests
 // does not matter: a lane collides iff any of its tests finds contact), so
-// the queue needs no ring index.  rad(k) is the radius of probe k.
-template <int WORDS, class Rad>
+// the queue needs no ring index.  rad(k) is the radius of probe k; UNI: every
+// probe has the radius the bins were built for (r_max), whose starting gap
+// the obstacle record holds, and entries carry no probe index.
+template <int WORDS, bool UNI, class Rad>
 struct GridProber {
     GridQueue<WORDS> &Q;
     const float4 (*rec)[2];
@@ -312,7 +317,7 @@ struct GridProber {
             if constexpr (WORDS > 2) m2 = (&Q.m[WORDS > 2 ? 1 : 0][first])[lane];
             const uint32_t o = (&Q.own[first])[lane];
             own = (int)(o & 0xffu);
-            pr = rad(o >> 8);
+            if constexpr (!UNI) pr = rad(o >> 8);
         }
         for (;;) {
             const uint64_t act = ballot(m != 0 || m2 != 0);
@@ -328,8 +333,14 @@ struct GridProber {
                     m2 &= m2 - 1;
                 }
                 const float4 a = rec[o][0], h = rec[o][1];
-                const float Rr = a.w + pr;
-                float g = -Rr * Rr;
+                float g;
+                if constexpr (UNI) {
+                    (void)pr;
+                    g = h.w;
+                } else {
+                    const float Rr = a.w + pr;
+                    g = -Rr * Rr;
+                }
                 const float c[3] = {e.x, e.y, e.z}, lo[3] = {a.x, a.y, a.z}, hi[3] = {h.x, h.y, h.z};
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
@@ -368,7 +379,7 @@ struct GridProber {
                 (&Q.c[tail])[r] = make_float4(c[0], c[1], c[2], __uint_as_float(mw[0]));
 #pragma unroll
                 for (int wd = 1; wd < WORDS; ++wd) (&Q.m[wd - 1][tail])[r] = mw[wd];
-                (&Q.own[tail])[r] = (uint16_t)((uint32_t)lane_id() | k << 8);
+                (&Q.own[tail])[r] = (uint16_t)(UNI ? (uint32_t)lane_id() : (uint32_t)lane_id() | k << 8);
             }
             tail += (uint32_t)__popcll(wmask);
             if (tail >= (uint32_t)kWave) {
@@ -395,14 +406,14 @@ struct GridProber {
 // every obstacle the exact test can find in contact.  The centre itself,
 // fma(t, p - b, b) as the full test forms it, is formed only for the
 // spheres queued for an exact test.
-template <int WORDS, class AP>
+template <int WORDS, bool UNI = false, class AP>
 __device__ __forceinline__ bool arm_hit_grid(const AP &R, const float (&q)[GTMP_MAX_JOINTS],
                                              const GridMaskTable *mk, const float4 (*rec)[2],
                                              const float (&inv)[3], const float (&off)[3],
                                              GridQueue<WORDS> &Qw, uint32_t &tests, bool live) {
     // the radius of a queued sphere, read per lane when its tests are drained
     const auto rad = [&](uint32_t k) { return R.r[k]; };
-    GridProber<WORDS, decltype(rad)> P(Qw, rec, tests, rad, live);
+    GridProber<WORDS, UNI, decltype(rad)> P(Qw, rec, tests, rad, live);
     float fb[3] = {off[0], off[1], off[2]};  // o_0 = 0
     arm_fk_visit<GTMP_MAX_JOINTS>(R, q, [&](int L, const float (&b)[3], const float (&p)[3]) {
         float fp[3], fd[3], d[3];
@@ -451,7 +462,7 @@ __device__ __forceinline__ bool point_hit_grid_by(const float (&p)[W][SP], const
                                                   const float (&off)[3], GridQueue<WORDS> &Qw, uint32_t &tests,
                                                   bool live) {
     const auto rad = [](uint32_t) { return 0.f; };
-    GridProber<WORDS, decltype(rad)> P(Qw, rec, tests, rad, live);
+    GridProber<WORDS, true, decltype(rad)> P(Qw, rec, tests, rad, live);
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
         float c[3] = {0.f, 0.f, 0.f};
