@@ -347,11 +347,11 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     constexpr int W = ARM ? 3 : D;
     constexpr int SP = ARM ? 1 : KP;  // interior states per evaluation
     static_assert(!ARM || KP % NCH == 0, "chunking must divide the sphere slots");
-    // arms outside lazy lists finish their last edges with the states spread
-    // over the lanes (below)
-    constexpr bool TAIL = ARM && !LIST;
+    // outside lazy lists the last edges are finished with their states
+    // spread over the lanes (below)
+    constexpr bool TAIL = !LIST;
     __shared__ float tord[GTMP_MAX_H];
-    __shared__ typename std::conditional<TAIL, uint8_t[256], char>::type tail_hit;  // per wave: 64 flags
+    __shared__ typename std::conditional<TAIL, uint32_t[256], char>::type tail_hit;  // per wave: 64 words
     constexpr int WG = Model::kWords > 0 ? Model::kWords : 1;
     constexpr int WS = point_mask_stride<WG>();
     // arms: the grid's own mask layout; points: the maps and obstacles here,
@@ -456,6 +456,46 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             return 1.f;
         }
     };
+    // gap sign of the SP point states j0, j0 + 1, ... (clipped to the last
+    // state) of the edge from uu along dd: <= 0 when one of them is in contact
+    auto point_gap = [&](const float (&uu)[D], const float (&dd)[D], int j0, bool live) -> float {
+        if constexpr (!ARM && GRID) {
+            float p[W][SP];
+#pragma unroll
+            for (int s = 0; s < SP; ++s) {
+                int jj = j0 + s;
+                jj = jj < A.n_int ? jj : A.n_int - 1;
+                const float t = tord[live ? jj : 0];
+#pragma unroll
+                for (int i = 0; i < W; ++i) p[i][s] = __builtin_fmaf(t, dd[i], uu[i]);
+            }
+            uint32_t tests = 0;
+            const bool hit =
+                point_hit_grid<W, SP, Model::kWords>(p, pmask.m, glds.rec, ginv, goff, gque[wv], tests, live);
+            n_tests += tests;
+            return hit ? -1.f : 1.f;
+        } else if constexpr (!ARM) {
+            Probes<W, KP> P;
+#pragma unroll
+            for (int s = 0; s < SP; ++s) {
+                int jj = j0 + s;
+                jj = jj < A.n_int ? jj : A.n_int - 1;
+                const float t = tord[live ? jj : 0];
+#pragma unroll
+                for (int i = 0; i < W; ++i) P.p[i][s] = __builtin_fmaf(t, dd[i], uu[i]);
+            }
+            float pr[KP];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) pr[k] = 0.f;
+            return probes_min_gap<W, KP, true>(P, pr, 0.f, S);
+        } else {
+            (void)uu;
+            (void)dd;
+            (void)j0;
+            (void)live;
+            return 1.f;
+        }
+    };
 
     while (true) {
         // ---- refill idle lanes from the current tile, taking new tiles as needed
@@ -542,35 +582,8 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
 #pragma unroll
             for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, dv[i], u[i]);
             gap = arm_gap(q, has);
-        } else if constexpr (GRID) {
-            float p[W][SP];
-#pragma unroll
-            for (int s = 0; s < SP; ++s) {
-                int jj = j + s;
-                jj = jj < A.n_int ? jj : A.n_int - 1;
-                const float t = tord[has ? jj : 0];
-#pragma unroll
-                for (int i = 0; i < W; ++i) p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
-            }
-            uint32_t tests = 0;
-            gap = point_hit_grid<W, SP, Model::kWords>(p, pmask.m, glds.rec, ginv, goff, gque[wv],
-                                                       tests, has)
-                      ? -1.f : 1.f;
-            n_tests += tests;
         } else {
-            Probes<W, KP> P;
-#pragma unroll
-            for (int s = 0; s < SP; ++s) {
-                int jj = j + s;
-                jj = jj < A.n_int ? jj : A.n_int - 1;
-                const float t = tord[has ? jj : 0];
-#pragma unroll
-                for (int i = 0; i < W; ++i) P.p[i][s] = __builtin_fmaf(t, dv[i], u[i]);
-            }
-            float pr[KP];
-#pragma unroll
-            for (int k = 0; k < KP; ++k) pr[k] = 0.f;
-            gap = probes_min_gap<W, KP, true>(P, pr, 0.f, S);
+            gap = point_gap(u, dv, j, has);
         }
         if (has) {
             if (gap <= 0.f) {
@@ -596,20 +609,25 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     if constexpr (TAIL) {
         // No tile is left.  Instead of each lane walking the rest of its own
         // edge while the lanes whose edges are done idle, the remaining
-        // (edge, state) pairs of the wave are spread over its lanes, 64 per
-        // round: an edge's pairs in its own state order, the edges in lane
-        // order.  An edge found in contact takes no further round; one whose
-        // states are all free is written as the main loop writes it.
-        uint8_t *th = tail_hit + wv * kWave;
-        uint32_t rem = has ? (uint32_t)(A.n_int - j) : 0u;
+        // evaluations of the wave's edges (SP consecutive states each) are
+        // spread over its lanes, 64 per round: an edge's in its own state
+        // order, the edges in lane order.  An edge found in contact takes no
+        // further round; one whose states are all free is written as the main
+        // loop writes it.  The states counted are those the main loop's early
+        // exit would have evaluated (up to the first evaluation in contact),
+        // so the count does not depend on how the evaluations were spread.
+        uint32_t *th = tail_hit + wv * kWave;  // per owner: first evaluation in contact this round
+        uint32_t rem = has ? (uint32_t)(A.n_int - j) : 0u;  // states left
+        uint32_t counted = 0;                                // states counted for this lane's edge
         // A pair's edge comes from its owner lane: its start and direction
-        // read across lanes, or (the bin-filtered kernel, whose registers are
-        // tighter) its endpoints re-read from the vertex array by id.
+        // read across lanes, or (the bin-filtered arm kernel, whose registers
+        // are tighter) its endpoints re-read from the vertex array by id.
         uint32_t ue = 0, ve = 0;
-        if constexpr (GRID)
+        if constexpr (ARM && GRID)
             if (rem > 0) edge_vertex_ids(A, e, ue, ve);
         for (;;) {
-            uint32_t incl = rem;  // inclusive prefix sum of rem over the lanes
+            const uint32_t nev = (rem + (uint32_t)SP - 1) / (uint32_t)SP;  // evaluations left
+            uint32_t incl = nev;  // inclusive prefix sum over the lanes
 #pragma unroll
             for (int o = 1; o < kWave; o <<= 1) {
                 const uint32_t y = lane_read(lane - o, incl);
@@ -617,46 +635,61 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             }
             const uint32_t total = uniform(__builtin_amdgcn_readlane(incl, kWave - 1));
             if (total == 0) break;
-            const uint32_t pre = incl - rem;
-            // pair `lane`: owner = the last lane whose prefix is <= lane (lanes
-            // after the last owner have prefix `total`, beyond every live pair)
+            const uint32_t pre = incl - nev;
+            // evaluation `lane`: owner = the last lane whose prefix is <= lane
+            // (lanes after the last owner have prefix `total`, beyond every
+            // live evaluation)
             const bool live = (uint32_t)lane < total;
             int own = 0;
 #pragma unroll
             for (int step = kWave / 2; step > 0; step >>= 1)
                 if (lane_read(own + step, pre) <= (uint32_t)lane) own += step;
-            const uint32_t st = (uint32_t)lane_read(own, (uint32_t)j) + ((uint32_t)lane - lane_read(own, pre));
-            const float t = tord[live ? st : 0];
-            float q[D];
-            if constexpr (GRID) {
-                float qu[D], qv[D];
-                load_vertex<D>(A, lane_read(own, ue), qu);
-                load_vertex<D>(A, lane_read(own, ve), qv);
-#pragma unroll
-                for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, qv[i] - qu[i], qu[i]);  // as the refill forms it
-            } else {
-#pragma unroll
-                for (int i = 0; i < D; ++i)
-                    q[i] = __builtin_fmaf(t, __uint_as_float(lane_read(own, __float_as_uint(dv[i]))),
-                                          __uint_as_float(lane_read(own, __float_as_uint(u[i]))));
-            }
-            th[lane] = 0;
+            const uint32_t kk = (uint32_t)lane - lane_read(own, pre);  // the owner's evaluation kk of this round
+            const int j0 = (int)(lane_read(own, (uint32_t)j) + kk * (uint32_t)SP);
+            th[lane] = 0xffffffffu;
             __builtin_amdgcn_wave_barrier();
-            const float gap = arm_gap(q, live);
-            n_states += (unsigned long long)__popcll(ballot(live));
-            asm volatile("" : "+s"(n_states));
-            if (live && gap <= 0.f) th[own] = 1;
+            float gap;
+            if constexpr (ARM) {
+                const float t = tord[live ? j0 : 0];
+                float q[D];
+                if constexpr (GRID) {
+                    float qu[D], qv[D];
+                    load_vertex<D>(A, lane_read(own, ue), qu);
+                    load_vertex<D>(A, lane_read(own, ve), qv);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) q[i] = __builtin_fmaf(t, qv[i] - qu[i], qu[i]);  // as the refill forms it
+                } else {
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        q[i] = __builtin_fmaf(t, __uint_as_float(lane_read(own, __float_as_uint(dv[i]))),
+                                              __uint_as_float(lane_read(own, __float_as_uint(u[i]))));
+                }
+                gap = arm_gap(q, live);
+            } else {
+                float tu[D], td[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    tu[i] = __uint_as_float(lane_read(own, __float_as_uint(u[i])));
+                    td[i] = __uint_as_float(lane_read(own, __float_as_uint(dv[i])));
+                }
+                gap = point_gap(tu, td, j0, live);
+            }
+            if (live && gap <= 0.f) atomicMin(&th[own], kk);
             __builtin_amdgcn_wave_barrier();
             if (rem > 0) {
-                const uint32_t took = pre >= (uint32_t)kWave ? 0u : min(rem, (uint32_t)kWave - pre);
-                if (th[lane] != 0) {
+                const uint32_t took = pre >= (uint32_t)kWave ? 0u : min(nev, (uint32_t)kWave - pre);
+                const uint32_t first = th[lane];
+                if (first != 0xffffffffu) {
+                    counted += (first + 1) * (uint32_t)SP;
                     rem = 0;  // failed: provisional cost and flag stand
                 } else {
-                    rem -= took;
-                    j += (int)took;
+                    counted += took * (uint32_t)SP;
+                    const uint32_t st = min(rem, took * (uint32_t)SP);
+                    rem -= st;
+                    j += (int)st;
                     if (rem == 0) {  // free edge: its cost is the length, as in the main loop
                         float dd[D], acc = 0.f;
-                        if constexpr (GRID) {
+                        if constexpr (ARM && GRID) {
                             float a[D], b[D];
                             load_vertex<D>(A, ue, a);
                             load_vertex<D>(A, ve, b);
@@ -675,6 +708,9 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             }
             __builtin_amdgcn_wave_barrier();
         }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) counted += lane_read(lane ^ o, counted);
+        n_states += uniform(counted);
     }
     if (A.stats && lane == 0) store_wave_stats(A, n_states, n_edges, GRID ? n_tests : 0u);
 }
