@@ -288,10 +288,65 @@ def test_single_sample_layers(gt, orc):
     assert list(pl.idx.cpu().numpy()) == [0] * 5 + [0]
 
 
+def _bisection_order(H):
+    """Interior grid points 1..H-2 of an edge breadth-first by bisection of
+    [0, H-1] (the order the interior kernel checks them in)."""
+    out, queue = [], [(0, H - 1)]
+    while queue:
+        a, b = queue.pop(0)
+        if b - a < 2:
+            continue
+        mid = (a + b) // 2
+        out.append(mid)
+        queue += [(a, mid), (mid, b)]
+    return out
+
+
 def test_stats_counters(gt, orc):
+    """The kernel's counters against the oracle: edges taken = edges with both
+    endpoints free; states = those a walk in bisection order with early exit
+    evaluates (up to and including the first state in contact), whatever the
+    kernel's spreading of its last edges over the lanes.  States and endpoints
+    within the 1e-5 band may fall either way: the counts are bracketed."""
     w = wl.make_workload("arm7", 0, N=128, M=3)
     pl = gpu_plan(gt, w)
     s = pl.stats.cpu().numpy()
     E = pl.E
     assert 0 < s[1] <= E and s[0] >= s[1]
     assert s[0] <= s[1] * (w["H"] - 2)
+    M, N, H, d = w["M"], w["N"], w["H"], w["d"]
+    Q = pl.Q.cpu().numpy().astype(np.float32)
+    q0 = np.asarray(w["q0"], np.float32)[None]
+    goals = np.asarray(w["goals"], np.float32).reshape(-1, d)
+    U = [np.repeat(q0, N, 0)]  # C_s | C_h | C_l edge order
+    V = [Q[0]]
+    for m in range(M - 1):
+        U.append(np.repeat(Q[m], N, 0))
+        V.append(np.tile(Q[m + 1], (N, 1)))
+    U.append(np.repeat(Q[M - 1], len(goals), 0))
+    V.append(np.tile(goals, (N, 1)))
+    U, V = np.concatenate(U), np.concatenate(V)
+    assert len(U) == E
+    model = orc.Model(w)
+    sdu, sdv = orc.state_sd(model, U), orc.state_sd(model, V)
+    sure = (sdu > P.BAND) & (sdv > P.BAND)
+    maybe = (sdu >= -P.BAND) & (sdv >= -P.BAND)
+    order = _bisection_order(H)
+    t = (np.asarray(order, np.float32) / np.float32(H - 1))[None, :, None]
+    ce = np.flatnonzero(maybe)
+    X = (U[ce, None, :] + t * (V[ce, None, :] - U[ce, None, :])).astype(np.float32)
+    sd = orc.state_sd(model, X.reshape(-1, d)).reshape(len(ce), len(order))
+    n = len(order)
+
+    def first(mask):  # states walked: up to the first flagged one, else all
+        hit = mask.any(1)
+        return np.where(hit, mask.argmax(1) + 1, n)
+
+    lo, hi = first(sd <= P.BAND), first(sd < -P.BAND)
+    only_maybe = ~sure[ce]  # endpoints in the band: taken or not
+    states_lo = int(lo[~only_maybe].sum())
+    states_hi = int(hi.sum())
+    _say("stats", "edges", int(s[1]), "in", int(sure.sum()), "..", int(maybe.sum()),
+         "states", int(s[0]), "in", states_lo, "..", states_hi)
+    assert sure.sum() <= s[1] <= maybe.sum()
+    assert states_lo <= s[0] <= states_hi
