@@ -422,9 +422,9 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
     uint32_t n_tests = 0;
 
     // lane state: the edge (flat id), its start and direction, next state
-    bool has = false;
+    bool has = false, fresh = false;
     float u[D], dv[D];
-    uint32_t e = 0;
+    uint32_t e = 0, uid = 0, vid = 0;
     int j = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) { u[i] = 0.f; dv[i] = 0.f; }
@@ -539,7 +539,6 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             const uint32_t take = avail < (uint32_t)n_need ? avail : (uint32_t)n_need;
             const int r = rank_in(need);
             if (!has && (uint32_t)r < take) {
-                uint32_t uid, vid;
                 if constexpr (LIST) {
                     e = A.edge_list[(size_t)tile * chunk + pos + r];
                     edge_vertex_ids(A, e, uid, vid);
@@ -550,13 +549,9 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                     vid = ri.v_base + n * ri.v_step;
                     e = (uint32_t)(ri.e_base + (uint64_t)n * ri.e_step);
                 }
-                float v[D];
-                load_vertex<D>(A, uid, u);
-                load_vertex<D>(A, vid, v);
-#pragma unroll
-                for (int i = 0; i < D; ++i) dv[i] = v[i] - u[i];
                 j = 0;
                 has = true;
+                fresh = true;
             }
             pos += take;
             if constexpr (!LIST) {
@@ -565,6 +560,16 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
             }
             need = ballot(!has && taker);
             n_need = __popcll(need);
+        }
+        // the vertices of the edges just taken, loaded once after the refill
+        // loop (only integers are carried around it)
+        if (fresh) {
+            float v[D];
+            load_vertex<D>(A, uid, u);
+            load_vertex<D>(A, vid, v);
+#pragma unroll
+            for (int i = 0; i < D; ++i) dv[i] = v[i] - u[i];
+            fresh = false;
         }
         const uint64_t busy = ballot(has);
         if (busy == 0) break;  // exhausted and every lane idle
