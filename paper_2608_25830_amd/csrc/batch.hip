@@ -238,9 +238,9 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : (
     RowInfo ri{};
     bool exhausted = false;
     unsigned long long n_states = 0, n_edges = 0;
-    bool has = false;
+    bool has = false, fresh = false;
     float u[D], dv[D];
-    uint32_t e = 0;
+    uint32_t e = 0, uid = 0, vid = 0;
     int j = 0;
     int n_int = 0;
 #pragma unroll
@@ -321,19 +321,29 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : (
             if (!has && (uint32_t)r < take) {
                 const uint32_t seg = tile - (tile / A.tiles_per_row) * A.tiles_per_row;
                 const uint32_t n = seg * kTile + A.tile_off[(size_t)tile * kTile + pos + r];
-                float v[D];
-                load_vertex<D>(A, ri.u_base + n * ri.u_step, u);
-                load_vertex<D>(A, ri.v_base + n * ri.v_step, v);
-#pragma unroll
-                for (int i = 0; i < D; ++i) dv[i] = v[i] - u[i];
+                uid = ri.u_base + n * ri.u_step;
+                vid = ri.v_base + n * ri.v_step;
                 e = (uint32_t)(ri.e_base + (uint64_t)n * ri.e_step);
                 j = 0;
                 has = true;
+                fresh = true;
             }
             pos += take;
             n_edges += take;
             need = ballot(!has);
             n_need = __popcll(need);
+        }
+        // the vertices of the edges just taken (all of the current plan: the
+        // plan changes only when no lane is busy), loaded once after the
+        // refill loop, which carries only integers
+        if (fresh) {
+            const EdgeArgs &A = plans[cur].A;
+            float v[D];
+            load_vertex<D>(A, uid, u);
+            load_vertex<D>(A, vid, v);
+#pragma unroll
+            for (int i = 0; i < D; ++i) dv[i] = v[i] - u[i];
+            fresh = false;
         }
         const uint64_t busy = ballot(has);
         if (busy == 0) {
