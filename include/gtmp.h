@@ -151,7 +151,10 @@ typedef struct gtmp_edge_opts {
                                  1024 tiles of 256 edges and the scene 1 to 96 obstacles; other
                                  values (and lazy rounds) = every state against every obstacle */
     int32_t reserved[3];
-    unsigned long long *stats; /* optional device [4]: states evaluated, edges checked in the
+    unsigned long long *stats; /* optional device [4]: states evaluated (those a walk of each
+                                  edge's interior states in the check order, stopping at the
+                                  first state in contact, evaluates; evaluations are counted
+                                  whole, states_per_iter at a time), edges checked in the
                                   interior pass, exact sphere-obstacle tests made behind the
                                   obstacle bins (sphere_chunks 0), [3] unused.  Added to. */
     void *ev_begin;            /* optional hipEvent_t recorded on `stream` just before the
