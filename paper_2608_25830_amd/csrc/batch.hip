@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kWords > 1 ? 3 : (
 #pragma unroll
                     for (int i = 0; i < D; ++i)
                         acc = __builtin_fmaf(dv[i], dv[i], acc);  // zero past d
-                    *cost_slot(A, e) = __builtin_sqrtf(acc);
+                    *cost_slot(A, e) = len_sqrt(acc);
                     if (A.flags) A.flags[e] = 0;
                     has = false;
                 }

@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
 #pragma unroll
                     for (int i = 0; i < D; ++i)
                         acc = __builtin_fmaf(dv[i], dv[i], acc);  // zero past d
-                    *cost_slot(A, e) = __builtin_sqrtf(acc);
+                    *cost_slot(A, e) = len_sqrt(acc);
                     if (A.flags) A.flags[e] = 0;
                     has = false;
                 }
@@ -706,7 +706,7 @@ __global__ void __launch_bounds__(256, Model::kGrid ? (Model::kArm ? 6 : 4) : NC
                         }
 #pragma unroll
                         for (int i = 0; i < D; ++i) acc = __builtin_fmaf(dd[i], dd[i], acc);  // zero past d
-                        *cost_slot(A, e) = __builtin_sqrtf(acc);
+                        *cost_slot(A, e) = len_sqrt(acc);
                         if (A.flags) A.flags[e] = 0;
                     }
                 }
@@ -845,7 +845,7 @@ __global__ void __launch_bounds__(256) k_list_finish(EdgeArgs A) {
                 const float dv = v[i] - u[i];
                 acc = __builtin_fmaf(dv, dv, acc);
             }
-        const float len = __builtin_sqrtf(acc);
+        const float len = len_sqrt(acc);
         const bool hit = A.list_mark[e] == 2;
         *cost_slot(A, e) = hit ? failed_cost(len, A.penalty) : len;
         if (A.flags) A.flags[e] = hit ? 1 : 0;

@@ -597,6 +597,11 @@ __device__ __forceinline__ void load_vertex(const EdgeArgs &A, uint32_t vid, flo
     }
 }
 
+// Square root of an edge's squared length: the hardware square root (within
+// one ulp; every kernel that writes an edge length takes it, so the lengths
+// agree bit for bit between them).
+__device__ __forceinline__ float len_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Euclidean length in configuration space (FP32, fixed summation order so
 // that the pre-pass and the interior kernel produce the same value).  The
 // coordinates past d are zero in both endpoints (the packed vertex array and
@@ -611,7 +616,7 @@ __device__ __forceinline__ float edge_len(const float (&u)[D], const float (&v)[
         const float t = v[i] - u[i];
         acc = __builtin_fmaf(t, t, acc);
     }
-    return __builtin_sqrtf(acc);
+    return len_sqrt(acc);
 }
 
 __device__ __forceinline__ float failed_cost(float len, float penalty) { return len + penalty; }
