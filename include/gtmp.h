@@ -87,8 +87,8 @@ typedef struct gtmp_problem {
  * chained from a base frame at the origin; sphere k sits on link
  * sph_link[k] (1..n_joints) at fraction sph_t[k] from frame origin
  * o_{L-1} to o_L, with radius sph_r[k].  Spheres must be listed in
- * non-decreasing link order.  A twist dh[i][1] within 1e-6 rad of 0 or
- * +-pi/2 is taken as exactly that angle (its cosine and sine as 1 / 0 or
+ * non-decreasing link order.  A twist dh[i][1] within 1e-7 rad of 0 or
+ * +-pi/2 (the FP32 value nearest pi/2 is 4.4e-8 off) is taken as exactly that angle (its cosine and sine as 1 / 0 or
  * 0 / +-1); any other twist as given.  A point robot ignores every field but
  * kind. */
 typedef struct gtmp_robot {

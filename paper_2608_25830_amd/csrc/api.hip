@@ -64,14 +64,15 @@ gtmp_status to_arm(const gtmp_robot *r, int d, gtmp::ArmParams *out) {
         a.a[j] = r->dh[j][0];
         a.dz[j] = r->dh[j][2];
         a.off[j] = r->dh[j][3];
-        // a twist within 1e-6 rad of 0 or +-pi/2 is taken as exact: (cos, sin)
+        // a twist within 1e-7 rad of 0 or +-pi/2 (the FP32 pi/2 is 4.4e-8 off) is
+        // taken as exact: (cos, sin)
         // = (1, 0) or (0, +-1), which the kinematics apply without products
         const double al = (double)r->dh[j][1], qt = 1.5707963267948966;
-        if (fabs(al) <= 1e-6) {
+        if (fabs(al) <= 1e-7) {
             a.ca[j] = 1.f; a.sa[j] = 0.f; a.twist[j] = gtmp::kTwistNone;
-        } else if (fabs(al - qt) <= 1e-6) {
+        } else if (fabs(al - qt) <= 1e-7) {
             a.ca[j] = 0.f; a.sa[j] = 1.f; a.twist[j] = gtmp::kTwistPlus;
-        } else if (fabs(al + qt) <= 1e-6) {
+        } else if (fabs(al + qt) <= 1e-7) {
             a.ca[j] = 0.f; a.sa[j] = -1.f; a.twist[j] = gtmp::kTwistMinus;
         } else {
             a.ca[j] = (float)cos(al);

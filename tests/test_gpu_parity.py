@@ -137,6 +137,34 @@ def test_edges_match_oracle(gt, orc, name, scene, kw, mode):
         np.testing.assert_allclose(ms[fin], ref[fin], atol=2e-5, rtol=1e-5)
 
 
+@pytest.mark.parametrize("twists", ["general", "quarter-plus-ulp", "quarter-minus-ulp"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_edges_match_oracle_twists(gt, orc, twists, mode):
+    """DH twists other than the workloads' 0 / +-pi/2 (which the GPU applies
+    as exact quarter turns): arbitrary angles, and the floats one step above
+    or below +-pi/2 (beyond the 1e-7 rad snapping tolerance: the general frame
+    update with a cosine near 0).  Flags and costs against the oracle under
+    the same rules as every edge test."""
+    w = wl.make_workload("arm7", 1, N=96, M=3)
+    g = np.random.default_rng(7)
+    dh = np.array(w["dh"], dtype=np.float32)
+    if twists == "general":
+        dh[:, 1] = g.uniform(-np.pi, np.pi, dh.shape[0]).astype(np.float32)
+    else:
+        q = np.float32(np.pi / 2)
+        step = np.nextafter(q, np.float32(4)) if twists == "quarter-plus-ulp" else np.nextafter(q, np.float32(0))
+        dh[:, 1] = np.where(np.arange(dh.shape[0]) % 2 == 0, step, -step).astype(np.float32)
+    w["dh"] = dh
+    _say("edges twists", twists, "mode", mode)
+    pl = gpu_plan(gt, w, mode=mode, minsd=(mode == 1))
+    Q = orc.sample_layers(w["M"], w["N"], w["d"], w["lo"], w["hi"], w["seed"], 0)
+    cost, minsd, flag = oracle_all(orc, w, Q)
+    got = P.flat(pl.C_s.cpu().numpy(), pl.C_h.cpu().numpy()[: w["M"] - 1], pl.C_l.cpu().numpy())
+    rep = P.compare_edges(got, pl.flags.cpu().numpy(), P.flat(*cost), P.flat(*minsd), P.flat(*flag))
+    _say("edges report", rep)
+    assert rep["failed"] < rep["edges"]  # the scene leaves some edges free
+
+
 @pytest.mark.parametrize("spi", [1, 2, 4, 8])
 def test_states_per_iter_invariance(gt, orc, spi):
     w = wl.make_workload("2d-large", 2, N=200, M=3)
