@@ -147,8 +147,10 @@ __global__ void k_store_params(ArmParams R, ArmParams *dst) {
 
 // The robot table for the interior kernel plus the tolerance of the expanded
 // sphere test: tol = 2^-19 ((reach + max|c|)^2 + (max r_o + r0)^2) over the
-// sphere obstacles (one wave).
-__global__ void k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
+// sphere obstacles (one wave).  R is only read (the two computed words are
+// substituted as the table is copied), so it stays in kernel-argument memory
+// rather than being copied to per-lane scratch.
+__global__ void __launch_bounds__(64) k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
     float cmax = 0.f, rmax = 0.f;
     for (int o = threadIdx.x; o < S.n_sph; o += blockDim.x) {
         const float *c = S.sph + 4 * o;
@@ -162,7 +164,7 @@ __global__ void k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
     }
     // rounding of the bound itself: inflate by 1e-3 relative
     const float pc = (R.reach + cmax) * 1.001f, rr = (rmax + R.r0) * 1.001f;
-    R.sph_tol = 0x1p-19f * (pc * pc + rr * rr);
+    const float sph_tol = 0x1p-19f * (pc * pc + rr * rr);
     // Links near the base that no obstacle can reach: an obstacle (box of
     // half-extents h around c, grown by rho) is at distance dist(0, box) - rho
     // from the base, and a sphere of link L has |centre| <= link_reach[L-1];
@@ -192,15 +194,17 @@ __global__ void k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
         dmin = __builtin_fminf(dmin, __shfl_xor(dmin, off));
         rk_max = __builtin_fmaxf(rk_max, __shfl_xor(rk_max, off));
     }
-    R.k_first = 0;
+    int k_first = 0;
     for (int L = 1; L <= R.n_joints; ++L) {
         if (!(dmin > (R.link_reach[L - 1] + rk_max) * 1.001f + 1e-6f)) break;
-        R.k_first = R.lk_end[L - 1];
+        k_first = R.lk_end[L - 1];
     }
     const uint32_t *src = reinterpret_cast<const uint32_t *>(&R);
     uint32_t *d = reinterpret_cast<uint32_t *>(dst);
     constexpr int n = sizeof(ArmParams) / 4;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = src[i];
+    constexpr int w_tol = offsetof(ArmParams, sph_tol) / 4, w_first = offsetof(ArmParams, k_first) / 4;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        d[i] = i == w_tol ? __float_as_uint(sph_tol) : i == w_first ? (uint32_t)k_first : src[i];
 }
 
 __global__ void k_zero_u32(uint32_t *p, int n) {

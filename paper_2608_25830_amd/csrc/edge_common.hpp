@@ -537,6 +537,31 @@ struct RowInfo {
     uint32_t c_step;
 };
 
+// Row info of row, given m = (row - 1) / N for an inner row (ignored for the
+// others): a walk over consecutive rows carries m instead of dividing.
+__device__ __forceinline__ RowInfo decode_row_m(const EdgeArgs &A, uint32_t row, uint32_t m) {
+    RowInfo r;
+    const uint32_t N = (uint32_t)A.N;
+    const uint32_t inner_rows = (uint32_t)(A.M - 1) * N;
+    if (row == 0) {
+        r.u_base = 0; r.u_step = 0; r.v_base = 1; r.v_step = 1;
+        r.e_base = 0; r.e_step = 1; r.c_base = A.C_s; r.c_step = 1;
+    } else if (row <= inner_rows) {
+        const uint32_t ri = row - 1;       // = m N + u
+        r.u_base = row; r.u_step = 0;
+        r.v_base = 1 + (m + 1) * N; r.v_step = 1;
+        r.e_base = (uint64_t)N + (uint64_t)ri * N; r.e_step = 1;
+        r.c_base = A.C_h + (size_t)ri * N; r.c_step = 1;
+    } else {
+        const uint32_t g = row - 1 - inner_rows;
+        r.u_base = 1 + (uint32_t)(A.M - 1) * N; r.u_step = 1;
+        r.v_base = 1 + (uint32_t)A.M * N + g; r.v_step = 0;
+        r.e_base = (uint64_t)N + (uint64_t)inner_rows * N + g; r.e_step = (uint32_t)A.G;
+        r.c_base = A.C_l + g; r.c_step = (uint32_t)A.G;
+    }
+    return r;
+}
+
 __device__ __forceinline__ RowInfo decode_row(const EdgeArgs &A, uint32_t row) {
     RowInfo r;
     const uint32_t N = (uint32_t)A.N;
@@ -622,12 +647,25 @@ __device__ __forceinline__ float edge_len(const float (&u)[D], const float (&v)[
 __device__ __forceinline__ float failed_cost(float len, float penalty) { return len + penalty; }
 
 // ------------------------------------------------------------------ pre-pass
+// Takes x as read here: a load of x still in flight is waited for at this
+// point (inside a branch that loaded it) rather than where the branches
+// meet, where the wait would also cover every store issued before it.
+template <int D>
+__device__ __forceinline__ void settle(float (&x)[D]) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) asm volatile("" : "+v"(x[i]));
+}
+__device__ __forceinline__ void settle(uint32_t &x) { asm volatile("" : "+v"(x)); }
+
 // One block per (A.prepass_rows <= kPrepassRows consecutive rows, row
 // segment): thread i takes column seg * kTile + i of every row.  Consecutive
 // rows of a layer share their target vertices, so a thread loads its target
 // once and reuses it while the rows' targets stay the same; the per-tile
-// compaction of all the rows shares one barrier.  Small graphs take one row
-// per block (more blocks in flight).
+// compaction of all the rows shares one barrier.  A row whose source vertex
+// is the same for every column (all but the goal rows) reads it from LDS,
+// where the block stages the sources of all its rows at once before the
+// rows are costed: the block waits for memory once, not once per row.  Small
+// graphs take one row per block (more blocks in flight).
 constexpr int kPrepassRows = 8;
 constexpr uint32_t kPrepassRowsMinTiles = 4096;  // graphs from this size take kPrepassRows rows per block
 
@@ -644,7 +682,11 @@ __host__ __device__ inline uint32_t prepass_block_count(const EdgeArgs &A) {
 // Pre-pass block b of a plan (blocks of kTile threads).
 template <int D>
 __device__ __forceinline__ void prepass_block(const EdgeArgs &A, uint32_t b) {
-    __shared__ uint32_t wave_cnt[kPrepassRows][kTile / kWave];
+    static_assert(kTile / kWave == 4, "one 16-byte read of a row's wave counts");
+    __shared__ __align__(16) uint32_t wave_cnt[kPrepassRows][kTile / kWave];
+    __shared__ float src_x[kPrepassRows][D];  // uniform source vertex of each row
+    __shared__ uint8_t src_fl[kPrepassRows];
+    static_assert(kPrepassRows * D <= kTile, "one staging thread per source coordinate");
     const int w = threadIdx.x / kWave;
     const uint32_t seg = b % A.tiles_per_row;
     const uint32_t row0 = (b / A.tiles_per_row) * A.prepass_rows;
@@ -652,41 +694,104 @@ __device__ __forceinline__ void prepass_block(const EdgeArgs &A, uint32_t b) {
     const uint32_t n = seg * kTile + threadIdx.x;
     const bool col = n < (uint32_t)A.N;
     uint32_t candbits = 0;
-    uint32_t vb = 0xffffffffu, vs = 0xffffffffu;  // target pattern of the loaded v
     float v[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) v[i] = 0.f;
-    uint8_t vfl = 0;
+    uint32_t vfl = 0;
+    // Layer of the block's first inner row (one division per block; the rows
+    // after it step m on when they cross into the next layer).
+    const uint32_t N = (uint32_t)A.N, inner_rows = (uint32_t)(A.M - 1) * N;
+    uint32_t m = (row0 > 0 ? row0 - 1 : 0) / N;
+    // Target of the first row (issued before the staging loads, so that both
+    // are in flight together).
+    const RowInfo ri0 = decode_row_m(A, row0, m);
+    uint32_t vb = ri0.v_base, vs = ri0.v_step;  // target pattern of the loaded v
+    if (col) {
+        const uint32_t vid = vb + n * vs;
+        load_vertex<D>(A, vid, v);
+        vfl = A.vflag[vid];
+    }
+    {
+        // The source of row 0 and of every inner row is vertex id = row.
+        const uint32_t r = threadIdx.x / D, j = threadIdx.x % D, row = row0 + r;
+        if (r < (uint32_t)A.prepass_rows && row < rows && row <= inner_rows) {
+            const float x = A.verts[(size_t)row * A.dp + j];
+            const uint8_t f = j == 0 ? A.vflag[row] : 0;
+            src_x[r][j] = x;
+            if (j == 0) src_fl[r] = f;
+        }
+    }
+    settle<D>(v);
+    settle(vfl);
+    __syncthreads();
+    // Cost and flag of edge e (source u, target v), written through cp;
+    // whether its interior still has to be checked.
+    auto cost_edge = [&](const float (&u)[D], uint32_t ufl, uint64_t e, float *cp) -> bool {
+        const float len = edge_len<D>(u, v, A.d);
+        bool failed = (ufl | vfl) != 0 || len > A.max_len;
+        if (A.prune) failed = failed || A.prune[e] != 0;
+        *cp = failed_cost(len, A.penalty);
+        if (A.flags) A.flags[e] = 1;
+        return !failed;
+    };
+    const uint32_t last = row0 + kPrepassRows - 1;
+    if (A.prepass_rows == kPrepassRows && row0 > 0 && last <= inner_rows && last - 1 < (m + 1) * N) {
+        // Every row an inner row of layer m: sources staged, one target, the
+        // row's costs N apart.
+        const size_t off0 = (size_t)(row0 - 1) * N + n;
 #pragma unroll
-    for (int r = 0; r < kPrepassRows; ++r) {
-        const uint32_t row = row0 + r;
-        if (r >= A.prepass_rows || row >= rows) break;
-        const RowInfo ri = decode_row(A, row);
-        bool cand = false;
-        if (ri.v_base != vb || ri.v_step != vs) {
-            vb = ri.v_base;
-            vs = ri.v_step;
+        for (int r = 0; r < kPrepassRows; ++r) {
+            bool cand = false;
             if (col) {
-                const uint32_t vid = vb + n * vs;
-                load_vertex<D>(A, vid, v);
-                vfl = A.vflag[vid];
+                float u[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) u[i] = src_x[r][i];
+                const size_t off = off0 + (size_t)r * N;
+                cand = cost_edge(u, src_fl[r], (uint64_t)N + off, A.C_h + off);
             }
+            candbits |= (cand ? 1u : 0u) << r;
+            const uint64_t mask = ballot(cand);
+            if (lane_id() == 0) wave_cnt[r][w] = (uint32_t)__popcll(mask);
         }
-        const uint64_t e = ri.e_base + (uint64_t)n * ri.e_step;
-        if (col) {
-            const uint32_t uid = ri.u_base + n * ri.u_step;
-            float u[D];
-            load_vertex<D>(A, uid, u);
-            const float len = edge_len<D>(u, v, A.d);
-            bool failed = (A.vflag[uid] | vfl) != 0 || len > A.max_len;
-            if (A.prune) failed = failed || A.prune[e] != 0;
-            ri.c_base[(size_t)n * ri.c_step] = failed_cost(len, A.penalty);
-            if (A.flags) A.flags[e] = 1;
-            cand = !failed;
+    } else {
+#pragma unroll
+        for (int r = 0; r < kPrepassRows; ++r) {
+            const uint32_t row = row0 + r;
+            if (r >= A.prepass_rows || row >= rows) break;
+            while (row > 0 && row - 1 >= (m + 1) * N) ++m;
+            const RowInfo ri = decode_row_m(A, row, m);
+            bool cand = false;
+            if (ri.v_base != vb || ri.v_step != vs) {
+                vb = ri.v_base;
+                vs = ri.v_step;
+                if (col) {
+                    const uint32_t vid = vb + n * vs;
+                    load_vertex<D>(A, vid, v);
+                    vfl = A.vflag[vid];
+                    settle<D>(v);
+                    settle(vfl);
+                }
+            }
+            if (col) {
+                float u[D];
+                uint32_t ufl;
+                if (ri.u_step == 0) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i) u[i] = src_x[r][i];
+                    ufl = src_fl[r];
+                } else {
+                    const uint32_t uid = ri.u_base + n * ri.u_step;
+                    load_vertex<D>(A, uid, u);
+                    ufl = A.vflag[uid];
+                    settle<D>(u);
+                    settle(ufl);
+                }
+                cand = cost_edge(u, ufl, ri.e_base + (uint64_t)n * ri.e_step, ri.c_base + (size_t)n * ri.c_step);
+            }
+            candbits |= (cand ? 1u : 0u) << r;
+            const uint64_t mask = ballot(cand);
+            if (lane_id() == 0) wave_cnt[r][w] = (uint32_t)__popcll(mask);
         }
-        candbits |= (cand ? 1u : 0u) << r;
-        const uint64_t mask = ballot(cand);
-        if (lane_id() == 0) wave_cnt[r][w] = (uint32_t)__popcll(mask);
     }
     __syncthreads();
 #pragma unroll
@@ -694,11 +799,13 @@ __device__ __forceinline__ void prepass_block(const EdgeArgs &A, uint32_t b) {
         const uint32_t row = row0 + r;
         if (r >= A.prepass_rows || row >= rows) break;
         const uint32_t tile = row * A.tiles_per_row + seg;
+        const uint4 c4 = *reinterpret_cast<const uint4 *>(wave_cnt[r]);
+        const uint32_t cnt[kTile / kWave] = {c4.x, c4.y, c4.z, c4.w};
         uint32_t base = 0, total = 0;
 #pragma unroll
         for (int k = 0; k < kTile / kWave; ++k) {
-            if (k < w) base += wave_cnt[r][k];
-            total += wave_cnt[r][k];
+            if (k < w) base += cnt[k];
+            total += cnt[k];
         }
         const bool cand = (candbits >> r) & 1u;
         const uint64_t mask = ballot(cand);

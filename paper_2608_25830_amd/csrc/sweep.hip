@@ -258,9 +258,51 @@ hipError_t launch_minplus(int M, int N, int G, const float *C_s, const float *C_
 }
 
 // ---------------------------------------------------------------- extraction
-__global__ void k_extract(int M, int N, int G, int d, const int32_t *a_s, const int32_t *A, const float *V_s,
-                          const float *Q, const float *q0, const float *goals, int32_t *idx, float *wp, float *cost) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Chains of up to this many vertices are followed once into LDS and their
+// waypoints copied by every lane at once; longer ones by one thread.
+constexpr int kExtractChain = 4096;
+
+__global__ void __launch_bounds__(64) k_extract(int M, int N, int G, int d, const int32_t *a_s, const int32_t *A,
+                                                const float *V_s, const float *Q, const float *q0,
+                                                const float *goals, int32_t *idx, float *wp, float *cost) {
+    if (blockIdx.x != 0) return;
+    if (M + 1 <= kExtractChain) {
+        __shared__ int32_t chain[kExtractChain];
+        __shared__ int ok_s;
+        if (threadIdx.x == 0) {
+            const float vs = *V_s;
+            int i = *a_s;
+            // a minimiser outside its layer can only come from inconsistent
+            // inputs; it is reported as "no path" rather than followed
+            bool ok = i >= 0 && i < N && vs < __builtin_inff();
+            chain[0] = i;
+            for (int m = 0; m < M && ok; ++m) {
+                const int nxt = A[(size_t)m * N + i];
+                ok = nxt >= 0 && nxt < (m + 1 < M ? N : G);
+                i = nxt;
+                chain[m + 1] = i;
+            }
+            ok_s = ok;
+            *cost = ok ? vs : __builtin_inff();
+        }
+        __syncthreads();
+        const bool ok = ok_s != 0;
+        for (int m = threadIdx.x; m <= M; m += blockDim.x) idx[m] = ok ? chain[m] : -1;
+        // waypoint k: row k / d of q0 | the chosen layer samples | the goal
+        const int n_wp = (M + 2) * d;
+        for (int k = threadIdx.x; k < n_wp; k += blockDim.x) {
+            const int row = k / d, j = k - row * d;
+            float x = __builtin_nanf("");
+            if (ok) {
+                if (row == 0) x = q0[j];
+                else if (row <= M) x = Q[((size_t)(row - 1) * N + chain[row - 1]) * d + j];
+                else x = goals[(size_t)chain[M] * d + j];
+            }
+            wp[k] = x;
+        }
+        return;
+    }
+    if (threadIdx.x != 0) return;
     const float vs = *V_s;
     int i = *a_s;
     *cost = vs;
@@ -270,8 +312,6 @@ __global__ void k_extract(int M, int N, int G, int d, const int32_t *a_s, const 
         *cost = __builtin_inff();
         return;
     }
-    // a minimiser outside its layer can only come from inconsistent inputs;
-    // it is reported as "no path" rather than followed
     bool ok = i < N;
     for (int m = 0; m < M && ok; ++m) {
         const int nxt = A[(size_t)m * N + i];
