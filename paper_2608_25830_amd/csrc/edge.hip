@@ -147,12 +147,14 @@ __global__ void k_store_params(ArmParams R, ArmParams *dst) {
 
 // The robot table for the interior kernel plus the tolerance of the expanded
 // sphere test: tol = 2^-19 ((reach + max|c|)^2 + (max r_o + r0)^2) over the
-// sphere obstacles (one wave).  R is only read (the two computed words are
-// substituted as the table is copied), so it stays in kernel-argument memory
-// rather than being copied to per-lane scratch.
-__global__ void __launch_bounds__(64) k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
+// sphere obstacles (one wave, lanes 0..63 of the caller).  R is only read
+// (the two computed words are substituted as the table is copied), so it
+// stays in kernel-argument memory rather than being copied to per-lane
+// scratch.
+__device__ __forceinline__ void store_params_tol_wave(const ArmParams &R, ArmParams *dst, const SceneParams &S) {
+    const int lane = threadIdx.x;
     float cmax = 0.f, rmax = 0.f;
-    for (int o = threadIdx.x; o < S.n_sph; o += blockDim.x) {
+    for (int o = lane; o < S.n_sph; o += kWave) {
         const float *c = S.sph + 4 * o;
         cmax = __builtin_fmaxf(cmax, __builtin_sqrtf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]));
         rmax = __builtin_fmaxf(rmax, __builtin_fabsf(c[3]));
@@ -172,7 +174,7 @@ __global__ void __launch_bounds__(64) k_store_params_tol(ArmParams R, ArmParams 
     // 1e-6, no sphere of links 1..L can touch one (the exact test's rounding
     // is far inside that margin), and the bin filter may skip them.
     float dmin = __builtin_inff(), rk_max = 0.f;
-    for (int o = threadIdx.x; o < S.n_sph + S.n_box; o += blockDim.x) {
+    for (int o = lane; o < S.n_sph + S.n_box; o += kWave) {
         float dd;
         if (o < S.n_sph) {
             const float *c = S.sph + 4 * o;
@@ -188,7 +190,7 @@ __global__ void __launch_bounds__(64) k_store_params_tol(ArmParams R, ArmParams 
         }
         dmin = __builtin_fminf(dmin, dd != dd ? -__builtin_inff() : dd);  // NaN data: nothing is skipped
     }
-    for (int k = threadIdx.x; k < R.n_spheres; k += blockDim.x) rk_max = __builtin_fmaxf(rk_max, R.r[k]);
+    for (int k = lane; k < R.n_spheres; k += kWave) rk_max = __builtin_fmaxf(rk_max, R.r[k]);
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
         dmin = __builtin_fminf(dmin, __shfl_xor(dmin, off));
@@ -203,8 +205,12 @@ __global__ void __launch_bounds__(64) k_store_params_tol(ArmParams R, ArmParams 
     uint32_t *d = reinterpret_cast<uint32_t *>(dst);
     constexpr int n = sizeof(ArmParams) / 4;
     constexpr int w_tol = offsetof(ArmParams, sph_tol) / 4, w_first = offsetof(ArmParams, k_first) / 4;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int i = lane; i < n; i += kWave)
         d[i] = i == w_tol ? __float_as_uint(sph_tol) : i == w_first ? (uint32_t)k_first : src[i];
+}
+
+__global__ void __launch_bounds__(kWave) k_store_params_tol(ArmParams R, ArmParams *dst, SceneParams S) {
+    store_params_tol_wave(R, dst, S);
 }
 
 __global__ void k_zero_u32(uint32_t *p, int n) {
@@ -215,6 +221,15 @@ __global__ void k_zero_u32(uint32_t *p, int n) {
 __global__ void __launch_bounds__(kGridBuildThreads) k_build_grid(SceneParams S, int wdim, float r_max,
                                                                         ObsGrid *G) {
     build_grid_block(S, wdim, r_max, G);
+}
+
+// An arm plan's obstacle bins (block 0) and its robot table with the sphere
+// test's tolerance (block 1, first wave) in one launch of two blocks:
+// neither reads what the other writes.
+__global__ void __launch_bounds__(kGridBuildThreads) k_build_grid_params(SceneParams S, float r_max, ObsGrid *G,
+                                                                         ArmParams R, ArmParams *dst) {
+    if (blockIdx.x == 0) build_grid_block(S, 3, r_max, G);
+    else if (threadIdx.x < kWave) store_params_tol_wave(R, dst, S);
 }
 
 // ------------------------------------------------------------------ 1. vertices
@@ -312,8 +327,12 @@ __global__ void __launch_bounds__(256) k_vertices_point(EdgeArgs A, SceneParams 
 
 // ------------------------------------------------------------------ 2. pre-pass
 // (prepass_block in edge_common.hpp; shared with the batched planner)
+// Block 0 also resets the interior kernel's tile cursors (read by nothing
+// before that kernel, which the stream orders after this one).
 template <int D>
 __global__ void __launch_bounds__(kTile) k_prepass(EdgeArgs A) {
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < kCursors * kCursorStride; i += kTile) A.counter[i] = 0u;
     prepass_block<D>(A, blockIdx.x);
 }
 
@@ -1017,7 +1036,8 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
     if (phases & kPhaseVertices) {
         if (gw) {
             // the bins serve the vertex flags and, later, the interior kernel
-            hipLaunchKernelGGL(k_build_grid, dim3(1), dim3(kGridBuildThreads), 0, s, S, 3, r_max, grid);
+            // (which also reads the robot table written beside them)
+            hipLaunchKernelGGL(k_build_grid_params, dim3(2), dim3(kGridBuildThreads), 0, s, S, r_max, grid, R, Rg);
             // one wave per block: a plan has few vertices, so small blocks spread them over more CUs
             constexpr int vt = kVertexGridWaves * kWave;
             const unsigned vb64 = (A.n_vertices + vt - 1) / vt;
@@ -1029,8 +1049,8 @@ static hipError_t launch_arm_kp(const EdgeArgs &A, const ArmParams &R, const Sce
                                    vflag);
         } else {
             hipLaunchKernelGGL(k_vertices_arm<KP>, dim3(vb), dim3(256), 0, s, A, R, S, q0, goals, Q, verts, vflag);
+            hipLaunchKernelGGL(k_store_params_tol, dim3(1), dim3(kWave), 0, s, R, Rg, S);
         }
-        hipLaunchKernelGGL(k_store_params_tol, dim3(1), dim3(64), 0, s, R, Rg, S);
     }
     if (!(phases & kPhaseEdges)) return hipGetLastError();
     if (!A.edge_list) hipLaunchKernelGGL(k_prepass<GTMP_MAX_JOINTS>, dim3(prepass_blocks(A)), dim3(kTile), 0, s, A);
@@ -1247,9 +1267,10 @@ hipError_t launch_edge_phases(const EdgePlan &plan, const ArmParams *arm, const 
         return hipGetLastError();
     }
 
-    // fast mode: reset the tile cursor with a fill kernel (no memset node, so
-    // the sequence can be captured into a graph and replayed)
-    if (phases & kPhaseEdges)
+    // fast mode: the tile cursors are reset by the pre-pass; a lazy round's
+    // list has no pre-pass and resets them with a fill kernel (no memset
+    // node, so the sequence can be captured into a graph and replayed)
+    if ((phases & kPhaseEdges) && A.edge_list)
         hipLaunchKernelGGL(k_zero_u32, dim3(kCursors * kCursorStride / 256), dim3(256), 0, s, A.counter,
                            kCursors * kCursorStride);
     if (arm) {

@@ -137,6 +137,56 @@ def test_edges_match_oracle(gt, orc, name, scene, kw, mode):
         np.testing.assert_allclose(ms[fin], ref[fin], atol=2e-5, rtol=1e-5)
 
 
+# Graphs of at least 4,096 pre-pass tiles, whose pre-pass blocks take eight
+# consecutive rows: blocks spanning two or three layers (N < 8), layer
+# boundaries at every offset within a block with a ragged last column segment
+# (N = 300), last blocks holding several goal rows (G = 3, whose source
+# vertex varies along the row), and one sample per layer (every block spans
+# eight layers).  The plan's path and waypoints check the extraction on chains
+# of about a thousand vertices (staged in LDS) and of 4,101 (past the staged
+# length: one thread walks the chain).
+PREPASS_ROW_CASES = [("2d-large", 0, dict(N=4, M=1100, H=8), 1), ("2d-large", 1, dict(N=300, M=9, H=8), 3),
+                     ("arm7", 0, dict(N=5, M=900, H=6), 3), ("2d-large", 2, dict(N=1, M=4100, H=8), 1)]
+
+
+@pytest.mark.parametrize("name,scene,kw,G", PREPASS_ROW_CASES)
+def test_eight_row_prepass_blocks_match_oracle(gt, orc, name, scene, kw, G):
+    w = wl.make_workload(name, scene, **kw)
+    if G > 1:
+        rng = np.random.default_rng(11)
+        lo, hi = np.asarray(w["lo"], np.float64), np.asarray(w["hi"], np.float64)
+        extra = (lo + (hi - lo) * rng.random((G - 1, w["d"]))).astype(np.float32)
+        w["goals"] = np.concatenate([w["goals"], extra]).astype(np.float32)
+        w["G"] = G
+    M, N = w["M"], w["N"]
+    assert (1 + (M - 1) * N + G) * -(-N // 256) >= 4096  # eight rows per pre-pass block
+    _say("eight-row pre-pass", name, scene, kw, "G", G)
+    pl = gpu_plan(gt, w)
+    ref = orc.plan(w)
+    got = P.flat(pl.C_s.cpu().numpy(), pl.C_h.cpu().numpy()[: M - 1], pl.C_l.cpu().numpy())
+    rep = P.compare_edges(got, pl.flags.cpu().numpy(), P.flat(*ref["cost"]), P.flat(*ref["minsd"]),
+                          P.flat(*ref["flag"]))
+    _say("report", rep)
+    c_gpu = float(pl.cost.item())
+    idx_gpu = pl.idx.cpu().numpy()
+    # The sweep sums a path's M + 1 positive edge costs one layer at a time in
+    # FP32: besides the costs' own 1e-5, the sum may drift by (M + 1) 2^-24
+    # relative (the recursive-summation bound), 6.6e-5 at M = 1100.
+    rel = P.REL + (M + 1) * 2.0 ** -24
+    if rep["excused"] == 0:
+        assert c_gpu == pytest.approx(ref["path_cost"], rel=rel)
+        n = P.check_path_indices(ref["cost"], ref["V"], ref["idx"], idx_gpu, ref["path_cost"], rel=rel)
+        _say("indices compared", n, "of", M + 1)
+        # past the first near-tie: the returned chain is one whose oracle
+        # edge costs sum to the returned cost
+        assert P.path_cost_from_oracle(ref["cost"], idx_gpu) == pytest.approx(c_gpu, rel=rel)
+    if np.isfinite(c_gpu):
+        wp = pl.wp.cpu().numpy()
+        assert np.array_equal(wp[0], w["q0"]) and np.array_equal(wp[-1], w["goals"][idx_gpu[-1]])
+        for m in range(M):
+            assert np.array_equal(wp[m + 1], ref["Q"][m, idx_gpu[m]])
+
+
 @pytest.mark.parametrize("twists", ["general", "quarter-plus-ulp", "quarter-minus-ulp"])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_edges_match_oracle_twists(gt, orc, twists, mode):
