@@ -141,12 +141,13 @@ def test_edges_match_oracle(gt, orc, name, scene, kw, mode):
 # consecutive rows: blocks spanning two or three layers (N < 8), layer
 # boundaries at every offset within a block with a ragged last column segment
 # (N = 300), last blocks holding several goal rows (G = 3, whose source
-# vertex varies along the row), and one sample per layer (every block spans
-# eight layers).  The plan's path and waypoints check the extraction on chains
+# vertex varies along the row), one sample per layer (every block spans
+# eight layers), and a 3-D point robot (M = 17, N = 256: 4,098 tiles).  The plan's path and waypoints check the extraction on chains
 # of about a thousand vertices (staged in LDS) and of 4,101 (past the staged
 # length: one thread walks the chain).
 PREPASS_ROW_CASES = [("2d-large", 0, dict(N=4, M=1100, H=8), 1), ("2d-large", 1, dict(N=300, M=9, H=8), 3),
-                     ("arm7", 0, dict(N=5, M=900, H=6), 3), ("2d-large", 2, dict(N=1, M=4100, H=8), 1)]
+                     ("arm7", 0, dict(N=5, M=900, H=6), 3), ("2d-large", 2, dict(N=1, M=4100, H=8), 1),
+                     ("3d-point", 1, dict(N=256, M=17), 1)]
 
 
 @pytest.mark.parametrize("name,scene,kw,G", PREPASS_ROW_CASES)
