@@ -275,19 +275,7 @@ __global__ void __launch_bounds__(kVertexGridWaves * kWave) k_vertices_arm_grid(
                                                                                 float *verts, uint8_t *vflag) {
     __shared__ GridLds<WG> glds_raw;
     __shared__ GridQueue<WG> gque[kVertexGridWaves];  // one queue per wave of the block
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(A.grid);
-        uint4 *dst = reinterpret_cast<uint4 *>(&glds_raw);
-        for (int k = threadIdx.x; k < (int)(grid_lds_bytes<WG>() / 16); k += blockDim.x) dst[k] = src[k];
-    }
-    __syncthreads();
-    const ObsGrid &G = *reinterpret_cast<const ObsGrid *>(&glds_raw);
-    float inv[3], off[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        inv[k] = G.inv[k];
-        off[k] = G.off[k];
-    }
+    // the vertex first, so that its loads and the bins' are in flight together
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < A.n_vertices;
     const uint32_t MN = (uint32_t)A.M * (uint32_t)A.N;
@@ -299,8 +287,19 @@ __global__ void __launch_bounds__(kVertexGridWaves * kWave) k_vertices_arm_grid(
 #pragma unroll
         for (int j = 0; j < GTMP_MAX_JOINTS; ++j)
             if (j < A.d) q[j] = src[j];
+    }
+    copy_to_lds<grid_lds_bytes<WG>(), kVertexGridWaves * kWave>(&glds_raw, A.grid, threadIdx.x);
+    if (valid) {
 #pragma unroll
         for (int j = 0; j < GTMP_MAX_JOINTS; ++j) verts[(size_t)i * A.dp + j] = q[j];
+    }
+    __syncthreads();
+    const ObsGrid &G = *reinterpret_cast<const ObsGrid *>(&glds_raw);
+    float inv[3], off[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        inv[k] = G.inv[k];
+        off[k] = G.off[k];
     }
     uint32_t tests = 0;
     const bool hit = arm_hit_grid<WG>(R, q, G.mask, G.rec, inv, off, gque[wave_in_block()], tests, valid);

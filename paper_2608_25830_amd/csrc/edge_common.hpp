@@ -47,6 +47,31 @@ struct alignas(16) GridLds {
     unsigned char bytes[grid_lds_bytes<WORDS>()];
 };
 
+// Copy of the first BYTES bytes of src (global) to dst (LDS) by THREADS
+// threads, tid being the caller's index among them: every 16-byte load of a
+// thread is issued before its first store, so the copy waits for memory once
+// rather than once per load.
+// (A native vector type: an array of HIP's uint4 structs is not promoted to
+// registers.)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <size_t BYTES, int THREADS>
+__device__ __forceinline__ void copy_to_lds(void *dst, const void *src, int tid) {
+    constexpr int n16 = (int)(BYTES / 16), iters = (n16 + THREADS - 1) / THREADS;
+    const u32x4 *s = reinterpret_cast<const u32x4 *>(src);
+    u32x4 *d = reinterpret_cast<u32x4 *>(dst);
+    u32x4 t[iters];
+#pragma unroll
+    for (int i = 0; i < iters; ++i) {
+        const int k = tid + i * THREADS;
+        t[i] = s[k < n16 ? k : n16 - 1];  // unconditional: past the end, the last piece again
+    }
+#pragma unroll
+    for (int i = 0; i < iters; ++i) {
+        const int k = tid + i * THREADS;
+        if (k < n16) d[k] = t[i];
+    }
+}
+
 // Point kernels keep the mask words of one (axis, bin) cell side by side in
 // LDS, padded to 1, 2 or 4 words, so that a probe reads each axis with one
 // vector load.
