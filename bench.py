@@ -12,7 +12,7 @@ kernel (the early-exit interior edge checker) measured with HIP events on the
 stream it runs on, and the FP64 oracle timed on the host cores on a bounded
 sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload arm7]
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--workload arm7]
     python bench.py --form batch [--steps 2] [--warmup 1]
 
 ``--form batch`` times the batched form instead: 512 independent plans
@@ -663,8 +663,10 @@ def bench_surrogate(args, torch, wl, gtmp):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 50 for the plain form, whose step is about a millisecond, so that "
+                         "one late host enqueue barely moves the mean; 10 for the others)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 5 plain, 2 others)")
     ap.add_argument("--workload", default="arm7")
     ap.add_argument("--form", default="plain", choices=["plain", "batch", "surrogate", "restart", "classes", "rrtc",
                                                               "lazy"])
@@ -689,6 +691,10 @@ def main():
                     help="before the plans, copy a buffer of this many MiB once (reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 50 if args.form == "plain" else 10
+    if args.warmup is None:
+        args.warmup = 5 if args.form == "plain" else 2
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the planner is not built for "
               f"several GPUs.", file=sys.stderr)
