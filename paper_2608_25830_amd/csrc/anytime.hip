@@ -543,11 +543,22 @@ __global__ void __launch_bounds__(256) k_bx_rank_init(const ExpandJob *jobs, int
                           reinterpret_cast<rank::RankState *>(J.rankws));
 }
 
-__global__ void __launch_bounds__(256) k_bx_rank_pass(const ExpandJob *jobs, int m, int pass) {
+// The jobs whose layer pairs at one layer take the radix selection, listed
+// by the host (which holds the same job table) as a kernel argument, so that
+// the selection's grids have rows for those jobs only instead of for every
+// job of the stage; a captured launch keeps its own copy of the list.
+constexpr int kMaxListedJobs = 1024;
+struct JobList {
+    uint32_t all;                 // 1: every job, grid row y is job y
+    uint16_t id[kMaxListedJobs];  // else grid row y is job id[y]
+};
+__device__ __forceinline__ uint32_t listed_job(const JobList &sel) { return sel.all ? blockIdx.y : sel.id[blockIdx.y]; }
+
+__global__ void __launch_bounds__(256) k_bx_rank_pass(const ExpandJob *jobs, const JobList sel, int m, int pass) {
     __shared__ uint32_t h[rank::kRankBins];
     __shared__ uint32_t part[256];
     __shared__ bool last;
-    const ExpandJob &J = jobs[blockIdx.y];
+    const ExpandJob &J = jobs[listed_job(sel)];
     LayerPairs L;
     if (!job_ranks_large(J, m, L)) return;  // every block of the job returns alike
     rank::rank_pass_block(pass, J.d, L.U, L.nv, L.V, (uint32_t)L.npairs, (uint32_t)L.K,
@@ -555,8 +566,8 @@ __global__ void __launch_bounds__(256) k_bx_rank_pass(const ExpandJob *jobs, int
                           reinterpret_cast<rank::RankState *>(J.rankws), blockIdx.x, gridDim.x, h, part, last);
 }
 
-__global__ void __launch_bounds__(256) k_bx_rank_compact(const ExpandJob *jobs, int m) {
-    const ExpandJob &J = jobs[blockIdx.y];
+__global__ void __launch_bounds__(256) k_bx_rank_compact(const ExpandJob *jobs, const JobList sel, int m) {
+    const ExpandJob &J = jobs[listed_job(sel)];
     LayerPairs L;
     if (!job_ranks_large(J, m, L)) return;
     rank::rank_compact_block(J.d, L.U, L.nv, L.V, (uint32_t)L.npairs, reinterpret_cast<rank::RankState *>(J.rankws),
@@ -621,17 +632,29 @@ hipError_t launch_expand_jobs(const ExpandJob *jobs_dev, const std::vector<Expan
     if (most > 0)
         hipLaunchKernelGGL(k_bx_relayout, dim3((unsigned)std::min<uint64_t>((most + 255) / 256, 4096), nj), dim3(256), 0,
                            s, jobs_dev);
+    JobList sel{};
     for (int m = 0; m < maxM; ++m) {
         bool any_small = false;
         uint64_t large = 0;
         int slots = 0;
-        for (const ExpandJob &J : jobs) {
-            if (m >= J.M || J.n_old >= J.N) continue;
+        uint32_t n_large = 0;
+        for (unsigned j = 0; j < nj; ++j) {
+            const ExpandJob &J = jobs[j];
+            if (m >= J.M || J.n_old >= J.N) continue;  // the device's job_active
             const LayerPairs L = layer_pairs(J, m);
             if (L.npairs > 0 && L.npairs <= (uint64_t)rank::kRankSortCap) any_small = true;
-            if (L.npairs > (uint64_t)rank::kRankSortCap) large = std::max(large, L.npairs);
+            if (L.npairs > (uint64_t)rank::kRankSortCap) {  // the device's job_ranks_large
+                large = std::max(large, L.npairs);
+                if (n_large < (uint32_t)kMaxListedJobs) sel.id[n_large] = (uint16_t)j;
+                ++n_large;
+            }
             slots = std::max(slots, J.N - J.n_old);
         }
+        // more listed jobs than the list holds: rows for every job (the
+        // others return at once, as every job's blocks do once its
+        // selection is done)
+        sel.all = n_large > (uint32_t)kMaxListedJobs || nj > 65536u ? 1u : 0u;
+        const unsigned rows = sel.all ? nj : n_large;
         if (slots == 0) continue;
         hipLaunchKernelGGL(k_bx_coin, dim3(nj), dim3(1024), 0, s, jobs_dev, m);
         if (any_small) hipLaunchKernelGGL(k_bx_rank_small, dim3(nj), dim3(rank::kRankSortThreads), 0, s, jobs_dev, m);
@@ -639,8 +662,8 @@ hipError_t launch_expand_jobs(const ExpandJob *jobs_dev, const std::vector<Expan
             const unsigned bx = (unsigned)std::min<uint64_t>((large + 1023) / 1024, 1024);
             hipLaunchKernelGGL(k_bx_rank_init, dim3(nj), dim3(256), 0, s, jobs_dev, m);
             for (int pass = 0; pass < rank::kRankPasses; ++pass)
-                hipLaunchKernelGGL(k_bx_rank_pass, dim3(bx, nj), dim3(256), 0, s, jobs_dev, m, pass);
-            hipLaunchKernelGGL(k_bx_rank_compact, dim3(bx, nj), dim3(256), 0, s, jobs_dev, m);
+                hipLaunchKernelGGL(k_bx_rank_pass, dim3(bx, rows), dim3(256), 0, s, jobs_dev, sel, m, pass);
+            hipLaunchKernelGGL(k_bx_rank_compact, dim3(bx, rows), dim3(256), 0, s, jobs_dev, sel, m);
             hipLaunchKernelGGL(k_bx_rank_sort, dim3(nj), dim3(rank::kRankSortThreads), 0, s, jobs_dev, m);
         }
         hipLaunchKernelGGL(k_bx_fill, dim3((unsigned)((slots + kExpandSlots - 1) / kExpandSlots), nj),
